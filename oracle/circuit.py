@@ -1,0 +1,309 @@
+"""The encrypted KAN circuit on the oracle's RNS-CKKS (O1 running O2's math).
+
+TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the
+CPU-baseline leg of the benchmark; never by the product package.
+
+Per KANLayer (Method, Figure 2 structure) on a ciphertext x whose slots hold
+the layer input in blocks of n_blk slots:
+  * first layer: Fast Repeat Packing (Algorithm 1) without the mask, because
+    a fresh ciphertext already holds zeros outside [0, n_i);
+  * spline branch: PolyComp on x_rep - g1 and g2 - x_rep, their product, and k
+    rounds of Algorithm 2 (each round relinearises once after summing both
+    tensor products);
+  * SiLU branch: the fitted Chebyshev polynomial by baby-step giant-step;
+  * both linear layers (W_b after SiLU, the fused W_f = W' P after the basis)
+    by the hybrid diagonal method with baby-step giant-step rotations, their
+    partial sums added and folded over all slots, so the output is periodic
+    with period d = next power of two >= n_out (the next layer's repeat
+    packing comes for free).
+Every step fixes where rescales happen and at which scale each plaintext is
+encoded, which the GPU path reproduces independently.
+"""
+import math
+
+import numpy as np
+
+from .kan import fused_weights
+
+
+def pow2ceil(n):
+    return 1 << max(0, (n - 1).bit_length())
+
+
+def clog2(n):
+    return max(0, (n - 1).bit_length())
+
+
+# --------------------------------------------------------------------------
+# polynomial evaluators
+# --------------------------------------------------------------------------
+def odd_poly(ev, v, a):
+    """sum_i a_i v^(2i+1) for degree 3, 5 or 7 in depth 2, 3, 3."""
+    l = v.level
+    if len(a) == 2:
+        v2 = ev.mul(v, v)
+        t3 = ev.mul(ev.lincomb([(v, a[1])], l - 1), v2)
+        return ev.add(ev.lincomb([(v, a[0])], l - 2), t3)
+    if len(a) == 3:
+        v2 = ev.mul(v, v)
+        v4 = ev.mul(v2, v2)
+        t3 = ev.mul(ev.lincomb([(v, a[1])], l - 1), v2)
+        t5 = ev.mul(ev.lincomb([(v, a[2])], l - 2), v4)
+        return ev.add(ev.lincomb([(v, a[0]), (t3, 1.0)], l - 3), t5)
+    if len(a) == 4:
+        v2 = ev.mul(v, v)
+        v4 = ev.mul(v2, v2)
+        t3 = ev.mul(ev.lincomb([(v, a[1])], l - 1), v2)
+        t7 = ev.mul(ev.lincomb([(v, a[3])], l - 1), v2)
+        B = ev.add(t7, ev.lincomb([(v, a[2])], l - 2))
+        Cc = ev.mul(B, v4)
+        return ev.add(ev.lincomb([(v, a[0]), (t3, 1.0)], l - 3), Cc)
+    raise ValueError("odd polynomial of unsupported degree")
+
+
+def polycomp(ev, v, stages):
+    """PolyComp(v, 0) = (F(v/2R)+1)/2 with the scalings folded into the stages."""
+    for a in stages:
+        v = odd_poly(ev, v, list(a))
+    return ev.add_const(v, 0.5)
+
+
+def cheb_split(c, G):
+    """p = q T_G + r for Chebyshev coefficients c (len n <= 2G):
+    q_0 = c_G, q_j = 2 c_{G+j}; r_i = c_i, r_{G-j} -= c_{G+j}  (j >= 1)."""
+    n = len(c)
+    q = [c[G]] + [2.0 * c[G + j] for j in range(1, n - G)]
+    r = list(c[:G])
+    for j in range(1, n - G):
+        r[G - j] = r[G - j] - c[G + j]
+    return q, r
+
+
+class ChebEval:
+    """Chebyshev series on [lo, hi] by baby-step giant-step.
+
+    T_1 = alpha x + beta (one rescale), babies T_2..T_b with
+    T_2i = 2 T_i^2 - 1 and T_2i+1 = 2 T_i T_{i+1} - T_1, giants
+    T_2b, T_4b, ... by squaring; the series is split recursively by the
+    largest giant below its length, and every sub-result lands exactly on the
+    level its consumer needs (leaf lincombs target that level directly)."""
+
+    def __init__(self, ev, x, coeffs, lo, hi):
+        self.ev = ev
+        self.c = [float(v) for v in coeffs]
+        deg = len(self.c) - 1
+        m = clog2(deg + 1)
+        self.b = 1 << ((m + 1) // 2)
+        alpha = 2.0 / (hi - lo)
+        beta = -(hi + lo) / (hi - lo)
+        T1 = ev.add_const(ev.lincomb([(x, alpha)], x.level - 1), beta)
+        T = {1: T1}
+        for i in range(2, self.b + 1):
+            if i % 2 == 0:
+                h = T[i // 2]
+                T[i] = ev.add_const(ev.mul_int(ev.mul(h, h), 2), -1.0)
+            else:
+                a, c = T[(i - 1) // 2], T[(i + 1) // 2]
+                lv = min(a.level, c.level)
+                p = ev.mul_int(ev.mul(ev.level_down(a, lv), ev.level_down(c, lv)), 2)
+                T[i] = ev.sub(p, ev.level_down(T1, p.level))
+        G = 2 * self.b
+        while G < deg + 1:
+            h = T[G // 2]
+            T[G] = ev.add_const(ev.mul_int(ev.mul(h, h), 2), -1.0)
+            G *= 2
+        self.T = T
+
+    def giant(self, n):
+        G = self.b
+        while 2 * G < n:
+            G *= 2
+        return G
+
+    def feasible(self, c, t):
+        n = len(c)
+        if n <= self.b:
+            return t <= min(self.T[i].level for i in range(1, n)) - 1
+        G = self.giant(n)
+        q, r = cheb_split(c, G)
+        if len(q) == 1:
+            ok_q = t <= self.T[G].level - 1
+        else:
+            ok_q = t + 1 <= self.T[G].level and self.feasible(q, t + 1)
+        return ok_q and self.feasible(r, t)
+
+    def rec(self, c, t):
+        ev = self.ev
+        n = len(c)
+        if n <= self.b:
+            terms = [(self.T[i], c[i]) for i in range(1, n)]
+            return ev.add_const(ev.lincomb(terms, t), c[0])
+        G = self.giant(n)
+        q, r = cheb_split(c, G)
+        if len(q) == 1:
+            prod = ev.lincomb([(self.T[G], q[0])], t)
+        else:
+            qc = self.rec(q, t + 1)
+            prod = ev.mul(qc, ev.level_down(self.T[G], t + 1))
+        return ev.add(prod, self.rec(r, t))
+
+    def run(self):
+        t = self.T[1].level - 1
+        while not self.feasible(self.c, t):
+            t -= 1
+            if t < 0:
+                raise RuntimeError("Chebyshev evaluation does not fit the level budget")
+        return self.rec(self.c, t)
+
+
+def cheb_eval(ev, x, coeffs, lo, hi):
+    return ChebEval(ev, x, coeffs, lo, hi).run()
+
+
+# --------------------------------------------------------------------------
+# packing, B-spline bases, linear layers
+# --------------------------------------------------------------------------
+def repeat_pack(ev, x, n_blk, nlog):
+    """Algorithm 1 without the mask: x <- rot(x, -n_blk 2^(j-1)) + x."""
+    for j in range(1, nlog + 1):
+        x = ev.add(ev.rotate(x, -n_blk * (1 << (j - 1))), x)
+    return x
+
+
+def coltile(knots, lo, hi, n_blk, n_in, slots):
+    """ColTile(G, lo, hi) of the knot matrix G (row i = t_1..t_r for every
+    input): block m (m < hi-lo) holds t_{lo+m} in slots m n_blk + i, i < n_in;
+    every other slot is 0.  lo, hi are 1-based as in Algorithm 2."""
+    v = np.zeros(slots)
+    for m in range(hi - lo):
+        v[m * n_blk:m * n_blk + n_in] = knots[lo + m - 1]
+    return v
+
+
+def block_mask(nblocks, n_blk, n_in, slots):
+    v = np.zeros(slots, bool)
+    for m in range(nblocks):
+        v[m * n_blk:m * n_blk + n_in] = True
+    return v
+
+
+def bspline_basis(ev, xr, L, n_blk):
+    """Algorithm 2 on the repeat-packed ciphertext xr."""
+    slots = ev.ctx.p.slots
+    r = L.g + 2 * L.k + 1
+    g1 = coltile(L.knots, 1, r, n_blk, L.n_in, slots)
+    g2 = coltile(L.knots, 2, r + 1, n_blk, L.n_in, slots)
+    x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
+    x2 = polycomp(ev, ev.add_vec(ev.mul_int(xr, -1), g2), L.comp)
+    b = ev.mul(x1, x2)
+    for j in range(1, L.k + 1):
+        nbl = r - j - 1
+        t1 = coltile(L.knots, 1, r - j, n_blk, L.n_in, slots)
+        t2 = coltile(L.knots, j + 1, r, n_blk, L.n_in, slots)
+        t3 = coltile(L.knots, j + 2, r + 1, n_blk, L.n_in, slots)
+        t4 = coltile(L.knots, 2, r - j + 1, n_blk, L.n_in, slots)
+        msk = block_mask(nbl, n_blk, L.n_in, slots)
+        A1 = np.zeros(slots)
+        A2 = np.zeros(slots)
+        A1[msk] = 1.0 / (t2[msk] - t1[msk])
+        A2[msk] = 1.0 / (t3[msk] - t4[msk])
+        lb = b.level
+        P1 = ev.add_vec(ev.lincomb([(xr, A1)], lb), -(t1 * A1))
+        P2 = ev.add_vec(ev.lincomb([(xr, -A2)], lb), t3 * A2)
+        rb = ev.rotate(b, n_blk)
+        b = ev.relin_rescale(ev.tensor_add(ev.tensor(P1, b), ev.tensor(P2, rb)))
+    return b
+
+
+def diag_vector(M, d, i, slots):
+    """Generalised diagonal i of M (n_out x n_in) for output period d:
+    entry j is M[j mod d][(j+i) mod slots] when both indices are in range."""
+    n_out, n_in = M.shape
+    j = np.arange(slots)
+    r = j % d
+    c = (j + i) % slots
+    v = np.zeros(slots)
+    ok = (r < n_out) & (c < n_in)
+    v[ok] = M[r[ok], c[ok]]
+    return v
+
+
+def bsgs_split(d):
+    b1 = 1 << ((clog2(d) + 1) // 2)
+    return b1, d // b1
+
+
+def matvec_partial(ev, x, M, d, t):
+    """z = sum_{i<d} diag_i * rot(x, i) at level t by baby-step giant-step:
+    z = sum_gi rot( sum_bi rot(diag_{gi b1 + bi}, -gi b1) * rot(x, bi), gi b1 ).
+    x is mod-dropped to t+1 before the baby-step rotations."""
+    slots = ev.ctx.p.slots
+    b1, g1 = bsgs_split(d)
+    xd = ev.mod_drop(x, t + 1)
+    rots = [xd] + [ev.rotate(xd, bi) for bi in range(1, b1)]
+    z = None
+    for gi in range(g1):
+        terms = []
+        for bi in range(b1):
+            dv = np.roll(diag_vector(M, d, gi * b1 + bi, slots), gi * b1)
+            terms.append((rots[bi], dv))
+        inner = ev.lincomb(terms, t)
+        if gi:
+            inner = ev.rotate(inner, gi * b1)
+        z = inner if z is None else ev.add(z, inner)
+    return z
+
+
+def fold(ev, z, d):
+    """z <- z + rot(z, s) for s = slots/2, slots/4, ..., d."""
+    s = ev.ctx.p.slots // 2
+    while s >= d:
+        z = ev.add(z, ev.rotate(z, s))
+        s //= 2
+    return z
+
+
+def layer_forward(ev, x, L, n_blk, first):
+    d = pow2ceil(L.n_out)
+    xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
+    b = bspline_basis(ev, xr, L, n_blk)
+    s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
+    t = min(b.level, s.level) - 1
+    Wf = fused_weights(L, n_blk)
+    Wb = np.zeros((L.n_out, n_blk))
+    Wb[:, :L.n_in] = L.wb
+    z = ev.add(matvec_partial(ev, b, Wf, d, t), matvec_partial(ev, s, Wb, d, t))
+    return fold(ev, z, d), d
+
+
+def eval_kan(ev, ct, layers, refresh=None):
+    """Run the layers on ct (input in slots [0, n_in)).  `refresh`, if given,
+    is called between layers with the ciphertext and returns a fresh one at the
+    top level (the client-aided stand-in for bootstrapping)."""
+    n_blk = layers[0].n_in
+    for li, L in enumerate(layers):
+        if li > 0 and refresh is not None:
+            ct = refresh(ct, li)
+        ct, n_blk = layer_forward(ev, ct, L, n_blk, li == 0)
+    return ct
+
+
+def rotation_steps(layers, slots):
+    """Every rotation amount the circuit uses (for key generation)."""
+    steps = set()
+    n_blk = layers[0].n_in
+    for li, L in enumerate(layers):
+        d = pow2ceil(L.n_out)
+        if li == 0:
+            for j in range(1, clog2(L.g + 2 * L.k) + 1):
+                steps.add(-n_blk * (1 << (j - 1)))
+        steps.add(n_blk)
+        b1, g1 = bsgs_split(d)
+        steps.update(range(1, b1))
+        steps.update(gi * b1 for gi in range(1, g1))
+        s = slots // 2
+        while s >= d:
+            steps.add(s)
+            s //= 2
+        n_blk = d
+    return sorted(steps)

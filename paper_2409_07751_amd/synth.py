@@ -1,0 +1,106 @@
+"""Seeded synthetic workloads: parameter sizes, KAN shapes, random weights and
+inputs.  This module holds none of the method's arithmetic; it only draws
+numbers, so both the GPU path and the CPU checker can take their inputs from
+it.
+
+Workloads (the data sets of the paper are not available; these inputs have
+their shapes and value ranges):
+  tiny    N=2^13, 8 Q primes (60 + 7x40 bits), 1 special prime, scale 2^40,
+          KAN [2,5,1], k=3, G=5 on [-1,1], c ~ N(0, 0.1^2), w_b ~ N(0, 0.3^2),
+          SiLU degree 15 on [-4,4], one input x ~ U[-1,1]^2;
+  formula N=2^15, 17 Q primes (60 + 16x40), 2 special primes, scale 2^40,
+          KAN [4,10,10,1], k=3, G=10 on [-1,1], SiLU degree 27 (data range);
+  image   N=2^16, 25 Q primes (60 + 24x45), 4 special primes, scale 2^45,
+          KAN [784,64,10], k=3, G=8 on [0,1], weights N(0, 0.05^2), SiLU
+          degree 31, 28x28 images with pixels U[0,1] quantised to k/255
+          (the MNIST shape), raster-scanned;
+  cifar   same parameters, KAN [3072,128,10] on 32x32x3 images (the CIFAR-10
+          shape), pixels U[0,1].
+Seeds: weights 1, inputs 2, keygen 3, encryption 4, arrivals 5, calibration 6.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_WEIGHTS, SEED_INPUTS, SEED_KEYGEN, SEED_ENC, SEED_ARRIVALS, SEED_CALIB = 1, 2, 3, 4, 5, 6
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    logN: int
+    L: int
+    scale_bits: int
+    alpha: int
+    w: int                       # key-switch digit width in Q limbs
+    shape: tuple                 # KAN layer widths
+    g: int
+    k: int
+    grid: tuple                  # grid of the first layer
+    silu_degree: int
+    silu_range: tuple = None     # fixed SiLU range, or None for the data range
+    comp_degrees: tuple = ()     # comparison composite stage degrees per layer
+    wb_std: float = 0.3
+    c_std: float = 0.1
+    input_kind: str = "uniform_pm1"
+    refresh: bool = False        # client-aided refresh between layers
+    base_bits: int = 60
+    special_bits: int = 60
+    sigma: float = 3.2
+
+
+WORKLOADS = {
+    "tiny": Workload("tiny", 13, 7, 40, 1, 1, (2, 5, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
+                     ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True),
+    "formula": Workload("formula", 15, 16, 40, 2, 2, (4, 10, 10, 1), 10, 3, (-1.0, 1.0), 27, None,
+                        ((7, 7), (7, 7), (7, 7)), 0.3, 0.1, "uniform_pm1", True),
+    "image": Workload("image", 16, 24, 45, 4, 5, (784, 64, 10), 8, 3, (0.0, 1.0), 31, None,
+                      ((7, 7), (7, 7)), 0.05, 0.05, "pixels255"),
+    "cifar": Workload("cifar", 16, 24, 45, 4, 5, (3072, 128, 10), 8, 3, (0.0, 1.0), 31, None,
+                      ((7, 7), (7, 7)), 0.05, 0.05, "pixels"),
+}
+
+
+def _rng(*key):
+    return np.random.default_rng(list(key))
+
+
+def raw_weights(wl: Workload, seed=SEED_WEIGHTS):
+    """Random-init weights of the KAN shape: per layer w_b (n_out x n_in),
+    w_s = 1 and per-edge spline coefficients c (n_out x n_in x (g+k))."""
+    layers = []
+    for li in range(len(wl.shape) - 1):
+        n_in, n_out = wl.shape[li], wl.shape[li + 1]
+        r = _rng(seed, li)
+        wb = r.normal(0.0, wl.wb_std, (n_out, n_in))
+        c = r.normal(0.0, wl.c_std, (n_out, n_in, wl.g + wl.k))
+        layers.append({"wb": wb, "ws": np.ones((n_out, n_in)), "c": c, "g": wl.g, "k": wl.k})
+    return layers
+
+
+def inputs(wl: Workload, n, seed=SEED_INPUTS, stream=0):
+    """n raster-scanned input vectors of the workload's first-layer width."""
+    r = _rng(seed, stream)
+    n_in = wl.shape[0]
+    if wl.input_kind == "uniform_pm1":
+        return r.uniform(-1.0, 1.0, (n, n_in))
+    if wl.input_kind == "pixels255":
+        return np.round(r.uniform(0.0, 1.0, (n, n_in)) * 255.0) / 255.0
+    if wl.input_kind == "pixels":
+        return r.uniform(0.0, 1.0, (n, n_in))
+    raise ValueError(wl.input_kind)
+
+
+def calibration_inputs(wl: Workload, n=4096):
+    return inputs(wl, n, seed=SEED_CALIB)
+
+
+def poisson_arrivals(rate, n, seed=SEED_ARRIVALS):
+    """arrival times (s) of n requests at `rate` per second."""
+    r = _rng(seed, 0)
+    return np.cumsum(r.exponential(1.0 / rate, n))
+
+
+def request_mix(n, names, probs, seed=SEED_ARRIVALS):
+    r = _rng(seed, 1)
+    return [names[i] for i in r.choice(len(names), size=n, p=probs)]

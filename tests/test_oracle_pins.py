@@ -1,0 +1,520 @@
+"""Pins of the CPU oracle against mathematics that does not depend on it:
+schoolbook products, big-integer CRT, Galois identities, decryption bounds,
+RFC 8439 vectors, closed forms of the comparison polynomials, numpy's Chebyshev
+fit, the Cox-de Boor definition and dense linear algebra."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ckks, circuit, kan
+from oracle.ckks import P, Params, lib
+from oracle.slotsim import SimCt, SlotSim
+from paper_2409_07751_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def py_is_prime(n):
+    """Independent Miller-Rabin with Python integers."""
+    if n < 2:
+        return False
+    for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41):
+        if n % p == 0:
+            return n == p
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41):
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+SMALL = Params(logN=5, L=4, scale_bits=40, alpha=2, w=2)
+
+
+@pytest.fixture(scope="module")
+def small():
+    ctx = ckks.Context(SMALL)
+    keys = ckks.Keys(ctx, 3, [1, 2, -1, 5])
+    return ctx, keys, ckks.Oracle(ctx, keys)
+
+
+# --------------------------------------------------------------------------
+# ring arithmetic
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("logN", [1, 3, 6, 8])
+def test_ntt_product_matches_schoolbook(logN):
+    L = lib()
+    N = 1 << logN
+    rng = np.random.default_rng(logN)
+    ctx = ckks.Context(Params(logN=max(logN, 2), L=2, scale_bits=40, alpha=1, w=1))
+    for q in list(ctx.q) + list(ctx.pm):
+        if (int(q) - 1) % (2 * N):
+            continue
+        a = rng.integers(0, int(q), N, dtype=np.uint64)
+        b = rng.integers(0, int(q), N, dtype=np.uint64)
+        o1 = np.zeros(N, np.uint64)
+        o2 = np.zeros(N, np.uint64)
+        L.oc_negacyclic_mul(P(a), P(b), P(o1), logN, int(q))
+        L.oc_schoolbook_mul(P(a), P(b), P(o2), logN, int(q))
+        assert (o1 == o2).all()
+        # schoolbook itself against Python big ints, X^N = -1
+        ref = [0] * N
+        for i in range(N):
+            for j in range(N):
+                k = i + j
+                v = int(a[i]) * int(b[j])
+                if k < N:
+                    ref[k] += v
+                else:
+                    ref[k - N] -= v
+        assert [r % int(q) for r in ref] == [int(v) for v in o2]
+        c = a.copy()
+        L.oc_ntt_fwd(P(c), logN, int(q))
+        L.oc_ntt_inv(P(c), logN, int(q))
+        assert (c == a).all()
+
+
+def test_forward_transform_is_evaluation_at_odd_powers():
+    L = lib()
+    logN, N = 4, 16
+    ctx = ckks.Context(Params(logN=logN, L=1, scale_bits=40, alpha=1, w=1))
+    q = int(ctx.q[1])
+    psi = int(L.oc_find_psi(q, logN))
+    assert pow(psi, N, q) == q - 1
+    a = np.arange(1, N + 1, dtype=np.uint64)
+    f = a.copy()
+    L.oc_ntt_fwd(P(f), logN, q)
+    for k in range(N):
+        x = pow(psi, 2 * k + 1, q)
+        assert int(f[k]) == sum(int(a[j]) * pow(x, j, q) for j in range(N)) % q
+
+
+@pytest.mark.parametrize("name", ["tiny", "formula", "image"])
+def test_prime_chain(name):
+    wl = synth.WORKLOADS[name]
+    ctx = ckks.Context(Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w))
+    M = 2 << wl.logN
+    allp = [int(v) for v in list(ctx.q) + list(ctx.pm)]
+    assert len(set(allp)) == len(allp)
+    for p in allp:
+        assert p % M == 1 and py_is_prime(p)
+    # base prime: the largest 60-bit prime = 1 mod 2N
+    q0 = int(ctx.q[0])
+    assert q0 < 2 ** 60 and all(not py_is_prime(c) for c in range(q0 + M, 2 ** 60, M))
+    # special primes: the next ones below it
+    cands = [c for c in range(q0 - M, int(min(ctx.pm)) - 1, -M) if py_is_prime(c)]
+    assert cands == [int(v) for v in ctx.pm]
+    # canonical scales: S_L = Delta, S_{l-1} = S_l^2 / q_l, all within 2^-15 of Delta
+    delta = 2.0 ** wl.scale_bits
+    assert ctx.S[wl.L] == delta
+    for l in range(wl.L, 0, -1):
+        assert ctx.S[l - 1] == ctx.S[l] * ctx.S[l] / float(ctx.q[l])
+        assert abs(ctx.S[l - 1] / delta - 1) < 2 ** -15
+        # q_l is the prime nearest S_l^2/Delta among unused primes = 1 mod 2N
+        T = ctx.S[l] * ctx.S[l] / delta
+        ql = int(ctx.q[l])
+        for c in range(ql - M, int(T - abs(T - ql)) - 1, -M):
+            assert not py_is_prime(c) or c in allp
+        for c in range(ql + M, int(T + abs(T - ql)) + 1, M):
+            assert not py_is_prime(c) or c in allp
+
+
+def crt(res, mods):
+    Q = math.prod(mods)
+    x = 0
+    for r, m in zip(res, mods):
+        h = Q // m
+        x += int(r) * h * pow(h, -1, m)
+    return x % Q, Q
+
+
+def test_rescale_is_rounded_division(small):
+    ctx, _, _ = small
+    L = lib()
+    logN, N = SMALL.logN, SMALL.N
+    rng = np.random.default_rng(7)
+    l = 3
+    mods = [int(v) for v in ctx.q[: l + 1]]
+    c = np.array([rng.integers(0, m, N, dtype=np.uint64) for m in mods], np.uint64)
+    out = np.zeros((l, N), np.uint64)
+    L.oc_rescale(P(c), P(out), l, logN, P(ctx.q))
+    for n in range(N):
+        x, Q = crt(c[:, n], mods)
+        if x > Q // 2:
+            x -= Q
+        ql = mods[l]
+        want = (x + ql // 2) // ql  # floor((x + h)/q_l): rounding with h = floor(q_l/2)
+        got, Ql = crt(out[:, n], mods[:l])
+        assert got == want % Ql
+
+
+def test_bconv_and_moddown_against_crt(small):
+    ctx, _, _ = small
+    L = lib()
+    logN, N = SMALL.logN, SMALL.N
+    rng = np.random.default_rng(8)
+    src = [int(v) for v in ctx.q[:2]]
+    dst = [int(v) for v in list(ctx.q[2:]) + list(ctx.pm)]
+    x = np.array([rng.integers(0, m, N, dtype=np.uint64) for m in src], np.uint64)
+    out = np.zeros((len(dst), N), np.uint64)
+    L.oc_bconv(P(x), 2, P(ckks.u64a(src)), P(out), len(dst), P(ckks.u64a(dst)), logN)
+    B = math.prod(src)
+    for n in range(N):
+        v, _ = crt(x[:, n], src)
+        # fast conversion returns v + u B with 0 <= u < len(src)
+        us = set()
+        for p, o in zip(dst, out[:, n]):
+            us.add(next(u for u in range(len(src)) if (v + u * B) % p == int(o)))
+        assert len(us) == 1
+    # ModDown: (a - Conv_P->Q([a]_P)) / P is round-free division of a by P
+    nq, alpha = 3, SMALL.alpha
+    qm = [int(v) for v in ctx.q[:nq]]
+    pm = [int(v) for v in ctx.pm]
+    allm = qm + pm
+    a = np.array([rng.integers(0, m, N, dtype=np.uint64) for m in allm], np.uint64)
+    o = np.zeros((nq, N), np.uint64)
+    L.oc_moddown(P(a), P(o), nq, alpha, logN, P(ctx.q), P(ctx.pm))
+    Pp = math.prod(pm)
+    for n in range(N):
+        xa, QP = crt(a[:, n], allm)
+        ap, _ = crt(a[nq:, n], pm)
+        got, Q = crt(o[:, n], qm)
+        # exact: (x - ([x]_P + u P)) / P for the same small u on every limb
+        ok = any((xa - ap - u * Pp) // Pp % Q == got for u in range(alpha + 1))
+        assert ok
+
+
+def test_automorphism_identities(small):
+    ctx, _, ev = small
+    L = lib()
+    logN, N = SMALL.logN, SMALL.N
+    mods = ckks.u64a(ctx.q[:2])
+    rng = np.random.default_rng(9)
+    a = np.array([rng.integers(0, int(m), N, dtype=np.uint64) for m in mods], np.uint64)
+    for g, h in [(3, 5), (5, 5), (25, 2 * N - 1)]:
+        ag = np.zeros_like(a)
+        agh = np.zeros_like(a)
+        L.oc_automorph(P(a), P(ag), 2, logN, P(mods), g)
+        L.oc_automorph(P(ag), P(agh), 2, logN, P(mods), h)
+        direct = np.zeros_like(a)
+        L.oc_automorph(P(a), P(direct), 2, logN, P(mods), (g * h) % (2 * N))
+        assert (agh == direct).all()
+    # sigma_{5^t} rotates decoded slots left by t
+    z = rng.uniform(-1, 1, N // 2)
+    m = ev.encode(z, 2.0 ** 30, 1)
+    for t in (1, 3, -2):
+        gm = np.zeros_like(m)
+        L.oc_automorph(P(m), P(gm), 1, logN, P(ckks.u64a(ctx.q[:1])), ctx.galois_elt(t))
+        dz = ev.decode(gm[0], 2.0 ** 30, N // 2)
+        assert np.abs(dz - np.roll(z, -t)).max() < 1e-7
+
+
+def test_encode_fft_matches_direct_sum_and_roundtrip():
+    L = lib()
+    ctx = ckks.Context(Params(logN=10, L=2, scale_bits=40, alpha=1, w=1))
+    ev = ckks.Oracle(ctx)
+    rng = np.random.default_rng(10)
+    z = rng.uniform(-3, 3, 300)
+    scale = 2.0 ** 40 * 1.2345
+    hi = np.zeros(1024)
+    lo = np.zeros(1024)
+    L.oc_encode_coeffs_dd(P(z), len(z), scale, 10, P(hi), P(lo))
+    for i in (0, 1, 77, 511, 1023):
+        d = L.oc_encode_coeff_direct(P(z), len(z), scale, 10, i)
+        assert abs((hi[i] + lo[i]) - d) <= 1e-12 * scale
+    m = ev.encode(z, scale, 1)
+    got = ev.decode(m[0], scale, 300)
+    assert np.abs(got - z).max() < 1e-9
+    # constants: one coefficient round(c X), every other coefficient 0
+    mc = ev.encode(np.full(512, 0.75), scale, 1)
+    assert int(mc[0, 0]) == round(0.75 * scale) and (mc[0, 1:] == 0).all()
+    assert int(ev.encode_const(0.75, scale, 1)[0]) == round(0.75 * scale)
+
+
+def test_encode_rounding_ties_to_even():
+    ctx = ckks.Context(Params(logN=5, L=1, scale_bits=40, alpha=1, w=1))
+    ev = ckks.Oracle(ctx)
+    q = int(ctx.q[0])
+    for c, X, want in [(0.5, 3.0, 2), (0.5, 5.0, 2), (-0.5, 3.0, -2), (0.5, 7.0, 4), (1.5, 1.0, 2)]:
+        r = int(ev.encode_const(c, X, 1)[0])
+        assert (r if r < q // 2 else r - q) == want
+
+
+def test_chacha20_rfc8439_vectors():
+    import ctypes
+    L = lib()
+    rows = [l.split() for l in open(os.path.join(GOLD, "chacha20_rfc8439.txt")) if l.strip() and l[0] != "#"]
+    d = {r[0]: r[1:] for r in rows}
+    q = d["quarter"]
+    a, b, c, dd = [np.array([int(v, 16)], np.uint32) for v in q[:4]]
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    L.oc_chacha_quarter.argtypes = [u32p] * 4
+    L.oc_chacha_quarter(P(a), P(b), P(c), P(dd))
+    assert [int(v[0]) for v in (a, b, c, dd)] == [int(v, 16) for v in q[5:9]]
+    key = np.array([int(v, 16) for v in d["block_key"]], np.uint32)
+    nonce = np.array([int(v, 16) for v in d["block_nonce"]], np.uint32)
+    out = np.zeros(16, np.uint32)
+    L.oc_chacha20_block(P(key), int(d["block_counter"][0]), P(nonce), P(out))
+    assert [int(v) for v in out] == [int(v, 16) for v in d["block_out"]]
+
+
+def test_samplers_statistics():
+    L = lib()
+    T = np.zeros(39, np.uint64)
+    L.oc_gauss_table(3.2, P(T))
+    assert (np.diff(T.astype(object)) > 0).all()
+    # thresholds are the normalised CDF of exp(-k^2/(2 sigma^2)) on [-19, 19]
+    rho = np.exp(-np.arange(-19, 20) ** 2 / (2 * 3.2 ** 2))
+    cdf = np.cumsum(rho) / rho.sum()
+    assert np.allclose(T[:38].astype(float) / 2.0 ** 64, cdf[:38], rtol=0, atol=1e-15)
+    e = np.zeros(1 << 16, np.int64)
+    L.oc_sample_gauss(11, 3, 0, 0, 3.2, 16, P(e))
+    assert abs(e.mean()) < 0.05 and abs(e.std() - 3.2) < 0.05 and np.abs(e).max() <= 19
+    s = np.zeros(1 << 16, np.int64)
+    L.oc_sample_ternary(11, 1, 0, 0, 16, P(s))
+    counts = [(s == v).mean() for v in (-1, 0, 1)]
+    assert set(np.unique(s)) <= {-1, 0, 1} and max(abs(c - 1 / 3) for c in counts) < 0.01
+    u = np.zeros(1 << 16, np.uint64)
+    q = 1099511627689
+    L.oc_sample_uniform(11, 2, 0, 0, q, 16, P(u))
+    assert u.max() < q and abs(u.astype(float).mean() / q - 0.5) < 0.01
+
+
+# --------------------------------------------------------------------------
+# CKKS operations
+# --------------------------------------------------------------------------
+def test_encrypt_decrypt_within_noise_bound(small):
+    ctx, keys, ev = small
+    rng = np.random.default_rng(12)
+    z = rng.uniform(-1, 1, SMALL.slots)
+    ct = ev.encrypt(z, 5)
+    # |e| <= 19 per coefficient; decoded slot error <= N * 19 / Delta
+    assert np.abs(ev.decrypt(ct, SMALL.slots) - z).max() < SMALL.N * 19 / ctx.S[SMALL.L] + 1e-9
+
+
+def test_keyswitch_and_relinearisation(small):
+    ctx, keys, ev = small
+    rng = np.random.default_rng(13)
+    a = rng.uniform(-1, 1, SMALL.slots)
+    b = rng.uniform(-1, 1, SMALL.slots)
+    ca, cb = ev.encrypt(a, 6), ev.encrypt(b, 7)
+    assert np.abs(ev.decrypt(ev.mul(ca, cb), SMALL.slots) - a * b).max() < 1e-6
+    for t in (1, 2, -1, 5):
+        assert np.abs(ev.decrypt(ev.rotate(ca, t), SMALL.slots) - np.roll(a, -t)).max() < 1e-6
+    # rotating at a lower level and after a mod-drop
+    c2 = ev.mod_drop(ca, 2)
+    assert np.abs(ev.decrypt(ev.rotate(c2, 1), SMALL.slots) - np.roll(a, -1)).max() < 1e-6
+
+
+def test_lincomb_and_level_down(small):
+    ctx, keys, ev = small
+    rng = np.random.default_rng(14)
+    a = rng.uniform(-1, 1, SMALL.slots)
+    w = rng.uniform(-2, 2, SMALL.slots)
+    ca = ev.encrypt(a, 8)
+    m = ev.mul(ca, ca)
+    lc = ev.lincomb([(ca, 0.25), (m, w)], 1)
+    assert lc.level == 1
+    assert np.abs(ev.decrypt(lc, SMALL.slots) - (0.25 * a + w * a * a)).max() < 1e-6
+    d = ev.level_down(ca, 0)
+    assert d.level == 0 and np.abs(ev.decrypt(d, SMALL.slots) - a).max() < 1e-6
+
+
+# --------------------------------------------------------------------------
+# KAN pieces
+# --------------------------------------------------------------------------
+def test_composite_closed_forms_and_symmetry():
+    rows = [l.split() for l in open(os.path.join(GOLD, "composite_fn.txt")) if l.strip() and l[0] != "#"]
+    for r in rows:
+        n, den = int(r[0]), float(r[1])
+        want = [float(v) / den for v in r[2:]]
+        assert kan.fn_odd_coeffs(n) == want
+    u = np.linspace(-1, 1, 2001)
+    for degs in [(3,), (7,), (7, 7), (5, 3)]:
+        st = kan.composite_stages(list(degs), 0.5)  # 2R = 1: input already in [-1, 1]
+        S = kan.polycomp(u, st)
+        assert abs(kan.polycomp(0.0, st) - 0.5) < 1e-15
+        assert np.abs(S + kan.polycomp(-u, st) - 1.0).max() < 1e-12
+        assert S.min() >= -1e-12 and S.max() <= 1 + 1e-12
+        assert kan.polycomp(1.0, st) == pytest.approx(1.0) and kan.polycomp(-1.0, st) == pytest.approx(0.0)
+
+
+def test_bspline_partition_of_unity_and_cubic_closed_form():
+    g, k = 5, 3
+    t = kan.make_knots(-1.0, 1.0, g, k)
+    x = np.linspace(-1, 1, 1001)[:-1]
+    B = kan.bspline_exact(x, t, k)
+    assert B.shape == (1000, g + k)
+    assert np.abs(B.sum(-1) - 1).max() < 1e-12
+    # uniform cubic B-spline on [t_m, t_{m+4}]: pieces u^3/6, (-3u^3+3u^2+3u+1)/6,
+    # (3u^3-6u^2+4)/6, (1-u)^3/6 with u the offset in the current cell
+    h = t[1] - t[0]
+    m = 2
+    for xv in np.linspace(t[m], t[m + 4], 97)[:-1]:
+        cell = int(np.floor((xv - t[m]) / h + 1e-12))
+        u = (xv - t[m + cell]) / h
+        want = [u ** 3 / 6, (-3 * u ** 3 + 3 * u ** 2 + 3 * u + 1) / 6, (3 * u ** 3 - 6 * u ** 2 + 4) / 6,
+                (1 - u) ** 3 / 6][cell]
+        assert kan.bspline_exact(np.array([xv]), t, k)[0, m] == pytest.approx(want, abs=1e-12)
+
+
+def test_soft_bspline_with_exact_comparison_is_exact_at_knots():
+    """With S the exact comparison (1/2 at equality), Algorithm 2's order-0
+    products are 1/2 on both sides of a knot, and every order k >= 1 basis is
+    exact there; away from knots it equals Cox-de Boor."""
+    g, k = 4, 3
+    t = kan.make_knots(0.0, 1.0, g, k)
+    L = kan.Layer(1, 1, g, k, t, None, None, None, None, 0, 1, 1.0, [])
+    orig = kan.polycomp
+    try:
+        kan.polycomp = lambda v, stages: np.where(v > 0, 1.0, np.where(v < 0, 0.0, 0.5))
+        xs = np.concatenate([t[k:g + k + 1], [0.13, 0.5001, 0.77]])
+        soft = kan.soft_bspline(xs, L)
+        exact = kan.bspline_exact(xs, t, k)
+        exact[np.isclose(xs, 1.0)] = kan.bspline_exact(np.array([1.0 - 1e-13]), t, k)  # right end
+        assert np.abs(soft - exact).max() < 1e-9
+    finally:
+        kan.polycomp = orig
+
+
+def test_wls_matches_weighted_chebfit_and_ols():
+    from numpy.polynomial import chebyshev as C
+    lo, hi, deg, mu, sd = -3.0, 5.0, 11, 0.7, 0.9
+    coef = kan.wls_fit_silu(lo, hi, deg, mu, sd)
+    x = np.linspace(lo, hi, 4001)
+    u = (2 * x - (lo + hi)) / (hi - lo)
+    w = np.where(np.abs(x - mu) <= 3 * sd, 10.0, 1.0)
+    ref = C.chebfit(u, kan.silu(x), deg, w=np.sqrt(w))
+    assert np.abs(coef - ref).max() < 1e-9
+    # w = 1 everywhere (sigma huge) reduces to ordinary least squares
+    ols = kan.wls_fit_silu(lo, hi, deg, mu, 1e9)
+    assert np.abs(ols - C.chebfit(u, kan.silu(x), deg)).max() < 1e-9
+    # weighting lowers the error inside mu +- 3 sigma compared with OLS
+    inside = np.abs(x - mu) <= 3 * sd
+    err_w = np.abs(C.chebval(u, coef) - kan.silu(x))[inside].max()
+    err_o = np.abs(C.chebval(u, ols) - kan.silu(x))[inside].max()
+    assert err_w < err_o
+
+
+def test_chebyshev_range_clamps():
+    assert kan.approx_range(0.0, 1.0, -10.0, 10.0) == (-5.0, 5.0)
+    assert kan.approx_range(0.0, 1.0, -2.0, 10.0) == (-2.0, 5.0)
+    assert kan.approx_range(0.0, 1.0, -10.0, 3.0) == (-5.0, 3.0)
+    assert kan.approx_range(1.0, 0.1, 0.0, 1.2) == (0.5, 1.2)
+
+
+def test_alg3_maps_column_major_to_row_major():
+    for n_r, n_c in [(3, 4), (5, 2), (1, 6)]:
+        A = np.arange(n_r * n_c, dtype=float).reshape(n_r, n_c) + 1
+        Pm = kan.alg3_permutation(n_r, n_c)
+        vec_col = A.T.reshape(-1)   # ColTile order: column by column
+        vec_row = A.reshape(-1)     # row-major
+        assert (Pm @ vec_col == vec_row).all()
+        Wp = np.random.default_rng(0).normal(size=(2, n_r * n_c))
+        assert np.allclose((Wp @ Pm)[:, :], Wp[:, kan.alg3_index(n_r, n_c)])
+
+
+# --------------------------------------------------------------------------
+# the circuit on the slot simulator (packing, diagonals, polynomial splits)
+# --------------------------------------------------------------------------
+def test_repeat_packing_alg1():
+    sim = SlotSim(128)
+    x = np.arange(1, 6, dtype=float)
+    for g, k in [(5, 3), (3, 2), (2, 1)]:
+        nlog = circuit.clog2(g + 2 * k)
+        sim.count["rot"] = 0
+        out = circuit.repeat_pack(sim, sim.fresh(x, 5), 5, nlog)
+        assert sim.count["rot"] == math.ceil(math.log2(g + 2 * k))
+        want = np.zeros(128)
+        want[:5 * 2 ** nlog] = np.tile(x, 2 ** nlog)
+        assert (out.v == want).all()
+
+
+@pytest.mark.parametrize("n_out,n_in,slots", [(5, 7, 64), (10, 64, 512), (64, 784, 4096), (1, 8, 32)])
+def test_bsgs_matvec_equals_dense(n_out, n_in, slots):
+    rng = np.random.default_rng(n_out * n_in)
+    M = rng.normal(size=(n_out, n_in))
+    x = rng.normal(size=n_in)
+    sim = SlotSim(slots)
+    d = circuit.pow2ceil(n_out)
+    z = circuit.matvec_partial(sim, sim.fresh(x, 9), M, d, 5)
+    y = circuit.fold(sim, z, d)
+    full = np.tile(np.concatenate([M @ x, np.zeros(d - n_out)]), slots // d)
+    assert np.abs(y.v - full).max() < 1e-9
+    b1, g1 = circuit.bsgs_split(d)
+    assert b1 * g1 == d
+
+
+def test_chebyshev_bsgs_on_simulator():
+    rng = np.random.default_rng(3)
+    for deg in (15, 27, 31):
+        c = rng.normal(size=deg + 1) / (1 + np.arange(deg + 1)) ** 2
+        x = rng.uniform(-3, 2, 40)
+        sim = SlotSim(64)
+        out = circuit.cheb_eval(sim, sim.fresh(x, 20), c, -3.0, 2.0)
+        from numpy.polynomial import chebyshev as C
+        want = C.chebval((2 * x + 1) / 5, c)
+        assert np.abs(out.v[:40] - want).max() < 1e-9
+        # depth: affine map + ceil(log2(deg+1)) + 1 for the scalar leaves
+        assert out.level >= 20 - (1 + circuit.clog2(deg + 1) + 1)
+
+
+def test_odd_poly_depths_on_simulator():
+    sim = SlotSim(16)
+    x = np.linspace(-1, 1, 16)
+    for a, depth in [([1.5, -0.5], 2), ([1.875, -1.25, 0.375], 3), ([2.1875, -2.1875, 1.3125, -0.3125], 3)]:
+        out = circuit.odd_poly(sim, sim.fresh(x, 10), a)
+        assert out.level == 10 - depth
+        assert np.abs(out.v - kan.eval_odd(x, a)).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny", "image"])
+def test_circuit_on_simulator_equals_fp64_kan(name):
+    """The slot circuit (repeat packing, Algorithm 2 with rotations, fused
+    weights W_f = W'P, BSGS matvecs and folding) equals the plain HE-friendly
+    network, and fits the workload's level budget."""
+    wl = synth.WORKLOADS[name]
+    raw = synth.raw_weights(wl)
+    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * len(raw),
+                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range)
+    x = synth.inputs(wl, 2)
+    sim = SlotSim(1 << (wl.logN - 1))
+    for row in x:
+        ct = sim.fresh(row, wl.L)
+        refresh = (lambda c, li: SimCt(wl.L, c.v)) if wl.refresh else None
+        out = circuit.eval_kan(sim, ct, layers, refresh)
+        assert out.level >= 0
+        want = kan.he_friendly_kan(row[None], layers)[0]
+        assert np.abs(out.v[:len(want)] - want).max() < 1e-8 * max(1, np.abs(want).max())
+    assert sorted(sim.rot_steps) == sorted(set(circuit.rotation_steps(layers, sim.ctx.p.slots)) & sim.rot_steps)
+    assert set(circuit.rotation_steps(layers, sim.ctx.p.slots)) == sim.rot_steps
+
+
+def test_oracle_he_kan_tiny_matches_fp64_circuit():
+    """Encrypted inference on the oracle (tiny workload, client-aided refresh
+    between layers) decrypts to the FP64 HE-friendly circuit within 1e-2."""
+    wl = synth.WORKLOADS["tiny"]
+    raw = synth.raw_weights(wl)
+    layers = kan.compile_model(raw, synth.calibration_inputs(wl), [wl.silu_degree] * 2,
+                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range)
+    prm = Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+    ctx = ckks.Context(prm)
+    keys = ckks.Keys(ctx, synth.SEED_KEYGEN, circuit.rotation_steps(layers, prm.slots))
+    ev = ckks.Oracle(ctx, keys)
+    x = synth.inputs(wl, 1)[0]
+    out = circuit.eval_kan(ev, ev.encrypt(x, synth.SEED_ENC), layers,
+                           lambda c, li: ev.encrypt(ev.decrypt(c, prm.slots), 100 + li))
+    y = ev.decrypt(out, 1)
+    assert abs(y[0] - kan.he_friendly_kan(x[None], layers)[0, 0]) < 1e-2
