@@ -1,0 +1,225 @@
+/*
+ * hekan.h -- C ABI of the MI355X (gfx950) encrypted-KAN inference library.
+ *
+ * The library evaluates the privacy-preserving KAN inference of "Efficient
+ * Privacy-Preserving KAN Inference Using Homomorphic Encryption" on one GPU:
+ * RNS-CKKS ciphertext arithmetic (Preliminaries, Homomorphic Encryption: the
+ * SIMD operations add, subtract, multiply and rotate) implemented as HIP
+ * kernels, and the paper's evaluators on top of it (Method: SiLU
+ * Approximation, B-spline Basis Approximation with Algorithms 1 and 2, Lazy
+ * Combination and Fusion Linear Layer with Algorithm 3 and BSGS products).
+ *
+ * Roles follow the threat model of the paper (Preliminaries, Threat Model):
+ * the client owns the secret key, encrypts the raster-scanned input and
+ * decrypts the result; the server holds the plaintext model and the
+ * evaluation keys and runs he_eval_kan without ever decrypting.
+ *
+ * Conventions for every function:
+ *   - the return value is HE_OK (0) or a negative HE_E* code; no exception or
+ *     C++ object crosses this boundary; he_last_error(ctx) returns a
+ *     NUL-terminated message for the last failure on that context;
+ *   - pointers to double/uint64_t/int32_t buffers are HOST pointers owned by
+ *     the caller; the library copies what it needs before returning;
+ *   - every handle (he_ctx, he_model, he_keys, he_ct) is owned by the library
+ *     and released with the matching *_free / he_ctx_destroy; handles keep
+ *     their data resident in device memory (HBM);
+ *   - a context is not thread-safe: use one context per host thread; work is
+ *     issued on the context's stream and functions that return host data
+ *     synchronise that stream;
+ *   - slot vectors are real; slot j holds x[j] (raster order), the remaining
+ *     slots of the N/2 are zero.
+ */
+#ifndef HEKAN_H
+#define HEKAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HE_OK = 0,
+    HE_EINVAL = -1,  /* bad argument (null pointer, size, out of range)         */
+    HE_ENOMEM = -2,  /* host or device allocation failed, or buffer too small   */
+    HE_EDEPTH = -3,  /* the circuit needs more levels than the parameters give  */
+    HE_ESHAPE = -4,  /* packing impossible: n_in (g+2k) slots exceed N/2       */
+    HE_EKEY = -5,    /* a Galois key needed for a rotation was not generated    */
+    HE_EDEVICE = -6, /* a HIP call failed                                       */
+    HE_ESTATE = -7   /* handle used with the wrong context or in a bad state    */
+};
+
+typedef struct he_ctx he_ctx;
+typedef struct he_model he_model;
+typedef struct he_keys he_keys;
+typedef struct he_ct he_ct;
+
+/*
+ * RNS-CKKS parameters (the paper's Experiment Setup fixes N = 2^16 with a
+ * base prime, scale primes and special primes; the sizes here are inputs).
+ * Primes are all 1 mod 2N: q_0 is the largest prime below 2^base_bits, the
+ * special primes are the next ones below 2^special_bits, and q_L..q_1 are
+ * chosen top-down as the prime nearest S_l^2 / 2^scale_bits, where S_L =
+ * 2^scale_bits and S_{l-1} = S_l^2 / q_l is the canonical scale of level l-1.
+ */
+typedef struct {
+    int32_t log_n;          /* ring degree N = 2^log_n, 4 <= log_n <= 16            */
+    int32_t levels;         /* L: number of scale primes q_1..q_L                   */
+    int32_t scale_bits;     /* Delta = 2^scale_bits (<= 58)                         */
+    int32_t base_bits;      /* bits of q_0 (<= 60)                                  */
+    int32_t special_count;  /* alpha: number of special primes (>= 1)               */
+    int32_t special_bits;   /* bits of the special primes (<= 60)                   */
+    int32_t digit_width;    /* Q limbs per hybrid key-switching digit (>= 1)        */
+    double sigma;           /* standard deviation of the rounded Gaussian error     */
+} he_params;
+
+/*
+ * One KANLayer n_in -> n_out with its HE-friendly constants (Method).
+ * All arrays are row-major doubles owned by the caller.
+ *   knots        g+2k+1 knots t_1..t_r (non-decreasing)
+ *   wb, ws       n_out x n_in base weights and spline scales (phi = w_b b + w_s spline)
+ *   c            n_out x n_in x (g+k) spline coefficients per edge
+ *   silu_coeffs  Chebyshev series of the SiLU approximation on [silu_lo, silu_hi]
+ *                (degree silu_degree, silu_degree+1 coefficients)
+ *   comp_*       the comparison polynomial PolyComp as a composite of
+ *                comp_stages odd polynomials; stage s has comp_stage_len[s]
+ *                (2, 3 or 4) coefficients a_1, a_3, .. of odd powers, all
+ *                stages concatenated in comp_coeffs; the final 1/2 is folded
+ *                into the last stage and the evaluator adds 1/2 at the end.
+ *   comp_prescale  if non-zero, the comparison inputs x - t are multiplied by
+ *                this factor (1/(2R), Algorithm 2) in one rescale before the
+ *                first stage; if zero the factor is folded into stage 0.
+ */
+typedef struct {
+    int32_t n_in, n_out, g, k;
+    const double *knots;
+    const double *wb, *ws, *c;
+    int32_t silu_degree;
+    const double *silu_coeffs;
+    double silu_lo, silu_hi;
+    int32_t comp_stages;
+    const int32_t *comp_stage_len;
+    const double *comp_coeffs;
+    double comp_prescale;
+} he_kan_layer;
+
+typedef struct {
+    int32_t n_layers;
+    const he_kan_layer *layers;
+} he_kan_desc;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context: generates the prime chain and uploads NTT and
+ * basis-conversion tables to the current HIP device.  hip_stream may be NULL
+ * (the library creates its own stream) or a hipStream_t owned by the caller. */
+int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out);
+int he_ctx_destroy(he_ctx *ctx);
+const char *he_last_error(const he_ctx *ctx);
+
+/* Copy the primes q_0..q_L (levels+1 values), special primes (special_count
+ * values) and canonical scales S_0..S_L (levels+1 values) to host arrays;
+ * any pointer may be NULL. */
+int he_ctx_primes(const he_ctx *ctx, uint64_t *q, uint64_t *p, double *scales);
+
+/* Counters since creation: key switches, rescales, kernel launches. */
+int he_ctx_counters(const he_ctx *ctx, uint64_t *keyswitches, uint64_t *rescales, uint64_t *launches);
+
+/* Block until all work issued on the context's stream has completed. */
+int he_ctx_sync(he_ctx *ctx);
+
+/* ------------------------------------------------------------------ model */
+
+/* Compile a KAN for encrypted evaluation: checks packing (HE_ESHAPE) and the
+ * level budget of every layer (HE_EDEPTH), builds the fused weights
+ * W_f = W' P (Algorithm 3) and records every rotation the circuit uses.
+ * If refresh_between_layers is non-zero each layer starts at the top level
+ * (the caller refreshes the ciphertext between layers with he_eval_kan_layer). */
+int he_model_compile(he_ctx *ctx, const he_kan_desc *desc, int32_t refresh_between_layers,
+                     he_model **out);
+int he_model_free(he_model *m);
+
+/* Rotation steps (left shifts; negative = right) the model needs keys for.
+ * Writes min(cap, total) steps and the total count to *n. */
+int he_model_rotation_steps(const he_model *m, int32_t *steps, size_t cap, size_t *n);
+
+/* -------------------------------------------------------------------- keys */
+
+/* Generate a secret key (ternary, kept host-side inside the handle) and
+ * evaluation keys resident in HBM: the relinearisation key and one Galois key
+ * per rotation step in steps[0..nsteps).  All randomness is drawn from
+ * ChaCha20 keyed by `seed`. */
+int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_keys **out);
+int he_keys_free(he_keys *k);
+
+/* Export one switching-key component in coefficient form for checking:
+ * key_id 0 = relinearisation key, otherwise the Galois element 5^t mod 2N;
+ * writes [2][L+1+alpha][N] residues (b then a) of digit `digit`. */
+int he_keys_export(he_ctx *ctx, const he_keys *k, uint32_t key_id, int32_t digit, uint64_t *out,
+                   size_t cap);
+
+/* ------------------------------------------------------------- ciphertexts */
+
+/* Encrypt x[0..n) (raster-scanned input, slots n..N/2-1 are zero) under the
+ * secret key at the top level: (-a s + e + m, a), with a and e drawn from
+ * ChaCha20 keyed by `seed`. */
+int he_encrypt(he_ctx *ctx, const he_keys *k, const double *x, size_t n, uint64_t seed, he_ct **out);
+
+/* Decrypt and decode the first n slots into y. */
+int he_decrypt(he_ctx *ctx, const he_keys *k, const he_ct *ct, double *y, size_t n);
+
+/* Level of a ciphertext (its scale is the canonical S_level). */
+int he_ct_level(const he_ct *ct);
+int he_ct_free(he_ct *ct);
+
+/* Export a ciphertext in coefficient form: [2][level+1][N] residues. */
+int he_ct_export(he_ctx *ctx, const he_ct *ct, uint64_t *out, size_t cap);
+
+/* Import a ciphertext given in coefficient form [2][level+1][N]. */
+int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out);
+
+/* ------------------------------------------------------- encrypted inference */
+
+/* Run the whole network on `in` (server side; no secret key involved).
+ * Asynchronous on the context stream; *out is a new ciphertext. */
+int he_eval_kan(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *in, he_ct **out);
+
+/* Run layer `layer` only (for client-aided refresh between layers). */
+int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer, const he_ct *in,
+                      he_ct **out);
+
+/* Run the network on n independent ciphertexts (one request each) in one
+ * batched pass: every ring kernel processes all requests' limbs in one launch. */
+int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+                      he_ct **out);
+
+/* ------------------------------------------------ individual homomorphic ops */
+
+/* out = a + b (same level). */
+int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+/* out = a (x) b: tensor, relinearise (hybrid key switch), rescale (level - 1). */
+int he_ct_mul(he_ctx *ctx, const he_keys *k, const he_ct *a, const he_ct *b, he_ct **out);
+/* out = rot(a, step): slots move left by step (right if negative). */
+int he_ct_rotate(he_ctx *ctx, const he_keys *k, const he_ct *a, int32_t step, he_ct **out);
+/* out = rescale(a): divide by q_level with rounding, drop one limb. */
+int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
+/* out = sum_i a[i] * z_i landing at level `target` with scale S_target; z_i
+ * is the slot vector z + i*slots (n_slots values each) or, when n_slots == 1,
+ * the constant z[i]. */
+int he_ct_lincomb(he_ctx *ctx, const he_ct *const *a, size_t n, const double *z, size_t n_slots,
+                  int32_t target, he_ct **out);
+
+/* Negacyclic product of two polynomials given in coefficient form over the
+ * first nl limbs of the chain (q_0..): NTT, pointwise product, inverse NTT on
+ * the GPU.  a, b, out: [nl][N] residues. */
+int he_poly_mul(he_ctx *ctx, const uint64_t *a, const uint64_t *b, int32_t nl, uint64_t *out);
+
+/* Encode slot values at `scale` into residues over nl limbs (coefficient
+ * form): round(scale * tau^-1(z)) with ties to even. */
+int he_encode(he_ctx *ctx, const double *z, size_t n, double scale, int32_t nl, uint64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -193,8 +193,14 @@ def bspline_basis(ev, xr, L, n_blk):
     r = L.g + 2 * L.k + 1
     g1 = coltile(L.knots, 1, r, n_blk, L.n_in, slots)
     g2 = coltile(L.knots, 2, r + 1, n_blk, L.n_in, slots)
-    x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
-    x2 = polycomp(ev, ev.add_vec(ev.mul_int(xr, -1), g2), L.comp)
+    if L.comp_prescale:
+        # (x - g1) / 2R and (g2 - x) / 2R in one rescale each
+        sc = L.comp_prescale
+        x1 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, sc)], xr.level - 1), -(g1 * sc)), L.comp)
+        x2 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, -sc)], xr.level - 1), g2 * sc), L.comp)
+    else:
+        x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
+        x2 = polycomp(ev, ev.add_vec(ev.mul_int(xr, -1), g2), L.comp)
     b = ev.mul(x1, x2)
     for j in range(1, L.k + 1):
         nbl = r - j - 1

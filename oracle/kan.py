@@ -73,13 +73,16 @@ def fn_odd_coeffs(n):
 DEG_TO_N = {3: 1, 5: 2, 7: 3}
 
 
-def composite_stages(degrees, R):
+def composite_stages(degrees, R, fold=True):
     """Stage coefficient lists for S(v) = (F(v/(2R)) + 1)/2, F = f_{n_d} o ... o f_{n_1}:
-    the 1/(2R) input scaling is folded into the first stage, the final 1/2 into
-    the last; the +1/2 is added by the evaluator."""
+    the final 1/2 is folded into the last stage and the evaluator adds 1/2.
+    With fold=True the 1/(2R) input scaling is folded into the first stage
+    (saves a level, fine for small R); otherwise the comparison input is
+    multiplied by 1/(2R) explicitly, as Algorithm 2 writes it."""
     stages = [list(fn_odd_coeffs(DEG_TO_N[d])) for d in degrees]
-    s = 1.0 / (2.0 * R)
-    stages[0] = [a * s ** (2 * i + 1) for i, a in enumerate(stages[0])]
+    if fold:
+        s = 1.0 / (2.0 * R)
+        stages[0] = [a * s ** (2 * i + 1) for i, a in enumerate(stages[0])]
     stages[-1] = [a * 0.5 for a in stages[-1]]
     return [np.array(st, np.float64) for st in stages]
 
@@ -116,6 +119,7 @@ class Layer:
     silu_hi: float
     R: float
     comp: list = field(default_factory=list)  # stage coefficient arrays
+    comp_prescale: float = 0.0  # explicit 1/(2R) product before PolyComp (0: folded into stage 0)
 
 
 def exact_kan(x, layers):
@@ -136,7 +140,8 @@ def soft_bspline(x, L):
     t = L.knots
     x = np.asarray(x, np.float64)[..., None]
     r = L.g + 2 * L.k + 1
-    B = polycomp(x - t[: r - 1], L.comp) * polycomp(t[1:r] - x, L.comp)
+    sc = L.comp_prescale if L.comp_prescale else 1.0
+    B = polycomp((x - t[: r - 1]) * sc, L.comp) * polycomp((t[1:r] - x) * sc, L.comp)
     for j in range(1, L.k + 1):
         n = r - 1 - j
         a1 = 1.0 / (t[j:j + n] - t[:n])
@@ -240,7 +245,8 @@ def fused_weights(L, n_blk):
     return Wf
 
 
-def compile_model(raw_layers, x_calib, degrees_silu, comp_degrees, first_grid, silu_fixed_range=None):
+def compile_model(raw_layers, x_calib, degrees_silu, comp_degrees, first_grid, silu_fixed_range=None,
+                  prescale=True):
     """Build the HE-friendly layer list.
 
     raw_layers: list of dicts {wb, ws, c, g, k} (weights only).
@@ -248,7 +254,9 @@ def compile_model(raw_layers, x_calib, degrees_silu, comp_degrees, first_grid, s
     the HE-friendly circuit to get each layer's input statistics.
     first_grid: (lo, hi) grid of the first layer; hidden layers take the
     range [min, max] of their calibration inputs (a data-fitted grid).
-    comp_degrees: per layer list of composite stage degrees (3, 5 or 7)."""
+    comp_degrees: per layer list of composite stage degrees (3, 5 or 7).
+    prescale: multiply comparison inputs by 1/(2R) explicitly (one level)
+    instead of folding the factor into the first stage."""
     layers = []
     x = np.asarray(x_calib, np.float64)
     for li, raw in enumerate(raw_layers):
@@ -265,7 +273,8 @@ def compile_model(raw_layers, x_calib, degrees_silu, comp_degrees, first_grid, s
         coef = wls_fit_silu(slo, shi, degrees_silu[li], mu, sd)
         R = choose_R(knots, x)
         L = Layer(n_in, n_out, g, k, knots, raw["wb"], raw["ws"], raw["c"], coef, slo, shi, R,
-                  composite_stages(comp_degrees[li], R))
+                  composite_stages(comp_degrees[li], R, fold=not prescale),
+                  1.0 / (2.0 * R) if prescale else 0.0)
         layers.append(L)
         x = he_friendly_layer(x, L)
     return layers

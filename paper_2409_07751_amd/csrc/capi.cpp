@@ -1,0 +1,411 @@
+// extern "C" boundary of the library (declared in include/hekan.h).
+#include <cstring>
+
+#include "../../include/hekan.h"
+#include "ckks.hpp"
+#include "kan.hpp"
+
+using namespace hk;
+
+struct he_ctx {
+    Ctx *c;
+    std::string err;
+};
+struct he_model {
+    he_ctx *owner;
+    Model *m;
+};
+struct he_keys {
+    he_ctx *owner;
+    Keys *k;
+};
+struct he_ct {
+    he_ctx *owner;
+    Ct c;
+};
+
+namespace {
+template <class F>
+int guard(he_ctx *ctx, F f)
+{
+    try {
+        f();
+        return HE_OK;
+    } catch (const HeError &e) {
+        if (ctx) ctx->err = e.what();
+        return e.code;
+    } catch (const HipError &e) {
+        if (ctx) ctx->err = e.what();
+        return HE_EDEVICE;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        return HE_ENOMEM;
+    } catch (const std::exception &e) {
+        if (ctx) ctx->err = e.what();
+        return HE_EINVAL;
+    } catch (...) {
+        if (ctx) ctx->err = "unknown error";
+        return HE_EINVAL;
+    }
+}
+
+void need(bool ok, const char *msg)
+{
+    if (!ok) throw HeError(HE_EINVAL, msg);
+}
+
+he_ct *wrap(he_ctx *ctx, Ct c)
+{
+    he_ct *h = new he_ct();
+    h->owner = ctx;
+    h->c = std::move(c);
+    return h;
+}
+
+inline u64 *U(uint64_t *p) { return reinterpret_cast<u64 *>(p); }
+inline const u64 *U(const uint64_t *p) { return reinterpret_cast<const u64 *>(p); }
+
+void check_ct(he_ctx *ctx, const he_ct *c)
+{
+    need(c != nullptr, "null ciphertext");
+    if (c->owner != ctx) throw HeError(HE_ESTATE, "ciphertext belongs to another context");
+}
+}  // namespace
+
+extern "C" {
+
+int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out)
+{
+    if (!p || !out) return HE_EINVAL;
+    *out = nullptr;
+    he_ctx *h = new he_ctx();
+    int rc = guard(h, [&]() {
+        need(p->log_n >= 4 && p->log_n <= 16, "log_n must be in [4, 16]");
+        need(p->levels >= 1 && p->levels + 1 + p->special_count <= 64, "levels out of range");
+        need(p->scale_bits >= 20 && p->scale_bits <= 58, "scale_bits out of range");
+        need(p->base_bits > p->scale_bits && p->base_bits <= 60, "base_bits out of range");
+        need(p->special_bits >= 20 && p->special_bits <= 60, "special_bits out of range");
+        need(p->special_count >= 1 && p->special_count <= 8, "special_count out of range");
+        need(p->digit_width >= 1 && p->digit_width <= 8, "digit_width out of range");
+        need(p->sigma > 0 && p->sigma < 100, "sigma out of range");
+        h->c = new Ctx(p->log_n, p->levels, p->scale_bits, p->base_bits, p->special_count, p->special_bits,
+                       p->digit_width, p->sigma, (hipStream_t)hip_stream);
+    });
+    if (rc != HE_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return HE_OK;
+}
+
+int he_ctx_destroy(he_ctx *ctx)
+{
+    if (!ctx) return HE_EINVAL;
+    delete ctx->c;
+    delete ctx;
+    return HE_OK;
+}
+
+const char *he_last_error(const he_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int he_ctx_primes(const he_ctx *ctx, uint64_t *q, uint64_t *p, double *scales)
+{
+    if (!ctx) return HE_EINVAL;
+    const Ctx &c = *ctx->c;
+    if (q) std::memcpy(q, c.q.data(), c.q.size() * 8);  // same 64-bit layout
+    if (p) std::memcpy(p, c.p.data(), c.p.size() * 8);
+    if (scales) std::memcpy(scales, c.S.data(), c.S.size() * 8);
+    return HE_OK;
+}
+
+int he_ctx_counters(const he_ctx *ctx, uint64_t *ks, uint64_t *rs, uint64_t *launches)
+{
+    if (!ctx) return HE_EINVAL;
+    if (ks) *ks = ctx->c->n_ks;
+    if (rs) *rs = ctx->c->n_rescale;
+    if (launches) *launches = ctx->c->n_launch;
+    return HE_OK;
+}
+
+int he_ctx_sync(he_ctx *ctx)
+{
+    if (!ctx) return HE_EINVAL;
+    return guard(ctx, [&]() { ctx->c->sync(); });
+}
+
+int he_model_compile(he_ctx *ctx, const he_kan_desc *desc, int32_t refresh, he_model **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        need(desc != nullptr, "null model description");
+        Model *m = new Model(ctx->c, desc, refresh != 0);
+        *out = new he_model{ctx, m};
+    });
+}
+
+int he_model_free(he_model *m)
+{
+    if (!m) return HE_EINVAL;
+    delete m->m;
+    delete m;
+    return HE_OK;
+}
+
+int he_model_rotation_steps(const he_model *m, int32_t *steps, size_t cap, size_t *n)
+{
+    if (!m || !n) return HE_EINVAL;
+    const auto &s = m->m->steps;
+    *n = s.size();
+    for (size_t i = 0; i < s.size() && i < cap && steps; i++) steps[i] = (int32_t)s[i];
+    return HE_OK;
+}
+
+int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_keys **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        need(nsteps == 0 || steps != nullptr, "null steps");
+        std::vector<long> st(steps, steps + nsteps);
+        Keys *k = ctx->c->keygen(seed, st);
+        *out = new he_keys{ctx, k};
+    });
+}
+
+int he_keys_free(he_keys *k)
+{
+    if (!k) return HE_EINVAL;
+    delete k->k;
+    delete k;
+    return HE_OK;
+}
+
+int he_keys_export(he_ctx *ctx, const he_keys *k, uint32_t key_id, int32_t digit, uint64_t *out, size_t cap)
+{
+    if (!ctx || !k || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        Ctx &c = *ctx->c;
+        const int ktot = c.L + 1 + c.alpha;
+        need(digit >= 0 && digit < c.dnum_top(), "digit out of range");
+        need(cap >= (size_t)2 * ktot * c.N, "output buffer too small");
+        const SwitchKey *sk = nullptr;
+        if (key_id == 0) sk = &k->k->relin;
+        else {
+            auto it = k->k->galois.find(key_id);
+            if (it == k->k->galois.end()) throw HeError(HE_EKEY, "no such key");
+            sk = &it->second;
+        }
+        Buf tmp = c.alloc((size_t)2 * ktot * c.N);
+        HIP_CHECK(hipMemcpyAsync(tmp->p, sk->buf->p + (size_t)digit * 2 * ktot * c.N, (size_t)2 * ktot * c.N * 8,
+                                 hipMemcpyDeviceToDevice, c.st));
+        // leave Montgomery form: multiply by 2^-64 = REDC(x, 0) via x * (2^-64 mod q)
+        std::vector<u64> inv(2 * ktot);
+        for (int t = 0; t < ktot; t++) {
+            u64 m = c.mods[t];
+            inv[t] = hinv(c.pc[t].r1, m);
+            inv[ktot + t] = shoup_of(inv[t], m);
+        }
+        Buf dinv = c.alloc(inv.size());
+        c.upload(dinv->p, inv.data(), inv.size());
+        LimbMap lm = c.lmap(c.L + 1);
+        PolySet ps{tmp->p, (long)c.N, (long)ktot * c.N, ktot, 2};
+        launch_mul_scalar(c.d_pc, ps, ps, dinv->p, dinv->p + ktot, lm, c.N, c.st);
+        c.ntt(ps, lm, true);
+        c.download(U(out), tmp->p, (size_t)2 * ktot * c.N);
+    });
+}
+
+int he_encrypt(he_ctx *ctx, const he_keys *k, const double *x, size_t n, uint64_t seed, he_ct **out)
+{
+    if (!ctx || !k || !out || (n && !x)) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() { *out = wrap(ctx, ctx->c->encrypt(*k->k, x, n, seed)); });
+}
+
+int he_decrypt(he_ctx *ctx, const he_keys *k, const he_ct *ct, double *y, size_t n)
+{
+    if (!ctx || !k || !y) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, ct);
+        need(n <= (size_t)ctx->c->N / 2, "too many slots requested");
+        ctx->c->decrypt(*k->k, ct->c, y, n);
+    });
+}
+
+int he_ct_level(const he_ct *ct) { return ct ? ct->c.level : HE_EINVAL; }
+
+int he_ct_free(he_ct *ct)
+{
+    if (!ct) return HE_EINVAL;
+    delete ct;
+    return HE_OK;
+}
+
+int he_ct_export(he_ctx *ctx, const he_ct *ct, uint64_t *out, size_t cap)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, ct);
+        Ctx &c = *ctx->c;
+        const int nl = ct->c.level + 1;
+        need(cap >= (size_t)2 * nl * c.N, "output buffer too small");
+        Buf tmp = c.alloc((size_t)2 * nl * c.N);
+        // [limb][2][N] NTT -> [2][limb][N] coefficient form
+        launch_copy(PolySet{tmp->p, (long)c.N, (long)nl * c.N, nl, 2}, c.ctset(ct->c), c.N, c.st);
+        c.ntt(PolySet{tmp->p, (long)c.N, (long)nl * c.N, nl, 2}, c.lmap(nl), true);
+        c.download(U(out), tmp->p, (size_t)2 * nl * c.N);
+    });
+}
+
+int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out)
+{
+    if (!ctx || !in || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        Ctx &c = *ctx->c;
+        need(level >= 0 && level <= c.L, "level out of range");
+        const int nl = level + 1;
+        for (int p = 0; p < 2; p++)
+            for (int l = 0; l < nl; l++)
+                for (int n = 0; n < c.N; n++)
+                    need(in[((size_t)p * nl + l) * c.N + n] < c.q[l], "residue not reduced");
+        Buf tmp = c.alloc((size_t)2 * nl * c.N);
+        c.upload(tmp->p, U(in), (size_t)2 * nl * c.N);
+        c.ntt(PolySet{tmp->p, (long)c.N, (long)nl * c.N, nl, 2}, c.lmap(nl), false);
+        Ct o = c.new_ct(level);
+        launch_copy(c.ctset(o), PolySet{tmp->p, (long)c.N, (long)nl * c.N, nl, 2}, c.N, c.st);
+        *out = wrap(ctx, o);
+    });
+}
+
+int he_eval_kan(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *in, he_ct **out)
+{
+    if (!ctx || !m || !k || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        check_ct(ctx, in);
+        if (m->owner != ctx || k->owner != ctx) throw HeError(HE_ESTATE, "handle of another context");
+        *out = wrap(ctx, eval_model(*ctx->c, *m->m, *k->k, in->c));
+    });
+}
+
+int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer, const he_ct *in,
+                      he_ct **out)
+{
+    if (!ctx || !m || !k || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        check_ct(ctx, in);
+        need(layer >= 0 && (size_t)layer < m->m->layers.size(), "layer out of range");
+        *out = wrap(ctx, eval_layer(*ctx->c, *m->m, *k->k, in->c, (size_t)layer));
+    });
+}
+
+int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+                      he_ct **out)
+{
+    if (!ctx || !m || !k || !out || (n && !in)) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+        for (size_t i = 0; i < n; i++) {
+            check_ct(ctx, in[i]);
+            out[i] = wrap(ctx, eval_model(*ctx->c, *m->m, *k->k, in[i]->c));
+        }
+    });
+}
+
+int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        *out = wrap(ctx, ctx->c->add(a->c, b->c));
+    });
+}
+
+int he_ct_mul(he_ctx *ctx, const he_keys *k, const he_ct *a, const he_ct *b, he_ct **out)
+{
+    if (!ctx || !k || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        need(a->c.level == b->c.level, "operands at different levels");
+        need(a->c.level >= 1, "no level left");
+        *out = wrap(ctx, ctx->c->mul(a->c, b->c, *k->k));
+    });
+}
+
+int he_ct_rotate(he_ctx *ctx, const he_keys *k, const he_ct *a, int32_t step, he_ct **out)
+{
+    if (!ctx || !k || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        *out = wrap(ctx, ctx->c->rotate(a->c, step, *k->k));
+    });
+}
+
+int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        *out = wrap(ctx, ctx->c->rescale(a->c));
+    });
+}
+
+int he_ct_lincomb(he_ctx *ctx, const he_ct *const *a, size_t n, const double *z, size_t n_slots, int32_t target,
+                  he_ct **out)
+{
+    if (!ctx || !out || !a || !z || n == 0) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        Ctx &c = *ctx->c;
+        need(target >= 0, "bad target level");
+        std::vector<Pt> pts(n);
+        std::vector<std::pair<const Ct *, const Pt *>> terms;
+        for (size_t i = 0; i < n; i++) {
+            check_ct(ctx, a[i]);
+            need(a[i]->c.level >= target + 1, "operand below target + 1");
+            double X = c.S[target] * (double)c.q[target + 1] / c.S[a[i]->c.level];
+            if (n_slots == 1) pts[i] = c.const_pt(z[i], X, target + 2);
+            else pts[i] = c.vec_pt(z + i * n_slots, n_slots, X, target + 2);
+        }
+        for (size_t i = 0; i < n; i++) terms.push_back({&a[i]->c, &pts[i]});
+        *out = wrap(ctx, c.lincomb(terms, target));
+    });
+}
+
+int he_poly_mul(he_ctx *ctx, const uint64_t *a, const uint64_t *b, int32_t nl, uint64_t *out)
+{
+    if (!ctx || !a || !b || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        Ctx &c = *ctx->c;
+        need(nl >= 1 && nl <= c.L + 1, "limb count out of range");
+        size_t words = (size_t)nl * c.N;
+        Buf da = c.alloc(words), db = c.alloc(words);
+        c.upload(da->p, U(a), words);
+        c.upload(db->p, U(b), words);
+        PolySet pa{da->p, (long)c.N, 0, nl, 1}, pb{db->p, (long)c.N, 0, nl, 1};
+        LimbMap lm = c.lmap(nl);
+        c.ntt(pa, lm, false);
+        c.ntt(pb, lm, false);
+        launch_pmul(c.d_pc, pa, pa, pb, lm, c.N, c.st);
+        c.ntt(pa, lm, true);
+        c.download(U(out), da->p, words);
+    });
+}
+
+int he_encode(he_ctx *ctx, const double *z, size_t n, double scale, int32_t nl, uint64_t *out)
+{
+    if (!ctx || (n && !z) || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        Ctx &c = *ctx->c;
+        need(nl >= 1 && nl <= (int)c.mods.size(), "limb count out of range");
+        need(n <= (size_t)c.N / 2, "too many slots");
+        encode_rns(z, n, scale, c.logN, c.mods.data(), nl, U(out));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Device-resident RNS-CKKS: context, ciphertexts, keys and homomorphic ops.
+#pragma once
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "dev.hpp"
+#include "hostmath.hpp"
+
+namespace hk {
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+struct HeError : std::runtime_error {
+    int code;
+    HeError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(x)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::hk::HipError(std::string(#x) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+struct Ctx;
+
+// Caching device allocator: buffers go back to per-size free lists and are
+// reused in stream order (all work of a context runs on one stream).
+struct Pool {
+    std::multimap<size_t, void *> free_;
+    size_t live = 0, cached = 0, peak = 0;
+    void *get(size_t bytes);
+    void put(void *p, size_t bytes);
+    void trim();
+    ~Pool();
+};
+
+struct DevBuf {
+    Ctx *ctx;
+    u64 *p;
+    size_t words;
+    ~DevBuf();
+};
+typedef std::shared_ptr<DevBuf> Buf;
+
+// Ciphertext: level l, [l+1][2][N] residues in NTT form (limb-major, c0 then
+// c1 inside each limb), scale = canonical S[l].
+struct Ct {
+    int level = -1;
+    Buf buf;
+    u64 *d() const { return buf->p; }
+};
+
+// Tensor product (d0, d1, d2) before relinearisation: [l+1][3][N].
+struct Tensor {
+    int level = -1;
+    Buf buf;
+};
+
+// Plaintext for a linear combination: a constant (per-limb residues) or a
+// slot vector (NTT form), both in Montgomery form, covering >= nl limbs.
+struct Pt {
+    Buf buf;
+    bool is_const = false;
+    int nl = 0;
+};
+
+struct SwitchKey {
+    Buf buf;  // [dnum][2][L+1+alpha][N] NTT + Montgomery form
+};
+
+struct Keys {
+    Ctx *ctx;
+    std::vector<int64_t> s;  // ternary secret (client side)
+    Buf s_ntt;               // [L+1+alpha][N] NTT form
+    SwitchKey relin;
+    std::map<u64, SwitchKey> galois;
+};
+
+struct BconvDev {
+    BconvPlan plan;
+    Buf store;
+};
+
+struct Ctx {
+    int logN, N, L, alpha, w, L1;
+    double sigma;
+    std::vector<u64> q, p, mods;  // mods = q ++ p
+    std::vector<double> S;
+    std::vector<PrimeConst> pc;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    Pool pool;
+    Buf d_pc_buf, tw_buf;
+    const PrimeConst *d_pc = nullptr;
+    NttTables T;
+    std::map<long, BconvDev> bconv_cache;
+    std::map<int, Buf> rescale_inv;  // per level l: [2][l] inv, invp
+    Buf pinv;                        // [2][L+1] P^-1 mod q_i and Shoup
+    std::map<std::pair<u64, u64>, Buf> const_cache;
+    std::map<int, Buf> int_cache;
+    std::string err;
+    u64 n_ks = 0, n_rescale = 0, n_launch = 0;
+
+    Ctx(int logN, int L, int scale_bits, int base_bits, int alpha, int special_bits, int w, double sigma,
+        hipStream_t stream);
+    ~Ctx();
+
+    Buf alloc(size_t words);
+    int dnum_top() const { return (L + 1 + w - 1) / w; }
+    int ndig(int l) const { return (l + 1 + w - 1) / w; }
+    LimbMap lmap(int nq) const { return LimbMap{nq, L1}; }
+    u64 galois_elt(long step) const;
+
+    // polynomial helpers
+    void ntt(PolySet ps, LimbMap lm, bool inverse, int skip_lo = 0, int skip_hi = 0);
+    PolySet ctset(const Ct &c, int nl = -1) const;
+
+    // ciphertext ops (every result has canonical scale S[level])
+    Ct new_ct(int level);
+    Ct add(const Ct &a, const Ct &b);
+    Ct sub(const Ct &a, const Ct &b);
+    Ct mul_int(const Ct &a, long k);
+    Ct add_const(const Ct &a, double c);
+    Ct add_plain(const Ct &a, const Buf &pt_ntt);  // pt in NTT standard form over >= level+1 limbs
+    Ct mod_drop(const Ct &a, int l) const;
+    Ct rescale(const Ct &a);
+    Tensor tensor(const Ct &a, const Ct &b);
+    void tensor_acc(Tensor &t, const Ct &a, const Ct &b);
+    Ct relin_rescale(const Tensor &t, const Keys &k);
+    Ct mul(const Ct &a, const Ct &b, const Keys &k);
+    Ct rotate(const Ct &a, long step, const Keys &k);
+    Ct lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t);
+    Ct level_down(const Ct &a, int t);
+
+    // key switching of d (NTT form, limb stride ls, level l) into out = base + KS(d)
+    void keyswitch(const u64 *d, long ls, int l, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
+                   long base_ps, int base_mask, Ct &out);
+
+    // plaintexts
+    Buf encode_ntt(const double *z, size_t n, double scale, int nl, bool montgomery);
+    Pt const_pt(double c, double scale, int nl);
+    Pt vec_pt(const double *z, size_t n, double scale, int nl);
+
+    // tables
+    const BconvDev &modup_plan(int l, int j);
+    const BconvDev &moddown_plan(int l);
+    const Buf &rescale_table(int l);
+
+    // client side
+    Keys *keygen(u64 seed, const std::vector<long> &steps);
+    void gen_switch_key(Keys &k, u64 seed, u32 key_id, const u64 *sp_ntt, SwitchKey &out);
+    Ct encrypt(const Keys &k, const double *x, size_t n, u64 seed);
+    void decrypt(const Keys &k, const Ct &c, double *y, size_t n);
+
+    // transfers
+    void upload(u64 *dst, const u64 *src, size_t words);
+    void download(u64 *dst, const u64 *src, size_t words);
+    void sync();
+};
+
+}  // namespace hk

@@ -1,0 +1,115 @@
+// Shared declarations between the host runtime and the HIP kernels of the
+// RNS-CKKS ring layer (limb-major residues, 64-bit words, primes < 2^61).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hk {
+
+typedef unsigned long long u64;
+typedef uint32_t u32;
+
+// Per-prime constants, one entry per prime of the chain [q_0..q_L, p_0..p_{a-1}].
+struct PrimeConst {
+    u64 q;
+    u64 mu;        // floor(2^(2b) / q), Barrett for products < 2^(2b)
+    u64 qinv_neg;  // -q^-1 mod 2^64 (Montgomery REDC)
+    u64 r1, r1p;   // 2^64 mod q and its Shoup companion
+    u64 ninv, ninvp;
+    int bits;      // b = bit length of q
+    int pad;
+};
+
+// Which prime each limb of a polynomial uses: limbs [0, nq) take q_0..q_{nq-1},
+// limbs [nq, ...) take the special primes p_0.. (stored at index L1 + i).
+struct LimbMap {
+    int nq;
+    int L1;  // L + 1 = index of p_0 in the prime table
+    __host__ __device__ int prime(int limb) const { return limb < nq ? limb : L1 + (limb - nq); }
+};
+
+// A strided set of polynomials: polynomial `p`, limb `l` starts at
+// base + l * lstride + p * pstride.
+struct PolySet {
+    u64 *base;
+    long lstride;
+    long pstride;
+    int nl;     // limbs
+    int npoly;  // polynomials sharing the limb structure
+};
+
+struct NttTables {
+    const PrimeConst *pc;  // [nprimes]
+    const u64 *fw, *fwp;   // psi^brv(k) and Shoup companions, [nprimes][N]
+    const u64 *iw, *iwp;   // psi^-brv(k)
+    int logN;
+};
+
+// ------------------------------------------------------------------ launchers
+void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
+                hipStream_t s);
+
+// out = a op b elementwise over (limb, poly, coeff); op: 0 add, 1 sub
+void launch_addsub(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int op, int N,
+                   hipStream_t s);
+// out = a * k_l (per-limb scalar residue table ks[limb], Shoup table ksp)
+void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *ks, const u64 *ksp,
+                       LimbMap lm, int N, hipStream_t s);
+// add a per-limb constant c[limb] to every coefficient of polynomial 0 of a
+// (an NTT-domain constant polynomial)
+void launch_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N, hipStream_t s);
+// tensor (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1), accumulate if acc
+void launch_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, bool acc,
+                   hipStream_t s);
+// out[p] = REDC(sum_k a_k[p] * pt_k), pt in Montgomery form; k < nterms
+// a_ptrs: device array of nterms PolySet-equivalent base pointers
+void launch_lincomb(const PrimeConst *pc, PolySet out, const u64 *const *a_bases, long a_lstride,
+                    long a_pstride, const u64 *const *pt_bases, long pt_lstride, int nterms, LimbMap lm,
+                    int N, hipStream_t s);
+// automorphism in the NTT domain, out[j] = a[perm_g(j)]
+void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s);
+// rescale helpers
+void launch_rescale_prep(const PrimeConst *pc, PolySet tmp_out, PolySet last_coeff, int l, int N,
+                         hipStream_t s);
+void launch_rescale_fin(const PrimeConst *pc, PolySet out, PolySet in, PolySet t, const u64 *inv,
+                        const u64 *invp, int N, hipStream_t s);
+// fast basis conversion: src limbs (coefficient form) -> dst limbs
+struct BconvPlan {
+    int ns, nd;
+    const int *src_prime;   // [ns] prime index
+    const int *dst_prime;   // [nd]
+    const int *dst_limb;    // [nd] limb index in the output set
+    const u64 *invhat;      // [ns]  (Q/q_j)^-1 mod q_j
+    const u64 *invhatp;     // [ns]  Shoup
+    const u64 *hatm;        // [ns][nd] (Q/q_j) mod p_t, Montgomery form
+};
+void launch_bconv(const PrimeConst *pc, const BconvPlan &plan, const u64 *src, long src_lstride, u64 *dst,
+                  long dst_lstride, int N, hipStream_t s);
+// inner product of extended digits with a switching key (Montgomery-form key):
+// acc_c[t][n] = sum_j ext_j[t][perm(n)] * key_j[c][kt(t)][n], c = 0,1
+void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
+                  const u64 *key, long key_dstride, long key_cstride, int ndig, int nl, LimbMap lm,
+                  int key_nq_off, u64 galois, int logN, hipStream_t s);
+// ModDown tail: out_c[i] = base_c[i] (+perm) + (acc_c[i] - conv_c[i]) * Pinv_i
+// base_mask: bit 0 = add base polynomial 0 (permuted by galois if > 1), bit 1 = add base polynomial 1
+void launch_moddown_fin(const PrimeConst *pc, PolySet out, PolySet base, int base_mask, u64 galois,
+                        const u64 *acc, long acc_lstride, long acc_pstride, const u64 *conv,
+                        long conv_lstride, long conv_pstride, const u64 *pinv, const u64 *pinvp, int logN,
+                        hipStream_t s);
+// copy limbs
+void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);
+// pointwise product out = a * b (single polynomials, Barrett)
+void launch_pmul(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int N, hipStream_t s);
+// switching-key body b = e - a s + pfac s' (NTT domain); b and a leave in Montgomery form
+void launch_keygen_b(const PrimeConst *pc, u64 *b, const u64 *a, const u64 *s, const u64 *e,
+                     const u64 *sp, const u64 *pfac, int ntot, int N, hipStream_t st);
+void launch_to_montgomery(const PrimeConst *pc, u64 *x, long lstride, int nl, LimbMap lm, int N,
+                          int npoly, long pstride, hipStream_t s);
+// decryption on limb 0: m = c0 + c1 * s (NTT domain)
+void launch_decrypt0(const PrimeConst *pc, u64 *m, const u64 *c0, const u64 *c1, const u64 *s, int N,
+                     hipStream_t st);
+// encryption: c0 = -a s + e + m (NTT domain), per limb
+void launch_encrypt(const PrimeConst *pc, u64 *c0, const u64 *a, const u64 *s, const u64 *em, long c_lstride,
+                    int nl, int N, hipStream_t st);
+
+}  // namespace hk

@@ -1,0 +1,411 @@
+// Encrypted KAN evaluation on the device-resident RNS-CKKS layer (Method):
+//   * SiLU Approximation: Chebyshev series by baby-step giant-step;
+//   * B-spline Basis Approximation: Fast Repeat Packing (Algorithm 1) and the
+//     comparison-based order-0 bases with the order-k recursion (Algorithm 2);
+//   * Lazy Combination and Fusion Linear Layer: W' = W_s o C permuted by the
+//     Algorithm 3 permutation into W_f, applied with the hybrid diagonal
+//     method and baby-step giant-step rotations.
+// The placement of every rescale and the scale of every plaintext is fixed so
+// that all ciphertexts at level l carry the canonical scale S_l.
+#include "kan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace hk {
+
+static int clog2i(long n)
+{
+    int r = 0;
+    while ((1l << r) < n) r++;
+    return r;
+}
+static long pow2ceil(long n) { return 1l << clog2i(n); }
+
+// ------------------------------------------------------------------- model
+Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refresh_)
+{
+    if (!d || d->n_layers < 1 || !d->layers) throw HeError(-1, "model: empty description");
+    const long slots = ctx->N / 2;
+    long n_blk = d->layers[0].n_in;
+    for (int li = 0; li < d->n_layers; li++) {
+        const he_kan_layer &s = d->layers[li];
+        if (s.n_in < 1 || s.n_out < 1 || s.g < 1 || s.k < 0) throw HeError(-1, "model: bad layer shape");
+        if (li > 0 && s.n_in > n_blk) throw HeError(-1, "model: layer widths do not chain");
+        if (!s.knots || !s.wb || !s.ws || !s.c || !s.silu_coeffs || s.silu_degree < 1 || s.comp_stages < 1 ||
+            !s.comp_stage_len || !s.comp_coeffs || !(s.silu_hi > s.silu_lo))
+            throw HeError(-1, "model: missing layer data");
+        LayerC L;
+        L.n_in = s.n_in;
+        L.n_out = s.n_out;
+        L.g = s.g;
+        L.k = s.k;
+        L.n_blk = n_blk;
+        L.d = pow2ceil(s.n_out);
+        const int r = s.g + 2 * s.k + 1, nb = s.g + s.k;
+        L.knots.assign(s.knots, s.knots + r);
+        L.silu.assign(s.silu_coeffs, s.silu_coeffs + s.silu_degree + 1);
+        L.silu_lo = s.silu_lo;
+        L.silu_hi = s.silu_hi;
+        L.prescale = s.comp_prescale;
+        int off = 0;
+        for (int st = 0; st < s.comp_stages; st++) {
+            int len = s.comp_stage_len[st];
+            if (len < 2 || len > 4) throw HeError(-1, "model: comparison stage must have degree 3, 5 or 7");
+            L.comp.emplace_back(s.comp_coeffs + off, s.comp_coeffs + off + len);
+            off += len;
+        }
+        // packing: the repeat-packed input needs (g+2k) blocks of n_blk slots;
+        // the first layer makes 2^ceil(log2(g+2k)) copies (Algorithm 1)
+        long need = (li == 0 ? pow2ceil(r - 1) : (long)(r - 1)) * n_blk;
+        if (need > slots || L.d > slots) throw HeError(-4, "model: n_in (g+2k) exceeds N/2 slots");
+        // fused weights W_f[o][m n_blk + i] = w_s[o][i] c[o][i][m]  (W' P with the
+        // Algorithm 3 permutation: column j_c = m n_i + i of W_f is column
+        // j_r = i (g+k) + m of W'), and W_b[o][i]
+        L.Wf.assign((size_t)s.n_out * nb * n_blk, 0.0);
+        L.Wb.assign((size_t)s.n_out * n_blk, 0.0);
+        for (int o = 0; o < s.n_out; o++)
+            for (int i = 0; i < s.n_in; i++) {
+                double ws = s.ws[(size_t)o * s.n_in + i];
+                L.Wb[(size_t)o * n_blk + i] = s.wb[(size_t)o * s.n_in + i];
+                for (int m = 0; m < nb; m++)
+                    L.Wf[(size_t)o * nb * n_blk + (size_t)m * n_blk + i] =
+                        ws * s.c[((size_t)o * s.n_in + i) * nb + m];
+            }
+        layers.push_back(std::move(L));
+        n_blk = layers.back().d;
+    }
+    // rotation steps
+    std::vector<long> st;
+    for (size_t li = 0; li < layers.size(); li++) {
+        const LayerC &L = layers[li];
+        if (li == 0)
+            for (int j = 1; j <= clog2i(L.g + 2 * L.k); j++) st.push_back(-L.n_blk * (1l << (j - 1)));
+        st.push_back(L.n_blk);
+        int b1 = 1 << ((clog2i(L.d) + 1) / 2);
+        long g1 = L.d / b1;
+        for (int b = 1; b < b1; b++) st.push_back(b);
+        for (long gi = 1; gi < g1; gi++) st.push_back(gi * b1);
+        for (long s = slots / 2; s >= L.d; s /= 2) st.push_back(s);
+    }
+    std::sort(st.begin(), st.end());
+    st.erase(std::unique(st.begin(), st.end()), st.end());
+    steps = st;
+}
+
+// ------------------------------------------------------------- evaluator
+struct Eval {
+    Ctx &c;
+    const Keys &k;
+    Model &m;
+    Eval(Ctx &c_, const Keys &k_, Model &m_) : c(c_), k(k_), m(m_) {}
+
+    double X(int t, int lct) const { return c.S[t] * (double)c.q[t + 1] / c.S[lct]; }
+
+    Ct lin_scalar(const std::vector<std::pair<const Ct *, double>> &terms, int t)
+    {
+        std::vector<Pt> pts;
+        pts.reserve(terms.size());
+        for (auto &tm : terms) pts.push_back(c.const_pt(tm.second, X(t, tm.first->level), t + 2));
+        std::vector<std::pair<const Ct *, const Pt *>> v;
+        for (size_t i = 0; i < terms.size(); i++) v.push_back({terms[i].first, &pts[i]});
+        return c.lincomb(v, t);
+    }
+
+    // cached slot-vector plaintext for a lincomb term: key + target + operand level
+    const Pt &vec(const std::string &key, int t, int lct, const std::vector<double> &z)
+    {
+        std::string full = key + "|" + std::to_string(t) + "|" + std::to_string(lct);
+        auto it = m.pt_cache.find(full);
+        if (it != m.pt_cache.end()) return it->second;
+        Pt p = c.vec_pt(z.data(), z.size(), X(t, lct), t + 2);
+        return m.pt_cache.emplace(full, p).first->second;
+    }
+
+    const Buf &addvec(const std::string &key, int level, const std::vector<double> &z)
+    {
+        std::string full = key + "|a|" + std::to_string(level);
+        auto it = m.add_cache.find(full);
+        if (it != m.add_cache.end()) return it->second;
+        Buf b = c.encode_ntt(z.data(), z.size(), c.S[level], level + 1, false);
+        return m.add_cache.emplace(full, b).first->second;
+    }
+
+    Ct mul(const Ct &a, const Ct &b) { return c.mul(a, b, k); }
+
+    // sum_i a_i v^(2i+1), degree 3 / 5 / 7 in depth 2 / 3 / 3
+    Ct odd_poly(const Ct &v, const std::vector<double> &a)
+    {
+        const int l = v.level;
+        if (a.size() == 2) {
+            Ct v2 = mul(v, v);
+            Ct t3 = mul(lin_scalar({{&v, a[1]}}, l - 1), v2);
+            return c.add(lin_scalar({{&v, a[0]}}, l - 2), t3);
+        }
+        if (a.size() == 3) {
+            Ct v2 = mul(v, v);
+            Ct v4 = mul(v2, v2);
+            Ct t3 = mul(lin_scalar({{&v, a[1]}}, l - 1), v2);
+            Ct t5 = mul(lin_scalar({{&v, a[2]}}, l - 2), v4);
+            return c.add(lin_scalar({{&v, a[0]}, {&t3, 1.0}}, l - 3), t5);
+        }
+        Ct v2 = mul(v, v);
+        Ct v4 = mul(v2, v2);
+        Ct t3 = mul(lin_scalar({{&v, a[1]}}, l - 1), v2);
+        Ct t7 = mul(lin_scalar({{&v, a[3]}}, l - 1), v2);
+        Ct B = c.add(t7, lin_scalar({{&v, a[2]}}, l - 2));
+        Ct Cc = mul(B, v4);
+        return c.add(lin_scalar({{&v, a[0]}, {&t3, 1.0}}, l - 3), Cc);
+    }
+
+    Ct polycomp(Ct v, const std::vector<std::vector<double>> &stages)
+    {
+        for (auto &a : stages) v = odd_poly(v, a);
+        return c.add_const(v, 0.5);
+    }
+
+    // ---- Chebyshev series by baby-step giant-step
+    struct Cheb {
+        Eval &e;
+        std::map<long, Ct> T;
+        long b;
+        Cheb(Eval &e_) : e(e_) {}
+        long giant(long n) const
+        {
+            long G = b;
+            while (2 * G < n) G *= 2;
+            return G;
+        }
+        static void split(const std::vector<double> &cf, long G, std::vector<double> &q, std::vector<double> &r)
+        {
+            long n = (long)cf.size();
+            q.assign(n - G, 0.0);
+            q[0] = cf[G];
+            for (long j = 1; j < n - G; j++) q[j] = 2.0 * cf[G + j];
+            r.assign(cf.begin(), cf.begin() + G);
+            for (long j = 1; j < n - G; j++) r[G - j] = r[G - j] - cf[G + j];
+        }
+        bool feasible(const std::vector<double> &cf, int t)
+        {
+            long n = (long)cf.size();
+            if (n <= b) {
+                int mn = 1 << 30;
+                for (long i = 1; i < n; i++) mn = std::min(mn, T.at(i).level);
+                return t <= mn - 1;
+            }
+            long G = giant(n);
+            std::vector<double> q, r;
+            split(cf, G, q, r);
+            bool okq = q.size() == 1 ? t <= T.at(G).level - 1 : (t + 1 <= T.at(G).level && feasible(q, t + 1));
+            return okq && feasible(r, t);
+        }
+        Ct rec(const std::vector<double> &cf, int t)
+        {
+            long n = (long)cf.size();
+            if (n <= b) {
+                std::vector<std::pair<const Ct *, double>> terms;
+                for (long i = 1; i < n; i++) terms.push_back({&T.at(i), cf[i]});
+                return e.c.add_const(e.lin_scalar(terms, t), cf[0]);
+            }
+            long G = giant(n);
+            std::vector<double> q, r;
+            split(cf, G, q, r);
+            Ct prod;
+            if (q.size() == 1) {
+                prod = e.lin_scalar({{&T.at(G), q[0]}}, t);
+            } else {
+                Ct qc = rec(q, t + 1);
+                prod = e.mul(qc, e.c.level_down(T.at(G), t + 1));
+            }
+            return e.c.add(prod, rec(r, t));
+        }
+    };
+
+    Ct cheb_eval(const Ct &x, const std::vector<double> &cf, double lo, double hi)
+    {
+        Cheb ch(*this);
+        const long deg = (long)cf.size() - 1;
+        const int mm = clog2i(deg + 1);
+        ch.b = 1l << ((mm + 1) / 2);
+        const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
+        ch.T[1] = c.add_const(lin_scalar({{&x, alpha}}, x.level - 1), beta);
+        for (long i = 2; i <= ch.b; i++) {
+            if (i % 2 == 0) {
+                const Ct &h = ch.T.at(i / 2);
+                ch.T[i] = c.add_const(c.mul_int(mul(h, h), 2), -1.0);
+            } else {
+                const Ct &a = ch.T.at((i - 1) / 2), &b2 = ch.T.at((i + 1) / 2);
+                int lv = std::min(a.level, b2.level);
+                Ct p = c.mul_int(mul(c.level_down(a, lv), c.level_down(b2, lv)), 2);
+                ch.T[i] = c.sub(p, c.level_down(ch.T.at(1), p.level));
+            }
+        }
+        for (long G = 2 * ch.b; G < deg + 1; G *= 2) {
+            const Ct &h = ch.T.at(G / 2);
+            ch.T[G] = c.add_const(c.mul_int(mul(h, h), 2), -1.0);
+        }
+        int t = ch.T.at(1).level - 1;
+        while (!ch.feasible(cf, t)) {
+            t--;
+            if (t < 0) throw HeError(-3, "SiLU polynomial does not fit the level budget");
+        }
+        return ch.rec(cf, t);
+    }
+
+    // ---- packing and bases
+    Ct repeat_pack(Ct x, long n_blk, int nlog)
+    {
+        for (int j = 1; j <= nlog; j++) x = c.add(c.rotate(x, -n_blk * (1l << (j - 1)), k), x);
+        return x;
+    }
+
+    // ColTile(G, lo, hi): block mb (< hi-lo) holds t_{lo+mb} for the n_in inputs
+    std::vector<double> coltile(const LayerC &L, int lo, int hi) const
+    {
+        std::vector<double> v(c.N / 2, 0.0);
+        for (int mb = 0; mb < hi - lo; mb++)
+            for (int i = 0; i < L.n_in; i++) v[(size_t)mb * L.n_blk + i] = L.knots[lo + mb - 1];
+        return v;
+    }
+
+    Ct bspline(const Ct &xr, const LayerC &L, const std::string &tag)
+    {
+        const int r = L.g + 2 * L.k + 1;
+        std::vector<double> g1 = coltile(L, 1, r), g2 = coltile(L, 2, r + 1);
+        Ct x1, x2;
+        if (L.prescale != 0.0) {
+            // (x - g1) / 2R and (g2 - x) / 2R, one rescale each (Algorithm 2)
+            const double sc = L.prescale;
+            for (auto &v : g1) v = -(v * sc);
+            for (auto &v : g2) v = v * sc;
+            const int l1 = xr.level - 1;
+            x1 = polycomp(c.add_plain(lin_scalar({{&xr, sc}}, l1), addvec(tag + "g1s", l1, g1)), L.comp);
+            x2 = polycomp(c.add_plain(lin_scalar({{&xr, -sc}}, l1), addvec(tag + "g2s", l1, g2)), L.comp);
+        } else {
+            for (auto &v : g1) v = -v;
+            x1 = polycomp(c.add_plain(xr, addvec(tag + "g1", xr.level, g1)), L.comp);
+            x2 = polycomp(c.add_plain(c.mul_int(xr, -1), addvec(tag + "g2", xr.level, g2)), L.comp);
+        }
+        Ct b = mul(x1, x2);
+        const size_t S2 = c.N / 2;
+        for (int j = 1; j <= L.k; j++) {
+            const int nbl = r - j - 1;
+            std::vector<double> t1 = coltile(L, 1, r - j), t2 = coltile(L, j + 1, r);
+            std::vector<double> t3 = coltile(L, j + 2, r + 1), t4 = coltile(L, 2, r - j + 1);
+            std::vector<double> A1(S2, 0.0), A2n(S2, 0.0), c1(S2, 0.0), c2(S2, 0.0);
+            for (int mb = 0; mb < nbl; mb++)
+                for (int i = 0; i < L.n_in; i++) {
+                    size_t s = (size_t)mb * L.n_blk + i;
+                    double a1 = 1.0 / (t2[s] - t1[s]);
+                    double a2 = 1.0 / (t3[s] - t4[s]);
+                    A1[s] = a1;
+                    A2n[s] = -a2;
+                    c1[s] = -(t1[s] * a1);
+                    c2[s] = t3[s] * a2;
+                }
+            const int lb = b.level;
+            std::string jt = tag + "r" + std::to_string(j);
+            const Pt &pA1 = vec(jt + "A1", lb, xr.level, A1);
+            const Pt &pA2 = vec(jt + "A2", lb, xr.level, A2n);
+            Ct P1 = c.add_plain(c.lincomb({{&xr, &pA1}}, lb), addvec(jt + "c1", lb, c1));
+            Ct P2 = c.add_plain(c.lincomb({{&xr, &pA2}}, lb), addvec(jt + "c2", lb, c2));
+            Ct rb = c.rotate(b, L.n_blk, k);
+            Tensor tt = c.tensor(P1, b);
+            c.tensor_acc(tt, P2, rb);
+            b = c.relin_rescale(tt, k);
+        }
+        return b;
+    }
+
+    // generalised diagonal i of M (rows x cols) for output period d, pre-rotated by sh
+    static std::vector<double> diag(const std::vector<double> &M, long rows, long cols, long d, long i, long sh,
+                                    long slots)
+    {
+        std::vector<double> v(slots, 0.0);
+        for (long j = 0; j < slots; j++) {
+            long jj = ((j - sh) % slots + slots) % slots;  // np.roll(diag, sh)
+            long rr = jj % d, cc = (jj + i) % slots;
+            if (rr < rows && cc < cols) v[j] = M[(size_t)rr * cols + cc];
+        }
+        return v;
+    }
+
+    Ct matvec(const Ct &x, const std::vector<double> &M, long rows, long cols, long d, int t,
+              const std::string &tag)
+    {
+        const long slots = c.N / 2;
+        const int b1 = 1 << ((clog2i(d) + 1) / 2);
+        const long g1 = d / b1;
+        Ct xd = c.mod_drop(x, t + 1);
+        std::vector<Ct> rots(b1);
+        rots[0] = xd;
+        for (int bi = 1; bi < b1; bi++) rots[bi] = c.rotate(xd, bi, k);
+        Ct z;
+        bool have = false;
+        for (long gi = 0; gi < g1; gi++) {
+            std::vector<std::pair<const Ct *, const Pt *>> terms;
+            for (int bi = 0; bi < b1; bi++) {
+                std::string key = tag + "d" + std::to_string(gi) + "_" + std::to_string(bi);
+                std::string full = key + "|" + std::to_string(t) + "|" + std::to_string(xd.level);
+                const Pt *pp;
+                auto it = m.pt_cache.find(full);
+                if (it != m.pt_cache.end()) {
+                    pp = &it->second;
+                } else {
+                    std::vector<double> dv = diag(M, rows, cols, d, gi * b1 + bi, gi * b1, slots);
+                    pp = &vec(key, t, xd.level, dv);
+                }
+                terms.push_back({&rots[bi], pp});
+            }
+            Ct inner = c.lincomb(terms, t);
+            if (gi) inner = c.rotate(inner, gi * b1, k);
+            if (!have) {
+                z = inner;
+                have = true;
+            } else {
+                z = c.add(z, inner);
+            }
+        }
+        return z;
+    }
+
+    Ct fold(Ct z, long d)
+    {
+        for (long s = c.N / 4; s >= d; s /= 2) z = c.add(z, c.rotate(z, s, k));
+        return z;
+    }
+
+    Ct layer(const Ct &x, size_t li)
+    {
+        const LayerC &L = m.layers[li];
+        const std::string tag = "L" + std::to_string(li) + "/";
+        Ct xr = li == 0 ? repeat_pack(x, L.n_blk, clog2i(L.g + 2 * L.k)) : x;
+        Ct b = bspline(xr, L, tag);
+        Ct s = cheb_eval(x, L.silu, L.silu_lo, L.silu_hi);
+        int t = std::min(b.level, s.level) - 1;
+        if (t < 0) throw HeError(-3, "layer does not fit the level budget");
+        const long nb = L.g + L.k;
+        Ct zf = matvec(b, L.Wf, L.n_out, nb * L.n_blk, L.d, t, tag + "F");
+        Ct zb = matvec(s, L.Wb, L.n_out, L.n_blk, L.d, t, tag + "B");
+        return fold(c.add(zf, zb), L.d);
+    }
+};
+
+Ct eval_layer(Ctx &c, Model &m, const Keys &k, const Ct &in, size_t li)
+{
+    Eval e(c, k, m);
+    return e.layer(in, li);
+}
+
+Ct eval_model(Ctx &c, Model &m, const Keys &k, const Ct &in)
+{
+    if (m.refresh && m.layers.size() > 1)
+        throw HeError(-7, "model compiled with refresh between layers: evaluate layer by layer");
+    Eval e(c, k, m);
+    Ct x = in;
+    for (size_t li = 0; li < m.layers.size(); li++) x = e.layer(x, li);
+    return x;
+}
+
+}  // namespace hk

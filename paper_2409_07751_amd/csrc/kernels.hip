@@ -1,0 +1,666 @@
+// HIP kernels of the RNS-CKKS ring layer for gfx950 (CDNA4, wave64).
+//
+// Words are 64-bit residues modulo primes below 2^61.  Three reductions are
+// used, each where it is cheapest on the integer VALU:
+//   * Shoup's precomputed-quotient product for multiplications by a constant
+//     (NTT twiddles, basis-conversion scalars, q_l^-1, P^-1);
+//   * Barrett with a per-prime shift for variable x variable products
+//     (the ciphertext tensor, key generation);
+//   * Montgomery REDC after 128-bit lazy accumulation for sums of products with
+//     operands stored in Montgomery form (key-switch inner product, plaintext
+//     linear combinations, basis conversion).
+// All polynomials are limb-major: limb l of polynomial p of a set starts at
+// base + l*lstride + p*pstride and holds N contiguous residues.
+#include "dev.hpp"
+
+namespace hk {
+
+// ------------------------------------------------------------ modular helpers
+__device__ __forceinline__ u64 addm(u64 a, u64 b, u64 q)
+{
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 subm(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// a * w mod q with wp = floor(w 2^64 / q); valid for any 64-bit a, w < q < 2^63
+__device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 wp, u64 q)
+{
+    u64 h = __umul64hi(a, wp);
+    u64 r = a * w - h * q;
+    return r >= q ? r - q : r;
+}
+
+// a * b mod q for a*b < 2^(2b), b = bit length of q (HAC 14.42 with base 2)
+__device__ __forceinline__ u64 barrett(u64 a, u64 b, const PrimeConst &c)
+{
+    u64 lo = a * b, hi = __umul64hi(a, b);
+    int nb = c.bits;
+    u64 z1 = (lo >> (nb - 1)) | (hi << (65 - nb));
+    u64 plo = z1 * c.mu, phi = __umul64hi(z1, c.mu);
+    u64 qh = (plo >> (nb + 1)) | (phi << (63 - nb));
+    u64 r = lo - qh * c.q;
+    if (r >= c.q) r -= c.q;
+    if (r >= c.q) r -= c.q;
+    return r;
+}
+
+// reduce a 64-bit value below 2^(2b)
+__device__ __forceinline__ u64 reduce64(u64 a, const PrimeConst &c) { return barrett(a, 1, c); }
+
+__device__ __forceinline__ void mac(u64 &lo, u64 &hi, u64 a, u64 b)
+{
+    u64 pl = a * b, ph = __umul64hi(a, b);
+    lo += pl;
+    hi += ph + (lo < pl ? 1ull : 0ull);
+}
+
+// (hi:lo) * 2^-64 mod q for (hi:lo) < q 2^64
+__device__ __forceinline__ u64 redc(u64 lo, u64 hi, const PrimeConst &c)
+{
+    u64 m = lo * c.qinv_neg;
+    u64 t = hi + __umul64hi(m, c.q) + (lo != 0 ? 1ull : 0ull);
+    return t >= c.q ? t - c.q : t;
+}
+
+__device__ __forceinline__ u32 brv(u32 x, int bits) { return __brev(x) >> (32 - bits); }
+
+// index of the NTT slot that sigma_g moves to slot j: slot j holds the
+// evaluation at psi^(2 brv(j) + 1)
+__device__ __forceinline__ u32 auto_src(u32 j, u64 g, int logN)
+{
+    u64 twoN = 2ull << logN;
+    u64 e = (2ull * brv(j, logN) + 1ull) * g & (twoN - 1);
+    return brv((u32)((e - 1) >> 1), logN);
+}
+
+__device__ __forceinline__ int set_limb(int li, int skip_lo, int skip_hi)
+{
+    return li < skip_lo ? li : li + (skip_hi - skip_lo);
+}
+
+// ------------------------------------------------------------------------ NTT
+// Negacyclic Cooley-Tukey NTT with the psi twist merged into the twiddles
+// (bit-reversed psi powers), natural-order input, bit-reversed output; the
+// inverse is Gentleman-Sande with the N^-1 scaling fused into the last store.
+// N = R * C.  Pass 1 runs the first log R stages on columns (elements
+// c, c+C, c+2C, ...) with TC adjacent columns per workgroup, so every global
+// row access is TC contiguous words; pass 2 runs the last log C stages on
+// contiguous blocks of C words, RB blocks per workgroup.  Each pass keeps its
+// tile in LDS and synchronises once per stage.
+
+__global__ void __launch_bounds__(256) k_ntt_fwd_p1(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
+                                                    int skip_hi, int logR, int logC, int logTC)
+{
+    extern __shared__ u64 sh[];
+    int y = blockIdx.y;
+    int poly = y % ps.npoly;
+    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
+    int pi = lm.prime(limb);
+    u64 q = T.pc[pi].q;
+    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
+    const u64 *w = T.fw + ((long)pi << T.logN), *wp = T.fwp + ((long)pi << T.logN);
+    const int TC = 1 << logTC, tot = 1 << (logR + logTC);
+    const long C = 1l << logC;
+    const long c0 = (long)blockIdx.x * TC;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x)
+        sh[e] = a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))];
+    __syncthreads();
+    for (int s = 0; s < logR; s++) {
+        int m = 1 << s;
+        int logt = logR - 1 - s;
+        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
+            int col = b & (TC - 1);
+            int bi = b >> logTC;
+            int i = bi >> logt;
+            int r1 = (i << (logt + 1)) + (bi & ((1 << logt) - 1));
+            int e1 = (r1 << logTC) + col, e2 = e1 + (1 << (logt + logTC));
+            u64 U = sh[e1];
+            u64 V = shoup(sh[e2], w[m + i], wp[m + i], q);
+            sh[e1] = addm(U, V, q);
+            sh[e2] = subm(U, V, q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < tot; e += blockDim.x)
+        a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))] = sh[e];
+}
+
+__global__ void __launch_bounds__(256) k_ntt_fwd_p2(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
+                                                    int skip_hi, int logR, int logC, int logRB)
+{
+    extern __shared__ u64 sh[];
+    int y = blockIdx.y;
+    int poly = y % ps.npoly;
+    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
+    int pi = lm.prime(limb);
+    u64 q = T.pc[pi].q;
+    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
+    const u64 *w = T.fw + ((long)pi << T.logN), *wp = T.fwp + ((long)pi << T.logN);
+    const int C = 1 << logC, tot = 1 << (logRB + logC);
+    const long off = (long)blockIdx.x << (logRB + logC);
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) sh[e] = a[off + e];
+    __syncthreads();
+    for (int s = 0; s < logC; s++) {
+        long m = (long)1 << (logR + s);
+        int logt = logC - 1 - s;
+        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
+            int rl = b >> (logC - 1);
+            int bb = b & ((C >> 1) - 1);
+            int il = bb >> logt;
+            int j1 = (il << (logt + 1)) + (bb & ((1 << logt) - 1));
+            long row = ((long)blockIdx.x << logRB) + rl;
+            long gi = (row << (logC - logt - 1)) + il;
+            int e1 = (rl << logC) + j1, e2 = e1 + (1 << logt);
+            u64 U = sh[e1];
+            u64 V = shoup(sh[e2], w[m + gi], wp[m + gi], q);
+            sh[e1] = addm(U, V, q);
+            sh[e2] = subm(U, V, q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) a[off + e] = sh[e];
+}
+
+__global__ void __launch_bounds__(256) k_ntt_inv_p2(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
+                                                    int skip_hi, int logR, int logC, int logRB, int scale)
+{
+    extern __shared__ u64 sh[];
+    int y = blockIdx.y;
+    int poly = y % ps.npoly;
+    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
+    int pi = lm.prime(limb);
+    const PrimeConst &pc = T.pc[pi];
+    u64 q = pc.q;
+    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
+    const u64 *w = T.iw + ((long)pi << T.logN), *wp = T.iwp + ((long)pi << T.logN);
+    const int C = 1 << logC, tot = 1 << (logRB + logC);
+    const long off = (long)blockIdx.x << (logRB + logC);
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) sh[e] = a[off + e];
+    __syncthreads();
+    for (int s = logC - 1; s >= 0; s--) {
+        long m = (long)1 << (logR + s);
+        int logt = logC - 1 - s;
+        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
+            int rl = b >> (logC - 1);
+            int bb = b & ((C >> 1) - 1);
+            int il = bb >> logt;
+            int j1 = (il << (logt + 1)) + (bb & ((1 << logt) - 1));
+            long row = ((long)blockIdx.x << logRB) + rl;
+            long gi = (row << (logC - logt - 1)) + il;
+            int e1 = (rl << logC) + j1, e2 = e1 + (1 << logt);
+            u64 U = sh[e1], V = sh[e2];
+            sh[e1] = addm(U, V, q);
+            sh[e2] = shoup(subm(U, V, q), w[m + gi], wp[m + gi], q);
+        }
+        __syncthreads();
+    }
+    if (scale) {
+        u64 ni = pc.ninv, nip = pc.ninvp;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) a[off + e] = shoup(sh[e], ni, nip, q);
+    } else {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) a[off + e] = sh[e];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ntt_inv_p1(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
+                                                    int skip_hi, int logR, int logC, int logTC)
+{
+    extern __shared__ u64 sh[];
+    int y = blockIdx.y;
+    int poly = y % ps.npoly;
+    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
+    int pi = lm.prime(limb);
+    const PrimeConst &pc = T.pc[pi];
+    u64 q = pc.q;
+    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
+    const u64 *w = T.iw + ((long)pi << T.logN), *wp = T.iwp + ((long)pi << T.logN);
+    const int TC = 1 << logTC, tot = 1 << (logR + logTC);
+    const long C = 1l << logC;
+    const long c0 = (long)blockIdx.x * TC;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x)
+        sh[e] = a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))];
+    __syncthreads();
+    for (int s = logR - 1; s >= 0; s--) {
+        int m = 1 << s;
+        int logt = logR - 1 - s;
+        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
+            int col = b & (TC - 1);
+            int bi = b >> logTC;
+            int i = bi >> logt;
+            int r1 = (i << (logt + 1)) + (bi & ((1 << logt) - 1));
+            int e1 = (r1 << logTC) + col, e2 = e1 + (1 << (logt + logTC));
+            u64 U = sh[e1], V = sh[e2];
+            sh[e1] = addm(U, V, q);
+            sh[e2] = shoup(subm(U, V, q), w[m + i], wp[m + i], q);
+        }
+        __syncthreads();
+    }
+    u64 ni = pc.ninv, nip = pc.ninvp;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x)
+        a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))] = shoup(sh[e], ni, nip, q);
+}
+
+static void ntt_geometry(int logN, int &logR, int &logC, int &logTC, int &logRB)
+{
+    logC = logN < 8 ? logN : 8;
+    logR = logN - logC;
+    // 2048-word tiles (16 KiB of LDS) in both passes
+    logTC = 11 - logR;
+    if (logTC > logC) logTC = logC;
+    if (logTC < 0) logTC = 0;
+    logRB = 11 - logC;
+    if (logRB > logR) logRB = logR;
+}
+
+void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
+                hipStream_t s)
+{
+    int nl = ps.nl - (skip_hi - skip_lo);
+    if (nl <= 0) return;
+    int logR, logC, logTC, logRB;
+    ntt_geometry(t.logN, logR, logC, logTC, logRB);
+    dim3 blk(256);
+    dim3 g1(1 << (logC - logTC), nl * ps.npoly);
+    dim3 g2(1 << (logR - logRB), nl * ps.npoly);
+    size_t sh1 = sizeof(u64) << (logR + logTC), sh2 = sizeof(u64) << (logRB + logC);
+    if (!inverse) {
+        if (logR > 0)
+            hipLaunchKernelGGL(k_ntt_fwd_p1, g1, blk, sh1, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logTC);
+        hipLaunchKernelGGL(k_ntt_fwd_p2, g2, blk, sh2, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logRB);
+    } else {
+        hipLaunchKernelGGL(k_ntt_inv_p2, g2, blk, sh2, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logRB,
+                           logR == 0 ? 1 : 0);
+        if (logR > 0)
+            hipLaunchKernelGGL(k_ntt_inv_p1, g1, blk, sh1, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logTC);
+    }
+}
+
+// ----------------------------------------------------------- elementwise ops
+#define EW_INDEX                                                                   \
+    int y = blockIdx.y;                                                            \
+    int poly = y % a.npoly, limb = y / a.npoly;                                    \
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;                          \
+    if (n >= N) return;
+
+__global__ void k_addsub(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int op, int N)
+{
+    EW_INDEX
+    u64 q = pc[lm.prime(limb)].q;
+    u64 x = a.base[limb * a.lstride + poly * a.pstride + n];
+    u64 z = b.base[limb * b.lstride + poly * b.pstride + n];
+    out.base[limb * out.lstride + poly * out.pstride + n] = op == 0 ? addm(x, z, q) : subm(x, z, q);
+}
+
+void launch_addsub(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int op, int N,
+                   hipStream_t s)
+{
+    dim3 g((N + 255) / 256, a.nl * a.npoly);
+    hipLaunchKernelGGL(k_addsub, g, dim3(256), 0, s, pc, out, a, b, lm, op, N);
+}
+
+__global__ void k_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *ks, const u64 *ksp,
+                             LimbMap lm, int N)
+{
+    EW_INDEX
+    u64 q = pc[lm.prime(limb)].q;
+    u64 x = a.base[limb * a.lstride + poly * a.pstride + n];
+    out.base[limb * out.lstride + poly * out.pstride + n] = shoup(x, ks[limb], ksp[limb], q);
+}
+
+void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *ks, const u64 *ksp,
+                       LimbMap lm, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, a.nl * a.npoly);
+    hipLaunchKernelGGL(k_mul_scalar, g, dim3(256), 0, s, pc, out, a, ks, ksp, lm, N);
+}
+
+__global__ void k_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N)
+{
+    EW_INDEX
+    if (poly != 0) return;
+    u64 q = pc[lm.prime(limb)].q;
+    u64 *p = a.base + limb * a.lstride + n;
+    *p = addm(*p, c[limb], q);
+}
+
+void launch_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N, hipStream_t s)
+{
+    PolySet a1 = a;
+    a1.npoly = 1;
+    dim3 g((N + 255) / 256, a.nl);
+    hipLaunchKernelGGL(k_add_const, g, dim3(256), 0, s, pc, a1, c, lm, N);
+}
+
+// d: [limb][3][N] (pstride), a, b: two polynomials each
+__global__ void k_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, int acc)
+{
+    int limb = blockIdx.y;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[lm.prime(limb)];
+    const u64 *pa = a.base + limb * a.lstride + n, *pb = b.base + limb * b.lstride + n;
+    u64 a0 = pa[0], a1 = pa[a.pstride], b0 = pb[0], b1 = pb[b.pstride];
+    u64 d0 = barrett(a0, b0, c);
+    u64 d1 = addm(barrett(a0, b1, c), barrett(a1, b0, c), c.q);
+    u64 d2 = barrett(a1, b1, c);
+    u64 *pd = d.base + limb * d.lstride + n;
+    if (acc) {
+        d0 = addm(d0, pd[0], c.q);
+        d1 = addm(d1, pd[d.pstride], c.q);
+        d2 = addm(d2, pd[2 * d.pstride], c.q);
+    }
+    pd[0] = d0;
+    pd[d.pstride] = d1;
+    pd[2 * d.pstride] = d2;
+}
+
+void launch_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, bool acc,
+                   hipStream_t s)
+{
+    dim3 g((N + 255) / 256, a.nl);
+    hipLaunchKernelGGL(k_tensor, g, dim3(256), 0, s, pc, d, a, b, lm, N, acc ? 1 : 0);
+}
+
+#define LC_MAX 16
+struct LcArgs {
+    const u64 *a[LC_MAX];
+    const u64 *pt[LC_MAX];
+    int is_const[LC_MAX];
+};
+
+__global__ void k_lincomb(const PrimeConst *pc, PolySet out, LcArgs args, long a_lstride, long a_pstride,
+                          long pt_lstride, int nterms, LimbMap lm, int N)
+{
+    int y = blockIdx.y;
+    int poly = y % out.npoly, limb = y / out.npoly;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[lm.prime(limb)];
+    u64 lo = 0, hi = 0;
+    for (int k = 0; k < nterms; k++) {
+        u64 x = args.a[k][limb * a_lstride + poly * a_pstride + n];
+        u64 p = args.is_const[k] ? args.pt[k][limb] : args.pt[k][limb * pt_lstride + n];
+        mac(lo, hi, x, p);
+    }
+    out.base[limb * out.lstride + poly * out.pstride + n] = redc(lo, hi, c);
+}
+
+void launch_lincomb(const PrimeConst *pc, PolySet out, const u64 *const *a_bases, long a_lstride,
+                    long a_pstride, const u64 *const *pt_bases, long pt_lstride, int nterms, LimbMap lm,
+                    int N, hipStream_t s)
+{
+    LcArgs args;
+    for (int k = 0; k < nterms; k++) {
+        args.a[k] = a_bases[k];
+        // a constant term is tagged by the low bit of its pointer
+        uintptr_t v = (uintptr_t)pt_bases[k];
+        args.is_const[k] = (int)(v & 1);
+        args.pt[k] = (const u64 *)(v & ~(uintptr_t)1);
+    }
+    dim3 g((N + 255) / 256, out.nl * out.npoly);
+    hipLaunchKernelGGL(k_lincomb, g, dim3(256), 0, s, pc, out, args, a_lstride, a_pstride, pt_lstride,
+                       nterms, lm, N);
+}
+
+__global__ void k_automorph(PolySet out, PolySet a, u64 g, int logN)
+{
+    int y = blockIdx.y;
+    int poly = y % a.npoly, limb = y / a.npoly;
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (1u << logN)) return;
+    out.base[limb * out.lstride + poly * out.pstride + j] =
+        a.base[limb * a.lstride + poly * a.pstride + auto_src(j, g, logN)];
+}
+
+void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s)
+{
+    int N = 1 << logN;
+    dim3 gr((N + 255) / 256, a.nl * a.npoly);
+    hipLaunchKernelGGL(k_automorph, gr, dim3(256), 0, s, out, a, g, logN);
+}
+
+__global__ void k_copy(PolySet out, PolySet a, int N)
+{
+    EW_INDEX
+    out.base[limb * out.lstride + poly * out.pstride + n] = a.base[limb * a.lstride + poly * a.pstride + n];
+}
+
+void launch_copy(PolySet out, PolySet in, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, in.nl * in.npoly);
+    hipLaunchKernelGGL(k_copy, g, dim3(256), 0, s, out, in, N);
+}
+
+__global__ void k_pmul(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int N)
+{
+    EW_INDEX
+    const PrimeConst &c = pc[lm.prime(limb)];
+    u64 x = a.base[limb * a.lstride + poly * a.pstride + n];
+    u64 z = b.base[limb * b.lstride + poly * b.pstride + n];
+    out.base[limb * out.lstride + poly * out.pstride + n] = barrett(x, z, c);
+}
+
+void launch_pmul(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, a.nl * a.npoly);
+    hipLaunchKernelGGL(k_pmul, g, dim3(256), 0, s, pc, out, a, b, lm, N);
+}
+
+// ------------------------------------------------------------------ rescale
+// last: limb l of each polynomial in coefficient form (npoly polys, 1 limb);
+// tmp[i][p] = ([last + h]_{q_l} - h) mod q_i for i < l, h = floor(q_l / 2)
+__global__ void k_rescale_prep(const PrimeConst *pc, PolySet tmp, PolySet last, int l, int N)
+{
+    int y = blockIdx.y;
+    int poly = y % tmp.npoly, i = y / tmp.npoly;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    u64 ql = pc[l].q, h = ql >> 1;
+    const PrimeConst &c = pc[i];
+    u64 r = addm(last.base[poly * last.pstride + n], h, ql);
+    u64 hi = reduce64(h, c);
+    tmp.base[i * tmp.lstride + poly * tmp.pstride + n] = subm(reduce64(r, c), hi, c.q);
+}
+
+void launch_rescale_prep(const PrimeConst *pc, PolySet tmp_out, PolySet last_coeff, int l, int N,
+                         hipStream_t s)
+{
+    dim3 g((N + 255) / 256, l * tmp_out.npoly);
+    hipLaunchKernelGGL(k_rescale_prep, g, dim3(256), 0, s, pc, tmp_out, last_coeff, l, N);
+}
+
+__global__ void k_rescale_fin(const PrimeConst *pc, PolySet out, PolySet in, PolySet t, const u64 *inv,
+                              const u64 *invp, int N)
+{
+    int y = blockIdx.y;
+    int poly = y % out.npoly, i = y / out.npoly;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    u64 q = pc[i].q;
+    u64 x = in.base[i * in.lstride + poly * in.pstride + n];
+    u64 z = t.base[i * t.lstride + poly * t.pstride + n];
+    out.base[i * out.lstride + poly * out.pstride + n] = shoup(subm(x, z, q), inv[i], invp[i], q);
+}
+
+void launch_rescale_fin(const PrimeConst *pc, PolySet out, PolySet in, PolySet t, const u64 *inv,
+                        const u64 *invp, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, out.nl * out.npoly);
+    hipLaunchKernelGGL(k_rescale_fin, g, dim3(256), 0, s, pc, out, in, t, inv, invp, N);
+}
+
+// ------------------------------------------------------- basis conversion
+// out_t = REDC( sum_j [x_j * invhat_j]_{q_j} * hatm_{j,t} ),  hatm in Montgomery form
+// Every thread converts one coefficient for a chunk of BC_TCH target limbs.
+#define BC_TCH 4
+__global__ void k_bconv(const PrimeConst *pc, BconvPlan plan, const u64 *src, long src_ls, u64 *dst,
+                        long dst_ls, int N)
+{
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    u64 y[8];
+    for (int j = 0; j < plan.ns; j++) {
+        const PrimeConst &c = pc[plan.src_prime[j]];
+        y[j] = shoup(src[j * src_ls + n], plan.invhat[j], plan.invhatp[j], c.q);
+    }
+    int t0 = blockIdx.y * BC_TCH;
+    int t1 = t0 + BC_TCH < plan.nd ? t0 + BC_TCH : plan.nd;
+    for (int t = t0; t < t1; t++) {
+        const PrimeConst &c = pc[plan.dst_prime[t]];
+        u64 lo = 0, hi = 0;
+        for (int j = 0; j < plan.ns; j++) mac(lo, hi, y[j], plan.hatm[j * plan.nd + t]);
+        dst[plan.dst_limb[t] * dst_ls + n] = redc(lo, hi, c);
+    }
+}
+
+void launch_bconv(const PrimeConst *pc, const BconvPlan &plan, const u64 *src, long src_lstride, u64 *dst,
+                  long dst_lstride, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, (plan.nd + BC_TCH - 1) / BC_TCH);
+    hipLaunchKernelGGL(k_bconv, g, dim3(256), 0, s, pc, plan, src, src_lstride, dst, dst_lstride, N);
+}
+
+// ---------------------------------------------------- key-switch inner product
+__global__ void k_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
+                        const u64 *key, long key_dstride, long key_cstride, int ndig, LimbMap lm,
+                        int key_nq_off, u64 galois, int logN)
+{
+    int t = blockIdx.y;
+    u32 n = blockIdx.x * blockDim.x + threadIdx.x;
+    int N = 1 << logN;
+    if (n >= (u32)N) return;
+    const PrimeConst &c = pc[lm.prime(t)];
+    int kt = t < lm.nq ? t : key_nq_off + (t - lm.nq);
+    u32 src = galois > 1 ? auto_src(n, galois, logN) : n;
+    u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+    for (int j = 0; j < ndig; j++) {
+        u64 e = ext[j * ext_dstride + (long)t * N + src];
+        const u64 *kp = key + j * key_dstride + (long)kt * N + n;
+        mac(lo0, hi0, e, kp[0]);
+        mac(lo1, hi1, e, kp[key_cstride]);
+    }
+    acc[(long)t * N + n] = redc(lo0, hi0, c);
+    acc[acc_pstride + (long)t * N + n] = redc(lo1, hi1, c);
+}
+
+void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
+                  const u64 *key, long key_dstride, long key_cstride, int ndig, int nl, LimbMap lm,
+                  int key_nq_off, u64 galois, int logN, hipStream_t s)
+{
+    int N = 1 << logN;
+    dim3 g((N + 255) / 256, nl);
+    hipLaunchKernelGGL(k_keyip, g, dim3(256), 0, s, pc, acc, acc_pstride, ext, ext_dstride, key, key_dstride,
+                       key_cstride, ndig, lm, key_nq_off, galois, logN);
+}
+
+// ModDown tail on Q limbs: out_c = base_c + (acc_c - conv_c) * P^-1
+__global__ void k_moddown_fin(const PrimeConst *pc, PolySet out, PolySet base, int has_base0, int has_base1,
+                              u64 g0, const u64 *acc, long acc_ls, long acc_ps, const u64 *conv, long conv_ls,
+                              long conv_ps, const u64 *pinv, const u64 *pinvp, int logN)
+{
+    int y = blockIdx.y;
+    int poly = y & 1, i = y >> 1;
+    u32 n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (1u << logN)) return;
+    u64 q = pc[i].q;
+    u64 v = subm(acc[i * acc_ls + poly * acc_ps + n], conv[i * conv_ls + poly * conv_ps + n], q);
+    v = shoup(v, pinv[i], pinvp[i], q);
+    int has = poly == 0 ? has_base0 : has_base1;
+    if (has) {
+        u32 src = (poly == 0 && g0 > 1) ? auto_src(n, g0, logN) : n;
+        v = addm(v, base.base[i * base.lstride + poly * base.pstride + src], q);
+    }
+    out.base[i * out.lstride + poly * out.pstride + n] = v;
+}
+
+void launch_moddown_fin(const PrimeConst *pc, PolySet out, PolySet base, int base_mask, u64 galois,
+                        const u64 *acc, long acc_lstride, long acc_pstride, const u64 *conv,
+                        long conv_lstride, long conv_pstride, const u64 *pinv, const u64 *pinvp, int logN,
+                        hipStream_t s)
+{
+    int N = 1 << logN;
+    dim3 g((N + 255) / 256, out.nl * 2);
+    hipLaunchKernelGGL(k_moddown_fin, g, dim3(256), 0, s, pc, out, base, base_mask & 1, (base_mask >> 1) & 1,
+                       galois, acc, acc_lstride, acc_pstride, conv, conv_lstride,
+                       conv_pstride, pinv, pinvp, logN);
+}
+
+// -------------------------------------------------------- keys and client ops
+// b = e - a s + pfac * s' (NTT domain, standard form), then both b and a are
+// converted to Montgomery form for the inner product
+__global__ void k_keygen_b(const PrimeConst *pc, u64 *b, u64 *a, const u64 *s, const u64 *e, const u64 *sp,
+                           const u64 *pfac, int N)
+{
+    int t = blockIdx.y;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[t];
+    long o = (long)t * N + n;
+    u64 as = barrett(a[o], s[o], c);
+    u64 v = subm(e[o], as, c.q);
+    if (pfac[t]) v = addm(v, barrett(pfac[t], sp[o], c), c.q);
+    b[o] = shoup(v, c.r1, c.r1p, c.q);
+    a[o] = shoup(a[o], c.r1, c.r1p, c.q);
+}
+
+void launch_keygen_b(const PrimeConst *pc, u64 *b, const u64 *a, const u64 *s, const u64 *e, const u64 *sp,
+                     const u64 *pfac, int ntot, int N, hipStream_t st)
+{
+    dim3 g((N + 255) / 256, ntot);
+    hipLaunchKernelGGL(k_keygen_b, g, dim3(256), 0, st, pc, b, (u64 *)a, s, e, sp, pfac, N);
+}
+
+__global__ void k_to_mont(const PrimeConst *pc, u64 *x, long ls, long ps_, int npoly, LimbMap lm, int N)
+{
+    int y = blockIdx.y;
+    int poly = y % npoly, limb = y / npoly;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[lm.prime(limb)];
+    u64 *p = x + limb * ls + poly * ps_ + n;
+    *p = shoup(*p, c.r1, c.r1p, c.q);
+}
+
+void launch_to_montgomery(const PrimeConst *pc, u64 *x, long lstride, int nl, LimbMap lm, int N, int npoly,
+                          long pstride, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, nl * npoly);
+    hipLaunchKernelGGL(k_to_mont, g, dim3(256), 0, s, pc, x, lstride, pstride, npoly, lm, N);
+}
+
+__global__ void k_decrypt0(const PrimeConst *pc, u64 *m, const u64 *c0, const u64 *c1, const u64 *s, int N)
+{
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[0];
+    m[n] = addm(c0[n], barrett(c1[n], s[n], c), c.q);
+}
+
+void launch_decrypt0(const PrimeConst *pc, u64 *m, const u64 *c0, const u64 *c1, const u64 *s, int N,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decrypt0, dim3((N + 255) / 256), dim3(256), 0, st, pc, m, c0, c1, s, N);
+}
+
+// c0 = em - a s  (em = e + m, NTT domain); c0 and a are the two polynomials
+// of limb l of the ciphertext (lstride c_lstride), s is [l][N]
+__global__ void k_encrypt(const PrimeConst *pc, u64 *c0, const u64 *a, const u64 *s, const u64 *em,
+                          long c_ls, int N)
+{
+    int l = blockIdx.y;
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[l];
+    u64 as = barrett(a[l * c_ls + n], s[(long)l * N + n], c);
+    c0[l * c_ls + n] = subm(em[(long)l * N + n], as, c.q);
+}
+
+void launch_encrypt(const PrimeConst *pc, u64 *c0, const u64 *a, const u64 *s, const u64 *em, long c_lstride,
+                    int nl, int N, hipStream_t st)
+{
+    dim3 g((N + 255) / 256, nl);
+    hipLaunchKernelGGL(k_encrypt, g, dim3(256), 0, st, pc, c0, a, s, em, c_lstride, N);
+}
+
+}  // namespace hk

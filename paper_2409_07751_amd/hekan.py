@@ -1,0 +1,308 @@
+"""Thin ctypes binding of libhekan.so (include/hekan.h).  Argument marshalling
+only: every homomorphic operation runs in the library's HIP kernels.  There is
+no CPU fallback; if the library is missing this module raises on import of
+the library (call `python -m paper_2409_07751_amd.build` first)."""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhekan.so")
+
+HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEPTH, HE_ESHAPE, HE_EKEY, HE_EDEVICE, HE_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {-1: "HE_EINVAL", -2: "HE_ENOMEM", -3: "HE_EDEPTH", -4: "HE_ESHAPE", -5: "HE_EKEY", -6: "HE_EDEVICE",
+          -7: "HE_ESTATE"}
+
+
+class HeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class he_params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_int32), ("levels", ctypes.c_int32), ("scale_bits", ctypes.c_int32),
+                ("base_bits", ctypes.c_int32), ("special_count", ctypes.c_int32),
+                ("special_bits", ctypes.c_int32), ("digit_width", ctypes.c_int32), ("sigma", ctypes.c_double)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class he_kan_layer(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_out", ctypes.c_int32), ("g", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("knots", _dp), ("wb", _dp), ("ws", _dp), ("c", _dp), ("silu_degree", ctypes.c_int32),
+                ("silu_coeffs", _dp), ("silu_lo", ctypes.c_double), ("silu_hi", ctypes.c_double),
+                ("comp_stages", ctypes.c_int32), ("comp_stage_len", _i32p), ("comp_coeffs", _dp),
+                ("comp_prescale", ctypes.c_double)]
+
+
+class he_kan_desc(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(he_kan_layer))]
+
+
+_lib = None
+
+_SIGS = {
+    "he_ctx_create": [ctypes.POINTER(he_params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ctx_destroy": [ctypes.c_void_p],
+    "he_ctx_primes": [ctypes.c_void_p, _u64p, _u64p, _dp],
+    "he_ctx_counters": [ctypes.c_void_p, _u64p, _u64p, _u64p],
+    "he_ctx_sync": [ctypes.c_void_p],
+    "he_model_compile": [ctypes.c_void_p, ctypes.POINTER(he_kan_desc), ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_void_p)],
+    "he_model_free": [ctypes.c_void_p],
+    "he_model_rotation_steps": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "he_keygen": [ctypes.c_void_p, ctypes.c_uint64, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
+    "he_keys_free": [ctypes.c_void_p],
+    "he_keys_export": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, _u64p, ctypes.c_size_t],
+    "he_encrypt": [ctypes.c_void_p, ctypes.c_void_p, _dp, ctypes.c_size_t, ctypes.c_uint64,
+                   ctypes.POINTER(ctypes.c_void_p)],
+    "he_decrypt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp, ctypes.c_size_t],
+    "he_ct_level": [ctypes.c_void_p],
+    "he_ct_free": [ctypes.c_void_p],
+    "he_ct_export": [ctypes.c_void_p, ctypes.c_void_p, _u64p, ctypes.c_size_t],
+    "he_ct_import": [ctypes.c_void_p, _u64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
+    "he_eval_kan": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.POINTER(ctypes.c_void_p)],
+    "he_eval_kan_layer": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_void_p)],
+    "he_eval_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                          ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_add": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_mul": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_rotate": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                     ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_rescale": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_lincomb": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, _dp, ctypes.c_size_t,
+                      ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
+    "he_poly_mul": [ctypes.c_void_p, _u64p, _u64p, ctypes.c_int32, _u64p],
+    "he_encode": [ctypes.c_void_p, _dp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32, _u64p],
+}
+
+
+def lib():
+    """Load libhekan.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhekan.so is not built; run `python -m paper_2409_07751_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.he_last_error.argtypes = [ctypes.c_void_p]
+        L.he_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(a):
+    t = {np.float64: _dp, np.int32: _i32p, np.uint64: _u64p}[a.dtype.type]
+    return a.ctypes.data_as(t)
+
+
+class Context:
+    """RNS-CKKS context on the current HIP device (see he_params)."""
+
+    def __init__(self, log_n, levels, scale_bits, special_count, digit_width, base_bits=60, special_bits=60,
+                 sigma=3.2, stream=None):
+        self.lib = lib()
+        p = he_params(log_n, levels, scale_bits, base_bits, special_count, special_bits, digit_width, sigma)
+        h = ctypes.c_void_p()
+        rc = self.lib.he_ctx_create(ctypes.byref(p), ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if rc != HE_OK:
+            raise HeError(rc, "context creation failed")
+        self.h = h
+        self.log_n, self.N, self.L, self.alpha, self.w = log_n, 1 << log_n, levels, special_count, digit_width
+        self.slots = self.N // 2
+
+    def check(self, rc):
+        if rc != HE_OK:
+            raise HeError(rc, self.lib.he_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.he_ctx_destroy(self.h)
+            self.h = None
+
+    def primes(self):
+        q = np.zeros(self.L + 1, np.uint64)
+        p = np.zeros(self.alpha, np.uint64)
+        S = np.zeros(self.L + 1, np.float64)
+        self.check(self.lib.he_ctx_primes(self.h, _ptr(q), _ptr(p), _ptr(S)))
+        return q, p, S
+
+    def counters(self):
+        v = [ctypes.c_uint64() for _ in range(3)]
+        self.check(self.lib.he_ctx_counters(self.h, *[ctypes.byref(x) for x in v]))
+        return {"keyswitches": v[0].value, "rescales": v[1].value, "launches": v[2].value}
+
+    def sync(self):
+        self.check(self.lib.he_ctx_sync(self.h))
+
+    # -- keys, ciphertexts --------------------------------------------------
+    def keygen(self, seed, steps):
+        s = _arr(list(steps), np.int32)
+        h = ctypes.c_void_p()
+        self.check(self.lib.he_keygen(self.h, seed, _ptr(s) if len(s) else None, len(s), ctypes.byref(h)))
+        return Keys(self, h)
+
+    def encrypt(self, keys, x, seed):
+        x = _arr(x, np.float64)
+        h = ctypes.c_void_p()
+        self.check(self.lib.he_encrypt(self.h, keys.h, _ptr(x), len(x), seed, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def decrypt(self, keys, ct, n):
+        y = np.zeros(n, np.float64)
+        self.check(self.lib.he_decrypt(self.h, keys.h, ct.h, _ptr(y), n))
+        return y
+
+    def import_ct(self, res, level):
+        res = _arr(res, np.uint64)
+        assert res.shape == (2, level + 1, self.N)
+        h = ctypes.c_void_p()
+        self.check(self.lib.he_ct_import(self.h, _ptr(res), level, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def _new(self, fn, *args):
+        h = ctypes.c_void_p()
+        self.check(fn(self.h, *args, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def add(self, a, b):
+        return self._new(self.lib.he_ct_add, a.h, b.h)
+
+    def mul(self, keys, a, b):
+        return self._new(self.lib.he_ct_mul, keys.h, a.h, b.h)
+
+    def rotate(self, keys, a, step):
+        return self._new(self.lib.he_ct_rotate, keys.h, a.h, step)
+
+    def rescale(self, a):
+        return self._new(self.lib.he_ct_rescale, a.h)
+
+    def lincomb(self, cts, zs, target):
+        """sum_i cts[i] * zs[i] at level target; zs: list of scalars or of slot vectors."""
+        arr = (ctypes.c_void_p * len(cts))(*[c.h.value for c in cts])
+        if np.isscalar(zs[0]):
+            z = _arr(zs, np.float64)
+            ns = 1
+        else:
+            ns = max(len(v) for v in zs)
+            z = np.zeros((len(zs), ns))
+            for i, v in enumerate(zs):
+                z[i, :len(v)] = v
+            z = _arr(z.reshape(-1), np.float64)
+        return self._new(self.lib.he_ct_lincomb, arr, len(cts), _ptr(z), ns, target)
+
+    def poly_mul(self, a, b):
+        a, b = _arr(a, np.uint64), _arr(b, np.uint64)
+        out = np.zeros_like(a)
+        self.check(self.lib.he_poly_mul(self.h, _ptr(a), _ptr(b), a.shape[0], _ptr(out)))
+        return out
+
+    def encode(self, z, scale, nl):
+        z = _arr(z, np.float64)
+        out = np.zeros((nl, self.N), np.uint64)
+        self.check(self.lib.he_encode(self.h, _ptr(z), len(z), scale, nl, _ptr(out)))
+        return out
+
+    # -- inference ------------------------------------------------------------
+    def compile(self, layers, refresh=False):
+        return Model(self, layers, refresh)
+
+    def eval_kan(self, model, keys, ct):
+        return self._new(self.lib.he_eval_kan, model.h, keys.h, ct.h)
+
+    def eval_kan_layer(self, model, keys, layer, ct):
+        return self._new(self.lib.he_eval_kan_layer, model.h, keys.h, layer, ct.h)
+
+    def eval_kan_batch(self, model, keys, cts):
+        n = len(cts)
+        arr = (ctypes.c_void_p * n)(*[c.h.value for c in cts])
+        outs = (ctypes.c_void_p * n)()
+        self.check(self.lib.he_eval_kan_batch(self.h, model.h, keys.h, arr, n, outs))
+        return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+class Keys:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def export(self, key_id, digit):
+        c = self.ctx
+        ktot = c.L + 1 + c.alpha
+        out = np.zeros((2, ktot, c.N), np.uint64)
+        c.check(c.lib.he_keys_export(c.h, self.h, key_id, digit, _ptr(out), out.size))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.ctx.h:
+            self.ctx.lib.he_keys_free(self.h)
+            self.h = None
+
+
+class Ciphertext:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    @property
+    def level(self):
+        return self.ctx.lib.he_ct_level(self.h)
+
+    def export(self):
+        c = self.ctx
+        l = self.level
+        out = np.zeros((2, l + 1, c.N), np.uint64)
+        c.check(c.lib.he_ct_export(c.h, self.h, _ptr(out), out.size))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.ctx.h:
+            self.ctx.lib.he_ct_free(self.h)
+            self.h = None
+
+
+class Model:
+    def __init__(self, ctx, layers, refresh=False):
+        self.ctx = ctx
+        keep = []
+        arr = (he_kan_layer * len(layers))()
+        for i, L in enumerate(layers):
+            f = lambda a: keep.append(_arr(a, np.float64)) or keep[-1]
+            knots, wb, ws, c = f(L.knots), f(L.wb), f(L.ws), f(L.c)
+            sc = f(L.silu_coeffs)
+            lens = _arr([len(s) for s in L.comp], np.int32)
+            keep.append(lens)
+            cc = f(np.concatenate([np.asarray(s, np.float64) for s in L.comp]))
+            arr[i] = he_kan_layer(L.n_in, L.n_out, L.g, L.k, _ptr(knots), _ptr(wb), _ptr(ws), _ptr(c),
+                                  len(sc) - 1, _ptr(sc), L.silu_lo, L.silu_hi, len(L.comp), _ptr(lens), _ptr(cc),
+                                  float(getattr(L, "comp_prescale", 0.0)))
+        desc = he_kan_desc(len(layers), arr)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.he_model_compile(ctx.h, ctypes.byref(desc), 1 if refresh else 0, ctypes.byref(h)))
+        self.h = h
+        self.n_layers = len(layers)
+
+    def rotation_steps(self):
+        n = ctypes.c_size_t()
+        self.ctx.check(self.ctx.lib.he_model_rotation_steps(self.h, None, 0, ctypes.byref(n)))
+        s = np.zeros(n.value, np.int32)
+        self.ctx.check(self.ctx.lib.he_model_rotation_steps(self.h, _ptr(s), n.value, ctypes.byref(n)))
+        return [int(v) for v in s]
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.ctx.h:
+            self.ctx.lib.he_model_free(self.h)
+            self.h = None

@@ -44,6 +44,7 @@ class Workload:
     c_std: float = 0.1
     input_kind: str = "uniform_pm1"
     refresh: bool = False        # client-aided refresh between layers
+    prescale: bool = True        # explicit 1/(2R) before PolyComp (False: folded, saves a level)
     base_bits: int = 60
     special_bits: int = 60
     sigma: float = 3.2
@@ -51,7 +52,7 @@ class Workload:
 
 WORKLOADS = {
     "tiny": Workload("tiny", 13, 7, 40, 1, 1, (2, 5, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
-                     ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True),
+                     ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True, False),
     "formula": Workload("formula", 15, 16, 40, 2, 2, (4, 10, 10, 1), 10, 3, (-1.0, 1.0), 27, None,
                         ((7, 7), (7, 7), (7, 7)), 0.3, 0.1, "uniform_pm1", True),
     "image": Workload("image", 16, 24, 45, 4, 5, (784, 64, 10), 8, 3, (0.0, 1.0), 31, None,

@@ -488,7 +488,7 @@ def test_circuit_on_simulator_equals_fp64_kan(name):
     wl = synth.WORKLOADS[name]
     raw = synth.raw_weights(wl)
     layers = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * len(raw),
-                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range)
+                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
     x = synth.inputs(wl, 2)
     sim = SlotSim(1 << (wl.logN - 1))
     for row in x:
@@ -508,7 +508,7 @@ def test_oracle_he_kan_tiny_matches_fp64_circuit():
     wl = synth.WORKLOADS["tiny"]
     raw = synth.raw_weights(wl)
     layers = kan.compile_model(raw, synth.calibration_inputs(wl), [wl.silu_degree] * 2,
-                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range)
+                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
     prm = Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
     ctx = ckks.Context(prm)
     keys = ckks.Keys(ctx, synth.SEED_KEYGEN, circuit.rotation_steps(layers, prm.slots))
