@@ -81,176 +81,203 @@ __device__ __forceinline__ int set_limb(int li, int skip_lo, int skip_hi)
 
 // ------------------------------------------------------------------------ NTT
 // Negacyclic Cooley-Tukey NTT with the psi twist merged into the twiddles
-// (bit-reversed psi powers), natural-order input, bit-reversed output; the
-// inverse is Gentleman-Sande with the N^-1 scaling fused into the last store.
-// N = R * C.  Pass 1 runs the first log R stages on columns (elements
-// c, c+C, c+2C, ...) with TC adjacent columns per workgroup, so every global
-// row access is TC contiguous words; pass 2 runs the last log C stages on
-// contiguous blocks of C words, RB blocks per workgroup.  Each pass keeps its
-// tile in LDS and synchronises once per stage.
+// (bit-reversed psi powers): natural-order input, bit-reversed output; the
+// inverse is Gentleman-Sande with N^-1 fused into its last store.
+//
+// N = R * C with C = 2^min(logN, 8).  Pass 1 runs the first log R stages on
+// columns (elements c, c+C, c+2C, ...), a 2048-word tile of TC adjacent
+// columns per workgroup; pass 2 runs the last log C stages on contiguous
+// rows of C words, RB rows per workgroup.  Inside a pass each thread holds a
+// radix-8 unit (three stages) in registers; units are exchanged through LDS
+// between phases, so a pass costs two LDS round trips instead of one per
+// stage.  The first phase reads global memory and the last writes it.
+// Butterflies are Harvey's lazy ones: forward values stay in [0, 4q),
+// inverse values in [0, 2q), and only the final store reduces to [0, q).
 
-__global__ void __launch_bounds__(256) k_ntt_fwd_p1(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
-                                                    int skip_hi, int logR, int logC, int logTC)
+template <int LOGN>
+struct NttGeo {
+    static constexpr int LC = LOGN < 8 ? LOGN : 8;
+    static constexpr int LR = LOGN - LC;
+    static constexpr int LTC = (11 - LR) < LC ? (11 - LR) : LC;
+    static constexpr int LRB = (11 - LC) < LR ? (11 - LC) : LR;
+};
+
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - __umul64hi(a, wp) * q; }
+
+// X, Y in [0, 4q) -> [0, 4q)
+__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2)
 {
-    extern __shared__ u64 sh[];
-    int y = blockIdx.y;
-    int poly = y % ps.npoly;
-    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
-    int pi = lm.prime(limb);
-    u64 q = T.pc[pi].q;
-    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
-    const u64 *w = T.fw + ((long)pi << T.logN), *wp = T.fwp + ((long)pi << T.logN);
-    const int TC = 1 << logTC, tot = 1 << (logR + logTC);
-    const long C = 1l << logC;
-    const long c0 = (long)blockIdx.x * TC;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x)
-        sh[e] = a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))];
-    __syncthreads();
-    for (int s = 0; s < logR; s++) {
-        int m = 1 << s;
-        int logt = logR - 1 - s;
-        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
-            int col = b & (TC - 1);
-            int bi = b >> logTC;
-            int i = bi >> logt;
-            int r1 = (i << (logt + 1)) + (bi & ((1 << logt) - 1));
-            int e1 = (r1 << logTC) + col, e2 = e1 + (1 << (logt + logTC));
-            u64 U = sh[e1];
-            u64 V = shoup(sh[e2], w[m + i], wp[m + i], q);
-            sh[e1] = addm(U, V, q);
-            sh[e2] = subm(U, V, q);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < tot; e += blockDim.x)
-        a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))] = sh[e];
+    u64 x = X >= q2 ? X - q2 : X;
+    u64 t = shoup_lazy(Y, w, wp, q);
+    X = x + t;
+    Y = x - t + q2;
 }
 
-__global__ void __launch_bounds__(256) k_ntt_fwd_p2(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
-                                                    int skip_hi, int logR, int logC, int logRB)
+// X, Y in [0, 2q) -> [0, 2q)
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2)
 {
-    extern __shared__ u64 sh[];
-    int y = blockIdx.y;
-    int poly = y % ps.npoly;
-    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
-    int pi = lm.prime(limb);
-    u64 q = T.pc[pi].q;
-    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
-    const u64 *w = T.fw + ((long)pi << T.logN), *wp = T.fwp + ((long)pi << T.logN);
-    const int C = 1 << logC, tot = 1 << (logRB + logC);
-    const long off = (long)blockIdx.x << (logRB + logC);
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) sh[e] = a[off + e];
-    __syncthreads();
-    for (int s = 0; s < logC; s++) {
-        long m = (long)1 << (logR + s);
-        int logt = logC - 1 - s;
-        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
-            int rl = b >> (logC - 1);
-            int bb = b & ((C >> 1) - 1);
-            int il = bb >> logt;
-            int j1 = (il << (logt + 1)) + (bb & ((1 << logt) - 1));
-            long row = ((long)blockIdx.x << logRB) + rl;
-            long gi = (row << (logC - logt - 1)) + il;
-            int e1 = (rl << logC) + j1, e2 = e1 + (1 << logt);
-            u64 U = sh[e1];
-            u64 V = shoup(sh[e2], w[m + gi], wp[m + gi], q);
-            sh[e1] = addm(U, V, q);
-            sh[e2] = subm(U, V, q);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) a[off + e] = sh[e];
+    u64 s = X + Y;
+    s = s >= q2 ? s - q2 : s;
+    u64 t = X - Y + q2;
+    X = s;
+    Y = shoup_lazy(t, w, wp, q);
 }
 
-__global__ void __launch_bounds__(256) k_ntt_inv_p2(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
-                                                    int skip_hi, int logR, int logC, int logRB, int scale)
+enum { SRC_GLOBAL = 0, SRC_LDS = 1 };
+enum { OUT_LDS = 0, OUT_LAZY = 1, OUT_REDUCE4 = 2, OUT_SCALE = 3 };
+
+// One phase of R stages (min distance 2^LS positions) over a tile of
+// 2^LP positions x 2^LL lines.  PASS 1: positions are rows, lines columns;
+// PASS 2: positions are words of a row, lines rows.
+template <int LOGN, int PASS, bool FWD, int R, int LS, int SRC, int OUT>
+__device__ __forceinline__ void ntt_phase(u64 *sh, u64 *a, long blk, const u64 *w, const u64 *wp,
+                                          const PrimeConst &pc)
 {
-    extern __shared__ u64 sh[];
-    int y = blockIdx.y;
-    int poly = y % ps.npoly;
-    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
-    int pi = lm.prime(limb);
-    const PrimeConst &pc = T.pc[pi];
-    u64 q = pc.q;
-    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
-    const u64 *w = T.iw + ((long)pi << T.logN), *wp = T.iwp + ((long)pi << T.logN);
-    const int C = 1 << logC, tot = 1 << (logRB + logC);
-    const long off = (long)blockIdx.x << (logRB + logC);
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) sh[e] = a[off + e];
-    __syncthreads();
-    for (int s = logC - 1; s >= 0; s--) {
-        long m = (long)1 << (logR + s);
-        int logt = logC - 1 - s;
-        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
-            int rl = b >> (logC - 1);
-            int bb = b & ((C >> 1) - 1);
-            int il = bb >> logt;
-            int j1 = (il << (logt + 1)) + (bb & ((1 << logt) - 1));
-            long row = ((long)blockIdx.x << logRB) + rl;
-            long gi = (row << (logC - logt - 1)) + il;
-            int e1 = (rl << logC) + j1, e2 = e1 + (1 << logt);
-            u64 U = sh[e1], V = sh[e2];
-            sh[e1] = addm(U, V, q);
-            sh[e2] = shoup(subm(U, V, q), w[m + gi], wp[m + gi], q);
+    typedef NttGeo<LOGN> G;
+    constexpr int LP = PASS == 1 ? G::LR : G::LC;
+    constexpr int LL = PASS == 1 ? G::LTC : G::LRB;
+    constexpr int LU = LP - R + LL;
+    constexpr int LHI = LP - LS - R;
+    constexpr int LG = PASS == 1 ? LS + G::LC : LS;  // log2 of the global stride of a unit
+    const u64 q = pc.q, q2 = 2 * q;
+    const long N = 1l << LOGN;
+#pragma unroll
+    for (int it = 0; it < ((1 << LU) + 255) / 256; it++) {
+        const int u = it * 256 + (int)threadIdx.x;
+        if ((1 << LU) % 256 != 0 && u >= (1 << LU)) break;
+        int lo, hi, line;
+        if (PASS == 1) {
+            line = u & ((1 << LL) - 1);
+            const int v = u >> LL;
+            lo = v & ((1 << LS) - 1);
+            hi = v >> LS;
+        } else {
+            lo = u & ((1 << LS) - 1);
+            const int v = u >> LS;
+            hi = v & ((1 << LHI) - 1);
+            line = v >> LHI;
         }
-        __syncthreads();
+        const int p0 = (hi << (LS + R)) | lo;
+        // global index of position p on this line; LDS index
+        auto gidx = [&](int p) -> long {
+            return PASS == 1 ? ((long)p << G::LC) + (blk << G::LTC) + line
+                             : (((blk << G::LRB) + line) << G::LC) + p;
+        };
+        auto lidx = [&](int p) -> int { return PASS == 1 ? (p << LL) + line : (line << LP) + p; };
+        u64 x[1 << R];
+#pragma unroll
+        for (int k = 0; k < (1 << R); k++) {
+            const int p = p0 + (k << LS);
+            x[k] = SRC == SRC_GLOBAL ? a[gidx(p)] : sh[lidx(p)];
+        }
+        if (FWD) {
+#pragma unroll
+            for (int h = R - 1; h >= 0; h--) {
+#pragma unroll
+                for (int k = 0; k < (1 << R); k++) {
+                    if (k & (1 << h)) continue;
+                    const long idx = (N + gidx(p0 + (k << LS))) >> (LG + h + 1);
+                    ct_bfly(x[k], x[k + (1 << h)], w[idx], wp[idx], q, q2);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < R; h++) {
+#pragma unroll
+                for (int k = 0; k < (1 << R); k++) {
+                    if (k & (1 << h)) continue;
+                    const long idx = (N + gidx(p0 + (k << LS))) >> (LG + h + 1);
+                    gs_bfly(x[k], x[k + (1 << h)], w[idx], wp[idx], q, q2);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < (1 << R); k++) {
+            const int p = p0 + (k << LS);
+            u64 v = x[k];
+            if (OUT == OUT_LDS) {
+                sh[lidx(p)] = v;
+                continue;
+            }
+            if (OUT == OUT_REDUCE4) {
+                v = v >= q2 ? v - q2 : v;
+                v = v >= q ? v - q : v;
+            } else if (OUT == OUT_SCALE) {
+                v = shoup_lazy(v, pc.ninv, pc.ninvp, q);
+                v = v >= q ? v - q : v;
+            }
+            a[gidx(p)] = v;
+        }
     }
-    if (scale) {
-        u64 ni = pc.ninv, nip = pc.ninvp;
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) a[off + e] = shoup(sh[e], ni, nip, q);
+}
+
+// phase plan: forward 3,3,..,rem; inverse rem,..,3,3
+template <int LP, bool FWD, int PH>
+struct PhasePlan {
+    static constexpr int NPH = (LP + 2) / 3;
+    static constexpr int REM = LP - 3 * (NPH - 1);
+    static constexpr int R = FWD ? (PH < NPH - 1 ? 3 : REM) : (PH == 0 ? REM : 3);
+    static constexpr int BEFORE = FWD ? 3 * PH : (PH == 0 ? 0 : REM + 3 * (PH - 1));
+    static constexpr int LS = FWD ? LP - BEFORE - R : BEFORE;
+};
+
+template <int LOGN, int PASS, bool FWD, int PH, int LAST_OUT>
+__device__ __forceinline__ void ntt_phases(u64 *sh, u64 *a, long blk, const u64 *w, const u64 *wp,
+                                           const PrimeConst &pc)
+{
+    typedef NttGeo<LOGN> G;
+    constexpr int LP = PASS == 1 ? G::LR : G::LC;
+    typedef PhasePlan<LP, FWD, PH> P;
+    constexpr bool first = PH == 0, last = PH == P::NPH - 1;
+    constexpr int SRC = first ? SRC_GLOBAL : SRC_LDS;
+    constexpr int OUT = last ? LAST_OUT : OUT_LDS;
+    ntt_phase<LOGN, PASS, FWD, P::R, P::LS, SRC, OUT>(sh, a, blk, w, wp, pc);
+    if constexpr (!last) {
+        __syncthreads();
+        ntt_phases<LOGN, PASS, FWD, PH + 1, LAST_OUT>(sh, a, blk, w, wp, pc);
+    }
+}
+
+template <int LOGN, int PASS, bool FWD, int LAST_OUT>
+__global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi)
+{
+    typedef NttGeo<LOGN> G;
+    constexpr int LT = PASS == 1 ? G::LR + G::LTC : G::LC + G::LRB;
+    __shared__ u64 sh[1 << LT];
+    const int y = blockIdx.y;
+    const int poly = y % ps.npoly;
+    const int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
+    const int pi = lm.prime(limb);
+    const PrimeConst pc = T.pc[pi];
+    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
+    const u64 *w = (FWD ? T.fw : T.iw) + ((long)pi << LOGN);
+    const u64 *wp = (FWD ? T.fwp : T.iwp) + ((long)pi << LOGN);
+    ntt_phases<LOGN, PASS, FWD, 0, LAST_OUT>(sh, a, (long)blockIdx.x, w, wp, pc);
+}
+
+template <int LOGN>
+static void ntt_launch_n(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
+                         int nl, hipStream_t s)
+{
+    typedef NttGeo<LOGN> G;
+    dim3 blk(256);
+    dim3 g1(1 << (G::LC - G::LTC), nl * ps.npoly);
+    dim3 g2(1 << (G::LR - G::LRB), nl * ps.npoly);
+    if constexpr (G::LR > 0) {
+        if (!inverse) {
+            hipLaunchKernelGGL((k_ntt<LOGN, 1, true, OUT_LAZY>), g1, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            hipLaunchKernelGGL((k_ntt<LOGN, 2, true, OUT_REDUCE4>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+        } else {
+            hipLaunchKernelGGL((k_ntt<LOGN, 2, false, OUT_LAZY>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            hipLaunchKernelGGL((k_ntt<LOGN, 1, false, OUT_SCALE>), g1, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+        }
     } else {
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) a[off + e] = sh[e];
+        (void)g1;
+        if (!inverse)
+            hipLaunchKernelGGL((k_ntt<LOGN, 2, true, OUT_REDUCE4>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+        else
+            hipLaunchKernelGGL((k_ntt<LOGN, 2, false, OUT_SCALE>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
     }
-}
-
-__global__ void __launch_bounds__(256) k_ntt_inv_p1(NttTables T, PolySet ps, LimbMap lm, int skip_lo,
-                                                    int skip_hi, int logR, int logC, int logTC)
-{
-    extern __shared__ u64 sh[];
-    int y = blockIdx.y;
-    int poly = y % ps.npoly;
-    int limb = set_limb(y / ps.npoly, skip_lo, skip_hi);
-    int pi = lm.prime(limb);
-    const PrimeConst &pc = T.pc[pi];
-    u64 q = pc.q;
-    u64 *a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
-    const u64 *w = T.iw + ((long)pi << T.logN), *wp = T.iwp + ((long)pi << T.logN);
-    const int TC = 1 << logTC, tot = 1 << (logR + logTC);
-    const long C = 1l << logC;
-    const long c0 = (long)blockIdx.x * TC;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x)
-        sh[e] = a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))];
-    __syncthreads();
-    for (int s = logR - 1; s >= 0; s--) {
-        int m = 1 << s;
-        int logt = logR - 1 - s;
-        for (int b = threadIdx.x; b < (tot >> 1); b += blockDim.x) {
-            int col = b & (TC - 1);
-            int bi = b >> logTC;
-            int i = bi >> logt;
-            int r1 = (i << (logt + 1)) + (bi & ((1 << logt) - 1));
-            int e1 = (r1 << logTC) + col, e2 = e1 + (1 << (logt + logTC));
-            u64 U = sh[e1], V = sh[e2];
-            sh[e1] = addm(U, V, q);
-            sh[e2] = shoup(subm(U, V, q), w[m + i], wp[m + i], q);
-        }
-        __syncthreads();
-    }
-    u64 ni = pc.ninv, nip = pc.ninvp;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x)
-        a[(long)(e >> logTC) * C + c0 + (e & (TC - 1))] = shoup(sh[e], ni, nip, q);
-}
-
-static void ntt_geometry(int logN, int &logR, int &logC, int &logTC, int &logRB)
-{
-    logC = logN < 8 ? logN : 8;
-    logR = logN - logC;
-    // 2048-word tiles (16 KiB of LDS) in both passes
-    logTC = 11 - logR;
-    if (logTC > logC) logTC = logC;
-    if (logTC < 0) logTC = 0;
-    logRB = 11 - logC;
-    if (logRB > logR) logRB = logR;
 }
 
 void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
@@ -258,21 +285,21 @@ void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int ski
 {
     int nl = ps.nl - (skip_hi - skip_lo);
     if (nl <= 0) return;
-    int logR, logC, logTC, logRB;
-    ntt_geometry(t.logN, logR, logC, logTC, logRB);
-    dim3 blk(256);
-    dim3 g1(1 << (logC - logTC), nl * ps.npoly);
-    dim3 g2(1 << (logR - logRB), nl * ps.npoly);
-    size_t sh1 = sizeof(u64) << (logR + logTC), sh2 = sizeof(u64) << (logRB + logC);
-    if (!inverse) {
-        if (logR > 0)
-            hipLaunchKernelGGL(k_ntt_fwd_p1, g1, blk, sh1, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logTC);
-        hipLaunchKernelGGL(k_ntt_fwd_p2, g2, blk, sh2, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logRB);
-    } else {
-        hipLaunchKernelGGL(k_ntt_inv_p2, g2, blk, sh2, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logRB,
-                           logR == 0 ? 1 : 0);
-        if (logR > 0)
-            hipLaunchKernelGGL(k_ntt_inv_p1, g1, blk, sh1, s, t, ps, lm, skip_lo, skip_hi, logR, logC, logTC);
+    switch (t.logN) {
+    case 4: ntt_launch_n<4>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 5: ntt_launch_n<5>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 6: ntt_launch_n<6>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 7: ntt_launch_n<7>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 8: ntt_launch_n<8>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 9: ntt_launch_n<9>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 10: ntt_launch_n<10>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 11: ntt_launch_n<11>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 12: ntt_launch_n<12>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 13: ntt_launch_n<13>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 14: ntt_launch_n<14>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 15: ntt_launch_n<15>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 16: ntt_launch_n<16>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    default: break;
     }
 }
 
