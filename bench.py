@@ -23,6 +23,149 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# ALU roofline of the NTT passes: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz give
+# 39.3e12 VALU lane-issue slots per second; one lazy Shoup butterfly on 64-bit
+# words (29.5 VALU instructions, 10 of them multiply-class) sustains 24.3
+# slots per butterfly when independent butterflies run from registers, so the
+# butterfly roof is 39.3e12 / 24.3 = 1.62e12 per second.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+LANE_SLOTS_PER_BFLY = 24.3
+NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1")
+# set by a calibrated rocprofv3 --pmc run of this command (see profiles/); None if stale
+TRAFFIC_BYTES_PER_LAUNCH = None
+
+
+def roofline(kernel, prof):
+    """Achieved vs peak for the dominant kernel from the live HIP-event timings."""
+    if prof["launches"] == 0:
+        return None
+    secs = prof["ms"] * 1e-3
+    if kernel in NTT_KERNELS:
+        achieved = prof["ops"] / secs / 1e9          # G butterflies / s
+        peak = VALU_SLOTS_PER_S / LANE_SLOTS_PER_BFLY / 1e9
+        unit = "G butterflies/s"
+    else:
+        achieved = prof["bytes"] / secs / 1e9
+        peak = 8000.0
+        unit = "GB/s"
+    return {"bound": "alu" if kernel in NTT_KERNELS else "hbm", "kernel": kernel, "achieved": round(achieved, 2),
+            "peak": round(peak, 2), "unit": unit, "frac": round(achieved / peak, 4),
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+            "algorithmic_bytes_per_launch": prof["bytes"] / prof["launches"],
+            "achieved_algorithmic_GBps": round(prof["bytes"] / secs / 1e9, 1),
+            "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 3), "launches": prof["launches"]}
+
+
+def copy_probe(mib):
+    """One device-to-device copy of a known size through the HIP runtime, so a
+    counter run can calibrate FETCH_SIZE / WRITE_SIZE."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    n = mib << 20
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(n)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(n)) == 0
+    assert hip.hipMemset(a, 1, ctypes.c_size_t(n)) == 0
+    assert hip.hipMemcpy(b, a, ctypes.c_size_t(n), 3) == 0  # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    log("copy probe: %d MiB device-to-device" % mib)
+
+
+def cpu_baseline(wl, budget):
+    """The CPU oracle (plain C + Python, one thread) on a bounded sample of the
+    same workload: it runs the [784,64,10] encrypted inference from its start
+    for `budget` seconds (key generation excluded) and the throughput is
+    extrapolated from the fraction of the inference's key-switch work done,
+    weighting a key switch at level l by its limb-digit count
+    ceil((l+1)/w) (l+1+alpha)."""
+    from oracle import ckks as O, circuit, kan
+    from oracle.slotsim import SlotSim
+    from paper_2409_07751_amd import synth
+
+    layers = kan.compile_model(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024),
+                               [wl.silu_degree] * (len(wl.shape) - 1), [list(c) for c in wl.comp_degrees],
+                               wl.grid, wl.silu_range, prescale=wl.prescale)
+    prm = O.Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+
+    def work(l):
+        return ((l + 1 + wl.w - 1) // wl.w) * (l + 1 + wl.alpha)
+
+    class Rec(SlotSim):
+        def __init__(self, slots):
+            super().__init__(slots)
+            self.w = 0
+
+        def relin_rescale(self, t):
+            self.w += work(t[0])
+            return super().relin_rescale(t)
+
+        def rotate(self, a, t):
+            if t % self.ctx.p.slots:
+                self.w += work(a.level)
+            return super().rotate(a, t)
+
+    sim = Rec(prm.slots)
+    circuit.eval_kan(sim, sim.fresh(np.zeros(wl.shape[0]), wl.L), layers)
+    total_work = sim.w
+
+    ctx = O.Context(prm)
+    keys = O.Keys.__new__(O.Keys)
+    keys.ctx = ctx
+    L = O.lib()
+    s = np.zeros(prm.N, np.int64)
+    L.oc_sample_ternary(3, 1, 0, 0, prm.logN, O.P(s))
+    ktot = prm.L + 1 + prm.alpha
+    keys.s_res = np.zeros((ktot, prm.N), np.uint64)
+    L.oc_small_to_rns(O.P(s), O.P(keys.s_res), ktot, prm.logN, O.P(ctx.all_mods))
+    dnum = (prm.L + 1 + prm.w - 1) // prm.w
+    state = {"keygen": 0.0, "work": 0, "t0": None}
+
+    class LazyKeys(dict):
+        def __missing__(self, g):
+            t0 = time.perf_counter()
+            sp = np.zeros_like(keys.s_res)
+            if g == 0:
+                L.oc_poly_mul(O.P(keys.s_res), O.P(keys.s_res), O.P(sp), ktot, prm.logN, O.P(ctx.all_mods))
+            else:
+                L.oc_automorph(O.P(keys.s_res), O.P(sp), ktot, prm.logN, O.P(ctx.all_mods), g)
+            self[g] = keys._gen(3, g, sp, dnum)
+            state["keygen"] += time.perf_counter() - t0
+            return self[g]
+
+    keys.keys = LazyKeys()
+
+    class Stop(Exception):
+        pass
+
+    class Timed(O.Oracle):
+        def keyswitch(self, d, l, key_id, galois=0):
+            keys.keys[key_id]  # generate outside the measured time
+            if time.perf_counter() - state["t0"] - state["keygen"] > budget:
+                raise Stop()
+            r = super().keyswitch(d, l, key_id, galois)
+            state["work"] += work(l)
+            return r
+
+    ev = Timed(ctx, keys)
+    x = synth.inputs(wl, 1)[0]
+    ct = ev.encrypt(x, synth.SEED_ENC)
+    log("cpu baseline: oracle running the inference for %.0f s" % budget)
+    state["t0"] = time.perf_counter()
+    try:
+        circuit.eval_kan(ev, ct, layers)
+    except Stop:
+        pass
+    elapsed = time.perf_counter() - state["t0"] - state["keygen"]
+    frac = state["work"] / total_work
+    log("cpu baseline: %.4f of the key-switch work in %.1f s" % (frac, elapsed))
+    return {"value": round(frac / elapsed, 6), "unit": "inferences/s", "cores": 1, "kind": "oracle",
+            "sample": "first %.0f s of one [784,64,10] inference on the single-threaded CPU oracle "
+                      "(%d key switches, %.2f%% of the inference's key-switch work, key generation excluded); "
+                      "extrapolated by key-switch work" % (elapsed, ev.count["ks"], 100 * frac)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -32,6 +175,9 @@ def main():
     ap.add_argument("--workload", default="image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--roofline-kernel", default="ntt_fwd_pass1")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box in this setup has a single MI355X "
@@ -76,6 +222,7 @@ def main():
     c0 = ctx.counters()
     lat = []
     ctx.sync()
+    ctx.profile(args.roofline_kernel)
     t_start = time.perf_counter()
     for s in range(args.steps):
         t0 = time.perf_counter()
@@ -84,7 +231,12 @@ def main():
         del outs
     ctx.sync()
     elapsed = time.perf_counter() - t_start
+    prof = ctx.profile_read()
+    ctx.profile(None)
     c1 = ctx.counters()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+    roof = roofline(args.roofline_kernel, prof)
     ks_per_step = (c1["keyswitches"] - c0["keyswitches"]) / args.steps
     inf_s = B * args.steps / elapsed
     lat_ms = np.array(lat) * 1e3
@@ -109,7 +261,10 @@ def main():
         "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
         "max_abs_err_vs_fp64_circuit": err,
         "launches_per_step": (c1["launches"] - c0["launches"]) / args.steps,
+        "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     del cts, keys, model
     ctx.close()
     print(json.dumps(res), flush=True)

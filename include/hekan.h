@@ -129,6 +129,17 @@ int he_ctx_counters(const he_ctx *ctx, uint64_t *keyswitches, uint64_t *rescales
 /* Block until all work issued on the context's stream has completed. */
 int he_ctx_sync(he_ctx *ctx);
 
+/* Kernel timing for measurement: while enabled, every launch of one kernel
+ * (0 forward NTT pass 1, 1 forward NTT pass 2, 2 inverse NTT pass 2,
+ * 3 inverse NTT pass 1, 4 basis conversion, 5 key-switch inner product) is
+ * bracketed by HIP events on the context stream.  kernel = -1 disables.
+ * Enabling clears earlier records.  he_ctx_profile_read synchronises and
+ * returns the summed event time, the number of launches, and the launches'
+ * algorithmic bytes (every operand word read or written once) and operations
+ * (NTT butterflies, or 64-bit multiply-accumulates). */
+int he_ctx_profile(he_ctx *ctx, int32_t kernel);
+int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, double *bytes, double *ops);
+
 /* ------------------------------------------------------------------ model */
 
 /* Compile a KAN for encrypted evaluation: checks packing (HE_ESHAPE) and the

@@ -134,6 +134,26 @@ int he_ctx_sync(he_ctx *ctx)
     return guard(ctx, [&]() { ctx->c->sync(); });
 }
 
+int he_ctx_profile(he_ctx *ctx, int32_t kernel)
+{
+    if (!ctx || kernel < -1 || kernel >= KID_COUNT) return HE_EINVAL;
+    return guard(ctx, [&]() { ctx->c->profile(kernel); });
+}
+
+int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, double *bytes, double *ops)
+{
+    if (!ctx) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        double ms, b, o;
+        u64 n;
+        ctx->c->profile_read(ms, n, b, o);
+        if (total_ms) *total_ms = ms;
+        if (launches) *launches = n;
+        if (bytes) *bytes = b;
+        if (ops) *ops = o;
+    });
+}
+
 int he_model_compile(he_ctx *ctx, const he_kan_desc *desc, int32_t refresh, he_model **out)
 {
     if (!ctx || !out) return HE_EINVAL;

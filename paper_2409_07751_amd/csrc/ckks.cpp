@@ -72,6 +72,53 @@ void Ctx::download(u64 *dst, const u64 *src, size_t words)
 
 void Ctx::sync() { HIP_CHECK(hipStreamSynchronize(st)); }
 
+// ------------------------------------------------------------- kernel timer
+void KernelTimer::before(hipStream_t s)
+{
+    if (used == cap) {
+        size_t ncap = cap ? 2 * cap : 1024;
+        Rec *n = new Rec[ncap];
+        for (size_t i = 0; i < cap; i++) n[i] = recs[i];
+        for (size_t i = cap; i < ncap; i++) {
+            HIP_CHECK(hipEventCreate(&n[i].a));
+            HIP_CHECK(hipEventCreate(&n[i].b));
+        }
+        delete[] recs;
+        recs = n;
+        cap = ncap;
+    }
+    HIP_CHECK(hipEventRecord(recs[used].a, s));
+}
+
+void KernelTimer::after(hipStream_t s, double bytes, double ops)
+{
+    HIP_CHECK(hipEventRecord(recs[used].b, s));
+    recs[used].bytes = bytes;
+    recs[used].ops = ops;
+    used++;
+}
+
+void Ctx::profile(int kernel_id)
+{
+    sync();
+    timer.target = kernel_id;
+    timer.used = 0;
+}
+
+void Ctx::profile_read(double &ms, u64 &launches, double &bytes, double &ops)
+{
+    sync();
+    ms = bytes = ops = 0;
+    for (size_t i = 0; i < timer.used; i++) {
+        float t = 0;
+        HIP_CHECK(hipEventElapsedTime(&t, timer.recs[i].a, timer.recs[i].b));
+        ms += t;
+        bytes += timer.recs[i].bytes;
+        ops += timer.recs[i].ops;
+    }
+    launches = timer.used;
+}
+
 // ------------------------------------------------------------------ context
 Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int special_bits, int w_, double sigma_,
          hipStream_t stream)
@@ -156,6 +203,11 @@ Ctx::~Ctx()
         if (st) (void)hipStreamSynchronize(st);
     } catch (...) {
     }
+    for (size_t i = 0; i < timer.cap; i++) {
+        (void)hipEventDestroy(timer.recs[i].a);
+        (void)hipEventDestroy(timer.recs[i].b);
+    }
+    delete[] timer.recs;
     bconv_cache.clear();
     rescale_inv.clear();
     const_cache.clear();
@@ -176,7 +228,7 @@ u64 Ctx::galois_elt(long step) const
 
 void Ctx::ntt(PolySet ps, LimbMap lm, bool inverse, int skip_lo, int skip_hi)
 {
-    launch_ntt(T, ps, lm, skip_lo, skip_hi, inverse, st);
+    launch_ntt(T, ps, lm, skip_lo, skip_hi, inverse, st, &timer);
     n_launch += 2;
 }
 
@@ -416,20 +468,20 @@ void Ctx::keyswitch(const u64 *d, long ls, int l, const SwitchKey &key, u64 galo
         launch_copy(PolySet{ej + (size_t)lo * N, (long)N, 0, hi - lo, 1},
                     PolySet{(u64 *)d + lo * ls, ls, 0, hi - lo, 1}, N, st);
         const BconvDev &bp = modup_plan(l, j);
-        launch_bconv(d_pc, bp.plan, dc->p + (size_t)lo * N, (long)N, ej, (long)N, N, st);
+        launch_bconv(d_pc, bp.plan, dc->p + (size_t)lo * N, (long)N, ej, (long)N, N, st, &timer);
         ntt(PolySet{ej, (long)N, 0, next, 1}, lm, false, lo, hi);
         n_launch += 2;
     }
     Buf acc = alloc((size_t)2 * next * N);
     launch_keyip(d_pc, acc->p, (long)next * N, ext->p, (long)next * N, key.buf->p, 2l * ktot * N,
-                 (long)ktot * N, nd, next, lm, L1, galois, logN, st);
+                 (long)ktot * N, nd, next, lm, L1, galois, logN, st, &timer);
     // ModDown
     ntt(PolySet{acc->p + (size_t)nq * N, (long)N, (long)next * N, alpha, 2}, LimbMap{0, L1}, true);
     Buf conv = alloc((size_t)2 * nq * N);
     const BconvDev &dp = moddown_plan(l);
     for (int c = 0; c < 2; c++)
         launch_bconv(d_pc, dp.plan, acc->p + (size_t)c * next * N + (size_t)nq * N, (long)N,
-                     conv->p + (size_t)c * nq * N, (long)N, N, st);
+                     conv->p + (size_t)c * nq * N, (long)N, N, st, &timer);
     ntt(PolySet{conv->p, (long)N, (long)nq * N, nq, 2}, lm, false);
     launch_moddown_fin(d_pc, ctset(out, nq), PolySet{(u64 *)base, base_ls, base_ps, nq, 2}, base_mask, galois,
                        acc->p, (long)N, (long)next * N, conv->p, (long)N, (long)nq * N, pinv->p,

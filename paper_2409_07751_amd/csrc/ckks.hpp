@@ -105,6 +105,9 @@ struct Ctx {
     std::map<int, Buf> int_cache;
     std::string err;
     u64 n_ks = 0, n_rescale = 0, n_launch = 0;
+    KernelTimer timer;
+    void profile(int kernel_id);  // -1 disables; clears previous records
+    void profile_read(double &ms, u64 &launches, double &bytes, double &ops);
 
     Ctx(int logN, int L, int scale_bits, int base_bits, int alpha, int special_bits, int w, double sigma,
         hipStream_t stream);

@@ -45,9 +45,26 @@ struct NttTables {
     int logN;
 };
 
+// Optional per-kernel timer: HIP events recorded on the launch stream around
+// every launch of one selected kernel, with the launch's algorithmic bytes and
+// butterflies/multiply-accumulates.
+enum KernelId { KID_NTT_FWD1 = 0, KID_NTT_FWD2, KID_NTT_INV2, KID_NTT_INV1, KID_BCONV, KID_KEYIP, KID_COUNT };
+struct KernelTimer {
+    int target = -1;
+    struct Rec {
+        hipEvent_t a, b;
+        double bytes, ops;
+    };
+    Rec *recs = nullptr;
+    size_t used = 0, cap = 0;
+    bool on(int id) const { return id == target; }
+    void before(hipStream_t s);
+    void after(hipStream_t s, double bytes, double ops);
+};
+
 // ------------------------------------------------------------------ launchers
 void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
-                hipStream_t s);
+                hipStream_t s, KernelTimer *tm = nullptr);
 
 // out = a op b elementwise over (limb, poly, coeff); op: 0 add, 1 sub
 void launch_addsub(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int op, int N,
@@ -84,12 +101,12 @@ struct BconvPlan {
     const u64 *hatm;        // [ns][nd] (Q/q_j) mod p_t, Montgomery form
 };
 void launch_bconv(const PrimeConst *pc, const BconvPlan &plan, const u64 *src, long src_lstride, u64 *dst,
-                  long dst_lstride, int N, hipStream_t s);
+                  long dst_lstride, int N, hipStream_t s, KernelTimer *tm = nullptr);
 // inner product of extended digits with a switching key (Montgomery-form key):
 // acc_c[t][n] = sum_j ext_j[t][perm(n)] * key_j[c][kt(t)][n], c = 0,1
 void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
                   const u64 *key, long key_dstride, long key_cstride, int ndig, int nl, LimbMap lm,
-                  int key_nq_off, u64 galois, int logN, hipStream_t s);
+                  int key_nq_off, u64 galois, int logN, hipStream_t s, KernelTimer *tm = nullptr);
 // ModDown tail: out_c[i] = base_c[i] (+perm) + (acc_c[i] - conv_c[i]) * Pinv_i
 // base_mask: bit 0 = add base polynomial 0 (permuted by galois if > 1), bit 1 = add base polynomial 1
 void launch_moddown_fin(const PrimeConst *pc, PolySet out, PolySet base, int base_mask, u64 galois,

@@ -257,19 +257,38 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
 
 template <int LOGN>
 static void ntt_launch_n(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
-                         int nl, hipStream_t s)
+                         int nl, hipStream_t s, KernelTimer *tm)
 {
     typedef NttGeo<LOGN> G;
     dim3 blk(256);
     dim3 g1(1 << (G::LC - G::LTC), nl * ps.npoly);
     dim3 g2(1 << (G::LR - G::LRB), nl * ps.npoly);
+    // algorithmic work of one pass: every word read and written once, N/2
+    // butterflies per stage
+    const double polys = (double)nl * ps.npoly;
+    const double bytes = 16.0 * (double)(1l << LOGN) * polys;
+    const double b1 = polys * (double)(1l << (LOGN - 1)) * G::LR, b2 = polys * (double)(1l << (LOGN - 1)) * G::LC;
+    auto timed = [&](int id, double ops, auto launch) {
+        bool on = tm && tm->on(id);
+        if (on) tm->before(s);
+        launch();
+        if (on) tm->after(s, bytes, ops);
+    };
     if constexpr (G::LR > 0) {
         if (!inverse) {
-            hipLaunchKernelGGL((k_ntt<LOGN, 1, true, OUT_LAZY>), g1, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
-            hipLaunchKernelGGL((k_ntt<LOGN, 2, true, OUT_REDUCE4>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            timed(KID_NTT_FWD1, b1, [&] {
+                hipLaunchKernelGGL((k_ntt<LOGN, 1, true, OUT_LAZY>), g1, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            });
+            timed(KID_NTT_FWD2, b2, [&] {
+                hipLaunchKernelGGL((k_ntt<LOGN, 2, true, OUT_REDUCE4>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            });
         } else {
-            hipLaunchKernelGGL((k_ntt<LOGN, 2, false, OUT_LAZY>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
-            hipLaunchKernelGGL((k_ntt<LOGN, 1, false, OUT_SCALE>), g1, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            timed(KID_NTT_INV2, b2, [&] {
+                hipLaunchKernelGGL((k_ntt<LOGN, 2, false, OUT_LAZY>), g2, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            });
+            timed(KID_NTT_INV1, b1, [&] {
+                hipLaunchKernelGGL((k_ntt<LOGN, 1, false, OUT_SCALE>), g1, blk, 0, s, t, ps, lm, skip_lo, skip_hi);
+            });
         }
     } else {
         (void)g1;
@@ -281,24 +300,24 @@ static void ntt_launch_n(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo
 }
 
 void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
-                hipStream_t s)
+                hipStream_t s, KernelTimer *tm)
 {
     int nl = ps.nl - (skip_hi - skip_lo);
     if (nl <= 0) return;
     switch (t.logN) {
-    case 4: ntt_launch_n<4>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 5: ntt_launch_n<5>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 6: ntt_launch_n<6>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 7: ntt_launch_n<7>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 8: ntt_launch_n<8>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 9: ntt_launch_n<9>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 10: ntt_launch_n<10>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 11: ntt_launch_n<11>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 12: ntt_launch_n<12>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 13: ntt_launch_n<13>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 14: ntt_launch_n<14>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 15: ntt_launch_n<15>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
-    case 16: ntt_launch_n<16>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s); break;
+    case 4: ntt_launch_n<4>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 5: ntt_launch_n<5>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 6: ntt_launch_n<6>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 7: ntt_launch_n<7>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 8: ntt_launch_n<8>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 9: ntt_launch_n<9>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 10: ntt_launch_n<10>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 11: ntt_launch_n<11>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 12: ntt_launch_n<12>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 13: ntt_launch_n<13>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 14: ntt_launch_n<14>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 15: ntt_launch_n<15>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
+    case 16: ntt_launch_n<16>(t, ps, lm, skip_lo, skip_hi, inverse, nl, s, tm); break;
     default: break;
     }
 }
@@ -542,10 +561,13 @@ __global__ void k_bconv(const PrimeConst *pc, BconvPlan plan, const u64 *src, lo
 }
 
 void launch_bconv(const PrimeConst *pc, const BconvPlan &plan, const u64 *src, long src_lstride, u64 *dst,
-                  long dst_lstride, int N, hipStream_t s)
+                  long dst_lstride, int N, hipStream_t s, KernelTimer *tm)
 {
     dim3 g((N + 255) / 256, (plan.nd + BC_TCH - 1) / BC_TCH);
+    bool on = tm && tm->on(KID_BCONV);
+    if (on) tm->before(s);
     hipLaunchKernelGGL(k_bconv, g, dim3(256), 0, s, pc, plan, src, src_lstride, dst, dst_lstride, N);
+    if (on) tm->after(s, 8.0 * N * (plan.ns + plan.nd), (double)N * plan.ns * plan.nd);
 }
 
 // ---------------------------------------------------- key-switch inner product
@@ -573,12 +595,16 @@ __global__ void k_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const 
 
 void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
                   const u64 *key, long key_dstride, long key_cstride, int ndig, int nl, LimbMap lm,
-                  int key_nq_off, u64 galois, int logN, hipStream_t s)
+                  int key_nq_off, u64 galois, int logN, hipStream_t s, KernelTimer *tm)
 {
     int N = 1 << logN;
     dim3 g((N + 255) / 256, nl);
+    bool on = tm && tm->on(KID_KEYIP);
+    if (on) tm->before(s);
     hipLaunchKernelGGL(k_keyip, g, dim3(256), 0, s, pc, acc, acc_pstride, ext, ext_dstride, key, key_dstride,
                        key_cstride, ndig, lm, key_nq_off, galois, logN);
+    // reads ndig extended digits and 2 ndig key polynomials, writes 2 outputs
+    if (on) tm->after(s, 8.0 * N * nl * (3.0 * ndig + 2.0), 2.0 * N * nl * ndig);
 }
 
 // ModDown tail on Q limbs: out_c = base_c + (acc_c - conv_c) * P^-1

@@ -52,6 +52,8 @@ _SIGS = {
     "he_ctx_primes": [ctypes.c_void_p, _u64p, _u64p, _dp],
     "he_ctx_counters": [ctypes.c_void_p, _u64p, _u64p, _u64p],
     "he_ctx_sync": [ctypes.c_void_p],
+    "he_ctx_profile": [ctypes.c_void_p, ctypes.c_int32],
+    "he_ctx_profile_read": [ctypes.c_void_p, _dp, _u64p, _dp, _dp],
     "he_model_compile": [ctypes.c_void_p, ctypes.POINTER(he_kan_desc), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_void_p)],
     "he_model_free": [ctypes.c_void_p],
@@ -149,6 +151,20 @@ class Context:
 
     def sync(self):
         self.check(self.lib.he_ctx_sync(self.h))
+
+    KERNELS = {"ntt_fwd_pass1": 0, "ntt_fwd_pass2": 1, "ntt_inv_pass2": 2, "ntt_inv_pass1": 3, "bconv": 4,
+               "keyip": 5}
+
+    def profile(self, kernel):
+        """Time every launch of `kernel` (a KERNELS name, or None to stop)."""
+        self.check(self.lib.he_ctx_profile(self.h, -1 if kernel is None else self.KERNELS[kernel]))
+
+    def profile_read(self):
+        ms, by, ops = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_uint64()
+        self.check(self.lib.he_ctx_profile_read(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by),
+                                                ctypes.byref(ops)))
+        return {"ms": ms.value, "launches": n.value, "bytes": by.value, "ops": ops.value}
 
     # -- keys, ciphertexts --------------------------------------------------
     def keygen(self, seed, steps):
