@@ -64,7 +64,7 @@ typedef struct he_ct he_ct;
  * 2^scale_bits and S_{l-1} = S_l^2 / q_l is the canonical scale of level l-1.
  */
 typedef struct {
-    int32_t log_n;          /* ring degree N = 2^log_n, 4 <= log_n <= 16            */
+    int32_t log_n;          /* ring degree N = 2^log_n, 10 <= log_n <= 16           */
     int32_t levels;         /* L: number of scale primes q_1..q_L                   */
     int32_t scale_bits;     /* Delta = 2^scale_bits (<= 58)                         */
     int32_t base_bits;      /* bits of q_0 (<= 60)                                  */

@@ -80,7 +80,7 @@ int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out)
     *out = nullptr;
     he_ctx *h = new he_ctx();
     int rc = guard(h, [&]() {
-        need(p->log_n >= 4 && p->log_n <= 16, "log_n must be in [4, 16]");
+        need(p->log_n >= 10 && p->log_n <= 16, "log_n must be in [10, 16]");
         need(p->levels >= 1 && p->levels + 1 + p->special_count <= 64, "levels out of range");
         need(p->scale_bits >= 20 && p->scale_bits <= 58, "scale_bits out of range");
         need(p->base_bits > p->scale_bits && p->base_bits <= 60, "base_bits out of range");
@@ -218,8 +218,14 @@ int he_keys_export(he_ctx *ctx, const he_keys *k, uint32_t key_id, int32_t digit
             sk = &it->second;
         }
         Buf tmp = c.alloc((size_t)2 * ktot * c.N);
-        HIP_CHECK(hipMemcpyAsync(tmp->p, sk->buf->p + (size_t)digit * 2 * ktot * c.N, (size_t)2 * ktot * c.N * 8,
-                                 hipMemcpyDeviceToDevice, c.st));
+        const u64 *src = sk->buf->p + (size_t)digit * 2 * ktot * c.N;
+        if (key_id == 0) {
+            HIP_CHECK(hipMemcpyAsync(tmp->p, src, (size_t)2 * ktot * c.N * 8, hipMemcpyDeviceToDevice, c.st));
+        } else {
+            // Galois keys are stored permuted by sigma^-1: undo it
+            launch_automorph(PolySet{tmp->p, (long)c.N, 0, 2 * ktot, 1}, PolySet{(u64 *)src, (long)c.N, 0, 2 * ktot, 1},
+                             key_id, c.logN, c.st);
+        }
         // leave Montgomery form: multiply by 2^-64 = REDC(x, 0) via x * (2^-64 mod q)
         std::vector<u64> inv(2 * ktot);
         for (int t = 0; t < ktot; t++) {

@@ -195,6 +195,25 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
     }
     pinv = alloc(pv.size());
     upload(pinv->p, pv.data(), pv.size());
+    // ModDown constants: P-limb INTT scale (P/p_k)^-1 N^-1 mod p_k, and
+    // (P/p_k) mod q_i in Montgomery form
+    std::vector<u64> md(2 * alpha + (size_t)alpha * (L + 1));
+    for (int k = 0; k < alpha; k++) {
+        u64 pk = p[k], h = 1;
+        for (int k2 = 0; k2 < alpha; k2++)
+            if (k2 != k) h = hmul(h, p[k2] % pk, pk);
+        u64 sc = hmul(hinv(h, pk), hinv((u64)N % pk, pk), pk);
+        md[k] = sc;
+        md[alpha + k] = shoup_of(sc, pk);
+        for (int i = 0; i <= L; i++) {
+            u64 hq = 1;
+            for (int k2 = 0; k2 < alpha; k2++)
+                if (k2 != k) hq = hmul(hq, p[k2] % q[i], q[i]);
+            md[2 * alpha + (size_t)k * (L + 1) + i] = (u64)(((u128)hq << 64) % q[i]);
+        }
+    }
+    md_tab = alloc(md.size());
+    upload(md_tab->p, md.data(), md.size());
 }
 
 Ctx::~Ctx()
@@ -208,7 +227,8 @@ Ctx::~Ctx()
         (void)hipEventDestroy(timer.recs[i].b);
     }
     delete[] timer.recs;
-    bconv_cache.clear();
+    ks_cache.clear();
+    md_tab.reset();
     rescale_inv.clear();
     const_cache.clear();
     int_cache.clear();
@@ -341,152 +361,116 @@ const Buf &Ctx::rescale_table(int l)
     return rescale_inv.emplace(l, b).first->second;
 }
 
+// Rescale with rounding (divide by q_l, drop limb l): the dropped limb goes to
+// coefficient form; the forward transforms of ([c_l + h] - h) mod q_i and the
+// final (c_i - t_i) q_l^-1 run inside one fused NTT.
 Ct Ctx::rescale(const Ct &a)
 {
     int l = a.level;
     if (l < 1) throw HeError(-3, "rescale: no level left");
     n_rescale++;
-    // limb l of both polynomials to coefficient form
     Buf last = alloc(2 * (size_t)N);
-    PolySet lastset{last->p, 2l * N, (long)N, 1, 2};
-    PolySet src{a.d() + (size_t)l * 2 * N, 2l * N, (long)N, 1, 2};
-    launch_copy(lastset, src, N, st);
-    PolySet lastview{last->p - (size_t)l * 2 * N, 2l * N, (long)N, l + 1, 2};
-    ntt(lastview, lmap(l + 1), true, 0, l);
+    launch_intt_from(T, PolySet{last->p, (long)N, (long)N, 1, 2}, LimbMap{1, L1, l}, a.d() + (size_t)l * 2 * N,
+                     2l * N, (long)N, 0, nullptr, nullptr, st, &timer);
     Buf tmp = alloc((size_t)l * 2 * N);
-    PolySet tset{tmp->p, 2l * N, (long)N, l, 2};
-    launch_rescale_prep(d_pc, tset, lastset, l, N, st);
-    ntt(tset, lmap(l), false);
     Ct o = new_ct(l - 1);
     const Buf &inv = rescale_table(l);
-    launch_rescale_fin(d_pc, ctset(o), ctset(a, l), tset, inv->p, inv->p + l, N, st);
-    n_launch += 3;
+    launch_rescale_ntt(T, tmp->p, l, last->p, q[l], a.d(), 2l * N, (long)N, o.d(), 2l * N, (long)N, inv->p,
+                       inv->p + l, L1, st, &timer);
+    n_launch += 4;
     return o;
 }
 
-// --------------------------------------------------------- basis conversion
-static BconvDev make_plan(Ctx &c, const std::vector<int> &sp, const std::vector<int> &dp,
-                          const std::vector<int> &dl)
+// ----------------------------------------------------------- key switching
+const KsTable &Ctx::ks_table(int l)
 {
-    int ns = (int)sp.size(), nd = (int)dp.size();
-    if (ns > 8) throw HeError(-1, "basis conversion from more than 8 limbs is not supported");
-    std::vector<u64> invhat(ns), invhatp(ns), hatm((size_t)ns * nd);
-    for (int j = 0; j < ns; j++) {
-        u64 qj = c.mods[sp[j]];
-        u64 h = 1;
-        for (int k = 0; k < ns; k++)
-            if (k != j) h = hmul(h, c.mods[sp[k]] % qj, qj);
-        invhat[j] = hinv(h, qj);
-        invhatp[j] = shoup_of(invhat[j], qj);
-        for (int t = 0; t < nd; t++) {
-            u64 pt = c.mods[dp[t]];
-            u64 hp = 1;
-            for (int k = 0; k < ns; k++)
-                if (k != j) hp = hmul(hp, c.mods[sp[k]] % pt, pt);
-            hatm[(size_t)j * nd + t] = (u64)(((u128)hp << 64) % pt);  // Montgomery form
-        }
-    }
-    size_t ints = (size_t)(ns + 2 * nd);
-    size_t words = (ints + 1) / 2 + 2 * ns + (size_t)ns * nd;
-    BconvDev d;
-    d.store = c.alloc(words);
-    std::vector<u64> host(words, 0);
-    int32_t *ip = (int32_t *)host.data();
-    for (int j = 0; j < ns; j++) ip[j] = sp[j];
-    for (int t = 0; t < nd; t++) {
-        ip[ns + t] = dp[t];
-        ip[ns + nd + t] = dl[t];
-    }
-    size_t off = (ints + 1) / 2;
-    std::memcpy(&host[off], invhat.data(), ns * 8);
-    std::memcpy(&host[off + ns], invhatp.data(), ns * 8);
-    std::memcpy(&host[off + 2 * ns], hatm.data(), hatm.size() * 8);
-    c.upload(d.store->p, host.data(), words);
-    int32_t *dip = (int32_t *)d.store->p;
-    d.plan.ns = ns;
-    d.plan.nd = nd;
-    d.plan.src_prime = dip;
-    d.plan.dst_prime = dip + ns;
-    d.plan.dst_limb = dip + ns + nd;
-    d.plan.invhat = d.store->p + off;
-    d.plan.invhatp = d.store->p + off + ns;
-    d.plan.hatm = d.store->p + off + 2 * ns;
-    return d;
-}
-
-const BconvDev &Ctx::modup_plan(int l, int j)
-{
-    long key = ((long)1 << 40) | ((long)l << 20) | j;
-    auto it = bconv_cache.find(key);
-    if (it != bconv_cache.end()) return it->second;
-    int nq = l + 1, lo = j * w, hi = std::min(lo + w, nq);
-    std::vector<int> sp, dp, dl;
-    for (int i = lo; i < hi; i++) sp.push_back(i);
+    auto it = ks_cache.find(l);
+    if (it != ks_cache.end()) return it->second;
+    const int nq = l + 1, next = nq + alpha, nd = ndig(l);
+    std::vector<u64> v(2 * (size_t)nq + (size_t)nd * w * next, 0);
     LimbMap lm = lmap(nq);
-    for (int t = 0; t < nq + alpha; t++)
-        if (t < lo || t >= hi) {
-            dp.push_back(lm.prime(t));
-            dl.push_back(t);
+    for (int j = 0; j < nd; j++) {
+        const int lo = j * w, hi = std::min(lo + w, nq);
+        for (int i = lo; i < hi; i++) {
+            u64 h = 1;
+            for (int k = lo; k < hi; k++)
+                if (k != i) h = hmul(h, q[k] % q[i], q[i]);
+            u64 sc = hmul(hinv(h, q[i]), hinv((u64)N % q[i], q[i]), q[i]);
+            v[i] = sc;
+            v[nq + i] = shoup_of(sc, q[i]);
+            for (int t = 0; t < next; t++) {
+                if (t >= lo && t < hi) continue;
+                u64 m = mods[lm.prime(t)], hm = 1;
+                for (int k = lo; k < hi; k++)
+                    if (k != i) hm = hmul(hm, q[k] % m, m);
+                v[2 * (size_t)nq + ((size_t)j * w + (i - lo)) * next + t] = (u64)(((u128)hm << 64) % m);
+            }
         }
-    return bconv_cache.emplace(key, make_plan(*this, sp, dp, dl)).first->second;
-}
-
-const BconvDev &Ctx::moddown_plan(int l)
-{
-    long key = ((long)2 << 40) | ((long)l << 20);
-    auto it = bconv_cache.find(key);
-    if (it != bconv_cache.end()) return it->second;
-    std::vector<int> sp, dp, dl;
-    for (int i = 0; i < alpha; i++) sp.push_back(L1 + i);
-    for (int i = 0; i <= l; i++) {
-        dp.push_back(i);
-        dl.push_back(i);
     }
-    return bconv_cache.emplace(key, make_plan(*this, sp, dp, dl)).first->second;
+    KsTable kt;
+    kt.buf = alloc(v.size());
+    upload(kt.buf->p, v.data(), v.size());
+    kt.scale = kt.buf->p;
+    kt.scalep = kt.buf->p + nq;
+    kt.hatm = kt.buf->p + 2 * nq;
+    return ks_cache.emplace(l, kt).first->second;
 }
 
-// -------------------------------------------------------------- key switch
 // Hybrid key switching (Han-Ki): d is split into digits of w Q limbs; each
 // digit is extended to Q_l u P by fast basis conversion (ModUp), multiplied by
 // the key digit and accumulated; the sum is divided by P (ModDown).  For a
-// rotation the Galois automorphism acts on the extended digits inside the
-// inner product, so rotations of the same ciphertext can share ModUp.
+// rotation the Galois automorphism acts on the extended digits; because the
+// Galois keys are stored permuted by sigma^-1, the inner product runs
+// unpermuted and sigma is applied when ModDown reads the accumulator.
+Ctx::ModUp Ctx::modup(const u64 *d, long ls, int l)
+{
+    ModUp m;
+    m.d = d;
+    m.ls = ls;
+    m.l = l;
+    const int nq = l + 1, next = nq + alpha, nd = ndig(l);
+    const LimbMap lm = lmap(nq);
+    const KsTable &kt = ks_table(l);
+    // y = INTT(d) * invhat / N, then every digit's conversion and NTT
+    Buf y = alloc((size_t)nq * N);
+    launch_intt_from(T, PolySet{y->p, (long)N, 0, nq, 1}, lm, d, ls, 0, 0, kt.scale, kt.scalep, st, &timer);
+    m.ext = alloc((size_t)nd * next * N);
+    launch_modup(T, m.ext->p, nd, nq, alpha, w, lm, y->p, kt.hatm, st, &timer);
+    n_launch += 3;
+    return m;
+}
+
+void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
+                         long base_ps, int base_mask, Ct &out)
+{
+    n_ks++;
+    const int l = m.l, nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
+    const LimbMap lm = lmap(nq);
+    Buf acc = alloc((size_t)2 * next * N);
+    launch_keyip(d_pc, acc->p, (long)next * N, m.ext->p, (long)next * N, m.d, m.ls, key.buf->p, 2l * ktot * N,
+                 (long)ktot * N, nd, next, nq, w, lm, L1, logN, st, &timer);
+    // ModDown
+    Buf yP = alloc((size_t)2 * alpha * N);
+    launch_intt_from(T, PolySet{yP->p, (long)N, (long)alpha * N, alpha, 2}, LimbMap{0, L1}, acc->p + (size_t)nq * N,
+                     (long)N, (long)next * N, galois, md_tab->p, md_tab->p + alpha, st, &timer);
+    Buf tmp = alloc((size_t)2 * nq * N);
+    OutModdownArgs oa{acc->p, (long)N, (long)next * N, base, base_ls, base_ps, base_mask, galois, out.d(), 2l * N,
+                      (long)N, pinv->p, pinv->p + L + 1};
+    launch_moddown(T, tmp->p, nq, alpha, lm, yP->p, md_tab->p + 2 * alpha, L + 1, oa, st, &timer);
+    n_launch += 6;
+}
+
+// Hybrid key switching (Han-Ki): d is split into digits of w Q limbs; each
+// digit is extended to Q_l u P by fast basis conversion (ModUp), multiplied by
+// the key digit and accumulated; the sum is divided by P (ModDown).  For a
+// rotation the Galois automorphism acts on the extended digits; because the
+// Galois keys are stored permuted by sigma^-1, the inner product runs
+// unpermuted and sigma is applied when ModDown reads the accumulator.
 void Ctx::keyswitch(const u64 *d, long ls, int l, const SwitchKey &key, u64 galois, const u64 *base,
                     long base_ls, long base_ps, int base_mask, Ct &out)
 {
-    n_ks++;
-    const int nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
-    const LimbMap lm = lmap(nq);
-    Buf dc = alloc((size_t)nq * N);
-    PolySet dcs{dc->p, (long)N, 0, nq, 1};
-    launch_copy(dcs, PolySet{(u64 *)d, ls, 0, nq, 1}, N, st);
-    ntt(dcs, lm, true);
-    Buf ext = alloc((size_t)nd * next * N);
-    for (int j = 0; j < nd; j++) {
-        int lo = j * w, hi = std::min(lo + w, nq);
-        u64 *ej = ext->p + (size_t)j * next * N;
-        launch_copy(PolySet{ej + (size_t)lo * N, (long)N, 0, hi - lo, 1},
-                    PolySet{(u64 *)d + lo * ls, ls, 0, hi - lo, 1}, N, st);
-        const BconvDev &bp = modup_plan(l, j);
-        launch_bconv(d_pc, bp.plan, dc->p + (size_t)lo * N, (long)N, ej, (long)N, N, st, &timer);
-        ntt(PolySet{ej, (long)N, 0, next, 1}, lm, false, lo, hi);
-        n_launch += 2;
-    }
-    Buf acc = alloc((size_t)2 * next * N);
-    launch_keyip(d_pc, acc->p, (long)next * N, ext->p, (long)next * N, key.buf->p, 2l * ktot * N,
-                 (long)ktot * N, nd, next, lm, L1, galois, logN, st, &timer);
-    // ModDown
-    ntt(PolySet{acc->p + (size_t)nq * N, (long)N, (long)next * N, alpha, 2}, LimbMap{0, L1}, true);
-    Buf conv = alloc((size_t)2 * nq * N);
-    const BconvDev &dp = moddown_plan(l);
-    for (int c = 0; c < 2; c++)
-        launch_bconv(d_pc, dp.plan, acc->p + (size_t)c * next * N + (size_t)nq * N, (long)N,
-                     conv->p + (size_t)c * nq * N, (long)N, N, st, &timer);
-    ntt(PolySet{conv->p, (long)N, (long)nq * N, nq, 2}, lm, false);
-    launch_moddown_fin(d_pc, ctset(out, nq), PolySet{(u64 *)base, base_ls, base_ps, nq, 2}, base_mask, galois,
-                       acc->p, (long)N, (long)next * N, conv->p, (long)N, (long)nq * N, pinv->p,
-                       pinv->p + L + 1, logN, st);
-    n_launch += 5;
+    ModUp m = modup(d, ls, l);
+    keyswitch_from(m, key, galois, base, base_ls, base_ps, base_mask, out);
 }
 
 Tensor Ctx::tensor(const Ct &a, const Ct &b)
@@ -518,6 +502,28 @@ Ct Ctx::relin_rescale(const Tensor &t, const Keys &k)
 }
 
 Ct Ctx::mul(const Ct &a, const Ct &b, const Keys &k) { return relin_rescale(tensor(a, b), k); }
+
+std::vector<Ct> Ctx::rotate_many(const Ct &a, const std::vector<long> &steps, const Keys &k)
+{
+    std::vector<Ct> out;
+    bool need = false;
+    for (long s : steps) need |= galois_elt(s) != 1;
+    ModUp m;
+    if (need) m = modup(a.d() + N, 2l * N, a.level);
+    for (long s : steps) {
+        u64 g = galois_elt(s);
+        if (g == 1) {
+            out.push_back(a);
+            continue;
+        }
+        auto it = k.galois.find(g);
+        if (it == k.galois.end()) throw HeError(-5, "no Galois key for rotation step " + std::to_string(s));
+        Ct o = new_ct(a.level);
+        keyswitch_from(m, it->second, g, a.d(), 2l * N, (long)N, 1, o);
+        out.push_back(o);
+    }
+    return out;
+}
 
 Ct Ctx::rotate(const Ct &a, long step, const Keys &k)
 {
@@ -702,7 +708,15 @@ Keys *Ctx::keygen(u64 seed, const std::vector<long> &steps)
         if (g == 1 || k->galois.count(g)) continue;
         launch_automorph(PolySet{sg->p, (long)N, 0, ktot, 1}, sset, g, logN, st);
         n_launch++;
-        gen_switch_key(*k, seed, (u32)g, sg->p, k->galois[g]);
+        SwitchKey &gk = k->galois[g];
+        gen_switch_key(*k, seed, (u32)g, sg->p, gk);
+        // store sigma_g^-1(key) so the inner product needs no permutation
+        const size_t words = (size_t)dnum_top() * 2 * ktot * N;
+        Buf perm = alloc(words);
+        launch_automorph(PolySet{perm->p, (long)N, 0, (int)(words / N), 1}, PolySet{gk.buf->p, (long)N, 0,
+                         (int)(words / N), 1}, hinv(g, 2ull * N), logN, st);
+        n_launch++;
+        gk.buf = perm;
     }
     return k.release();
 }

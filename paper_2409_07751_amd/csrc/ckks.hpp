@@ -81,9 +81,12 @@ struct Keys {
     std::map<u64, SwitchKey> galois;
 };
 
-struct BconvDev {
-    BconvPlan plan;
-    Buf store;
+// per-level key-switch constants: [2][nq] INTT output scale (inverse hat of
+// the limb's digit times N^-1, Shoup pair) then [ndig][w][nq+alpha] ModUp
+// conversion constants (Montgomery form)
+struct KsTable {
+    Buf buf;
+    const u64 *scale, *scalep, *hatm;
 };
 
 struct Ctx {
@@ -98,9 +101,10 @@ struct Ctx {
     Buf d_pc_buf, tw_buf;
     const PrimeConst *d_pc = nullptr;
     NttTables T;
-    std::map<long, BconvDev> bconv_cache;
+    std::map<int, KsTable> ks_cache;
     std::map<int, Buf> rescale_inv;  // per level l: [2][l] inv, invp
     Buf pinv;                        // [2][L+1] P^-1 mod q_i and Shoup
+    Buf md_tab;                      // [2][alpha] P-limb INTT scale, then [alpha][L+1] P->Q constants
     std::map<std::pair<u64, u64>, Buf> const_cache;
     std::map<int, Buf> int_cache;
     std::string err;
@@ -140,9 +144,21 @@ struct Ctx {
     Ct lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t);
     Ct level_down(const Ct &a, int t);
 
-    // key switching of d (NTT form, limb stride ls, level l) into out = base + KS(d)
+    // key switching of d (NTT form, limb stride ls, level l) into out = base + KS(d);
+    // the ModUp part can be shared by several keys (hoisted rotations)
+    struct ModUp {
+        const u64 *d = nullptr;
+        long ls = 0;
+        int l = -1;
+        Buf ext;
+    };
+    ModUp modup(const u64 *d, long ls, int l);
+    void keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
+                        long base_ps, int base_mask, Ct &out);
     void keyswitch(const u64 *d, long ls, int l, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
                    long base_ps, int base_mask, Ct &out);
+    // rotations of one ciphertext by several steps sharing one ModUp
+    std::vector<Ct> rotate_many(const Ct &a, const std::vector<long> &steps, const Keys &k);
 
     // plaintexts
     Buf encode_ntt(const double *z, size_t n, double scale, int nl, bool montgomery);
@@ -150,8 +166,7 @@ struct Ctx {
     Pt vec_pt(const double *z, size_t n, double scale, int nl);
 
     // tables
-    const BconvDev &modup_plan(int l, int j);
-    const BconvDev &moddown_plan(int l);
+    const KsTable &ks_table(int l);
     const Buf &rescale_table(int l);
 
     // client side

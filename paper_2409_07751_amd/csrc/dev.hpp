@@ -24,8 +24,9 @@ struct PrimeConst {
 // limbs [nq, ...) take the special primes p_0.. (stored at index L1 + i).
 struct LimbMap {
     int nq;
-    int L1;  // L + 1 = index of p_0 in the prime table
-    __host__ __device__ int prime(int limb) const { return limb < nq ? limb : L1 + (limb - nq); }
+    int L1;         // L + 1 = index of p_0 in the prime table
+    int q_off = 0;  // limb i < nq uses q_{i + q_off}
+    __host__ __device__ int prime(int limb) const { return limb < nq ? limb + q_off : L1 + (limb - nq); }
 };
 
 // A strided set of polynomials: polynomial `p`, limb `l` starts at
@@ -85,34 +86,41 @@ void launch_lincomb(const PrimeConst *pc, PolySet out, const u64 *const *a_bases
                     int N, hipStream_t s);
 // automorphism in the NTT domain, out[j] = a[perm_g(j)]
 void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s);
-// rescale helpers
-void launch_rescale_prep(const PrimeConst *pc, PolySet tmp_out, PolySet last_coeff, int l, int N,
-                         hipStream_t s);
-void launch_rescale_fin(const PrimeConst *pc, PolySet out, PolySet in, PolySet t, const u64 *inv,
-                        const u64 *invp, int N, hipStream_t s);
-// fast basis conversion: src limbs (coefficient form) -> dst limbs
-struct BconvPlan {
-    int ns, nd;
-    const int *src_prime;   // [ns] prime index
-    const int *dst_prime;   // [nd]
-    const int *dst_limb;    // [nd] limb index in the output set
-    const u64 *invhat;      // [ns]  (Q/q_j)^-1 mod q_j
-    const u64 *invhatp;     // [ns]  Shoup
-    const u64 *hatm;        // [ns][nd] (Q/q_j) mod p_t, Montgomery form
-};
-void launch_bconv(const PrimeConst *pc, const BconvPlan &plan, const u64 *src, long src_lstride, u64 *dst,
-                  long dst_lstride, int N, hipStream_t s, KernelTimer *tm = nullptr);
-// inner product of extended digits with a switching key (Montgomery-form key):
-// acc_c[t][n] = sum_j ext_j[t][perm(n)] * key_j[c][kt(t)][n], c = 0,1
+// inner product of the extended digits with a switching key (NTT +
+// Montgomery form): acc_c[t] = sum_j e_j[t] * key_j[c][kt(t)], c = 0, 1, where
+// e_j[t] is the input d itself on digit j's own limbs and ext_j[t] elsewhere.
+// Galois keys are stored permuted by sigma^-1, so no permutation happens here.
 void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
-                  const u64 *key, long key_dstride, long key_cstride, int ndig, int nl, LimbMap lm,
-                  int key_nq_off, u64 galois, int logN, hipStream_t s, KernelTimer *tm = nullptr);
-// ModDown tail: out_c[i] = base_c[i] (+perm) + (acc_c[i] - conv_c[i]) * Pinv_i
-// base_mask: bit 0 = add base polynomial 0 (permuted by galois if > 1), bit 1 = add base polynomial 1
-void launch_moddown_fin(const PrimeConst *pc, PolySet out, PolySet base, int base_mask, u64 galois,
-                        const u64 *acc, long acc_lstride, long acc_pstride, const u64 *conv,
-                        long conv_lstride, long conv_pstride, const u64 *pinv, const u64 *pinvp, int logN,
-                        hipStream_t s);
+                  const u64 *d, long d_ls, const u64 *key, long key_dstride, long key_cstride, int ndig, int nl,
+                  int nq, int w, LimbMap lm, int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
+
+// --- fused transforms (ntt.hip)
+// inverse transform of src (through sigma_galois if galois > 1) into `work`;
+// limb i is multiplied by scale[i] (N^-1 folded in), or by N^-1 if scale is null
+void launch_intt_from(const NttTables &t, PolySet work, LimbMap lm, const u64 *src, long src_ls, long src_ps,
+                      u64 galois, const u64 *scale, const u64 *scalep, hipStream_t s, KernelTimer *tm = nullptr);
+// ModUp of every digit at once: ext [ndig][nq+alpha][N] <- NTT(BConv(y_digit))
+// on every limb outside the digit; hatm [ndig][w][nq+alpha] Montgomery form
+void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, LimbMap lm, const u64 *y,
+                  const u64 *hatm, hipStream_t s, KernelTimer *tm = nullptr);
+struct OutModdownArgs {
+    const u64 *acc;
+    long acc_ls, acc_ps;
+    const u64 *base;
+    long bls, bps;
+    int mask;  // bit c: add base polynomial c (polynomial 0 through sigma_galois)
+    u64 galois;
+    u64 *out;
+    long ols, ops;
+    const u64 *pinv, *pinvp;
+};
+// ModDown: out_c = base_c + (acc_c - NTT(BConv_{P->Q}(yP_c))) P^-1, tmp [2][nq][N]
+void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, LimbMap lm, const u64 *yP, const u64 *hatm,
+                    long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
+// rescale by q_l of both polynomials: out_i = (in_i - NTT_i([last + h] - h)) q_l^-1
+void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, const u64 *last, u64 ql, const u64 *in, long in_ls,
+                        long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp, int L1,
+                        hipStream_t s, KernelTimer *tm = nullptr);
 // copy limbs
 void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);
 // pointwise product out = a * b (single polynomials, Barrett)

@@ -338,9 +338,10 @@ struct Eval {
         const int b1 = 1 << ((clog2i(d) + 1) / 2);
         const long g1 = d / b1;
         Ct xd = c.mod_drop(x, t + 1);
-        std::vector<Ct> rots(b1);
-        rots[0] = xd;
-        for (int bi = 1; bi < b1; bi++) rots[bi] = c.rotate(xd, bi, k);
+        // baby steps share one ModUp (hoisting; same residues as separate rotations)
+        std::vector<long> bsteps;
+        for (int bi = 0; bi < b1; bi++) bsteps.push_back(bi);
+        std::vector<Ct> rots = c.rotate_many(xd, bsteps, k);
         Ct z;
         bool have = false;
         for (long gi = 0; gi < g1; gi++) {

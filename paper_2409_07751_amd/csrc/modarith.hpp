@@ -1,0 +1,68 @@
+// Device-side modular arithmetic on 64-bit words (primes below 2^61).
+#pragma once
+#include "dev.hpp"
+
+namespace hk {
+
+// ------------------------------------------------------------ modular helpers
+__device__ __forceinline__ u64 addm(u64 a, u64 b, u64 q)
+{
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 subm(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// a * w mod q with wp = floor(w 2^64 / q); valid for any 64-bit a, w < q < 2^63
+__device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 wp, u64 q)
+{
+    u64 h = __umul64hi(a, wp);
+    u64 r = a * w - h * q;
+    return r >= q ? r - q : r;
+}
+
+// a * b mod q for a*b < 2^(2b), b = bit length of q (HAC 14.42 with base 2)
+__device__ __forceinline__ u64 barrett(u64 a, u64 b, const PrimeConst &c)
+{
+    u64 lo = a * b, hi = __umul64hi(a, b);
+    int nb = c.bits;
+    u64 z1 = (lo >> (nb - 1)) | (hi << (65 - nb));
+    u64 plo = z1 * c.mu, phi = __umul64hi(z1, c.mu);
+    u64 qh = (plo >> (nb + 1)) | (phi << (63 - nb));
+    u64 r = lo - qh * c.q;
+    if (r >= c.q) r -= c.q;
+    if (r >= c.q) r -= c.q;
+    return r;
+}
+
+// reduce a 64-bit value below 2^(2b)
+__device__ __forceinline__ u64 reduce64(u64 a, const PrimeConst &c) { return barrett(a, 1, c); }
+
+__device__ __forceinline__ void mac(u64 &lo, u64 &hi, u64 a, u64 b)
+{
+    u64 pl = a * b, ph = __umul64hi(a, b);
+    lo += pl;
+    hi += ph + (lo < pl ? 1ull : 0ull);
+}
+
+// (hi:lo) * 2^-64 mod q for (hi:lo) < q 2^64
+__device__ __forceinline__ u64 redc(u64 lo, u64 hi, const PrimeConst &c)
+{
+    u64 m = lo * c.qinv_neg;
+    u64 t = hi + __umul64hi(m, c.q) + (lo != 0 ? 1ull : 0ull);
+    return t >= c.q ? t - c.q : t;
+}
+
+__device__ __forceinline__ u32 brv(u32 x, int bits) { return __brev(x) >> (32 - bits); }
+
+// index of the NTT slot that sigma_g moves to slot j: slot j holds the
+// evaluation at psi^(2 brv(j) + 1)
+__device__ __forceinline__ u32 auto_src(u32 j, u64 g, int logN)
+{
+    u64 twoN = 2ull << logN;
+    u64 e = (2ull * brv(j, logN) + 1ull) * g & (twoN - 1);
+    return brv((u32)((e - 1) >> 1), logN);
+}
+
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - __umul64hi(a, wp) * q; }
+
+}  // namespace hk

@@ -1,0 +1,507 @@
+// Negacyclic NTT kernels for gfx950 and the key-switch / rescale pipelines
+// fused into them.
+//
+// The transform is Cooley-Tukey with the psi twist merged into the twiddles
+// (bit-reversed psi powers): natural-order input, bit-reversed output; the
+// inverse is Gentleman-Sande.  N = R * C with C = 2^min(logN, 8).  Pass 1 runs
+// the first log R stages on columns (elements c, c+C, c+2C, ...) with a
+// 2048-word tile of TC adjacent columns per workgroup; pass 2 runs the last
+// log C stages on contiguous rows of C words, RB rows per workgroup.  Inside a
+// pass every thread holds a radix-8 unit (three stages) in registers; units are
+// exchanged through LDS between phases.  Butterflies are Harvey's lazy ones:
+// forward values stay in [0, 4q), inverse values in [0, 2q).
+//
+// The first load and the last store of each transform go through policy
+// objects, so neighbouring ring steps run inside the transform instead of as
+// separate passes over HBM:
+//   * fast basis conversion (ModUp of every key-switch digit, ModDown from P)
+//     is computed on the pass-1 load of the forward transform;
+//   * the rescale input ([c_l + h]_{q_l} - h) mod q_i is formed on that load,
+//     and (c_i - t_i) q_l^-1 on the pass-2 store;
+//   * the ModDown tail base + (acc - conv) P^-1 runs on the pass-2 store;
+//   * inverse transforms read their input from another buffer (optionally
+//     through a Galois permutation) and fold a per-limb constant into N^-1.
+#include "dev.hpp"
+#include "modarith.hpp"
+
+namespace hk {
+
+template <int LOGN>
+struct NttGeo {
+    static constexpr int LC = LOGN < 8 ? LOGN : 8;
+    static constexpr int LR = LOGN - LC;
+    static constexpr int LTC = (11 - LR) < LC ? (11 - LR) : LC;
+    static constexpr int LRB = (11 - LC) < LR ? (11 - LC) : LR;
+};
+
+// X, Y in [0, 4q) -> [0, 4q)
+__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2)
+{
+    u64 x = X >= q2 ? X - q2 : X;
+    u64 t = shoup_lazy(Y, w, wp, q);
+    X = x + t;
+    Y = x - t + q2;
+}
+
+// X, Y in [0, 2q) -> [0, 2q)
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2)
+{
+    u64 s = X + Y;
+    s = s >= q2 ? s - q2 : s;
+    u64 t = X - Y + q2;
+    X = s;
+    Y = shoup_lazy(t, w, wp, q);
+}
+
+__device__ __forceinline__ u64 reduce4(u64 v, u64 q)
+{
+    v = v >= 2 * q ? v - 2 * q : v;
+    return v >= q ? v - q : v;
+}
+
+// ------------------------------------------------------------------ policies
+// Context of one block: working polynomial pointer, limb, polynomial, prime.
+struct Blk {
+    u64 *a;
+    int limb, poly;
+    const PrimeConst *pc;
+    int logN;
+};
+
+struct InWork {
+    __device__ u64 load(const Blk &b, long g) const { return b.a[g]; }
+};
+
+// read the same (limb, poly) of another set, through sigma_galois if galois > 1
+struct InSrc {
+    const u64 *base;
+    long ls, ps;
+    u64 galois;
+    __device__ u64 load(const Blk &b, long g) const
+    {
+        long gg = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
+        return base[b.limb * ls + b.poly * ps + gg];
+    }
+};
+
+// fast basis conversion: sum_k y_k * hat(k, target) with y in coefficient form
+// (already multiplied by the inverse hat constants), hat in Montgomery form
+struct InBconv {
+    const u64 *src;     // polynomial p's sources start at src + p * src_ps, limb stride N
+    long src_ps;
+    const u64 *hatm;    // hat(k, t) at hatm[p * hat_ps + k * hat_ks + t]
+    long hat_ps, hat_ks;
+    int ns_fixed;       // > 0: every polynomial has ns_fixed sources
+    int w, nq;          // else digit p has min(w, nq - p w) sources
+    __device__ u64 load(const Blk &b, long g) const
+    {
+        const int ns = ns_fixed > 0 ? ns_fixed : min(w, nq - b.poly * w);
+        const long N = 1l << b.logN;
+        const u64 *s = src + b.poly * src_ps + g;
+        const u64 *h = hatm + b.poly * hat_ps + b.limb;
+        u64 lo = 0, hi = 0;
+        for (int k = 0; k < ns; k++) mac(lo, hi, s[k * N], h[k * hat_ks]);
+        return redc(lo, hi, *b.pc);
+    }
+};
+
+// rescale input ([c_l + h]_{q_l} - h) mod q_i from the dropped limb c_l
+struct InRescale {
+    const u64 *last;  // polynomial p at last + p * last_ps (coefficient form)
+    long last_ps;
+    u64 ql;
+    __device__ u64 load(const Blk &b, long g) const
+    {
+        const u64 h = ql >> 1;
+        u64 r = last[b.poly * last_ps + g] + h;
+        r = r >= ql ? r - ql : r;
+        return subm(reduce64(r, *b.pc), reduce64(h, *b.pc), b.pc->q);
+    }
+};
+
+enum { OW_LAZY = 0, OW_REDUCE = 1, OW_SCALE_N = 2 };
+template <int MODE>
+struct OutWork {
+    __device__ void store(const Blk &b, long g, u64 v) const
+    {
+        const u64 q = b.pc->q;
+        if (MODE == OW_REDUCE) v = reduce4(v, q);
+        if (MODE == OW_SCALE_N) {
+            v = shoup_lazy(v, b.pc->ninv, b.pc->ninvp, q);
+            v = v >= q ? v - q : v;
+        }
+        b.a[g] = v;
+    }
+};
+
+// inverse transform, last store: multiply by a per-limb constant (N^-1 folded in)
+struct OutScaleTab {
+    const u64 *s, *sp;
+    __device__ void store(const Blk &b, long g, u64 v) const
+    {
+        const u64 q = b.pc->q;
+        v = shoup_lazy(v, s[b.limb], sp[b.limb], q);
+        b.a[g] = v >= q ? v - q : v;
+    }
+};
+
+// rescale tail: out = (in - t) * q_l^-1
+struct OutRescaleFin {
+    const u64 *in;
+    long ls, ps;
+    u64 *out;
+    long ols, ops;
+    const u64 *inv, *invp;
+    __device__ void store(const Blk &b, long g, u64 v) const
+    {
+        const u64 q = b.pc->q;
+        v = reduce4(v, q);
+        u64 x = in[b.limb * ls + b.poly * ps + g];
+        out[b.limb * ols + b.poly * ops + g] = shoup(subm(x, v, q), inv[b.limb], invp[b.limb], q);
+    }
+};
+
+// ModDown tail: out_c = base_c + (acc_c - conv_c) * P^-1, acc and base poly 0
+// read through sigma_galois
+struct OutModdownFin {
+    const u64 *acc;
+    long acc_ls, acc_ps;
+    const u64 *base;
+    long bls, bps;
+    int mask;
+    u64 galois;
+    u64 *out;
+    long ols, ops;
+    const u64 *pinv, *pinvp;
+    __device__ void store(const Blk &b, long g, u64 v) const
+    {
+        const u64 q = b.pc->q;
+        v = reduce4(v, q);
+        const long gp = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
+        u64 a = acc[b.limb * acc_ls + b.poly * acc_ps + gp];
+        u64 r = shoup(subm(a, v, q), pinv[b.limb], pinvp[b.limb], q);
+        if (mask >> b.poly & 1) r = addm(r, base[b.limb * bls + b.poly * bps + (b.poly == 0 ? gp : g)], q);
+        out[b.limb * ols + b.poly * ops + g] = r;
+    }
+};
+
+// ----------------------------------------------------------------- phases
+// One phase of R stages (min distance 2^LS positions) over a tile of
+// 2^LP positions x 2^LL lines.  PASS 1: positions are rows, lines columns;
+// PASS 2: positions are words of a row, lines rows.
+template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT>
+__device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
+                                          const IN &in, const OUT &out)
+{
+    typedef NttGeo<LOGN> G;
+    constexpr int LP = PASS == 1 ? G::LR : G::LC;
+    constexpr int LL = PASS == 1 ? G::LTC : G::LRB;
+    constexpr int LU = LP - R + LL;
+    constexpr int LHI = LP - LS - R;
+    constexpr int LG = PASS == 1 ? LS + G::LC : LS;
+    const u64 q = bk.pc->q, q2 = 2 * q;
+    const long N = 1l << LOGN;
+#pragma unroll
+    for (int it = 0; it < ((1 << LU) + 255) / 256; it++) {
+        const int u = it * 256 + (int)threadIdx.x;
+        if ((1 << LU) % 256 != 0 && u >= (1 << LU)) break;
+        int lo, hi, line;
+        if (PASS == 1) {
+            line = u & ((1 << LL) - 1);
+            const int v = u >> LL;
+            lo = v & ((1 << LS) - 1);
+            hi = v >> LS;
+        } else {
+            lo = u & ((1 << LS) - 1);
+            const int v = u >> LS;
+            hi = v & ((1 << LHI) - 1);
+            line = v >> LHI;
+        }
+        const int p0 = (hi << (LS + R)) | lo;
+        auto gidx = [&](int p) -> long {
+            return PASS == 1 ? ((long)p << G::LC) + (blk << G::LTC) + line
+                             : (((blk << G::LRB) + line) << G::LC) + p;
+        };
+        auto lidx = [&](int p) -> int { return PASS == 1 ? (p << LL) + line : (line << LP) + p; };
+        u64 x[1 << R];
+#pragma unroll
+        for (int k = 0; k < (1 << R); k++) {
+            const int p = p0 + (k << LS);
+            x[k] = FIRST ? in.load(bk, gidx(p)) : sh[lidx(p)];
+        }
+        if (FWD) {
+#pragma unroll
+            for (int h = R - 1; h >= 0; h--) {
+#pragma unroll
+                for (int k = 0; k < (1 << R); k++) {
+                    if (k & (1 << h)) continue;
+                    const long idx = (N + gidx(p0 + (k << LS))) >> (LG + h + 1);
+                    ct_bfly(x[k], x[k + (1 << h)], w[idx], wp[idx], q, q2);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < R; h++) {
+#pragma unroll
+                for (int k = 0; k < (1 << R); k++) {
+                    if (k & (1 << h)) continue;
+                    const long idx = (N + gidx(p0 + (k << LS))) >> (LG + h + 1);
+                    gs_bfly(x[k], x[k + (1 << h)], w[idx], wp[idx], q, q2);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < (1 << R); k++) {
+            const int p = p0 + (k << LS);
+            if (LAST) out.store(bk, gidx(p), x[k]);
+            else sh[lidx(p)] = x[k];
+        }
+    }
+}
+
+// phase plan: forward 3,3,..,rem; inverse rem,..,3,3
+template <int LP, bool FWD, int PH>
+struct PhasePlan {
+    static constexpr int NPH = (LP + 2) / 3;
+    static constexpr int REM = LP - 3 * (NPH - 1);
+    static constexpr int R = FWD ? (PH < NPH - 1 ? 3 : REM) : (PH == 0 ? REM : 3);
+    static constexpr int BEFORE = FWD ? 3 * PH : (PH == 0 ? 0 : REM + 3 * (PH - 1));
+    static constexpr int LS = FWD ? LP - BEFORE - R : BEFORE;
+};
+
+template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT>
+__device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
+                                           const IN &in, const OUT &out)
+{
+    typedef NttGeo<LOGN> G;
+    constexpr int LP = PASS == 1 ? G::LR : G::LC;
+    typedef PhasePlan<LP, FWD, PH> P;
+    constexpr bool first = PH == 0, last = PH == P::NPH - 1;
+    ntt_phase<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, w, wp, in, out);
+    if constexpr (!last) {
+        __syncthreads();
+        ntt_phases<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, w, wp, in, out);
+    }
+}
+
+// own_w > 0: polynomial p of the set is key-switch digit p; its own limbs
+// [p own_w, min(p own_w + own_w, own_nq)) are skipped
+template <int LOGN, int PASS, bool FWD, class IN, class OUT>
+__global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi,
+                                             int own_w, int own_nq, IN in, OUT out)
+{
+    typedef NttGeo<LOGN> G;
+    constexpr int LT = PASS == 1 ? G::LR + G::LTC : G::LC + G::LRB;
+    __shared__ u64 sh[1 << LT];
+    const int y = blockIdx.y;
+    const int poly = y % ps.npoly;
+    const int li = y / ps.npoly;
+    const int limb = li < skip_lo ? li : li + (skip_hi - skip_lo);
+    if (own_w > 0 && limb >= poly * own_w && limb < min(poly * own_w + own_w, own_nq)) return;
+    const int pi = lm.prime(limb);
+    Blk bk;
+    bk.a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
+    bk.limb = limb;
+    bk.poly = poly;
+    bk.pc = T.pc + pi;
+    bk.logN = LOGN;
+    const u64 *w = (FWD ? T.fw : T.iw) + ((long)pi << LOGN);
+    const u64 *wp = (FWD ? T.fwp : T.iwp) + ((long)pi << LOGN);
+    ntt_phases<LOGN, PASS, FWD, 0, IN, OUT>(sh, bk, (long)blockIdx.x, w, wp, in, out);
+}
+
+// ---------------------------------------------------------------- launchers
+struct NttJob {
+    PolySet ps;
+    LimbMap lm;
+    int skip_lo = 0, skip_hi = 0, own_w = 0, own_nq = 0;
+};
+
+template <int LOGN, class IN, class OUT>
+static void fwd_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &out, hipStream_t s, KernelTimer *tm)
+{
+    typedef NttGeo<LOGN> G;
+    const int nl = j.ps.nl - (j.skip_hi - j.skip_lo);
+    dim3 blk(256), g1(1 << (G::LC - G::LTC), nl * j.ps.npoly), g2(1 << (G::LR - G::LRB), nl * j.ps.npoly);
+    const double polys = (double)nl * j.ps.npoly, bytes = 16.0 * (double)(1l << LOGN) * polys;
+    if constexpr (G::LR > 0) {
+        bool on = tm && tm->on(KID_NTT_FWD1);
+        if (on) tm->before(s);
+        hipLaunchKernelGGL((k_ntt<LOGN, 1, true, IN, OutWork<OW_LAZY>>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo,
+                           j.skip_hi, j.own_w, j.own_nq, in, OutWork<OW_LAZY>());
+        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
+        on = tm && tm->on(KID_NTT_FWD2);
+        if (on) tm->before(s);
+        hipLaunchKernelGGL((k_ntt<LOGN, 2, true, InWork, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, InWork(), out);
+        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
+    } else {
+        (void)g1;
+        (void)bytes;
+        hipLaunchKernelGGL((k_ntt<LOGN, 2, true, IN, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, in, out);
+    }
+}
+
+template <int LOGN, class IN, class OUT>
+static void inv_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &out, hipStream_t s, KernelTimer *tm)
+{
+    typedef NttGeo<LOGN> G;
+    const int nl = j.ps.nl - (j.skip_hi - j.skip_lo);
+    dim3 blk(256), g1(1 << (G::LC - G::LTC), nl * j.ps.npoly), g2(1 << (G::LR - G::LRB), nl * j.ps.npoly);
+    const double polys = (double)nl * j.ps.npoly, bytes = 16.0 * (double)(1l << LOGN) * polys;
+    if constexpr (G::LR > 0) {
+        bool on = tm && tm->on(KID_NTT_INV2);
+        if (on) tm->before(s);
+        hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OutWork<OW_LAZY>>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo,
+                           j.skip_hi, j.own_w, j.own_nq, in, OutWork<OW_LAZY>());
+        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
+        on = tm && tm->on(KID_NTT_INV1);
+        if (on) tm->before(s);
+        hipLaunchKernelGGL((k_ntt<LOGN, 1, false, InWork, OUT>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, InWork(), out);
+        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
+    } else {
+        (void)g1;
+        (void)bytes;
+        hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, in, out);
+    }
+}
+
+#define NTT_DISPATCH(FN, ...)                                                                  \
+    switch (t.logN) {                                                                          \
+    case 10: FN<10>(__VA_ARGS__); break;                                                       \
+    case 11: FN<11>(__VA_ARGS__); break;                                                       \
+    case 12: FN<12>(__VA_ARGS__); break;                                                       \
+    case 13: FN<13>(__VA_ARGS__); break;                                                       \
+    case 14: FN<14>(__VA_ARGS__); break;                                                       \
+    case 15: FN<15>(__VA_ARGS__); break;                                                       \
+    case 16: FN<16>(__VA_ARGS__); break;                                                       \
+    default: break;                                                                            \
+    }
+
+template <int LOGN>
+static void plain_n(const NttTables &t, const NttJob &j, bool inverse, hipStream_t s, KernelTimer *tm)
+{
+    if (!inverse) fwd_n<LOGN>(t, j, InWork(), OutWork<OW_REDUCE>(), s, tm);
+    else inv_n<LOGN>(t, j, InWork(), OutWork<OW_SCALE_N>(), s, tm);
+}
+
+void launch_ntt(const NttTables &t, PolySet ps, LimbMap lm, int skip_lo, int skip_hi, bool inverse,
+                hipStream_t s, KernelTimer *tm)
+{
+    NttJob j;
+    j.ps = ps;
+    j.lm = lm;
+    j.skip_lo = skip_lo;
+    j.skip_hi = skip_hi;
+    if (ps.nl - (skip_hi - skip_lo) <= 0) return;
+    NTT_DISPATCH(plain_n, t, j, inverse, s, tm);
+}
+
+// inverse transform of `src` (read through sigma_galois if galois > 1) into the
+// working set ps, every limb multiplied by scale[limb] (N^-1 folded in)
+template <int LOGN>
+static void intt_src_n(const NttTables &t, const NttJob &j, const InSrc &in, const OutScaleTab &o, hipStream_t s,
+                       KernelTimer *tm)
+{
+    if (o.s) inv_n<LOGN>(t, j, in, o, s, tm);
+    else inv_n<LOGN>(t, j, in, OutWork<OW_SCALE_N>(), s, tm);
+}
+
+void launch_intt_from(const NttTables &t, PolySet work, LimbMap lm, const u64 *src, long src_ls, long src_ps,
+                      u64 galois, const u64 *scale, const u64 *scalep, hipStream_t s, KernelTimer *tm)
+{
+    NttJob j;
+    j.ps = work;
+    j.lm = lm;
+    InSrc in{src, src_ls, src_ps, galois};
+    OutScaleTab o{scale, scalep};
+    NTT_DISPATCH(intt_src_n, t, j, in, o, s, tm);
+}
+
+// ModUp of all digits: ext is [ndig][next][N]; the forward transform of every
+// non-own limb of every digit starts from the fast basis conversion of the
+// digit's inverse-hat-scaled coefficients y (limb stride N)
+template <int LOGN>
+static void modup_n(const NttTables &t, const NttJob &j, const InBconv &in, hipStream_t s, KernelTimer *tm)
+{
+    fwd_n<LOGN>(t, j, in, OutWork<OW_REDUCE>(), s, tm);
+}
+
+void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, LimbMap lm, const u64 *y,
+                  const u64 *hatm, hipStream_t s, KernelTimer *tm)
+{
+    const long N = 1l << t.logN;
+    const int next = nq + alpha;
+    NttJob j;
+    j.ps = PolySet{ext, N, (long)next * N, next, ndig};
+    j.lm = lm;
+    j.own_w = w;
+    j.own_nq = nq;
+    InBconv in;
+    in.src = y;
+    in.src_ps = (long)w * N;
+    in.hatm = hatm;
+    in.hat_ps = (long)w * next;
+    in.hat_ks = next;
+    in.ns_fixed = 0;
+    in.w = w;
+    in.nq = nq;
+    NTT_DISPATCH(modup_n, t, j, in, s, tm);
+}
+
+// ModDown: yP [2][alpha][N] (inverse-hat-scaled P limbs, coefficient form) ->
+// forward transform of the conversion to Q_l, tail fused into the last store
+template <int LOGN>
+static void moddown_n(const NttTables &t, const NttJob &j, const InBconv &in, const OutModdownFin &o, hipStream_t s,
+                      KernelTimer *tm)
+{
+    fwd_n<LOGN>(t, j, in, o, s, tm);
+}
+
+void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, LimbMap lm, const u64 *yP, const u64 *hatm,
+                    long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm)
+{
+    const long N = 1l << t.logN;
+    NttJob j;
+    j.ps = PolySet{tmp, N, (long)nq * N, nq, 2};
+    j.lm = lm;
+    InBconv in;
+    in.src = yP;
+    in.src_ps = (long)alpha * N;
+    in.hatm = hatm;
+    in.hat_ps = 0;
+    in.hat_ks = hat_ks;
+    in.ns_fixed = alpha;
+    in.w = 0;
+    in.nq = nq;
+    OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bps, a.mask, a.galois, a.out, a.ols, a.ops,
+                    a.pinv, a.pinvp};
+    NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
+}
+
+// rescale of both polynomials: tmp [2][l][N] working set; last = dropped limb
+// in coefficient form ([2][N]); out = (in - NTT(...)) q_l^-1
+template <int LOGN>
+static void rescale_n(const NttTables &t, const NttJob &j, const InRescale &in, const OutRescaleFin &o,
+                      hipStream_t s, KernelTimer *tm)
+{
+    fwd_n<LOGN>(t, j, in, o, s, tm);
+}
+
+void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, const u64 *last, u64 ql, const u64 *in, long in_ls,
+                        long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
+                        int L1, hipStream_t s, KernelTimer *tm)
+{
+    const long N = 1l << t.logN;
+    NttJob j;
+    j.ps = PolySet{tmp, N, (long)l * N, l, 2};
+    j.lm = LimbMap{l, L1, 0};
+    InRescale ir{last, N, ql};
+    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp};
+    NTT_DISPATCH(rescale_n, t, j, ir, o, s, tm);
+}
+
+}  // namespace hk
