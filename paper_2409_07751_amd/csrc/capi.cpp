@@ -335,10 +335,15 @@ int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he
     if (!ctx || !m || !k || !out || (n && !in)) return HE_EINVAL;
     return guard(ctx, [&]() {
         for (size_t i = 0; i < n; i++) out[i] = nullptr;
+        if (n == 0) return;
+        std::vector<const Ct *> v;
         for (size_t i = 0; i < n; i++) {
             check_ct(ctx, in[i]);
-            out[i] = wrap(ctx, eval_model(*ctx->c, *m->m, *k->k, in[i]->c));
+            v.push_back(&in[i]->c);
         }
+        Ctx &c = *ctx->c;
+        Ct res = eval_model(c, *m->m, *k->k, c.pack(v));
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, c.unpack(res, (int)i));
     });
 }
 

@@ -254,22 +254,25 @@ void Ctx::ntt(PolySet ps, LimbMap lm, bool inverse, int skip_lo, int skip_hi)
 
 PolySet Ctx::ctset(const Ct &c, int nl) const
 {
-    return PolySet{c.d(), 2l * N, (long)N, nl < 0 ? c.level + 1 : nl, 2};
+    return PolySet{c.d(), 2l * N * c.nb, (long)N, nl < 0 ? c.level + 1 : nl, 2 * c.nb};
 }
 
+PolySet Ctx::c0set(const Ct &c) const { return PolySet{c.d(), 2l * N * c.nb, 2l * N, c.level + 1, c.nb}; }
+
 // ------------------------------------------------------------ simple ct ops
-Ct Ctx::new_ct(int level)
+Ct Ctx::new_ct(int level, int nb)
 {
     Ct c;
     c.level = level;
-    c.buf = alloc((size_t)(level + 1) * 2 * N);
+    c.nb = nb;
+    c.buf = alloc((size_t)(level + 1) * 2 * N * nb);
     return c;
 }
 
 Ct Ctx::add(const Ct &a, const Ct &b)
 {
-    if (a.level != b.level) throw HeError(-1, "add: level mismatch");
-    Ct o = new_ct(a.level);
+    if (a.level != b.level || a.nb != b.nb) throw HeError(-1, "add: level mismatch");
+    Ct o = new_ct(a.level, a.nb);
     launch_addsub(d_pc, ctset(o), ctset(a), ctset(b), lmap(a.level + 1), 0, N, st);
     n_launch++;
     return o;
@@ -277,8 +280,8 @@ Ct Ctx::add(const Ct &a, const Ct &b)
 
 Ct Ctx::sub(const Ct &a, const Ct &b)
 {
-    if (a.level != b.level) throw HeError(-1, "sub: level mismatch");
-    Ct o = new_ct(a.level);
+    if (a.level != b.level || a.nb != b.nb) throw HeError(-1, "sub: level mismatch");
+    Ct o = new_ct(a.level, a.nb);
     launch_addsub(d_pc, ctset(o), ctset(a), ctset(b), lmap(a.level + 1), 1, N, st);
     n_launch++;
     return o;
@@ -298,7 +301,7 @@ Ct Ctx::mul_int(const Ct &a, long k)
         upload(b->p, v.data(), v.size());
         it = int_cache.emplace((int)k, b).first;
     }
-    Ct o = new_ct(a.level);
+    Ct o = new_ct(a.level, a.nb);
     launch_mul_scalar(d_pc, ctset(o), ctset(a), it->second->p, it->second->p + L + 1, lmap(a.level + 1), N, st);
     n_launch++;
     return o;
@@ -319,20 +322,19 @@ Ct Ctx::add_const(const Ct &a, double c)
         upload(b->p, v.data(), v.size());
         it = const_cache.emplace(key, b).first;
     }
-    Ct o = new_ct(a.level);
+    Ct o = new_ct(a.level, a.nb);
     launch_copy(ctset(o), ctset(a), N, st);
-    launch_add_const(d_pc, ctset(o), it->second->p, lmap(a.level + 1), N, st);
+    launch_add_const(d_pc, c0set(o), it->second->p, lmap(a.level + 1), N, st);
     n_launch += 2;
     return o;
 }
 
 Ct Ctx::add_plain(const Ct &a, const Buf &pt)
 {
-    Ct o = new_ct(a.level);
+    Ct o = new_ct(a.level, a.nb);
     launch_copy(ctset(o), ctset(a), N, st);
-    PolySet o0 = ctset(o);
-    o0.npoly = 1;
-    PolySet p0{pt->p, (long)N, 0, a.level + 1, 1};
+    PolySet o0 = c0set(o);
+    PolySet p0{pt->p, (long)N, 0, a.level + 1, a.nb};
     launch_addsub(d_pc, o0, o0, p0, lmap(a.level + 1), 0, N, st);
     n_launch += 2;
     return o;
@@ -366,17 +368,17 @@ const Buf &Ctx::rescale_table(int l)
 // final (c_i - t_i) q_l^-1 run inside one fused NTT.
 Ct Ctx::rescale(const Ct &a)
 {
-    int l = a.level;
+    const int l = a.level, np = 2 * a.nb;
     if (l < 1) throw HeError(-3, "rescale: no level left");
     n_rescale++;
-    Buf last = alloc(2 * (size_t)N);
-    launch_intt_from(T, PolySet{last->p, (long)N, (long)N, 1, 2}, LimbMap{1, L1, l}, a.d() + (size_t)l * 2 * N,
-                     2l * N, (long)N, 0, nullptr, nullptr, st, &timer);
-    Buf tmp = alloc((size_t)l * 2 * N);
-    Ct o = new_ct(l - 1);
+    Buf last = alloc((size_t)np * N);
+    launch_intt_from(T, PolySet{last->p, (long)N, (long)N, 1, np}, LimbMap{1, L1, l},
+                     a.d() + (size_t)l * 2 * N * a.nb, 2l * N * a.nb, (long)N, 0, nullptr, nullptr, st, &timer);
+    Buf tmp = alloc((size_t)l * np * N);
+    Ct o = new_ct(l - 1, a.nb);
     const Buf &inv = rescale_table(l);
-    launch_rescale_ntt(T, tmp->p, l, last->p, q[l], a.d(), 2l * N, (long)N, o.d(), 2l * N, (long)N, inv->p,
-                       inv->p + l, L1, st, &timer);
+    launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
+                       (long)N, inv->p, inv->p + l, L1, st, &timer);
     n_launch += 4;
     return o;
 }
@@ -422,41 +424,46 @@ const KsTable &Ctx::ks_table(int l)
 // rotation the Galois automorphism acts on the extended digits; because the
 // Galois keys are stored permuted by sigma^-1, the inner product runs
 // unpermuted and sigma is applied when ModDown reads the accumulator.
-Ctx::ModUp Ctx::modup(const u64 *d, long ls, int l)
+Ctx::ModUp Ctx::modup(const u64 *d, long ls, long es, int l, int nb)
 {
     ModUp m;
     m.d = d;
     m.ls = ls;
+    m.es = es;
     m.l = l;
+    m.nb = nb;
     const int nq = l + 1, next = nq + alpha, nd = ndig(l);
     const LimbMap lm = lmap(nq);
     const KsTable &kt = ks_table(l);
     // y = INTT(d) * invhat / N, then every digit's conversion and NTT
-    Buf y = alloc((size_t)nq * N);
-    launch_intt_from(T, PolySet{y->p, (long)N, 0, nq, 1}, lm, d, ls, 0, 0, kt.scale, kt.scalep, st, &timer);
-    m.ext = alloc((size_t)nd * next * N);
-    launch_modup(T, m.ext->p, nd, nq, alpha, w, lm, y->p, kt.hatm, st, &timer);
+    Buf y = alloc((size_t)nb * nq * N);
+    launch_intt_from(T, PolySet{y->p, (long)N, (long)nq * N, nq, nb}, lm, d, ls, es, 0, kt.scale, kt.scalep, st,
+                     &timer);
+    m.ext = alloc((size_t)nb * nd * next * N);
+    launch_modup(T, m.ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, st, &timer);
     n_launch += 3;
     return m;
 }
 
 void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
-                         long base_ps, int base_mask, Ct &out)
+                         long base_es, int base_mask, Ct &out)
 {
-    n_ks++;
-    const int l = m.l, nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
+    n_ks += m.nb;
+    const int l = m.l, nb = m.nb, nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
     const LimbMap lm = lmap(nq);
-    Buf acc = alloc((size_t)2 * next * N);
-    launch_keyip(d_pc, acc->p, (long)next * N, m.ext->p, (long)next * N, m.d, m.ls, key.buf->p, 2l * ktot * N,
-                 (long)ktot * N, nd, next, nq, w, lm, L1, logN, st, &timer);
-    // ModDown
-    Buf yP = alloc((size_t)2 * alpha * N);
-    launch_intt_from(T, PolySet{yP->p, (long)N, (long)alpha * N, alpha, 2}, LimbMap{0, L1}, acc->p + (size_t)nq * N,
-                     (long)N, (long)next * N, galois, md_tab->p, md_tab->p + alpha, st, &timer);
-    Buf tmp = alloc((size_t)2 * nq * N);
-    OutModdownArgs oa{acc->p, (long)N, (long)next * N, base, base_ls, base_ps, base_mask, galois, out.d(), 2l * N,
-                      (long)N, pinv->p, pinv->p + L + 1};
-    launch_moddown(T, tmp->p, nq, alpha, lm, yP->p, md_tab->p + 2 * alpha, L + 1, oa, st, &timer);
+    Buf acc = alloc((size_t)nb * 2 * next * N);
+    launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, m.ext->p, (long)next * N, (long)nd * next * N, m.d,
+                 m.ls, m.es, key.buf->p, 2l * ktot * N, (long)ktot * N, nd, next, nq, w, nb, lm, L1, logN, st,
+                 &timer);
+    // ModDown of the 2 nb accumulator polynomials
+    Buf yP = alloc((size_t)nb * 2 * alpha * N);
+    launch_intt_from(T, PolySet{yP->p, (long)N, (long)alpha * N, alpha, 2 * nb}, LimbMap{0, L1},
+                     acc->p + (size_t)nq * N, (long)N, (long)next * N, galois, md_tab->p, md_tab->p + alpha, st,
+                     &timer);
+    Buf tmp = alloc((size_t)nb * 2 * nq * N);
+    OutModdownArgs oa{acc->p, (long)N, (long)next * N, base, base_ls, base_es, (long)N, base_mask, galois, out.d(),
+                      2l * N * nb, (long)N, pinv->p, pinv->p + L + 1};
+    launch_moddown(T, tmp->p, nq, alpha, 2 * nb, lm, yP->p, md_tab->p + 2 * alpha, L + 1, oa, st, &timer);
     n_launch += 6;
 }
 
@@ -466,20 +473,22 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
 // rotation the Galois automorphism acts on the extended digits; because the
 // Galois keys are stored permuted by sigma^-1, the inner product runs
 // unpermuted and sigma is applied when ModDown reads the accumulator.
-void Ctx::keyswitch(const u64 *d, long ls, int l, const SwitchKey &key, u64 galois, const u64 *base,
-                    long base_ls, long base_ps, int base_mask, Ct &out)
+// d: nb polynomials, limb stride ls, element stride es.
+void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
+                    const u64 *base, long base_ls, long base_es, int base_mask, Ct &out)
 {
-    ModUp m = modup(d, ls, l);
-    keyswitch_from(m, key, galois, base, base_ls, base_ps, base_mask, out);
+    ModUp m = modup(d, ls, es, l, nb);
+    keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out);
 }
 
 Tensor Ctx::tensor(const Ct &a, const Ct &b)
 {
-    if (a.level != b.level) throw HeError(-1, "tensor: level mismatch");
+    if (a.level != b.level || a.nb != b.nb) throw HeError(-1, "tensor: level mismatch");
     Tensor t;
     t.level = a.level;
-    t.buf = alloc((size_t)(a.level + 1) * 3 * N);
-    launch_tensor(d_pc, PolySet{t.buf->p, 3l * N, (long)N, a.level + 1, 3}, ctset(a), ctset(b),
+    t.nb = a.nb;
+    t.buf = alloc((size_t)(a.level + 1) * 3 * N * a.nb);
+    launch_tensor(d_pc, PolySet{t.buf->p, 3l * N * a.nb, 3l * N, a.level + 1, a.nb}, c0set(a), c0set(b),
                   lmap(a.level + 1), N, false, st);
     n_launch++;
     return t;
@@ -487,17 +496,19 @@ Tensor Ctx::tensor(const Ct &a, const Ct &b)
 
 void Ctx::tensor_acc(Tensor &t, const Ct &a, const Ct &b)
 {
-    if (a.level != b.level || a.level != t.level) throw HeError(-1, "tensor: level mismatch");
-    launch_tensor(d_pc, PolySet{t.buf->p, 3l * N, (long)N, a.level + 1, 3}, ctset(a), ctset(b),
+    if (a.level != b.level || a.level != t.level || a.nb != t.nb || b.nb != t.nb)
+        throw HeError(-1, "tensor: level mismatch");
+    launch_tensor(d_pc, PolySet{t.buf->p, 3l * N * a.nb, 3l * N, a.level + 1, a.nb}, c0set(a), c0set(b),
                   lmap(a.level + 1), N, true, st);
     n_launch++;
 }
 
 Ct Ctx::relin_rescale(const Tensor &t, const Keys &k)
 {
-    Ct c = new_ct(t.level);
+    Ct c = new_ct(t.level, t.nb);
     const u64 *tb = t.buf->p;
-    keyswitch(tb + 2 * (size_t)N, 3l * N, t.level, k.relin, 0, tb, 3l * N, (long)N, 3, c);
+    const long ls = 3l * N * t.nb, es = 3l * N;
+    keyswitch(tb + 2 * (size_t)N, ls, es, t.level, t.nb, k.relin, 0, tb, ls, es, 3, c);
     return rescale(c);
 }
 
@@ -508,8 +519,9 @@ std::vector<Ct> Ctx::rotate_many(const Ct &a, const std::vector<long> &steps, co
     std::vector<Ct> out;
     bool need = false;
     for (long s : steps) need |= galois_elt(s) != 1;
+    const long ls = 2l * N * a.nb, es = 2l * N;
     ModUp m;
-    if (need) m = modup(a.d() + N, 2l * N, a.level);
+    if (need) m = modup(a.d() + N, ls, es, a.level, a.nb);
     for (long s : steps) {
         u64 g = galois_elt(s);
         if (g == 1) {
@@ -518,8 +530,8 @@ std::vector<Ct> Ctx::rotate_many(const Ct &a, const std::vector<long> &steps, co
         }
         auto it = k.galois.find(g);
         if (it == k.galois.end()) throw HeError(-5, "no Galois key for rotation step " + std::to_string(s));
-        Ct o = new_ct(a.level);
-        keyswitch_from(m, it->second, g, a.d(), 2l * N, (long)N, 1, o);
+        Ct o = new_ct(a.level, a.nb);
+        keyswitch_from(m, it->second, g, a.d(), ls, es, 1, o);
         out.push_back(o);
     }
     return out;
@@ -531,8 +543,9 @@ Ct Ctx::rotate(const Ct &a, long step, const Keys &k)
     if (g == 1) return a;
     auto it = k.galois.find(g);
     if (it == k.galois.end()) throw HeError(-5, "no Galois key for rotation step " + std::to_string(step));
-    Ct o = new_ct(a.level);
-    keyswitch(a.d() + N, 2l * N, a.level, it->second, g, a.d(), 2l * N, (long)N, 1, o);
+    Ct o = new_ct(a.level, a.nb);
+    const long ls = 2l * N * a.nb, es = 2l * N;
+    keyswitch(a.d() + N, ls, es, a.level, a.nb, it->second, g, a.d(), ls, es, 1, o);
     return o;
 }
 
@@ -592,8 +605,8 @@ Pt Ctx::vec_pt(const double *z, size_t n, double scale, int nl)
 Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t)
 {
     if (terms.empty()) throw HeError(-1, "lincomb: no terms");
-    int nl = t + 2;
-    Ct acc = new_ct(t + 1);
+    const int nl = t + 2, nb = terms[0].first->nb;
+    Ct acc = new_ct(t + 1, nb);
     const int CH = 15;
     bool first = true;
     for (size_t s0 = 0; s0 < terms.size(); s0 += CH) {
@@ -601,6 +614,7 @@ Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int
         std::vector<const u64 *> ab, pb;
         for (size_t i = s0; i < s1; i++) {
             if (terms[i].first->level < t + 1) throw HeError(-3, "lincomb: operand below target level");
+            if (terms[i].first->nb != nb) throw HeError(-1, "lincomb: batch mismatch");
             if (terms[i].second->nl < nl) throw HeError(-1, "lincomb: plaintext has too few limbs");
             ab.push_back(terms[i].first->d());
             const u64 *pp = terms[i].second->buf->p;
@@ -608,12 +622,12 @@ Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int
             pb.push_back(pp);
         }
         if (first) {
-            launch_lincomb(d_pc, ctset(acc), ab.data(), 2l * N, (long)N, pb.data(), (long)N, (int)ab.size(),
+            launch_lincomb(d_pc, ctset(acc), ab.data(), 2l * N * nb, (long)N, pb.data(), (long)N, (int)ab.size(),
                            lmap(nl), N, st);
             first = false;
         } else {
-            Ct part = new_ct(t + 1);
-            launch_lincomb(d_pc, ctset(part), ab.data(), 2l * N, (long)N, pb.data(), (long)N, (int)ab.size(),
+            Ct part = new_ct(t + 1, nb);
+            launch_lincomb(d_pc, ctset(part), ab.data(), 2l * N * nb, (long)N, pb.data(), (long)N, (int)ab.size(),
                            lmap(nl), N, st);
             launch_addsub(d_pc, ctset(acc), ctset(acc), ctset(part), lmap(nl), 0, N, st);
             n_launch++;
@@ -629,6 +643,28 @@ Ct Ctx::level_down(const Ct &a, int t)
     if (a.level < t) throw HeError(-3, "level_down: target above operand");
     Pt one = const_pt(1.0, S[t] * (double)q[t + 1] / S[a.level], t + 2);
     return lincomb({{&a, &one}}, t);
+}
+
+// ----------------------------------------------------------- batches
+Ct Ctx::pack(const std::vector<const Ct *> &cts)
+{
+    if (cts.empty()) throw HeError(-1, "pack: empty batch");
+    const int l = cts[0]->level, nb = (int)cts.size();
+    Ct o = new_ct(l, nb);
+    for (int e = 0; e < nb; e++) {
+        if (cts[e]->level != l || cts[e]->nb != 1) throw HeError(-1, "pack: ciphertexts at different levels");
+        launch_copy(PolySet{o.d() + (size_t)e * 2 * N, 2l * N * nb, (long)N, l + 1, 2}, ctset(*cts[e]), N, st);
+        n_launch++;
+    }
+    return o;
+}
+
+Ct Ctx::unpack(const Ct &b, int e)
+{
+    Ct o = new_ct(b.level, 1);
+    launch_copy(ctset(o), PolySet{b.d() + (size_t)e * 2 * N, 2l * N * b.nb, (long)N, b.level + 1, 2}, N, st);
+    n_launch++;
+    return o;
 }
 
 // ------------------------------------------------------------------- client

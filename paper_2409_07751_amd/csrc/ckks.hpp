@@ -49,8 +49,10 @@ typedef std::shared_ptr<DevBuf> Buf;
 
 // Ciphertext: level l, [l+1][2][N] residues in NTT form (limb-major, c0 then
 // c1 inside each limb), scale = canonical S[l].
+// A batch of nb ciphertexts is [l+1][nb][2][N]: every launch covers all of them.
 struct Ct {
     int level = -1;
+    int nb = 1;
     Buf buf;
     u64 *d() const { return buf->p; }
 };
@@ -58,6 +60,7 @@ struct Ct {
 // Tensor product (d0, d1, d2) before relinearisation: [l+1][3][N].
 struct Tensor {
     int level = -1;
+    int nb = 1;
     Buf buf;
 };
 
@@ -125,10 +128,11 @@ struct Ctx {
 
     // polynomial helpers
     void ntt(PolySet ps, LimbMap lm, bool inverse, int skip_lo = 0, int skip_hi = 0);
-    PolySet ctset(const Ct &c, int nl = -1) const;
+    PolySet ctset(const Ct &c, int nl = -1) const;  // all 2 nb polynomials
+    PolySet c0set(const Ct &c) const;              // the nb c0 polynomials (c1 at +N)
 
     // ciphertext ops (every result has canonical scale S[level])
-    Ct new_ct(int level);
+    Ct new_ct(int level, int nb = 1);
     Ct add(const Ct &a, const Ct &b);
     Ct sub(const Ct &a, const Ct &b);
     Ct mul_int(const Ct &a, long k);
@@ -148,15 +152,18 @@ struct Ctx {
     // the ModUp part can be shared by several keys (hoisted rotations)
     struct ModUp {
         const u64 *d = nullptr;
-        long ls = 0;
-        int l = -1;
+        long ls = 0, es = 0;
+        int l = -1, nb = 1;
         Buf ext;
     };
-    ModUp modup(const u64 *d, long ls, int l);
+    ModUp modup(const u64 *d, long ls, long es, int l, int nb);
     void keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
-                        long base_ps, int base_mask, Ct &out);
-    void keyswitch(const u64 *d, long ls, int l, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
-                   long base_ps, int base_mask, Ct &out);
+                        long base_es, int base_mask, Ct &out);
+    void keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
+                   const u64 *base, long base_ls, long base_es, int base_mask, Ct &out);
+    // batches of single ciphertexts at one level
+    Ct pack(const std::vector<const Ct *> &cts);
+    Ct unpack(const Ct &batch, int e);
     // rotations of one ciphertext by several steps sharing one ModUp
     std::vector<Ct> rotate_many(const Ct &a, const std::vector<long> &steps, const Keys &k);
 

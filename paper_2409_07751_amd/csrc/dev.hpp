@@ -90,37 +90,40 @@ void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s);
 // Montgomery form): acc_c[t] = sum_j e_j[t] * key_j[c][kt(t)], c = 0, 1, where
 // e_j[t] is the input d itself on digit j's own limbs and ext_j[t] elsewhere.
 // Galois keys are stored permuted by sigma^-1, so no permutation happens here.
-void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
-                  const u64 *d, long d_ls, const u64 *key, long key_dstride, long key_cstride, int ndig, int nl,
-                  int nq, int w, LimbMap lm, int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
+void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
+                  long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
+                  long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
+                  int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
 
 // --- fused transforms (ntt.hip)
 // inverse transform of src (through sigma_galois if galois > 1) into `work`;
 // limb i is multiplied by scale[i] (N^-1 folded in), or by N^-1 if scale is null
 void launch_intt_from(const NttTables &t, PolySet work, LimbMap lm, const u64 *src, long src_ls, long src_ps,
                       u64 galois, const u64 *scale, const u64 *scalep, hipStream_t s, KernelTimer *tm = nullptr);
-// ModUp of every digit at once: ext [ndig][nq+alpha][N] <- NTT(BConv(y_digit))
-// on every limb outside the digit; hatm [ndig][w][nq+alpha] Montgomery form
-void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, LimbMap lm, const u64 *y,
-                  const u64 *hatm, hipStream_t s, KernelTimer *tm = nullptr);
+// ModUp of every digit of nb ciphertexts at once: ext [nb][ndig][nq+alpha][N] <-
+// NTT(BConv(y_digit)) on every limb outside the digit; y [nb][nq][N];
+// hatm [ndig][w][nq+alpha] Montgomery form
+void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
+                  const u64 *y, const u64 *hatm, hipStream_t s, KernelTimer *tm = nullptr);
 struct OutModdownArgs {
     const u64 *acc;
     long acc_ls, acc_ps;
-    const u64 *base;
-    long bls, bps;
-    int mask;  // bit c: add base polynomial c (polynomial 0 through sigma_galois)
+    const u64 *base;  // element e component c of limb i at base + i bls + e bes + c bcs
+    long bls, bes, bcs;
+    int mask;  // bit c: add base component c (component 0 through sigma_galois)
     u64 galois;
     u64 *out;
     long ols, ops;
     const u64 *pinv, *pinvp;
 };
-// ModDown: out_c = base_c + (acc_c - NTT(BConv_{P->Q}(yP_c))) P^-1, tmp [2][nq][N]
-void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, LimbMap lm, const u64 *yP, const u64 *hatm,
-                    long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
-// rescale by q_l of both polynomials: out_i = (in_i - NTT_i([last + h] - h)) q_l^-1
-void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, const u64 *last, u64 ql, const u64 *in, long in_ls,
-                        long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp, int L1,
-                        hipStream_t s, KernelTimer *tm = nullptr);
+// ModDown of npoly (= 2 nb) polynomials: out_p = base_p + (acc_p - NTT(BConv_{P->Q}(yP_p))) P^-1,
+// tmp [npoly][nq][N], yP [npoly][alpha][N]
+void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, LimbMap lm, const u64 *yP,
+                    const u64 *hatm, long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
+// rescale by q_l of npoly polynomials: out_i = (in_i - NTT_i([last + h] - h)) q_l^-1
+void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
+                        long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
+                        int L1, hipStream_t s, KernelTimer *tm = nullptr);
 // copy limbs
 void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);
 // pointwise product out = a * b (single polynomials, Barrett)

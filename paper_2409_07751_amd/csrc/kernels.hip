@@ -59,47 +59,47 @@ void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *
 __global__ void k_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N)
 {
     EW_INDEX
-    if (poly != 0) return;
     u64 q = pc[lm.prime(limb)].q;
-    u64 *p = a.base + limb * a.lstride + n;
+    u64 *p = a.base + limb * a.lstride + poly * a.pstride + n;
     *p = addm(*p, c[limb], q);
 }
 
+// a: the c0 polynomials of a ciphertext batch
 void launch_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N, hipStream_t s)
 {
-    PolySet a1 = a;
-    a1.npoly = 1;
-    dim3 g((N + 255) / 256, a.nl);
-    hipLaunchKernelGGL(k_add_const, g, dim3(256), 0, s, pc, a1, c, lm, N);
+    dim3 g((N + 255) / 256, a.nl * a.npoly);
+    hipLaunchKernelGGL(k_add_const, g, dim3(256), 0, s, pc, a, c, lm, N);
 }
 
-// d: [limb][3][N] (pstride), a, b: two polynomials each
+// batch element e of d holds (d0, d1, d2) at +0, +N, +2N; of a and b (c0, c1)
+// at +0, +N; pstride is the element stride
 __global__ void k_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, int acc)
 {
-    int limb = blockIdx.y;
-    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int e = y % a.npoly, limb = y / a.npoly;
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const PrimeConst &c = pc[lm.prime(limb)];
-    const u64 *pa = a.base + limb * a.lstride + n, *pb = b.base + limb * b.lstride + n;
-    u64 a0 = pa[0], a1 = pa[a.pstride], b0 = pb[0], b1 = pb[b.pstride];
+    const u64 *pa = a.base + limb * a.lstride + e * a.pstride + n, *pb = b.base + limb * b.lstride + e * b.pstride + n;
+    u64 a0 = pa[0], a1 = pa[N], b0 = pb[0], b1 = pb[N];
     u64 d0 = barrett(a0, b0, c);
     u64 d1 = addm(barrett(a0, b1, c), barrett(a1, b0, c), c.q);
     u64 d2 = barrett(a1, b1, c);
-    u64 *pd = d.base + limb * d.lstride + n;
+    u64 *pd = d.base + limb * d.lstride + e * d.pstride + n;
     if (acc) {
         d0 = addm(d0, pd[0], c.q);
-        d1 = addm(d1, pd[d.pstride], c.q);
-        d2 = addm(d2, pd[2 * d.pstride], c.q);
+        d1 = addm(d1, pd[N], c.q);
+        d2 = addm(d2, pd[2 * N], c.q);
     }
     pd[0] = d0;
-    pd[d.pstride] = d1;
-    pd[2 * d.pstride] = d2;
+    pd[N] = d1;
+    pd[2 * N] = d2;
 }
 
 void launch_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, bool acc,
                    hipStream_t s)
 {
-    dim3 g((N + 255) / 256, a.nl);
+    dim3 g((N + 255) / 256, a.nl * a.npoly);
     hipLaunchKernelGGL(k_tensor, g, dim3(256), 0, s, pc, d, a, b, lm, N, acc ? 1 : 0);
 }
 
@@ -189,40 +189,45 @@ void launch_pmul(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMa
 }
 
 // ---------------------------------------------------- key-switch inner product
-__global__ void k_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
-                        const u64 *d, long d_ls, const u64 *key, long key_dstride, long key_cstride, int ndig,
-                        int nq, int w, LimbMap lm, int key_nq_off, int logN)
+__global__ void k_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
+                        long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
+                        long key_dstride, long key_cstride, int ndig, int nq, int w, LimbMap lm, int key_nq_off,
+                        int logN)
 {
-    const int t = blockIdx.y;
+    const int t = blockIdx.y, b = blockIdx.z;
     const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long N = 1l << logN;
     if (n >= N) return;
     const PrimeConst &c = pc[lm.prime(t)];
     const int kt = t < lm.nq ? t : key_nq_off + (t - lm.nq);
+    const u64 *eb = ext + b * ext_bstride, *db = d + b * d_bstride;
     u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
     for (int j = 0; j < ndig; j++) {
         const bool own = t >= j * w && t < min(j * w + w, nq);
-        const u64 e = own ? d[t * d_ls + n] : ext[j * ext_dstride + t * N + n];
+        const u64 e = own ? db[t * d_ls + n] : eb[j * ext_dstride + t * N + n];
         const u64 *kp = key + j * key_dstride + kt * N + n;
         mac(lo0, hi0, e, kp[0]);
         mac(lo1, hi1, e, kp[key_cstride]);
     }
-    acc[t * N + n] = redc(lo0, hi0, c);
-    acc[acc_pstride + t * N + n] = redc(lo1, hi1, c);
+    u64 *ab = acc + b * acc_bstride;
+    ab[t * N + n] = redc(lo0, hi0, c);
+    ab[acc_pstride + t * N + n] = redc(lo1, hi1, c);
 }
 
-void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, const u64 *ext, long ext_dstride,
-                  const u64 *d, long d_ls, const u64 *key, long key_dstride, long key_cstride, int ndig, int nl,
-                  int nq, int w, LimbMap lm, int key_nq_off, int logN, hipStream_t s, KernelTimer *tm)
+void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
+                  long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
+                  long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
+                  int key_nq_off, int logN, hipStream_t s, KernelTimer *tm)
 {
     const int N = 1 << logN;
-    dim3 g((N + 255) / 256, nl);
+    dim3 g((N + 255) / 256, nl, nb);
     bool on = tm && tm->on(KID_KEYIP);
     if (on) tm->before(s);
-    hipLaunchKernelGGL(k_keyip, g, dim3(256), 0, s, pc, acc, acc_pstride, ext, ext_dstride, d, d_ls, key,
-                       key_dstride, key_cstride, ndig, nq, w, lm, key_nq_off, logN);
-    // reads ndig extended digits and 2 ndig key polynomials, writes 2 outputs
-    if (on) tm->after(s, 8.0 * N * nl * (3.0 * ndig + 2.0), 2.0 * N * nl * ndig);
+    hipLaunchKernelGGL(k_keyip, g, dim3(256), 0, s, pc, acc, acc_pstride, acc_bstride, ext, ext_dstride,
+                       ext_bstride, d, d_ls, d_bstride, key, key_dstride, key_cstride, ndig, nq, w, lm, key_nq_off,
+                       logN);
+    // reads nb ndig extended digits and 2 ndig key polynomials, writes 2 nb outputs
+    if (on) tm->after(s, 8.0 * N * nl * (nb * ndig + 2.0 * ndig + 2.0 * nb), 2.0 * N * nl * ndig * nb);
 }
 
 // -------------------------------------------------------- keys and client ops

@@ -87,18 +87,22 @@ struct InSrc {
 // fast basis conversion: sum_k y_k * hat(k, target) with y in coefficient form
 // (already multiplied by the inverse hat constants), hat in Montgomery form
 struct InBconv {
-    const u64 *src;     // polynomial p's sources start at src + p * src_ps, limb stride N
-    long src_ps;
-    const u64 *hatm;    // hat(k, t) at hatm[p * hat_ps + k * hat_ks + t]
+    // polynomial p = e ndig + j (batch element e, digit j): sources at
+    // src + e src_bs + j src_ps, limb stride N; hat(k, t) at hatm[j hat_ps + k hat_ks + t]
+    const u64 *src;
+    long src_bs, src_ps;
+    const u64 *hatm;
     long hat_ps, hat_ks;
+    int ndig;
     int ns_fixed;       // > 0: every polynomial has ns_fixed sources
-    int w, nq;          // else digit p has min(w, nq - p w) sources
+    int w, nq;          // else digit j has min(w, nq - j w) sources
     __device__ u64 load(const Blk &b, long g) const
     {
-        const int ns = ns_fixed > 0 ? ns_fixed : min(w, nq - b.poly * w);
+        const int e = b.poly / ndig, j = b.poly - e * ndig;
+        const int ns = ns_fixed > 0 ? ns_fixed : min(w, nq - j * w);
         const long N = 1l << b.logN;
-        const u64 *s = src + b.poly * src_ps + g;
-        const u64 *h = hatm + b.poly * hat_ps + b.limb;
+        const u64 *s = src + e * src_bs + j * src_ps + g;
+        const u64 *h = hatm + j * hat_ps + b.limb;
         u64 lo = 0, hi = 0;
         for (int k = 0; k < ns; k++) mac(lo, hi, s[k * N], h[k * hat_ks]);
         return redc(lo, hi, *b.pc);
@@ -161,13 +165,13 @@ struct OutRescaleFin {
     }
 };
 
-// ModDown tail: out_c = base_c + (acc_c - conv_c) * P^-1, acc and base poly 0
-// read through sigma_galois
+// ModDown tail: out_p = base_p + (acc_p - conv_p) * P^-1 for polynomial
+// p = 2 e + c; acc and base component 0 read through sigma_galois
 struct OutModdownFin {
     const u64 *acc;
     long acc_ls, acc_ps;
     const u64 *base;
-    long bls, bps;
+    long bls, bes, bcs;
     int mask;
     u64 galois;
     u64 *out;
@@ -180,7 +184,8 @@ struct OutModdownFin {
         const long gp = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
         u64 a = acc[b.limb * acc_ls + b.poly * acc_ps + gp];
         u64 r = shoup(subm(a, v, q), pinv[b.limb], pinvp[b.limb], q);
-        if (mask >> b.poly & 1) r = addm(r, base[b.limb * bls + b.poly * bps + (b.poly == 0 ? gp : g)], q);
+        const int e = b.poly >> 1, c = b.poly & 1;
+        if (mask >> c & 1) r = addm(r, base[b.limb * bls + e * bes + c * bcs + (c == 0 ? gp : g)], q);
         out[b.limb * ols + b.poly * ops + g] = r;
     }
 };
@@ -284,11 +289,11 @@ __device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, con
     }
 }
 
-// own_w > 0: polynomial p of the set is key-switch digit p; its own limbs
-// [p own_w, min(p own_w + own_w, own_nq)) are skipped
+// own_w > 0: polynomial p of the set is key-switch digit j = p mod own_ndig;
+// its own limbs [j own_w, min(j own_w + own_w, own_nq)) are skipped
 template <int LOGN, int PASS, bool FWD, class IN, class OUT>
 __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi,
-                                             int own_w, int own_nq, IN in, OUT out)
+                                             int own_w, int own_nq, int own_ndig, IN in, OUT out)
 {
     typedef NttGeo<LOGN> G;
     constexpr int LT = PASS == 1 ? G::LR + G::LTC : G::LC + G::LRB;
@@ -297,7 +302,10 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
     const int poly = y % ps.npoly;
     const int li = y / ps.npoly;
     const int limb = li < skip_lo ? li : li + (skip_hi - skip_lo);
-    if (own_w > 0 && limb >= poly * own_w && limb < min(poly * own_w + own_w, own_nq)) return;
+    if (own_w > 0) {
+        const int j = poly % own_ndig;
+        if (limb >= j * own_w && limb < min(j * own_w + own_w, own_nq)) return;
+    }
     const int pi = lm.prime(limb);
     Blk bk;
     bk.a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
@@ -314,7 +322,7 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
 struct NttJob {
     PolySet ps;
     LimbMap lm;
-    int skip_lo = 0, skip_hi = 0, own_w = 0, own_nq = 0;
+    int skip_lo = 0, skip_hi = 0, own_w = 0, own_nq = 0, own_ndig = 1;
 };
 
 template <int LOGN, class IN, class OUT>
@@ -328,18 +336,18 @@ static void fwd_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &
         bool on = tm && tm->on(KID_NTT_FWD1);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 1, true, IN, OutWork<OW_LAZY>>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo,
-                           j.skip_hi, j.own_w, j.own_nq, in, OutWork<OW_LAZY>());
+                           j.skip_hi, j.own_w, j.own_nq, j.own_ndig, in, OutWork<OW_LAZY>());
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
         on = tm && tm->on(KID_NTT_FWD2);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 2, true, InWork, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
-                           j.own_w, j.own_nq, InWork(), out);
+                           j.own_w, j.own_nq, j.own_ndig, InWork(), out);
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
     } else {
         (void)g1;
         (void)bytes;
         hipLaunchKernelGGL((k_ntt<LOGN, 2, true, IN, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
-                           j.own_w, j.own_nq, in, out);
+                           j.own_w, j.own_nq, j.own_ndig, in, out);
     }
 }
 
@@ -354,18 +362,18 @@ static void inv_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &
         bool on = tm && tm->on(KID_NTT_INV2);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OutWork<OW_LAZY>>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo,
-                           j.skip_hi, j.own_w, j.own_nq, in, OutWork<OW_LAZY>());
+                           j.skip_hi, j.own_w, j.own_nq, j.own_ndig, in, OutWork<OW_LAZY>());
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
         on = tm && tm->on(KID_NTT_INV1);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 1, false, InWork, OUT>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
-                           j.own_w, j.own_nq, InWork(), out);
+                           j.own_w, j.own_nq, j.own_ndig, InWork(), out);
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
     } else {
         (void)g1;
         (void)bytes;
         hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
-                           j.own_w, j.own_nq, in, out);
+                           j.own_w, j.own_nq, j.own_ndig, in, out);
     }
 }
 
@@ -430,19 +438,22 @@ static void modup_n(const NttTables &t, const NttJob &j, const InBconv &in, hipS
     fwd_n<LOGN>(t, j, in, OutWork<OW_REDUCE>(), s, tm);
 }
 
-void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, LimbMap lm, const u64 *y,
-                  const u64 *hatm, hipStream_t s, KernelTimer *tm)
+void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
+                  const u64 *y, const u64 *hatm, hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     const int next = nq + alpha;
     NttJob j;
-    j.ps = PolySet{ext, N, (long)next * N, next, ndig};
+    j.ps = PolySet{ext, N, (long)next * N, next, ndig * nb};
     j.lm = lm;
     j.own_w = w;
     j.own_nq = nq;
+    j.own_ndig = ndig;
     InBconv in;
     in.src = y;
+    in.src_bs = (long)nq * N;
     in.src_ps = (long)w * N;
+    in.ndig = ndig;
     in.hatm = hatm;
     in.hat_ps = (long)w * next;
     in.hat_ks = next;
@@ -461,23 +472,25 @@ static void moddown_n(const NttTables &t, const NttJob &j, const InBconv &in, co
     fwd_n<LOGN>(t, j, in, o, s, tm);
 }
 
-void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, LimbMap lm, const u64 *yP, const u64 *hatm,
-                    long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm)
+void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, LimbMap lm, const u64 *yP,
+                    const u64 *hatm, long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     NttJob j;
-    j.ps = PolySet{tmp, N, (long)nq * N, nq, 2};
+    j.ps = PolySet{tmp, N, (long)nq * N, nq, npoly};
     j.lm = lm;
     InBconv in;
     in.src = yP;
-    in.src_ps = (long)alpha * N;
+    in.src_bs = (long)alpha * N;
+    in.src_ps = 0;
+    in.ndig = 1;
     in.hatm = hatm;
     in.hat_ps = 0;
     in.hat_ks = hat_ks;
     in.ns_fixed = alpha;
     in.w = 0;
     in.nq = nq;
-    OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bps, a.mask, a.galois, a.out, a.ols, a.ops,
+    OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.mask, a.galois, a.out, a.ols, a.ops,
                     a.pinv, a.pinvp};
     NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
 }
@@ -491,13 +504,13 @@ static void rescale_n(const NttTables &t, const NttJob &j, const InRescale &in, 
     fwd_n<LOGN>(t, j, in, o, s, tm);
 }
 
-void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, const u64 *last, u64 ql, const u64 *in, long in_ls,
-                        long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
+void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
+                        long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
                         int L1, hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     NttJob j;
-    j.ps = PolySet{tmp, N, (long)l * N, l, 2};
+    j.ps = PolySet{tmp, N, (long)l * N, l, npoly};
     j.lm = LimbMap{l, L1, 0};
     InRescale ir{last, N, ql};
     OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp};

@@ -253,3 +253,41 @@ def test_kan_image_accuracy(image):
         want = kan.he_friendly_kan(x[i][None], layers)[0]
         note("max err", np.abs(y - want).max(), "level", out.level)
         assert np.abs(y - want).max() < 1e-2
+
+
+def test_batch_equals_single_tiny(tiny):
+    """Requests evaluated together in one batch give exactly the residues they
+    give alone (first [2,5,1] layer as a one-layer model)."""
+    wl, ctx, octx = tiny
+    wl, layers = tiny_model()
+    model = ctx.compile(layers[:1])
+    keys = ctx.keygen(synth.SEED_KEYGEN, model.rotation_steps())
+    xs = synth.inputs(wl, 3, stream=7)
+    cts = [ctx.encrypt(keys, xs[i], 50 + i) for i in range(3)]
+    note("tiny batch of 3")
+    outs = ctx.eval_kan_batch(model, keys, cts)
+    for i in range(3):
+        alone = ctx.eval_kan(model, keys, cts[i]).export()
+        assert (outs[i].export() == alone).all(), "request %d differs in the batch" % i
+    # the batch of one is the plain path
+    one = ctx.eval_kan_batch(model, keys, cts[:1])[0].export()
+    assert (one == ctx.eval_kan(model, keys, cts[0]).export()).all()
+
+
+@pytest.mark.timeout(900)
+def test_batch_equals_single_image(image):
+    wl, ctx, octx = image
+    raw = synth.raw_weights(wl)
+    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
+                               [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
+    model = ctx.compile(layers)
+    keys = ctx.keygen(synth.SEED_KEYGEN, model.rotation_steps())
+    xs = synth.inputs(wl, 3, stream=9)
+    cts = [ctx.encrypt(keys, xs[i], 60 + i) for i in range(3)]
+    note("image batch of 3")
+    outs = ctx.eval_kan_batch(model, keys, cts)
+    for i in range(3):
+        alone = ctx.eval_kan(model, keys, cts[i]).export()
+        assert (outs[i].export() == alone).all(), "request %d differs in the batch" % i
+        y = ctx.decrypt(keys, outs[i], 10)
+        assert np.abs(y - kan.he_friendly_kan(xs[i][None], layers)[0]).max() < 1e-2
