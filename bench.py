@@ -166,6 +166,59 @@ def cpu_baseline(wl, budget):
                       "extrapolated by key-switch work" % (elapsed, ev.count["ks"], 100 * frac)}
 
 
+SERVE_MIX = (("formula16", 0.5), ("image", 0.3), ("cifar", 0.2))
+
+
+def serve_run(args, batched_rate):
+    """Poisson arrivals of requests drawn from the serving mix, served with
+    layer-granular continuous batching under an HBM budget; arrival rate 0.7x
+    the measured batched throughput of the image model."""
+    from paper_2409_07751_amd import compile as pc
+    from paper_2409_07751_amd import hekan, synth
+    from paper_2409_07751_amd.serve import GpuEngine, Request, Server, latency_report
+
+    mix = [(n, p) for n, p in SERVE_MIX if n in synth.WORKLOADS and synth.WORKLOADS[n].shape[0] <= 1024]
+    names = [n for n, _ in mix]
+    probs = np.array([p for _, p in mix])
+    probs = probs / probs.sum()
+    wl0 = synth.WORKLOADS["image"]
+    ctx = hekan.Context(wl0.logN, wl0.L, wl0.scale_bits, wl0.alpha, wl0.w)
+    layers, models = {}, {}
+    for n in names:
+        wl = synth.WORKLOADS[n]
+        layers[n] = pc.compile_kan(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024), wl.silu_degree,
+                                   [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+        models[n] = ctx.compile(layers[n])
+    steps = sorted(set(s for m in models.values() for s in m.rotation_steps()))
+    keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    eng = GpuEngine(ctx, keys, models)
+    for n in names:
+        x = synth.inputs(synth.WORKLOADS[n], 1, stream=3)[0]
+        eng.calibrate(n, ctx.encrypt(keys, x, 7))
+    free = ctx.memory()
+    budget = 40 * 2 ** 30
+    rate = 0.7 * batched_rate
+    nreq = args.serve_requests
+    kinds = synth.request_mix(nreq, names, probs)
+    arr = synth.poisson_arrivals(rate, nreq)
+    reqs = []
+    for i, n in enumerate(kinds):
+        x = synth.inputs(synth.WORKLOADS[n], 1, stream=100 + i)[0]
+        reqs.append(Request(i, n, ctx.encrypt(keys, x, 1000 + i), float(arr[i])))
+    ctx.sync()
+    log("serving %d requests at %.1f/s, budget %.1f GiB (pool live %.1f GiB)" % (nreq, rate, budget / 2 ** 30,
+                                                                                 free["live"] / 2 ** 30))
+    done = Server(eng, budget, max_batch=args.serve_batch).run(reqs)
+    rep = latency_report(done)
+    rep.update({"arrival_rate_per_s": round(rate, 3), "mix": {n: float(p) for n, p in zip(names, probs)},
+                "hbm_budget_GiB": budget / 2 ** 30,
+                "working_MiB_per_request": {n: round(eng.work[n] / 2 ** 20, 1) for n in names}})
+    log("serving:", rep)
+    del reqs, done, keys, models, eng
+    ctx.close()
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +229,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--roofline-kernel", default="ntt_fwd_pass1")
+    ap.add_argument("--serve", action="store_true", help="also run the continuous-batching server")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -263,6 +319,8 @@ def main():
         "launches_per_step": (c1["launches"] - c0["launches"]) / args.steps,
         "roofline": roof,
     }
+    if args.serve:
+        res["serving"] = serve_run(args, res["value"])
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     del cts, keys, model

@@ -205,6 +205,16 @@ int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t 
 int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
                       he_ct **out);
 
+/* Run layer `layer` on n ciphertexts (all at the same level) in one batched
+ * pass: the building block of layer-granular continuous batching. */
+int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer,
+                            const he_ct *const *in, size_t n, he_ct **out);
+
+/* Device memory held by the context's pool: bytes in live buffers, bytes
+ * cached for reuse, and the peak of live bytes since the last reset
+ * (reset_peak != 0 resets it to the current live bytes). */
+int he_ctx_memory(he_ctx *ctx, uint64_t *live, uint64_t *cached, uint64_t *peak, int32_t reset_peak);
+
 /* ------------------------------------------------ individual homomorphic ops */
 
 /* out = a + b (same level). */

@@ -347,6 +347,36 @@ int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he
     });
 }
 
+int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer,
+                            const he_ct *const *in, size_t n, he_ct **out)
+{
+    if (!ctx || !m || !k || !out || (n && !in)) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+        if (n == 0) return;
+        need(layer >= 0 && (size_t)layer < m->m->layers.size(), "layer out of range");
+        std::vector<const Ct *> v;
+        for (size_t i = 0; i < n; i++) {
+            check_ct(ctx, in[i]);
+            v.push_back(&in[i]->c);
+        }
+        Ctx &c = *ctx->c;
+        Ct res = eval_layer(c, *m->m, *k->k, c.pack(v), (size_t)layer);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, c.unpack(res, (int)i));
+    });
+}
+
+int he_ctx_memory(he_ctx *ctx, uint64_t *live, uint64_t *cached, uint64_t *peak, int32_t reset_peak)
+{
+    if (!ctx) return HE_EINVAL;
+    Pool &p = ctx->c->pool;
+    if (live) *live = p.live;
+    if (cached) *cached = p.cached;
+    if (peak) *peak = p.peak;
+    if (reset_peak) p.peak = p.live;
+    return HE_OK;
+}
+
 int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out)
 {
     if (!ctx || !out) return HE_EINVAL;

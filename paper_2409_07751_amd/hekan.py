@@ -74,6 +74,9 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_void_p)],
     "he_eval_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                           ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
+    "he_eval_kan_layer_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ctx_memory": [ctypes.c_void_p, _u64p, _u64p, _u64p, ctypes.c_int32],
     "he_ct_add": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_mul": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.POINTER(ctypes.c_void_p)],
@@ -243,6 +246,18 @@ class Context:
 
     def eval_kan_layer(self, model, keys, layer, ct):
         return self._new(self.lib.he_eval_kan_layer, model.h, keys.h, layer, ct.h)
+
+    def eval_kan_layer_batch(self, model, keys, layer, cts):
+        n = len(cts)
+        arr = (ctypes.c_void_p * n)(*[c.h.value for c in cts])
+        outs = (ctypes.c_void_p * n)()
+        self.check(self.lib.he_eval_kan_layer_batch(self.h, model.h, keys.h, layer, arr, n, outs))
+        return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+    def memory(self, reset_peak=False):
+        v = [ctypes.c_uint64() for _ in range(3)]
+        self.check(self.lib.he_ctx_memory(self.h, *[ctypes.byref(x) for x in v], 1 if reset_peak else 0))
+        return {"live": v[0].value, "cached": v[1].value, "peak": v[2].value}
 
     def eval_kan_batch(self, model, keys, cts):
         n = len(cts)

@@ -1,0 +1,138 @@
+"""Continuous-batching server for encrypted KAN inference on one GPU.
+
+Requests (already-encrypted inputs for one of several compiled models) arrive
+over time.  The server keeps every admitted request's state on the device
+(its current ciphertext and the index of the next layer) and repeatedly runs
+one layer for a batch of requests that are at the same layer of the same
+model: new arrivals join the next layer-0 batch while earlier requests move
+on through later layers, so requests that arrive while others are on the GPU
+share launches with them.  Admission is by an HBM budget: a waiting request
+enters the active set only if the measured per-request working memory of its
+model fits next to the requests already in flight (evaluation keys and
+plaintext caches are resident and shared).
+
+The engine interface (`run_layer`, `working_bytes`) is implemented by
+`GpuEngine` over the C ABI; tests substitute a host-only engine to check the
+scheduler.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    model: str
+    ct: object               # current ciphertext (device handle)
+    arrival: float           # seconds from the start of the run
+    layer: int = 0
+    admitted: float = None
+    done: float = None
+    batches: list = field(default_factory=list)  # batch sizes this request ran in
+
+
+class GpuEngine:
+    """Runs layers through the library; one context, evaluation keys resident."""
+
+    def __init__(self, ctx, keys, models):
+        self.ctx, self.keys, self.models = ctx, keys, models  # models: name -> hekan.Model
+        self.work = {}
+
+    def n_layers(self, name):
+        return self.models[name].n_layers
+
+    def run_layer(self, name, layer, cts):
+        return self.ctx.eval_kan_layer_batch(self.models[name], self.keys, layer, cts)
+
+    def sync(self):
+        self.ctx.sync()
+
+    def calibrate(self, name, ct):
+        """Measure the peak extra device memory of one request through every
+        layer of `name` (plaintext caches warm)."""
+        self.ctx.sync()
+        base = self.ctx.memory(reset_peak=True)["live"]
+        x = ct
+        for li in range(self.n_layers(name)):
+            x = self.run_layer(name, li, [x])[0]
+        self.ctx.sync()
+        peak = self.ctx.memory()["peak"]
+        del x
+        self.work[name] = max(peak - base, 1)
+        return self.work[name]
+
+    def working_bytes(self, name):
+        return self.work[name]
+
+
+class Server:
+    def __init__(self, engine, hbm_budget, max_batch=16):
+        self.engine, self.budget, self.max_batch = engine, hbm_budget, max_batch
+        self.waiting, self.active, self.finished = [], [], []
+        self.in_use = 0
+        self.trace = []  # (time, model, layer, batch size)
+
+    def _admit(self, now):
+        # FIFO: a request blocked by the budget blocks the ones behind it
+        while self.waiting and self.waiting[0].arrival <= now:
+            r = self.waiting[0]
+            need = self.engine.working_bytes(r.model)
+            if self.active and self.in_use + need > self.budget:
+                break
+            self.waiting.pop(0)
+            r.admitted = now
+            self.in_use += need
+            self.active.append(r)
+
+    def _step(self, now_fn):
+        # the (model, layer) group of the oldest active request, batched
+        oldest = min(self.active, key=lambda r: (r.arrival, r.rid))
+        group = [r for r in self.active if r.model == oldest.model and r.layer == oldest.layer]
+        group.sort(key=lambda r: (r.arrival, r.rid))
+        batch = group[: self.max_batch]
+        outs = self.engine.run_layer(oldest.model, oldest.layer, [r.ct for r in batch])
+        self.engine.sync()
+        t = now_fn()
+        self.trace.append((t, oldest.model, oldest.layer, len(batch)))
+        for r, o in zip(batch, outs):
+            r.ct = o
+            r.layer += 1
+            r.batches.append(len(batch))
+            if r.layer == self.engine.n_layers(r.model):
+                r.done = t
+                self.active.remove(r)
+                self.in_use -= self.engine.working_bytes(r.model)
+                self.finished.append(r)
+
+    def run(self, requests, clock=None):
+        """Serve `requests` (arrival times relative to the start); returns the
+        finished requests.  `clock` returns seconds since the start (defaults
+        to the wall clock)."""
+        t0 = time.perf_counter()
+        now_fn = clock or (lambda: time.perf_counter() - t0)
+        self.waiting = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        while self.waiting or self.active:
+            now = now_fn()
+            self._admit(now)
+            if not self.active:
+                # idle until the next arrival
+                nxt = self.waiting[0].arrival
+                if clock is None:
+                    time.sleep(max(0.0, nxt - now_fn()))
+                else:
+                    clock.advance_to(nxt)
+                continue
+            self._step(now_fn)
+        return self.finished
+
+
+def latency_report(finished):
+    lat = np.array([r.done - r.arrival for r in finished])
+    span = max(r.done for r in finished) - min(r.arrival for r in finished)
+    sizes = [b for r in finished for b in r.batches]
+    return {"requests": len(finished), "inferences_per_s": round(len(finished) / span, 4),
+            "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "mean_batch": round(float(np.mean(sizes)), 2), "span_s": round(span, 3)}

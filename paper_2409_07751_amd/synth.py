@@ -55,6 +55,10 @@ WORKLOADS = {
                      ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True, False),
     "formula": Workload("formula", 15, 16, 40, 2, 2, (4, 10, 10, 1), 10, 3, (-1.0, 1.0), 27, None,
                         ((7, 7), (7, 7), (7, 7)), 0.3, 0.1, "uniform_pm1", True),
+    # the [4,10,10,1] formula-scale KAN at the image parameters (serving mix):
+    # three 8-level layers, f_3 with 1/(2R) folded (R is small on [-1, 1])
+    "formula16": Workload("formula16", 16, 24, 45, 4, 5, (4, 10, 10, 1), 10, 3, (-1.0, 1.0), 27, None,
+                          ((7,), (7,), (7,)), 0.3, 0.1, "uniform_pm1", False, False),
     "image": Workload("image", 16, 24, 45, 4, 5, (784, 64, 10), 8, 3, (0.0, 1.0), 31, None,
                       ((7, 7), (7, 7)), 0.05, 0.05, "pixels255"),
     "cifar": Workload("cifar", 16, 24, 45, 4, 5, (3072, 128, 10), 8, 3, (0.0, 1.0), 31, None,
