@@ -31,11 +31,14 @@ def log(*a):
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 LANE_SLOTS_PER_BFLY = 24.3
 NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1")
-# set by a calibrated rocprofv3 --pmc run of this command (see profiles/); None if stale
-TRAFFIC_BYTES_PER_LAUNCH = None
+# HBM bytes per launch of the default roofline kernel at the default batch,
+# from calibrated FETCH_SIZE + WRITE_SIZE counter runs of this benchmark
+# (profiles/ntt_fwd_pass1_image_b16_hbm_traffic.md); reset to None whenever
+# the kernel changes until the counters are taken again
+TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 325.05e6}
 
 
-def roofline(kernel, prof):
+def roofline(kernel, prof, batch):
     """Achieved vs peak for the dominant kernel from the live HIP-event timings."""
     if prof["launches"] == 0:
         return None
@@ -50,7 +53,7 @@ def roofline(kernel, prof):
         unit = "GB/s"
     return {"bound": "alu" if kernel in NTT_KERNELS else "hbm", "kernel": kernel, "achieved": round(achieved, 2),
             "peak": round(peak, 2), "unit": unit, "frac": round(achieved / peak, 4),
-            "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH.get(kernel) if batch == 16 else None,
             "algorithmic_bytes_per_launch": prof["bytes"] / prof["launches"],
             "achieved_algorithmic_GBps": round(prof["bytes"] / secs / 1e9, 1),
             "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 3), "launches": prof["launches"]}
@@ -166,6 +169,22 @@ def cpu_baseline(wl, budget):
                       "extrapolated by key-switch work" % (elapsed, ev.count["ks"], 100 * frac)}
 
 
+def plain_path(ctx, model, keys, ct, steps):
+    """The per-ciphertext path: one inference at a time, same kernels."""
+    ctx.eval_kan(model, keys, ct)
+    ctx.sync()
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        out = ctx.eval_kan(model, keys, ct)
+        ctx.sync()
+        lat.append(time.perf_counter() - t0)
+        del out
+    lat = np.array(lat)
+    return {"inferences_per_s": round(steps / lat.sum(), 4), "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3), "steps": steps}
+
+
 SERVE_MIX = (("formula16", 0.5), ("image", 0.3), ("cifar", 0.2))
 
 
@@ -224,12 +243,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--plain-steps", type=int, default=10,
+                    help="steps of the plain per-ciphertext path (batch 1) timed for comparison; 0 skips")
     ap.add_argument("--workload", default="image")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--roofline-kernel", default="ntt_fwd_pass1")
-    ap.add_argument("--serve", action="store_true", help="also run the continuous-batching server")
+    ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching server run")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -292,7 +313,7 @@ def main():
     c1 = ctx.counters()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
-    roof = roofline(args.roofline_kernel, prof)
+    roof = roofline(args.roofline_kernel, prof, B)
     ks_per_step = (c1["keyswitches"] - c0["keyswitches"]) / args.steps
     inf_s = B * args.steps / elapsed
     lat_ms = np.array(lat) * 1e3
@@ -319,7 +340,10 @@ def main():
         "launches_per_step": (c1["launches"] - c0["launches"]) / args.steps,
         "roofline": roof,
     }
-    if args.serve:
+    if args.plain_steps:
+        res["plain_path"] = plain_path(ctx, model, keys, cts[0], args.plain_steps)
+        res["batched_vs_plain"] = round(res["value"] / res["plain_path"]["inferences_per_s"], 3)
+    if not args.no_serve:
         res["serving"] = serve_run(args, res["value"])
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -30,7 +30,9 @@ template <int LOGN>
 struct NttGeo {
     static constexpr int LC = LOGN < 8 ? LOGN : 8;
     static constexpr int LR = LOGN - LC;
-    static constexpr int LTC = (11 - LR) < LC ? (11 - LR) : LC;
+    // pass-1 tile: 2^12 words, so a tile row spans at least 16 columns (one
+    // 128-byte line); pass-2 tile: 2^11 words of whole rows
+    static constexpr int LTC = (12 - LR) < LC ? (12 - LR) : LC;
     static constexpr int LRB = (11 - LC) < LR ? (11 - LC) : LR;
 };
 
@@ -298,9 +300,14 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
     typedef NttGeo<LOGN> G;
     constexpr int LT = PASS == 1 ? G::LR + G::LTC : G::LC + G::LRB;
     __shared__ u64 sh[1 << LT];
+    // pass 1 runs the limbs of one polynomial back to back (limb fastest), so
+    // blocks that read the same sources (basis conversion, rescale input) for
+    // the same column tile share an XCD's L2; pass 2 runs the polynomials of
+    // one limb back to back, sharing that prime's twiddle slice
     const int y = blockIdx.y;
-    const int poly = y % ps.npoly;
-    const int li = y / ps.npoly;
+    const int nll = gridDim.y / ps.npoly;
+    const int poly = PASS == 1 ? y / nll : y % ps.npoly;
+    const int li = PASS == 1 ? y % nll : y / ps.npoly;
     const int limb = li < skip_lo ? li : li + (skip_hi - skip_lo);
     if (own_w > 0) {
         const int j = poly % own_ndig;
