@@ -35,7 +35,7 @@ NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1
 # from calibrated FETCH_SIZE + WRITE_SIZE counter runs of this benchmark
 # (profiles/ntt_fwd_pass1_image_b16_hbm_traffic.md); reset to None whenever
 # the kernel changes until the counters are taken again
-TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 325.05e6}
+TRAFFIC_BYTES_PER_LAUNCH = {}
 
 
 def roofline(kernel, prof, batch):

@@ -70,7 +70,8 @@ typedef struct {
     int32_t base_bits;      /* bits of q_0 (<= 60)                                  */
     int32_t special_count;  /* alpha: number of special primes (>= 1)               */
     int32_t special_bits;   /* bits of the special primes (<= 60)                   */
-    int32_t digit_width;    /* Q limbs per hybrid key-switching digit (>= 1)        */
+    int32_t digit_width;    /* Q limbs per hybrid key-switching digit, 1..8, with   */
+                            /* ceil((levels + 1) / digit_width) <= 16 digits        */
     double sigma;           /* standard deviation of the rounded Gaussian error     */
 } he_params;
 

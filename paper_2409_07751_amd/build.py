@@ -15,7 +15,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["kernels.hip", "ntt.hip", "hostmath.cpp", "ckks.cpp", "kan.cpp", "capi.cpp"]
 
-COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
+COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-ffp-contract=off", "-I" + os.path.join(HERE, "..", "include")]
 # every HIP compilation: gfx950 only, and no packed-FP32 instructions
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -87,6 +87,7 @@ int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out)
         need(p->special_bits >= 20 && p->special_bits <= 60, "special_bits out of range");
         need(p->special_count >= 1 && p->special_count <= 8, "special_count out of range");
         need(p->digit_width >= 1 && p->digit_width <= 8, "digit_width out of range");
+        need((p->levels + p->digit_width) / p->digit_width <= 16, "more than 16 key-switch digits");
         need(p->sigma > 0 && p->sigma < 100, "sigma out of range");
         h->c = new Ctx(p->log_n, p->levels, p->scale_bits, p->base_bits, p->special_count, p->special_bits,
                        p->digit_width, p->sigma, (hipStream_t)hip_stream);

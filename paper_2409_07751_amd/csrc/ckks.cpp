@@ -150,12 +150,19 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
         c.r1p = shoup_of(c.r1, m);
         c.ninv = hinv((u64)N % m, m);
         c.ninvp = shoup_of(c.ninv, m);
+        c.fp = c.bits <= 46;
+        c.qd = (double)m;
+        c.qinvd = 1.0 / (double)m;
+        const u64 r32 = (u64)(((u128)1 << 32) % m);
+        c.r32d = (double)r32;
+        c.r32c = (double)r32 / (double)m;
     }
     d_pc_buf = alloc((sizeof(PrimeConst) * np + 7) / 8);
     HIP_CHECK(hipMemcpyAsync(d_pc_buf->p, pc.data(), sizeof(PrimeConst) * np, hipMemcpyHostToDevice, st));
     d_pc = (const PrimeConst *)d_pc_buf->p;
     // twiddles: psi^brv(k) and psi^-brv(k) with Shoup companions
     std::vector<u64> tw((size_t)4 * np * N);
+    std::vector<TwF> twf((size_t)2 * np * N);
     for (int i = 0; i < np; i++) {
         u64 m = mods[i];
         u64 psi = primitive_2n_root(m, logN), ipsi = hinv(psi, m);
@@ -175,8 +182,14 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
             fwp[k] = shoup_of(fw[k], m);
             iw[k] = ipw[r];
             iwp[k] = shoup_of(iw[k], m);
+            twf[(size_t)i * N + k] = TwF{(double)fw[k], (double)fw[k] / (double)m};
+            twf[(size_t)(np + i) * N + k] = TwF{(double)iw[k], (double)iw[k] / (double)m};
         }
     }
+    twf_buf = alloc(twf.size() * 2);
+    upload(twf_buf->p, (const u64 *)twf.data(), twf.size() * 2);
+    T.ffw = (const TwF *)twf_buf->p;
+    T.fiw = (const TwF *)twf_buf->p + (size_t)np * N;
     tw_buf = alloc(tw.size());
     upload(tw_buf->p, tw.data(), tw.size());
     T.pc = d_pc;
@@ -234,6 +247,7 @@ Ctx::~Ctx()
     int_cache.clear();
     pinv.reset();
     tw_buf.reset();
+    twf_buf.reset();
     d_pc_buf.reset();
     pool.trim();
     if (own_stream && st) (void)hipStreamDestroy(st);
@@ -390,7 +404,10 @@ const KsTable &Ctx::ks_table(int l)
     if (it != ks_cache.end()) return it->second;
     const int nq = l + 1, next = nq + alpha, nd = ndig(l);
     std::vector<u64> v(2 * (size_t)nq + (size_t)nd * w * next, 0);
+    std::vector<TwF> vf((size_t)nd * w * next, TwF{0.0, 0.0});
     LimbMap lm = lmap(nq);
+    KsTable kt;
+    kt.wide[0] = kt.wide[1] = 0;
     for (int j = 0; j < nd; j++) {
         const int lo = j * w, hi = std::min(lo + w, nq);
         for (int i = lo; i < hi; i++) {
@@ -400,16 +417,21 @@ const KsTable &Ctx::ks_table(int l)
             u64 sc = hmul(hinv(h, q[i]), hinv((u64)N % q[i], q[i]), q[i]);
             v[i] = sc;
             v[nq + i] = shoup_of(sc, q[i]);
+            if (64 - __builtin_clzll(q[i]) > 50) kt.wide[j / 8] |= 1ull << (8 * (j % 8) + (i - lo));
             for (int t = 0; t < next; t++) {
                 if (t >= lo && t < hi) continue;
                 u64 m = mods[lm.prime(t)], hm = 1;
                 for (int k = lo; k < hi; k++)
                     if (k != i) hm = hmul(hm, q[k] % m, m);
-                v[2 * (size_t)nq + ((size_t)j * w + (i - lo)) * next + t] = (u64)(((u128)hm << 64) % m);
+                const size_t o = ((size_t)j * w + (i - lo)) * next + t;
+                v[2 * (size_t)nq + o] = (u64)(((u128)hm << 64) % m);
+                if (pc[lm.prime(t)].fp) vf[o] = TwF{(double)hm, (double)hm / (double)m};
             }
         }
     }
-    KsTable kt;
+    kt.fbuf = alloc(vf.size() * 2);
+    upload(kt.fbuf->p, (const u64 *)vf.data(), vf.size() * 2);
+    kt.hatf = (const TwF *)kt.fbuf->p;
     kt.buf = alloc(v.size());
     upload(kt.buf->p, v.data(), v.size());
     kt.scale = kt.buf->p;
@@ -440,7 +462,7 @@ Ctx::ModUp Ctx::modup(const u64 *d, long ls, long es, int l, int nb)
     launch_intt_from(T, PolySet{y->p, (long)N, (long)nq * N, nq, nb}, lm, d, ls, es, 0, kt.scale, kt.scalep, st,
                      &timer);
     m.ext = alloc((size_t)nb * nd * next * N);
-    launch_modup(T, m.ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, st, &timer);
+    launch_modup(T, m.ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, kt.hatf, kt.wide, st, &timer);
     n_launch += 3;
     return m;
 }
@@ -452,9 +474,10 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
     const int l = m.l, nb = m.nb, nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
     const LimbMap lm = lmap(nq);
     Buf acc = alloc((size_t)nb * 2 * next * N);
-    launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, m.ext->p, (long)next * N, (long)nd * next * N, m.d,
-                 m.ls, m.es, key.buf->p, 2l * ktot * N, (long)ktot * N, nd, next, nq, w, nb, lm, L1, logN, st,
-                 &timer);
+    if (launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, m.ext->p, (long)next * N, (long)nd * next * N,
+                     m.d, m.ls, m.es, key.buf->p, 2l * ktot * N, (long)ktot * N, nd, next, nq, w, nb, lm, L1, logN,
+                     st, &timer) != 0)
+        throw HeError(-1, "key switch: " + std::to_string(nd) + " digits (at most 16 supported)");
     // ModDown of the 2 nb accumulator polynomials
     Buf yP = alloc((size_t)nb * 2 * alpha * N);
     launch_intt_from(T, PolySet{yP->p, (long)N, (long)alpha * N, alpha, 2 * nb}, LimbMap{0, L1},

@@ -88,8 +88,10 @@ struct Keys {
 // the limb's digit times N^-1, Shoup pair) then [ndig][w][nq+alpha] ModUp
 // conversion constants (Montgomery form)
 struct KsTable {
-    Buf buf;
+    Buf buf, fbuf;
     const u64 *scale, *scalep, *hatm;
+    const TwF *hatf;  // hatm in standard form as FP64 pairs (entries for FP64 targets)
+    u64 wide[2];      // bit 8 j + k: source k of digit j is a prime above 2^50
 };
 
 struct Ctx {
@@ -101,7 +103,7 @@ struct Ctx {
     hipStream_t st = nullptr;
     bool own_stream = false;
     Pool pool;
-    Buf d_pc_buf, tw_buf;
+    Buf d_pc_buf, tw_buf, twf_buf;
     const PrimeConst *d_pc = nullptr;
     NttTables T;
     std::map<int, KsTable> ks_cache;

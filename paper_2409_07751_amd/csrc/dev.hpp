@@ -17,7 +17,14 @@ struct PrimeConst {
     u64 r1, r1p;   // 2^64 mod q and its Shoup companion
     u64 ninv, ninvp;
     int bits;      // b = bit length of q
-    int pad;
+    int fp;        // 1: the transforms of this prime run in exact FP64 arithmetic (q < 2^46)
+    double qd, qinvd;  // q and 1/q as doubles
+    double r32d, r32c; // 2^32 mod q and (2^32 mod q) / q as doubles (FP64 primes)
+};
+
+// FP64 twiddle: w and w/q (w < q < 2^46 is exact in a double)
+struct alignas(16) TwF {
+    double w, c;
 };
 
 // Which prime each limb of a polynomial uses: limbs [0, nq) take q_0..q_{nq-1},
@@ -43,6 +50,7 @@ struct NttTables {
     const PrimeConst *pc;  // [nprimes]
     const u64 *fw, *fwp;   // psi^brv(k) and Shoup companions, [nprimes][N]
     const u64 *iw, *iwp;   // psi^-brv(k)
+    const TwF *ffw, *fiw;  // the same twiddles as FP64 pairs, [nprimes][N]
     int logN;
 };
 
@@ -90,10 +98,11 @@ void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s);
 // Montgomery form): acc_c[t] = sum_j e_j[t] * key_j[c][kt(t)], c = 0, 1, where
 // e_j[t] is the input d itself on digit j's own limbs and ext_j[t] elsewhere.
 // Galois keys are stored permuted by sigma^-1, so no permutation happens here.
-void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
-                  long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
-                  long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
-                  int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
+// Returns -1 (nothing launched) unless 1 <= ndig <= 16.
+int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
+                 long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
+                 long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
+                 int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
 
 // --- fused transforms (ntt.hip)
 // inverse transform of src (through sigma_galois if galois > 1) into `work`;
@@ -102,9 +111,13 @@ void launch_intt_from(const NttTables &t, PolySet work, LimbMap lm, const u64 *s
                       u64 galois, const u64 *scale, const u64 *scalep, hipStream_t s, KernelTimer *tm = nullptr);
 // ModUp of every digit of nb ciphertexts at once: ext [nb][ndig][nq+alpha][N] <-
 // NTT(BConv(y_digit)) on every limb outside the digit; y [nb][nq][N];
-// hatm [ndig][w][nq+alpha] Montgomery form
+// hatm [ndig][w][nq+alpha] Montgomery form; hatf the same constants in
+// standard form as FP64 pairs (used for targets on FP64 primes); bit
+// 8 j + k of wide (j < 8: wide[0], else wide[1]) marks source k of digit j as
+// a prime of more than 50 bits
 void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
-                  const u64 *y, const u64 *hatm, hipStream_t s, KernelTimer *tm = nullptr);
+                  const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], hipStream_t s,
+                  KernelTimer *tm = nullptr);
 struct OutModdownArgs {
     const u64 *acc;
     long acc_ls, acc_ps;

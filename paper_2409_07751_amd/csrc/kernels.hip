@@ -189,45 +189,74 @@ void launch_pmul(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMa
 }
 
 // ---------------------------------------------------- key-switch inner product
-__global__ void k_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
-                        long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
-                        long key_dstride, long key_cstride, int ndig, int nq, int w, LimbMap lm, int key_nq_off,
-                        int logN)
+// One thread per (coefficient, limb): the 2 ndig key words of that coefficient
+// are loaded once into registers and reused for every batch element, so the
+// key is read from HBM once per launch whatever the batch size.  MAXD bounds
+// ndig; with ndig <= 16 and q < 2^60 the 128-bit sums stay below q 2^64, as
+// Montgomery reduction requires.
+template <int MAXD>
+__global__ void __launch_bounds__(256) k_keyip(const PrimeConst *pc, u64 *__restrict__ acc, long acc_pstride,
+                                               long acc_bstride, const u64 *__restrict__ ext, long ext_dstride,
+                                               long ext_bstride, const u64 *__restrict__ d, long d_ls,
+                                               long d_bstride, const u64 *__restrict__ key, long key_dstride,
+                                               long key_cstride, int ndig, int nq, int w, int nb, LimbMap lm,
+                                               int key_nq_off, int logN)
 {
-    const int t = blockIdx.y, b = blockIdx.z;
+    const int t = blockIdx.y;
     const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long N = 1l << logN;
     if (n >= N) return;
     const PrimeConst &c = pc[lm.prime(t)];
     const int kt = t < lm.nq ? t : key_nq_off + (t - lm.nq);
-    const u64 *eb = ext + b * ext_bstride, *db = d + b * d_bstride;
-    u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
-    for (int j = 0; j < ndig; j++) {
-        const bool own = t >= j * w && t < min(j * w + w, nq);
-        const u64 e = own ? db[t * d_ls + n] : eb[j * ext_dstride + t * N + n];
-        const u64 *kp = key + j * key_dstride + kt * N + n;
-        mac(lo0, hi0, e, kp[0]);
-        mac(lo1, hi1, e, kp[key_cstride]);
+    u64 k0[MAXD], k1[MAXD];
+#pragma unroll
+    for (int j = 0; j < MAXD; j++) {
+        if (j < ndig) {
+            const u64 *kp = key + j * key_dstride + kt * N + n;
+            k0[j] = kp[0];
+            k1[j] = kp[key_cstride];
+        }
     }
-    u64 *ab = acc + b * acc_bstride;
-    ab[t * N + n] = redc(lo0, hi0, c);
-    ab[acc_pstride + t * N + n] = redc(lo1, hi1, c);
+    // the digit whose own limbs include t reads the input polynomial itself
+    const int jown = t < nq ? t / w : -1;
+#pragma unroll 2
+    for (int b = 0; b < nb; b++) {
+        const u64 *eb = ext + b * ext_bstride + t * N + n;
+        u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+#pragma unroll
+        for (int j = 0; j < MAXD; j++) {
+            if (j < ndig) {
+                const u64 e = j == jown ? d[b * d_bstride + t * d_ls + n] : eb[j * ext_dstride];
+                mac(lo0, hi0, e, k0[j]);
+                mac(lo1, hi1, e, k1[j]);
+            }
+        }
+        u64 *ab = acc + b * acc_bstride + t * N + n;
+        ab[0] = redc(lo0, hi0, c);
+        ab[acc_pstride] = redc(lo1, hi1, c);
+    }
 }
 
-void launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
-                  long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
-                  long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
-                  int key_nq_off, int logN, hipStream_t s, KernelTimer *tm)
+int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
+                 long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
+                 long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
+                 int key_nq_off, int logN, hipStream_t s, KernelTimer *tm)
 {
+    if (ndig < 1 || ndig > 16) return -1;
     const int N = 1 << logN;
-    dim3 g((N + 255) / 256, nl, nb);
+    dim3 g((N + 255) / 256, nl);
     bool on = tm && tm->on(KID_KEYIP);
     if (on) tm->before(s);
-    hipLaunchKernelGGL(k_keyip, g, dim3(256), 0, s, pc, acc, acc_pstride, acc_bstride, ext, ext_dstride,
-                       ext_bstride, d, d_ls, d_bstride, key, key_dstride, key_cstride, ndig, nq, w, lm, key_nq_off,
-                       logN);
+#define KEYIP_ARGS                                                                                              \
+    pc, acc, acc_pstride, acc_bstride, ext, ext_dstride, ext_bstride, d, d_ls, d_bstride, key, key_dstride,     \
+        key_cstride, ndig, nq, w, nb, lm, key_nq_off, logN
+    if (ndig <= 4) hipLaunchKernelGGL(k_keyip<4>, g, dim3(256), 0, s, KEYIP_ARGS);
+    else if (ndig <= 8) hipLaunchKernelGGL(k_keyip<8>, g, dim3(256), 0, s, KEYIP_ARGS);
+    else hipLaunchKernelGGL(k_keyip<16>, g, dim3(256), 0, s, KEYIP_ARGS);
+#undef KEYIP_ARGS
     // reads nb ndig extended digits and 2 ndig key polynomials, writes 2 nb outputs
     if (on) tm->after(s, 8.0 * N * nl * (nb * ndig + 2.0 * ndig + 2.0 * nb), 2.0 * N * nl * ndig * nb);
+    return 0;
 }
 
 // -------------------------------------------------------- keys and client ops

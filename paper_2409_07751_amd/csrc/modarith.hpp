@@ -65,4 +65,36 @@ __device__ __forceinline__ u32 auto_src(u32 j, u64 g, int logN)
 
 __device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - __umul64hi(a, wp) * q; }
 
+// ------------------------------------------------- exact FP64 residue arithmetic
+// For q < 2^46 a residue, and every intermediate below, is an integer held
+// exactly in a double; FP64 FMA runs at the full vector rate while 64-bit
+// integer multiplies take several instructions.  Values are kept in a signed
+// ("balanced") range and reduced only when they leave the transform.
+
+// u64 below 2^52 -> the same integer as a double
+__device__ __forceinline__ double u2d(u64 v)
+{
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+
+// integer-valued double with |v| < 2^52 -> v mod q in [0, q)
+__device__ __forceinline__ u64 d2u_mod(double v, double q, double qi)
+{
+    double r = __fma_rn(-rint(v * qi), q, v);  // exact, |r| <= q/2 + 1
+    r = r < 0.0 ? r + q : r;
+    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0xFFFFFFFFFFFFFull;
+}
+
+// y w mod q up to sign, |result| <= 3q/4, for |y| <= 2^50, 0 <= w < q < 2^46,
+// c = fl(w / q): the quotient estimate t = rint(y c) is within 3/4 of y w / q,
+// p + e = y w exactly (e = the rounding error of p, exact by FMA), and
+// p - t q is an integer below 2^47 in magnitude, so the FMA is exact too
+__device__ __forceinline__ double mulm_fp(double y, double w, double c, double q)
+{
+    const double t = rint(y * c);
+    const double p = y * w;
+    const double e = __fma_rn(y, w, -p);
+    return __fma_rn(-t, q, p) + e;
+}
+
 }  // namespace hk

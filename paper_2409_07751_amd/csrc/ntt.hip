@@ -22,6 +22,8 @@
 //   * inverse transforms read their input from another buffer (optionally
 //     through a Galois permutation) and fold a per-limb constant into N^-1.
 #include "dev.hpp"
+#include <type_traits>
+
 #include "modarith.hpp"
 
 namespace hk {
@@ -98,16 +100,88 @@ struct InBconv {
     int ndig;
     int ns_fixed;       // > 0: every polynomial has ns_fixed sources
     int w, nq;          // else digit j has min(w, nq - j w) sources
+    const TwF *hatf;    // non-null: FP64 pairs (hat, hat / q_t), same indexing, for FP64 targets
+    u64 wide[2];        // bit 8 j + k: source k of digit j is a prime above 2^50
+    __device__ int nsrc(int j) const { return ns_fixed > 0 ? ns_fixed : min(w, nq - j * w); }
     __device__ u64 load(const Blk &b, long g) const
     {
         const int e = b.poly / ndig, j = b.poly - e * ndig;
-        const int ns = ns_fixed > 0 ? ns_fixed : min(w, nq - j * w);
+        const int ns = nsrc(j);
         const long N = 1l << b.logN;
         const u64 *s = src + e * src_bs + j * src_ps + g;
         const u64 *h = hatm + j * hat_ps + b.limb;
         u64 lo = 0, hi = 0;
         for (int k = 0; k < ns; k++) mac(lo, hi, s[k * N], h[k * hat_ks]);
         return redc(lo, hi, *b.pc);
+    }
+    // M positions at once, sources outermost: M independent loads in flight
+    // per source instead of one dependent chain per position
+    template <int M>
+    __device__ void load_many(const Blk &b, const long *g, u64 *x) const
+    {
+        const int e = b.poly / ndig, j = b.poly - e * ndig;
+        const int ns = nsrc(j);
+        const long N = 1l << b.logN;
+        const u64 *s = src + e * src_bs + j * src_ps;
+        const u64 *h = hatm + j * hat_ps + b.limb;
+        u64 lo[M], hi[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) lo[m] = hi[m] = 0;
+#pragma unroll 2
+        for (int k = 0; k < ns; k++) {
+            const u64 hk = h[k * hat_ks];
+            u64 y[M];
+#pragma unroll
+            for (int m = 0; m < M; m++) y[m] = s[k * N + g[m]];
+#pragma unroll
+            for (int m = 0; m < M; m++) mac(lo[m], hi[m], y[m], hk);
+        }
+#pragma unroll
+        for (int m = 0; m < M; m++) x[m] = redc(lo[m], hi[m], *b.pc);
+    }
+    // the same sums for a target on an FP64 prime, reduced to |x| <= q/2 + 1:
+    // each term is one exact FP64 modular product; a source word above 2^50
+    // is first folded to (y >> 32)(2^32 mod q) + (y mod 2^32)
+    template <int M>
+    __device__ void load_many_d(const Blk &b, const long *g, double *x) const
+    {
+        if (!hatf) {
+            u64 v[M];
+            load_many<M>(b, g, v);
+#pragma unroll
+            for (int m = 0; m < M; m++) x[m] = u2d(v[m]);
+            return;
+        }
+        const int e = b.poly / ndig, j = b.poly - e * ndig;
+        const int ns = nsrc(j);
+        const long N = 1l << b.logN;
+        const u64 *s = src + e * src_bs + j * src_ps;
+        const TwF *h = hatf + j * hat_ps + b.limb;
+        const double q = b.pc->qd;
+        const u64 wj = (j < 8 ? wide[0] >> (8 * j) : wide[1] >> (8 * (j - 8))) & 0xff;
+        double acc[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) acc[m] = 0.0;
+#pragma unroll 2
+        for (int k = 0; k < ns; k++) {
+            const TwF t = h[k * hat_ks];
+            u64 y[M];
+#pragma unroll
+            for (int m = 0; m < M; m++) y[m] = s[k * N + g[m]];
+            if (wj >> k & 1) {
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    const double yd = mulm_fp(u2d(y[m] >> 32), b.pc->r32d, b.pc->r32c, q) + u2d(y[m] & 0xffffffffull);
+                    acc[m] += mulm_fp(yd, t.w, t.c, q);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; m++) acc[m] += mulm_fp(u2d(y[m]), t.w, t.c, q);
+            }
+        }
+        const double qi = b.pc->qinvd;
+#pragma unroll
+        for (int m = 0; m < M; m++) x[m] = __fma_rn(-rint(acc[m] * qi), q, acc[m]);
     }
 };
 
@@ -125,10 +199,15 @@ struct InRescale {
     }
 };
 
+// Output policies.  NPRE > 0: the policy reads NPRE further words per output
+// position; the kernel loads them with fetch() before the first phase, so
+// they are in flight during the butterflies, and hands them to store().
 enum { OW_LAZY = 0, OW_REDUCE = 1, OW_SCALE_N = 2 };
 template <int MODE>
 struct OutWork {
-    __device__ void store(const Blk &b, long g, u64 v) const
+    static constexpr int NPRE = 0;
+    __device__ void fetch(const Blk &, long, u64 *) const {}
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *) const
     {
         const u64 q = b.pc->q;
         if (MODE == OW_REDUCE) v = reduce4(v, q);
@@ -143,7 +222,9 @@ struct OutWork {
 // inverse transform, last store: multiply by a per-limb constant (N^-1 folded in)
 struct OutScaleTab {
     const u64 *s, *sp;
-    __device__ void store(const Blk &b, long g, u64 v) const
+    static constexpr int NPRE = 0;
+    __device__ void fetch(const Blk &, long, u64 *) const {}
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *) const
     {
         const u64 q = b.pc->q;
         v = shoup_lazy(v, s[b.limb], sp[b.limb], q);
@@ -158,12 +239,13 @@ struct OutRescaleFin {
     u64 *out;
     long ols, ops;
     const u64 *inv, *invp;
-    __device__ void store(const Blk &b, long g, u64 v) const
+    static constexpr int NPRE = 1;
+    __device__ void fetch(const Blk &b, long g, u64 *pre) const { pre[0] = in[b.limb * ls + b.poly * ps + g]; }
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
     {
         const u64 q = b.pc->q;
         v = reduce4(v, q);
-        u64 x = in[b.limb * ls + b.poly * ps + g];
-        out[b.limb * ols + b.poly * ops + g] = shoup(subm(x, v, q), inv[b.limb], invp[b.limb], q);
+        out[b.limb * ols + b.poly * ops + g] = shoup(subm(pre[0], v, q), inv[b.limb], invp[b.limb], q);
     }
 };
 
@@ -179,40 +261,73 @@ struct OutModdownFin {
     u64 *out;
     long ols, ops;
     const u64 *pinv, *pinvp;
-    __device__ void store(const Blk &b, long g, u64 v) const
+    static constexpr int NPRE = 2;
+    __device__ void fetch(const Blk &b, long g, u64 *pre) const
+    {
+        const long gp = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
+        pre[0] = acc[b.limb * acc_ls + b.poly * acc_ps + gp];
+        const int e = b.poly >> 1, c = b.poly & 1;
+        pre[1] = (mask >> c & 1) ? base[b.limb * bls + e * bes + c * bcs + (c == 0 ? gp : g)] : 0;
+    }
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
     {
         const u64 q = b.pc->q;
         v = reduce4(v, q);
-        const long gp = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
-        u64 a = acc[b.limb * acc_ls + b.poly * acc_ps + gp];
-        u64 r = shoup(subm(a, v, q), pinv[b.limb], pinvp[b.limb], q);
-        const int e = b.poly >> 1, c = b.poly & 1;
-        if (mask >> c & 1) r = addm(r, base[b.limb * bls + e * bes + c * bcs + (c == 0 ? gp : g)], q);
+        u64 r = shoup(subm(pre[0], v, q), pinv[b.limb], pinvp[b.limb], q);
+        if (mask >> (b.poly & 1) & 1) r = addm(r, pre[1], q);
         out[b.limb * ols + b.poly * ops + g] = r;
     }
 };
 
+// between the two passes of one transform: lazy u64 words, or the raw
+// balanced doubles of the FP64 path (the next pass of the same prime reads them)
+struct InMid {
+    __device__ u64 load(const Blk &b, long g) const { return b.a[g]; }
+    __device__ double load_d(const Blk &b, long g) const { return __longlong_as_double((long long)b.a[g]); }
+};
+struct OutMid {
+    static constexpr int NPRE = 0;
+    __device__ void fetch(const Blk &, long, u64 *) const {}
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *) const { b.a[g] = v; }
+    __device__ void store_d(const Blk &b, long g, double v) const { b.a[g] = (u64)__double_as_longlong(v); }
+};
+
+template <class IN>
+__device__ __forceinline__ double load_fp(const IN &in, const Blk &b, long g)
+{
+    if constexpr (std::is_same<IN, InMid>::value) return in.load_d(b, g);
+    else return u2d(in.load(b, g));  // every other input policy yields words below 4q
+}
+
+template <class OUT>
+__device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, double v, const u64 *pre)
+{
+    if constexpr (std::is_same<OUT, OutMid>::value) out.store_d(b, g, v);
+    else out.store(b, g, d2u_mod(v, b.pc->qd, b.pc->qinvd), pre);
+}
+
 // ----------------------------------------------------------------- phases
 // One phase of R stages (min distance 2^LS positions) over a tile of
 // 2^LP positions x 2^LL lines.  PASS 1: positions are rows, lines columns;
-// PASS 2: positions are words of a row, lines rows.
-template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT>
-__device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
-                                          const IN &in, const OUT &out)
-{
+// PASS 2: positions are words of a row, lines rows.  Unit u of the phase owns
+// the 2^R positions p0 + k 2^LS of one line.
+template <int LOGN, int PASS, int R, int LS>
+struct PhaseIdx {
     typedef NttGeo<LOGN> G;
-    constexpr int LP = PASS == 1 ? G::LR : G::LC;
-    constexpr int LL = PASS == 1 ? G::LTC : G::LRB;
-    constexpr int LU = LP - R + LL;
-    constexpr int LHI = LP - LS - R;
-    constexpr int LG = PASS == 1 ? LS + G::LC : LS;
-    const u64 q = bk.pc->q, q2 = 2 * q;
-    const long N = 1l << LOGN;
-#pragma unroll
-    for (int it = 0; it < ((1 << LU) + 255) / 256; it++) {
+    static constexpr int LP = PASS == 1 ? G::LR : G::LC;
+    static constexpr int LL = PASS == 1 ? G::LTC : G::LRB;
+    static constexpr int LU = LP - R + LL;
+    static constexpr int LHI = LP - LS - R;
+    static constexpr int LG = PASS == 1 ? LS + G::LC : LS;  // log2 of the word distance 2^LS positions span
+    static constexpr int ITERS = ((1 << LU) + 255) / 256;
+    int p0, line;
+    long blk;
+    // false if unit it * 256 + threadIdx.x does not exist
+    __device__ __forceinline__ bool set(int it, long b)
+    {
         const int u = it * 256 + (int)threadIdx.x;
-        if ((1 << LU) % 256 != 0 && u >= (1 << LU)) break;
-        int lo, hi, line;
+        if ((1 << LU) % 256 != 0 && u >= (1 << LU)) return false;
+        int lo, hi;
         if (PASS == 1) {
             line = u & ((1 << LL) - 1);
             const int v = u >> LL;
@@ -224,44 +339,144 @@ __device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, cons
             hi = v & ((1 << LHI) - 1);
             line = v >> LHI;
         }
-        const int p0 = (hi << (LS + R)) | lo;
-        auto gidx = [&](int p) -> long {
-            return PASS == 1 ? ((long)p << G::LC) + (blk << G::LTC) + line
-                             : (((blk << G::LRB) + line) << G::LC) + p;
-        };
-        auto lidx = [&](int p) -> int { return PASS == 1 ? (p << LL) + line : (line << LP) + p; };
-        u64 x[1 << R];
+        p0 = (hi << (LS + R)) | lo;
+        blk = b;
+        return true;
+    }
+    __device__ __forceinline__ long gidx(int k) const
+    {
+        const int p = p0 + (k << LS);
+        return PASS == 1 ? ((long)p << G::LC) + (blk << G::LTC) + line : (((blk << G::LRB) + line) << G::LC) + p;
+    }
+    __device__ __forceinline__ int lidx(int k) const
+    {
+        const int p = p0 + (k << LS);
+        return PASS == 1 ? (p << LL) + line : (line << LP) + p;
+    }
+    // the twiddle of the stage-h pair (k, k + 2^h) is entry
+    // (N + gidx(k)) >> (LG + h + 1); bits [LG, LG + R) of gidx(0) are clear,
+    // so that is tw0(h) + (k >> (h + 1))
+    __device__ __forceinline__ long tw0(int h) const { return ((1l << LOGN) + gidx(0)) >> (LG + h + 1); }
+};
+
+// NPRE words per position of the last phase, loaded before the first phase
+template <int NPRE, int N>
+struct PreBuf {
+    u64 v[N][NPRE];
+};
+template <int N>
+struct PreBuf<0, N> {
+    u64 v[1][1];
+};
+
+template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT, class PB>
+__device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
+                                          const IN &in, const OUT &out, const PB &pre)
+{
+    typedef PhaseIdx<LOGN, PASS, R, LS> I;
+    const u64 q = bk.pc->q, q2 = 2 * q;
 #pragma unroll
-        for (int k = 0; k < (1 << R); k++) {
-            const int p = p0 + (k << LS);
-            x[k] = FIRST ? in.load(bk, gidx(p)) : sh[lidx(p)];
+    for (int it = 0; it < I::ITERS; it++) {
+        I ix;
+        if (!ix.set(it, blk)) break;
+        u64 x[1 << R];
+        if constexpr (FIRST && std::is_same<IN, InBconv>::value) {
+            long g[1 << R];
+#pragma unroll
+            for (int k = 0; k < (1 << R); k++) g[k] = ix.gidx(k);
+            in.template load_many<(1 << R)>(bk, g, x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < (1 << R); k++) x[k] = FIRST ? in.load(bk, ix.gidx(k)) : sh[ix.lidx(k)];
         }
         if (FWD) {
 #pragma unroll
             for (int h = R - 1; h >= 0; h--) {
+                const long ib = ix.tw0(h);
 #pragma unroll
                 for (int k = 0; k < (1 << R); k++) {
                     if (k & (1 << h)) continue;
-                    const long idx = (N + gidx(p0 + (k << LS))) >> (LG + h + 1);
+                    const long idx = ib + (k >> (h + 1));
                     ct_bfly(x[k], x[k + (1 << h)], w[idx], wp[idx], q, q2);
                 }
             }
         } else {
 #pragma unroll
             for (int h = 0; h < R; h++) {
+                const long ib = ix.tw0(h);
 #pragma unroll
                 for (int k = 0; k < (1 << R); k++) {
                     if (k & (1 << h)) continue;
-                    const long idx = (N + gidx(p0 + (k << LS))) >> (LG + h + 1);
+                    const long idx = ib + (k >> (h + 1));
                     gs_bfly(x[k], x[k + (1 << h)], w[idx], wp[idx], q, q2);
                 }
             }
         }
 #pragma unroll
         for (int k = 0; k < (1 << R); k++) {
-            const int p = p0 + (k << LS);
-            if (LAST) out.store(bk, gidx(p), x[k]);
-            else sh[lidx(p)] = x[k];
+            if (LAST) out.store(bk, ix.gidx(k), x[k], pre.v[LAST ? (it << R) + k : 0]);
+            else sh[ix.lidx(k)] = x[k];
+        }
+    }
+}
+
+// The same phase on the FP64 path (primes below 2^46).  Forward: no reduction
+// inside the transform; starting below 4q, sixteen stages that each add at
+// most 3q/4 keep every value within 16q <= 2^50.  Inverse: the sum of each
+// butterfly is reduced to |s| <= q/2 + 1, the difference stays within 8q.
+template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT, class PB>
+__device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const IN &in,
+                                             const OUT &out, const PB &pre)
+{
+    typedef PhaseIdx<LOGN, PASS, R, LS> I;
+    const double q = bk.pc->qd, qi = bk.pc->qinvd;
+#pragma unroll
+    for (int it = 0; it < I::ITERS; it++) {
+        I ix;
+        if (!ix.set(it, blk)) break;
+        double x[1 << R];
+        if constexpr (FIRST && std::is_same<IN, InBconv>::value) {
+            long g[1 << R];
+#pragma unroll
+            for (int k = 0; k < (1 << R); k++) g[k] = ix.gidx(k);
+            in.template load_many_d<(1 << R)>(bk, g, x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < (1 << R); k++) x[k] = FIRST ? load_fp(in, bk, ix.gidx(k)) : sh[ix.lidx(k)];
+        }
+        if (FWD) {
+#pragma unroll
+            for (int h = R - 1; h >= 0; h--) {
+                const long ib = ix.tw0(h);
+#pragma unroll
+                for (int k = 0; k < (1 << R); k++) {
+                    if (k & (1 << h)) continue;
+                    const TwF t = tw[ib + (k >> (h + 1))];
+                    const double r = mulm_fp(x[k + (1 << h)], t.w, t.c, q);
+                    const double a = x[k];
+                    x[k] = a + r;
+                    x[k + (1 << h)] = a - r;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < R; h++) {
+                const long ib = ix.tw0(h);
+#pragma unroll
+                for (int k = 0; k < (1 << R); k++) {
+                    if (k & (1 << h)) continue;
+                    const TwF t = tw[ib + (k >> (h + 1))];
+                    const double a = x[k], b = x[k + (1 << h)];
+                    const double sm = a + b;
+                    x[k] = __fma_rn(-rint(sm * qi), q, sm);
+                    x[k + (1 << h)] = mulm_fp(a - b, t.w, t.c, q);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < (1 << R); k++) {
+            if (LAST) store_fp(out, bk, ix.gidx(k), x[k], pre.v[LAST ? (it << R) + k : 0]);
+            else sh[ix.lidx(k)] = x[k];
         }
     }
 }
@@ -276,18 +491,41 @@ struct PhasePlan {
     static constexpr int LS = FWD ? LP - BEFORE - R : BEFORE;
 };
 
-template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT>
+template <int LOGN, int PASS, bool FWD>
+struct LastPhase {
+    static constexpr int LP = PASS == 1 ? NttGeo<LOGN>::LR : NttGeo<LOGN>::LC;
+    typedef PhasePlan<LP, FWD, PhasePlan<LP, FWD, 0>::NPH - 1> P;
+    typedef PhaseIdx<LOGN, PASS, P::R, P::LS> I;
+    static constexpr int NPOS = I::ITERS << P::R;
+};
+
+template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
-                                           const IN &in, const OUT &out)
+                                           const IN &in, const OUT &out, const PB &pre)
 {
     typedef NttGeo<LOGN> G;
     constexpr int LP = PASS == 1 ? G::LR : G::LC;
     typedef PhasePlan<LP, FWD, PH> P;
     constexpr bool first = PH == 0, last = PH == P::NPH - 1;
-    ntt_phase<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, w, wp, in, out);
+    ntt_phase<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, w, wp, in, out, pre);
     if constexpr (!last) {
         __syncthreads();
-        ntt_phases<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, w, wp, in, out);
+        ntt_phases<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, w, wp, in, out, pre);
+    }
+}
+
+template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT, class PB>
+__device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const IN &in,
+                                              const OUT &out, const PB &pre)
+{
+    typedef NttGeo<LOGN> G;
+    constexpr int LP = PASS == 1 ? G::LR : G::LC;
+    typedef PhasePlan<LP, FWD, PH> P;
+    constexpr bool first = PH == 0, last = PH == P::NPH - 1;
+    ntt_phase_fp<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, tw, in, out, pre);
+    if constexpr (!last) {
+        __syncthreads();
+        ntt_phases_fp<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, tw, in, out, pre);
     }
 }
 
@@ -320,9 +558,26 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
     bk.poly = poly;
     bk.pc = T.pc + pi;
     bk.logN = LOGN;
+    typedef LastPhase<LOGN, PASS, FWD> LPh;
+    PreBuf<OUT::NPRE, LPh::NPOS> pre;
+    if constexpr (OUT::NPRE > 0) {
+#pragma unroll
+        for (int it = 0; it < LPh::I::ITERS; it++) {
+            typename LPh::I ix;
+            if (!ix.set(it, (long)blockIdx.x)) break;
+#pragma unroll
+            for (int k = 0; k < (1 << LPh::P::R); k++) out.fetch(bk, ix.gidx(k), pre.v[(it << LPh::P::R) + k]);
+        }
+    }
+    if (bk.pc->fp) {
+        const TwF *tw = (FWD ? T.ffw : T.fiw) + ((long)pi << LOGN);
+        ntt_phases_fp<LOGN, PASS, FWD, 0, IN, OUT>(reinterpret_cast<double *>(sh), bk, (long)blockIdx.x, tw, in, out,
+                                                   pre);
+        return;
+    }
     const u64 *w = (FWD ? T.fw : T.iw) + ((long)pi << LOGN);
     const u64 *wp = (FWD ? T.fwp : T.iwp) + ((long)pi << LOGN);
-    ntt_phases<LOGN, PASS, FWD, 0, IN, OUT>(sh, bk, (long)blockIdx.x, w, wp, in, out);
+    ntt_phases<LOGN, PASS, FWD, 0, IN, OUT>(sh, bk, (long)blockIdx.x, w, wp, in, out, pre);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -342,13 +597,13 @@ static void fwd_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &
     if constexpr (G::LR > 0) {
         bool on = tm && tm->on(KID_NTT_FWD1);
         if (on) tm->before(s);
-        hipLaunchKernelGGL((k_ntt<LOGN, 1, true, IN, OutWork<OW_LAZY>>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo,
-                           j.skip_hi, j.own_w, j.own_nq, j.own_ndig, in, OutWork<OW_LAZY>());
+        hipLaunchKernelGGL((k_ntt<LOGN, 1, true, IN, OutMid>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, j.own_ndig, in, OutMid());
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
         on = tm && tm->on(KID_NTT_FWD2);
         if (on) tm->before(s);
-        hipLaunchKernelGGL((k_ntt<LOGN, 2, true, InWork, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
-                           j.own_w, j.own_nq, j.own_ndig, InWork(), out);
+        hipLaunchKernelGGL((k_ntt<LOGN, 2, true, InMid, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, j.own_ndig, InMid(), out);
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
     } else {
         (void)g1;
@@ -368,13 +623,13 @@ static void inv_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &
     if constexpr (G::LR > 0) {
         bool on = tm && tm->on(KID_NTT_INV2);
         if (on) tm->before(s);
-        hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OutWork<OW_LAZY>>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo,
-                           j.skip_hi, j.own_w, j.own_nq, j.own_ndig, in, OutWork<OW_LAZY>());
+        hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OutMid>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, j.own_ndig, in, OutMid());
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
         on = tm && tm->on(KID_NTT_INV1);
         if (on) tm->before(s);
-        hipLaunchKernelGGL((k_ntt<LOGN, 1, false, InWork, OUT>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
-                           j.own_w, j.own_nq, j.own_ndig, InWork(), out);
+        hipLaunchKernelGGL((k_ntt<LOGN, 1, false, InMid, OUT>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
+                           j.own_w, j.own_nq, j.own_ndig, InMid(), out);
         if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
     } else {
         (void)g1;
@@ -446,7 +701,8 @@ static void modup_n(const NttTables &t, const NttJob &j, const InBconv &in, hipS
 }
 
 void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
-                  const u64 *y, const u64 *hatm, hipStream_t s, KernelTimer *tm)
+                  const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], hipStream_t s,
+                  KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     const int next = nq + alpha;
@@ -467,6 +723,9 @@ void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int
     in.ns_fixed = 0;
     in.w = w;
     in.nq = nq;
+    in.hatf = hatf;
+    in.wide[0] = wide[0];
+    in.wide[1] = wide[1];
     NTT_DISPATCH(modup_n, t, j, in, s, tm);
 }
 
@@ -497,6 +756,9 @@ void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, 
     in.ns_fixed = alpha;
     in.w = 0;
     in.nq = nq;
+    // every source is a special prime: the integer conversion is as cheap here
+    in.hatf = nullptr;
+    in.wide[0] = in.wide[1] = 0;
     OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.mask, a.galois, a.out, a.ols, a.ops,
                     a.pinv, a.pinvp};
     NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
