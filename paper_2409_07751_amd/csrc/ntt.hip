@@ -5,11 +5,16 @@
 // (bit-reversed psi powers): natural-order input, bit-reversed output; the
 // inverse is Gentleman-Sande.  N = R * C with C = 2^min(logN, 8).  Pass 1 runs
 // the first log R stages on columns (elements c, c+C, c+2C, ...) with a
-// 2048-word tile of TC adjacent columns per workgroup; pass 2 runs the last
-// log C stages on contiguous rows of C words, RB rows per workgroup.  Inside a
-// pass every thread holds a radix-8 unit (three stages) in registers; units are
-// exchanged through LDS between phases.  Butterflies are Harvey's lazy ones:
-// forward values stay in [0, 4q), inverse values in [0, 2q).
+// 4096-word tile of at least 16 adjacent columns per workgroup; pass 2 runs
+// the last log C stages on contiguous rows of C words, 8 rows per workgroup.
+// Inside a pass every thread holds a radix-8 unit (three stages) in
+// registers; units are exchanged through LDS between phases.
+//
+// Each limb takes one of two arithmetic paths, chosen per workgroup by its
+// prime: primes below 2^46 use exact FP64 arithmetic (full-rate FMA, values
+// kept as signed integers in doubles, no reduction inside a forward
+// transform); wider primes use Harvey's lazy butterflies on 64-bit words
+// (forward values in [0, 4q), inverse values in [0, 2q)).
 //
 // The first load and the last store of each transform go through policy
 // objects, so neighbouring ring steps run inside the transform instead of as
@@ -72,8 +77,12 @@ struct Blk {
     int logN;
 };
 
+// Every policy states the words it reads per coefficient position over a
+// launch of npoly polynomials x nl limbs (read_words for inputs, extra_words
+// for outputs), for the algorithmic byte count of the kernel timer.
 struct InWork {
     __device__ u64 load(const Blk &b, long g) const { return b.a[g]; }
+    double read_words(int npoly, int nl) const { return (double)npoly * nl; }
 };
 
 // read the same (limb, poly) of another set, through sigma_galois if galois > 1
@@ -86,6 +95,7 @@ struct InSrc {
         long gg = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
         return base[b.limb * ls + b.poly * ps + gg];
     }
+    double read_words(int npoly, int nl) const { return (double)npoly * nl; }
 };
 
 // fast basis conversion: sum_k y_k * hat(k, target) with y in coefficient form
@@ -103,6 +113,12 @@ struct InBconv {
     const TwF *hatf;    // non-null: FP64 pairs (hat, hat / q_t), same indexing, for FP64 targets
     u64 wide[2];        // bit 8 j + k: source k of digit j is a prime above 2^50
     __device__ int nsrc(int j) const { return ns_fixed > 0 ? ns_fixed : min(w, nq - j * w); }
+    // each source limb is read once per launch: the ndig digits of a batch
+    // element together hold its nq limbs
+    double read_words(int npoly, int) const
+    {
+        return ns_fixed > 0 ? (double)npoly * ns_fixed : (double)(npoly / ndig) * nq;
+    }
     __device__ u64 load(const Blk &b, long g) const
     {
         const int e = b.poly / ndig, j = b.poly - e * ndig;
@@ -197,6 +213,7 @@ struct InRescale {
         r = r >= ql ? r - ql : r;
         return subm(reduce64(r, *b.pc), reduce64(h, *b.pc), b.pc->q);
     }
+    double read_words(int npoly, int) const { return (double)npoly; }  // the dropped limb, shared by all limbs
 };
 
 // Output policies.  NPRE > 0: the policy reads NPRE further words per output
@@ -206,6 +223,7 @@ enum { OW_LAZY = 0, OW_REDUCE = 1, OW_SCALE_N = 2 };
 template <int MODE>
 struct OutWork {
     static constexpr int NPRE = 0;
+    double extra_words(int, int) const { return 0; }
     __device__ void fetch(const Blk &, long, u64 *) const {}
     __device__ void store(const Blk &b, long g, u64 v, const u64 *) const
     {
@@ -223,6 +241,7 @@ struct OutWork {
 struct OutScaleTab {
     const u64 *s, *sp;
     static constexpr int NPRE = 0;
+    double extra_words(int, int) const { return 0; }
     __device__ void fetch(const Blk &, long, u64 *) const {}
     __device__ void store(const Blk &b, long g, u64 v, const u64 *) const
     {
@@ -240,6 +259,7 @@ struct OutRescaleFin {
     long ols, ops;
     const u64 *inv, *invp;
     static constexpr int NPRE = 1;
+    double extra_words(int npoly, int nl) const { return (double)npoly * nl; }
     __device__ void fetch(const Blk &b, long g, u64 *pre) const { pre[0] = in[b.limb * ls + b.poly * ps + g]; }
     __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
     {
@@ -262,6 +282,10 @@ struct OutModdownFin {
     long ols, ops;
     const u64 *pinv, *pinvp;
     static constexpr int NPRE = 2;
+    double extra_words(int npoly, int nl) const
+    {
+        return (double)npoly * nl + (double)(npoly / 2) * nl * ((mask & 1) + (mask >> 1 & 1));
+    }
     __device__ void fetch(const Blk &b, long g, u64 *pre) const
     {
         const long gp = galois > 1 ? (long)auto_src((u32)g, galois, b.logN) : g;
@@ -283,10 +307,12 @@ struct OutModdownFin {
 // balanced doubles of the FP64 path (the next pass of the same prime reads them)
 struct InMid {
     __device__ u64 load(const Blk &b, long g) const { return b.a[g]; }
+    double read_words(int npoly, int nl) const { return (double)npoly * nl; }
     __device__ double load_d(const Blk &b, long g) const { return __longlong_as_double((long long)b.a[g]); }
 };
 struct OutMid {
     static constexpr int NPRE = 0;
+    double extra_words(int, int) const { return 0; }
     __device__ void fetch(const Blk &, long, u64 *) const {}
     __device__ void store(const Blk &b, long g, u64 v, const u64 *) const { b.a[g] = v; }
     __device__ void store_d(const Blk &b, long g, double v) const { b.a[g] = (u64)__double_as_longlong(v); }
@@ -348,10 +374,16 @@ struct PhaseIdx {
         const int p = p0 + (k << LS);
         return PASS == 1 ? ((long)p << G::LC) + (blk << G::LTC) + line : (((blk << G::LRB) + line) << G::LC) + p;
     }
+    // LDS word of position k.  Pass 2 keeps whole 256-word rows and XORs row
+    // bits 4..6 into bits 0..3 (bit 4 -> 0, bit 5 -> 1 and 2, bit 6 -> 3), so
+    // the phases' word strides 1, 4 and 32 all spread 16 consecutive lanes
+    // over distinct banks; pass-1 lanes already read 16 consecutive words
     __device__ __forceinline__ int lidx(int k) const
     {
         const int p = p0 + (k << LS);
-        return PASS == 1 ? (p << LL) + line : (line << LP) + p;
+        if (PASS == 1) return (p << LL) + line;
+        if constexpr (LP == 8) return (line << LP) + (p ^ (((p >> 4) & 1) | (((p >> 5) & 1) * 6) | (((p >> 6) & 1) << 3)));
+        return (line << LP) + p;
     }
     // the twiddle of the stage-h pair (k, k + 2^h) is entry
     // (N + gidx(k)) >> (LG + h + 1); bits [LG, LG + R) of gidx(0) are clear,
@@ -481,13 +513,16 @@ __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk
     }
 }
 
-// phase plan: forward 3,3,..,rem; inverse rem,..,3,3
+// phase plan: radix-8 phases, forward 3,3,..,rem; inverse rem,..,3,3
+// (radix-16 phases need up to 140 VGPRs in the fused variants and measured
+// slower)
+constexpr int RMAX = 3;
 template <int LP, bool FWD, int PH>
 struct PhasePlan {
-    static constexpr int NPH = (LP + 2) / 3;
-    static constexpr int REM = LP - 3 * (NPH - 1);
-    static constexpr int R = FWD ? (PH < NPH - 1 ? 3 : REM) : (PH == 0 ? REM : 3);
-    static constexpr int BEFORE = FWD ? 3 * PH : (PH == 0 ? 0 : REM + 3 * (PH - 1));
+    static constexpr int NPH = (LP + RMAX - 1) / RMAX;
+    static constexpr int REM = LP - RMAX * (NPH - 1);
+    static constexpr int R = FWD ? (PH < NPH - 1 ? RMAX : REM) : (PH == 0 ? REM : RMAX);
+    static constexpr int BEFORE = FWD ? RMAX * PH : (PH == 0 ? 0 : REM + RMAX * (PH - 1));
     static constexpr int LS = FWD ? LP - BEFORE - R : BEFORE;
 };
 
@@ -593,21 +628,26 @@ static void fwd_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &
     typedef NttGeo<LOGN> G;
     const int nl = j.ps.nl - (j.skip_hi - j.skip_lo);
     dim3 blk(256), g1(1 << (G::LC - G::LTC), nl * j.ps.npoly), g2(1 << (G::LR - G::LRB), nl * j.ps.npoly);
-    const double polys = (double)nl * j.ps.npoly, bytes = 16.0 * (double)(1l << LOGN) * polys;
+    // limb-polynomials transformed (a key-switch digit's own limbs are skipped)
+    const double polys = (double)nl * j.ps.npoly - (j.own_w > 0 ? (double)(j.ps.npoly / j.own_ndig) * j.own_nq : 0.0);
+    const double wb = 8.0 * (double)(1l << LOGN);
+    const double bytes1 = wb * (in.read_words(j.ps.npoly, nl) + polys);
+    const double bytes2 = wb * (2.0 * polys + out.extra_words(j.ps.npoly, nl));
     if constexpr (G::LR > 0) {
         bool on = tm && tm->on(KID_NTT_FWD1);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 1, true, IN, OutMid>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
                            j.own_w, j.own_nq, j.own_ndig, in, OutMid());
-        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
+        if (on) tm->after(s, bytes1, polys * (double)(1l << (LOGN - 1)) * G::LR);
         on = tm && tm->on(KID_NTT_FWD2);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 2, true, InMid, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
                            j.own_w, j.own_nq, j.own_ndig, InMid(), out);
-        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
+        if (on) tm->after(s, bytes2, polys * (double)(1l << (LOGN - 1)) * G::LC);
     } else {
         (void)g1;
-        (void)bytes;
+        (void)bytes1;
+        (void)bytes2;
         hipLaunchKernelGGL((k_ntt<LOGN, 2, true, IN, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
                            j.own_w, j.own_nq, j.own_ndig, in, out);
     }
@@ -619,21 +659,24 @@ static void inv_n(const NttTables &t, const NttJob &j, const IN &in, const OUT &
     typedef NttGeo<LOGN> G;
     const int nl = j.ps.nl - (j.skip_hi - j.skip_lo);
     dim3 blk(256), g1(1 << (G::LC - G::LTC), nl * j.ps.npoly), g2(1 << (G::LR - G::LRB), nl * j.ps.npoly);
-    const double polys = (double)nl * j.ps.npoly, bytes = 16.0 * (double)(1l << LOGN) * polys;
+    const double polys = (double)nl * j.ps.npoly, wb = 8.0 * (double)(1l << LOGN);
+    const double bytes2 = wb * (in.read_words(j.ps.npoly, nl) + polys);
+    const double bytes1 = wb * (2.0 * polys + out.extra_words(j.ps.npoly, nl));
     if constexpr (G::LR > 0) {
         bool on = tm && tm->on(KID_NTT_INV2);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OutMid>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
                            j.own_w, j.own_nq, j.own_ndig, in, OutMid());
-        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LC);
+        if (on) tm->after(s, bytes2, polys * (double)(1l << (LOGN - 1)) * G::LC);
         on = tm && tm->on(KID_NTT_INV1);
         if (on) tm->before(s);
         hipLaunchKernelGGL((k_ntt<LOGN, 1, false, InMid, OUT>), g1, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
                            j.own_w, j.own_nq, j.own_ndig, InMid(), out);
-        if (on) tm->after(s, bytes, polys * (double)(1l << (LOGN - 1)) * G::LR);
+        if (on) tm->after(s, bytes1, polys * (double)(1l << (LOGN - 1)) * G::LR);
     } else {
         (void)g1;
-        (void)bytes;
+        (void)bytes1;
+        (void)bytes2;
         hipLaunchKernelGGL((k_ntt<LOGN, 2, false, IN, OUT>), g2, blk, 0, s, t, j.ps, j.lm, j.skip_lo, j.skip_hi,
                            j.own_w, j.own_nq, j.own_ndig, in, out);
     }
