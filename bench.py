@@ -184,17 +184,18 @@ SERVE_MIX = (("formula16", 0.5), ("image", 0.3), ("cifar", 0.2))
 
 
 def serve_run(args, batched_rate):
-    """Poisson arrivals of requests drawn from the serving mix, served with
-    layer-granular continuous batching under an HBM budget; arrival rate 0.7x
-    the measured batched throughput of the image model."""
+    """Requests drawn from the serving mix on one context with every model's
+    keys resident: (1) Poisson arrivals at 0.7x the measured batched image
+    throughput, served with layer-granular continuous batching under an HBM
+    budget (p50/p99 latency, inferences/s); (2) the mixed batch: 64 requests
+    present at once under a 96 GiB budget, grouped by (model, layer) into
+    launches of up to 32."""
     from paper_2409_07751_amd import compile as pc
     from paper_2409_07751_amd import hekan, synth
     from paper_2409_07751_amd.serve import GpuEngine, Request, Server, latency_report
 
-    mix = [(n, p) for n, p in SERVE_MIX if n in synth.WORKLOADS and synth.WORKLOADS[n].shape[0] <= 1024]
-    names = [n for n, _ in mix]
-    probs = np.array([p for _, p in mix])
-    probs = probs / probs.sum()
+    names = [n for n, _ in SERVE_MIX]
+    probs = np.array([p for _, p in SERVE_MIX])
     wl0 = synth.WORKLOADS["image"]
     ctx = hekan.Context(wl0.logN, wl0.L, wl0.scale_bits, wl0.alpha, wl0.w)
     layers, models = {}, {}
@@ -204,22 +205,29 @@ def serve_run(args, batched_rate):
                                    [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
         models[n] = ctx.compile(layers[n])
     steps = sorted(set(s for m in models.values() for s in m.rotation_steps()))
+    t0 = time.time()
     keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    ctx.sync()
+    log("serving keygen %.1fs (%d Galois keys)" % (time.time() - t0, len(steps)))
     eng = GpuEngine(ctx, keys, models)
     for n in names:
         x = synth.inputs(synth.WORKLOADS[n], 1, stream=3)[0]
-        eng.calibrate(n, ctx.encrypt(keys, x, 7))
+        eng.calibrate(n, ctx.encrypt_input(models[n], keys, x, 7))
     free = ctx.memory()
     budget = 40 * 2 ** 30
+
+    def make(nreq, arrivals, stream0):
+        kinds = synth.request_mix(nreq, names, probs, seed=synth.SEED_ARRIVALS + stream0)
+        reqs = []
+        for i, n in enumerate(kinds):
+            x = synth.inputs(synth.WORKLOADS[n], 1, stream=stream0 + i)[0]
+            reqs.append(Request(i, n, ctx.encrypt_input(models[n], keys, x, 1000 + 10 * i), float(arrivals[i])))
+        ctx.sync()
+        return reqs
+
     rate = 0.7 * batched_rate
     nreq = args.serve_requests
-    kinds = synth.request_mix(nreq, names, probs)
-    arr = synth.poisson_arrivals(rate, nreq)
-    reqs = []
-    for i, n in enumerate(kinds):
-        x = synth.inputs(synth.WORKLOADS[n], 1, stream=100 + i)[0]
-        reqs.append(Request(i, n, ctx.encrypt(keys, x, 1000 + i), float(arr[i])))
-    ctx.sync()
+    reqs = make(nreq, synth.poisson_arrivals(rate, nreq), 100)
     log("serving %d requests at %.1f/s, budget %.1f GiB (pool live %.1f GiB)" % (nreq, rate, budget / 2 ** 30,
                                                                                  free["live"] / 2 ** 30))
     done = Server(eng, budget, max_batch=args.serve_batch).run(reqs)
@@ -228,9 +236,21 @@ def serve_run(args, batched_rate):
                 "hbm_budget_GiB": budget / 2 ** 30,
                 "working_MiB_per_request": {n: round(eng.work[n] / 2 ** 20, 1) for n in names}})
     log("serving:", rep)
+    del reqs, done
+
+    reqs = make(64, np.zeros(64), 5000)
+    log("mixed batch of 64 requests")
+    t0 = time.perf_counter()
+    done = Server(eng, 96 * 2 ** 30, max_batch=32).run(reqs)
+    ctx.sync()
+    span = time.perf_counter() - t0
+    kinds = {n: sum(1 for r in done if r.model == n) for n in names}
+    mixed = {"requests": len(done), "inferences_per_s": round(len(done) / span, 3), "span_s": round(span, 3),
+             "mean_batch": latency_report(done)["mean_batch"], "per_model": kinds}
+    log("mixed batch:", mixed)
     del reqs, done, keys, models, eng
     ctx.close()
-    return rep
+    return rep, mixed
 
 
 def main():
@@ -339,7 +359,7 @@ def main():
         res["plain_path"] = plain_path(ctx, model, keys, cts[0], args.plain_steps)
         res["batched_vs_plain"] = round(res["value"] / res["plain_path"]["inferences_per_s"], 3)
     if not args.no_serve:
-        res["serving"] = serve_run(args, res["value"])
+        res["serving"], res["batched_mix"] = serve_run(args, res["value"])
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     del cts, keys, model

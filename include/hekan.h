@@ -156,6 +156,14 @@ int he_model_free(he_model *m);
  * Writes min(cap, total) steps and the total count to *n. */
 int he_model_rotation_steps(const he_model *m, int32_t *steps, size_t cap, size_t *n);
 
+/* Input layout (what the client encrypts).  The first layer's repeat packing
+ * (Algorithm 1) needs n_in * 2^ceil(log2(g+2k)) slots; when that exceeds N/2
+ * the input is split into the fewest chunks of consecutive features that fit,
+ * sizes as equal as possible: chunk c = features [c n_in / nc, (c+1) n_in / nc),
+ * encrypted as its own ciphertext in slots [0, chunk size).  Writes the
+ * nc + 1 bounds (min(cap, nc + 1) of them) and nc to *n_chunks. */
+int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t *n_chunks);
+
 /* -------------------------------------------------------------------- keys */
 
 /* Generate a secret key (ternary, kept host-side inside the handle) and
@@ -193,21 +201,35 @@ int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out);
 
 /* ------------------------------------------------------- encrypted inference */
 
-/* Run the whole network on `in` (server side; no secret key involved).
- * Asynchronous on the context stream; *out is a new ciphertext. */
+/* Run the whole network on `in` (server side; no secret key involved) for a
+ * model with one input ciphertext (HE_ESHAPE otherwise).  Asynchronous on the
+ * context stream; *out is a new ciphertext. */
 int he_eval_kan(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *in, he_ct **out);
 
-/* Run layer `layer` only (for client-aided refresh between layers). */
+/* The same for any input layout: in[0..n_in) are the input chunks in order
+ * (n_in must equal he_model_input_chunks' count, HE_ESHAPE otherwise).  Each
+ * chunk runs the first layer's packing, bases and SiLU on its own and is
+ * multiplied by its columns of the layer's weights; the partial sums are
+ * added before the layer's fold. */
+int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n_in,
+                       he_ct **out);
+
+/* Run layer `layer` only (for client-aided refresh between layers); layer 0
+ * of a model with several input chunks needs he_eval_kan_layer_batch. */
 int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer, const he_ct *in,
                       he_ct **out);
 
-/* Run the network on n independent ciphertexts (one request each) in one
- * batched pass: every ring kernel processes all requests' limbs in one launch. */
+/* Run the network on n independent requests in one batched pass: every ring
+ * kernel processes all requests' limbs in one launch.  in holds n * nc
+ * ciphertexts, request-major (request i's chunk c at in[i nc + c], nc = the
+ * model's input chunk count); out receives n ciphertexts. */
 int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
                       he_ct **out);
 
-/* Run layer `layer` on n ciphertexts (all at the same level) in one batched
- * pass: the building block of layer-granular continuous batching. */
+/* Run layer `layer` on n requests (all at the same level) in one batched
+ * pass: the building block of layer-granular continuous batching.  For layer
+ * 0, in holds n * nc ciphertexts laid out as for he_eval_kan_batch; for later
+ * layers, n. */
 int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer,
                             const he_ct *const *in, size_t n, he_ct **out);
 

@@ -15,10 +15,16 @@ the layer input in blocks of n_blk slots:
     by the hybrid diagonal method with baby-step giant-step rotations, their
     partial sums added and folded over all slots, so the output is periodic
     with period d = next power of two >= n_out (the next layer's repeat
-    packing comes for free).
+    packing comes for free);
+  * a first layer whose repeat-packed footprint n_i 2^ceil(log2(g+2k))
+    exceeds the slot count takes its input as several ciphertexts, one per
+    chunk of consecutive features: each chunk is packed and expanded on its
+    own and multiplied by its columns of W_b and W_f, and the chunks' partial
+    sums are added before the single fold.
 Every step fixes where rescales happen and at which scale each plaintext is
 encoded, which the GPU path reproduces independently.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -269,8 +275,22 @@ def fold(ev, z, d):
     return z
 
 
-def layer_forward(ev, x, L, n_blk, first):
-    d = pow2ceil(L.n_out)
+def chunk_bounds(L, slots):
+    """Feature ranges [b_c, b_{c+1}) of the first layer's input ciphertexts:
+    the fewest chunks whose repeat-packed footprint (chunk size times
+    2^ceil(log2(g+2k))) fits the slots, sizes as equal as possible."""
+    copies = 1 << clog2(L.g + 2 * L.k)
+    nc = max(1, -(-L.n_in * copies // slots))
+    return [c * L.n_in // nc for c in range(nc + 1)]
+
+
+def sub_layer(L, lo, hi):
+    """The layer restricted to input features [lo, hi)."""
+    return dataclasses.replace(L, n_in=hi - lo, wb=L.wb[:, lo:hi], ws=L.ws[:, lo:hi], c=L.c[:, lo:hi])
+
+
+def layer_part(ev, x, L, n_blk, first, d):
+    """Both branches of one layer on one input ciphertext, before the fold."""
     xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
     b = bspline_basis(ev, xr, L, n_blk)
     s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
@@ -278,20 +298,40 @@ def layer_forward(ev, x, L, n_blk, first):
     Wf = fused_weights(L, n_blk)
     Wb = np.zeros((L.n_out, n_blk))
     Wb[:, :L.n_in] = L.wb
-    z = ev.add(matvec_partial(ev, b, Wf, d, t), matvec_partial(ev, s, Wb, d, t))
+    return ev.add(matvec_partial(ev, b, Wf, d, t), matvec_partial(ev, s, Wb, d, t))
+
+
+def layer_forward(ev, xs, L, n_blk, first):
+    """xs: the first layer's chunk ciphertexts (see chunk_bounds), else [x]."""
+    d = pow2ceil(L.n_out)
+    if first:
+        bounds = chunk_bounds(L, ev.ctx.p.slots)
+        parts = [(sub_layer(L, lo, hi), hi - lo) for lo, hi in zip(bounds[:-1], bounds[1:])]
+    else:
+        parts = [(L, n_blk)]
+    if len(xs) != len(parts):
+        raise ValueError("layer takes %d input ciphertexts, got %d" % (len(parts), len(xs)))
+    z = None
+    for x, (Lc, nb) in zip(xs, parts):
+        zc = layer_part(ev, x, Lc, nb, first, d)
+        z = zc if z is None else ev.add(z, zc)
     return fold(ev, z, d), d
 
 
 def eval_kan(ev, ct, layers, refresh=None):
-    """Run the layers on ct (input in slots [0, n_in)).  `refresh`, if given,
-    is called between layers with the ciphertext and returns a fresh one at the
+    """Run the layers on ct: one ciphertext (input in slots [0, n_in)) or the
+    list of the first layer's chunk ciphertexts (chunk c holds features
+    [b_c, b_{c+1}) in slots [0, b_{c+1} - b_c)).  `refresh`, if given, is
+    called between layers with the ciphertext and returns a fresh one at the
     top level (the client-aided stand-in for bootstrapping)."""
+    xs = list(ct) if isinstance(ct, (list, tuple)) else [ct]
     n_blk = layers[0].n_in
     for li, L in enumerate(layers):
         if li > 0 and refresh is not None:
-            ct = refresh(ct, li)
-        ct, n_blk = layer_forward(ev, ct, L, n_blk, li == 0)
-    return ct
+            xs = [refresh(xs[0], li)]
+        x, n_blk = layer_forward(ev, xs, L, n_blk, li == 0)
+        xs = [x]
+    return xs[0]
 
 
 def rotation_steps(layers, slots):
@@ -301,9 +341,13 @@ def rotation_steps(layers, slots):
     for li, L in enumerate(layers):
         d = pow2ceil(L.n_out)
         if li == 0:
-            for j in range(1, clog2(L.g + 2 * L.k) + 1):
-                steps.add(-n_blk * (1 << (j - 1)))
-        steps.add(n_blk)
+            bounds = chunk_bounds(L, slots)
+            for nb in set(hi - lo for lo, hi in zip(bounds[:-1], bounds[1:])):
+                for j in range(1, clog2(L.g + 2 * L.k) + 1):
+                    steps.add(-nb * (1 << (j - 1)))
+                steps.add(nb)
+        else:
+            steps.add(n_blk)
         b1, g1 = bsgs_split(d)
         steps.update(range(1, b1))
         steps.update(gi * b1 for gi in range(1, g1))

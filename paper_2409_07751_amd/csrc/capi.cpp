@@ -307,14 +307,53 @@ int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out)
     });
 }
 
+// n requests x nin input ciphertexts each (request-major) -> one batch per input
+static std::vector<Ct> batch_inputs(he_ctx *ctx, const he_ct *const *in, size_t n, size_t nin)
+{
+    Ctx &c = *ctx->c;
+    std::vector<Ct> xs;
+    for (size_t p = 0; p < nin; p++) {
+        std::vector<const Ct *> v;
+        for (size_t i = 0; i < n; i++) {
+            const he_ct *h = in[i * nin + p];
+            check_ct(ctx, h);
+            v.push_back(&h->c);
+        }
+        xs.push_back(n == 1 ? *v[0] : c.pack(v));
+    }
+    return xs;
+}
+
+static void check_model(he_ctx *ctx, const he_model *m, const he_keys *k)
+{
+    if (m->owner != ctx || k->owner != ctx) throw HeError(HE_ESTATE, "handle of another context");
+}
+
+int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t *n)
+{
+    if (!m || !n) return HE_EINVAL;
+    const auto &parts = m->m->layers[0].parts;
+    *n = parts.size();
+    for (size_t i = 0; i <= parts.size() && i < cap; i++)
+        bounds[i] = i < parts.size() ? parts[i].lo : parts.back().lo + parts.back().n_in;
+    return HE_OK;
+}
+
 int he_eval_kan(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *in, he_ct **out)
 {
-    if (!ctx || !m || !k || !out) return HE_EINVAL;
+    return he_eval_kan_chunks(ctx, m, k, &in, 1, out);
+}
+
+int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n_in,
+                       he_ct **out)
+{
+    if (!ctx || !m || !k || !out || !in) return HE_EINVAL;
     *out = nullptr;
     return guard(ctx, [&]() {
-        check_ct(ctx, in);
-        if (m->owner != ctx || k->owner != ctx) throw HeError(HE_ESTATE, "handle of another context");
-        *out = wrap(ctx, eval_model(*ctx->c, *m->m, *k->k, in->c));
+        check_model(ctx, m, k);
+        if (n_in != m->m->n_inputs())
+            throw HeError(HE_ESHAPE, "the model takes " + std::to_string(m->m->n_inputs()) + " input ciphertexts");
+        *out = wrap(ctx, eval_model(*ctx->c, *m->m, *k->k, batch_inputs(ctx, in, 1, n_in)));
     });
 }
 
@@ -323,11 +362,7 @@ int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t 
 {
     if (!ctx || !m || !k || !out) return HE_EINVAL;
     *out = nullptr;
-    return guard(ctx, [&]() {
-        check_ct(ctx, in);
-        need(layer >= 0 && (size_t)layer < m->m->layers.size(), "layer out of range");
-        *out = wrap(ctx, eval_layer(*ctx->c, *m->m, *k->k, in->c, (size_t)layer));
-    });
+    return he_eval_kan_layer_batch(ctx, m, k, layer, &in, 1, out);
 }
 
 int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
@@ -337,14 +372,10 @@ int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he
     return guard(ctx, [&]() {
         for (size_t i = 0; i < n; i++) out[i] = nullptr;
         if (n == 0) return;
-        std::vector<const Ct *> v;
-        for (size_t i = 0; i < n; i++) {
-            check_ct(ctx, in[i]);
-            v.push_back(&in[i]->c);
-        }
+        check_model(ctx, m, k);
         Ctx &c = *ctx->c;
-        Ct res = eval_model(c, *m->m, *k->k, c.pack(v));
-        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, c.unpack(res, (int)i));
+        Ct res = eval_model(c, *m->m, *k->k, batch_inputs(ctx, in, n, m->m->n_inputs()));
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, n == 1 ? res : c.unpack(res, (int)i));
     });
 }
 
@@ -355,15 +386,12 @@ int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, in
     return guard(ctx, [&]() {
         for (size_t i = 0; i < n; i++) out[i] = nullptr;
         if (n == 0) return;
+        check_model(ctx, m, k);
         need(layer >= 0 && (size_t)layer < m->m->layers.size(), "layer out of range");
-        std::vector<const Ct *> v;
-        for (size_t i = 0; i < n; i++) {
-            check_ct(ctx, in[i]);
-            v.push_back(&in[i]->c);
-        }
+        const size_t nin = layer == 0 ? m->m->n_inputs() : 1;
         Ctx &c = *ctx->c;
-        Ct res = eval_layer(c, *m->m, *k->k, c.pack(v), (size_t)layer);
-        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, c.unpack(res, (int)i));
+        Ct res = eval_layer(c, *m->m, *k->k, batch_inputs(ctx, in, n, nin), (size_t)layer);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, n == 1 ? res : c.unpack(res, (int)i));
     });
 }
 

@@ -41,7 +41,6 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
         L.n_out = s.n_out;
         L.g = s.g;
         L.k = s.k;
-        L.n_blk = n_blk;
         L.d = pow2ceil(s.n_out);
         const int r = s.g + 2 * s.k + 1, nb = s.g + s.k;
         L.knots.assign(s.knots, s.knots + r);
@@ -56,23 +55,41 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
             L.comp.emplace_back(s.comp_coeffs + off, s.comp_coeffs + off + len);
             off += len;
         }
-        // packing: the repeat-packed input needs (g+2k) blocks of n_blk slots;
-        // the first layer makes 2^ceil(log2(g+2k)) copies (Algorithm 1)
-        long need = (li == 0 ? pow2ceil(r - 1) : (long)(r - 1)) * n_blk;
-        if (need > slots || L.d > slots) throw HeError(-4, "model: n_in (g+2k) exceeds N/2 slots");
-        // fused weights W_f[o][m n_blk + i] = w_s[o][i] c[o][i][m]  (W' P with the
-        // Algorithm 3 permutation: column j_c = m n_i + i of W_f is column
-        // j_r = i (g+k) + m of W'), and W_b[o][i]
-        L.Wf.assign((size_t)s.n_out * nb * n_blk, 0.0);
-        L.Wb.assign((size_t)s.n_out * n_blk, 0.0);
-        for (int o = 0; o < s.n_out; o++)
-            for (int i = 0; i < s.n_in; i++) {
-                double ws = s.ws[(size_t)o * s.n_in + i];
-                L.Wb[(size_t)o * n_blk + i] = s.wb[(size_t)o * s.n_in + i];
-                for (int m = 0; m < nb; m++)
-                    L.Wf[(size_t)o * nb * n_blk + (size_t)m * n_blk + i] =
-                        ws * s.c[((size_t)o * s.n_in + i) * nb + m];
-            }
+        if (L.d > slots) throw HeError(-4, "model: n_out exceeds N/2 slots");
+        // packing: the first layer makes 2^ceil(log2(g+2k)) copies of its input
+        // (Algorithm 1); when n_in copies do not fit the slots the input comes
+        // as the fewest feature chunks that do, sizes as equal as possible
+        // (chunk c = features [c n_in / nc, (c+1) n_in / nc)); later layers
+        // need (g+2k) blocks of the previous output period
+        int nc = 1;
+        if (li == 0) {
+            const long copies = pow2ceil(r - 1);
+            nc = (int)std::max(1l, ((long)s.n_in * copies + slots - 1) / slots);
+            if (nc > s.n_in) throw HeError(-4, "model: g+2k copies of one input exceed N/2 slots");
+        } else if ((long)(r - 1) * n_blk > slots) {
+            throw HeError(-4, "model: n_in (g+2k) exceeds N/2 slots");
+        }
+        for (int pc = 0; pc < nc; pc++) {
+            Part P;
+            P.lo = (int)((long)pc * s.n_in / nc);
+            P.n_in = (int)((long)(pc + 1) * s.n_in / nc) - P.lo;
+            P.n_blk = li == 0 ? P.n_in : n_blk;
+            if (li == 0 && pow2ceil(r - 1) * P.n_blk > slots) throw HeError(-4, "model: chunk exceeds N/2 slots");
+            // fused weights W_f[o][m n_blk + i] = w_s[o][i] c[o][i][m]  (W' P with
+            // the Algorithm 3 permutation: column j_c = m n_i + i of W_f is column
+            // j_r = i (g+k) + m of W'), and W_b[o][i], over the part's inputs
+            P.Wf.assign((size_t)s.n_out * nb * P.n_blk, 0.0);
+            P.Wb.assign((size_t)s.n_out * P.n_blk, 0.0);
+            for (int o = 0; o < s.n_out; o++)
+                for (int i = 0; i < P.n_in; i++) {
+                    const size_t e = (size_t)o * s.n_in + P.lo + i;
+                    const double ws = s.ws[e];
+                    P.Wb[(size_t)o * P.n_blk + i] = s.wb[e];
+                    for (int m = 0; m < nb; m++)
+                        P.Wf[(size_t)o * nb * P.n_blk + (size_t)m * P.n_blk + i] = ws * s.c[e * nb + m];
+                }
+            L.parts.push_back(std::move(P));
+        }
         layers.push_back(std::move(L));
         n_blk = layers.back().d;
     }
@@ -80,9 +97,11 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
     std::vector<long> st;
     for (size_t li = 0; li < layers.size(); li++) {
         const LayerC &L = layers[li];
-        if (li == 0)
-            for (int j = 1; j <= clog2i(L.g + 2 * L.k); j++) st.push_back(-L.n_blk * (1l << (j - 1)));
-        st.push_back(L.n_blk);
+        for (const Part &P : L.parts) {
+            if (li == 0)
+                for (int j = 1; j <= clog2i(L.g + 2 * L.k); j++) st.push_back(-P.n_blk * (1l << (j - 1)));
+            st.push_back(P.n_blk);
+        }
         int b1 = 1 << ((clog2i(L.d) + 1) / 2);
         long g1 = L.d / b1;
         for (int b = 1; b < b1; b++) st.push_back(b);
@@ -260,19 +279,19 @@ struct Eval {
         return x;
     }
 
-    // ColTile(G, lo, hi): block mb (< hi-lo) holds t_{lo+mb} for the n_in inputs
-    std::vector<double> coltile(const LayerC &L, int lo, int hi) const
+    // ColTile(G, lo, hi): block mb (< hi-lo) holds t_{lo+mb} for the part's inputs
+    std::vector<double> coltile(const LayerC &L, const Part &P, int lo, int hi) const
     {
         std::vector<double> v(c.N / 2, 0.0);
         for (int mb = 0; mb < hi - lo; mb++)
-            for (int i = 0; i < L.n_in; i++) v[(size_t)mb * L.n_blk + i] = L.knots[lo + mb - 1];
+            for (int i = 0; i < P.n_in; i++) v[(size_t)mb * P.n_blk + i] = L.knots[lo + mb - 1];
         return v;
     }
 
-    Ct bspline(const Ct &xr, const LayerC &L, const std::string &tag)
+    Ct bspline(const Ct &xr, const LayerC &L, const Part &P, const std::string &tag)
     {
         const int r = L.g + 2 * L.k + 1;
-        std::vector<double> g1 = coltile(L, 1, r), g2 = coltile(L, 2, r + 1);
+        std::vector<double> g1 = coltile(L, P, 1, r), g2 = coltile(L, P, 2, r + 1);
         Ct x1, x2;
         if (L.prescale != 0.0) {
             // (x - g1) / 2R and (g2 - x) / 2R, one rescale each (Algorithm 2)
@@ -291,12 +310,12 @@ struct Eval {
         const size_t S2 = c.N / 2;
         for (int j = 1; j <= L.k; j++) {
             const int nbl = r - j - 1;
-            std::vector<double> t1 = coltile(L, 1, r - j), t2 = coltile(L, j + 1, r);
-            std::vector<double> t3 = coltile(L, j + 2, r + 1), t4 = coltile(L, 2, r - j + 1);
+            std::vector<double> t1 = coltile(L, P, 1, r - j), t2 = coltile(L, P, j + 1, r);
+            std::vector<double> t3 = coltile(L, P, j + 2, r + 1), t4 = coltile(L, P, 2, r - j + 1);
             std::vector<double> A1(S2, 0.0), A2n(S2, 0.0), c1(S2, 0.0), c2(S2, 0.0);
             for (int mb = 0; mb < nbl; mb++)
-                for (int i = 0; i < L.n_in; i++) {
-                    size_t s = (size_t)mb * L.n_blk + i;
+                for (int i = 0; i < P.n_in; i++) {
+                    size_t s = (size_t)mb * P.n_blk + i;
                     double a1 = 1.0 / (t2[s] - t1[s]);
                     double a2 = 1.0 / (t3[s] - t4[s]);
                     A1[s] = a1;
@@ -310,7 +329,7 @@ struct Eval {
             const Pt &pA2 = vec(jt + "A2", lb, xr.level, A2n);
             Ct P1 = c.add_plain(c.lincomb({{&xr, &pA1}}, lb), addvec(jt + "c1", lb, c1));
             Ct P2 = c.add_plain(c.lincomb({{&xr, &pA2}}, lb), addvec(jt + "c2", lb, c2));
-            Ct rb = c.rotate(b, L.n_blk, k);
+            Ct rb = c.rotate(b, P.n_blk, k);
             Tensor tt = c.tensor(P1, b);
             c.tensor_acc(tt, P2, rb);
             b = c.relin_rescale(tt, k);
@@ -377,35 +396,53 @@ struct Eval {
         return z;
     }
 
-    Ct layer(const Ct &x, size_t li)
+    // both branches of the layer on one part's ciphertext, before the fold
+    Ct part(const Ct &x, size_t li, size_t pc)
     {
         const LayerC &L = m.layers[li];
-        const std::string tag = "L" + std::to_string(li) + "/";
-        Ct xr = li == 0 ? repeat_pack(x, L.n_blk, clog2i(L.g + 2 * L.k)) : x;
-        Ct b = bspline(xr, L, tag);
+        const Part &P = L.parts[pc];
+        const std::string tag =
+            "L" + std::to_string(li) + "/" + (L.parts.size() > 1 ? "c" + std::to_string(pc) + "/" : "");
+        Ct xr = li == 0 ? repeat_pack(x, P.n_blk, clog2i(L.g + 2 * L.k)) : x;
+        Ct b = bspline(xr, L, P, tag);
         Ct s = cheb_eval(x, L.silu, L.silu_lo, L.silu_hi);
         int t = std::min(b.level, s.level) - 1;
         if (t < 0) throw HeError(-3, "layer does not fit the level budget");
         const long nb = L.g + L.k;
-        Ct zf = matvec(b, L.Wf, L.n_out, nb * L.n_blk, L.d, t, tag + "F");
-        Ct zb = matvec(s, L.Wb, L.n_out, L.n_blk, L.d, t, tag + "B");
-        return fold(c.add(zf, zb), L.d);
+        Ct zf = matvec(b, P.Wf, L.n_out, nb * P.n_blk, L.d, t, tag + "F");
+        Ct zb = matvec(s, P.Wb, L.n_out, P.n_blk, L.d, t, tag + "B");
+        return c.add(zf, zb);
+    }
+
+    // the parts' partial sums share one layout: add them, then fold once
+    Ct layer(const std::vector<Ct> &xs, size_t li)
+    {
+        const LayerC &L = m.layers[li];
+        if (xs.size() != L.parts.size())
+            throw HeError(-4, "layer " + std::to_string(li) + " takes " + std::to_string(L.parts.size()) +
+                                  " input ciphertexts, got " + std::to_string(xs.size()));
+        for (size_t pc = 1; pc < xs.size(); pc++)
+            if (xs[pc].level != xs[0].level || xs[pc].nb != xs[0].nb)
+                throw HeError(-1, "input ciphertexts differ in level or batch size");
+        Ct z = part(xs[0], li, 0);
+        for (size_t pc = 1; pc < xs.size(); pc++) z = c.add(z, part(xs[pc], li, pc));
+        return fold(z, L.d);
     }
 };
 
-Ct eval_layer(Ctx &c, Model &m, const Keys &k, const Ct &in, size_t li)
+Ct eval_layer(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in, size_t li)
 {
     Eval e(c, k, m);
     return e.layer(in, li);
 }
 
-Ct eval_model(Ctx &c, Model &m, const Keys &k, const Ct &in)
+Ct eval_model(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in)
 {
     if (m.refresh && m.layers.size() > 1)
         throw HeError(-7, "model compiled with refresh between layers: evaluate layer by layer");
     Eval e(c, k, m);
-    Ct x = in;
-    for (size_t li = 0; li < m.layers.size(); li++) x = e.layer(x, li);
+    Ct x = e.layer(in, 0);
+    for (size_t li = 1; li < m.layers.size(); li++) x = e.layer({x}, li);
     return x;
 }
 

@@ -9,16 +9,24 @@
 
 namespace hk {
 
+// The inputs [lo, lo + n_in) of a layer that arrive in one ciphertext.
+struct Part {
+    int lo, n_in;
+    long n_blk;              // slots per input block (first layer: n_in; later: previous d)
+    std::vector<double> Wf;  // n_out x (g+k) n_blk, ColTile column order
+    std::vector<double> Wb;  // n_out x n_blk
+};
+
 struct LayerC {
     int n_in, n_out, g, k;
-    long n_blk;  // slots per input block (first layer: n_in; later: previous d)
-    long d;      // output period: next power of two >= n_out
+    long d;  // output period: next power of two >= n_out
     std::vector<double> knots, silu;
     double silu_lo, silu_hi;
     std::vector<std::vector<double>> comp;
-    double prescale;         // explicit 1/(2R) before PolyComp, 0 = folded
-    std::vector<double> Wf;  // n_out x (g+k) n_blk, ColTile column order
-    std::vector<double> Wb;  // n_out x n_blk
+    double prescale;  // explicit 1/(2R) before PolyComp, 0 = folded
+    // first layer: one part per input ciphertext (feature chunks, when the
+    // repeat-packed input would not fit the slots); later layers: one part
+    std::vector<Part> parts;
 };
 
 struct Model {
@@ -29,9 +37,12 @@ struct Model {
     std::unordered_map<std::string, Pt> pt_cache;   // Montgomery NTT plaintexts for lincombs
     std::unordered_map<std::string, Buf> add_cache; // NTT plaintexts added to ciphertexts
     Model(Ctx *c, const he_kan_desc *d, bool refresh);
+    size_t n_inputs() const { return layers[0].parts.size(); }
 };
 
-Ct eval_layer(Ctx &c, Model &m, const Keys &k, const Ct &in, size_t li);
-Ct eval_model(Ctx &c, Model &m, const Keys &k, const Ct &in);
+// in: one ciphertext per part of the layer (the first layer's feature
+// chunks, or the previous layer's output)
+Ct eval_layer(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in, size_t li);
+Ct eval_model(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in);
 
 }  // namespace hk

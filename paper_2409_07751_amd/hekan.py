@@ -58,6 +58,7 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_void_p)],
     "he_model_free": [ctypes.c_void_p],
     "he_model_rotation_steps": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "he_model_input_chunks": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "he_keygen": [ctypes.c_void_p, ctypes.c_uint64, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_keys_free": [ctypes.c_void_p],
     "he_keys_export": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, _u64p, ctypes.c_size_t],
@@ -70,6 +71,8 @@ _SIGS = {
     "he_ct_import": [ctypes.c_void_p, _u64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
     "he_eval_kan": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                     ctypes.POINTER(ctypes.c_void_p)],
+    "he_eval_kan_chunks": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                           ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_eval_kan_layer": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_void_p)],
     "he_eval_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
@@ -241,15 +244,36 @@ class Context:
     def compile(self, layers, refresh=False):
         return Model(self, layers, refresh)
 
+    def encrypt_input(self, model, keys, x, seed):
+        """Encrypt one request's input in the model's layout: one ciphertext per
+        input chunk (he_model_input_chunks), chunk c with seed + c."""
+        b = model.input_chunks()
+        x = _arr(x, np.float64)
+        cts = [self.encrypt(keys, x[lo:hi], seed + c) for c, (lo, hi) in enumerate(zip(b[:-1], b[1:]))]
+        return cts[0] if len(cts) == 1 else cts
+
     def eval_kan(self, model, keys, ct):
+        """ct: one ciphertext, or the list of a request's input chunks."""
+        if isinstance(ct, (list, tuple)):
+            arr = (ctypes.c_void_p * len(ct))(*[c.h.value for c in ct])
+            return self._new(self.lib.he_eval_kan_chunks, model.h, keys.h, arr, len(ct))
         return self._new(self.lib.he_eval_kan, model.h, keys.h, ct.h)
+
+    def eval_kan_chunks(self, model, keys, cts):
+        return self.eval_kan(model, keys, list(cts))
 
     def eval_kan_layer(self, model, keys, layer, ct):
         return self._new(self.lib.he_eval_kan_layer, model.h, keys.h, layer, ct.h)
 
+    @staticmethod
+    def _flat(cts):
+        # requests given as ciphertexts or as lists of input chunks, request-major
+        return [c for r in cts for c in (r if isinstance(r, (list, tuple)) else [r])]
+
     def eval_kan_layer_batch(self, model, keys, layer, cts):
         n = len(cts)
-        arr = (ctypes.c_void_p * n)(*[c.h.value for c in cts])
+        flat = self._flat(cts)
+        arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
         outs = (ctypes.c_void_p * n)()
         self.check(self.lib.he_eval_kan_layer_batch(self.h, model.h, keys.h, layer, arr, n, outs))
         return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
@@ -261,7 +285,8 @@ class Context:
 
     def eval_kan_batch(self, model, keys, cts):
         n = len(cts)
-        arr = (ctypes.c_void_p * n)(*[c.h.value for c in cts])
+        flat = self._flat(cts)
+        arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
         outs = (ctypes.c_void_p * n)()
         self.check(self.lib.he_eval_kan_batch(self.h, model.h, keys.h, arr, n, outs))
         return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
@@ -325,6 +350,14 @@ class Model:
         ctx.check(ctx.lib.he_model_compile(ctx.h, ctypes.byref(desc), 1 if refresh else 0, ctypes.byref(h)))
         self.h = h
         self.n_layers = len(layers)
+
+    def input_chunks(self):
+        """Feature bounds [b_0 = 0, b_1, ..., b_nc = n_in] of the input chunks."""
+        n = ctypes.c_size_t()
+        self.ctx.check(self.ctx.lib.he_model_input_chunks(self.h, None, 0, ctypes.byref(n)))
+        b = np.zeros(n.value + 1, np.int32)
+        self.ctx.check(self.ctx.lib.he_model_input_chunks(self.h, _ptr(b), n.value + 1, ctypes.byref(n)))
+        return [int(v) for v in b]
 
     def rotation_steps(self):
         n = ctypes.c_size_t()

@@ -63,6 +63,10 @@ WORKLOADS = {
                       ((7, 7), (7, 7)), 0.05, 0.05, "pixels255"),
     "cifar": Workload("cifar", 16, 24, 45, 4, 5, (3072, 128, 10), 8, 3, (0.0, 1.0), 31, None,
                       ((7, 7), (7, 7)), 0.05, 0.05, "pixels"),
+    # the tiny parameters with a first layer too wide for one ciphertext
+    # (384 x 16 repeat-packed slots > 4096): two input ciphertexts
+    "tinychunk": Workload("tinychunk", 13, 7, 40, 1, 1, (384, 4, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
+                          ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True, False),
 }
 
 

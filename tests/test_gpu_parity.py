@@ -218,7 +218,7 @@ def test_kan_tiny_layers_bit_exact_and_accuracy(tiny):
     for li, L in enumerate(layers):
         note("tiny layer", li)
         out = ctx.eval_kan_layer(model, keys, li, ct)
-        oout, n_blk = circuit.layer_forward(ev, oct_, L, n_blk, li == 0)
+        oout, n_blk = circuit.layer_forward(ev, [oct_], L, n_blk, li == 0)
         e = out.export()
         assert out.level == oout.level
         assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "layer %d residues differ" % li
@@ -291,3 +291,72 @@ def test_batch_equals_single_image(image):
         assert (outs[i].export() == alone).all(), "request %d differs in the batch" % i
         y = ctx.decrypt(keys, outs[i], 10)
         assert np.abs(y - kan.he_friendly_kan(xs[i][None], layers)[0]).max() < 1e-2
+
+
+def test_kan_chunked_first_layer_bit_exact(tiny):
+    """A first layer too wide for one ciphertext ([384,4,1] at N = 2^13: 384 x 16
+    repeat-packed slots > 4096) takes two input chunks: the output residues
+    equal the oracle's, the chunk bounds and rotation steps agree, and two
+    requests batched together give exactly their residues alone."""
+    wl, ctx, octx = tiny
+    wl = synth.WORKLOADS["tinychunk"]
+    raw = synth.raw_weights(wl)
+    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
+                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+    model = ctx.compile(layers, refresh=True)
+    bounds = model.input_chunks()
+    assert bounds == circuit.chunk_bounds(layers[0], octx.p.slots) == [0, 192, 384]
+    steps = model.rotation_steps()
+    assert steps == circuit.rotation_steps(layers, octx.p.slots)
+    note("tinychunk keygen", len(steps))
+    keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    okeys = O.Keys(octx, synth.SEED_KEYGEN, steps)
+    ev = O.Oracle(octx, okeys)
+    x = synth.inputs(wl, 2)
+    reqs = [ctx.encrypt_input(model, keys, x[i], synth.SEED_ENC + 10 * i) for i in range(2)]
+    assert len(reqs[0]) == 2
+    note("tinychunk layer 0 alone")
+    alone = [ctx.eval_kan_layer_batch(model, keys, 0, [r])[0] for r in reqs]
+    note("tinychunk layer 0 oracle")
+    ocs = [ev.encrypt(x[0][lo:hi], synth.SEED_ENC + c) for c, (lo, hi) in enumerate(zip(bounds[:-1], bounds[1:]))]
+    oout, _ = circuit.layer_forward(ev, ocs, layers[0], layers[0].n_in, True)
+    e = alone[0].export()
+    assert alone[0].level == oout.level
+    assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "chunked layer residues differ"
+    note("tinychunk layer 0 batched")
+    both = ctx.eval_kan_layer_batch(model, keys, 0, reqs)
+    for a, b in zip(alone, both):
+        assert (a.export() == b.export()).all()
+    y = ctx.decrypt(keys, alone[1], layers[0].n_out)
+    want = kan.he_friendly_layer(x[1][None], layers[0])[0]
+    assert np.abs(y - want).max() < 1e-2
+
+
+@pytest.mark.timeout(900)
+def test_kan_cifar_chunked_accuracy_and_batch(image):
+    """Encrypted [3072,128,10] inference at N = 2^16 with its input in two
+    ciphertexts: batched results equal single ones bit for bit and decrypt
+    within 1e-2 of the FP64 HE-friendly circuit."""
+    wl, ctx, octx = image
+    wl = synth.WORKLOADS["cifar"]
+    raw = synth.raw_weights(wl)
+    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
+                               [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
+    model = ctx.compile(layers)
+    assert model.input_chunks() == [0, 1536, 3072]
+    steps = model.rotation_steps()
+    assert steps == circuit.rotation_steps(layers, octx.p.slots)
+    note("cifar keygen", len(steps))
+    keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    x = synth.inputs(wl, 2)
+    reqs = [ctx.encrypt_input(model, keys, x[i], synth.SEED_ENC + 10 * i) for i in range(2)]
+    note("cifar batch")
+    both = ctx.eval_kan_batch(model, keys, reqs)
+    for i in range(2):
+        note("cifar single", i)
+        one = ctx.eval_kan(model, keys, reqs[i])
+        assert (one.export() == both[i].export()).all()
+        y = ctx.decrypt(keys, one, 10)
+        want = kan.he_friendly_kan(x[i][None], layers)[0]
+        note("max err", np.abs(y - want).max(), "level", one.level)
+        assert np.abs(y - want).max() < 1e-2

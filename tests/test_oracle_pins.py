@@ -480,10 +480,11 @@ def test_odd_poly_depths_on_simulator():
         assert np.abs(out.v - kan.eval_odd(x, a)).max() < 1e-12
 
 
-@pytest.mark.parametrize("name", ["tiny", "image"])
+@pytest.mark.parametrize("name", ["tiny", "image", "cifar", "tinychunk"])
 def test_circuit_on_simulator_equals_fp64_kan(name):
     """The slot circuit (repeat packing, Algorithm 2 with rotations, fused
-    weights W_f = W'P, BSGS matvecs and folding) equals the plain HE-friendly
+    weights W_f = W'P, BSGS matvecs and folding; a first layer too wide for
+    one ciphertext split into feature chunks) equals the plain HE-friendly
     network, and fits the workload's level budget."""
     wl = synth.WORKLOADS[name]
     raw = synth.raw_weights(wl)
@@ -491,8 +492,10 @@ def test_circuit_on_simulator_equals_fp64_kan(name):
                                [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
     x = synth.inputs(wl, 2)
     sim = SlotSim(1 << (wl.logN - 1))
+    bounds = circuit.chunk_bounds(layers[0], sim.ctx.p.slots)
+    assert len(bounds) - 1 == {"tiny": 1, "image": 1, "cifar": 2, "tinychunk": 2}[name]
     for row in x:
-        ct = sim.fresh(row, wl.L)
+        ct = [sim.fresh(row[lo:hi], wl.L) for lo, hi in zip(bounds[:-1], bounds[1:])]
         refresh = (lambda c, li: SimCt(wl.L, c.v)) if wl.refresh else None
         out = circuit.eval_kan(sim, ct, layers, refresh)
         assert out.level >= 0
@@ -500,6 +503,19 @@ def test_circuit_on_simulator_equals_fp64_kan(name):
         assert np.abs(out.v[:len(want)] - want).max() < 1e-8 * max(1, np.abs(want).max())
     assert sorted(sim.rot_steps) == sorted(set(circuit.rotation_steps(layers, sim.ctx.p.slots)) & sim.rot_steps)
     assert set(circuit.rotation_steps(layers, sim.ctx.p.slots)) == sim.rot_steps
+
+
+def test_chunk_bounds():
+    """Fewest chunks whose repeat-packed footprint fits, sizes within one."""
+    L = kan.Layer(3072, 128, 8, 3, np.zeros(15), np.zeros((128, 3072)), np.zeros((128, 3072)),
+                  np.zeros((128, 3072, 11)), np.zeros(4), 0.0, 1.0, 1.0)
+    assert circuit.chunk_bounds(L, 32768) == [0, 1536, 3072]        # 3072 x 16 = 49152 slots
+    assert circuit.chunk_bounds(L, 65536) == [0, 3072]
+    L.n_in = 785
+    b = circuit.chunk_bounds(L, 4096)                                # 785 x 16 / 4096 -> 4 chunks
+    assert b[0] == 0 and b[-1] == 785 and len(b) == 5
+    assert max(hi - lo for lo, hi in zip(b[:-1], b[1:])) * 16 <= 4096
+    assert max(hi - lo for lo, hi in zip(b[:-1], b[1:])) - min(hi - lo for lo, hi in zip(b[:-1], b[1:])) <= 1
 
 
 def test_oracle_he_kan_tiny_matches_fp64_circuit():
