@@ -108,6 +108,13 @@ typedef struct {
 typedef struct {
     int32_t n_layers;
     const he_kan_layer *layers;
+    /* input vectors per ciphertext, a power of two (0 reads as 1): feature i
+     * of vector s in slot i S + s, output o of vector s in slot o S + s; the
+     * linear layers act as W (x) I_S, whose only non-zero generalised
+     * diagonals are multiples of S, so rotations are S times longer but as
+     * many.  Every layer must fit: (g+2k) blocks of (previous output period
+     * d) S slots within N/2. */
+    int32_t samples_per_ct;
 } he_kan_desc;
 
 /* ---------------------------------------------------------------- context */
@@ -158,10 +165,11 @@ int he_model_rotation_steps(const he_model *m, int32_t *steps, size_t cap, size_
 
 /* Input layout (what the client encrypts).  The first layer's repeat packing
  * (Algorithm 1) needs n_in * 2^ceil(log2(g+2k)) slots; when that exceeds N/2
- * the input is split into the fewest chunks of consecutive features that fit,
- * sizes as equal as possible: chunk c = features [c n_in / nc, (c+1) n_in / nc),
- * encrypted as its own ciphertext in slots [0, chunk size).  Writes the
- * nc + 1 bounds (min(cap, nc + 1) of them) and nc to *n_chunks. */
+ * the input is split into chunks of consecutive features, each holding
+ * cap = (N/2) / 2^ceil(log2(g+2k)) features and the last one the rest:
+ * chunk c = features [c cap, min((c+1) cap, n_in)), encrypted as its own
+ * ciphertext in slots [0, chunk size).  Writes the nc + 1 bounds
+ * (min(cap, nc + 1) of them) and nc to *n_chunks. */
 int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t *n_chunks);
 
 /* -------------------------------------------------------------------- keys */

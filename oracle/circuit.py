@@ -20,7 +20,12 @@ the layer input in blocks of n_blk slots:
     exceeds the slot count takes its input as several ciphertexts, one per
     chunk of consecutive features: each chunk is packed and expanded on its
     own and multiplied by its columns of W_b and W_f, and the chunks' partial
-    sums are added before the single fold.
+    sums are added before the single fold;
+  * S input vectors may share a ciphertext (S a power of two): feature i of
+    vector s sits in slot i S + s, every block is S times wider, and the
+    linear layers act as W (x) I_S, whose only non-zero generalised diagonals
+    are the multiples of S, so the rotations are S times longer but as many;
+    outputs are periodic with period d S.
 Every step fixes where rescales happen and at which scale each plaintext is
 encoded, which the GPU path reproduces independently.
 """
@@ -193,12 +198,14 @@ def block_mask(nblocks, n_blk, n_in, slots):
     return v
 
 
-def bspline_basis(ev, xr, L, n_blk):
-    """Algorithm 2 on the repeat-packed ciphertext xr."""
+def bspline_basis(ev, xr, L, n_blk, width=None):
+    """Algorithm 2 on the repeat-packed ciphertext xr; `width` valid slots per
+    block (n_in S when S vectors share the ciphertext)."""
     slots = ev.ctx.p.slots
+    width = L.n_in if width is None else width
     r = L.g + 2 * L.k + 1
-    g1 = coltile(L.knots, 1, r, n_blk, L.n_in, slots)
-    g2 = coltile(L.knots, 2, r + 1, n_blk, L.n_in, slots)
+    g1 = coltile(L.knots, 1, r, n_blk, width, slots)
+    g2 = coltile(L.knots, 2, r + 1, n_blk, width, slots)
     if L.comp_prescale:
         # (x - g1) / 2R and (g2 - x) / 2R in one rescale each
         sc = L.comp_prescale
@@ -210,11 +217,11 @@ def bspline_basis(ev, xr, L, n_blk):
     b = ev.mul(x1, x2)
     for j in range(1, L.k + 1):
         nbl = r - j - 1
-        t1 = coltile(L.knots, 1, r - j, n_blk, L.n_in, slots)
-        t2 = coltile(L.knots, j + 1, r, n_blk, L.n_in, slots)
-        t3 = coltile(L.knots, j + 2, r + 1, n_blk, L.n_in, slots)
-        t4 = coltile(L.knots, 2, r - j + 1, n_blk, L.n_in, slots)
-        msk = block_mask(nbl, n_blk, L.n_in, slots)
+        t1 = coltile(L.knots, 1, r - j, n_blk, width, slots)
+        t2 = coltile(L.knots, j + 1, r, n_blk, width, slots)
+        t3 = coltile(L.knots, j + 2, r + 1, n_blk, width, slots)
+        t4 = coltile(L.knots, 2, r - j + 1, n_blk, width, slots)
+        msk = block_mask(nbl, n_blk, width, slots)
         A1 = np.zeros(slots)
         A2 = np.zeros(slots)
         A1[msk] = 1.0 / (t2[msk] - t1[msk])
@@ -245,29 +252,32 @@ def bsgs_split(d):
     return b1, d // b1
 
 
-def matvec_partial(ev, x, M, d, t):
-    """z = sum_{i<d} diag_i * rot(x, i) at level t by baby-step giant-step:
-    z = sum_gi rot( sum_bi rot(diag_{gi b1 + bi}, -gi b1) * rot(x, bi), gi b1 ).
-    x is mod-dropped to t+1 before the baby-step rotations."""
+def matvec_partial(ev, x, M, d, t, S=1):
+    """z = sum_{i<d} diag_{iS} * rot(x, iS) at level t by baby-step giant-step:
+    z = sum_gi rot( sum_bi rot(diag_{(gi b1 + bi) S}, -gi b1 S) * rot(x, bi S), gi b1 S ),
+    diagonals of M taken with output period d S (for S = 1 every diagonal i < d;
+    for M = W (x) I_S the others are zero).  x is mod-dropped to t+1 before
+    the baby-step rotations."""
     slots = ev.ctx.p.slots
     b1, g1 = bsgs_split(d)
+    D = d * S
     xd = ev.mod_drop(x, t + 1)
-    rots = [xd] + [ev.rotate(xd, bi) for bi in range(1, b1)]
+    rots = [xd] + [ev.rotate(xd, bi * S) for bi in range(1, b1)]
     z = None
     for gi in range(g1):
         terms = []
         for bi in range(b1):
-            dv = np.roll(diag_vector(M, d, gi * b1 + bi, slots), gi * b1)
+            dv = np.roll(diag_vector(M, D, (gi * b1 + bi) * S, slots), gi * b1 * S)
             terms.append((rots[bi], dv))
         inner = ev.lincomb(terms, t)
         if gi:
-            inner = ev.rotate(inner, gi * b1)
+            inner = ev.rotate(inner, gi * b1 * S)
         z = inner if z is None else ev.add(z, inner)
     return z
 
 
 def fold(ev, z, d):
-    """z <- z + rot(z, s) for s = slots/2, slots/4, ..., d."""
+    """z <- z + rot(z, s) for s = slots/2, slots/4, ..., d (d: the output period)."""
     s = ev.ctx.p.slots // 2
     while s >= d:
         z = ev.add(z, ev.rotate(z, s))
@@ -275,13 +285,35 @@ def fold(ev, z, d):
     return z
 
 
-def chunk_bounds(L, slots):
+def chunk_bounds(L, slots, S=1):
     """Feature ranges [b_c, b_{c+1}) of the first layer's input ciphertexts:
-    the fewest chunks whose repeat-packed footprint (chunk size times
-    2^ceil(log2(g+2k))) fits the slots, sizes as equal as possible."""
-    copies = 1 << clog2(L.g + 2 * L.k)
-    nc = max(1, -(-L.n_in * copies // slots))
-    return [c * L.n_in // nc for c in range(nc + 1)]
+    each chunk holds as many consecutive features as its repeat-packed
+    footprint (chunk size times S times 2^ceil(log2(g+2k))) allows in the
+    slots, the last one the rest."""
+    cap = (slots >> clog2(L.g + 2 * L.k)) // S
+    if cap < 1:
+        raise ValueError("g+2k copies of one input exceed the slots")
+    return list(range(0, L.n_in, cap)) + [L.n_in]
+
+
+def pack_samples(X, S):
+    """Slot vector of S input vectors X (S x n): feature i of vector s in slot i S + s."""
+    X = np.atleast_2d(np.asarray(X, np.float64))
+    assert X.shape[0] == S
+    return X.T.reshape(-1)
+
+
+def strided(M, S, col_blocks=1, n_blk=None):
+    """W (x) I_S in the slot layout: M (n_out x col_blocks n_w, block m of
+    width n_w) -> rows o S + s, columns m n_blk + i S + s (n_blk >= n_w S)."""
+    n_out, cols = M.shape
+    n_w = cols // col_blocks
+    n_blk = n_w * S if n_blk is None else n_blk
+    out = np.zeros((n_out * S, col_blocks * n_blk))
+    for m in range(col_blocks):
+        for s in range(S):
+            out[s::S, m * n_blk + s:m * n_blk + n_w * S:S] = M[:, m * n_w:(m + 1) * n_w]
+    return out
 
 
 def sub_layer(L, lo, hi):
@@ -289,71 +321,75 @@ def sub_layer(L, lo, hi):
     return dataclasses.replace(L, n_in=hi - lo, wb=L.wb[:, lo:hi], ws=L.ws[:, lo:hi], c=L.c[:, lo:hi])
 
 
-def layer_part(ev, x, L, n_blk, first, d):
-    """Both branches of one layer on one input ciphertext, before the fold."""
+def layer_part(ev, x, L, n_blk, first, d, S=1):
+    """Both branches of one layer on one input ciphertext, before the fold.
+    n_blk: slots per input block (n_in S for a first layer)."""
     xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
-    b = bspline_basis(ev, xr, L, n_blk)
+    b = bspline_basis(ev, xr, L, n_blk, L.n_in * S)
     s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
     t = min(b.level, s.level) - 1
-    Wf = fused_weights(L, n_blk)
-    Wb = np.zeros((L.n_out, n_blk))
-    Wb[:, :L.n_in] = L.wb
-    return ev.add(matvec_partial(ev, b, Wf, d, t), matvec_partial(ev, s, Wb, d, t))
+    Wf = strided(fused_weights(L, L.n_in), S, L.g + L.k, n_blk)
+    Wb = strided(L.wb, S, 1, n_blk)
+    return ev.add(matvec_partial(ev, b, Wf, d, t, S), matvec_partial(ev, s, Wb, d, t, S))
 
 
-def layer_forward(ev, xs, L, n_blk, first):
-    """xs: the first layer's chunk ciphertexts (see chunk_bounds), else [x]."""
+def layer_forward(ev, xs, L, n_blk, first, S=1):
+    """xs: the first layer's chunk ciphertexts (see chunk_bounds), else [x];
+    n_blk: the previous output period (later layers).  Returns the output and
+    its period d S."""
     d = pow2ceil(L.n_out)
     if first:
-        bounds = chunk_bounds(L, ev.ctx.p.slots)
-        parts = [(sub_layer(L, lo, hi), hi - lo) for lo, hi in zip(bounds[:-1], bounds[1:])]
+        bounds = chunk_bounds(L, ev.ctx.p.slots, S)
+        parts = [(sub_layer(L, lo, hi), (hi - lo) * S) for lo, hi in zip(bounds[:-1], bounds[1:])]
     else:
         parts = [(L, n_blk)]
     if len(xs) != len(parts):
         raise ValueError("layer takes %d input ciphertexts, got %d" % (len(parts), len(xs)))
     z = None
     for x, (Lc, nb) in zip(xs, parts):
-        zc = layer_part(ev, x, Lc, nb, first, d)
+        zc = layer_part(ev, x, Lc, nb, first, d, S)
         z = zc if z is None else ev.add(z, zc)
-    return fold(ev, z, d), d
+    return fold(ev, z, d * S), d * S
 
 
-def eval_kan(ev, ct, layers, refresh=None):
-    """Run the layers on ct: one ciphertext (input in slots [0, n_in)) or the
+def eval_kan(ev, ct, layers, refresh=None, S=1):
+    """Run the layers on ct: one ciphertext (input in slots [0, n_in S)) or the
     list of the first layer's chunk ciphertexts (chunk c holds features
-    [b_c, b_{c+1}) in slots [0, b_{c+1} - b_c)).  `refresh`, if given, is
-    called between layers with the ciphertext and returns a fresh one at the
-    top level (the client-aided stand-in for bootstrapping)."""
+    [b_c, b_{c+1}) in slots [0, (b_{c+1} - b_c) S)); with S vectors per
+    ciphertext, feature i of vector s is in slot i S + s, and output o of
+    vector s comes out in slot o S + s.  `refresh`, if given, is called
+    between layers with the ciphertext and returns a fresh one at the top
+    level (the client-aided stand-in for bootstrapping)."""
     xs = list(ct) if isinstance(ct, (list, tuple)) else [ct]
-    n_blk = layers[0].n_in
+    n_blk = 0
     for li, L in enumerate(layers):
         if li > 0 and refresh is not None:
             xs = [refresh(xs[0], li)]
-        x, n_blk = layer_forward(ev, xs, L, n_blk, li == 0)
+        x, n_blk = layer_forward(ev, xs, L, n_blk, li == 0, S)
         xs = [x]
     return xs[0]
 
 
-def rotation_steps(layers, slots):
+def rotation_steps(layers, slots, S=1):
     """Every rotation amount the circuit uses (for key generation)."""
     steps = set()
-    n_blk = layers[0].n_in
+    n_blk = 0
     for li, L in enumerate(layers):
         d = pow2ceil(L.n_out)
         if li == 0:
-            bounds = chunk_bounds(L, slots)
-            for nb in set(hi - lo for lo, hi in zip(bounds[:-1], bounds[1:])):
+            bounds = chunk_bounds(L, slots, S)
+            for nb in set((hi - lo) * S for lo, hi in zip(bounds[:-1], bounds[1:])):
                 for j in range(1, clog2(L.g + 2 * L.k) + 1):
                     steps.add(-nb * (1 << (j - 1)))
                 steps.add(nb)
         else:
             steps.add(n_blk)
         b1, g1 = bsgs_split(d)
-        steps.update(range(1, b1))
-        steps.update(gi * b1 for gi in range(1, g1))
+        steps.update(bi * S for bi in range(1, b1))
+        steps.update(gi * b1 * S for gi in range(1, g1))
         s = slots // 2
-        while s >= d:
+        while s >= d * S:
             steps.add(s)
             s //= 2
-        n_blk = d
+        n_blk = d * S
     return sorted(steps)

@@ -28,11 +28,13 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
 {
     if (!d || d->n_layers < 1 || !d->layers) throw HeError(-1, "model: empty description");
     const long slots = ctx->N / 2;
-    long n_blk = d->layers[0].n_in;
+    S = d->samples_per_ct <= 0 ? 1 : d->samples_per_ct;
+    if ((S & (S - 1)) != 0 || S > slots) throw HeError(-1, "model: samples per ciphertext must be a power of two");
+    long n_blk = 0;
     for (int li = 0; li < d->n_layers; li++) {
         const he_kan_layer &s = d->layers[li];
         if (s.n_in < 1 || s.n_out < 1 || s.g < 1 || s.k < 0) throw HeError(-1, "model: bad layer shape");
-        if (li > 0 && s.n_in > n_blk) throw HeError(-1, "model: layer widths do not chain");
+        if (li > 0 && (long)s.n_in * S > n_blk) throw HeError(-1, "model: layer widths do not chain");
         if (!s.knots || !s.wb || !s.ws || !s.c || !s.silu_coeffs || s.silu_degree < 1 || s.comp_stages < 1 ||
             !s.comp_stage_len || !s.comp_coeffs || !(s.silu_hi > s.silu_lo))
             throw HeError(-1, "model: missing layer data");
@@ -55,43 +57,44 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
             L.comp.emplace_back(s.comp_coeffs + off, s.comp_coeffs + off + len);
             off += len;
         }
-        if (L.d > slots) throw HeError(-4, "model: n_out exceeds N/2 slots");
+        if (L.d * S > slots) throw HeError(-4, "model: n_out S exceeds N/2 slots");
         // packing: the first layer makes 2^ceil(log2(g+2k)) copies of its input
-        // (Algorithm 1); when n_in copies do not fit the slots the input comes
-        // as the fewest feature chunks that do, sizes as equal as possible
-        // (chunk c = features [c n_in / nc, (c+1) n_in / nc)); later layers
-        // need (g+2k) blocks of the previous output period
-        int nc = 1;
+        // (Algorithm 1); when n_in S copies do not fit the slots the input comes
+        // as feature chunks, each as wide as the copies allow (cap =
+        // slots / 2^ceil(log2(g+2k)) / S features), the last one the rest;
+        // later layers need (g+2k) blocks of the previous output period
+        long cap = s.n_in;
         if (li == 0) {
-            const long copies = pow2ceil(r - 1);
-            nc = (int)std::max(1l, ((long)s.n_in * copies + slots - 1) / slots);
-            if (nc > s.n_in) throw HeError(-4, "model: g+2k copies of one input exceed N/2 slots");
+            cap = slots / pow2ceil(r - 1) / S;
+            if (cap < 1) throw HeError(-4, "model: g+2k copies of one input exceed N/2 slots");
         } else if ((long)(r - 1) * n_blk > slots) {
             throw HeError(-4, "model: n_in (g+2k) exceeds N/2 slots");
         }
-        for (int pc = 0; pc < nc; pc++) {
+        for (long lo = 0; lo < s.n_in; lo += cap) {
             Part P;
-            P.lo = (int)((long)pc * s.n_in / nc);
-            P.n_in = (int)((long)(pc + 1) * s.n_in / nc) - P.lo;
-            P.n_blk = li == 0 ? P.n_in : n_blk;
-            if (li == 0 && pow2ceil(r - 1) * P.n_blk > slots) throw HeError(-4, "model: chunk exceeds N/2 slots");
-            // fused weights W_f[o][m n_blk + i] = w_s[o][i] c[o][i][m]  (W' P with
-            // the Algorithm 3 permutation: column j_c = m n_i + i of W_f is column
-            // j_r = i (g+k) + m of W'), and W_b[o][i], over the part's inputs
-            P.Wf.assign((size_t)s.n_out * nb * P.n_blk, 0.0);
-            P.Wb.assign((size_t)s.n_out * P.n_blk, 0.0);
+            P.lo = (int)lo;
+            P.n_in = (int)std::min(cap, (long)s.n_in - lo);
+            P.width = (long)P.n_in * S;
+            P.n_blk = li == 0 ? P.width : n_blk;
+            // fused weights W_f[o][m][i] = w_s[o][i] c[o][i][m] (W' P with the
+            // Algorithm 3 permutation: column j_c = m n_i + i of W_f is column
+            // j_r = i (g+k) + m of W'), and W_b[o][i], over the part's inputs;
+            // their slot layout (block m at m n_blk, input i of vector v at
+            // i S + v) is formed when the diagonals are
+            P.Wf.assign((size_t)s.n_out * nb * P.n_in, 0.0);
+            P.Wb.assign((size_t)s.n_out * P.n_in, 0.0);
             for (int o = 0; o < s.n_out; o++)
                 for (int i = 0; i < P.n_in; i++) {
                     const size_t e = (size_t)o * s.n_in + P.lo + i;
                     const double ws = s.ws[e];
-                    P.Wb[(size_t)o * P.n_blk + i] = s.wb[e];
+                    P.Wb[(size_t)o * P.n_in + i] = s.wb[e];
                     for (int m = 0; m < nb; m++)
-                        P.Wf[(size_t)o * nb * P.n_blk + (size_t)m * P.n_blk + i] = ws * s.c[e * nb + m];
+                        P.Wf[((size_t)o * nb + m) * P.n_in + i] = ws * s.c[e * nb + m];
                 }
             L.parts.push_back(std::move(P));
         }
         layers.push_back(std::move(L));
-        n_blk = layers.back().d;
+        n_blk = layers.back().d * S;
     }
     // rotation steps
     std::vector<long> st;
@@ -102,11 +105,12 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
                 for (int j = 1; j <= clog2i(L.g + 2 * L.k); j++) st.push_back(-P.n_blk * (1l << (j - 1)));
             st.push_back(P.n_blk);
         }
+        const long D = L.d * S;
         int b1 = 1 << ((clog2i(L.d) + 1) / 2);
         long g1 = L.d / b1;
-        for (int b = 1; b < b1; b++) st.push_back(b);
-        for (long gi = 1; gi < g1; gi++) st.push_back(gi * b1);
-        for (long s = slots / 2; s >= L.d; s /= 2) st.push_back(s);
+        for (int b = 1; b < b1; b++) st.push_back(b * S);
+        for (long gi = 1; gi < g1; gi++) st.push_back(gi * b1 * S);
+        for (long s = slots / 2; s >= D; s /= 2) st.push_back(s);
     }
     std::sort(st.begin(), st.end());
     st.erase(std::unique(st.begin(), st.end()), st.end());
@@ -284,7 +288,7 @@ struct Eval {
     {
         std::vector<double> v(c.N / 2, 0.0);
         for (int mb = 0; mb < hi - lo; mb++)
-            for (int i = 0; i < P.n_in; i++) v[(size_t)mb * P.n_blk + i] = L.knots[lo + mb - 1];
+            for (long i = 0; i < P.width; i++) v[(size_t)mb * P.n_blk + i] = L.knots[lo + mb - 1];
         return v;
     }
 
@@ -314,7 +318,7 @@ struct Eval {
             std::vector<double> t3 = coltile(L, P, j + 2, r + 1), t4 = coltile(L, P, 2, r - j + 1);
             std::vector<double> A1(S2, 0.0), A2n(S2, 0.0), c1(S2, 0.0), c2(S2, 0.0);
             for (int mb = 0; mb < nbl; mb++)
-                for (int i = 0; i < P.n_in; i++) {
+                for (long i = 0; i < P.width; i++) {
                     size_t s = (size_t)mb * P.n_blk + i;
                     double a1 = 1.0 / (t2[s] - t1[s]);
                     double a2 = 1.0 / (t3[s] - t4[s]);
@@ -337,29 +341,45 @@ struct Eval {
         return b;
     }
 
-    // generalised diagonal i of M (rows x cols) for output period d, pre-rotated by sh
-    static std::vector<double> diag(const std::vector<double> &M, long rows, long cols, long d, long i, long sh,
-                                    long slots)
+    // Weights of one linear layer in the slot layout: output o of vector v in
+    // row o S + v; column m n_blk + i S + v holds input i of vector v in
+    // block m (W (x) I_S over nblocks blocks of n_in inputs).  W is
+    // [rows][nblocks][n_in].
+    struct SlotMatrix {
+        const std::vector<double> &W;
+        long n_out, nblocks, n_in, n_blk, S;
+        double at(long r, long col) const
+        {
+            const long o = r / S, v = r % S, mb = col / n_blk, rem = col % n_blk, i = rem / S;
+            if (o >= n_out || mb >= nblocks || i >= n_in || rem % S != v) return 0.0;
+            return W[((size_t)o * nblocks + mb) * n_in + i];
+        }
+    };
+
+    // generalised diagonal i of M for output period D, pre-rotated by sh
+    // (np.roll): entry j is M[j mod D][(j + i) mod slots]
+    static std::vector<double> diag(const SlotMatrix &M, long D, long i, long sh, long slots)
     {
         std::vector<double> v(slots, 0.0);
         for (long j = 0; j < slots; j++) {
-            long jj = ((j - sh) % slots + slots) % slots;  // np.roll(diag, sh)
-            long rr = jj % d, cc = (jj + i) % slots;
-            if (rr < rows && cc < cols) v[j] = M[(size_t)rr * cols + cc];
+            long jj = ((j - sh) % slots + slots) % slots;
+            v[j] = M.at(jj % D, (jj + i) % slots);
         }
         return v;
     }
 
-    Ct matvec(const Ct &x, const std::vector<double> &M, long rows, long cols, long d, int t,
-              const std::string &tag)
+    // z = sum_{i<d} diag_{iS} * rot(x, iS) by baby-step giant-step at level t;
+    // with S vectors per ciphertext only the multiples of S are non-zero
+    // diagonals of W (x) I_S, so the d terms use rotations by multiples of S
+    Ct matvec(const Ct &x, const SlotMatrix &M, long d, int t, const std::string &tag)
     {
-        const long slots = c.N / 2;
+        const long slots = c.N / 2, S = m.S, D = d * S;
         const int b1 = 1 << ((clog2i(d) + 1) / 2);
         const long g1 = d / b1;
         Ct xd = c.mod_drop(x, t + 1);
         // baby steps share one ModUp (hoisting; same residues as separate rotations)
         std::vector<long> bsteps;
-        for (int bi = 0; bi < b1; bi++) bsteps.push_back(bi);
+        for (int bi = 0; bi < b1; bi++) bsteps.push_back(bi * S);
         std::vector<Ct> rots = c.rotate_many(xd, bsteps, k);
         Ct z;
         bool have = false;
@@ -373,13 +393,13 @@ struct Eval {
                 if (it != m.pt_cache.end()) {
                     pp = &it->second;
                 } else {
-                    std::vector<double> dv = diag(M, rows, cols, d, gi * b1 + bi, gi * b1, slots);
+                    std::vector<double> dv = diag(M, D, (gi * b1 + bi) * S, gi * b1 * S, slots);
                     pp = &vec(key, t, xd.level, dv);
                 }
                 terms.push_back({&rots[bi], pp});
             }
             Ct inner = c.lincomb(terms, t);
-            if (gi) inner = c.rotate(inner, gi * b1, k);
+            if (gi) inner = c.rotate(inner, gi * b1 * S, k);
             if (!have) {
                 z = inner;
                 have = true;
@@ -409,8 +429,8 @@ struct Eval {
         int t = std::min(b.level, s.level) - 1;
         if (t < 0) throw HeError(-3, "layer does not fit the level budget");
         const long nb = L.g + L.k;
-        Ct zf = matvec(b, P.Wf, L.n_out, nb * P.n_blk, L.d, t, tag + "F");
-        Ct zb = matvec(s, P.Wb, L.n_out, P.n_blk, L.d, t, tag + "B");
+        Ct zf = matvec(b, SlotMatrix{P.Wf, L.n_out, nb, P.n_in, P.n_blk, m.S}, L.d, t, tag + "F");
+        Ct zb = matvec(s, SlotMatrix{P.Wb, L.n_out, 1, P.n_in, P.n_blk, m.S}, L.d, t, tag + "B");
         return c.add(zf, zb);
     }
 
@@ -426,7 +446,7 @@ struct Eval {
                 throw HeError(-1, "input ciphertexts differ in level or batch size");
         Ct z = part(xs[0], li, 0);
         for (size_t pc = 1; pc < xs.size(); pc++) z = c.add(z, part(xs[pc], li, pc));
-        return fold(z, L.d);
+        return fold(z, L.d * m.S);
     }
 };
 

@@ -12,9 +12,10 @@ namespace hk {
 // The inputs [lo, lo + n_in) of a layer that arrive in one ciphertext.
 struct Part {
     int lo, n_in;
-    long n_blk;              // slots per input block (first layer: n_in; later: previous d)
-    std::vector<double> Wf;  // n_out x (g+k) n_blk, ColTile column order
-    std::vector<double> Wb;  // n_out x n_blk
+    long n_blk;              // slots per input block (first layer: n_in S; later: previous d S)
+    long width;              // valid slots per block: n_in S
+    std::vector<double> Wf;  // n_out x (g+k) x n_in: W_f[o][m][i] = w_s[o][i] c[o][i][m]
+    std::vector<double> Wb;  // n_out x n_in
 };
 
 struct LayerC {
@@ -32,6 +33,7 @@ struct LayerC {
 struct Model {
     Ctx *ctx;
     bool refresh;
+    long S;  // input vectors per ciphertext
     std::vector<LayerC> layers;
     std::vector<long> steps;
     std::unordered_map<std::string, Pt> pt_cache;   // Montgomery NTT plaintexts for lincombs

@@ -41,7 +41,8 @@ class he_kan_layer(ctypes.Structure):
 
 
 class he_kan_desc(ctypes.Structure):
-    _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(he_kan_layer))]
+    _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(he_kan_layer)),
+                ("samples_per_ct", ctypes.c_int32)]
 
 
 _lib = None
@@ -241,16 +242,26 @@ class Context:
         return out
 
     # -- inference ------------------------------------------------------------
-    def compile(self, layers, refresh=False):
-        return Model(self, layers, refresh)
+    def compile(self, layers, refresh=False, samples=1):
+        return Model(self, layers, refresh, samples)
 
     def encrypt_input(self, model, keys, x, seed):
         """Encrypt one request's input in the model's layout: one ciphertext per
-        input chunk (he_model_input_chunks), chunk c with seed + c."""
+        input chunk (he_model_input_chunks), chunk c with seed + c.  For a model
+        with S > 1 vectors per ciphertext x is (S, n_in) and feature i of vector
+        s goes to slot i S + s."""
         b = model.input_chunks()
-        x = _arr(x, np.float64)
-        cts = [self.encrypt(keys, x[lo:hi], seed + c) for c, (lo, hi) in enumerate(zip(b[:-1], b[1:]))]
+        S = model.samples
+        x = np.asarray(x, np.float64).reshape(S, -1)
+        cts = [self.encrypt(keys, x[:, lo:hi].T.reshape(-1), seed + c)
+               for c, (lo, hi) in enumerate(zip(b[:-1], b[1:]))]
         return cts[0] if len(cts) == 1 else cts
+
+    def decrypt_output(self, model, keys, ct, n_out):
+        """The outputs of every vector of a request: (S, n_out) (output o of
+        vector s is slot o S + s)."""
+        S = model.samples
+        return self.decrypt(keys, ct, n_out * S).reshape(n_out, S).T
 
     def eval_kan(self, model, keys, ct):
         """ct: one ciphertext, or the list of a request's input chunks."""
@@ -331,8 +342,9 @@ class Ciphertext:
 
 
 class Model:
-    def __init__(self, ctx, layers, refresh=False):
+    def __init__(self, ctx, layers, refresh=False, samples=1):
         self.ctx = ctx
+        self.samples = samples
         keep = []
         arr = (he_kan_layer * len(layers))()
         for i, L in enumerate(layers):
@@ -345,7 +357,7 @@ class Model:
             arr[i] = he_kan_layer(L.n_in, L.n_out, L.g, L.k, _ptr(knots), _ptr(wb), _ptr(ws), _ptr(c),
                                   len(sc) - 1, _ptr(sc), L.silu_lo, L.silu_hi, len(L.comp), _ptr(lens), _ptr(cc),
                                   float(getattr(L, "comp_prescale", 0.0)))
-        desc = he_kan_desc(len(layers), arr)
+        desc = he_kan_desc(len(layers), arr, samples)
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.he_model_compile(ctx.h, ctypes.byref(desc), 1 if refresh else 0, ctypes.byref(h)))
         self.h = h

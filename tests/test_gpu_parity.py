@@ -305,7 +305,7 @@ def test_kan_chunked_first_layer_bit_exact(tiny):
                                [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
     model = ctx.compile(layers, refresh=True)
     bounds = model.input_chunks()
-    assert bounds == circuit.chunk_bounds(layers[0], octx.p.slots) == [0, 192, 384]
+    assert bounds == circuit.chunk_bounds(layers[0], octx.p.slots) == [0, 256, 384]
     steps = model.rotation_steps()
     assert steps == circuit.rotation_steps(layers, octx.p.slots)
     note("tinychunk keygen", len(steps))
@@ -343,7 +343,7 @@ def test_kan_cifar_chunked_accuracy_and_batch(image):
     layers = kan.compile_model(raw, synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
                                [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
     model = ctx.compile(layers)
-    assert model.input_chunks() == [0, 1536, 3072]
+    assert model.input_chunks() == [0, 2048, 3072]
     steps = model.rotation_steps()
     assert steps == circuit.rotation_steps(layers, octx.p.slots)
     note("cifar keygen", len(steps))

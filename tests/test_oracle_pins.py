@@ -506,16 +506,16 @@ def test_circuit_on_simulator_equals_fp64_kan(name):
 
 
 def test_chunk_bounds():
-    """Fewest chunks whose repeat-packed footprint fits, sizes within one."""
+    """Chunks filled to the slot capacity of the repeat-packed input, the last
+    one taking the rest."""
     L = kan.Layer(3072, 128, 8, 3, np.zeros(15), np.zeros((128, 3072)), np.zeros((128, 3072)),
                   np.zeros((128, 3072, 11)), np.zeros(4), 0.0, 1.0, 1.0)
-    assert circuit.chunk_bounds(L, 32768) == [0, 1536, 3072]        # 3072 x 16 = 49152 slots
+    assert circuit.chunk_bounds(L, 32768) == [0, 2048, 3072]        # 16 copies of 2048 inputs = 32768 slots
     assert circuit.chunk_bounds(L, 65536) == [0, 3072]
     L.n_in = 785
-    b = circuit.chunk_bounds(L, 4096)                                # 785 x 16 / 4096 -> 4 chunks
-    assert b[0] == 0 and b[-1] == 785 and len(b) == 5
-    assert max(hi - lo for lo, hi in zip(b[:-1], b[1:])) * 16 <= 4096
-    assert max(hi - lo for lo, hi in zip(b[:-1], b[1:])) - min(hi - lo for lo, hi in zip(b[:-1], b[1:])) <= 1
+    assert circuit.chunk_bounds(L, 4096) == [0, 256, 512, 768, 785]
+    L.n_in = 512
+    assert circuit.chunk_bounds(L, 4096) == [0, 256, 512]
 
 
 def test_oracle_he_kan_tiny_matches_fp64_circuit():
@@ -534,3 +534,40 @@ def test_oracle_he_kan_tiny_matches_fp64_circuit():
                            lambda c, li: ev.encrypt(ev.decrypt(c, prm.slots), 100 + li))
     y = ev.decrypt(out, 1)
     assert abs(y[0] - kan.he_friendly_kan(x[None], layers)[0, 0]) < 1e-2
+
+
+def test_strided_weights_equal_kronecker_product():
+    """The slot layout of S vectors per ciphertext: strided(W, S) = W (x) I_S,
+    and it maps the packed vectors to the packed products."""
+    rng = np.random.default_rng(11)
+    M = rng.normal(size=(5, 7))
+    X = rng.normal(size=(4, 7))
+    K = circuit.strided(M, 4)
+    assert (K == np.kron(M, np.eye(4))).all()
+    assert np.allclose(K @ circuit.pack_samples(X, 4), circuit.pack_samples(X @ M.T, 4))
+    # blocks with padding: block m of width 3 at m n_blk, n_blk = 16 >= 3 * 4
+    M2 = rng.normal(size=(2, 6))
+    K2 = circuit.strided(M2, 4, 2, 16)
+    assert (K2[:, :12] == np.kron(M2[:, :3], np.eye(4))).all() and (K2[:, 12:16] == 0).all()
+    assert (K2[:, 16:28] == np.kron(M2[:, 3:], np.eye(4))).all() and (K2[:, 28:] == 0).all()
+
+
+@pytest.mark.parametrize("name,S", [("tiny", 32), ("formula", 64)])
+def test_packed_vectors_on_simulator_equal_fp64_kan(name, S):
+    """S input vectors in one ciphertext (feature i of vector s in slot i S + s):
+    every vector's output equals the FP64 HE-friendly network, within the
+    level budget, with the rotation steps the circuit declares."""
+    wl = synth.WORKLOADS[name]
+    raw = synth.raw_weights(wl)
+    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * len(raw),
+                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+    X = synth.inputs(wl, S)
+    sim = SlotSim(1 << (wl.logN - 1))
+    assert circuit.chunk_bounds(layers[0], sim.ctx.p.slots, S) == [0, wl.shape[0]]
+    refresh = (lambda c, li: SimCt(wl.L, c.v)) if wl.refresh else None
+    out = circuit.eval_kan(sim, sim.fresh(circuit.pack_samples(X, S), wl.L), layers, refresh, S)
+    assert out.level >= 0
+    want = kan.he_friendly_kan(X, layers)                     # (S, n_out)
+    got = out.v[:wl.shape[-1] * S].reshape(wl.shape[-1], S).T
+    assert np.abs(got - want).max() < 1e-8 * max(1, np.abs(want).max())
+    assert set(circuit.rotation_steps(layers, sim.ctx.p.slots, S)) == sim.rot_steps
