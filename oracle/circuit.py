@@ -7,15 +7,18 @@ Per KANLayer (Method, Figure 2 structure) on a ciphertext x whose slots hold
 the layer input in blocks of n_blk slots:
   * first layer: Fast Repeat Packing (Algorithm 1) without the mask, because
     a fresh ciphertext already holds zeros outside [0, n_i);
-  * spline branch: PolyComp on x_rep - g1 and g2 - x_rep, their product, and k
-    rounds of Algorithm 2 (each round relinearises once after summing both
-    tensor products);
-  * SiLU branch: the fitted Chebyshev polynomial by baby-step giant-step;
+  * spline branch: PolyComp on x_rep - g1 and g2 - x_rep (the second taken
+    from the first by one rotation when the input holds one more block: the
+    composite is odd), their product, and k rounds of Algorithm 2 (each round
+    relinearises once after summing both tensor products);
+  * SiLU branch: the fitted Chebyshev polynomial by baby-step giant-step, on
+    the repeat-packed input with its coefficients masked to block g+k (the
+    first block the bases leave free);
   * both linear layers (W_b after SiLU, the fused W_f = W' P after the basis)
-    by the hybrid diagonal method with baby-step giant-step rotations, their
-    partial sums added and folded over all slots, so the output is periodic
-    with period d = next power of two >= n_out (the next layer's repeat
-    packing comes for free);
+    as one product of [W_f | W_b] with the sum of bases and masked SiLU, by
+    the hybrid diagonal method with baby-step giant-step rotations, folded
+    over all slots, so the output is periodic with period d = next power of
+    two >= n_out (the next layer's repeat packing comes for free);
   * a first layer whose repeat-packed footprint n_i 2^ceil(log2(g+2k))
     exceeds the slot count takes its input as several ciphertexts, one per
     chunk of consecutive features: each chunk is packed and expanded on its
@@ -99,8 +102,9 @@ class ChebEval:
     largest giant below its length, and every sub-result lands exactly on the
     level its consumer needs (leaf lincombs target that level directly)."""
 
-    def __init__(self, ev, x, coeffs, lo, hi):
+    def __init__(self, ev, x, coeffs, lo, hi, mask=None):
         self.ev = ev
+        self.mask = mask  # None, or a slot vector every coefficient is multiplied by
         self.c = [float(v) for v in coeffs]
         deg = len(self.c) - 1
         m = clog2(deg + 1)
@@ -143,16 +147,20 @@ class ChebEval:
             ok_q = t + 1 <= self.T[G].level and self.feasible(q, t + 1)
         return ok_q and self.feasible(r, t)
 
+    def coef(self, v):
+        return v if self.mask is None else v * self.mask
+
     def rec(self, c, t):
         ev = self.ev
         n = len(c)
         if n <= self.b:
-            terms = [(self.T[i], c[i]) for i in range(1, n)]
-            return ev.add_const(ev.lincomb(terms, t), c[0])
+            terms = [(self.T[i], self.coef(c[i])) for i in range(1, n)]
+            s = ev.lincomb(terms, t)
+            return ev.add_const(s, c[0]) if self.mask is None else ev.add_vec(s, c[0] * self.mask)
         G = self.giant(n)
         q, r = cheb_split(c, G)
         if len(q) == 1:
-            prod = ev.lincomb([(self.T[G], q[0])], t)
+            prod = ev.lincomb([(self.T[G], self.coef(q[0]))], t)
         else:
             qc = self.rec(q, t + 1)
             prod = ev.mul(qc, ev.level_down(self.T[G], t + 1))
@@ -167,8 +175,10 @@ class ChebEval:
         return self.rec(self.c, t)
 
 
-def cheb_eval(ev, x, coeffs, lo, hi):
-    return ChebEval(ev, x, coeffs, lo, hi).run()
+def cheb_eval(ev, x, coeffs, lo, hi, mask=None):
+    """The series on every slot of x; with a mask, every coefficient (and so
+    the result) is multiplied slot-wise by it, at no extra depth."""
+    return ChebEval(ev, x, coeffs, lo, hi, mask).run()
 
 
 # --------------------------------------------------------------------------
@@ -198,22 +208,35 @@ def block_mask(nblocks, n_blk, n_in, slots):
     return v
 
 
-def bspline_basis(ev, xr, L, n_blk, width=None):
+def bspline_basis(ev, xr, L, n_blk, width=None, shared=False):
     """Algorithm 2 on the repeat-packed ciphertext xr; `width` valid slots per
-    block (n_in S when S vectors share the ciphertext)."""
+    block (n_in S when S vectors share the ciphertext).  shared: xr holds the
+    input in g+2k+1 blocks, and the second comparison is taken from the first
+    one: the composite is odd, so S((t_{m+2} - x)/2R) = 1 - S((x - t_{m+2})/2R),
+    which is 1 minus the first comparison of block m+1 (one rotation instead
+    of a second PolyComp)."""
     slots = ev.ctx.p.slots
     width = L.n_in if width is None else width
     r = L.g + 2 * L.k + 1
-    g1 = coltile(L.knots, 1, r, n_blk, width, slots)
-    g2 = coltile(L.knots, 2, r + 1, n_blk, width, slots)
-    if L.comp_prescale:
-        # (x - g1) / 2R and (g2 - x) / 2R in one rescale each
-        sc = L.comp_prescale
-        x1 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, sc)], xr.level - 1), -(g1 * sc)), L.comp)
-        x2 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, -sc)], xr.level - 1), g2 * sc), L.comp)
+    if shared:
+        g1 = coltile(L.knots, 1, r + 1, n_blk, width, slots)      # t_1 .. t_r in blocks 0 .. r-1
+        if L.comp_prescale:
+            sc = L.comp_prescale
+            x1 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, sc)], xr.level - 1), -(g1 * sc)), L.comp)
+        else:
+            x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
+        x2 = ev.add_const(ev.mul_int(ev.rotate(x1, n_blk), -1), 1.0)
     else:
-        x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
-        x2 = polycomp(ev, ev.add_vec(ev.mul_int(xr, -1), g2), L.comp)
+        g1 = coltile(L.knots, 1, r, n_blk, width, slots)
+        g2 = coltile(L.knots, 2, r + 1, n_blk, width, slots)
+        if L.comp_prescale:
+            # (x - g1) / 2R and (g2 - x) / 2R in one rescale each
+            sc = L.comp_prescale
+            x1 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, sc)], xr.level - 1), -(g1 * sc)), L.comp)
+            x2 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, -sc)], xr.level - 1), g2 * sc), L.comp)
+        else:
+            x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
+            x2 = polycomp(ev, ev.add_vec(ev.mul_int(xr, -1), g2), L.comp)
     b = ev.mul(x1, x2)
     for j in range(1, L.k + 1):
         nbl = r - j - 1
@@ -321,16 +344,34 @@ def sub_layer(L, lo, hi):
     return dataclasses.replace(L, n_in=hi - lo, wb=L.wb[:, lo:hi], ws=L.ws[:, lo:hi], c=L.c[:, lo:hi])
 
 
+def shared_comparison(L, n_blk, first, slots):
+    """Whether the repeat-packed input holds g+2k+1 blocks (the first layer's
+    2^ceil(log2(g+2k)) copies, or a periodic hidden input), so that
+    bspline_basis can share one comparison between both of its inputs."""
+    r = L.g + 2 * L.k + 1
+    blocks = (1 << clog2(L.g + 2 * L.k)) if first else slots // n_blk
+    return blocks >= r and r * n_blk <= slots
+
+
 def layer_part(ev, x, L, n_blk, first, d, S=1):
     """Both branches of one layer on one input ciphertext, before the fold.
-    n_blk: slots per input block (n_in S for a first layer)."""
+    n_blk: slots per input block (n_in S for a first layer).  The SiLU branch
+    is evaluated on the repeat-packed input with its coefficients masked to
+    block g+k, the first block the g+k bases leave free, and added to the
+    bases, so one product with [W_f | W_b] (g+k+1 column blocks) computes both
+    linear layers."""
+    slots = ev.ctx.p.slots
+    nb = L.g + L.k
+    width = L.n_in * S
     xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
-    b = bspline_basis(ev, xr, L, n_blk, L.n_in * S)
-    s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
+    b = bspline_basis(ev, xr, L, n_blk, width, shared_comparison(L, n_blk, first, slots))
+    mask = np.zeros(slots)
+    mask[nb * n_blk:nb * n_blk + width] = 1.0
+    s = cheb_eval(ev, xr, L.silu_coeffs, L.silu_lo, L.silu_hi, mask)
     t = min(b.level, s.level) - 1
-    Wf = strided(fused_weights(L, L.n_in), S, L.g + L.k, n_blk)
-    Wb = strided(L.wb, S, 1, n_blk)
-    return ev.add(matvec_partial(ev, b, Wf, d, t, S), matvec_partial(ev, s, Wb, d, t, S))
+    z = ev.add(ev.mod_drop(b, t + 1), ev.mod_drop(s, t + 1))
+    W = strided(np.hstack([fused_weights(L, L.n_in), L.wb]), S, nb + 1, n_blk)
+    return matvec_partial(ev, z, W, d, t, S)
 
 
 def layer_forward(ev, xs, L, n_blk, first, S=1):

@@ -78,18 +78,17 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
             P.n_blk = li == 0 ? P.width : n_blk;
             // fused weights W_f[o][m][i] = w_s[o][i] c[o][i][m] (W' P with the
             // Algorithm 3 permutation: column j_c = m n_i + i of W_f is column
-            // j_r = i (g+k) + m of W'), and W_b[o][i], over the part's inputs;
-            // their slot layout (block m at m n_blk, input i of vector v at
-            // i S + v) is formed when the diagonals are
-            P.Wf.assign((size_t)s.n_out * nb * P.n_in, 0.0);
-            P.Wb.assign((size_t)s.n_out * P.n_in, 0.0);
+            // j_r = i (g+k) + m of W'), then W_b[o][i] as block g+k, over the
+            // part's inputs; their slot layout (block m at m n_blk, input i of
+            // vector v at i S + v) is formed when the diagonals are
+            P.W.assign((size_t)s.n_out * (nb + 1) * P.n_in, 0.0);
             for (int o = 0; o < s.n_out; o++)
                 for (int i = 0; i < P.n_in; i++) {
                     const size_t e = (size_t)o * s.n_in + P.lo + i;
                     const double ws = s.ws[e];
-                    P.Wb[(size_t)o * P.n_in + i] = s.wb[e];
                     for (int m = 0; m < nb; m++)
-                        P.Wf[((size_t)o * nb + m) * P.n_in + i] = ws * s.c[e * nb + m];
+                        P.W[((size_t)o * (nb + 1) + m) * P.n_in + i] = ws * s.c[e * nb + m];
+                    P.W[((size_t)o * (nb + 1) + nb) * P.n_in + i] = s.wb[e];
                 }
             L.parts.push_back(std::move(P));
         }
@@ -193,7 +192,32 @@ struct Eval {
         Eval &e;
         std::map<long, Ct> T;
         long b;
+        const std::vector<double> *mask = nullptr;  // every coefficient times this slot vector
+        std::string tag;                            // plaintext cache key prefix (masked leaves)
         Cheb(Eval &e_) : e(e_) {}
+        std::vector<double> masked(double v) const
+        {
+            std::vector<double> z(*mask);
+            for (auto &x : z) x *= v;
+            return z;
+        }
+        // sum_i T_i cf_i (i in 1..n-1) at level t, plus cf_0 when with_const;
+        // `path` names the leaf for the plaintext cache
+        Ct leaf(const std::vector<std::pair<const Ct *, double>> &terms, double c0, bool with_const, int t,
+                const std::string &path)
+        {
+            if (!mask) {
+                Ct s = e.lin_scalar(terms, t);
+                return with_const ? e.c.add_const(s, c0) : s;
+            }
+            std::vector<std::pair<const Ct *, const Pt *>> v;
+            for (size_t i = 0; i < terms.size(); i++)
+                v.push_back({terms[i].first,
+                             &e.vec(tag + path + "/" + std::to_string(i), t, terms[i].first->level,
+                                    masked(terms[i].second))});
+            Ct s = e.c.lincomb(v, t);
+            return with_const ? e.c.add_plain(s, e.addvec(tag + path + "/c", t, masked(c0))) : s;
+        }
         long giant(long n) const
         {
             long G = b;
@@ -223,31 +247,36 @@ struct Eval {
             bool okq = q.size() == 1 ? t <= T.at(G).level - 1 : (t + 1 <= T.at(G).level && feasible(q, t + 1));
             return okq && feasible(r, t);
         }
-        Ct rec(const std::vector<double> &cf, int t)
+        Ct rec(const std::vector<double> &cf, int t, const std::string &path = "")
         {
             long n = (long)cf.size();
             if (n <= b) {
                 std::vector<std::pair<const Ct *, double>> terms;
                 for (long i = 1; i < n; i++) terms.push_back({&T.at(i), cf[i]});
-                return e.c.add_const(e.lin_scalar(terms, t), cf[0]);
+                return leaf(terms, cf[0], true, t, path);
             }
             long G = giant(n);
             std::vector<double> q, r;
             split(cf, G, q, r);
             Ct prod;
             if (q.size() == 1) {
-                prod = e.lin_scalar({{&T.at(G), q[0]}}, t);
+                prod = leaf({{&T.at(G), q[0]}}, 0.0, false, t, path + "g");
             } else {
-                Ct qc = rec(q, t + 1);
+                Ct qc = rec(q, t + 1, path + "q");
                 prod = e.mul(qc, e.c.level_down(T.at(G), t + 1));
             }
-            return e.c.add(prod, rec(r, t));
+            return e.c.add(prod, rec(r, t, path + "r"));
         }
     };
 
-    Ct cheb_eval(const Ct &x, const std::vector<double> &cf, double lo, double hi)
+    // the series on every slot of x; with a mask every coefficient (and so the
+    // result) is multiplied slot-wise by it, at no extra depth
+    Ct cheb_eval(const Ct &x, const std::vector<double> &cf, double lo, double hi,
+                 const std::vector<double> *mask = nullptr, const std::string &tag = "")
     {
         Cheb ch(*this);
+        ch.mask = mask;
+        ch.tag = tag;
         const long deg = (long)cf.size() - 1;
         const int mm = clog2i(deg + 1);
         ch.b = 1l << ((mm + 1) / 2);
@@ -292,11 +321,30 @@ struct Eval {
         return v;
     }
 
-    Ct bspline(const Ct &xr, const LayerC &L, const Part &P, const std::string &tag)
+    // Algorithm 2 on the repeat-packed xr.  shared: xr holds the input in
+    // g+2k+1 blocks and the second comparison is taken from the first: the
+    // composite is odd, so S((t_{m+2} - x)/2R) = 1 - S((x - t_{m+2})/2R), which
+    // is 1 minus the first comparison of block m+1 (one rotation instead of a
+    // second PolyComp)
+    Ct bspline(const Ct &xr, const LayerC &L, const Part &P, const std::string &tag, bool shared)
     {
         const int r = L.g + 2 * L.k + 1;
-        std::vector<double> g1 = coltile(L, P, 1, r), g2 = coltile(L, P, 2, r + 1);
         Ct x1, x2;
+        if (shared) {
+            std::vector<double> g1 = coltile(L, P, 1, r + 1);
+            if (L.prescale != 0.0) {
+                const double sc = L.prescale;
+                for (auto &v : g1) v = -(v * sc);
+                const int l1 = xr.level - 1;
+                x1 = polycomp(c.add_plain(lin_scalar({{&xr, sc}}, l1), addvec(tag + "g1s", l1, g1)), L.comp);
+            } else {
+                for (auto &v : g1) v = -v;
+                x1 = polycomp(c.add_plain(xr, addvec(tag + "g1", xr.level, g1)), L.comp);
+            }
+            x2 = c.add_const(c.mul_int(c.rotate(x1, P.n_blk, k), -1), 1.0);
+            return bases(mul(x1, x2), xr, L, P, tag);
+        }
+        std::vector<double> g1 = coltile(L, P, 1, r), g2 = coltile(L, P, 2, r + 1);
         if (L.prescale != 0.0) {
             // (x - g1) / 2R and (g2 - x) / 2R, one rescale each (Algorithm 2)
             const double sc = L.prescale;
@@ -310,7 +358,13 @@ struct Eval {
             x1 = polycomp(c.add_plain(xr, addvec(tag + "g1", xr.level, g1)), L.comp);
             x2 = polycomp(c.add_plain(c.mul_int(xr, -1), addvec(tag + "g2", xr.level, g2)), L.comp);
         }
-        Ct b = mul(x1, x2);
+        return bases(mul(x1, x2), xr, L, P, tag);
+    }
+
+    // the k recursion rounds of Algorithm 2 from the order-0 bases b
+    Ct bases(Ct b, const Ct &xr, const LayerC &L, const Part &P, const std::string &tag)
+    {
+        const int r = L.g + 2 * L.k + 1;
         const size_t S2 = c.N / 2;
         for (int j = 1; j <= L.k; j++) {
             const int nbl = r - j - 1;
@@ -423,15 +477,24 @@ struct Eval {
         const Part &P = L.parts[pc];
         const std::string tag =
             "L" + std::to_string(li) + "/" + (L.parts.size() > 1 ? "c" + std::to_string(pc) + "/" : "");
+        const long slots = c.N / 2, nb = L.g + L.k;
+        const int r = L.g + 2 * L.k + 1;
         Ct xr = li == 0 ? repeat_pack(x, P.n_blk, clog2i(L.g + 2 * L.k)) : x;
-        Ct b = bspline(xr, L, P, tag);
-        Ct s = cheb_eval(x, L.silu, L.silu_lo, L.silu_hi);
+        // blocks of the input xr holds: the first layer's 2^ceil(log2(g+2k))
+        // copies, or a periodic hidden input
+        const long blocks = li == 0 ? pow2ceil(r - 1) : slots / P.n_blk;
+        const bool shared = blocks >= r && (long)r * P.n_blk <= slots;
+        Ct b = bspline(xr, L, P, tag, shared);
+        // SiLU on the repeat-packed input, masked to block g+k (the first block
+        // the g+k bases leave free), added to the bases: one product with
+        // [W_f | W_b] computes both linear layers
+        std::vector<double> mask(slots, 0.0);
+        for (long i = 0; i < P.width; i++) mask[(size_t)nb * P.n_blk + i] = 1.0;
+        Ct s = cheb_eval(xr, L.silu, L.silu_lo, L.silu_hi, &mask, tag + "S");
         int t = std::min(b.level, s.level) - 1;
         if (t < 0) throw HeError(-3, "layer does not fit the level budget");
-        const long nb = L.g + L.k;
-        Ct zf = matvec(b, SlotMatrix{P.Wf, L.n_out, nb, P.n_in, P.n_blk, m.S}, L.d, t, tag + "F");
-        Ct zb = matvec(s, SlotMatrix{P.Wb, L.n_out, 1, P.n_in, P.n_blk, m.S}, L.d, t, tag + "B");
-        return c.add(zf, zb);
+        Ct z = c.add(c.mod_drop(b, t + 1), c.mod_drop(s, t + 1));
+        return matvec(z, SlotMatrix{P.W, L.n_out, nb + 1, P.n_in, P.n_blk, m.S}, L.d, t, tag + "W");
     }
 
     // the parts' partial sums share one layout: add them, then fold once

@@ -14,8 +14,9 @@ struct Part {
     int lo, n_in;
     long n_blk;              // slots per input block (first layer: n_in S; later: previous d S)
     long width;              // valid slots per block: n_in S
-    std::vector<double> Wf;  // n_out x (g+k) x n_in: W_f[o][m][i] = w_s[o][i] c[o][i][m]
-    std::vector<double> Wb;  // n_out x n_in
+    // n_out x (g+k+1) x n_in: blocks m < g+k hold W_f[o][m][i] = w_s[o][i] c[o][i][m],
+    // block g+k holds W_b[o][i] (both linear layers as one product)
+    std::vector<double> W;
 };
 
 struct LayerC {
