@@ -191,35 +191,39 @@ def repeat_pack(ev, x, n_blk, nlog):
     return x
 
 
-def coltile(knots, lo, hi, n_blk, n_in, slots):
+def coltile(knots, lo, hi, n_blk, n_in, slots, period=None):
     """ColTile(G, lo, hi) of the knot matrix G (row i = t_1..t_r for every
     input): block m (m < hi-lo) holds t_{lo+m} in slots m n_blk + i, i < n_in;
-    every other slot is 0.  lo, hi are 1-based as in Algorithm 2."""
-    v = np.zeros(slots)
+    every other slot is 0; the layout repeats every `period` slots (default:
+    once).  lo, hi are 1-based as in Algorithm 2."""
+    period = slots if period is None else period
+    v = np.zeros(period)
     for m in range(hi - lo):
         v[m * n_blk:m * n_blk + n_in] = knots[lo + m - 1]
-    return v
+    return np.tile(v, slots // period)
 
 
-def block_mask(nblocks, n_blk, n_in, slots):
-    v = np.zeros(slots, bool)
+def block_mask(nblocks, n_blk, n_in, slots, period=None):
+    period = slots if period is None else period
+    v = np.zeros(period, bool)
     for m in range(nblocks):
         v[m * n_blk:m * n_blk + n_in] = True
-    return v
+    return np.tile(v, slots // period)
 
 
-def bspline_basis(ev, xr, L, n_blk, width=None, shared=False):
+def bspline_basis(ev, xr, L, n_blk, width=None, shared=False, period=None):
     """Algorithm 2 on the repeat-packed ciphertext xr; `width` valid slots per
     block (n_in S when S vectors share the ciphertext).  shared: xr holds the
     input in g+2k+1 blocks, and the second comparison is taken from the first
     one: the composite is odd, so S((t_{m+2} - x)/2R) = 1 - S((x - t_{m+2})/2R),
     which is 1 minus the first comparison of block m+1 (one rotation instead
-    of a second PolyComp)."""
+    of a second PolyComp).  period: the block layout repeats every `period`
+    slots (the input must repeat likewise)."""
     slots = ev.ctx.p.slots
     width = L.n_in if width is None else width
     r = L.g + 2 * L.k + 1
     if shared:
-        g1 = coltile(L.knots, 1, r + 1, n_blk, width, slots)      # t_1 .. t_r in blocks 0 .. r-1
+        g1 = coltile(L.knots, 1, r + 1, n_blk, width, slots, period)  # t_1 .. t_r in blocks 0 .. r-1
         if L.comp_prescale:
             sc = L.comp_prescale
             x1 = polycomp(ev, ev.add_vec(ev.lincomb([(xr, sc)], xr.level - 1), -(g1 * sc)), L.comp)
@@ -227,8 +231,8 @@ def bspline_basis(ev, xr, L, n_blk, width=None, shared=False):
             x1 = polycomp(ev, ev.add_vec(xr, -g1), L.comp)
         x2 = ev.add_const(ev.mul_int(ev.rotate(x1, n_blk), -1), 1.0)
     else:
-        g1 = coltile(L.knots, 1, r, n_blk, width, slots)
-        g2 = coltile(L.knots, 2, r + 1, n_blk, width, slots)
+        g1 = coltile(L.knots, 1, r, n_blk, width, slots, period)
+        g2 = coltile(L.knots, 2, r + 1, n_blk, width, slots, period)
         if L.comp_prescale:
             # (x - g1) / 2R and (g2 - x) / 2R in one rescale each
             sc = L.comp_prescale
@@ -240,11 +244,11 @@ def bspline_basis(ev, xr, L, n_blk, width=None, shared=False):
     b = ev.mul(x1, x2)
     for j in range(1, L.k + 1):
         nbl = r - j - 1
-        t1 = coltile(L.knots, 1, r - j, n_blk, width, slots)
-        t2 = coltile(L.knots, j + 1, r, n_blk, width, slots)
-        t3 = coltile(L.knots, j + 2, r + 1, n_blk, width, slots)
-        t4 = coltile(L.knots, 2, r - j + 1, n_blk, width, slots)
-        msk = block_mask(nbl, n_blk, width, slots)
+        t1 = coltile(L.knots, 1, r - j, n_blk, width, slots, period)
+        t2 = coltile(L.knots, j + 1, r, n_blk, width, slots, period)
+        t3 = coltile(L.knots, j + 2, r + 1, n_blk, width, slots, period)
+        t4 = coltile(L.knots, 2, r - j + 1, n_blk, width, slots, period)
+        msk = block_mask(nbl, n_blk, width, slots, period)
         A1 = np.zeros(slots)
         A2 = np.zeros(slots)
         A1[msk] = 1.0 / (t2[msk] - t1[msk])
@@ -257,13 +261,15 @@ def bspline_basis(ev, xr, L, n_blk, width=None, shared=False):
     return b
 
 
-def diag_vector(M, d, i, slots):
-    """Generalised diagonal i of M (n_out x n_in) for output period d:
-    entry j is M[j mod d][(j+i) mod slots] when both indices are in range."""
+def diag_vector(M, d, i, slots, period=None):
+    """Generalised diagonal i of M (n_out x n_in) for output period d and an
+    input that repeats every `period` slots (default: slots): entry j is
+    M[j mod d][(j+i) mod period] when both indices are in range."""
+    period = slots if period is None else period
     n_out, n_in = M.shape
     j = np.arange(slots)
     r = j % d
-    c = (j + i) % slots
+    c = (j + i) % period
     v = np.zeros(slots)
     ok = (r < n_out) & (c < n_in)
     v[ok] = M[r[ok], c[ok]]
@@ -275,12 +281,13 @@ def bsgs_split(d):
     return b1, d // b1
 
 
-def matvec_partial(ev, x, M, d, t, S=1):
+def matvec_partial(ev, x, M, d, t, S=1, period=None):
     """z = sum_{i<d} diag_{iS} * rot(x, iS) at level t by baby-step giant-step:
     z = sum_gi rot( sum_bi rot(diag_{(gi b1 + bi) S}, -gi b1 S) * rot(x, bi S), gi b1 S ),
     diagonals of M taken with output period d S (for S = 1 every diagonal i < d;
     for M = W (x) I_S the others are zero).  x is mod-dropped to t+1 before
-    the baby-step rotations."""
+    the baby-step rotations.  If x repeats every `period` slots, so do the
+    diagonals, and z needs folding within one period only."""
     slots = ev.ctx.p.slots
     b1, g1 = bsgs_split(d)
     D = d * S
@@ -290,7 +297,7 @@ def matvec_partial(ev, x, M, d, t, S=1):
     for gi in range(g1):
         terms = []
         for bi in range(b1):
-            dv = np.roll(diag_vector(M, D, (gi * b1 + bi) * S, slots), gi * b1 * S)
+            dv = np.roll(diag_vector(M, D, (gi * b1 + bi) * S, slots, period), gi * b1 * S)
             terms.append((rots[bi], dv))
         inner = ev.lincomb(terms, t)
         if gi:
@@ -299,9 +306,10 @@ def matvec_partial(ev, x, M, d, t, S=1):
     return z
 
 
-def fold(ev, z, d):
-    """z <- z + rot(z, s) for s = slots/2, slots/4, ..., d (d: the output period)."""
-    s = ev.ctx.p.slots // 2
+def fold(ev, z, d, period=None):
+    """z <- z + rot(z, s) for s = period/2, period/4, ..., d (d: the output
+    period; period: the period of z, default slots)."""
+    s = (ev.ctx.p.slots if period is None else period) // 2
     while s >= d:
         z = ev.add(z, ev.rotate(z, s))
         s //= 2
@@ -353,6 +361,14 @@ def shared_comparison(L, n_blk, first, slots):
     return blocks >= r and r * n_blk <= slots
 
 
+def hidden_period(L, n_blk, slots):
+    """A hidden layer's input repeats every n_blk slots, so its whole block
+    layout (g+2k+1 blocks: the comparisons, the bases and the masked SiLU)
+    can repeat every P = next power of two of that many slots; the product
+    then repeats every P as well and the fold runs over one period."""
+    return min(slots, pow2ceil((L.g + 2 * L.k + 1) * n_blk))
+
+
 def layer_part(ev, x, L, n_blk, first, d, S=1):
     """Both branches of one layer on one input ciphertext, before the fold.
     n_blk: slots per input block (n_in S for a first layer).  The SiLU branch
@@ -363,15 +379,16 @@ def layer_part(ev, x, L, n_blk, first, d, S=1):
     slots = ev.ctx.p.slots
     nb = L.g + L.k
     width = L.n_in * S
+    period = slots if first else hidden_period(L, n_blk, slots)
     xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
-    b = bspline_basis(ev, xr, L, n_blk, width, shared_comparison(L, n_blk, first, slots))
-    mask = np.zeros(slots)
+    b = bspline_basis(ev, xr, L, n_blk, width, shared_comparison(L, n_blk, first, slots), period)
+    mask = np.zeros(period)
     mask[nb * n_blk:nb * n_blk + width] = 1.0
-    s = cheb_eval(ev, xr, L.silu_coeffs, L.silu_lo, L.silu_hi, mask)
+    s = cheb_eval(ev, xr, L.silu_coeffs, L.silu_lo, L.silu_hi, np.tile(mask, slots // period))
     t = min(b.level, s.level) - 1
     z = ev.add(ev.mod_drop(b, t + 1), ev.mod_drop(s, t + 1))
     W = strided(np.hstack([fused_weights(L, L.n_in), L.wb]), S, nb + 1, n_blk)
-    return matvec_partial(ev, z, W, d, t, S)
+    return matvec_partial(ev, z, W, d, t, S, period)
 
 
 def layer_forward(ev, xs, L, n_blk, first, S=1):
@@ -390,7 +407,8 @@ def layer_forward(ev, xs, L, n_blk, first, S=1):
     for x, (Lc, nb) in zip(xs, parts):
         zc = layer_part(ev, x, Lc, nb, first, d, S)
         z = zc if z is None else ev.add(z, zc)
-    return fold(ev, z, d * S), d * S
+    period = ev.ctx.p.slots if first else hidden_period(L, n_blk, ev.ctx.p.slots)
+    return fold(ev, z, d * S, period), d * S
 
 
 def eval_kan(ev, ct, layers, refresh=None, S=1):
@@ -428,7 +446,7 @@ def rotation_steps(layers, slots, S=1):
         b1, g1 = bsgs_split(d)
         steps.update(bi * S for bi in range(1, b1))
         steps.update(gi * b1 * S for gi in range(1, g1))
-        s = slots // 2
+        s = (slots if li == 0 else hidden_period(L, n_blk, slots)) // 2
         while s >= d * S:
             steps.add(s)
             s //= 2

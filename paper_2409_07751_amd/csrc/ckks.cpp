@@ -190,6 +190,37 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
     upload(twf_buf->p, (const u64 *)twf.data(), twf.size() * 2);
     T.ffw = (const TwF *)twf_buf->p;
     T.fiw = (const TwF *)twf_buf->p + (size_t)np * N;
+    // factored second-pass twiddles (LC = 8 stages over rows of 256 words)
+    {
+        const int LR = logN - 8, rows = 1 << LR;
+        std::vector<TwF> ab((size_t)2 * np * ((size_t)rows * 8 + 256), TwF{0.0, 0.0});
+        for (int dir = 0; dir < 2; dir++)
+            for (int i = 0; i < np; i++) {
+                const u64 m = mods[i];
+                const u64 *W = &tw[(size_t)((dir == 0 ? 0 : 2) * np + i) * N];
+                TwF *A = &ab[((size_t)dir * np + i) * rows * 8];
+                TwF *B = &ab[(size_t)2 * np * rows * 8 + ((size_t)dir * np + i) * 256];
+                for (int sp = 0; sp < 8; sp++) {
+                    const size_t base = (size_t)1 << (LR + sp);
+                    for (int r = 0; r < rows; r++) {
+                        const u64 a = W[base + ((size_t)r << sp)];
+                        A[(size_t)r * 8 + sp] = TwF{(double)a, (double)a / (double)m};
+                    }
+                    const u64 inv0 = hinv(W[base], m);
+                    for (int u = 0; u < (1 << sp); u++) {
+                        const u64 b = hmul(W[base + u], inv0, m);
+                        B[(1 << sp) - 1 + u] = TwF{(double)b, (double)b / (double)m};
+                    }
+                }
+            }
+        twab_buf = alloc(ab.size() * 2);
+        upload(twab_buf->p, (const u64 *)ab.data(), ab.size() * 2);
+        const TwF *abp = (const TwF *)twab_buf->p;
+        T.fa = abp;
+        T.ia = abp + (size_t)np * rows * 8;
+        T.fb = abp + (size_t)2 * np * rows * 8;
+        T.ib = T.fb + (size_t)np * 256;
+    }
     tw_buf = alloc(tw.size());
     upload(tw_buf->p, tw.data(), tw.size());
     T.pc = d_pc;
@@ -248,6 +279,7 @@ Ctx::~Ctx()
     pinv.reset();
     tw_buf.reset();
     twf_buf.reset();
+    twab_buf.reset();
     d_pc_buf.reset();
     pool.trim();
     if (own_stream && st) (void)hipStreamDestroy(st);

@@ -103,7 +103,7 @@ struct Ctx {
     hipStream_t st = nullptr;
     bool own_stream = false;
     Pool pool;
-    Buf d_pc_buf, tw_buf, twf_buf;
+    Buf d_pc_buf, tw_buf, twf_buf, twab_buf;
     const PrimeConst *d_pc = nullptr;
     NttTables T;
     std::map<int, KsTable> ks_cache;

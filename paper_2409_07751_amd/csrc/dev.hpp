@@ -51,6 +51,12 @@ struct NttTables {
     const u64 *fw, *fwp;   // psi^brv(k) and Shoup companions, [nprimes][N]
     const u64 *iw, *iwp;   // psi^-brv(k)
     const TwF *ffw, *fiw;  // the same twiddles as FP64 pairs, [nprimes][N]
+    // factors of the second-pass twiddles (the last 8 stages): entry
+    // 2^st + (r << s) + u, st = logN - 8 + s, is A(r, s) B(s, u) with
+    // A(r, s) = W[2^st + (r << s)] ([nprimes][rows][8]) and
+    // B(s, u) = W[2^st + u] / W[2^st] ([nprimes][256] at (1 << s) - 1 + u);
+    // forward (fa, fb) and inverse (ia, ib), FP64 pairs
+    const TwF *fa, *fb, *ia, *ib;
     int logN;
 };
 

@@ -92,6 +92,11 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
                 }
             L.parts.push_back(std::move(P));
         }
+        // a hidden layer's input repeats every n_blk slots, so its whole block
+        // layout (g+2k+1 blocks: comparisons, bases, masked SiLU) can repeat
+        // every next power of two of that many slots; the product then repeats
+        // likewise and the fold runs over one period
+        L.period = li == 0 ? slots : std::min(slots, pow2ceil((long)r * n_blk));
         layers.push_back(std::move(L));
         n_blk = layers.back().d * S;
     }
@@ -109,7 +114,7 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
         long g1 = L.d / b1;
         for (int b = 1; b < b1; b++) st.push_back(b * S);
         for (long gi = 1; gi < g1; gi++) st.push_back(gi * b1 * S);
-        for (long s = slots / 2; s >= D; s /= 2) st.push_back(s);
+        for (long s = L.period / 2; s >= D; s /= 2) st.push_back(s);
     }
     std::sort(st.begin(), st.end());
     st.erase(std::unique(st.begin(), st.end()), st.end());
@@ -312,12 +317,20 @@ struct Eval {
         return x;
     }
 
-    // ColTile(G, lo, hi): block mb (< hi-lo) holds t_{lo+mb} for the part's inputs
+    // copy the first `period` entries of v over the rest of it
+    static void tile(std::vector<double> &v, long period)
+    {
+        for (size_t j = (size_t)period; j < v.size(); j++) v[j] = v[j - period];
+    }
+
+    // ColTile(G, lo, hi): block mb (< hi-lo) holds t_{lo+mb} for the part's
+    // inputs, the layout repeated every L.period slots
     std::vector<double> coltile(const LayerC &L, const Part &P, int lo, int hi) const
     {
         std::vector<double> v(c.N / 2, 0.0);
         for (int mb = 0; mb < hi - lo; mb++)
             for (long i = 0; i < P.width; i++) v[(size_t)mb * P.n_blk + i] = L.knots[lo + mb - 1];
+        tile(v, L.period);
         return v;
     }
 
@@ -381,6 +394,10 @@ struct Eval {
                     c1[s] = -(t1[s] * a1);
                     c2[s] = t3[s] * a2;
                 }
+            tile(A1, L.period);
+            tile(A2n, L.period);
+            tile(c1, L.period);
+            tile(c2, L.period);
             const int lb = b.level;
             std::string jt = tag + "r" + std::to_string(j);
             const Pt &pA1 = vec(jt + "A1", lb, xr.level, A1);
@@ -410,14 +427,15 @@ struct Eval {
         }
     };
 
-    // generalised diagonal i of M for output period D, pre-rotated by sh
-    // (np.roll): entry j is M[j mod D][(j + i) mod slots]
-    static std::vector<double> diag(const SlotMatrix &M, long D, long i, long sh, long slots)
+    // generalised diagonal i of M for output period D and an input repeating
+    // every `period` slots, pre-rotated by sh (np.roll): entry j is
+    // M[j mod D][(j + i) mod period]
+    static std::vector<double> diag(const SlotMatrix &M, long D, long i, long sh, long slots, long period)
     {
         std::vector<double> v(slots, 0.0);
         for (long j = 0; j < slots; j++) {
             long jj = ((j - sh) % slots + slots) % slots;
-            v[j] = M.at(jj % D, (jj + i) % slots);
+            v[j] = M.at(jj % D, (jj + i) % period);
         }
         return v;
     }
@@ -425,7 +443,7 @@ struct Eval {
     // z = sum_{i<d} diag_{iS} * rot(x, iS) by baby-step giant-step at level t;
     // with S vectors per ciphertext only the multiples of S are non-zero
     // diagonals of W (x) I_S, so the d terms use rotations by multiples of S
-    Ct matvec(const Ct &x, const SlotMatrix &M, long d, int t, const std::string &tag)
+    Ct matvec(const Ct &x, const SlotMatrix &M, long d, int t, long period, const std::string &tag)
     {
         const long slots = c.N / 2, S = m.S, D = d * S;
         const int b1 = 1 << ((clog2i(d) + 1) / 2);
@@ -447,7 +465,7 @@ struct Eval {
                 if (it != m.pt_cache.end()) {
                     pp = &it->second;
                 } else {
-                    std::vector<double> dv = diag(M, D, (gi * b1 + bi) * S, gi * b1 * S, slots);
+                    std::vector<double> dv = diag(M, D, (gi * b1 + bi) * S, gi * b1 * S, slots, period);
                     pp = &vec(key, t, xd.level, dv);
                 }
                 terms.push_back({&rots[bi], pp});
@@ -464,9 +482,10 @@ struct Eval {
         return z;
     }
 
-    Ct fold(Ct z, long d)
+    // z <- z + rot(z, s) for s = period/2, ..., d
+    Ct fold(Ct z, long d, long period)
     {
-        for (long s = c.N / 4; s >= d; s /= 2) z = c.add(z, c.rotate(z, s, k));
+        for (long s = period / 2; s >= d; s /= 2) z = c.add(z, c.rotate(z, s, k));
         return z;
     }
 
@@ -490,11 +509,12 @@ struct Eval {
         // [W_f | W_b] computes both linear layers
         std::vector<double> mask(slots, 0.0);
         for (long i = 0; i < P.width; i++) mask[(size_t)nb * P.n_blk + i] = 1.0;
+        tile(mask, L.period);
         Ct s = cheb_eval(xr, L.silu, L.silu_lo, L.silu_hi, &mask, tag + "S");
         int t = std::min(b.level, s.level) - 1;
         if (t < 0) throw HeError(-3, "layer does not fit the level budget");
         Ct z = c.add(c.mod_drop(b, t + 1), c.mod_drop(s, t + 1));
-        return matvec(z, SlotMatrix{P.W, L.n_out, nb + 1, P.n_in, P.n_blk, m.S}, L.d, t, tag + "W");
+        return matvec(z, SlotMatrix{P.W, L.n_out, nb + 1, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "W");
     }
 
     // the parts' partial sums share one layout: add them, then fold once
@@ -509,7 +529,7 @@ struct Eval {
                 throw HeError(-1, "input ciphertexts differ in level or batch size");
         Ct z = part(xs[0], li, 0);
         for (size_t pc = 1; pc < xs.size(); pc++) z = c.add(z, part(xs[pc], li, pc));
-        return fold(z, L.d * m.S);
+        return fold(z, L.d * m.S, L.period);
     }
 };
 

@@ -21,7 +21,8 @@ struct Part {
 
 struct LayerC {
     int n_in, n_out, g, k;
-    long d;  // output period: next power of two >= n_out
+    long d;       // output period: next power of two >= n_out
+    long period;  // the block layout repeats every `period` slots (first layer: N/2)
     std::vector<double> knots, silu;
     double silu_lo, silu_hi;
     std::vector<std::vector<double>> comp;

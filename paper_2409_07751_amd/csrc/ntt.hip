@@ -456,11 +456,26 @@ __device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, cons
 // inside the transform; starting below 4q, sixteen stages that each add at
 // most 3q/4 keep every value within 16q <= 2^50.  Inverse: the sum of each
 // butterfly is reduced to |s| <= q/2 + 1, the difference stays within 8q.
+// Second-pass twiddle of stage s' = LC-1-LS-h from the block's factor tables
+// in LDS (shB: B(s', u) at (1 << s') - 1 + u; shA: A(line, s') at 8 line + s'):
+// W = A B mod q up to sign (|W| <= 3q/4), with its quotient constant W / q.
+__device__ __forceinline__ TwF tw_factored(const TwF *shA, const TwF *shB, int line, int sp, long i, double q,
+                                           double qi)
+{
+    const TwF a = shA[line * 8 + sp];
+    const TwF b = shB[(1 << sp) - 1 + (int)(i & ((1l << sp) - 1))];
+    TwF t;
+    t.w = mulm_fp(a.w, b.w, b.c, q);
+    t.c = t.w * qi;
+    return t;
+}
+
 template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT, class PB>
-__device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const IN &in,
-                                             const OUT &out, const PB &pre)
+__device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const TwF *shA,
+                                             const TwF *shB, const IN &in, const OUT &out, const PB &pre)
 {
     typedef PhaseIdx<LOGN, PASS, R, LS> I;
+    typedef NttGeo<LOGN> G;
     const double q = bk.pc->qd, qi = bk.pc->qinvd;
 #pragma unroll
     for (int it = 0; it < I::ITERS; it++) {
@@ -483,7 +498,10 @@ __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk
 #pragma unroll
                 for (int k = 0; k < (1 << R); k++) {
                     if (k & (1 << h)) continue;
-                    const TwF t = tw[ib + (k >> (h + 1))];
+                    const long idx = ib + (k >> (h + 1));
+                    const int sp = G::LC - 1 - LS - h;
+                    const TwF t = PASS == 2 ? tw_factored(shA, shB, ix.line, sp, idx - (1l << (G::LR + sp)), q, qi)
+                                            : tw[idx];
                     const double r = mulm_fp(x[k + (1 << h)], t.w, t.c, q);
                     const double a = x[k];
                     x[k] = a + r;
@@ -497,7 +515,10 @@ __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk
 #pragma unroll
                 for (int k = 0; k < (1 << R); k++) {
                     if (k & (1 << h)) continue;
-                    const TwF t = tw[ib + (k >> (h + 1))];
+                    const long idx = ib + (k >> (h + 1));
+                    const int sp = G::LC - 1 - LS - h;
+                    const TwF t = PASS == 2 ? tw_factored(shA, shB, ix.line, sp, idx - (1l << (G::LR + sp)), q, qi)
+                                            : tw[idx];
                     const double a = x[k], b = x[k + (1 << h)];
                     const double sm = a + b;
                     x[k] = __fma_rn(-rint(sm * qi), q, sm);
@@ -550,17 +571,17 @@ __device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, con
 }
 
 template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT, class PB>
-__device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const IN &in,
-                                              const OUT &out, const PB &pre)
+__device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const TwF *shA,
+                                              const TwF *shB, const IN &in, const OUT &out, const PB &pre)
 {
     typedef NttGeo<LOGN> G;
     constexpr int LP = PASS == 1 ? G::LR : G::LC;
     typedef PhasePlan<LP, FWD, PH> P;
     constexpr bool first = PH == 0, last = PH == P::NPH - 1;
-    ntt_phase_fp<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, tw, in, out, pre);
+    ntt_phase_fp<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, tw, shA, shB, in, out, pre);
     if constexpr (!last) {
         __syncthreads();
-        ntt_phases_fp<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, tw, in, out, pre);
+        ntt_phases_fp<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, tw, shA, shB, in, out, pre);
     }
 }
 
@@ -572,7 +593,10 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
 {
     typedef NttGeo<LOGN> G;
     constexpr int LT = PASS == 1 ? G::LR + G::LTC : G::LC + G::LRB;
-    __shared__ u64 sh[1 << LT];
+    static_assert(PASS == 1 || G::LC == 8, "second-pass twiddle factors assume 256-word rows");
+    // pass 2: the tile, then the twiddle factors B (256 pairs) and A (8 per row)
+    constexpr int TWW = PASS == 2 ? 2 * (256 + 8 * (1 << G::LRB)) : 0;
+    __shared__ u64 sh[(1 << LT) + TWW];
     // pass 1 runs the limbs of one polynomial back to back (limb fastest), so
     // blocks that read the same sources (basis conversion, rescale input) for
     // the same column tile share an XCD's L2; pass 2 runs the polynomials of
@@ -606,8 +630,18 @@ __global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm
     }
     if (bk.pc->fp) {
         const TwF *tw = (FWD ? T.ffw : T.fiw) + ((long)pi << LOGN);
-        ntt_phases_fp<LOGN, PASS, FWD, 0, IN, OUT>(reinterpret_cast<double *>(sh), bk, (long)blockIdx.x, tw, in, out,
-                                                   pre);
+        TwF *shB = reinterpret_cast<TwF *>(sh + (1 << LT)), *shA = shB + 256;
+        if constexpr (PASS == 2) {
+            // the prime's B table and the block's rows of A, read once into LDS
+            const TwF *gB = (FWD ? T.fb : T.ib) + (long)pi * 256;
+            const TwF *gA = (FWD ? T.fa : T.ia) + (((long)pi << G::LR) + ((long)blockIdx.x << G::LRB)) * 8;
+            const int t = (int)threadIdx.x;
+            shB[t] = gB[t];
+            if (t < 8 * (1 << G::LRB)) shA[t] = gA[t];
+            __syncthreads();
+        }
+        ntt_phases_fp<LOGN, PASS, FWD, 0, IN, OUT>(reinterpret_cast<double *>(sh), bk, (long)blockIdx.x, tw, shA,
+                                                   shB, in, out, pre);
         return;
     }
     const u64 *w = (FWD ? T.fw : T.iw) + ((long)pi << LOGN);
