@@ -369,20 +369,16 @@ Ct Ctx::add_const(const Ct &a, double c)
         it = const_cache.emplace(key, b).first;
     }
     Ct o = new_ct(a.level, a.nb);
-    launch_copy(ctset(o), ctset(a), N, st);
-    launch_add_const(d_pc, c0set(o), it->second->p, lmap(a.level + 1), N, st);
-    n_launch += 2;
+    launch_add_c0(d_pc, ctset(o), ctset(a), it->second->p, nullptr, lmap(a.level + 1), N, st);
+    n_launch++;
     return o;
 }
 
 Ct Ctx::add_plain(const Ct &a, const Buf &pt)
 {
     Ct o = new_ct(a.level, a.nb);
-    launch_copy(ctset(o), ctset(a), N, st);
-    PolySet o0 = c0set(o);
-    PolySet p0{pt->p, (long)N, 0, a.level + 1, a.nb};
-    launch_addsub(d_pc, o0, o0, p0, lmap(a.level + 1), 0, N, st);
-    n_launch += 2;
+    launch_add_c0(d_pc, ctset(o), ctset(a), nullptr, pt->p, lmap(a.level + 1), N, st);
+    n_launch++;
     return o;
 }
 
@@ -500,7 +496,7 @@ Ctx::ModUp Ctx::modup(const u64 *d, long ls, long es, int l, int nb)
 }
 
 void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
-                         long base_es, int base_mask, Ct &out)
+                         long base_es, int base_mask, Ct &out, const Ct *addend)
 {
     n_ks += m.nb;
     const int l = m.l, nb = m.nb, nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
@@ -518,6 +514,12 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
     Buf tmp = alloc((size_t)nb * 2 * nq * N);
     OutModdownArgs oa{acc->p, (long)N, (long)next * N, base, base_ls, base_es, (long)N, base_mask, galois, out.d(),
                       2l * N * nb, (long)N, pinv->p, pinv->p + L + 1};
+    if (addend) {
+        if (addend->level != l || addend->nb != nb) throw HeError(-1, "rotate_add: operand shapes differ");
+        oa.add = addend->d();
+        oa.als = 2l * N * nb;
+        oa.aes = 2l * N;
+    }
     launch_moddown(T, tmp->p, nq, alpha, 2 * nb, lm, yP->p, md_tab->p + 2 * alpha, L + 1, oa, st, &timer);
     n_launch += 6;
 }
@@ -530,10 +532,10 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
 // unpermuted and sigma is applied when ModDown reads the accumulator.
 // d: nb polynomials, limb stride ls, element stride es.
 void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
-                    const u64 *base, long base_ls, long base_es, int base_mask, Ct &out)
+                    const u64 *base, long base_ls, long base_es, int base_mask, Ct &out, const Ct *addend)
 {
     ModUp m = modup(d, ls, es, l, nb);
-    keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out);
+    keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out, addend);
 }
 
 Tensor Ctx::tensor(const Ct &a, const Ct &b)
@@ -590,6 +592,18 @@ std::vector<Ct> Ctx::rotate_many(const Ct &a, const std::vector<long> &steps, co
         out.push_back(o);
     }
     return out;
+}
+
+Ct Ctx::rotate_add(const Ct &a, long step, const Ct &addend, const Keys &k)
+{
+    u64 g = galois_elt(step);
+    if (g == 1) return add(addend, a);
+    auto it = k.galois.find(g);
+    if (it == k.galois.end()) throw HeError(-5, "no Galois key for rotation step " + std::to_string(step));
+    Ct o = new_ct(a.level, a.nb);
+    const long ls = 2l * N * a.nb, es = 2l * N;
+    keyswitch(a.d() + N, ls, es, a.level, a.nb, it->second, g, a.d(), ls, es, 1, o, &addend);
+    return o;
 }
 
 Ct Ctx::rotate(const Ct &a, long step, const Keys &k)

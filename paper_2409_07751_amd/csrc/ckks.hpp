@@ -147,6 +147,8 @@ struct Ctx {
     Ct relin_rescale(const Tensor &t, const Keys &k);
     Ct mul(const Ct &a, const Ct &b, const Keys &k);
     Ct rotate(const Ct &a, long step, const Keys &k);
+    // addend + rot(a, step) in one key switch (the addition runs in ModDown's last pass)
+    Ct rotate_add(const Ct &a, long step, const Ct &addend, const Keys &k);
     Ct lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t);
     Ct level_down(const Ct &a, int t);
 
@@ -159,10 +161,12 @@ struct Ctx {
         Buf ext;
     };
     ModUp modup(const u64 *d, long ls, long es, int l, int nb);
+    // out = base (masked components, component 0 through sigma) + KS(d) [+ addend]
     void keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
-                        long base_es, int base_mask, Ct &out);
+                        long base_es, int base_mask, Ct &out, const Ct *addend = nullptr);
     void keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
-                   const u64 *base, long base_ls, long base_es, int base_mask, Ct &out);
+                   const u64 *base, long base_ls, long base_es, int base_mask, Ct &out,
+                   const Ct *addend = nullptr);
     // batches of single ciphertexts at one level
     Ct pack(const std::vector<const Ct *> &cts);
     Ct unpack(const Ct &batch, int e);

@@ -87,9 +87,11 @@ void launch_addsub(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, Limb
 // out = a * k_l (per-limb scalar residue table ks[limb], Shoup table ksp)
 void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *ks, const u64 *ksp,
                        LimbMap lm, int N, hipStream_t s);
-// add a per-limb constant c[limb] to every coefficient of polynomial 0 of a
-// (an NTT-domain constant polynomial)
-void launch_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N, hipStream_t s);
+// out = a with component 0 of every ciphertext plus a per-limb constant c[limb]
+// (c non-null) or plus the plaintext polynomial p [limb][N] (c null);
+// out and a are ciphertext sets (polynomial 2 e + component)
+void launch_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *c, const u64 *p, LimbMap lm, int N,
+                   hipStream_t s);
 // tensor (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1), accumulate if acc
 void launch_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, bool acc,
                    hipStream_t s);
@@ -134,6 +136,10 @@ struct OutModdownArgs {
     u64 *out;
     long ols, ops;
     const u64 *pinv, *pinvp;
+    // optional addend (null: none), added unpermuted to both components:
+    // element e component c of limb i at add + i als + e aes + c N
+    const u64 *add = nullptr;
+    long als = 0, aes = 0;
 };
 // ModDown of npoly (= 2 nb) polynomials: out_p = base_p + (acc_p - NTT(BConv_{P->Q}(yP_p))) P^-1,
 // tmp [npoly][nq][N], yP [npoly][alpha][N]

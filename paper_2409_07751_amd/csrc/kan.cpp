@@ -313,7 +313,7 @@ struct Eval {
     // ---- packing and bases
     Ct repeat_pack(Ct x, long n_blk, int nlog)
     {
-        for (int j = 1; j <= nlog; j++) x = c.add(c.rotate(x, -n_blk * (1l << (j - 1)), k), x);
+        for (int j = 1; j <= nlog; j++) x = c.rotate_add(x, -n_blk * (1l << (j - 1)), x, k);
         return x;
     }
 
@@ -471,12 +471,11 @@ struct Eval {
                 terms.push_back({&rots[bi], pp});
             }
             Ct inner = c.lincomb(terms, t);
-            if (gi) inner = c.rotate(inner, gi * b1 * S, k);
             if (!have) {
-                z = inner;
+                z = gi ? c.rotate(inner, gi * b1 * S, k) : inner;
                 have = true;
             } else {
-                z = c.add(z, inner);
+                z = gi ? c.rotate_add(inner, gi * b1 * S, z, k) : c.add(z, inner);
             }
         }
         return z;
@@ -485,7 +484,7 @@ struct Eval {
     // z <- z + rot(z, s) for s = period/2, ..., d
     Ct fold(Ct z, long d, long period)
     {
-        for (long s = period / 2; s >= d; s /= 2) z = c.add(z, c.rotate(z, s, k));
+        for (long s = period / 2; s >= d; s /= 2) z = c.rotate_add(z, s, z, k);
         return z;
     }
 

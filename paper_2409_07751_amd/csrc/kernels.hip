@@ -56,19 +56,20 @@ void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *
     hipLaunchKernelGGL(k_mul_scalar, g, dim3(256), 0, s, pc, out, a, ks, ksp, lm, N);
 }
 
-__global__ void k_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N)
+__global__ void k_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *c, const u64 *p, LimbMap lm,
+                         int N)
 {
     EW_INDEX
-    u64 q = pc[lm.prime(limb)].q;
-    u64 *p = a.base + limb * a.lstride + poly * a.pstride + n;
-    *p = addm(*p, c[limb], q);
+    u64 x = a.base[limb * a.lstride + poly * a.pstride + n];
+    if ((poly & 1) == 0) x = addm(x, c ? c[limb] : p[(long)limb * N + n], pc[lm.prime(limb)].q);
+    out.base[limb * out.lstride + poly * out.pstride + n] = x;
 }
 
-// a: the c0 polynomials of a ciphertext batch
-void launch_add_const(const PrimeConst *pc, PolySet a, const u64 *c, LimbMap lm, int N, hipStream_t s)
+void launch_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *c, const u64 *p, LimbMap lm, int N,
+                   hipStream_t s)
 {
     dim3 g((N + 255) / 256, a.nl * a.npoly);
-    hipLaunchKernelGGL(k_add_const, g, dim3(256), 0, s, pc, a, c, lm, N);
+    hipLaunchKernelGGL(k_add_c0, g, dim3(256), 0, s, pc, out, a, c, p, lm, N);
 }
 
 // batch element e of d holds (d0, d1, d2) at +0, +N, +2N; of a and b (c0, c1)

@@ -269,8 +269,9 @@ struct OutRescaleFin {
     }
 };
 
-// ModDown tail: out_p = base_p + (acc_p - conv_p) * P^-1 for polynomial
-// p = 2 e + c; acc and base component 0 read through sigma_galois
+// ModDown tail: out_p = base_p + (acc_p - conv_p) * P^-1 [+ add_p] for
+// polynomial p = 2 e + c; acc and base component 0 read through sigma_galois,
+// the optional addend unpermuted (rotate-and-add in one pass)
 struct OutModdownFin {
     const u64 *acc;
     long acc_ls, acc_ps;
@@ -281,10 +282,13 @@ struct OutModdownFin {
     u64 *out;
     long ols, ops;
     const u64 *pinv, *pinvp;
-    static constexpr int NPRE = 2;
+    const u64 *add;
+    long als, aes;
+    static constexpr int NPRE = 3;
     double extra_words(int npoly, int nl) const
     {
-        return (double)npoly * nl + (double)(npoly / 2) * nl * ((mask & 1) + (mask >> 1 & 1));
+        return (double)npoly * nl * (add ? 2.0 : 1.0) +
+               (double)(npoly / 2) * nl * ((mask & 1) + (mask >> 1 & 1));
     }
     __device__ void fetch(const Blk &b, long g, u64 *pre) const
     {
@@ -292,6 +296,7 @@ struct OutModdownFin {
         pre[0] = acc[b.limb * acc_ls + b.poly * acc_ps + gp];
         const int e = b.poly >> 1, c = b.poly & 1;
         pre[1] = (mask >> c & 1) ? base[b.limb * bls + e * bes + c * bcs + (c == 0 ? gp : g)] : 0;
+        pre[2] = add ? add[b.limb * als + e * aes + ((long)c << b.logN) + g] : 0;
     }
     __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
     {
@@ -299,6 +304,7 @@ struct OutModdownFin {
         v = reduce4(v, q);
         u64 r = shoup(subm(pre[0], v, q), pinv[b.limb], pinvp[b.limb], q);
         if (mask >> (b.poly & 1) & 1) r = addm(r, pre[1], q);
+        if (add) r = addm(r, pre[2], q);
         out[b.limb * ols + b.poly * ops + g] = r;
     }
 };
@@ -837,7 +843,7 @@ void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, 
     in.hatf = nullptr;
     in.wide[0] = in.wide[1] = 0;
     OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.mask, a.galois, a.out, a.ols, a.ops,
-                    a.pinv, a.pinvp};
+                    a.pinv, a.pinvp, a.add, a.als, a.aes};
     NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
 }
 
