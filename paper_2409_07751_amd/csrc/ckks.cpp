@@ -274,6 +274,7 @@ Ctx::~Ctx()
     ks_cache.clear();
     md_tab.reset();
     rescale_inv.clear();
+    rescale_add.clear();
     const_cache.clear();
     int_cache.clear();
     pinv.reset();
@@ -333,7 +334,7 @@ Ct Ctx::sub(const Ct &a, const Ct &b)
     return o;
 }
 
-Ct Ctx::mul_int(const Ct &a, long k)
+const Buf &Ctx::int_factor(long k)
 {
     auto it = int_cache.find((int)k);
     if (it == int_cache.end()) {
@@ -347,15 +348,36 @@ Ct Ctx::mul_int(const Ct &a, long k)
         upload(b->p, v.data(), v.size());
         it = int_cache.emplace((int)k, b).first;
     }
+    return it->second;
+}
+
+Ct Ctx::mul_int(const Ct &a, long k)
+{
+    const Buf &f = int_factor(k);
     Ct o = new_ct(a.level, a.nb);
-    launch_mul_scalar(d_pc, ctset(o), ctset(a), it->second->p, it->second->p + L + 1, lmap(a.level + 1), N, st);
+    launch_mul_scalar(d_pc, ctset(o), ctset(a), f->p, f->p + L + 1, lmap(a.level + 1), N, st);
     n_launch++;
     return o;
 }
 
-Ct Ctx::add_const(const Ct &a, double c)
+Ct Ctx::affine(const Ct &a, long k, const double *c, const Buf *pt)
 {
-    double sc = S[a.level];
+    const u64 *kf = nullptr, *kfp = nullptr;
+    if (k != 1) {
+        const Buf &f = int_factor(k);
+        kf = f->p;
+        kfp = f->p + L + 1;
+    }
+    const u64 *cr = c ? const_residues(*c, S[a.level]) : nullptr;
+    Ct o = new_ct(a.level, a.nb);
+    launch_add_c0(d_pc, ctset(o), ctset(a), kf, kfp, cr, pt ? (*pt)->p : nullptr, lmap(a.level + 1), N, st);
+    n_launch++;
+    return o;
+}
+
+// residues over every Q prime of the constant c encoded at scale sc (cached)
+const u64 *Ctx::const_residues(double c, double sc)
+{
     u64 kc, ks;
     std::memcpy(&kc, &c, 8);
     std::memcpy(&ks, &sc, 8);
@@ -368,8 +390,14 @@ Ct Ctx::add_const(const Ct &a, double c)
         upload(b->p, v.data(), v.size());
         it = const_cache.emplace(key, b).first;
     }
+    return it->second->p;
+}
+
+Ct Ctx::add_const(const Ct &a, double c)
+{
+    const u64 *cr = const_residues(c, S[a.level]);
     Ct o = new_ct(a.level, a.nb);
-    launch_add_c0(d_pc, ctset(o), ctset(a), it->second->p, nullptr, lmap(a.level + 1), N, st);
+    launch_add_c0(d_pc, ctset(o), ctset(a), nullptr, nullptr, cr, nullptr, lmap(a.level + 1), N, st);
     n_launch++;
     return o;
 }
@@ -377,7 +405,7 @@ Ct Ctx::add_const(const Ct &a, double c)
 Ct Ctx::add_plain(const Ct &a, const Buf &pt)
 {
     Ct o = new_ct(a.level, a.nb);
-    launch_add_c0(d_pc, ctset(o), ctset(a), nullptr, pt->p, lmap(a.level + 1), N, st);
+    launch_add_c0(d_pc, ctset(o), ctset(a), nullptr, nullptr, nullptr, pt->p, lmap(a.level + 1), N, st);
     n_launch++;
     return o;
 }
@@ -391,24 +419,50 @@ Ct Ctx::mod_drop(const Ct &a, int l) const
 }
 
 // ------------------------------------------------------------------ rescale
-const Buf &Ctx::rescale_table(int l)
+const Buf &Ctx::rescale_table(int l, long k)
 {
-    auto it = rescale_inv.find(l);
+    auto it = rescale_inv.find(std::make_pair(l, k));
     if (it != rescale_inv.end()) return it->second;
     std::vector<u64> v(2 * l);
     for (int i = 0; i < l; i++) {
-        v[i] = hinv(q[l] % q[i], q[i]);
+        const long r = k % (long)q[i];
+        const u64 km = r < 0 ? (u64)(r + (long)q[i]) : (u64)r;
+        v[i] = hmul(hinv(q[l] % q[i], q[i]), km, q[i]);
         v[l + i] = shoup_of(v[i], q[i]);
     }
     Buf b = alloc(std::max<size_t>(v.size(), 1));
     if (l) upload(b->p, v.data(), v.size());
-    return rescale_inv.emplace(l, b).first->second;
+    return rescale_inv.emplace(std::make_pair(l, k), b).first->second;
 }
 
 // Rescale with rounding (divide by q_l, drop limb l): the dropped limb goes to
 // coefficient form; the forward transforms of ([c_l + h] - h) mod q_i and the
 // final (c_i - t_i) q_l^-1 run inside one fused NTT.
-Ct Ctx::rescale(const Ct &a)
+Ct Ctx::rescale(const Ct &a) { return rescale_affine(a, 1, nullptr); }
+
+// per limb i < l: the constant c at scale S[l-1] divided by k q_l^-1 (mod q_i), so
+// that adding it before the rescale's final product adds c to the result
+const u64 *Ctx::rescale_addend(int l, long k, double c)
+{
+    u64 kc;
+    std::memcpy(&kc, &c, 8);
+    auto key = std::make_tuple(l, k, kc);
+    auto it = rescale_add.find(key);
+    if (it != rescale_add.end()) return it->second->p;
+    std::vector<u64> cr(L + 1), v(std::max(l, 1), 0);
+    encode_const_rns(c, S[l - 1], q.data(), L + 1, cr.data());
+    for (int i = 0; i < l; i++) {
+        const long r = k % (long)q[i];
+        const u64 km = r < 0 ? (u64)(r + (long)q[i]) : (u64)r;
+        if (km == 0) throw HeError(-1, "rescale: factor divisible by a prime");
+        v[i] = hmul(hmul(cr[i], q[l] % q[i], q[i]), hinv(km, q[i]), q[i]);
+    }
+    Buf b = alloc(v.size());
+    upload(b->p, v.data(), v.size());
+    return rescale_add.emplace(key, b).first->second->p;
+}
+
+Ct Ctx::rescale_affine(const Ct &a, long k, const double *c)
 {
     const int l = a.level, np = 2 * a.nb;
     if (l < 1) throw HeError(-3, "rescale: no level left");
@@ -418,9 +472,10 @@ Ct Ctx::rescale(const Ct &a)
                      a.d() + (size_t)l * 2 * N * a.nb, 2l * N * a.nb, (long)N, 0, nullptr, nullptr, st, &timer);
     Buf tmp = alloc((size_t)l * np * N);
     Ct o = new_ct(l - 1, a.nb);
-    const Buf &inv = rescale_table(l);
+    const Buf &inv = rescale_table(l, k);
+    const u64 *cadd = c ? rescale_addend(l, k, *c) : nullptr;
     launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
-                       (long)N, inv->p, inv->p + l, L1, st, &timer);
+                       (long)N, inv->p, inv->p + l, cadd, L1, st, &timer);
     n_launch += 4;
     return o;
 }
@@ -560,16 +615,21 @@ void Ctx::tensor_acc(Tensor &t, const Ct &a, const Ct &b)
     n_launch++;
 }
 
-Ct Ctx::relin_rescale(const Tensor &t, const Keys &k)
+Ct Ctx::relin_rescale(const Tensor &t, const Keys &k, long mul, const double *cadd)
 {
     Ct c = new_ct(t.level, t.nb);
     const u64 *tb = t.buf->p;
     const long ls = 3l * N * t.nb, es = 3l * N;
     keyswitch(tb + 2 * (size_t)N, ls, es, t.level, t.nb, k.relin, 0, tb, ls, es, 3, c);
-    return rescale(c);
+    return rescale_affine(c, mul, cadd);
 }
 
 Ct Ctx::mul(const Ct &a, const Ct &b, const Keys &k) { return relin_rescale(tensor(a, b), k); }
+
+Ct Ctx::mul_affine(const Ct &a, const Ct &b, const Keys &keys, long k, const double *c)
+{
+    return relin_rescale(tensor(a, b), keys, k, c);
+}
 
 std::vector<Ct> Ctx::rotate_many(const Ct &a, const std::vector<long> &steps, const Keys &k)
 {
@@ -671,7 +731,7 @@ Pt Ctx::vec_pt(const double *z, size_t n, double scale, int nl)
 // (mod-drop), multiplied by its plaintext (encoded by the caller at
 // S[t] q_{t+1} / S[level_i]), summed with one REDC per coefficient, and
 // rescaled once.
-Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t)
+Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t, const double *c)
 {
     if (terms.empty()) throw HeError(-1, "lincomb: no terms");
     const int nl = t + 2, nb = terms[0].first->nb;
@@ -703,7 +763,7 @@ Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int
         }
         n_launch++;
     }
-    return rescale(acc);
+    return rescale_affine(acc, 1, c);
 }
 
 Ct Ctx::level_down(const Ct &a, int t)

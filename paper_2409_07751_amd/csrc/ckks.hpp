@@ -3,6 +3,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -107,7 +108,8 @@ struct Ctx {
     const PrimeConst *d_pc = nullptr;
     NttTables T;
     std::map<int, KsTable> ks_cache;
-    std::map<int, Buf> rescale_inv;  // per level l: [2][l] inv, invp
+    std::map<std::pair<int, long>, Buf> rescale_inv;  // per (level l, factor k): [2][l] k q_l^-1, Shoup
+    std::map<std::tuple<int, long, u64>, Buf> rescale_add;  // per (l, k, constant bits): [l] pre-rescale addend
     Buf pinv;                        // [2][L+1] P^-1 mod q_i and Shoup
     Buf md_tab;                      // [2][alpha] P-limb INTT scale, then [alpha][L+1] P->Q constants
     std::map<std::pair<u64, u64>, Buf> const_cache;
@@ -140,16 +142,25 @@ struct Ctx {
     Ct mul_int(const Ct &a, long k);
     Ct add_const(const Ct &a, double c);
     Ct add_plain(const Ct &a, const Buf &pt_ntt);  // pt in NTT standard form over >= level+1 limbs
+    // k a [+ *c | + *pt] in one pass; same residues as mul_int then add_const / add_plain
+    Ct affine(const Ct &a, long k, const double *c, const Buf *pt);
     Ct mod_drop(const Ct &a, int l) const;
     Ct rescale(const Ct &a);
+    // k rescale(a) [+ c]: the integer factor and the constant (at the result's
+    // scale) are applied in the rescale's last pass; same residues as
+    // add_const(mul_int(rescale(a), k), c)
+    Ct rescale_affine(const Ct &a, long k, const double *c);
     Tensor tensor(const Ct &a, const Ct &b);
     void tensor_acc(Tensor &t, const Ct &a, const Ct &b);
-    Ct relin_rescale(const Tensor &t, const Keys &k);
+    Ct relin_rescale(const Tensor &t, const Keys &k, long mul = 1, const double *c = nullptr);
     Ct mul(const Ct &a, const Ct &b, const Keys &k);
+    // k (a b) [+ c] with the factor and constant folded into the rescale
+    Ct mul_affine(const Ct &a, const Ct &b, const Keys &keys, long k, const double *c);
     Ct rotate(const Ct &a, long step, const Keys &k);
     // addend + rot(a, step) in one key switch (the addition runs in ModDown's last pass)
     Ct rotate_add(const Ct &a, long step, const Ct &addend, const Keys &k);
-    Ct lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t);
+    // sum of ciphertext x plaintext terms, rescaled to level t [+ the constant *c, added in the rescale]
+    Ct lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t, const double *c = nullptr);
     Ct level_down(const Ct &a, int t);
 
     // key switching of d (NTT form, limb stride ls, level l) into out = base + KS(d);
@@ -180,7 +191,10 @@ struct Ctx {
 
     // tables
     const KsTable &ks_table(int l);
-    const Buf &rescale_table(int l);
+    const Buf &rescale_table(int l, long k = 1);
+    const Buf &int_factor(long k);  // [2][L+1] k mod q_i and Shoup
+    const u64 *rescale_addend(int l, long k, double c);
+    const u64 *const_residues(double c, double scale);
 
     // client side
     Keys *keygen(u64 seed, const std::vector<long> &steps);

@@ -87,11 +87,12 @@ void launch_addsub(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, Limb
 // out = a * k_l (per-limb scalar residue table ks[limb], Shoup table ksp)
 void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *ks, const u64 *ksp,
                        LimbMap lm, int N, hipStream_t s);
-// out = a with component 0 of every ciphertext plus a per-limb constant c[limb]
-// (c non-null) or plus the plaintext polynomial p [limb][N] (c null);
-// out and a are ciphertext sets (polynomial 2 e + component)
-void launch_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *c, const u64 *p, LimbMap lm, int N,
-                   hipStream_t s);
+// out = k a (kf non-null: per-limb factor k mod q and its Shoup word kfp) with
+// component 0 of every ciphertext plus a per-limb constant c[limb] (c
+// non-null) or plus the plaintext polynomial p [limb][N] (p non-null); out
+// and a are ciphertext sets (polynomial 2 e + component)
+void launch_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *kf, const u64 *kfp, const u64 *c,
+                   const u64 *p, LimbMap lm, int N, hipStream_t s);
 // tensor (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1), accumulate if acc
 void launch_tensor(const PrimeConst *pc, PolySet d, PolySet a, PolySet b, LimbMap lm, int N, bool acc,
                    hipStream_t s);
@@ -145,10 +146,11 @@ struct OutModdownArgs {
 // tmp [npoly][nq][N], yP [npoly][alpha][N]
 void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, LimbMap lm, const u64 *yP,
                     const u64 *hatm, long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
-// rescale by q_l of npoly polynomials: out_i = (in_i - NTT_i([last + h] - h)) q_l^-1
+// rescale by q_l of npoly polynomials: out_i = (in_i [+ cadd_i on even polynomials] - NTT_i([last + h] - h)) inv_i,
+// inv_i = k q_l^-1 mod q_i for an integer factor k
 void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
                         long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
-                        int L1, hipStream_t s, KernelTimer *tm = nullptr);
+                        const u64 *cadd, int L1, hipStream_t s, KernelTimer *tm = nullptr);
 // copy limbs
 void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);
 // pointwise product out = a * b (single polynomials, Barrett)

@@ -130,14 +130,15 @@ struct Eval {
 
     double X(int t, int lct) const { return c.S[t] * (double)c.q[t + 1] / c.S[lct]; }
 
-    Ct lin_scalar(const std::vector<std::pair<const Ct *, double>> &terms, int t)
+    // sum_i c_i x_i at level t [+ *cst]
+    Ct lin_scalar(const std::vector<std::pair<const Ct *, double>> &terms, int t, const double *cst = nullptr)
     {
         std::vector<Pt> pts;
         pts.reserve(terms.size());
         for (auto &tm : terms) pts.push_back(c.const_pt(tm.second, X(t, tm.first->level), t + 2));
         std::vector<std::pair<const Ct *, const Pt *>> v;
         for (size_t i = 0; i < terms.size(); i++) v.push_back({terms[i].first, &pts[i]});
-        return c.lincomb(v, t);
+        return c.lincomb(v, t, cst);
     }
 
     // cached slot-vector plaintext for a lincomb term: key + target + operand level
@@ -160,22 +161,24 @@ struct Eval {
     }
 
     Ct mul(const Ct &a, const Ct &b) { return c.mul(a, b, k); }
+    // km (a b) [+ cc], the factor and constant applied in the rescale
+    Ct mul_aff(const Ct &a, const Ct &b, long km, const double *cc) { return c.mul_affine(a, b, k, km, cc); }
 
-    // sum_i a_i v^(2i+1), degree 3 / 5 / 7 in depth 2 / 3 / 3
-    Ct odd_poly(const Ct &v, const std::vector<double> &a)
+    // sum_i a_i v^(2i+1) [+ *cst], degree 3 / 5 / 7 in depth 2 / 3 / 3
+    Ct odd_poly(const Ct &v, const std::vector<double> &a, const double *cst = nullptr)
     {
         const int l = v.level;
         if (a.size() == 2) {
             Ct v2 = mul(v, v);
             Ct t3 = mul(lin_scalar({{&v, a[1]}}, l - 1), v2);
-            return c.add(lin_scalar({{&v, a[0]}}, l - 2), t3);
+            return c.add(lin_scalar({{&v, a[0]}}, l - 2, cst), t3);
         }
         if (a.size() == 3) {
             Ct v2 = mul(v, v);
             Ct v4 = mul(v2, v2);
             Ct t3 = mul(lin_scalar({{&v, a[1]}}, l - 1), v2);
             Ct t5 = mul(lin_scalar({{&v, a[2]}}, l - 2), v4);
-            return c.add(lin_scalar({{&v, a[0]}, {&t3, 1.0}}, l - 3), t5);
+            return c.add(lin_scalar({{&v, a[0]}, {&t3, 1.0}}, l - 3, cst), t5);
         }
         Ct v2 = mul(v, v);
         Ct v4 = mul(v2, v2);
@@ -183,13 +186,16 @@ struct Eval {
         Ct t7 = mul(lin_scalar({{&v, a[3]}}, l - 1), v2);
         Ct B = c.add(t7, lin_scalar({{&v, a[2]}}, l - 2));
         Ct Cc = mul(B, v4);
-        return c.add(lin_scalar({{&v, a[0]}, {&t3, 1.0}}, l - 3), Cc);
+        return c.add(lin_scalar({{&v, a[0]}, {&t3, 1.0}}, l - 3, cst), Cc);
     }
 
+    // the composite plus 1/2 (the constant joins the last stage's rescale)
     Ct polycomp(Ct v, const std::vector<std::vector<double>> &stages)
     {
-        for (auto &a : stages) v = odd_poly(v, a);
-        return c.add_const(v, 0.5);
+        const double half = 0.5;
+        if (stages.empty()) return c.add_const(v, half);
+        for (size_t i = 0; i < stages.size(); i++) v = odd_poly(v, stages[i], i + 1 == stages.size() ? &half : nullptr);
+        return v;
     }
 
     // ---- Chebyshev series by baby-step giant-step
@@ -212,8 +218,7 @@ struct Eval {
                 const std::string &path)
         {
             if (!mask) {
-                Ct s = e.lin_scalar(terms, t);
-                return with_const ? e.c.add_const(s, c0) : s;
+                return e.lin_scalar(terms, t, with_const ? &c0 : nullptr);
             }
             std::vector<std::pair<const Ct *, const Pt *>> v;
             for (size_t i = 0; i < terms.size(); i++)
@@ -286,21 +291,23 @@ struct Eval {
         const int mm = clog2i(deg + 1);
         ch.b = 1l << ((mm + 1) / 2);
         const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
-        ch.T[1] = c.add_const(lin_scalar({{&x, alpha}}, x.level - 1), beta);
+        ch.T[1] = lin_scalar({{&x, alpha}}, x.level - 1, &beta);
         for (long i = 2; i <= ch.b; i++) {
             if (i % 2 == 0) {
                 const Ct &h = ch.T.at(i / 2);
-                ch.T[i] = c.add_const(c.mul_int(mul(h, h), 2), -1.0);
+                const double m1 = -1.0;
+                ch.T[i] = mul_aff(h, h, 2, &m1);
             } else {
                 const Ct &a = ch.T.at((i - 1) / 2), &b2 = ch.T.at((i + 1) / 2);
                 int lv = std::min(a.level, b2.level);
-                Ct p = c.mul_int(mul(c.level_down(a, lv), c.level_down(b2, lv)), 2);
+                Ct p = mul_aff(c.level_down(a, lv), c.level_down(b2, lv), 2, nullptr);
                 ch.T[i] = c.sub(p, c.level_down(ch.T.at(1), p.level));
             }
         }
         for (long G = 2 * ch.b; G < deg + 1; G *= 2) {
             const Ct &h = ch.T.at(G / 2);
-            ch.T[G] = c.add_const(c.mul_int(mul(h, h), 2), -1.0);
+            const double m1 = -1.0;
+            ch.T[G] = mul_aff(h, h, 2, &m1);
         }
         int t = ch.T.at(1).level - 1;
         while (!ch.feasible(cf, t)) {
@@ -354,7 +361,8 @@ struct Eval {
                 for (auto &v : g1) v = -v;
                 x1 = polycomp(c.add_plain(xr, addvec(tag + "g1", xr.level, g1)), L.comp);
             }
-            x2 = c.add_const(c.mul_int(c.rotate(x1, P.n_blk, k), -1), 1.0);
+            const double one = 1.0;
+            x2 = c.affine(c.rotate(x1, P.n_blk, k), -1, &one, nullptr);
             return bases(mul(x1, x2), xr, L, P, tag);
         }
         std::vector<double> g1 = coltile(L, P, 1, r), g2 = coltile(L, P, 2, r + 1);
@@ -369,7 +377,7 @@ struct Eval {
         } else {
             for (auto &v : g1) v = -v;
             x1 = polycomp(c.add_plain(xr, addvec(tag + "g1", xr.level, g1)), L.comp);
-            x2 = polycomp(c.add_plain(c.mul_int(xr, -1), addvec(tag + "g2", xr.level, g2)), L.comp);
+            x2 = polycomp(c.affine(xr, -1, nullptr, &addvec(tag + "g2", xr.level, g2)), L.comp);
         }
         return bases(mul(x1, x2), xr, L, P, tag);
     }

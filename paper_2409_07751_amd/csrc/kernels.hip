@@ -56,20 +56,22 @@ void launch_mul_scalar(const PrimeConst *pc, PolySet out, PolySet a, const u64 *
     hipLaunchKernelGGL(k_mul_scalar, g, dim3(256), 0, s, pc, out, a, ks, ksp, lm, N);
 }
 
-__global__ void k_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *c, const u64 *p, LimbMap lm,
-                         int N)
+__global__ void k_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *kf, const u64 *kfp, const u64 *c,
+                         const u64 *p, LimbMap lm, int N)
 {
     EW_INDEX
+    const u64 q = pc[lm.prime(limb)].q;
     u64 x = a.base[limb * a.lstride + poly * a.pstride + n];
-    if ((poly & 1) == 0) x = addm(x, c ? c[limb] : p[(long)limb * N + n], pc[lm.prime(limb)].q);
+    if (kf) x = shoup(x, kf[limb], kfp[limb], q);
+    if ((poly & 1) == 0 && (c || p)) x = addm(x, c ? c[limb] : p[(long)limb * N + n], q);
     out.base[limb * out.lstride + poly * out.pstride + n] = x;
 }
 
-void launch_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *c, const u64 *p, LimbMap lm, int N,
-                   hipStream_t s)
+void launch_add_c0(const PrimeConst *pc, PolySet out, PolySet a, const u64 *kf, const u64 *kfp, const u64 *c,
+                   const u64 *p, LimbMap lm, int N, hipStream_t s)
 {
     dim3 g((N + 255) / 256, a.nl * a.npoly);
-    hipLaunchKernelGGL(k_add_c0, g, dim3(256), 0, s, pc, out, a, c, p, lm, N);
+    hipLaunchKernelGGL(k_add_c0, g, dim3(256), 0, s, pc, out, a, kf, kfp, c, p, lm, N);
 }
 
 // batch element e of d holds (d0, d1, d2) at +0, +N, +2N; of a and b (c0, c1)

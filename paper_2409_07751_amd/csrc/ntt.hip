@@ -143,7 +143,7 @@ struct InBconv {
         u64 lo[M], hi[M];
 #pragma unroll
         for (int m = 0; m < M; m++) lo[m] = hi[m] = 0;
-#pragma unroll 2
+#pragma unroll 1
         for (int k = 0; k < ns; k++) {
             const u64 hk = h[k * hat_ks];
             u64 y[M];
@@ -178,7 +178,7 @@ struct InBconv {
         double acc[M];
 #pragma unroll
         for (int m = 0; m < M; m++) acc[m] = 0.0;
-#pragma unroll 2
+#pragma unroll 1
         for (int k = 0; k < ns; k++) {
             const TwF t = h[k * hat_ks];
             u64 y[M];
@@ -252,15 +252,25 @@ struct OutScaleTab {
 };
 
 // rescale tail: out = (in - t) * q_l^-1
+// inv holds k q_l^-1 mod q_i for an integer factor k (1 for a plain rescale);
+// cadd, if set, holds per limb a word added to component 0 (polynomial
+// p = 2 e + c, c = 0) of every ciphertext before the subtraction: a constant
+// c lands in the output as cadd = c / inv (mod q_i), so the addition happens
+// in the prefetch, away from the store's register peak
 struct OutRescaleFin {
     const u64 *in;
     long ls, ps;
     u64 *out;
     long ols, ops;
     const u64 *inv, *invp;
+    const u64 *cadd;
     static constexpr int NPRE = 1;
     double extra_words(int npoly, int nl) const { return (double)npoly * nl; }
-    __device__ void fetch(const Blk &b, long g, u64 *pre) const { pre[0] = in[b.limb * ls + b.poly * ps + g]; }
+    __device__ void fetch(const Blk &b, long g, u64 *pre) const
+    {
+        const u64 x = in[b.limb * ls + b.poly * ps + g];
+        pre[0] = cadd && (b.poly & 1) == 0 ? addm(x, cadd[b.limb], b.pc->q) : x;
+    }
     __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
     {
         const u64 q = b.pc->q;
@@ -593,8 +603,14 @@ __device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long bl
 
 // own_w > 0: polynomial p of the set is key-switch digit j = p mod own_ndig;
 // its own limbs [j own_w, min(j own_w + own_w, own_nq)) are skipped
+// minimum waves per SIMD the compiler must leave room for: the ModDown tail
+// holds three prefetched words per position and would otherwise take just
+// over 128 VGPRs (3 waves per SIMD instead of 4)
+template <class OUT> struct NttWaves { static constexpr int value = 1; };
+template <> struct NttWaves<OutModdownFin> { static constexpr int value = 4; };
+
 template <int LOGN, int PASS, bool FWD, class IN, class OUT>
-__global__ void __launch_bounds__(256) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi,
+__global__ void __launch_bounds__(256, NttWaves<OUT>::value) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi,
                                              int own_w, int own_nq, int own_ndig, IN in, OUT out)
 {
     typedef NttGeo<LOGN> G;
@@ -858,14 +874,14 @@ static void rescale_n(const NttTables &t, const NttJob &j, const InRescale &in, 
 
 void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
                         long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
-                        int L1, hipStream_t s, KernelTimer *tm)
+                        const u64 *cadd, int L1, hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     NttJob j;
     j.ps = PolySet{tmp, N, (long)l * N, l, npoly};
     j.lm = LimbMap{l, L1, 0};
     InRescale ir{last, N, ql};
-    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp};
+    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp, cadd};
     NTT_DISPATCH(rescale_n, t, j, ir, o, s, tm);
 }
 
