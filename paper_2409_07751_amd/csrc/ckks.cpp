@@ -276,6 +276,7 @@ Ctx::~Ctx()
     rescale_inv.clear();
     rescale_add.clear();
     const_cache.clear();
+    const_plain_cache.clear();
     int_cache.clear();
     pinv.reset();
     tw_buf.reset();
@@ -440,6 +441,28 @@ const Buf &Ctx::rescale_table(int l, long k)
 // final (c_i - t_i) q_l^-1 run inside one fused NTT.
 Ct Ctx::rescale(const Ct &a) { return rescale_affine(a, 1, nullptr); }
 
+Ct Ctx::rescale_const_mul(const Ct &a, const Pt &pt, int t, const double *c)
+{
+    const int l = t + 1, np = 2 * a.nb;
+    if (l < 1 || a.level < l) throw HeError(-3, "rescale_const_mul: operand below target + 1");
+    n_rescale++;
+    const u64 *w = pt.plain->p;
+    const long P = L + 1;
+    Buf last = alloc((size_t)np * N);
+    // limb l of C a in coefficient form: C_l N^-1 applied to the inverse transform of a's limb l
+    launch_intt_from(T, PolySet{last->p, (long)N, (long)N, 1, np}, LimbMap{1, L1, l},
+                     a.d() + (size_t)l * 2 * N * a.nb, 2l * N * a.nb, (long)N, 0, w + 2 * P + l, w + 3 * P + l, st,
+                     &timer);
+    Buf tmp = alloc((size_t)l * np * N);
+    Ct o = new_ct(l - 1, a.nb);
+    const Buf &inv = rescale_table(l, 1);
+    const u64 *cadd = c ? rescale_addend(l, 1, *c) : nullptr;
+    launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
+                       (long)N, inv->p, inv->p + l, w, w + P, cadd, L1, st, &timer);
+    n_launch += 4;
+    return o;
+}
+
 // per limb i < l: the constant c at scale S[l-1] divided by k q_l^-1 (mod q_i), so
 // that adding it before the rescale's final product adds c to the result
 const u64 *Ctx::rescale_addend(int l, long k, double c)
@@ -475,7 +498,7 @@ Ct Ctx::rescale_affine(const Ct &a, long k, const double *c)
     const Buf &inv = rescale_table(l, k);
     const u64 *cadd = c ? rescale_addend(l, k, *c) : nullptr;
     launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
-                       (long)N, inv->p, inv->p + l, cadd, L1, st, &timer);
+                       (long)N, inv->p, inv->p + l, nullptr, nullptr, cadd, L1, st, &timer);
     n_launch += 4;
     return o;
 }
@@ -487,10 +510,11 @@ const KsTable &Ctx::ks_table(int l)
     if (it != ks_cache.end()) return it->second;
     const int nq = l + 1, next = nq + alpha, nd = ndig(l);
     std::vector<u64> v(2 * (size_t)nq + (size_t)nd * w * next, 0);
-    std::vector<TwF> vf((size_t)nd * w * next, TwF{0.0, 0.0});
+    std::vector<TwF> vf((size_t)nd * w * next + nq, TwF{0.0, 0.0});
     LimbMap lm = lmap(nq);
     KsTable kt;
     kt.wide[0] = kt.wide[1] = 0;
+    kt.dbl[0] = kt.dbl[1] = 0;
     for (int j = 0; j < nd; j++) {
         const int lo = j * w, hi = std::min(lo + w, nq);
         for (int i = lo; i < hi; i++) {
@@ -501,6 +525,10 @@ const KsTable &Ctx::ks_table(int l)
             v[i] = sc;
             v[nq + i] = shoup_of(sc, q[i]);
             if (64 - __builtin_clzll(q[i]) > 50) kt.wide[j / 8] |= 1ull << (8 * (j % 8) + (i - lo));
+            if (pc[i].fp) {
+                kt.dbl[j / 8] |= 1ull << (8 * (j % 8) + (i - lo));
+                vf[(size_t)nd * w * next + i] = TwF{(double)sc, (double)sc / (double)q[i]};
+            }
             for (int t = 0; t < next; t++) {
                 if (t >= lo && t < hi) continue;
                 u64 m = mods[lm.prime(t)], hm = 1;
@@ -515,6 +543,7 @@ const KsTable &Ctx::ks_table(int l)
     kt.fbuf = alloc(vf.size() * 2);
     upload(kt.fbuf->p, (const u64 *)vf.data(), vf.size() * 2);
     kt.hatf = (const TwF *)kt.fbuf->p;
+    kt.scalef = kt.hatf + (size_t)nd * w * next;
     kt.buf = alloc(v.size());
     upload(kt.buf->p, v.data(), v.size());
     kt.scale = kt.buf->p;
@@ -542,10 +571,10 @@ Ctx::ModUp Ctx::modup(const u64 *d, long ls, long es, int l, int nb)
     const KsTable &kt = ks_table(l);
     // y = INTT(d) * invhat / N, then every digit's conversion and NTT
     Buf y = alloc((size_t)nb * nq * N);
-    launch_intt_from(T, PolySet{y->p, (long)N, (long)nq * N, nq, nb}, lm, d, ls, es, 0, kt.scale, kt.scalep, st,
-                     &timer);
+    launch_intt_modup(T, PolySet{y->p, (long)N, (long)nq * N, nq, nb}, lm, d, ls, es, kt.scale, kt.scalep,
+                      kt.scalef, st, &timer);
     m.ext = alloc((size_t)nb * nd * next * N);
-    launch_modup(T, m.ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, kt.hatf, kt.wide, st, &timer);
+    launch_modup(T, m.ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, kt.hatf, kt.wide, kt.dbl, st, &timer);
     n_launch += 3;
     return m;
 }
@@ -706,15 +735,25 @@ Pt Ctx::const_pt(double c, double scale, int nl)
     auto it = const_cache.find(key);
     if (it != const_cache.end()) {
         p.buf = it->second;
+        p.plain = const_plain_cache.at(key);
         return p;
     }
-    std::vector<u64> v(L + 1);
+    std::vector<u64> v(L + 1), w(4 * (size_t)(L + 1));
     encode_const_rns(c, scale, q.data(), L + 1, v.data());
-    for (int i = 0; i <= L; i++) v[i] = (u64)(((u128)v[i] << 64) % q[i]);
-    Buf b = alloc(v.size());
+    for (int i = 0; i <= L; i++) {
+        w[i] = v[i];
+        w[L + 1 + i] = shoup_of(v[i], q[i]);
+        w[2 * (L + 1) + i] = hmul(v[i], pc[i].ninv, q[i]);
+        w[3 * (L + 1) + i] = shoup_of(w[2 * (L + 1) + i], q[i]);
+        v[i] = (u64)(((u128)v[i] << 64) % q[i]);
+    }
+    Buf b = alloc(v.size()), bp = alloc(w.size());
     upload(b->p, v.data(), v.size());
+    upload(bp->p, w.data(), w.size());
     const_cache.emplace(key, b);
+    const_plain_cache.emplace(key, bp);
     p.buf = b;
+    p.plain = bp;
     return p;
 }
 
@@ -734,6 +773,8 @@ Pt Ctx::vec_pt(const double *z, size_t n, double scale, int nl)
 Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t, const double *c)
 {
     if (terms.empty()) throw HeError(-1, "lincomb: no terms");
+    if (terms.size() == 1 && terms[0].second->is_const && terms[0].second->plain)
+        return rescale_const_mul(*terms[0].first, *terms[0].second, t, c);
     const int nl = t + 2, nb = terms[0].first->nb;
     Ct acc = new_ct(t + 1, nb);
     const int CH = 15;

@@ -71,6 +71,9 @@ struct Pt {
     Buf buf;
     bool is_const = false;
     int nl = 0;
+    // constants only: [4][L+1] the residues C_i, their Shoup words, C_i N^-1
+    // and its Shoup words (standard form, for products folded into a rescale)
+    Buf plain;
 };
 
 struct SwitchKey {
@@ -92,7 +95,9 @@ struct KsTable {
     Buf buf, fbuf;
     const u64 *scale, *scalep, *hatm;
     const TwF *hatf;  // hatm in standard form as FP64 pairs (entries for FP64 targets)
+    const TwF *scalef;  // [nq] scale as FP64 pairs (entries for FP64 primes)
     u64 wide[2];      // bit 8 j + k: source k of digit j is a prime above 2^50
+    u64 dbl[2];       // bit 8 j + k: source k of digit j is an FP64 prime (held as a double)
 };
 
 struct Ctx {
@@ -113,6 +118,7 @@ struct Ctx {
     Buf pinv;                        // [2][L+1] P^-1 mod q_i and Shoup
     Buf md_tab;                      // [2][alpha] P-limb INTT scale, then [alpha][L+1] P->Q constants
     std::map<std::pair<u64, u64>, Buf> const_cache;
+    std::map<std::pair<u64, u64>, Buf> const_plain_cache;
     std::map<int, Buf> int_cache;
     std::string err;
     u64 n_ks = 0, n_rescale = 0, n_launch = 0;
@@ -150,6 +156,10 @@ struct Ctx {
     // scale) are applied in the rescale's last pass; same residues as
     // add_const(mul_int(rescale(a), k), c)
     Ct rescale_affine(const Ct &a, long k, const double *c);
+    // rescale to level t of C a (C the constant plaintext pt, a at level >= t + 1) [+ c]:
+    // the product happens in the rescale's passes; same residues as
+    // rescale(lincomb({a, pt}, t)) [+ c]
+    Ct rescale_const_mul(const Ct &a, const Pt &pt, int t, const double *c);
     Tensor tensor(const Ct &a, const Ct &b);
     void tensor_acc(Tensor &t, const Ct &a, const Ct &b);
     Ct relin_rescale(const Tensor &t, const Keys &k, long mul = 1, const double *c = nullptr);

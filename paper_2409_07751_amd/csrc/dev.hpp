@@ -118,14 +118,21 @@ int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstr
 // limb i is multiplied by scale[i] (N^-1 folded in), or by N^-1 if scale is null
 void launch_intt_from(const NttTables &t, PolySet work, LimbMap lm, const u64 *src, long src_ls, long src_ps,
                       u64 galois, const u64 *scale, const u64 *scalep, hipStream_t s, KernelTimer *tm = nullptr);
+// the inverse transform that starts ModUp: like launch_intt_from with a scale
+// table, but a limb on an FP64 prime takes its factor from scalef (value and
+// quotient constant) and is stored as the bits of a double in [0, q)
+void launch_intt_modup(const NttTables &t, PolySet work, LimbMap lm, const u64 *src, long src_ls, long src_ps,
+                       const u64 *scale, const u64 *scalep, const TwF *scalef, hipStream_t s,
+                       KernelTimer *tm = nullptr);
 // ModUp of every digit of nb ciphertexts at once: ext [nb][ndig][nq+alpha][N] <-
 // NTT(BConv(y_digit)) on every limb outside the digit; y [nb][nq][N];
 // hatm [ndig][w][nq+alpha] Montgomery form; hatf the same constants in
 // standard form as FP64 pairs (used for targets on FP64 primes); bit
 // 8 j + k of wide (j < 8: wide[0], else wide[1]) marks source k of digit j as
-// a prime of more than 50 bits
+// a prime of more than 50 bits, the same bit of dbl a source held as the bits
+// of a double (written by launch_intt_modup)
 void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
-                  const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], hipStream_t s,
+                  const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], const u64 dbl[2], hipStream_t s,
                   KernelTimer *tm = nullptr);
 struct OutModdownArgs {
     const u64 *acc;
@@ -146,11 +153,12 @@ struct OutModdownArgs {
 // tmp [npoly][nq][N], yP [npoly][alpha][N]
 void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, LimbMap lm, const u64 *yP,
                     const u64 *hatm, long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
-// rescale by q_l of npoly polynomials: out_i = (in_i [+ cadd_i on even polynomials] - NTT_i([last + h] - h)) inv_i,
-// inv_i = k q_l^-1 mod q_i for an integer factor k
+// rescale by q_l of npoly polynomials: out_i = (in_i pm_i [+ cadd_i on even polynomials] - NTT_i([last + h] - h)) inv_i,
+// inv_i = k q_l^-1 mod q_i for an integer factor k; pm (Shoup words pmp) a per-limb factor, or null for 1
 void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
                         long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
-                        const u64 *cadd, int L1, hipStream_t s, KernelTimer *tm = nullptr);
+                        const u64 *pm, const u64 *pmp, const u64 *cadd, int L1, hipStream_t s,
+                        KernelTimer *tm = nullptr);
 // copy limbs
 void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);
 // pointwise product out = a * b (single polynomials, Barrett)

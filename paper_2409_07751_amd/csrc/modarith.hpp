@@ -77,6 +77,12 @@ __device__ __forceinline__ double u2d(u64 v)
     return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
 }
 
+// the bits of a double holding an integer in [0, 2^52) -> that integer
+__device__ __forceinline__ u64 d2u_exact(u64 bits)
+{
+    return (u64)__double_as_longlong(__longlong_as_double((long long)bits) + 4503599627370496.0) & 0xFFFFFFFFFFFFFull;
+}
+
 // integer-valued double with |v| < 2^52 -> v mod q in [0, q)
 __device__ __forceinline__ u64 d2u_mod(double v, double q, double qi)
 {

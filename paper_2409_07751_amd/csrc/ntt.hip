@@ -112,6 +112,8 @@ struct InBconv {
     int w, nq;          // else digit j has min(w, nq - j w) sources
     const TwF *hatf;    // non-null: FP64 pairs (hat, hat / q_t), same indexing, for FP64 targets
     u64 wide[2];        // bit 8 j + k: source k of digit j is a prime above 2^50
+    u64 dbl[2];         // bit 8 j + k: source k of digit j holds the bits of a double (an FP64 prime's residue)
+    __device__ u64 bits(const u64 *m, int j) const { return (j < 8 ? m[0] >> (8 * j) : m[1] >> (8 * (j - 8))) & 0xff; }
     __device__ int nsrc(int j) const { return ns_fixed > 0 ? ns_fixed : min(w, nq - j * w); }
     // each source limb is read once per launch: the ndig digits of a batch
     // element together hold its nq limbs
@@ -126,8 +128,9 @@ struct InBconv {
         const long N = 1l << b.logN;
         const u64 *s = src + e * src_bs + j * src_ps + g;
         const u64 *h = hatm + j * hat_ps + b.limb;
+        const u64 dj = bits(dbl, j);
         u64 lo = 0, hi = 0;
-        for (int k = 0; k < ns; k++) mac(lo, hi, s[k * N], h[k * hat_ks]);
+        for (int k = 0; k < ns; k++) mac(lo, hi, dj >> k & 1 ? d2u_exact(s[k * N]) : s[k * N], h[k * hat_ks]);
         return redc(lo, hi, *b.pc);
     }
     // M positions at once, sources outermost: M independent loads in flight
@@ -140,6 +143,7 @@ struct InBconv {
         const long N = 1l << b.logN;
         const u64 *s = src + e * src_bs + j * src_ps;
         const u64 *h = hatm + j * hat_ps + b.limb;
+        const u64 dj = bits(dbl, j);
         u64 lo[M], hi[M];
 #pragma unroll
         for (int m = 0; m < M; m++) lo[m] = hi[m] = 0;
@@ -149,6 +153,10 @@ struct InBconv {
             u64 y[M];
 #pragma unroll
             for (int m = 0; m < M; m++) y[m] = s[k * N + g[m]];
+            if (dj >> k & 1) {
+#pragma unroll
+                for (int m = 0; m < M; m++) y[m] = d2u_exact(y[m]);
+            }
 #pragma unroll
             for (int m = 0; m < M; m++) mac(lo[m], hi[m], y[m], hk);
         }
@@ -174,7 +182,7 @@ struct InBconv {
         const u64 *s = src + e * src_bs + j * src_ps;
         const TwF *h = hatf + j * hat_ps + b.limb;
         const double q = b.pc->qd;
-        const u64 wj = (j < 8 ? wide[0] >> (8 * j) : wide[1] >> (8 * (j - 8))) & 0xff;
+        const u64 wj = bits(wide, j), dj = bits(dbl, j);
         double acc[M];
 #pragma unroll
         for (int m = 0; m < M; m++) acc[m] = 0.0;
@@ -190,6 +198,9 @@ struct InBconv {
                     const double yd = mulm_fp(u2d(y[m] >> 32), b.pc->r32d, b.pc->r32c, q) + u2d(y[m] & 0xffffffffull);
                     acc[m] += mulm_fp(yd, t.w, t.c, q);
                 }
+            } else if (dj >> k & 1) {
+#pragma unroll
+                for (int m = 0; m < M; m++) acc[m] += mulm_fp(__longlong_as_double((long long)y[m]), t.w, t.c, q);
             } else {
 #pragma unroll
                 for (int m = 0; m < M; m++) acc[m] += mulm_fp(u2d(y[m]), t.w, t.c, q);
@@ -251,9 +262,36 @@ struct OutScaleTab {
     }
 };
 
+// inverse transform, last store of the basis-conversion sources of ModUp: limb
+// i times scale[i] (N^-1 folded in); on an FP64 prime the product is taken in
+// FP64 (sf: the factor and its quotient constant), reduced to [0, q) and stored
+// as the bits of the double, which the conversion reads without converting
+struct OutScaleTabFp {
+    const u64 *s, *sp;
+    const TwF *sf;
+    static constexpr int NPRE = 0;
+    double extra_words(int, int) const { return 0; }
+    __device__ void fetch(const Blk &, long, u64 *) const {}
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *) const
+    {
+        const u64 q = b.pc->q;
+        v = shoup_lazy(v, s[b.limb], sp[b.limb], q);
+        b.a[g] = v >= q ? v - q : v;
+    }
+    __device__ void store_d(const Blk &b, long g, double v) const
+    {
+        const double q = b.pc->qd;
+        const TwF f = sf[b.limb];
+        double r = mulm_fp(v, f.w, f.c, q);
+        r = r < 0.0 ? r + q : r;
+        b.a[g] = (u64)__double_as_longlong(r);
+    }
+};
+
 // rescale tail: out = (in - t) * q_l^-1
 // inv holds k q_l^-1 mod q_i for an integer factor k (1 for a plain rescale);
-// cadd, if set, holds per limb a word added to component 0 (polynomial
+// pm, if set, a per-limb factor the input is multiplied by when it is fetched
+// (Shoup words pmp); cadd, if set, holds per limb a word added to component 0 (polynomial
 // p = 2 e + c, c = 0) of every ciphertext before the subtraction: a constant
 // c lands in the output as cadd = c / inv (mod q_i), so the addition happens
 // in the prefetch, away from the store's register peak
@@ -263,12 +301,14 @@ struct OutRescaleFin {
     u64 *out;
     long ols, ops;
     const u64 *inv, *invp;
+    const u64 *pm, *pmp;
     const u64 *cadd;
     static constexpr int NPRE = 1;
     double extra_words(int npoly, int nl) const { return (double)npoly * nl; }
     __device__ void fetch(const Blk &b, long g, u64 *pre) const
     {
-        const u64 x = in[b.limb * ls + b.poly * ps + g];
+        u64 x = in[b.limb * ls + b.poly * ps + g];
+        if (pm) x = shoup(x, pm[b.limb], pmp[b.limb], b.pc->q);
         pre[0] = cadd && (b.poly & 1) == 0 ? addm(x, cadd[b.limb], b.pc->q) : x;
     }
     __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
@@ -344,7 +384,7 @@ __device__ __forceinline__ double load_fp(const IN &in, const Blk &b, long g)
 template <class OUT>
 __device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, double v, const u64 *pre)
 {
-    if constexpr (std::is_same<OUT, OutMid>::value) out.store_d(b, g, v);
+    if constexpr (std::is_same<OUT, OutMid>::value || std::is_same<OUT, OutScaleTabFp>::value) out.store_d(b, g, v);
     else out.store(b, g, d2u_mod(v, b.pc->qd, b.pc->qinvd), pre);
 }
 
@@ -601,16 +641,17 @@ __device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long bl
     }
 }
 
-// own_w > 0: polynomial p of the set is key-switch digit j = p mod own_ndig;
-// its own limbs [j own_w, min(j own_w + own_w, own_nq)) are skipped
 // minimum waves per SIMD the compiler must leave room for: the ModDown tail
 // holds three prefetched words per position and would otherwise take just
-// over 128 VGPRs (3 waves per SIMD instead of 4)
-template <class OUT> struct NttWaves { static constexpr int value = 1; };
-template <> struct NttWaves<OutModdownFin> { static constexpr int value = 4; };
+// over 128 VGPRs (3 waves per SIMD instead of 4).  (Holding the conversion
+// pass to 96 VGPRs for 5 waves spills and measured no faster than 4 waves.)
+template <class IN, class OUT> struct NttWaves { static constexpr int value = 1; };
+template <class IN> struct NttWaves<IN, OutModdownFin> { static constexpr int value = 4; };
 
+// own_w > 0: polynomial p of the set is key-switch digit j = p mod own_ndig;
+// its own limbs [j own_w, min(j own_w + own_w, own_nq)) are skipped
 template <int LOGN, int PASS, bool FWD, class IN, class OUT>
-__global__ void __launch_bounds__(256, NttWaves<OUT>::value) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi,
+__global__ void __launch_bounds__(256, (NttWaves<IN, OUT>::value)) k_ntt(NttTables T, PolySet ps, LimbMap lm, int skip_lo, int skip_hi,
                                              int own_w, int own_nq, int own_ndig, IN in, OUT out)
 {
     typedef NttGeo<LOGN> G;
@@ -790,6 +831,24 @@ void launch_intt_from(const NttTables &t, PolySet work, LimbMap lm, const u64 *s
     NTT_DISPATCH(intt_src_n, t, j, in, o, s, tm);
 }
 
+template <int LOGN>
+static void intt_modup_n(const NttTables &t, const NttJob &j, const InSrc &in, const OutScaleTabFp &o,
+                         hipStream_t s, KernelTimer *tm)
+{
+    inv_n<LOGN>(t, j, in, o, s, tm);
+}
+
+void launch_intt_modup(const NttTables &t, PolySet work, LimbMap lm, const u64 *src, long src_ls, long src_ps,
+                       const u64 *scale, const u64 *scalep, const TwF *scalef, hipStream_t s, KernelTimer *tm)
+{
+    NttJob j;
+    j.ps = work;
+    j.lm = lm;
+    InSrc in{src, src_ls, src_ps, 0};
+    OutScaleTabFp o{scale, scalep, scalef};
+    NTT_DISPATCH(intt_modup_n, t, j, in, o, s, tm);
+}
+
 // ModUp of all digits: ext is [ndig][next][N]; the forward transform of every
 // non-own limb of every digit starts from the fast basis conversion of the
 // digit's inverse-hat-scaled coefficients y (limb stride N)
@@ -800,8 +859,8 @@ static void modup_n(const NttTables &t, const NttJob &j, const InBconv &in, hipS
 }
 
 void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
-                  const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], hipStream_t s,
-                  KernelTimer *tm)
+                  const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], const u64 dbl[2],
+                  hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     const int next = nq + alpha;
@@ -825,6 +884,8 @@ void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int
     in.hatf = hatf;
     in.wide[0] = wide[0];
     in.wide[1] = wide[1];
+    in.dbl[0] = dbl[0];
+    in.dbl[1] = dbl[1];
     NTT_DISPATCH(modup_n, t, j, in, s, tm);
 }
 
@@ -858,6 +919,7 @@ void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, 
     // every source is a special prime: the integer conversion is as cheap here
     in.hatf = nullptr;
     in.wide[0] = in.wide[1] = 0;
+    in.dbl[0] = in.dbl[1] = 0;
     OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.mask, a.galois, a.out, a.ols, a.ops,
                     a.pinv, a.pinvp, a.add, a.als, a.aes};
     NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
@@ -874,14 +936,14 @@ static void rescale_n(const NttTables &t, const NttJob &j, const InRescale &in, 
 
 void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
                         long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
-                        const u64 *cadd, int L1, hipStream_t s, KernelTimer *tm)
+                        const u64 *pm, const u64 *pmp, const u64 *cadd, int L1, hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     NttJob j;
     j.ps = PolySet{tmp, N, (long)l * N, l, npoly};
     j.lm = LimbMap{l, L1, 0};
     InRescale ir{last, N, ql};
-    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp, cadd};
+    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp, pm, pmp, cadd};
     NTT_DISPATCH(rescale_n, t, j, ir, o, s, tm);
 }
 
