@@ -139,7 +139,8 @@ int he_ctx_sync(he_ctx *ctx);
 
 /* Kernel timing for measurement: while enabled, every launch of one kernel
  * (0 forward NTT pass 1, 1 forward NTT pass 2, 2 inverse NTT pass 2,
- * 3 inverse NTT pass 1, 4 basis conversion, 5 key-switch inner product) is
+ * 3 inverse NTT pass 1, 4 basis conversion, 5 key-switch inner product,
+ * 6 ModUp's second pass fused with the key-switch inner product) is
  * bracketed by HIP events on the context stream.  kernel = -1 disables.
  * Enabling clears earlier records.  he_ctx_profile_read synchronises and
  * returns the summed event time, the number of launches, and the launches'

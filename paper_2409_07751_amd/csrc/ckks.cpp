@@ -157,6 +157,8 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
         c.r32d = (double)r32;
         c.r32c = (double)r32 / (double)m;
     }
+    ks_fused = L >= 1 && !pc[0].fp;
+    for (int i = 1; i < np; i++) ks_fused = ks_fused && (pc[i].fp == (i <= L));
     d_pc_buf = alloc((sizeof(PrimeConst) * np + 7) / 8);
     HIP_CHECK(hipMemcpyAsync(d_pc_buf->p, pc.data(), sizeof(PrimeConst) * np, hipMemcpyHostToDevice, st));
     d_pc = (const PrimeConst *)d_pc_buf->p;
@@ -587,9 +589,18 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
     const LimbMap lm = lmap(nq);
     Buf acc = alloc((size_t)nb * 2 * next * N);
     if (launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, m.ext->p, (long)next * N, (long)nd * next * N,
-                     m.d, m.ls, m.es, key.buf->p, 2l * ktot * N, (long)ktot * N, nd, next, nq, w, nb, lm, L1, logN,
-                     st, &timer) != 0)
+                     m.d, m.ls, m.es, key.buf->p, 2l * ktot * N, (long)ktot * N, nd, next, 0, 0, nq, w, nb, lm, L1,
+                     logN, st, &timer) != 0)
         throw HeError(-1, "key switch: " + std::to_string(nd) + " digits (at most 16 supported)");
+    n_launch++;
+    moddown_into(acc, l, nb, galois, base, base_ls, base_es, base_mask, out, addend);
+}
+
+void Ctx::moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *base, long base_ls, long base_es,
+                       int base_mask, Ct &out, const Ct *addend)
+{
+    const int nq = l + 1, next = nq + alpha;
+    const LimbMap lm = lmap(nq);
     // ModDown of the 2 nb accumulator polynomials
     Buf yP = alloc((size_t)nb * 2 * alpha * N);
     launch_intt_from(T, PolySet{yP->p, (long)N, (long)alpha * N, alpha, 2 * nb}, LimbMap{0, L1},
@@ -605,7 +616,7 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
         oa.aes = 2l * N;
     }
     launch_moddown(T, tmp->p, nq, alpha, 2 * nb, lm, yP->p, md_tab->p + 2 * alpha, L + 1, oa, st, &timer);
-    n_launch += 6;
+    n_launch += 5;
 }
 
 // Hybrid key switching (Han-Ki): d is split into digits of w Q limbs; each
@@ -618,8 +629,33 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
 void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
                     const u64 *base, long base_ls, long base_es, int base_mask, Ct &out, const Ct *addend)
 {
-    ModUp m = modup(d, ls, es, l, nb);
-    keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out, addend);
+    if (!ks_fused || !key.fbuf) {
+        ModUp m = modup(d, ls, es, l, nb);
+        keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out, addend);
+        return;
+    }
+    // ModUp with the inner product fused into the second pass on q_1..q_l; the
+    // extended digits are stored only on q_0 and the special primes, whose
+    // inner product follows separately
+    n_ks += nb;
+    const int nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
+    if (nd > 16) throw HeError(-1, "key switch: " + std::to_string(nd) + " digits (at most 16 supported)");
+    const LimbMap lm = lmap(nq);
+    const KsTable &kt = ks_table(l);
+    Buf y = alloc((size_t)nb * nq * N);
+    launch_intt_modup(T, PolySet{y->p, (long)N, (long)nq * N, nq, nb}, lm, d, ls, es, kt.scale, kt.scalep,
+                      kt.scalef, st, &timer);
+    Buf ext = alloc((size_t)nb * nd * next * N);
+    Buf acc = alloc((size_t)nb * 2 * next * N);
+    ModupKeyipArgs a{1, nq, 1, nb, d, ls, es, (const double *)key.fbuf->p, 2l * ktot * N, (long)ktot * N,
+                     acc->p, 2l * next * N, (long)next * N};
+    launch_modup_keyip(T, ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, kt.hatf, kt.wide, kt.dbl, a, st, &timer);
+    y.reset();
+    launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, ext->p, (long)next * N, (long)nd * next * N, d, ls, es,
+                 key.buf->p, 2l * ktot * N, (long)ktot * N, nd, 1 + alpha, 1, nq, nq, w, nb, lm, L1, logN, st, &timer);
+    ext.reset();
+    n_launch += 6;
+    moddown_into(acc, l, nb, galois, base, base_ls, base_es, base_mask, out, addend);
 }
 
 Tensor Ctx::tensor(const Ct &a, const Ct &b)
@@ -884,6 +920,17 @@ void Ctx::gen_switch_key(Keys &k, u64 seed, u32 key_id, const u64 *sp_ntt, Switc
     sync();
 }
 
+// the double copy of a key's FP64-prime limbs read by the fused ModUp products
+// (from the key as stored, i.e. after a Galois key's permutation)
+void Ctx::key_fp(SwitchKey &k)
+{
+    if (!ks_fused) return;
+    const int ktot = L + 1 + alpha, dn = dnum_top();
+    k.fbuf = alloc((size_t)dn * 2 * ktot * N);
+    launch_key_fp(d_pc, k.buf->p, k.fbuf->p, dn * 2 * ktot, ktot, N, st);
+    n_launch++;
+}
+
 Keys *Ctx::keygen(u64 seed, const std::vector<long> &steps)
 {
     const int ktot = L + 1 + alpha;
@@ -907,6 +954,7 @@ Keys *Ctx::keygen(u64 seed, const std::vector<long> &steps)
     launch_pmul(d_pc, PolySet{s2->p, (long)N, 0, ktot, 1}, sset, sset, lm, N, st);
     n_launch++;
     gen_switch_key(*k, seed, 0, s2->p, k->relin);
+    key_fp(k->relin);
     // Galois keys: s' = sigma_g(s), a permutation of NTT slots
     Buf sg = alloc(sr.size());
     for (long step : steps) {
@@ -923,6 +971,7 @@ Keys *Ctx::keygen(u64 seed, const std::vector<long> &steps)
                          (int)(words / N), 1}, hinv(g, 2ull * N), logN, st);
         n_launch++;
         gk.buf = perm;
+        key_fp(gk);
     }
     return k.release();
 }

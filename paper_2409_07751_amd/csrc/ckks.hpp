@@ -77,7 +77,8 @@ struct Pt {
 };
 
 struct SwitchKey {
-    Buf buf;  // [dnum][2][L+1+alpha][N] NTT + Montgomery form
+    Buf buf;   // [dnum][2][L+1+alpha][N] NTT + Montgomery form
+    Buf fbuf;  // the same layout in standard form as doubles, filled on FP64 primes (fused ModUp products)
 };
 
 struct Keys {
@@ -122,6 +123,9 @@ struct Ctx {
     std::map<int, Buf> int_cache;
     std::string err;
     u64 n_ks = 0, n_rescale = 0, n_launch = 0;
+    // q_0 and the special primes on the integer path, q_1..q_L on FP64: single
+    // key switches fuse the key inner product into ModUp's second pass
+    bool ks_fused = false;
     KernelTimer timer;
     void profile(int kernel_id);  // -1 disables; clears previous records
     void profile_read(double &ms, u64 &launches, double &bytes, double &ops);
@@ -188,6 +192,9 @@ struct Ctx {
     void keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
                    const u64 *base, long base_ls, long base_es, int base_mask, Ct &out,
                    const Ct *addend = nullptr);
+    // ModDown of the accumulators acc [nb][2][l+1+alpha][N] into out (base and addend as in keyswitch_from)
+    void moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *base, long base_ls, long base_es,
+                      int base_mask, Ct &out, const Ct *addend);
     // batches of single ciphertexts at one level
     Ct pack(const std::vector<const Ct *> &cts);
     Ct unpack(const Ct &batch, int e);
@@ -209,6 +216,7 @@ struct Ctx {
     // client side
     Keys *keygen(u64 seed, const std::vector<long> &steps);
     void gen_switch_key(Keys &k, u64 seed, u32 key_id, const u64 *sp_ntt, SwitchKey &out);
+    void key_fp(SwitchKey &k);
     Ct encrypt(const Keys &k, const double *x, size_t n, u64 seed);
     void decrypt(const Keys &k, const Ct &c, double *y, size_t n);
 

@@ -63,7 +63,7 @@ struct NttTables {
 // Optional per-kernel timer: HIP events recorded on the launch stream around
 // every launch of one selected kernel, with the launch's algorithmic bytes and
 // butterflies/multiply-accumulates.
-enum KernelId { KID_NTT_FWD1 = 0, KID_NTT_FWD2, KID_NTT_INV2, KID_NTT_INV1, KID_BCONV, KID_KEYIP, KID_COUNT };
+enum KernelId { KID_NTT_FWD1 = 0, KID_NTT_FWD2, KID_NTT_INV2, KID_NTT_INV1, KID_BCONV, KID_KEYIP, KID_MODUP_KEYIP, KID_COUNT };
 struct KernelTimer {
     int target = -1;
     struct Rec {
@@ -107,11 +107,15 @@ void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s);
 // Montgomery form): acc_c[t] = sum_j e_j[t] * key_j[c][kt(t)], c = 0, 1, where
 // e_j[t] is the input d itself on digit j's own limbs and ext_j[t] elsewhere.
 // Galois keys are stored permuted by sigma^-1, so no permutation happens here.
+// nl limbs t = i < skip_lo ? i : i + skip_hi - skip_lo (i < nl) are computed.
 // Returns -1 (nothing launched) unless 1 <= ndig <= 16.
 int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
                  long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
-                 long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
-                 int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
+                 long key_dstride, long key_cstride, int ndig, int nl, int skip_lo, int skip_hi, int nq, int w,
+                 int nb, LimbMap lm, int key_nq_off, int logN, hipStream_t s, KernelTimer *tm = nullptr);
+// the double (standard form) copy of a switching key's FP64-prime limbs: rows
+// r of N words, limb r mod ktot (prime index), from Montgomery words
+void launch_key_fp(const PrimeConst *pc, const u64 *kmont, u64 *kf, int rows, int ktot, int N, hipStream_t s);
 
 // --- fused transforms (ntt.hip)
 // inverse transform of src (through sigma_galois if galois > 1) into `work`;
@@ -134,6 +138,24 @@ void launch_intt_modup(const NttTables &t, PolySet work, LimbMap lm, const u64 *
 void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
                   const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], const u64 dbl[2], hipStream_t s,
                   KernelTimer *tm = nullptr);
+// the key inner product fused into ModUp's second pass on the limbs [fp_lo, fp_hi)
+// of FP64 primes (the other limbs' extended digits are stored as by launch_modup);
+// d: limb t of element e at d + t d_ls + e d_es; kf: key words in standard form as
+// doubles, digit j component c limb t at kf + j kf_ds + c kf_cs + t N; acc: element e
+// component c limb t at acc + e acc_es + c acc_cs + t N; own_int: the own limbs of
+// one element outside [fp_lo, fp_hi)
+struct ModupKeyipArgs {
+    int fp_lo, fp_hi, own_int, nb;
+    const u64 *d;
+    long d_ls, d_es;
+    const double *kf;
+    long kf_ds, kf_cs;
+    u64 *acc;
+    long acc_es, acc_cs;
+};
+void launch_modup_keyip(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
+                        const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], const u64 dbl[2],
+                        const ModupKeyipArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
 struct OutModdownArgs {
     const u64 *acc;
     long acc_ls, acc_ps;

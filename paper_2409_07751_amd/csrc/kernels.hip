@@ -202,10 +202,10 @@ __global__ void __launch_bounds__(256) k_keyip(const PrimeConst *pc, u64 *__rest
                                                long acc_bstride, const u64 *__restrict__ ext, long ext_dstride,
                                                long ext_bstride, const u64 *__restrict__ d, long d_ls,
                                                long d_bstride, const u64 *__restrict__ key, long key_dstride,
-                                               long key_cstride, int ndig, int nq, int w, int nb, LimbMap lm,
-                                               int key_nq_off, int logN)
+                                               long key_cstride, int ndig, int skip_lo, int skip_hi, int nq, int w,
+                                               int nb, LimbMap lm, int key_nq_off, int logN)
 {
-    const int t = blockIdx.y;
+    const int t = (int)blockIdx.y < skip_lo ? (int)blockIdx.y : (int)blockIdx.y + (skip_hi - skip_lo);
     const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long N = 1l << logN;
     if (n >= N) return;
@@ -242,8 +242,8 @@ __global__ void __launch_bounds__(256) k_keyip(const PrimeConst *pc, u64 *__rest
 
 int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstride, const u64 *ext,
                  long ext_dstride, long ext_bstride, const u64 *d, long d_ls, long d_bstride, const u64 *key,
-                 long key_dstride, long key_cstride, int ndig, int nl, int nq, int w, int nb, LimbMap lm,
-                 int key_nq_off, int logN, hipStream_t s, KernelTimer *tm)
+                 long key_dstride, long key_cstride, int ndig, int nl, int skip_lo, int skip_hi, int nq, int w,
+                 int nb, LimbMap lm, int key_nq_off, int logN, hipStream_t s, KernelTimer *tm)
 {
     if (ndig < 1 || ndig > 16) return -1;
     const int N = 1 << logN;
@@ -252,7 +252,7 @@ int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstr
     if (on) tm->before(s);
 #define KEYIP_ARGS                                                                                              \
     pc, acc, acc_pstride, acc_bstride, ext, ext_dstride, ext_bstride, d, d_ls, d_bstride, key, key_dstride,     \
-        key_cstride, ndig, nq, w, nb, lm, key_nq_off, logN
+        key_cstride, ndig, skip_lo, skip_hi, nq, w, nb, lm, key_nq_off, logN
     if (ndig <= 4) hipLaunchKernelGGL(k_keyip<4>, g, dim3(256), 0, s, KEYIP_ARGS);
     else if (ndig <= 8) hipLaunchKernelGGL(k_keyip<8>, g, dim3(256), 0, s, KEYIP_ARGS);
     else hipLaunchKernelGGL(k_keyip<16>, g, dim3(256), 0, s, KEYIP_ARGS);
@@ -260,6 +260,23 @@ int launch_keyip(const PrimeConst *pc, u64 *acc, long acc_pstride, long acc_bstr
     // reads nb ndig extended digits and 2 ndig key polynomials, writes 2 nb outputs
     if (on) tm->after(s, 8.0 * N * nl * (nb * ndig + 2.0 * ndig + 2.0 * nb), 2.0 * N * nl * ndig * nb);
     return 0;
+}
+
+__global__ void k_key_fp(const PrimeConst *pc, const u64 *kmont, u64 *kf, int ktot, int N)
+{
+    const int r = blockIdx.y;
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const PrimeConst &c = pc[r % ktot];
+    if (!c.fp) return;
+    const long o = (long)r * N + n;
+    kf[o] = (u64)__double_as_longlong((double)redc(kmont[o], 0, c));
+}
+
+void launch_key_fp(const PrimeConst *pc, const u64 *kmont, u64 *kf, int rows, int ktot, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, rows);
+    hipLaunchKernelGGL(k_key_fp, g, dim3(256), 0, s, pc, kmont, kf, ktot, N);
 }
 
 // -------------------------------------------------------- keys and client ops

@@ -75,6 +75,7 @@ struct Blk {
     int limb, poly;
     const PrimeConst *pc;
     int logN;
+    int tid;  // threadIdx.x, for OutLds only (see OpaqueTid)
 };
 
 // Every policy states the words it reads per coefficient position over a
@@ -217,12 +218,24 @@ struct InRescale {
     const u64 *last;  // polynomial p at last + p * last_ps (coefficient form)
     long last_ps;
     u64 ql;
+    double qld, hd;   // q_l and floor(q_l / 2) as doubles, when q_l < 2^52 (else qld = 0)
     __device__ u64 load(const Blk &b, long g) const
     {
         const u64 h = ql >> 1;
         u64 r = last[b.poly * last_ps + g] + h;
         r = r >= ql ? r - ql : r;
         return subm(reduce64(r, *b.pc), reduce64(h, *b.pc), b.pc->q);
+    }
+    // for an FP64 target: [c_l + h]_{q_l} - h is an integer of magnitude at
+    // most q_l / 2, formed exactly in FP64 and reduced to |x| <= q/2 + 1 (the
+    // same residue as load(), in the balanced range the transform accepts)
+    __device__ double load_d(const Blk &b, long g) const
+    {
+        if (qld == 0.0) return u2d(load(b, g));
+        double t = u2d(last[b.poly * last_ps + g]) + hd;
+        t = t >= qld ? t - qld : t;
+        const double v = t - hd;
+        return __fma_rn(-rint(v * b.pc->qinvd), b.pc->qd, v);
     }
     double read_words(int npoly, int) const { return (double)npoly; }  // the dropped limb, shared by all limbs
 };
@@ -359,6 +372,29 @@ struct OutModdownFin {
     }
 };
 
+// last phase of a second pass leaving the transformed tile in LDS (FP64
+// path): position g of the tile's rows goes to the word the row pass itself
+// uses for it (row bits 4..6 of the word index XORed into bits 0..3)
+struct OutLds {
+    double *sh;
+    int mask;  // tile words - 1
+    static constexpr int NPRE = 0;
+    double extra_words(int, int) const { return 0; }
+    __device__ void fetch(const Blk &, long, u64 *) const {}
+    __device__ void store(const Blk &, long, u64, const u64 *) const {}
+    __device__ static int word(int pos)  // pos: row r of the tile, word p: r 256 + p
+    {
+        const int p = pos & 255;
+        return (pos & ~255) + (p ^ (((p >> 4) & 1) | (((p >> 5) & 1) * 6) | (((p >> 6) & 1) << 3)));
+    }
+    __device__ void store_d(const Blk &, long g, double v) const { sh[word((int)g & mask)] = v; }
+};
+// the transforms of a kernel that runs several in a loop (OutLds) index with
+// a per-iteration copy of threadIdx.x, so their addresses are recomputed per
+// transform instead of all being hoisted out of the loop and kept live
+template <class OUT> struct OpaqueTid { static constexpr bool value = false; };
+template <> struct OpaqueTid<OutLds> { static constexpr bool value = true; };
+
 // between the two passes of one transform: lazy u64 words, or the raw
 // balanced doubles of the FP64 path (the next pass of the same prime reads them)
 struct InMid {
@@ -377,14 +413,15 @@ struct OutMid {
 template <class IN>
 __device__ __forceinline__ double load_fp(const IN &in, const Blk &b, long g)
 {
-    if constexpr (std::is_same<IN, InMid>::value) return in.load_d(b, g);
+    if constexpr (std::is_same<IN, InMid>::value || std::is_same<IN, InRescale>::value) return in.load_d(b, g);
     else return u2d(in.load(b, g));  // every other input policy yields words below 4q
 }
 
 template <class OUT>
-__device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, double v, const u64 *pre)
+__device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, double v, u64 *pre)
 {
     if constexpr (std::is_same<OUT, OutMid>::value || std::is_same<OUT, OutScaleTabFp>::value) out.store_d(b, g, v);
+    else if constexpr (std::is_same<OUT, OutLds>::value) out.store_d(b, g, v);
     else out.store(b, g, d2u_mod(v, b.pc->qd, b.pc->qinvd), pre);
 }
 
@@ -405,9 +442,10 @@ struct PhaseIdx {
     int p0, line;
     long blk;
     // false if unit it * 256 + threadIdx.x does not exist
-    __device__ __forceinline__ bool set(int it, long b)
+    __device__ __forceinline__ bool set(int it, long b) { return set(it, b, (int)threadIdx.x); }
+    __device__ __forceinline__ bool set(int it, long b, int tid)
     {
-        const int u = it * 256 + (int)threadIdx.x;
+        const int u = it * 256 + tid;
         if ((1 << LU) % 256 != 0 && u >= (1 << LU)) return false;
         int lo, hi;
         if (PASS == 1) {
@@ -459,14 +497,14 @@ struct PreBuf<0, N> {
 
 template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
-                                          const IN &in, const OUT &out, const PB &pre)
+                                          const IN &in, const OUT &out, PB &pre)
 {
     typedef PhaseIdx<LOGN, PASS, R, LS> I;
     const u64 q = bk.pc->q, q2 = 2 * q;
 #pragma unroll
     for (int it = 0; it < I::ITERS; it++) {
         I ix;
-        if (!ix.set(it, blk)) break;
+        if (!(OpaqueTid<OUT>::value ? ix.set(it, blk, bk.tid) : ix.set(it, blk))) break;
         u64 x[1 << R];
         if constexpr (FIRST && std::is_same<IN, InBconv>::value) {
             long g[1 << R];
@@ -528,7 +566,7 @@ __device__ __forceinline__ TwF tw_factored(const TwF *shA, const TwF *shB, int l
 
 template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const TwF *shA,
-                                             const TwF *shB, const IN &in, const OUT &out, const PB &pre)
+                                             const TwF *shB, const IN &in, const OUT &out, PB &pre)
 {
     typedef PhaseIdx<LOGN, PASS, R, LS> I;
     typedef NttGeo<LOGN> G;
@@ -536,7 +574,7 @@ __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk
 #pragma unroll
     for (int it = 0; it < I::ITERS; it++) {
         I ix;
-        if (!ix.set(it, blk)) break;
+        if (!(OpaqueTid<OUT>::value ? ix.set(it, blk, bk.tid) : ix.set(it, blk))) break;
         double x[1 << R];
         if constexpr (FIRST && std::is_same<IN, InBconv>::value) {
             long g[1 << R];
@@ -613,7 +651,7 @@ struct LastPhase {
 
 template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, const u64 *w, const u64 *wp,
-                                           const IN &in, const OUT &out, const PB &pre)
+                                           const IN &in, const OUT &out, PB &pre)
 {
     typedef NttGeo<LOGN> G;
     constexpr int LP = PASS == 1 ? G::LR : G::LC;
@@ -628,7 +666,7 @@ __device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, con
 
 template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const TwF *shA,
-                                              const TwF *shB, const IN &in, const OUT &out, const PB &pre)
+                                              const TwF *shB, const IN &in, const OUT &out, PB &pre)
 {
     typedef NttGeo<LOGN> G;
     constexpr int LP = PASS == 1 ? G::LR : G::LC;
@@ -710,6 +748,103 @@ __global__ void __launch_bounds__(256, (NttWaves<IN, OUT>::value)) k_ntt(NttTabl
     const u64 *w = (FWD ? T.fw : T.iw) + ((long)pi << LOGN);
     const u64 *wp = (FWD ? T.fwp : T.iwp) + ((long)pi << LOGN);
     ntt_phases<LOGN, PASS, FWD, 0, IN, OUT>(sh, bk, (long)blockIdx.x, w, wp, in, out, pre);
+}
+
+// ModUp's second pass fused with the key inner product, for the limbs on FP64
+// primes: a block owns one (limb, row tile) of one batch element and runs the
+// forward row pass of every digit's extended polynomial in turn (the digit's
+// own limb is the input polynomial itself, already in NTT form); each result
+// is left in LDS and multiplied there by the digit's two key words (standard
+// form, doubles), the products summed in registers, so the extended digits
+// never reach HBM; the two sums are stored reduced to [0, q).  A thread owns
+// tile words threadIdx.x + 256 k, so key, input and output accesses are
+// coalesced.  c = w / q is formed as w fl(1/q): each product is then within
+// q + 2^37 of zero and 16 digits stay below 2^50.  Blocks of one (limb, tile)
+// and different elements are placed on one XCD (hardware block b runs on XCD
+// b mod 8), so the tile's key words come from HBM once and then from L2.
+// mid: pass-1 output, limb t of polynomial p (= e ndig + j) at mid + t mid_ls + p mid_ps;
+// d: limb t of element e at d + t d_ls + e d_es; kf: digit j, component c, limb t at
+// kf + j kf_ds + c kf_cs + t N (doubles); acc: element e component c limb t at
+// acc + e acc_es + c acc_cs + t N.
+template <int LOGN>
+__global__ void __launch_bounds__(256, 4) k_modup_keyip(NttTables T, const u64 *mid, long mid_ls, long mid_ps,
+                                                        const u64 *d, long d_ls, long d_es, const double *kf,
+                                                        long kf_ds, long kf_cs, u64 *acc, long acc_es, long acc_cs,
+                                                        int ndig, int w, int nb, int limb_lo, int ngroups)
+{
+    typedef NttGeo<LOGN> G;
+    static_assert(G::LC == 8, "row tiles of 256-word rows");
+    constexpr int LT = G::LC + G::LRB;
+    constexpr int TWW = 2 * (256 + 8 * (1 << G::LRB));
+    constexpr long N = 1l << LOGN;
+    constexpr int TILES = 1 << (G::LR - G::LRB);
+    constexpr int NP = (1 << LT) / 256;  // words per thread
+    __shared__ u64 sh[(1 << LT) + TWW];
+    double *shd = reinterpret_cast<double *>(sh);
+    const int b = (int)blockIdx.x, i = b >> 3;
+    const int e = i % nb, grp = (i / nb) * 8 + (b & 7);
+    if (grp >= ngroups) return;
+    const int limb = limb_lo + grp / TILES;
+    const long tile = grp % TILES;
+    Blk bk;
+    bk.limb = limb;
+    bk.pc = T.pc + limb;  // Q limbs: limb index = prime index
+    bk.logN = LOGN;
+    const double q = bk.pc->qd, qi = bk.pc->qinvd;
+    const TwF *tw = T.ffw + ((long)limb << LOGN);
+    TwF *shB = reinterpret_cast<TwF *>(sh + (1 << LT)), *shA = shB + 256;
+    {
+        const TwF *gB = T.fb + (long)limb * 256;
+        const TwF *gA = T.fa + (((long)limb << G::LR) + (tile << G::LRB)) * 8;
+        const int t = (int)threadIdx.x;
+        shB[t] = gB[t];
+        if (t < 8 * (1 << G::LRB)) shA[t] = gA[t];
+    }
+    double a0[NP], a1[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) a0[k] = a1[k] = 0.0;
+    const int jown = limb / w;
+    for (int j = 0; j < ndig; j++) {
+        const double *k0 = kf + j * kf_ds + (long)limb * N, *k1 = k0 + kf_cs;
+        // a fresh copy of the thread index per digit: the transform's addresses
+        // are recomputed per digit instead of all being kept live across the loop
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const long g0 = (tile << LT) + tid;
+        if (j == jown) {
+            const u64 *dp = d + (long)limb * d_ls + (long)e * d_es;
+#pragma unroll
+            for (int k = 0; k < NP; k++) {
+                const long g = g0 + 256 * k;
+                const double x = u2d(dp[g]), w0 = k0[g], w1 = k1[g];
+                a0[k] += mulm_fp(x, w0, w0 * qi, q);
+                a1[k] += mulm_fp(x, w1, w1 * qi, q);
+            }
+            continue;
+        }
+        bk.poly = e * ndig + j;
+        bk.a = const_cast<u64 *>(mid) + (long)limb * mid_ls + (long)bk.poly * mid_ps;
+        bk.tid = tid;
+        __syncthreads();  // factor tables in place; the previous digit's LDS reads are done
+        PreBuf<0, 1> none;
+        ntt_phases_fp<LOGN, 2, true, 0, InMid, OutLds>(shd, bk, tile, tw, shA, shB, InMid(), OutLds{shd, (1 << LT) - 1}, none);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const long g = g0 + 256 * k;
+            const double x = shd[OutLds::word(tid + 256 * k)], w0 = k0[g], w1 = k1[g];
+            a0[k] += mulm_fp(x, w0, w0 * qi, q);
+            a1[k] += mulm_fp(x, w1, w1 * qi, q);
+        }
+    }
+    u64 *o0 = acc + (long)e * acc_es + (long)limb * N, *o1 = o0 + acc_cs;
+    const long g0 = (tile << LT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const long g = g0 + 256 * k;
+        o0[g] = d2u_mod(a0[k], q, qi);
+        o1[g] = d2u_mod(a1[k], q, qi);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -889,6 +1024,79 @@ void launch_modup(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int
     NTT_DISPATCH(modup_n, t, j, in, s, tm);
 }
 
+// ModUp with the key inner product fused into its second pass on the FP64
+// limbs [fp_lo, fp_hi): pass 1 for every non-own limb, pass 2 (stored) on the
+// other limbs, then k_modup_keyip on the FP64 limbs
+template <int LOGN>
+static void modup_keyip_n(const NttTables &t, const NttJob &j, const InBconv &in, const ModupKeyipArgs &a,
+                          hipStream_t s, KernelTimer *tm)
+{
+    typedef NttGeo<LOGN> G;
+    static_assert(G::LR > 0, "two passes");
+    const int nl = j.ps.nl, np = j.ps.npoly;
+    const double wb = 8.0 * (double)(1l << LOGN);
+    const double own = (double)(np / j.own_ndig) * j.own_nq;
+    dim3 blk(256), g1(1 << (G::LC - G::LTC), nl * np);
+    bool on = tm && tm->on(KID_NTT_FWD1);
+    if (on) tm->before(s);
+    hipLaunchKernelGGL((k_ntt<LOGN, 1, true, InBconv, OutMid>), g1, blk, 0, s, t, j.ps, j.lm, 0, 0, j.own_w, j.own_nq,
+                       j.own_ndig, in, OutMid());
+    if (on) tm->after(s, wb * (in.read_words(np, nl) + (double)nl * np - own),
+                      ((double)nl * np - own) * (double)(1l << (LOGN - 1)) * G::LR);
+    const int nfp = a.fp_hi - a.fp_lo, nli = nl - nfp;
+    // integer-prime limbs: the second pass stores the extended digits (own limbs skipped: 1 per
+    // element for the one own limb outside [fp_lo, fp_hi), the base prime)
+    dim3 g2(1 << (G::LR - G::LRB), nli * np);
+    on = tm && tm->on(KID_NTT_FWD2);
+    if (on) tm->before(s);
+    hipLaunchKernelGGL((k_ntt<LOGN, 2, true, InMid, OutWork<OW_REDUCE>>), g2, blk, 0, s, t, j.ps, j.lm, a.fp_lo,
+                       a.fp_hi, j.own_w, j.own_nq, j.own_ndig, InMid(), OutWork<OW_REDUCE>());
+    const double pi2 = (double)nli * np - (double)(np / j.own_ndig) * a.own_int;
+    if (on) tm->after(s, wb * 2.0 * pi2, pi2 * (double)(1l << (LOGN - 1)) * G::LC);
+    constexpr int TILES = 1 << (G::LR - G::LRB);
+    const int ngroups = nfp * TILES;
+    on = tm && tm->on(KID_MODUP_KEYIP);
+    if (on) tm->before(s);
+    hipLaunchKernelGGL((k_modup_keyip<LOGN>), dim3(((ngroups + 7) / 8) * 8 * a.nb), blk, 0, s, t, j.ps.base,
+                       j.ps.lstride, j.ps.pstride, a.d, a.d_ls, a.d_es, a.kf, a.kf_ds, a.kf_cs, a.acc, a.acc_es,
+                       a.acc_cs, j.own_ndig, j.own_w, a.nb, a.fp_lo, ngroups);
+    // per limb and element: ndig words read (pass-1 output or the input limb), two written;
+    // per limb: 2 ndig key words
+    if (on) tm->after(s, wb * nfp * ((double)a.nb * j.own_ndig + 2.0 * j.own_ndig + 2.0 * a.nb),
+                      (double)nfp * a.nb * (double)(1l << (LOGN - 1)) * G::LC * (j.own_ndig - 1));
+}
+
+void launch_modup_keyip(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
+                        const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], const u64 dbl[2],
+                        const ModupKeyipArgs &a, hipStream_t s, KernelTimer *tm)
+{
+    const long N = 1l << t.logN;
+    const int next = nq + alpha;
+    NttJob j;
+    j.ps = PolySet{ext, N, (long)next * N, next, ndig * nb};
+    j.lm = lm;
+    j.own_w = w;
+    j.own_nq = nq;
+    j.own_ndig = ndig;
+    InBconv in;
+    in.src = y;
+    in.src_bs = (long)nq * N;
+    in.src_ps = (long)w * N;
+    in.ndig = ndig;
+    in.hatm = hatm;
+    in.hat_ps = (long)w * next;
+    in.hat_ks = next;
+    in.ns_fixed = 0;
+    in.w = w;
+    in.nq = nq;
+    in.hatf = hatf;
+    in.wide[0] = wide[0];
+    in.wide[1] = wide[1];
+    in.dbl[0] = dbl[0];
+    in.dbl[1] = dbl[1];
+    NTT_DISPATCH(modup_keyip_n, t, j, in, a, s, tm);
+}
+
 // ModDown: yP [2][alpha][N] (inverse-hat-scaled P limbs, coefficient form) ->
 // forward transform of the conversion to Q_l, tail fused into the last store
 template <int LOGN>
@@ -942,7 +1150,8 @@ void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u6
     NttJob j;
     j.ps = PolySet{tmp, N, (long)l * N, l, npoly};
     j.lm = LimbMap{l, L1, 0};
-    InRescale ir{last, N, ql};
+    const bool small = ql < (1ull << 52);
+    InRescale ir{last, N, ql, small ? (double)ql : 0.0, small ? (double)(ql >> 1) : 0.0};
     OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp, pm, pmp, cadd};
     NTT_DISPATCH(rescale_n, t, j, ir, o, s, tm);
 }

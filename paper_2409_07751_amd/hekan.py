@@ -160,7 +160,7 @@ class Context:
         self.check(self.lib.he_ctx_sync(self.h))
 
     KERNELS = {"ntt_fwd_pass1": 0, "ntt_fwd_pass2": 1, "ntt_inv_pass2": 2, "ntt_inv_pass1": 3, "bconv": 4,
-               "keyip": 5}
+               "keyip": 5, "modup_keyip": 6}
 
     def profile(self, kernel):
         """Time every launch of `kernel` (a KERNELS name, or None to stop)."""
