@@ -239,6 +239,13 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
         pv[i] = hinv(P, q[i]);
         pv[L + 1 + i] = shoup_of(pv[i], q[i]);
     }
+    // then the same values as FP64 pairs (value, value / q_i)
+    pv.resize(4 * (L + 1));
+    for (int i = 0; i <= L; i++) {
+        const double w = (double)pv[i], c = w / (double)q[i];
+        std::memcpy(&pv[2 * (L + 1) + 2 * i], &w, 8);
+        std::memcpy(&pv[2 * (L + 1) + 2 * i + 1], &c, 8);
+    }
     pinv = alloc(pv.size());
     upload(pinv->p, pv.data(), pv.size());
     // ModDown constants: P-limb INTT scale (P/p_k)^-1 N^-1 mod p_k, and
@@ -426,12 +433,16 @@ const Buf &Ctx::rescale_table(int l, long k)
 {
     auto it = rescale_inv.find(std::make_pair(l, k));
     if (it != rescale_inv.end()) return it->second;
-    std::vector<u64> v(2 * l);
+    // [l] k q_l^-1 mod q_i, [l] Shoup words, [l] FP64 pairs (value, value / q_i)
+    std::vector<u64> v(4 * l);
     for (int i = 0; i < l; i++) {
         const long r = k % (long)q[i];
         const u64 km = r < 0 ? (u64)(r + (long)q[i]) : (u64)r;
         v[i] = hmul(hinv(q[l] % q[i], q[i]), km, q[i]);
         v[l + i] = shoup_of(v[i], q[i]);
+        const double w = (double)v[i], c = w / (double)q[i];
+        std::memcpy(&v[2 * l + 2 * i], &w, 8);
+        std::memcpy(&v[2 * l + 2 * i + 1], &c, 8);
     }
     Buf b = alloc(std::max<size_t>(v.size(), 1));
     if (l) upload(b->p, v.data(), v.size());
@@ -460,7 +471,7 @@ Ct Ctx::rescale_const_mul(const Ct &a, const Pt &pt, int t, const double *c)
     const Buf &inv = rescale_table(l, 1);
     const u64 *cadd = c ? rescale_addend(l, 1, *c) : nullptr;
     launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
-                       (long)N, inv->p, inv->p + l, w, w + P, cadd, L1, st, &timer);
+                       (long)N, inv->p, inv->p + l, (const TwF *)(inv->p + 2 * l), w, w + P, cadd, L1, st, &timer);
     n_launch += 4;
     return o;
 }
@@ -500,7 +511,8 @@ Ct Ctx::rescale_affine(const Ct &a, long k, const double *c)
     const Buf &inv = rescale_table(l, k);
     const u64 *cadd = c ? rescale_addend(l, k, *c) : nullptr;
     launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
-                       (long)N, inv->p, inv->p + l, nullptr, nullptr, cadd, L1, st, &timer);
+                       (long)N, inv->p, inv->p + l, (const TwF *)(inv->p + 2 * l), nullptr, nullptr, cadd, L1, st,
+                       &timer);
     n_launch += 4;
     return o;
 }
@@ -609,6 +621,7 @@ void Ctx::moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *bas
     Buf tmp = alloc((size_t)nb * 2 * nq * N);
     OutModdownArgs oa{acc->p, (long)N, (long)next * N, base, base_ls, base_es, (long)N, base_mask, galois, out.d(),
                       2l * N * nb, (long)N, pinv->p, pinv->p + L + 1};
+    oa.pinvf = (const TwF *)(pinv->p + 2 * (L + 1));
     if (addend) {
         if (addend->level != l || addend->nb != nb) throw HeError(-1, "rotate_add: operand shapes differ");
         oa.add = addend->d();

@@ -170,16 +170,18 @@ struct OutModdownArgs {
     // element e component c of limb i at add + i als + e aes + c N
     const u64 *add = nullptr;
     long als = 0, aes = 0;
+    const TwF *pinvf = nullptr;  // pinv as FP64 pairs (value, value / q_i), read on FP64 primes
 };
 // ModDown of npoly (= 2 nb) polynomials: out_p = base_p + (acc_p - NTT(BConv_{P->Q}(yP_p))) P^-1,
 // tmp [npoly][nq][N], yP [npoly][alpha][N]
 void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, LimbMap lm, const u64 *yP,
                     const u64 *hatm, long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
 // rescale by q_l of npoly polynomials: out_i = (in_i pm_i [+ cadd_i on even polynomials] - NTT_i([last + h] - h)) inv_i,
-// inv_i = k q_l^-1 mod q_i for an integer factor k; pm (Shoup words pmp) a per-limb factor, or null for 1
+// inv_i = k q_l^-1 mod q_i for an integer factor k (invf: as FP64 pairs (value, value / q_i), read on FP64
+// primes); pm (Shoup words pmp) a per-limb factor, or null for 1
 void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
                         long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
-                        const u64 *pm, const u64 *pmp, const u64 *cadd, int L1, hipStream_t s,
+                        const TwF *invf, const u64 *pm, const u64 *pmp, const u64 *cadd, int L1, hipStream_t s,
                         KernelTimer *tm = nullptr);
 // copy limbs
 void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);

@@ -314,6 +314,7 @@ struct OutRescaleFin {
     u64 *out;
     long ols, ops;
     const u64 *inv, *invp;
+    const TwF *invf;  // inv as FP64 pairs (value, value / q) for FP64 primes
     const u64 *pm, *pmp;
     const u64 *cadd;
     static constexpr int NPRE = 1;
@@ -329,6 +330,16 @@ struct OutRescaleFin {
         const u64 q = b.pc->q;
         v = reduce4(v, q);
         out[b.limb * ols + b.poly * ops + g] = shoup(subm(pre[0], v, q), inv[b.limb], invp[b.limb], q);
+    }
+    // FP64 prime: v is the transform's unreduced output (|v| <= 17q), the
+    // product is one exact FP64 modular product within 3q/4 of zero
+    __device__ void store_d(const Blk &b, long g, double v, const u64 *pre) const
+    {
+        const double q = b.pc->qd;
+        const TwF f = invf[b.limb];
+        double r = mulm_fp(u2d(pre[0]) - v, f.w, f.c, q);
+        r = r < 0.0 ? r + q : r;
+        out[b.limb * ols + b.poly * ops + g] = d2u_exact((u64)__double_as_longlong(r));
     }
 };
 
@@ -347,6 +358,7 @@ struct OutModdownFin {
     const u64 *pinv, *pinvp;
     const u64 *add;
     long als, aes;
+    const TwF *pinvf;  // pinv as FP64 pairs (value, value / q) for FP64 primes
     static constexpr int NPRE = 3;
     double extra_words(int npoly, int nl) const
     {
@@ -369,6 +381,17 @@ struct OutModdownFin {
         if (mask >> (b.poly & 1) & 1) r = addm(r, pre[1], q);
         if (add) r = addm(r, pre[2], q);
         out[b.limb * ols + b.poly * ops + g] = r;
+    }
+    // FP64 prime: (acc - v) P^-1 as one exact FP64 modular product (|v| <= 17q),
+    // plus the base and addend words (each below q), then reduced to [0, q)
+    __device__ void store_d(const Blk &b, long g, double v, const u64 *pre) const
+    {
+        const double q = b.pc->qd;
+        const TwF f = pinvf[b.limb];
+        double r = mulm_fp(u2d(pre[0]) - v, f.w, f.c, q);
+        if (mask >> (b.poly & 1) & 1) r += u2d(pre[1]);
+        if (add) r += u2d(pre[2]);
+        out[b.limb * ols + b.poly * ops + g] = d2u_mod(r, q, b.pc->qinvd);
     }
 };
 
@@ -422,6 +445,8 @@ __device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, d
 {
     if constexpr (std::is_same<OUT, OutMid>::value || std::is_same<OUT, OutScaleTabFp>::value) out.store_d(b, g, v);
     else if constexpr (std::is_same<OUT, OutLds>::value) out.store_d(b, g, v);
+    else if constexpr (std::is_same<OUT, OutRescaleFin>::value || std::is_same<OUT, OutModdownFin>::value)
+        out.store_d(b, g, v, pre);
     else out.store(b, g, d2u_mod(v, b.pc->qd, b.pc->qinvd), pre);
 }
 
@@ -1129,7 +1154,7 @@ void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, 
     in.wide[0] = in.wide[1] = 0;
     in.dbl[0] = in.dbl[1] = 0;
     OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.mask, a.galois, a.out, a.ols, a.ops,
-                    a.pinv, a.pinvp, a.add, a.als, a.aes};
+                    a.pinv, a.pinvp, a.add, a.als, a.aes, a.pinvf};
     NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
 }
 
@@ -1144,7 +1169,8 @@ static void rescale_n(const NttTables &t, const NttJob &j, const InRescale &in, 
 
 void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u64 *last, u64 ql, const u64 *in,
                         long in_ls, long in_ps, u64 *out, long out_ls, long out_ps, const u64 *inv, const u64 *invp,
-                        const u64 *pm, const u64 *pmp, const u64 *cadd, int L1, hipStream_t s, KernelTimer *tm)
+                        const TwF *invf, const u64 *pm, const u64 *pmp, const u64 *cadd, int L1, hipStream_t s,
+                        KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     NttJob j;
@@ -1152,7 +1178,7 @@ void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u6
     j.lm = LimbMap{l, L1, 0};
     const bool small = ql < (1ull << 52);
     InRescale ir{last, N, ql, small ? (double)ql : 0.0, small ? (double)(ql >> 1) : 0.0};
-    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp, pm, pmp, cadd};
+    OutRescaleFin o{in, in_ls, in_ps, out, out_ls, out_ps, inv, invp, invf, pm, pmp, cadd};
     NTT_DISPATCH(rescale_n, t, j, ir, o, s, tm);
 }
 
