@@ -146,6 +146,9 @@ def test_ops_bit_exact_tiny(tiny, tiny_keys):
         if lvl >= 2:
             z = np.random.default_rng(lvl).normal(size=octx.p.slots)
             same(ctx.lincomb([ca, cb], [0.25, -1.5], lvl - 2), ev.lincomb([(oa, 0.25), (ob, -1.5)], lvl - 2))
+            # one constant term: the product runs inside the rescale's passes
+            same(ctx.lincomb([ca], [-0.625], lvl - 2), ev.lincomb([(oa, -0.625)], lvl - 2))
+            same(ctx.lincomb([ca], [1.0], lvl - 1), ev.lincomb([(oa, 1.0)], lvl - 1))
             same(ctx.lincomb([ca, cb], [z, z[::-1].copy()], lvl - 1),
                  ev.lincomb([(oa, z), (ob, z[::-1].copy())], lvl - 1))
 
