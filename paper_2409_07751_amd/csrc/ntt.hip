@@ -490,8 +490,9 @@ struct PhaseIdx {
     }
     __device__ __forceinline__ long gidx(int k) const
     {
-        const int p = p0 + (k << LS);
-        return PASS == 1 ? ((long)p << G::LC) + (blk << G::LTC) + line : (((blk << G::LRB) + line) << G::LC) + p;
+        // positions are below N <= 2^16: 32-bit arithmetic
+        const int p = p0 + (k << LS), b = (int)blk;
+        return (long)(unsigned)(PASS == 1 ? (p << G::LC) + (b << G::LTC) + line : (((b << G::LRB) + line) << G::LC) + p);
     }
     // LDS word of position k.  Pass 2 keeps whole 256-word rows and XORs row
     // bits 4..6 into bits 0..3 (bit 4 -> 0, bit 5 -> 1 and 2, bit 6 -> 3), so
@@ -507,7 +508,10 @@ struct PhaseIdx {
     // the twiddle of the stage-h pair (k, k + 2^h) is entry
     // (N + gidx(k)) >> (LG + h + 1); bits [LG, LG + R) of gidx(0) are clear,
     // so that is tw0(h) + (k >> (h + 1))
-    __device__ __forceinline__ long tw0(int h) const { return ((1l << LOGN) + gidx(0)) >> (LG + h + 1); }
+    __device__ __forceinline__ long tw0(int h) const
+    {
+        return (long)(((1u << LOGN) + (unsigned)gidx(0)) >> (LG + h + 1));
+    }
 };
 
 // NPRE words per position of the last phase, loaded before the first phase
