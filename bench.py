@@ -182,6 +182,24 @@ def plain_path(ctx, model, keys, ct, steps):
             "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3), "steps": steps}
 
 
+def graph_path(ctx, model, keys, cts, steps, want, n_out):
+    """The same inference captured once into a HIP graph and replayed (the
+    host's launch cost off the device's critical path): inferences/s over
+    `steps` replays for this batch, and the replayed result's accuracy."""
+    graph, outs = ctx.capture_kan_batch(model, keys, cts)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    ctx.sync()
+    elapsed = time.perf_counter() - t0
+    err = max(float(np.abs(ctx.decrypt(keys, outs[i], n_out) - want[i]).max()) for i in range(len(cts)))
+    graph.free()
+    del outs
+    return {"batch": len(cts), "inferences_per_s": round(len(cts) * steps / elapsed, 4),
+            "ms_per_replay": round(elapsed / steps * 1e3, 3), "replays": steps, "max_abs_err_vs_fp64_circuit": err}
+
+
 SERVE_MIX = (("formula16", 0.5), ("image", 0.3), ("cifar", 0.2))
 
 
@@ -264,6 +282,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=10,
                     help="steps of the plain per-ciphertext path (batch 1) timed for comparison; 0 skips")
     ap.add_argument("--workload", default="image")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="replays of the inference captured into a HIP graph, at the batch and at batch 1 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--roofline-kernel", default="ntt_fwd_pass1")
@@ -360,6 +380,9 @@ def main():
     if args.plain_steps:
         res["plain_path"] = plain_path(ctx, model, keys, cts[0], args.plain_steps)
         res["batched_vs_plain"] = round(res["value"] / res["plain_path"]["inferences_per_s"], 3)
+    if args.graph_steps:
+        res["graph_path"] = [graph_path(ctx, model, keys, c, args.graph_steps, want, wl.shape[-1])
+                             for c in (cts, cts[:1])]
     if not args.no_serve:
         res["serving"], res["batched_mix"] = serve_run(args, res["value"])
     if not args.no_cpu_baseline:

@@ -54,6 +54,7 @@ typedef struct he_ctx he_ctx;
 typedef struct he_model he_model;
 typedef struct he_keys he_keys;
 typedef struct he_ct he_ct;
+typedef struct he_graph he_graph;
 
 /*
  * RNS-CKKS parameters (the paper's Experiment Setup fixes N = 2^16 with a
@@ -234,6 +235,23 @@ int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t 
  * model's input chunk count); out receives n ciphertexts. */
 int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
                       he_ct **out);
+
+/* A batched inference (as he_eval_kan_batch) captured once into a HIP graph
+ * and replayed: the schedule of one layer after another, for callers that
+ * evaluate the same request set repeatedly (and to take the host's launch
+ * cost off the device's critical path).  The call runs the inference once
+ * eagerly (filling every cache, so the captured run makes no host transfer or
+ * synchronisation) and then captures a second run on the context stream; out
+ * receives n ciphertexts holding its result.  Each he_graph_launch recomputes
+ * them in place, asynchronously on the context stream, from the current
+ * contents of the same input ciphertexts.  The graph keeps its inputs,
+ * outputs and temporaries allocated until he_graph_free (freeing the handles
+ * earlier is allowed); free it before its context.  Errors: HE_EINVAL for
+ * null arguments or n = 0, HE_EDEVICE if the runtime refuses the capture. */
+int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+                               he_ct **out, he_graph **g);
+int he_graph_launch(he_graph *g);
+int he_graph_free(he_graph *g);
 
 /* Run layer `layer` on n requests (all at the same level) in one batched
  * pass: the building block of layer-granular continuous batching.  For layer

@@ -23,6 +23,13 @@ struct he_ct {
     he_ctx *owner;
     Ct c;
 };
+struct he_graph {
+    he_ctx *owner;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<Ct> keep;                          // inputs and outputs the graph reads and writes
+    std::multimap<size_t, void *> held;           // temporaries, owned until the graph is freed
+};
 
 namespace {
 template <class F>
@@ -392,6 +399,82 @@ int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, in
         Ctx &c = *ctx->c;
         Ct res = eval_layer(c, *m->m, *k->k, batch_inputs(ctx, in, n, nin), (size_t)layer);
         for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, n == 1 ? res : c.unpack(res, (int)i));
+    });
+}
+
+int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+                               he_ct **out, he_graph **g)
+{
+    if (!ctx || !m || !k || !out || !g || !in || n == 0) return HE_EINVAL;
+    *g = nullptr;
+    for (size_t i = 0; i < n; i++) out[i] = nullptr;
+    return guard(ctx, [&]() {
+        check_model(ctx, m, k);
+        Ctx &c = *ctx->c;
+        const size_t nin = m->m->n_inputs();
+        // an eager run fills every cache and leaves the pool holding the buffers a run needs,
+        // so the captured run makes no host transfer and no synchronisation
+        {
+            Ct res = eval_model(c, *m->m, *k->k, batch_inputs(ctx, in, n, nin));
+            if (n > 1)
+                for (size_t i = 0; i < n; i++) (void)c.unpack(res, (int)i);
+        }
+        c.sync();
+        std::unique_ptr<he_graph> gr(new he_graph);
+        gr->owner = ctx;
+        const int timer = c.timer.target;
+        c.timer.target = -1;
+        c.pool.hold = &gr->held;
+        std::vector<Ct> outs;
+        HIP_CHECK(hipStreamBeginCapture(c.st, hipStreamCaptureModeRelaxed));
+        try {
+            Ct res = eval_model(c, *m->m, *k->k, batch_inputs(ctx, in, n, nin));
+            for (size_t i = 0; i < n; i++) outs.push_back(n == 1 ? res : c.unpack(res, (int)i));
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(c.st, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            c.pool.hold = nullptr;
+            c.timer.target = timer;
+            for (auto &h : gr->held) c.pool.free_.emplace(h.first, h.second), c.pool.cached += h.first;
+            throw;
+        }
+        c.pool.hold = nullptr;
+        c.timer.target = timer;
+        // the graph's temporaries count as live memory until the graph is freed
+        for (auto &h : gr->held) c.pool.live += h.first;
+        const hipError_t ec = hipStreamEndCapture(c.st, &gr->graph);
+        if (ec != hipSuccess || !gr->graph) {
+            for (auto &h : gr->held) c.pool.put(h.second, h.first);
+            throw HeError(HE_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ec));
+        }
+        HIP_CHECK(hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0));
+        // captured launches were recorded, not run: one launch computes the outputs
+        HIP_CHECK(hipGraphLaunch(gr->exec, c.st));
+        for (size_t i = 0; i < n * nin; i++) gr->keep.push_back(in[i]->c);
+        for (auto &o : outs) gr->keep.push_back(o);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, outs[i]);
+        *g = gr.release();
+    });
+}
+
+int he_graph_launch(he_graph *g)
+{
+    if (!g) return HE_EINVAL;
+    return guard(g->owner, [&]() { HIP_CHECK(hipGraphLaunch(g->exec, g->owner->c->st)); });
+}
+
+int he_graph_free(he_graph *g)
+{
+    if (!g) return HE_EINVAL;
+    return guard(g->owner, [&]() {
+        Ctx &c = *g->owner->c;
+        c.sync();
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        for (auto &h : g->held) c.pool.put(h.second, h.first);
+        g->keep.clear();
+        delete g;
     });
 }
 

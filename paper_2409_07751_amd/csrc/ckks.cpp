@@ -12,8 +12,18 @@ namespace hk {
 void *Pool::get(size_t bytes)
 {
     bytes = (bytes + 255) & ~(size_t)255;
-    auto it = free_.find(bytes);
     void *p = nullptr;
+    if (hold) {
+        auto h = hold->find(bytes);
+        if (h != hold->end()) {
+            p = h->second;
+            hold->erase(h);
+            live += bytes;
+            peak = std::max(peak, live);
+            return p;
+        }
+    }
+    auto it = free_.find(bytes);
     if (it != free_.end()) {
         p = it->second;
         free_.erase(it);
@@ -37,6 +47,10 @@ void Pool::put(void *p, size_t bytes)
 {
     bytes = (bytes + 255) & ~(size_t)255;
     live -= bytes;
+    if (hold) {
+        hold->emplace(bytes, p);
+        return;
+    }
     cached += bytes;
     free_.emplace(bytes, p);
 }

@@ -34,6 +34,10 @@ struct Ctx;
 struct Pool {
     std::multimap<size_t, void *> free_;
     size_t live = 0, cached = 0, peak = 0;
+    // while a graph is being captured, buffers released go to this list
+    // instead of the shared one: the capture reuses them (its launches run in
+    // order), and afterwards the graph owns them until it is destroyed
+    std::multimap<size_t, void *> *hold = nullptr;
     void *get(size_t bytes);
     void put(void *p, size_t bytes);
     void trim();

@@ -54,6 +54,10 @@ _SIGS = {
     "he_ctx_counters": [ctypes.c_void_p, _u64p, _u64p, _u64p],
     "he_ctx_sync": [ctypes.c_void_p],
     "he_ctx_profile": [ctypes.c_void_p, ctypes.c_int32],
+    "he_graph_capture_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "he_graph_launch": [ctypes.c_void_p],
+    "he_graph_free": [ctypes.c_void_p],
     "he_ctx_profile_read": [ctypes.c_void_p, _dp, _u64p, _dp, _dp],
     "he_model_compile": [ctypes.c_void_p, ctypes.POINTER(he_kan_desc), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_void_p)],
@@ -301,6 +305,32 @@ class Context:
         outs = (ctypes.c_void_p * n)()
         self.check(self.lib.he_eval_kan_batch(self.h, model.h, keys.h, arr, n, outs))
         return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+    def capture_kan_batch(self, model, keys, cts):
+        """he_graph_capture_kan_batch: returns (graph, outputs); graph.launch()
+        recomputes the outputs in place from the same inputs."""
+        n = len(cts)
+        flat = self._flat(cts)
+        arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
+        outs = (ctypes.c_void_p * n)()
+        g = ctypes.c_void_p()
+        self.check(self.lib.he_graph_capture_kan_batch(self.h, model.h, keys.h, arr, n, outs, ctypes.byref(g)))
+        return Graph(self, g), [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+class Graph:
+    """A captured batched inference (he_graph_*)."""
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def launch(self):
+        self.ctx.check(self.ctx.lib.he_graph_launch(self.h))
+
+    def free(self):
+        if self.h:
+            self.ctx.check(self.ctx.lib.he_graph_free(self.h))
+            self.h = None
 
 
 class Keys:
