@@ -43,10 +43,10 @@ enum {
     HE_OK = 0,
     HE_EINVAL = -1,  /* bad argument (null pointer, size, out of range)         */
     HE_ENOMEM = -2,  /* host or device allocation failed, or buffer too small   */
-    HE_EDEPTH = -3,  /* the circuit needs more levels than the parameters give  */
+    HE_EDEPTH = -3,  /* the circuit needs more levels than its operand has      */
     HE_ESHAPE = -4,  /* packing impossible: n_in (g+2k) slots exceed N/2       */
     HE_EKEY = -5,    /* a Galois key needed for a rotation was not generated    */
-    HE_EDEVICE = -6, /* a HIP call failed                                       */
+    HE_EDEVICE = -6, /* a HIP call or a kernel launch failed                    */
     HE_ESTATE = -7   /* handle used with the wrong context or in a bad state    */
 };
 
@@ -152,9 +152,12 @@ int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, doubl
 
 /* ------------------------------------------------------------------ model */
 
-/* Compile a KAN for encrypted evaluation: checks packing (HE_ESHAPE) and the
- * level budget of every layer (HE_EDEPTH), builds the fused weights
- * W_f = W' P (Algorithm 3) and records every rotation the circuit uses.
+/* Compile a KAN for encrypted evaluation: checks the layer shapes and their
+ * packing (HE_ESHAPE), builds the fused weights W_f = W' P (Algorithm 3) and
+ * records every rotation the circuit uses.  The level budget is checked when
+ * a layer is evaluated: an input whose level cannot hold the layer's circuit
+ * makes the evaluation return HE_EDEPTH (the step that would go below level
+ * 0 stops it; no ciphertext below level 0 is ever formed).
  * If refresh_between_layers is non-zero each layer starts at the top level
  * (the caller refreshes the ciphertext between layers with he_eval_kan_layer). */
 int he_model_compile(he_ctx *ctx, const he_kan_desc *desc, int32_t refresh_between_layers,

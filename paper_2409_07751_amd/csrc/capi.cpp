@@ -36,7 +36,12 @@ template <class F>
 int guard(he_ctx *ctx, F f)
 {
     try {
+        // a launch that fails (a grid the device rejects) leaves its error to be
+        // read back: clear what an earlier caller left and check after the call
+        (void)hipGetLastError();
         f();
+        const hipError_t le = hipGetLastError();
+        if (le != hipSuccess) throw HipError(std::string("kernel launch failed: ") + hipGetErrorString(le));
         return HE_OK;
     } catch (const HeError &e) {
         if (ctx) ctx->err = e.what();

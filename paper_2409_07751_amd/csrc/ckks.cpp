@@ -656,7 +656,8 @@ void Ctx::moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *bas
 void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
                     const u64 *base, long base_ls, long base_es, int base_mask, Ct &out, const Ct *addend)
 {
-    if (!ks_fused || !key.fbuf) {
+    // the fused kernel handles q_1..q_l; at level 0 there are none
+    if (!ks_fused || !key.fbuf || l == 0) {
         ModUp m = modup(d, ls, es, l, nb);
         keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out, addend);
         return;
@@ -836,6 +837,7 @@ Pt Ctx::vec_pt(const double *z, size_t n, double scale, int nl)
 Ct Ctx::lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t, const double *c)
 {
     if (terms.empty()) throw HeError(-1, "lincomb: no terms");
+    if (t < 0) throw HeError(-3, "lincomb: no level left");
     if (terms.size() == 1 && terms[0].second->is_const && terms[0].second->plain)
         return rescale_const_mul(*terms[0].first, *terms[0].second, t, c);
     const int nl = t + 2, nb = terms[0].first->nb;
@@ -874,6 +876,7 @@ Ct Ctx::level_down(const Ct &a, int t)
 {
     if (a.level == t) return a;
     if (a.level < t) throw HeError(-3, "level_down: target above operand");
+    if (t < 0) throw HeError(-3, "level_down: no level left");
     Pt one = const_pt(1.0, S[t] * (double)q[t + 1] / S[a.level], t + 2);
     return lincomb({{&a, &one}}, t);
 }

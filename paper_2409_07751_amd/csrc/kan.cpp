@@ -128,7 +128,11 @@ struct Eval {
     Model &m;
     Eval(Ctx &c_, const Keys &k_, Model &m_) : c(c_), k(k_), m(m_) {}
 
-    double X(int t, int lct) const { return c.S[t] * (double)c.q[t + 1] / c.S[lct]; }
+    double X(int t, int lct) const
+    {
+        if (t < 0) throw HeError(-3, "the circuit needs more levels than its input has");
+        return c.S[t] * (double)c.q[t + 1] / c.S[lct];
+    }
 
     // sum_i c_i x_i at level t [+ *cst]
     Ct lin_scalar(const std::vector<std::pair<const Ct *, double>> &terms, int t, const double *cst = nullptr)

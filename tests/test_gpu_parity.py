@@ -140,6 +140,13 @@ def test_ops_bit_exact_tiny(tiny, tiny_keys):
 
         same(ctx.add(ca, cb), ev.add(oa, ob))
         same(ctx.rescale(ca), ev.rescale(oa))
+        if lvl == 1:
+            # level 0: no scale prime left; rotations still switch keys
+            z0, z1 = ctx.rescale(ca), ctx.rescale(cb)
+            o0, o1 = ev.rescale(oa), ev.rescale(ob)
+            same(ctx.add(z0, z1), ev.add(o0, o1))
+            for s in (1, -1, 7):
+                same(ctx.rotate(keys, z0, s), ev.rotate(o0, s))
         same(ctx.mul(keys, ca, cb), ev.mul(oa, ob))
         for s in (1, -1, 7, 1024):
             same(ctx.rotate(keys, ca, s), ev.rotate(oa, s))
@@ -294,6 +301,40 @@ def test_batch_equals_single_image(image):
         assert (outs[i].export() == alone).all(), "request %d differs in the batch" % i
         y = ctx.decrypt(keys, outs[i], 10)
         assert np.abs(y - kan.he_friendly_kan(xs[i][None], layers)[0]).max() < 1e-2
+
+
+@pytest.mark.timeout(900)
+def test_batch16_benchmark_configuration(image):
+    """The configuration the benchmark times: the model compiled by the
+    product's host compile, 16 image requests with the benchmark's inputs and
+    seeds in one batch.  Sampled requests (first, middle, last) equal their
+    single evaluation residue for residue; all 16 decrypt within 1e-2 of the
+    FP64 HE-friendly circuit."""
+    from paper_2409_07751_amd import compile as pc
+    wl, ctx, octx = image
+    raw = synth.raw_weights(wl)
+    calib = synth.calibration_inputs(wl, 1024)
+    comp = [list(c) for c in wl.comp_degrees]
+    layers = pc.compile_kan(raw, calib, wl.silu_degree, comp, wl.grid, wl.silu_range, prescale=wl.prescale)
+    olayers = kan.compile_model(raw, calib, [wl.silu_degree] * 2, comp, wl.grid, wl.silu_range, prescale=wl.prescale)
+    model = ctx.compile(layers)
+    keys = ctx.keygen(synth.SEED_KEYGEN, model.rotation_steps())
+    B = 16
+    x = synth.inputs(wl, B)
+    cts = [ctx.encrypt(keys, x[i], synth.SEED_ENC + i) for i in range(B)]
+    note("image batch of 16")
+    outs = ctx.eval_kan_batch(model, keys, cts)
+    want = kan.he_friendly_kan(x, olayers)
+    for i in range(B):
+        y = ctx.decrypt(keys, outs[i], 10)
+        assert np.abs(y - want[i]).max() < 1e-2, "request %d" % i
+    for i in (0, 7, 15):
+        assert (outs[i].export() == ctx.eval_kan(model, keys, cts[i]).export()).all(), "request %d" % i
+    # a ragged batch (not a power of two) of the same requests
+    note("image batch of 5")
+    five = ctx.eval_kan_batch(model, keys, cts[3:8])
+    for j in range(5):
+        assert (five[j].export() == outs[3 + j].export()).all(), "request %d of the batch of 5" % j
 
 
 def test_kan_chunked_first_layer_bit_exact(tiny):

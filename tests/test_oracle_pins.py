@@ -316,6 +316,10 @@ def test_keyswitch_and_relinearisation(small):
     # rotating at a lower level and after a mod-drop
     c2 = ev.mod_drop(ca, 2)
     assert np.abs(ev.decrypt(ev.rotate(c2, 1), SMALL.slots) - np.roll(a, -1)).max() < 1e-6
+    # at level 0 (one digit of one limb, no scale prime left)
+    c0 = ev.mod_drop(ca, 0)
+    for t in (1, -1):
+        assert np.abs(ev.decrypt(ev.rotate(c0, t), SMALL.slots) - np.roll(a, -t)).max() < 1e-6
 
 
 def test_lincomb_and_level_down(small):
