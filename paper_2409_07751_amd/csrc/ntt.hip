@@ -238,6 +238,47 @@ struct InRescale {
         return __fma_rn(-rint(v * b.pc->qinvd), b.pc->qd, v);
     }
     double read_words(int npoly, int) const { return (double)npoly; }  // the dropped limb, shared by all limbs
+    // M positions at once: every word is requested before the first is used,
+    // so the M reads are in flight together
+    template <int M>
+    __device__ void load_many(const Blk &b, const long *g, u64 *x) const
+    {
+        const u64 *src = last + b.poly * last_ps;
+#pragma unroll
+        for (int m = 0; m < M; m++) x[m] = src[g[m]];
+        const u64 h = ql >> 1, hq = reduce64(h, *b.pc);
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            u64 r = x[m] + h;
+            r = r >= ql ? r - ql : r;
+            x[m] = subm(reduce64(r, *b.pc), hq, b.pc->q);
+        }
+    }
+    template <int M>
+    __device__ void load_many_d(const Blk &b, const long *g, double *x) const
+    {
+        const u64 *src = last + b.poly * last_ps;
+        u64 raw[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) raw[m] = src[g[m]];
+        if (qld == 0.0) {
+            const u64 h = ql >> 1, hq = reduce64(h, *b.pc);
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                u64 r = raw[m] + h;
+                r = r >= ql ? r - ql : r;
+                x[m] = u2d(subm(reduce64(r, *b.pc), hq, b.pc->q));
+            }
+            return;
+        }
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            double t = u2d(raw[m]) + hd;
+            t = t >= qld ? t - qld : t;
+            const double v = t - hd;
+            x[m] = __fma_rn(-rint(v * b.pc->qinvd), b.pc->qd, v);
+        }
+    }
 };
 
 // Output policies.  NPRE > 0: the policy reads NPRE further words per output
@@ -306,8 +347,7 @@ struct OutScaleTabFp {
 // pm, if set, a per-limb factor the input is multiplied by when it is fetched
 // (Shoup words pmp); cadd, if set, holds per limb a word added to component 0 (polynomial
 // p = 2 e + c, c = 0) of every ciphertext before the subtraction: a constant
-// c lands in the output as cadd = c / inv (mod q_i), so the addition happens
-// in the prefetch, away from the store's register peak
+// c lands in the output as cadd = c / inv (mod q_i)
 struct OutRescaleFin {
     const u64 *in;
     long ls, ps;
@@ -319,9 +359,13 @@ struct OutRescaleFin {
     const u64 *cadd;
     static constexpr int NPRE = 1;
     double extra_words(int npoly, int nl) const { return (double)npoly * nl; }
-    __device__ void fetch(const Blk &b, long g, u64 *pre) const
+    // the word is only requested here (nothing uses it yet, so every prefetch
+    // of the block is in flight together); prepare() applies the factor and
+    // the constant once the last phase begins, before the block's first store
+    __device__ void fetch(const Blk &b, long g, u64 *pre) const { pre[0] = in[b.limb * ls + b.poly * ps + g]; }
+    __device__ void prepare(const Blk &b, u64 *pre) const
     {
-        u64 x = in[b.limb * ls + b.poly * ps + g];
+        u64 x = pre[0];
         if (pm) x = shoup(x, pm[b.limb], pmp[b.limb], b.pc->q);
         pre[0] = cadd && (b.poly & 1) == 0 ? addm(x, cadd[b.limb], b.pc->q) : x;
     }
@@ -440,6 +484,22 @@ __device__ __forceinline__ double load_fp(const IN &in, const Blk &b, long g)
     else return u2d(in.load(b, g));  // every other input policy yields words below 4q
 }
 
+// an output policy with prepare() transforms its prefetched words in place
+// when the last phase begins
+template <class T, class = void>
+struct HasPrepare : std::false_type {};
+template <class T>
+struct HasPrepare<T, std::void_t<decltype(&T::prepare)>> : std::true_type {};
+template <class OUT, class PB>
+__device__ __forceinline__ void prepare_pre(const OUT &out, const Blk &bk, PB &pre)
+{
+    if constexpr (HasPrepare<OUT>::value) {
+        constexpr int n = sizeof(pre.v) / sizeof(pre.v[0]);
+#pragma unroll
+        for (int i = 0; i < n; i++) out.prepare(bk, pre.v[i]);
+    }
+}
+
 template <class OUT>
 __device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, double v, u64 *pre)
 {
@@ -530,12 +590,13 @@ __device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, cons
 {
     typedef PhaseIdx<LOGN, PASS, R, LS> I;
     const u64 q = bk.pc->q, q2 = 2 * q;
+    if constexpr (LAST) prepare_pre(out, bk, pre);
 #pragma unroll
     for (int it = 0; it < I::ITERS; it++) {
         I ix;
         if (!(OpaqueTid<OUT>::value ? ix.set(it, blk, bk.tid) : ix.set(it, blk))) break;
         u64 x[1 << R];
-        if constexpr (FIRST && std::is_same<IN, InBconv>::value) {
+        if constexpr (FIRST && (std::is_same<IN, InBconv>::value || std::is_same<IN, InRescale>::value)) {
             long g[1 << R];
 #pragma unroll
             for (int k = 0; k < (1 << R); k++) g[k] = ix.gidx(k);
@@ -593,26 +654,30 @@ __device__ __forceinline__ TwF tw_factored(const TwF *shA, const TwF *shB, int l
     return t;
 }
 
-template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, class IN, class OUT, class PB>
+// PX: the first phase's words were loaded by the caller into px (position k of
+// iteration it at px[(it << R) + k])
+template <int LOGN, int PASS, bool FWD, int R, int LS, bool FIRST, bool LAST, bool PX, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const TwF *shA,
-                                             const TwF *shB, const IN &in, const OUT &out, PB &pre)
+                                             const TwF *shB, const IN &in, const OUT &out, PB &pre, const double *px)
 {
     typedef PhaseIdx<LOGN, PASS, R, LS> I;
     typedef NttGeo<LOGN> G;
     const double q = bk.pc->qd, qi = bk.pc->qinvd;
+    if constexpr (LAST) prepare_pre(out, bk, pre);
 #pragma unroll
     for (int it = 0; it < I::ITERS; it++) {
         I ix;
         if (!(OpaqueTid<OUT>::value ? ix.set(it, blk, bk.tid) : ix.set(it, blk))) break;
         double x[1 << R];
-        if constexpr (FIRST && std::is_same<IN, InBconv>::value) {
+        if constexpr (FIRST && (std::is_same<IN, InBconv>::value || std::is_same<IN, InRescale>::value)) {
             long g[1 << R];
 #pragma unroll
             for (int k = 0; k < (1 << R); k++) g[k] = ix.gidx(k);
             in.template load_many_d<(1 << R)>(bk, g, x);
         } else {
 #pragma unroll
-            for (int k = 0; k < (1 << R); k++) x[k] = FIRST ? load_fp(in, bk, ix.gidx(k)) : sh[ix.lidx(k)];
+            for (int k = 0; k < (1 << R); k++)
+                x[k] = FIRST ? (PX ? px[(it << R) + k] : load_fp(in, bk, ix.gidx(k))) : sh[ix.lidx(k)];
         }
         if (FWD) {
 #pragma unroll
@@ -693,20 +758,51 @@ __device__ __forceinline__ void ntt_phases(u64 *sh, const Blk &bk, long blk, con
     }
 }
 
-template <int LOGN, int PASS, bool FWD, int PH, class IN, class OUT, class PB>
+template <int LOGN, int PASS, bool FWD, int PH, bool PX, class IN, class OUT, class PB>
 __device__ __forceinline__ void ntt_phases_fp(double *sh, const Blk &bk, long blk, const TwF *tw, const TwF *shA,
-                                              const TwF *shB, const IN &in, const OUT &out, PB &pre)
+                                              const TwF *shB, const IN &in, const OUT &out, PB &pre,
+                                              const double *px)
 {
     typedef NttGeo<LOGN> G;
     constexpr int LP = PASS == 1 ? G::LR : G::LC;
     typedef PhasePlan<LP, FWD, PH> P;
     constexpr bool first = PH == 0, last = PH == P::NPH - 1;
-    ntt_phase_fp<LOGN, PASS, FWD, P::R, P::LS, first, last, IN, OUT>(sh, bk, blk, tw, shA, shB, in, out, pre);
+    ntt_phase_fp<LOGN, PASS, FWD, P::R, P::LS, first, last, PX && first, IN, OUT>(sh, bk, blk, tw, shA, shB, in, out,
+                                                                                  pre, px);
     if constexpr (!last) {
         __syncthreads();
-        ntt_phases_fp<LOGN, PASS, FWD, PH + 1, IN, OUT>(sh, bk, blk, tw, shA, shB, in, out, pre);
+        ntt_phases_fp<LOGN, PASS, FWD, PH + 1, false, IN, OUT>(sh, bk, blk, tw, shA, shB, in, out, pre, nullptr);
     }
 }
+
+// Whether k_ntt loads its row pass's first phase ahead of the factor tables
+// and keeps a private copy of the prime's constants: not for the ModDown
+// tail, which already holds three prefetched words per position (measured
+// slower with the first phase loaded early, and the copy makes it spill)
+template <class OUT>
+struct RowPreload {
+    static constexpr bool value = !std::is_same<OUT, OutModdownFin>::value;
+};
+
+// The words of a row pass's first phase (pass 2), loaded ahead of the block's
+// LDS set-up so that their reads overlap the factor-table reads and barrier
+template <int LOGN, bool FWD>
+struct RowFirst {
+    typedef PhasePlan<NttGeo<LOGN>::LC, FWD, 0> P;
+    typedef PhaseIdx<LOGN, 2, P::R, P::LS> I;
+    static constexpr int NX = I::ITERS << P::R;
+    template <class IN>
+    __device__ __forceinline__ static void load(const IN &in, const Blk &bk, long blk, int tid, double *px)
+    {
+#pragma unroll
+        for (int it = 0; it < I::ITERS; it++) {
+            I ix;
+            if (!ix.set(it, blk, tid)) break;
+#pragma unroll
+            for (int k = 0; k < (1 << P::R); k++) px[(it << P::R) + k] = load_fp(in, bk, ix.gidx(k));
+        }
+    }
+};
 
 // minimum waves per SIMD the compiler must leave room for: the ModDown tail
 // holds three prefetched words per position and would otherwise take just
@@ -745,7 +841,15 @@ __global__ void __launch_bounds__(256, (NttWaves<IN, OUT>::value)) k_ntt(NttTabl
     bk.a = ps.base + (long)limb * ps.lstride + (long)poly * ps.pstride;
     bk.limb = limb;
     bk.poly = poly;
-    bk.pc = T.pc + pi;
+    // a private copy of the prime's constants: held in registers, so the
+    // phases' barriers (which order memory) do not make them be read again
+    PrimeConst pcl;
+    if constexpr (RowPreload<OUT>::value) {
+        pcl = T.pc[pi];
+        bk.pc = &pcl;
+    } else {
+        bk.pc = T.pc + pi;
+    }
     bk.logN = LOGN;
     typedef LastPhase<LOGN, PASS, FWD> LPh;
     PreBuf<OUT::NPRE, LPh::NPOS> pre;
@@ -762,16 +866,33 @@ __global__ void __launch_bounds__(256, (NttWaves<IN, OUT>::value)) k_ntt(NttTabl
         const TwF *tw = (FWD ? T.ffw : T.fiw) + ((long)pi << LOGN);
         TwF *shB = reinterpret_cast<TwF *>(sh + (1 << LT)), *shA = shB + 256;
         if constexpr (PASS == 2) {
+            static_assert(!OpaqueTid<OUT>::value, "row pass of k_ntt indexes by threadIdx.x");
+            constexpr bool early = RowPreload<OUT>::value;
+            double px[RowFirst<LOGN, FWD>::NX];
+            if constexpr (early) RowFirst<LOGN, FWD>::load(in, bk, (long)blockIdx.x, (int)threadIdx.x, px);
             // the prime's B table and the block's rows of A, read once into LDS
             const TwF *gB = (FWD ? T.fb : T.ib) + (long)pi * 256;
             const TwF *gA = (FWD ? T.fa : T.ia) + (((long)pi << G::LR) + ((long)blockIdx.x << G::LRB)) * 8;
             const int t = (int)threadIdx.x;
-            shB[t] = gB[t];
-            if (t < 8 * (1 << G::LRB)) shA[t] = gA[t];
+            if constexpr (early) {
+                // both reads issued before either is used: the A index wraps, every
+                // thread reads and stores an entry of the block's rows (threads t
+                // and t + 64 store the same value at the same place)
+                const int ta = t & (8 * (1 << G::LRB) - 1);
+                const TwF vb = gB[t], va = gA[ta];
+                shB[t] = vb;
+                shA[ta] = va;
+            } else {
+                shB[t] = gB[t];
+                if (t < 8 * (1 << G::LRB)) shA[t] = gA[t];
+            }
             __syncthreads();
+            ntt_phases_fp<LOGN, PASS, FWD, 0, early, IN, OUT>(reinterpret_cast<double *>(sh), bk, (long)blockIdx.x, tw,
+                                                              shA, shB, in, out, pre, px);
+        } else {
+            ntt_phases_fp<LOGN, PASS, FWD, 0, false, IN, OUT>(reinterpret_cast<double *>(sh), bk, (long)blockIdx.x,
+                                                              tw, shA, shB, in, out, pre, nullptr);
         }
-        ntt_phases_fp<LOGN, PASS, FWD, 0, IN, OUT>(reinterpret_cast<double *>(sh), bk, (long)blockIdx.x, tw, shA,
-                                                   shB, in, out, pre);
         return;
     }
     const u64 *w = (FWD ? T.fw : T.iw) + ((long)pi << LOGN);
@@ -817,18 +938,13 @@ __global__ void __launch_bounds__(256, 4) k_modup_keyip(NttTables T, const u64 *
     const long tile = grp % TILES;
     Blk bk;
     bk.limb = limb;
-    bk.pc = T.pc + limb;  // Q limbs: limb index = prime index
+    const PrimeConst pcl = T.pc[limb];  // Q limbs: limb index = prime index; kept in registers
+    bk.pc = &pcl;
     bk.logN = LOGN;
     const double q = bk.pc->qd, qi = bk.pc->qinvd;
     const TwF *tw = T.ffw + ((long)limb << LOGN);
     TwF *shB = reinterpret_cast<TwF *>(sh + (1 << LT)), *shA = shB + 256;
-    {
-        const TwF *gB = T.fb + (long)limb * 256;
-        const TwF *gA = T.fa + (((long)limb << G::LR) + (tile << G::LRB)) * 8;
-        const int t = (int)threadIdx.x;
-        shB[t] = gB[t];
-        if (t < 8 * (1 << G::LRB)) shA[t] = gA[t];
-    }
+    bool tables = false;
     double a0[NP], a1[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) a0[k] = a1[k] = 0.0;
@@ -854,9 +970,27 @@ __global__ void __launch_bounds__(256, 4) k_modup_keyip(NttTables T, const u64 *
         bk.poly = e * ndig + j;
         bk.a = const_cast<u64 *>(mid) + (long)limb * mid_ls + (long)bk.poly * mid_ps;
         bk.tid = tid;
+        // the digit's first-phase words are requested before the barrier (and,
+        // for the first digit, before the factor tables), so their reads overlap
+        double px[RowFirst<LOGN, true>::NX];
+        RowFirst<LOGN, true>::load(InMid(), bk, tile, tid, px);
+        if (!tables) {
+            const TwF *gB = T.fb + (long)limb * 256;
+            const TwF *gA = T.fa + (((long)limb << G::LR) + (tile << G::LRB)) * 8;
+            const int t = (int)threadIdx.x;
+            // both reads issued before either is used: the A index wraps, every
+            // thread reads and stores an entry of the block's rows (threads t and
+            // t + 64 store the same value at the same place)
+            const int ta = t & (8 * (1 << G::LRB) - 1);
+            const TwF vb = gB[t], va = gA[ta];
+            shB[t] = vb;
+            shA[ta] = va;
+            tables = true;
+        }
         __syncthreads();  // factor tables in place; the previous digit's LDS reads are done
         PreBuf<0, 1> none;
-        ntt_phases_fp<LOGN, 2, true, 0, InMid, OutLds>(shd, bk, tile, tw, shA, shB, InMid(), OutLds{shd, (1 << LT) - 1}, none);
+        ntt_phases_fp<LOGN, 2, true, 0, true, InMid, OutLds>(shd, bk, tile, tw, shA, shB, InMid(),
+                                                              OutLds{shd, (1 << LT) - 1}, none, px);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NP; k++) {
