@@ -876,8 +876,10 @@ __global__ void __launch_bounds__(256, (NttWaves<IN, OUT>::value)) k_ntt(NttTabl
             const int t = (int)threadIdx.x;
             if constexpr (early) {
                 // both reads issued before either is used: the A index wraps, every
-                // thread reads and stores an entry of the block's rows (threads t
-                // and t + 64 store the same value at the same place)
+                // thread reads and stores an entry of the block's rows (threads
+                // whose indices differ by a multiple of 8 2^LRB store the same
+                // value at the same place)
+                static_assert(8 * (1 << G::LRB) <= 256, "one A entry per thread at most");
                 const int ta = t & (8 * (1 << G::LRB) - 1);
                 const TwF vb = gB[t], va = gA[ta];
                 shB[t] = vb;
@@ -979,8 +981,10 @@ __global__ void __launch_bounds__(256, 4) k_modup_keyip(NttTables T, const u64 *
             const TwF *gA = T.fa + (((long)limb << G::LR) + (tile << G::LRB)) * 8;
             const int t = (int)threadIdx.x;
             // both reads issued before either is used: the A index wraps, every
-            // thread reads and stores an entry of the block's rows (threads t and
-            // t + 64 store the same value at the same place)
+            // thread reads and stores an entry of the block's rows (threads whose
+            // indices differ by a multiple of 8 2^LRB store the same value at the
+            // same place)
+            static_assert(8 * (1 << G::LRB) <= 256, "one A entry per thread at most");
             const int ta = t & (8 * (1 << G::LRB) - 1);
             const TwF vb = gB[t], va = gA[ta];
             shB[t] = vb;
