@@ -294,8 +294,9 @@ def main():
                     help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every box in this setup has a single MI355X "
-              "(requests shard across GPUs with no exchange on the hot path; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): requests are independent, so N GPUs would "
+              "serve N queues, each with its own copy of the evaluation keys and no exchange on the "
+              "hot path", file=sys.stderr)
         sys.exit(2)
 
     from paper_2409_07751_amd import compile as pc
