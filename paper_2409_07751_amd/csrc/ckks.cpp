@@ -262,6 +262,16 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
     }
     pinv = alloc(pv.size());
     upload(pinv->p, pv.data(), pv.size());
+    // P mod q_i and Shoup words (the rescale term of the merged ModDown)
+    std::vector<u64> pmv(2 * (L + 1));
+    for (int i = 0; i <= L; i++) {
+        u64 P = 1;
+        for (u64 pj : p) P = hmul(P, pj % q[i], q[i]);
+        pmv[i] = P;
+        pmv[L + 1 + i] = shoup_of(P, q[i]);
+    }
+    pmod = alloc(pmv.size());
+    upload(pmod->p, pmv.data(), pmv.size());
     // ModDown constants: P-limb INTT scale (P/p_k)^-1 N^-1 mod p_k, and
     // (P/p_k) mod q_i in Montgomery form
     std::vector<u64> md(2 * alpha + (size_t)alpha * (L + 1));
@@ -302,6 +312,7 @@ Ctx::~Ctx()
     const_plain_cache.clear();
     int_cache.clear();
     pinv.reset();
+    pmod.reset();
     tw_buf.reset();
     twf_buf.reset();
     twab_buf.reset();
@@ -607,8 +618,7 @@ Ctx::ModUp Ctx::modup(const u64 *d, long ls, long es, int l, int nb)
     return m;
 }
 
-void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
-                         long base_es, int base_mask, Ct &out, const Ct *addend)
+Buf Ctx::inner_product(const ModUp &m, const SwitchKey &key)
 {
     n_ks += m.nb;
     const int l = m.l, nb = m.nb, nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
@@ -619,7 +629,14 @@ void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const
                      logN, st, &timer) != 0)
         throw HeError(-1, "key switch: " + std::to_string(nd) + " digits (at most 16 supported)");
     n_launch++;
-    moddown_into(acc, l, nb, galois, base, base_ls, base_es, base_mask, out, addend);
+    return acc;
+}
+
+void Ctx::keyswitch_from(const ModUp &m, const SwitchKey &key, u64 galois, const u64 *base, long base_ls,
+                         long base_es, int base_mask, Ct &out, const Ct *addend)
+{
+    Buf acc = inner_product(m, key);
+    moddown_into(acc, m.l, m.nb, galois, base, base_ls, base_es, base_mask, out, addend);
 }
 
 void Ctx::moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *base, long base_ls, long base_es,
@@ -656,12 +673,16 @@ void Ctx::moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *bas
 void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key, u64 galois,
                     const u64 *base, long base_ls, long base_es, int base_mask, Ct &out, const Ct *addend)
 {
+    Buf acc = keyswitch_acc(d, ls, es, l, nb, key);
+    moddown_into(acc, l, nb, galois, base, base_ls, base_es, base_mask, out, addend);
+}
+
+// ModUp and the key inner product of a key switch: the accumulators
+// [nb][2][l+1+alpha][N], before ModDown
+Buf Ctx::keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key)
+{
     // the fused kernel handles q_1..q_l; at level 0 there are none
-    if (!ks_fused || !key.fbuf || l == 0) {
-        ModUp m = modup(d, ls, es, l, nb);
-        keyswitch_from(m, key, galois, base, base_ls, base_es, base_mask, out, addend);
-        return;
-    }
+    if (!ks_fused || !key.fbuf || l == 0) return inner_product(modup(d, ls, es, l, nb), key);
     // ModUp with the inner product fused into the second pass on q_1..q_l; the
     // extended digits are stored only on q_0 and the special primes, whose
     // inner product follows separately
@@ -683,7 +704,45 @@ void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchK
                  key.buf->p, 2l * ktot * N, (long)ktot * N, nd, 1 + alpha, 1, nq, nq, w, nb, lm, L1, logN, st, &timer);
     ext.reset();
     n_launch += 6;
-    moddown_into(acc, l, nb, galois, base, base_ls, base_es, base_mask, out, addend);
+    return acc;
+}
+
+// ModDown of a relinearisation's accumulators followed by the rescale by q_l,
+// in the residues of moddown_into and rescale_affine but with one forward
+// transform per limb instead of two: limb l of the sum goes first (ModDown of
+// that limb alone, then to coefficient form); every other limb's transform
+// then takes ModDown's conversion plus P (mod q_i) times the rescale's input
+// word, and its tail forms (base + (acc - v) P^-1) k q_l^-1 (the transform is
+// linear, so this is (c_i - NTT(r_i)) k q_l^-1 with c = base + ModDown(acc))
+void Ctx::moddown_rescale_into(const Buf &acc, int l, int nb, const u64 *base, long base_ls, long base_es, long k,
+                               const double *cadd, Ct &out)
+{
+    const int nq = l + 1, next = nq + alpha, np = 2 * nb;
+    n_rescale++;
+    Buf yP = alloc((size_t)np * alpha * N);
+    launch_intt_from(T, PolySet{yP->p, (long)N, (long)alpha * N, alpha, np}, LimbMap{0, L1},
+                     acc->p + (size_t)nq * N, (long)N, (long)next * N, 0, md_tab->p, md_tab->p + alpha, st, &timer);
+    // limb l: ModDown of that limb alone (prime q_l through the limb map's offset,
+    // every table and operand pointer moved to limb l), then coefficient form
+    Buf cl = alloc((size_t)np * N), wl = alloc((size_t)np * N), last = alloc((size_t)np * N);
+    OutModdownArgs oa{acc->p + (size_t)l * N, (long)N, (long)next * N, base + (size_t)l * base_ls, base_ls, base_es,
+                      (long)N, 3, 0, cl->p, 0, (long)N, pinv->p + l, pinv->p + L + 1 + l};
+    oa.pinvf = (const TwF *)(pinv->p + 2 * (L + 1)) + l;
+    launch_moddown(T, wl->p, 1, alpha, np, LimbMap{1, L1, l}, yP->p, md_tab->p + 2 * alpha + l, L + 1, oa, st,
+                   &timer);
+    launch_intt_from(T, PolySet{last->p, (long)N, (long)N, 1, np}, LimbMap{1, L1, l}, cl->p, (long)N, (long)N, 0,
+                     nullptr, nullptr, st, &timer);
+    wl.reset();
+    // limbs 0..l-1
+    Buf tmp = alloc((size_t)l * np * N);
+    const Buf &inv = rescale_table(l, k);
+    OutModdownRescaleArgs ra{acc->p, (long)N, (long)next * N, base, base_ls, base_es, (long)N, out.d(),
+                             2l * N * nb, (long)N, pinv->p, pinv->p + L + 1,
+                             (const TwF *)(pinv->p + 2 * (L + 1)), inv->p, inv->p + l,
+                             (const TwF *)(inv->p + 2 * l), cadd ? rescale_addend(l, k, *cadd) : nullptr};
+    launch_moddown_rescale(T, tmp->p, l, alpha, np, yP->p, md_tab->p + 2 * alpha, L + 1, last->p, q[l],
+                           pmod->p, pmod->p + L + 1, ra, L1, st, &timer);
+    n_launch += 8;
 }
 
 Tensor Ctx::tensor(const Ct &a, const Ct &b)
@@ -710,9 +769,15 @@ void Ctx::tensor_acc(Tensor &t, const Ct &a, const Ct &b)
 
 Ct Ctx::relin_rescale(const Tensor &t, const Keys &k, long mul, const double *cadd)
 {
-    Ct c = new_ct(t.level, t.nb);
     const u64 *tb = t.buf->p;
     const long ls = 3l * N * t.nb, es = 3l * N;
+    if (t.level >= 1) {
+        Buf acc = keyswitch_acc(tb + 2 * (size_t)N, ls, es, t.level, t.nb, k.relin);
+        Ct o = new_ct(t.level - 1, t.nb);
+        moddown_rescale_into(acc, t.level, t.nb, tb, ls, es, mul, cadd, o);
+        return o;
+    }
+    Ct c = new_ct(t.level, t.nb);
     keyswitch(tb + 2 * (size_t)N, ls, es, t.level, t.nb, k.relin, 0, tb, ls, es, 3, c);
     return rescale_affine(c, mul, cadd);
 }

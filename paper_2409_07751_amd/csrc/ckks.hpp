@@ -121,6 +121,7 @@ struct Ctx {
     std::map<std::pair<int, long>, Buf> rescale_inv;  // per (level l, factor k): [2][l] k q_l^-1, Shoup
     std::map<std::tuple<int, long, u64>, Buf> rescale_add;  // per (l, k, constant bits): [l] pre-rescale addend
     Buf pinv;                        // [2][L+1] P^-1 mod q_i and Shoup
+    Buf pmod;                        // [2][L+1] P mod q_i and Shoup
     Buf md_tab;                      // [2][alpha] P-limb INTT scale, then [alpha][L+1] P->Q constants
     std::map<std::pair<u64, u64>, Buf> const_cache;
     std::map<std::pair<u64, u64>, Buf> const_plain_cache;
@@ -199,6 +200,13 @@ struct Ctx {
     // ModDown of the accumulators acc [nb][2][l+1+alpha][N] into out (base and addend as in keyswitch_from)
     void moddown_into(const Buf &acc, int l, int nb, u64 galois, const u64 *base, long base_ls, long base_es,
                       int base_mask, Ct &out, const Ct *addend);
+    // ModUp and inner product of a key switch (the accumulators before ModDown)
+    Buf keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key);
+    Buf inner_product(const ModUp &m, const SwitchKey &key);
+    // relinearisation tail: base (both components) + ModDown(acc), rescaled by q_l
+    // with factor k and constant *cadd, into out at level l - 1
+    void moddown_rescale_into(const Buf &acc, int l, int nb, const u64 *base, long base_ls, long base_es, long k,
+                              const double *cadd, Ct &out);
     // batches of single ciphertexts at one level
     Ct pack(const std::vector<const Ct *> &cts);
     Ct unpack(const Ct &batch, int e);

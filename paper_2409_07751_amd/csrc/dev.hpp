@@ -176,6 +176,25 @@ struct OutModdownArgs {
 // tmp [npoly][nq][N], yP [npoly][alpha][N]
 void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, LimbMap lm, const u64 *yP,
                     const u64 *hatm, long hat_ks, const OutModdownArgs &a, hipStream_t s, KernelTimer *tm = nullptr);
+// ModDown followed by the rescale by q_l, for a relinearisation (no automorphism, both
+// base components): limbs i < l of out = (base_i [+ cadd_i on component 0] + KS_i) k q_l^-1,
+// where KS is the ModDown of acc; `last` holds limb l of that sum in coefficient form
+struct OutModdownRescaleArgs {
+    const u64 *acc;
+    long acc_ls, acc_ps;
+    const u64 *base;
+    long bls, bes, bcs;
+    u64 *out;
+    long ols, ops;
+    const u64 *pinv, *pinvp;
+    const TwF *pinvf;
+    const u64 *inv, *invp;  // k q_l^-1 mod q_i and Shoup words
+    const TwF *invf;
+    const u64 *cadd;        // null, or per limb the constant c / inv (mod q_i) for component 0
+};
+void launch_moddown_rescale(const NttTables &t, u64 *tmp, int l, int alpha, int npoly, const u64 *yP,
+                            const u64 *hatm, long hat_ks, const u64 *last, u64 ql, const u64 *pm, const u64 *pmp,
+                            const OutModdownRescaleArgs &a, int L1, hipStream_t s, KernelTimer *tm = nullptr);
 // rescale by q_l of npoly polynomials: out_i = (in_i pm_i [+ cadd_i on even polynomials] - NTT_i([last + h] - h)) inv_i,
 // inv_i = k q_l^-1 mod q_i for an integer factor k (invf: as FP64 pairs (value, value / q_i), read on FP64
 // primes); pm (Shoup words pmp) a per-limb factor, or null for 1

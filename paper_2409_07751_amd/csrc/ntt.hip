@@ -439,6 +439,94 @@ struct OutModdownFin {
     }
 };
 
+// ModDown's basis conversion with the rescale that follows a relinearisation
+// folded in.  Besides the conversion of the P limbs (InBconv), each output word
+// gets P_i r, where r = ([c_l + h]_{q_l} - h) mod q_i is the rescale's input
+// word (limb l of the key-switched ciphertext in coefficient form, h =
+// floor(q_l / 2)) and P_i = P mod q_i.  The transform is linear, so
+// NTT(conv + P_i r) P^-1 = NTT(conv) P^-1 + NTT(r): the ModDown tail below then
+// forms c_i - NTT(r), which the rescale multiplies by q_l^-1.
+struct InBconvRs : InBconv {
+    const u64 *last;  // polynomial p at last + p last_ps
+    long last_ps;
+    u64 ql;
+    const u64 *pm, *pmp;  // P mod q_i and Shoup words
+    double read_words(int npoly, int nl) const { return InBconv::read_words(npoly, nl) + (double)npoly; }
+    template <int M>
+    __device__ void load_many(const Blk &b, const long *g, u64 *x) const
+    {
+        const u64 *src = last + b.poly * last_ps;
+        u64 rw[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) rw[m] = src[g[m]];
+        InBconv::template load_many<M>(b, g, x);  // below q
+        const u64 q = b.pc->q, h = ql >> 1, hq = reduce64(h, *b.pc);
+        const u64 w = pm[b.limb], wp = pmp[b.limb];
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            u64 r = rw[m] + h;
+            r = r >= ql ? r - ql : r;
+            r = subm(reduce64(r, *b.pc), hq, q);
+            x[m] = addm(x[m], shoup(r, w, wp, q), q);
+        }
+    }
+    template <int M>
+    __device__ void load_many_d(const Blk &b, const long *g, double *x) const
+    {
+        u64 v[M];
+        load_many<M>(b, g, v);
+#pragma unroll
+        for (int m = 0; m < M; m++) x[m] = u2d(v[m]);
+    }
+};
+
+// The tail of that ModDown (no automorphism, both base components): limb i < l
+// of the result is (base_i [+ cadd_i on component 0] + (acc_i - v) P^-1) inv_i
+// with inv_i = k q_l^-1 mod q_i, v the transform of InBconvRs's words: the
+// residues of ModDown followed by the rescale, computed in one pass
+struct OutModdownRescaleFin {
+    const u64 *acc;
+    long acc_ls, acc_ps;
+    const u64 *base;
+    long bls, bes, bcs;
+    u64 *out;
+    long ols, ops;
+    const u64 *pinv, *pinvp;
+    const TwF *pinvf;
+    const u64 *inv, *invp;
+    const TwF *invf;
+    const u64 *cadd;
+    static constexpr int NPRE = 2;
+    double extra_words(int npoly, int nl) const { return 2.0 * npoly * nl; }
+    __device__ void fetch(const Blk &b, long g, u64 *pre) const
+    {
+        pre[0] = acc[b.limb * acc_ls + b.poly * acc_ps + g];
+        pre[1] = base[b.limb * bls + (b.poly >> 1) * bes + (b.poly & 1) * bcs + g];
+    }
+    __device__ void prepare(const Blk &b, u64 *pre) const
+    {
+        if (cadd && (b.poly & 1) == 0) pre[1] = addm(pre[1], cadd[b.limb], b.pc->q);
+    }
+    __device__ void store(const Blk &b, long g, u64 v, const u64 *pre) const
+    {
+        const u64 q = b.pc->q;
+        v = reduce4(v, q);
+        const u64 r = addm(shoup(subm(pre[0], v, q), pinv[b.limb], pinvp[b.limb], q), pre[1], q);
+        out[b.limb * ols + b.poly * ops + g] = shoup(r, inv[b.limb], invp[b.limb], q);
+    }
+    // FP64 prime: (acc - v) P^-1 within 3q/4 of zero plus the base word below
+    // q, times inv as a second exact product, brought to [0, q)
+    __device__ void store_d(const Blk &b, long g, double v, const u64 *pre) const
+    {
+        const double q = b.pc->qd;
+        const TwF f = pinvf[b.limb], s = invf[b.limb];
+        const double r = mulm_fp(u2d(pre[0]) - v, f.w, f.c, q) + u2d(pre[1]);
+        double o = mulm_fp(r, s.w, s.c, q);
+        o = o < 0.0 ? o + q : o;
+        out[b.limb * ols + b.poly * ops + g] = d2u_exact((u64)__double_as_longlong(o));
+    }
+};
+
 // last phase of a second pass leaving the transformed tile in LDS (FP64
 // path): position g of the tile's rows goes to the word the row pass itself
 // uses for it (row bits 4..6 of the word index XORed into bits 0..3)
@@ -505,7 +593,8 @@ __device__ __forceinline__ void store_fp(const OUT &out, const Blk &b, long g, d
 {
     if constexpr (std::is_same<OUT, OutMid>::value || std::is_same<OUT, OutScaleTabFp>::value) out.store_d(b, g, v);
     else if constexpr (std::is_same<OUT, OutLds>::value) out.store_d(b, g, v);
-    else if constexpr (std::is_same<OUT, OutRescaleFin>::value || std::is_same<OUT, OutModdownFin>::value)
+    else if constexpr (std::is_same<OUT, OutRescaleFin>::value || std::is_same<OUT, OutModdownFin>::value ||
+                       std::is_same<OUT, OutModdownRescaleFin>::value)
         out.store_d(b, g, v, pre);
     else out.store(b, g, d2u_mod(v, b.pc->qd, b.pc->qinvd), pre);
 }
@@ -596,7 +685,8 @@ __device__ __forceinline__ void ntt_phase(u64 *sh, const Blk &bk, long blk, cons
         I ix;
         if (!(OpaqueTid<OUT>::value ? ix.set(it, blk, bk.tid) : ix.set(it, blk))) break;
         u64 x[1 << R];
-        if constexpr (FIRST && (std::is_same<IN, InBconv>::value || std::is_same<IN, InRescale>::value)) {
+        if constexpr (FIRST && (std::is_same<IN, InBconv>::value || std::is_same<IN, InRescale>::value ||
+                      std::is_same<IN, InBconvRs>::value)) {
             long g[1 << R];
 #pragma unroll
             for (int k = 0; k < (1 << R); k++) g[k] = ix.gidx(k);
@@ -669,7 +759,8 @@ __device__ __forceinline__ void ntt_phase_fp(double *sh, const Blk &bk, long blk
         I ix;
         if (!(OpaqueTid<OUT>::value ? ix.set(it, blk, bk.tid) : ix.set(it, blk))) break;
         double x[1 << R];
-        if constexpr (FIRST && (std::is_same<IN, InBconv>::value || std::is_same<IN, InRescale>::value)) {
+        if constexpr (FIRST && (std::is_same<IN, InBconv>::value || std::is_same<IN, InRescale>::value ||
+                      std::is_same<IN, InBconvRs>::value)) {
             long g[1 << R];
 #pragma unroll
             for (int k = 0; k < (1 << R); k++) g[k] = ix.gidx(k);
@@ -810,6 +901,8 @@ struct RowFirst {
 // pass to 96 VGPRs for 5 waves spills and measured no faster than 4 waves.)
 template <class IN, class OUT> struct NttWaves { static constexpr int value = 1; };
 template <class IN> struct NttWaves<IN, OutModdownFin> { static constexpr int value = 4; };
+// the conversion with the rescale term: one more word per position (else 132 VGPRs, 3 waves)
+template <> struct NttWaves<InBconvRs, OutMid> { static constexpr int value = 4; };
 
 // own_w > 0: polynomial p of the set is key-switch digit j = p mod own_ndig;
 // its own limbs [j own_w, min(j own_w + own_w, own_nq)) are skipped
@@ -1298,6 +1391,45 @@ void launch_moddown(const NttTables &t, u64 *tmp, int nq, int alpha, int npoly, 
     OutModdownFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.mask, a.galois, a.out, a.ols, a.ops,
                     a.pinv, a.pinvp, a.add, a.als, a.aes, a.pinvf};
     NTT_DISPATCH(moddown_n, t, j, in, o, s, tm);
+}
+
+template <int LOGN>
+static void moddown_rescale_n(const NttTables &t, const NttJob &j, const InBconvRs &in,
+                              const OutModdownRescaleFin &o, hipStream_t s, KernelTimer *tm)
+{
+    fwd_n<LOGN>(t, j, in, o, s, tm);
+}
+
+void launch_moddown_rescale(const NttTables &t, u64 *tmp, int l, int alpha, int npoly, const u64 *yP,
+                            const u64 *hatm, long hat_ks, const u64 *last, u64 ql, const u64 *pm, const u64 *pmp,
+                            const OutModdownRescaleArgs &a, int L1, hipStream_t s, KernelTimer *tm)
+{
+    const long N = 1l << t.logN;
+    NttJob j;
+    j.ps = PolySet{tmp, N, (long)l * N, l, npoly};
+    j.lm = LimbMap{l, L1, 0};
+    InBconvRs in;
+    in.src = yP;
+    in.src_bs = (long)alpha * N;
+    in.src_ps = 0;
+    in.ndig = 1;
+    in.hatm = hatm;
+    in.hat_ps = 0;
+    in.hat_ks = hat_ks;
+    in.ns_fixed = alpha;
+    in.w = 0;
+    in.nq = l;
+    in.hatf = nullptr;
+    in.wide[0] = in.wide[1] = 0;
+    in.dbl[0] = in.dbl[1] = 0;
+    in.last = last;
+    in.last_ps = N;
+    in.ql = ql;
+    in.pm = pm;
+    in.pmp = pmp;
+    OutModdownRescaleFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.out, a.ols, a.ops,
+                           a.pinv, a.pinvp, a.pinvf, a.inv, a.invp, a.invf, a.cadd};
+    NTT_DISPATCH(moddown_rescale_n, t, j, in, o, s, tm);
 }
 
 // rescale of both polynomials: tmp [2][l][N] working set; last = dropped limb
