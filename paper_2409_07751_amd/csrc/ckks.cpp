@@ -262,13 +262,17 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
     }
     pinv = alloc(pv.size());
     upload(pinv->p, pv.data(), pv.size());
-    // P mod q_i and Shoup words (the rescale term of the merged ModDown)
-    std::vector<u64> pmv(2 * (L + 1));
+    // P mod q_i, Shoup words and FP64 pairs (value, value / q_i): the rescale
+    // term of the merged ModDown
+    std::vector<u64> pmv(4 * (L + 1));
     for (int i = 0; i <= L; i++) {
         u64 P = 1;
         for (u64 pj : p) P = hmul(P, pj % q[i], q[i]);
         pmv[i] = P;
         pmv[L + 1 + i] = shoup_of(P, q[i]);
+        const double w = (double)P, c = w / (double)q[i];
+        std::memcpy(&pmv[2 * (L + 1) + 2 * i], &w, 8);
+        std::memcpy(&pmv[2 * (L + 1) + 2 * i + 1], &c, 8);
     }
     pmod = alloc(pmv.size());
     upload(pmod->p, pmv.data(), pmv.size());
@@ -741,7 +745,7 @@ void Ctx::moddown_rescale_into(const Buf &acc, int l, int nb, const u64 *base, l
                              (const TwF *)(pinv->p + 2 * (L + 1)), inv->p, inv->p + l,
                              (const TwF *)(inv->p + 2 * l), cadd ? rescale_addend(l, k, *cadd) : nullptr};
     launch_moddown_rescale(T, tmp->p, l, alpha, np, yP->p, md_tab->p + 2 * alpha, L + 1, last->p, q[l],
-                           pmod->p, pmod->p + L + 1, ra, L1, st, &timer);
+                           pmod->p, pmod->p + L + 1, (const TwF *)(pmod->p + 2 * (L + 1)), ra, L1, st, &timer);
     n_launch += 8;
 }
 

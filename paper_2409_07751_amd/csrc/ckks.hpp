@@ -121,7 +121,7 @@ struct Ctx {
     std::map<std::pair<int, long>, Buf> rescale_inv;  // per (level l, factor k): [2][l] k q_l^-1, Shoup
     std::map<std::tuple<int, long, u64>, Buf> rescale_add;  // per (l, k, constant bits): [l] pre-rescale addend
     Buf pinv;                        // [2][L+1] P^-1 mod q_i and Shoup
-    Buf pmod;                        // [2][L+1] P mod q_i and Shoup
+    Buf pmod;                        // [2][L+1] P mod q_i and Shoup, then [L+1] FP64 pairs
     Buf md_tab;                      // [2][alpha] P-limb INTT scale, then [alpha][L+1] P->Q constants
     std::map<std::pair<u64, u64>, Buf> const_cache;
     std::map<std::pair<u64, u64>, Buf> const_plain_cache;

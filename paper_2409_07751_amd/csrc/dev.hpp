@@ -194,7 +194,8 @@ struct OutModdownRescaleArgs {
 };
 void launch_moddown_rescale(const NttTables &t, u64 *tmp, int l, int alpha, int npoly, const u64 *yP,
                             const u64 *hatm, long hat_ks, const u64 *last, u64 ql, const u64 *pm, const u64 *pmp,
-                            const OutModdownRescaleArgs &a, int L1, hipStream_t s, KernelTimer *tm = nullptr);
+                            const TwF *pmf, const OutModdownRescaleArgs &a, int L1, hipStream_t s,
+                            KernelTimer *tm = nullptr);
 // rescale by q_l of npoly polynomials: out_i = (in_i pm_i [+ cadd_i on even polynomials] - NTT_i([last + h] - h)) inv_i,
 // inv_i = k q_l^-1 mod q_i for an integer factor k (invf: as FP64 pairs (value, value / q_i), read on FP64
 // primes); pm (Shoup words pmp) a per-limb factor, or null for 1

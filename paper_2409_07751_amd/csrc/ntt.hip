@@ -450,7 +450,9 @@ struct InBconvRs : InBconv {
     const u64 *last;  // polynomial p at last + p last_ps
     long last_ps;
     u64 ql;
+    double qld, hd;       // q_l and floor(q_l / 2) as doubles, when q_l < 2^52 (else qld = 0)
     const u64 *pm, *pmp;  // P mod q_i and Shoup words
+    const TwF *pmf;       // P mod q_i as FP64 pairs (value, value / q_i)
     double read_words(int npoly, int nl) const { return InBconv::read_words(npoly, nl) + (double)npoly; }
     template <int M>
     __device__ void load_many(const Blk &b, const long *g, u64 *x) const
@@ -470,13 +472,33 @@ struct InBconvRs : InBconv {
             x[m] = addm(x[m], shoup(r, w, wp, q), q);
         }
     }
+    // FP64 target: the rescale term in exact FP64 arithmetic (r within q/2 + 1
+    // of zero, P_i r one exact product within 3q/4), added to the conversion
+    // word (below q): within 4q, as the transform accepts
     template <int M>
     __device__ void load_many_d(const Blk &b, const long *g, double *x) const
     {
-        u64 v[M];
-        load_many<M>(b, g, v);
+        if (qld == 0.0) {
+            u64 v[M];
+            load_many<M>(b, g, v);
 #pragma unroll
-        for (int m = 0; m < M; m++) x[m] = u2d(v[m]);
+            for (int m = 0; m < M; m++) x[m] = u2d(v[m]);
+            return;
+        }
+        const u64 *src = last + b.poly * last_ps;
+        u64 rw[M], v[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) rw[m] = src[g[m]];
+        InBconv::template load_many<M>(b, g, v);
+        const double q = b.pc->qd, qi = b.pc->qinvd;
+        const TwF f = pmf[b.limb];
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            double t = u2d(rw[m]) + hd;
+            t = t >= qld ? t - qld : t;
+            const double r = t - hd;
+            x[m] = u2d(v[m]) + mulm_fp(__fma_rn(-rint(r * qi), q, r), f.w, f.c, q);
+        }
     }
 };
 
@@ -1402,7 +1424,7 @@ static void moddown_rescale_n(const NttTables &t, const NttJob &j, const InBconv
 
 void launch_moddown_rescale(const NttTables &t, u64 *tmp, int l, int alpha, int npoly, const u64 *yP,
                             const u64 *hatm, long hat_ks, const u64 *last, u64 ql, const u64 *pm, const u64 *pmp,
-                            const OutModdownRescaleArgs &a, int L1, hipStream_t s, KernelTimer *tm)
+                            const TwF *pmf, const OutModdownRescaleArgs &a, int L1, hipStream_t s, KernelTimer *tm)
 {
     const long N = 1l << t.logN;
     NttJob j;
@@ -1425,8 +1447,12 @@ void launch_moddown_rescale(const NttTables &t, u64 *tmp, int l, int alpha, int 
     in.last = last;
     in.last_ps = N;
     in.ql = ql;
+    const bool small = ql < (1ull << 52);
+    in.qld = small ? (double)ql : 0.0;
+    in.hd = small ? (double)(ql >> 1) : 0.0;
     in.pm = pm;
     in.pmp = pmp;
+    in.pmf = pmf;
     OutModdownRescaleFin o{a.acc, a.acc_ls, a.acc_ps, a.base, a.bls, a.bes, a.bcs, a.out, a.ols, a.ops,
                            a.pinv, a.pinvp, a.pinvf, a.inv, a.invp, a.invf, a.cadd};
     NTT_DISPATCH(moddown_rescale_n, t, j, in, o, s, tm);
