@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--roofline-kernel", default="ntt_fwd_pass1")
     ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching server run")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default key-switch configuration (fused, spans of 8) at every level")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -323,6 +325,15 @@ def main():
         outs = ctx.eval_kan_batch(model, keys, cts)
         ctx.sync()
         return outs
+
+    # key-switch configuration per level, chosen by measurement for the timed
+    # batch and for the plain path's batch of one
+    tune = {}
+    if not args.no_autotune:
+        t0 = time.time()
+        for nb in sorted({B, 1}):
+            tune[str(nb)] = ctx.autotune(keys, nb)
+        log("key-switch autotune %.1fs: %s" % (time.time() - t0, tune))
 
     for w in range(args.warmup):
         t0 = time.time()
@@ -377,6 +388,7 @@ def main():
         "max_abs_err_vs_fp64_circuit": err,
         "launches_per_step": (c1["launches"] - c0["launches"]) / args.steps,
         "roofline": roof,
+        "keyswitch_autotune": tune or None,
     }
     if args.plain_steps:
         res["plain_path"] = plain_path(ctx, model, keys, cts[0], args.plain_steps)

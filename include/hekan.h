@@ -150,6 +150,23 @@ int he_ctx_sync(he_ctx *ctx);
 int he_ctx_profile(he_ctx *ctx, int32_t kernel);
 int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, double *bytes, double *ops);
 
+/* Key-switch kernel configuration per (level, batch size): 0 = ModUp, then the
+ * key inner product over every limb; 1, 8 or 32 = ModUp's second pass fused
+ * with the inner product on the FP64 limbs, blocks ordered in spans of that
+ * many (limb, row tile) groups (8, the default: the blocks of one group land
+ * on one XCD whatever the batch element).  Every configuration computes the
+ * same residues; only the time differs.
+ * he_ctx_autotune times each configuration at every level 0..L for `batch`
+ * elements (one key switch with the relinearisation key of k on a zero input,
+ * the median of `reps` runs after a warm-up), keeps the fastest for that batch
+ * size, and writes the choices of levels 0..min(cap, L+1)-1 to choice and L+1
+ * to *n.  It synchronises the stream (HE_ESTATE while a graph is being
+ * captured on it).  he_ctx_set_keyswitch sets one entry by hand (HE_EINVAL for
+ * another config value). */
+int he_ctx_autotune(he_ctx *ctx, const he_keys *k, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
+                    size_t *n);
+int he_ctx_set_keyswitch(he_ctx *ctx, int32_t level, int32_t batch, int32_t config);
+
 /* ------------------------------------------------------------------ model */
 
 /* Compile a KAN for encrypted evaluation: checks the layer shapes and their

@@ -153,6 +153,27 @@ int he_ctx_profile(he_ctx *ctx, int32_t kernel)
     return guard(ctx, [&]() { ctx->c->profile(kernel); });
 }
 
+int he_ctx_autotune(he_ctx *ctx, const he_keys *k, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
+                    size_t *n)
+{
+    if (!ctx || !k || !n || batch < 1 || reps < 1 || (cap && !choice)) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        if (k->owner != ctx) throw HeError(HE_ESTATE, "keys of another context");
+        const std::vector<int> c = ctx->c->autotune_keyswitch(k->k->relin, batch, reps);
+        *n = c.size();
+        for (size_t i = 0; i < c.size() && i < cap; i++) choice[i] = c[i];
+    });
+}
+
+int he_ctx_set_keyswitch(he_ctx *ctx, int32_t level, int32_t batch, int32_t config)
+{
+    if (!ctx || batch < 1 || !(config == 0 || config == 1 || config == 8 || config == 32)) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        need(level >= 0 && level <= ctx->c->L, "level out of range");
+        ctx->c->ks_tune[std::make_pair((int)level, (int)batch)] = config;
+    });
+}
+
 int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, double *bytes, double *ops)
 {
     if (!ctx) return HE_EINVAL;

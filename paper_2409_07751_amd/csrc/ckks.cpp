@@ -685,8 +685,11 @@ void Ctx::keyswitch(const u64 *d, long ls, long es, int l, int nb, const SwitchK
 // [nb][2][l+1+alpha][N], before ModDown
 Buf Ctx::keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key)
 {
+    // the configuration chosen for this (level, batch), by default fused with spans of 8
+    auto tc = ks_tune.find(std::make_pair(l, nb));
+    const int cfg = tc == ks_tune.end() ? 8 : tc->second;
     // the fused kernel handles q_1..q_l; at level 0 there are none
-    if (!ks_fused || !key.fbuf || l == 0) return inner_product(modup(d, ls, es, l, nb), key);
+    if (!ks_fused || !key.fbuf || l == 0 || cfg == 0) return inner_product(modup(d, ls, es, l, nb), key);
     // ModUp with the inner product fused into the second pass on q_1..q_l; the
     // extended digits are stored only on q_0 and the special primes, whose
     // inner product follows separately
@@ -701,7 +704,7 @@ Buf Ctx::keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const Swit
     Buf ext = alloc((size_t)nb * nd * next * N);
     Buf acc = alloc((size_t)nb * 2 * next * N);
     ModupKeyipArgs a{1, nq, 1, nb, d, ls, es, (const double *)key.fbuf->p, 2l * ktot * N, (long)ktot * N,
-                     acc->p, 2l * next * N, (long)next * N};
+                     acc->p, 2l * next * N, (long)next * N, cfg};
     launch_modup_keyip(T, ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, kt.hatf, kt.wide, kt.dbl, a, st, &timer);
     y.reset();
     launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, ext->p, (long)next * N, (long)nd * next * N, d, ls, es,
@@ -709,6 +712,69 @@ Buf Ctx::keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const Swit
     ext.reset();
     n_launch += 6;
     return acc;
+}
+
+// Key-switch autotuner: for one batch size, at every level, times ModUp and
+// the key inner product (the part whose kernels differ) in each configuration
+// (0: ModUp, then the inner product over every limb; 1, 8, 32: the fused
+// kernel with block spans of that many groups) on a zero input, median of
+// `reps` runs after one warm-up, and keeps the fastest.  Every configuration
+// computes the same residues.  Synchronises the stream: not for use while a
+// graph is being captured.
+std::vector<int> Ctx::autotune_keyswitch(const SwitchKey &key, int nb, int reps)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_CHECK(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) throw HeError(-7, "autotune: the stream is being captured");
+    std::vector<int> chosen(L + 1, 8);
+    const int cands[4] = {0, 1, 8, 32};
+    // one zero input for every level (element stride (l+1) N within it)
+    const size_t words = (size_t)nb * (L + 1) * N;
+    Buf d = alloc(words);
+    {
+        std::vector<u64> z(words, 0);
+        upload(d->p, z.data(), words);
+    }
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    try {
+        for (int l = 0; l <= L; l++) {
+            const bool fused = ks_fused && key.fbuf && l > 0;
+            float best = 0.0f;
+            bool have = false;
+            for (int ci = 0; ci < 4; ci++) {
+                const int cfg = cands[ci];
+                if (!fused && cfg != 0) continue;
+                ks_tune[std::make_pair(l, nb)] = cfg;
+                std::vector<float> ms;
+                for (int r = 0; r <= reps; r++) {
+                    HIP_CHECK(hipEventRecord(e0, st));
+                    Buf acc = keyswitch_acc(d->p, (long)N, (long)(l + 1) * N, l, nb, key);
+                    HIP_CHECK(hipEventRecord(e1, st));
+                    HIP_CHECK(hipEventSynchronize(e1));
+                    float t = 0.0f;
+                    HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+                    if (r > 0) ms.push_back(t);
+                }
+                std::sort(ms.begin(), ms.end());
+                const float med = ms[ms.size() / 2];
+                if (!have || med < best) {
+                    best = med;
+                    chosen[l] = cfg;
+                    have = true;
+                }
+            }
+            ks_tune[std::make_pair(l, nb)] = chosen[l];
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return chosen;
 }
 
 // ModDown of a relinearisation's accumulators followed by the rescale by q_l,

@@ -202,6 +202,10 @@ struct Ctx {
                       int base_mask, Ct &out, const Ct *addend);
     // ModUp and inner product of a key switch (the accumulators before ModDown)
     Buf keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const SwitchKey &key);
+    // key-switch configuration per (level, batch size): 0 ModUp then inner
+    // product; 1, 8, 32 the fused kernel with that block span (default 8)
+    std::map<std::pair<int, int>, int> ks_tune;
+    std::vector<int> autotune_keyswitch(const SwitchKey &key, int nb, int reps);
     Buf inner_product(const ModUp &m, const SwitchKey &key);
     // relinearisation tail: base (both components) + ModDown(acc), rescaled by q_l
     // with factor k and constant *cadd, into out at level l - 1

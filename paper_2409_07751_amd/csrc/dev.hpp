@@ -152,6 +152,7 @@ struct ModupKeyipArgs {
     long kf_ds, kf_cs;
     u64 *acc;
     long acc_es, acc_cs;
+    int gspan = 8;  // (limb, tile) groups per span of the block order (8: one XCD per group)
 };
 void launch_modup_keyip(const NttTables &t, u64 *ext, int ndig, int nq, int alpha, int w, int nb, LimbMap lm,
                         const u64 *y, const u64 *hatm, const TwF *hatf, const u64 wide[2], const u64 dbl[2],

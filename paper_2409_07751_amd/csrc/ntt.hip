@@ -1026,9 +1026,12 @@ __global__ void __launch_bounds__(256, (NttWaves<IN, OUT>::value)) k_ntt(NttTabl
 // never reach HBM; the two sums are stored reduced to [0, q).  A thread owns
 // tile words threadIdx.x + 256 k, so key, input and output accesses are
 // coalesced.  c = w / q is formed as w fl(1/q): each product is then within
-// q + 2^37 of zero and 16 digits stay below 2^50.  Blocks of one (limb, tile)
-// and different elements are placed on one XCD (hardware block b runs on XCD
-// b mod 8), so the tile's key words come from HBM once and then from L2.
+// q + 2^37 of zero and 16 digits stay below 2^50.  Blocks are taken in spans
+// of gspan (limb, tile) groups, element by element: block ((s nb + e) gspan +
+// r) runs group s gspan + r of element e.  With gspan a multiple of 8 the
+// blocks of one group and different elements land on one XCD (hardware block
+// b runs on XCD b mod 8), so the tile's key words come from HBM once and then
+// from L2; gspan = 1 puts the elements of a group side by side instead.
 // mid: pass-1 output, limb t of polynomial p (= e ndig + j) at mid + t mid_ls + p mid_ps;
 // d: limb t of element e at d + t d_ls + e d_es; kf: digit j, component c, limb t at
 // kf + j kf_ds + c kf_cs + t N (doubles); acc: element e component c limb t at
@@ -1037,7 +1040,8 @@ template <int LOGN>
 __global__ void __launch_bounds__(256, 4) k_modup_keyip(NttTables T, const u64 *mid, long mid_ls, long mid_ps,
                                                         const u64 *d, long d_ls, long d_es, const double *kf,
                                                         long kf_ds, long kf_cs, u64 *acc, long acc_es, long acc_cs,
-                                                        int ndig, int w, int nb, int limb_lo, int ngroups)
+                                                        int ndig, int w, int nb, int limb_lo, int ngroups,
+                                                        int gspan)
 {
     typedef NttGeo<LOGN> G;
     static_assert(G::LC == 8, "row tiles of 256-word rows");
@@ -1048,8 +1052,8 @@ __global__ void __launch_bounds__(256, 4) k_modup_keyip(NttTables T, const u64 *
     constexpr int NP = (1 << LT) / 256;  // words per thread
     __shared__ u64 sh[(1 << LT) + TWW];
     double *shd = reinterpret_cast<double *>(sh);
-    const int b = (int)blockIdx.x, i = b >> 3;
-    const int e = i % nb, grp = (i / nb) * 8 + (b & 7);
+    const int b = (int)blockIdx.x, i = b / gspan;
+    const int e = i % nb, grp = (i / nb) * gspan + b % gspan;
     if (grp >= ngroups) return;
     const int limb = limb_lo + grp / TILES;
     const long tile = grp % TILES;
@@ -1339,9 +1343,10 @@ static void modup_keyip_n(const NttTables &t, const NttJob &j, const InBconv &in
     const int ngroups = nfp * TILES;
     on = tm && tm->on(KID_MODUP_KEYIP);
     if (on) tm->before(s);
-    hipLaunchKernelGGL((k_modup_keyip<LOGN>), dim3(((ngroups + 7) / 8) * 8 * a.nb), blk, 0, s, t, j.ps.base,
+    const int gs = a.gspan > 0 ? a.gspan : 8;
+    hipLaunchKernelGGL((k_modup_keyip<LOGN>), dim3(((ngroups + gs - 1) / gs) * gs * a.nb), blk, 0, s, t, j.ps.base,
                        j.ps.lstride, j.ps.pstride, a.d, a.d_ls, a.d_es, a.kf, a.kf_ds, a.kf_cs, a.acc, a.acc_es,
-                       a.acc_cs, j.own_ndig, j.own_w, a.nb, a.fp_lo, ngroups);
+                       a.acc_cs, j.own_ndig, j.own_w, a.nb, a.fp_lo, ngroups, gs);
     // per limb and element: ndig words read (pass-1 output or the input limb), two written;
     // per limb: 2 ndig key words
     if (on) tm->after(s, wb * nfp * ((double)a.nb * j.own_ndig + 2.0 * j.own_ndig + 2.0 * a.nb),

@@ -54,6 +54,9 @@ _SIGS = {
     "he_ctx_counters": [ctypes.c_void_p, _u64p, _u64p, _u64p],
     "he_ctx_sync": [ctypes.c_void_p],
     "he_ctx_profile": [ctypes.c_void_p, ctypes.c_int32],
+    "he_ctx_autotune": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                        ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "he_ctx_set_keyswitch": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "he_graph_capture_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
     "he_graph_launch": [ctypes.c_void_p],
@@ -165,6 +168,17 @@ class Context:
 
     KERNELS = {"ntt_fwd_pass1": 0, "ntt_fwd_pass2": 1, "ntt_inv_pass2": 2, "ntt_inv_pass1": 3, "bconv": 4,
                "keyip": 5, "modup_keyip": 6}
+
+    def autotune(self, keys, batch, reps=3):
+        """he_ctx_autotune: the key-switch configuration chosen at each level
+        0..L for this batch size (0 unfused; 1, 8, 32 fused with that span)."""
+        choice = (ctypes.c_int32 * (self.L + 1))()
+        n = ctypes.c_size_t()
+        self.check(self.lib.he_ctx_autotune(self.h, keys.h, batch, reps, choice, self.L + 1, ctypes.byref(n)))
+        return [int(choice[i]) for i in range(n.value)]
+
+    def set_keyswitch(self, level, batch, config):
+        self.check(self.lib.he_ctx_set_keyswitch(self.h, level, batch, config))
 
     def profile(self, kernel):
         """Time every launch of `kernel` (a KERNELS name, or None to stop)."""
