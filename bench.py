@@ -37,7 +37,7 @@ NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1
 # HBM bytes per launch of the default roofline kernel at the default batch,
 # from calibrated FETCH_SIZE + WRITE_SIZE counter runs of this benchmark;
 # emptied whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 306830000, "ntt_fwd_pass2": 490500000}
+TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 306800000, "ntt_fwd_pass2": 490580000}
 
 
 def roofline(kernel, prof, batch):
