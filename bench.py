@@ -35,7 +35,9 @@ def log(*a):
 HBM_PEAK_GBPS = 8000.0
 NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1")
 # HBM bytes per launch of the default roofline kernel at the default batch,
-# from calibrated FETCH_SIZE + WRITE_SIZE counter runs of this benchmark;
+# from calibrated FETCH_SIZE + WRITE_SIZE counter runs of this benchmark with
+# the default key-switch configuration (--no-autotune: the column pass's
+# launches are the same in every configuration, the row pass's are not);
 # emptied whenever the kernel changes until the counters are taken again
 TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 306800000, "ntt_fwd_pass2": 490580000}
 
