@@ -109,7 +109,7 @@ def cpu_baseline(wl, budget):
             return super().rotate(a, t)
 
     sim = Rec(prm.slots)
-    circuit.eval_kan(sim, sim.fresh(np.zeros(wl.shape[0]), wl.L), layers)
+    circuit.eval_kan(sim, sim.fresh(np.zeros(wl.shape[0]), wl.L), layers, circ=circuit.RESTRUCTURED)
     total_work = sim.w
 
     ctx = O.Context(prm)
@@ -156,7 +156,7 @@ def cpu_baseline(wl, budget):
     log("cpu baseline: oracle running the inference for %.0f s" % budget)
     state["t0"] = time.perf_counter()
     try:
-        circuit.eval_kan(ev, ct, layers)
+        circuit.eval_kan(ev, ct, layers, circ=circuit.RESTRUCTURED)
     except Stop:
         pass
     elapsed = time.perf_counter() - state["t0"] - state["keygen"]

@@ -4,21 +4,32 @@ TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the
 CPU-baseline leg of the benchmark; never by the product package.
 
 Per KANLayer (Method, Figure 2 structure) on a ciphertext x whose slots hold
-the layer input in blocks of n_blk slots:
+the layer input in blocks of n_blk slots, in the paper's order (`PAPER`):
   * first layer: Fast Repeat Packing (Algorithm 1) without the mask, because
     a fresh ciphertext already holds zeros outside [0, n_i);
-  * spline branch: PolyComp on x_rep - g1 and g2 - x_rep (the second taken
-    from the first by one rotation when the input holds one more block: the
-    composite is odd), their product, and k rounds of Algorithm 2 (each round
-    relinearises once after summing both tensor products);
-  * SiLU branch: the fitted Chebyshev polynomial by baby-step giant-step, on
-    the repeat-packed input with its coefficients masked to block g+k (the
-    first block the bases leave free);
-  * both linear layers (W_b after SiLU, the fused W_f = W' P after the basis)
-    as one product of [W_f | W_b] with the sum of bases and masked SiLU, by
-    the hybrid diagonal method with baby-step giant-step rotations, folded
-    over all slots, so the output is periodic with period d = next power of
-    two >= n_out (the next layer's repeat packing comes for free);
+  * spline branch, Algorithm 2 as written: PolyComp on (x_rep - g1)/2R and on
+    (g2 - x_rep)/2R, their product, and k rounds of the order recursion (each
+    round relinearises once after summing both tensor products);
+  * SiLU branch: the fitted Chebyshev polynomial by baby-step giant-step on x;
+  * the two linear layers as two products, W_f = W' P (Lazy Combination,
+    Algorithm 3) with the bases and W_b with the SiLU values, each by the
+    hybrid diagonal method with baby-step giant-step rotations and a fold
+    over all slots, so each output is periodic with period d = next power of
+    two >= n_out (the next layer's repeat packing comes for free); the layer
+    output is their sum.
+Three restructurings (`Circuit`) change no value of the FP64 circuit and cut
+key switches; each is a named option, checked against the paper's order:
+  * shared_comparison: when the input holds g+2k+1 blocks, the second
+    comparison S((t_{m+2} - x)/2R) is 1 - S((x - t_{m+2})/2R) (the composite
+    is odd), i.e. 1 minus the first comparison of block m+1: one rotation
+    instead of a second PolyComp;
+  * fused_linear: the SiLU branch runs on the repeat-packed input with its
+    coefficients masked to block g+k (the first block the bases leave free)
+    and is added to the bases, so one product with [W_f | W_b] and one fold
+    compute both linear layers;
+  * folded_period: a hidden layer's block layout repeats with the shortest
+    power-of-two period that holds its blocks, and the fold runs over one
+    period;
   * a first layer whose repeat-packed footprint n_i 2^ceil(log2(g+2k))
     exceeds the slot count takes its input as several ciphertexts, one per
     chunk of consecutive features: each chunk is packed and expanded on its
@@ -38,6 +49,19 @@ import math
 import numpy as np
 
 from .kan import fused_weights
+
+
+@dataclasses.dataclass(frozen=True)
+class Circuit:
+    """Which restructurings of the paper's circuit are applied (all off: the
+    paper's order)."""
+    shared_comparison: bool = False
+    fused_linear: bool = False
+    folded_period: bool = False
+
+
+PAPER = Circuit()
+RESTRUCTURED = Circuit(True, True, True)
 
 
 def pow2ceil(n):
@@ -361,40 +385,56 @@ def shared_comparison(L, n_blk, first, slots):
     return blocks >= r and r * n_blk <= slots
 
 
-def hidden_period(L, n_blk, slots):
-    """A hidden layer's input repeats every n_blk slots, so its whole block
-    layout (g+2k+1 blocks: the comparisons, the bases and the masked SiLU)
-    can repeat every P = next power of two of that many slots; the product
-    then repeats every P as well and the fold runs over one period."""
-    return min(slots, pow2ceil((L.g + 2 * L.k + 1) * n_blk))
+def hidden_period(L, n_blk, slots, circ=RESTRUCTURED):
+    """The period of a hidden layer's block layout.  Its input repeats every
+    n_blk slots, so with folded_period the layout (g+2k blocks of
+    comparisons, or g+2k+1 when the second comparison is shared; g+k bases
+    and, fused, the masked SiLU block) repeats every P = next power of two of
+    that many slots, the products repeat every P as well and the fold runs
+    over one period.  Otherwise P is all the slots."""
+    if not circ.folded_period:
+        return slots
+    r = L.g + 2 * L.k + 1
+    nblocks = r if (circ.shared_comparison or (circ.fused_linear and L.k == 0)) else r - 1
+    return min(slots, pow2ceil(nblocks * n_blk))
 
 
-def layer_part(ev, x, L, n_blk, first, d, S=1):
+def layer_part(ev, x, L, n_blk, first, d, S=1, circ=PAPER):
     """Both branches of one layer on one input ciphertext, before the fold.
-    n_blk: slots per input block (n_in S for a first layer).  The SiLU branch
-    is evaluated on the repeat-packed input with its coefficients masked to
-    block g+k, the first block the g+k bases leave free, and added to the
-    bases, so one product with [W_f | W_b] (g+k+1 column blocks) computes both
-    linear layers."""
+    n_blk: slots per input block (n_in S for a first layer).  Returns the
+    pre-fold products: [z] for fused_linear (the SiLU branch evaluated on the
+    repeat-packed input with its coefficients masked to block g+k, the first
+    block the g+k bases leave free, added to the bases, and one product with
+    [W_f | W_b], g+k+1 column blocks), else [z_f, z_b] (W_f times the bases,
+    W_b times the SiLU values of x), both landing at the same level."""
     slots = ev.ctx.p.slots
     nb = L.g + L.k
     width = L.n_in * S
-    period = slots if first else hidden_period(L, n_blk, slots)
+    period = slots if first else hidden_period(L, n_blk, slots, circ)
     xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
-    b = bspline_basis(ev, xr, L, n_blk, width, shared_comparison(L, n_blk, first, slots), period)
-    mask = np.zeros(period)
-    mask[nb * n_blk:nb * n_blk + width] = 1.0
-    s = cheb_eval(ev, xr, L.silu_coeffs, L.silu_lo, L.silu_hi, np.tile(mask, slots // period))
+    shared = circ.shared_comparison and shared_comparison(L, n_blk, first, slots)
+    b = bspline_basis(ev, xr, L, n_blk, width, shared, period)
+    if circ.fused_linear:
+        mask = np.zeros(period)
+        mask[nb * n_blk:nb * n_blk + width] = 1.0
+        s = cheb_eval(ev, xr, L.silu_coeffs, L.silu_lo, L.silu_hi, np.tile(mask, slots // period))
+        t = min(b.level, s.level) - 1
+        z = ev.add(ev.mod_drop(b, t + 1), ev.mod_drop(s, t + 1))
+        W = strided(np.hstack([fused_weights(L, L.n_in), L.wb]), S, nb + 1, n_blk)
+        return [matvec_partial(ev, z, W, d, t, S, period)]
+    s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
     t = min(b.level, s.level) - 1
-    z = ev.add(ev.mod_drop(b, t + 1), ev.mod_drop(s, t + 1))
-    W = strided(np.hstack([fused_weights(L, L.n_in), L.wb]), S, nb + 1, n_blk)
-    return matvec_partial(ev, z, W, d, t, S, period)
+    Wf = strided(fused_weights(L, L.n_in), S, nb, n_blk)
+    Wb = strided(L.wb, S, 1, n_blk)
+    return [matvec_partial(ev, b, Wf, d, t, S, period), matvec_partial(ev, s, Wb, d, t, S, period)]
 
 
-def layer_forward(ev, xs, L, n_blk, first, S=1):
+def layer_forward(ev, xs, L, n_blk, first, S=1, circ=PAPER):
     """xs: the first layer's chunk ciphertexts (see chunk_bounds), else [x];
     n_blk: the previous output period (later layers).  Returns the output and
-    its period d S."""
+    its period d S.  The chunks' pre-fold products are added (per linear
+    layer), then each sum is folded; without fused_linear the layer output is
+    fold(z_f) + fold(z_b)."""
     d = pow2ceil(L.n_out)
     if first:
         bounds = chunk_bounds(L, ev.ctx.p.slots, S)
@@ -403,33 +443,37 @@ def layer_forward(ev, xs, L, n_blk, first, S=1):
         parts = [(L, n_blk)]
     if len(xs) != len(parts):
         raise ValueError("layer takes %d input ciphertexts, got %d" % (len(parts), len(xs)))
-    z = None
+    zs = None
     for x, (Lc, nb) in zip(xs, parts):
-        zc = layer_part(ev, x, Lc, nb, first, d, S)
-        z = zc if z is None else ev.add(z, zc)
-    period = ev.ctx.p.slots if first else hidden_period(L, n_blk, ev.ctx.p.slots)
-    return fold(ev, z, d * S, period), d * S
+        zc = layer_part(ev, x, Lc, nb, first, d, S, circ)
+        zs = zc if zs is None else [ev.add(a, b) for a, b in zip(zs, zc)]
+    period = ev.ctx.p.slots if first else hidden_period(L, n_blk, ev.ctx.p.slots, circ)
+    y = fold(ev, zs[0], d * S, period)
+    for z in zs[1:]:
+        y = ev.add(y, fold(ev, z, d * S, period))
+    return y, d * S
 
 
-def eval_kan(ev, ct, layers, refresh=None, S=1):
+def eval_kan(ev, ct, layers, refresh=None, S=1, circ=PAPER):
     """Run the layers on ct: one ciphertext (input in slots [0, n_in S)) or the
     list of the first layer's chunk ciphertexts (chunk c holds features
     [b_c, b_{c+1}) in slots [0, (b_{c+1} - b_c) S)); with S vectors per
     ciphertext, feature i of vector s is in slot i S + s, and output o of
     vector s comes out in slot o S + s.  `refresh`, if given, is called
     between layers with the ciphertext and returns a fresh one at the top
-    level (the client-aided stand-in for bootstrapping)."""
+    level (the client-aided stand-in for bootstrapping).  `circ` selects the
+    restructurings (default: the paper's order)."""
     xs = list(ct) if isinstance(ct, (list, tuple)) else [ct]
     n_blk = 0
     for li, L in enumerate(layers):
         if li > 0 and refresh is not None:
             xs = [refresh(xs[0], li)]
-        x, n_blk = layer_forward(ev, xs, L, n_blk, li == 0, S)
+        x, n_blk = layer_forward(ev, xs, L, n_blk, li == 0, S, circ)
         xs = [x]
     return xs[0]
 
 
-def rotation_steps(layers, slots, S=1):
+def rotation_steps(layers, slots, S=1, circ=PAPER):
     """Every rotation amount the circuit uses (for key generation)."""
     steps = set()
     n_blk = 0
@@ -446,7 +490,7 @@ def rotation_steps(layers, slots, S=1):
         b1, g1 = bsgs_split(d)
         steps.update(bi * S for bi in range(1, b1))
         steps.update(gi * b1 * S for gi in range(1, g1))
-        s = (slots if li == 0 else hidden_period(L, n_blk, slots)) // 2
+        s = (slots if li == 0 else hidden_period(L, n_blk, slots, circ)) // 2
         while s >= d * S:
             steps.add(s)
             s //= 2

@@ -30,7 +30,7 @@ def build(force=False):
     src = os.path.join(_HERE, "ckks_oracle.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-fopenmp", "-shared", "-o", tmp, src, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -75,6 +75,8 @@ def lib():
             "oc_encode_coeffs_dd": (None, [_dp, i32, d, i32, _dp, _dp]),
             "oc_decode": (None, [_u64p, u64, d, i32, i32, _dp]),
             "oc_encode_coeff_direct": (d, [_dp, i32, d, i32, u64]),
+            "oc_set_threads": (None, [i32]),
+            "oc_get_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -82,6 +84,16 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Host threads for the oracle's limb loops (n <= 0: all cores); results do
+    not depend on it."""
+    lib().oc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().oc_get_threads())
 
 
 def P(a):

@@ -22,8 +22,13 @@
  *   - canonical-embedding encoding in double-double precision, rounded to the
  *     nearest integer with ties to even;
  *   - sampling from the ChaCha20 block function (RFC 8439).
+ * Loops over independent RNS limbs (and, in the basis conversion, over
+ * independent coefficients) may run on several host threads (OpenMP); each
+ * iteration computes exactly what it computes alone, so the results do not
+ * depend on the thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -32,6 +37,10 @@ typedef uint64_t u64;
 typedef uint32_t u32;
 typedef unsigned __int128 u128;
 typedef __int128 i128;
+
+/* host threads used by the limb loops (0 or less: the OpenMP default) */
+void oc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+int oc_get_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------- */
 /* scalar modular arithmetic                                                   */
@@ -175,7 +184,16 @@ u64 oc_find_psi(u64 q, int logN)
     }
 }
 
+static const ntt_tab *make_tab(u64 q, int logN);
 static const ntt_tab *get_tab(u64 q, int logN)
+{
+    const ntt_tab *r;
+#pragma omp critical(oc_tabs)
+    r = make_tab(q, logN);
+    return r;
+}
+
+static const ntt_tab *make_tab(u64 q, int logN)
 {
     for (int i = 0; i < g_ntabs; i++)
         if (g_tabs[i].q == q && g_tabs[i].logN == logN) return &g_tabs[i];
@@ -302,6 +320,7 @@ void oc_poly_sub(const u64 *a, const u64 *b, u64 *out, int nl, int logN, const u
 void oc_poly_mul(const u64 *a, const u64 *b, u64 *out, int nl, int logN, const u64 *m)
 {
     u64 N = 1ULL << logN;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < nl; i++) oc_negacyclic_mul(a + i * N, b + i * N, out + i * N, logN, m[i]);
 }
 
@@ -318,6 +337,7 @@ void oc_poly_mul_scalar(const u64 *a, const u64 *cres, u64 *out, int nl, int log
 void oc_automorph(const u64 *a, u64 *out, int nl, int logN, const u64 *m, u64 g)
 {
     u64 N = 1ULL << logN, twoN = 2 * N;
+#pragma omp parallel for
     for (int i = 0; i < nl; i++)
         for (u64 j = 0; j < N; j++) {
             u64 e = (u64)(((u128)j * g) % twoN);
@@ -336,6 +356,7 @@ void oc_rescale(const u64 *c, u64 *out, int l, int logN, const u64 *q)
 {
     u64 N = 1ULL << logN;
     u64 ql = q[l], h = ql >> 1;
+#pragma omp parallel for
     for (int i = 0; i < l; i++) {
         u64 qi = q[i];
         u64 inv = oc_invm(ql % qi, qi), hi = h % qi;
@@ -369,16 +390,20 @@ void oc_bconv(const u64 *x, int ns, const u64 *sm, u64 *out, int nd, const u64 *
             hat[j * nd + p] = hp;
         }
     }
-    u64 *y = malloc(ns * sizeof(u64));
-    for (u64 n = 0; n < N; n++) {
-        for (int j = 0; j < ns; j++) y[j] = mulm(x[j * N + n], invhat[j], sm[j]);
-        for (int p = 0; p < nd; p++) {
-            u64 acc = 0;
-            for (int j = 0; j < ns; j++) acc = addm(acc, mulm(y[j], hat[j * nd + p], dm[p]), dm[p]);
-            out[p * N + n] = acc;
+#pragma omp parallel
+    {
+        u64 *y = malloc(ns * sizeof(u64));
+#pragma omp for
+        for (u64 n = 0; n < N; n++) {
+            for (int j = 0; j < ns; j++) y[j] = mulm(x[j * N + n], invhat[j], sm[j]);
+            for (int p = 0; p < nd; p++) {
+                u64 acc = 0;
+                for (int j = 0; j < ns; j++) acc = addm(acc, mulm(y[j], hat[j * nd + p], dm[p]), dm[p]);
+                out[p * N + n] = acc;
+            }
         }
+        free(y);
     }
-    free(y);
     free(hat);
     free(invhat);
 }
@@ -392,6 +417,7 @@ void oc_moddown(const u64 *a, u64 *out, int nq, int alpha, int logN, const u64 *
     u64 N = 1ULL << logN;
     u64 *conv = malloc((size_t)nq * N * sizeof(u64));
     oc_bconv(a + (u64)nq * N, alpha, p, conv, nq, q, logN);
+#pragma omp parallel for
     for (int i = 0; i < nq; i++) {
         u64 P = 1;
         for (int k = 0; k < alpha; k++) P = mulm(P, p[k] % q[i], q[i]);
@@ -425,7 +451,6 @@ void oc_keyswitch(const u64 *d, int l, const u64 *keys, int L, int alpha, int w,
     u64 *tmp = malloc((size_t)next * N * sizeof(u64));
     u64 *acc0 = calloc((size_t)next * N, sizeof(u64));
     u64 *acc1 = calloc((size_t)next * N, sizeof(u64));
-    u64 *prod = malloc(N * sizeof(u64));
     for (int j = 0; j < ndig; j++) {
         int lo = j * w, hi = lo + w < nq ? lo + w : nq;
         int nsrc = hi - lo;
@@ -448,19 +473,21 @@ void oc_keyswitch(const u64 *d, int l, const u64 *keys, int L, int alpha, int w,
             memcpy(ext, tmp, (size_t)next * N * sizeof(u64));
         }
         /* inner product with the key digit over every limb of Q_l u P */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int t = 0; t < next; t++) {
             int kt = t < nq ? t : L + 1 + (t - nq);
             const u64 *kb = keys + (((u64)j * 2 + 0) * ktot + kt) * N;
             const u64 *ka = keys + (((u64)j * 2 + 1) * ktot + kt) * N;
+            u64 *prod = malloc(N * sizeof(u64));
             oc_negacyclic_mul(ext + (u64)t * N, kb, prod, logN, mods[t]);
             for (u64 n = 0; n < N; n++) acc0[t * N + n] = addm(acc0[t * N + n], prod[n], mods[t]);
             oc_negacyclic_mul(ext + (u64)t * N, ka, prod, logN, mods[t]);
             for (u64 n = 0; n < N; n++) acc1[t * N + n] = addm(acc1[t * N + n], prod[n], mods[t]);
+            free(prod);
         }
     }
     oc_moddown(acc0, u0, nq, alpha, logN, q, p);
     oc_moddown(acc1, u1, nq, alpha, logN, q, p);
-    free(prod);
     free(acc1);
     free(acc0);
     free(tmp);
@@ -602,6 +629,7 @@ void oc_sample_gauss(u64 seed, u32 purpose, u32 id, u32 sub, double sigma, int l
 void oc_small_to_rns(const int64_t *e, u64 *out, int nl, int logN, const u64 *m)
 {
     u64 N = 1ULL << logN;
+#pragma omp parallel for
     for (int i = 0; i < nl; i++)
         for (u64 j = 0; j < N; j++) {
             int64_t v = e[j];
@@ -632,11 +660,12 @@ void oc_gen_switch_key(u64 seed, u32 key_id, const u64 *s_res, const u64 *sp_res
     for (int i = 0; i <= L; i++) mods[i] = q[i];
     for (int i = 0; i < alpha; i++) mods[L + 1 + i] = p[i];
     int64_t *e = malloc(N * sizeof(int64_t));
-    u64 *eres = malloc(N * sizeof(u64));
-    u64 *as = malloc(N * sizeof(u64));
     for (int j = 0; j < dnum; j++) {
         oc_sample_gauss(seed, 3, key_id, (u32)j << 16, sigma, logN, e);
+#pragma omp parallel for schedule(dynamic, 1)
         for (int t = 0; t < ktot; t++) {
+            u64 *eres = malloc(N * sizeof(u64));
+            u64 *as = malloc(N * sizeof(u64));
             u64 m = mods[t];
             u64 *kb = keys + (((u64)j * 2 + 0) * ktot + t) * N;
             u64 *ka = keys + (((u64)j * 2 + 1) * ktot + t) * N;
@@ -654,10 +683,10 @@ void oc_gen_switch_key(u64 seed, u32 key_id, const u64 *s_res, const u64 *sp_res
                 if (in_digit) v = addm(v, mulm(Pm, sp_res[(u64)t * N + n], m), m);
                 kb[n] = v;
             }
+            free(as);
+            free(eres);
         }
     }
-    free(as);
-    free(eres);
     free(e);
     free(mods);
 }

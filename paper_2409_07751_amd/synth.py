@@ -15,7 +15,9 @@ their shapes and value ranges):
           degree 31, 28x28 images with pixels U[0,1] quantised to k/255
           (the MNIST shape), raster-scanned;
   cifar   same parameters, KAN [3072,128,10] on 32x32x3 images (the CIFAR-10
-          shape), pixels U[0,1].
+          shape), pixels U[0,1];
+  toy     the tiny parameters, KAN [2,3,1] with g=2, k=1 (the grid of the
+          paper's toy example of the basis construction).
 Seeds: weights 1, inputs 2, keygen 3, encryption 4, arrivals 5, calibration 6.
 """
 from dataclasses import dataclass, field
@@ -63,6 +65,11 @@ WORKLOADS = {
                       ((7, 7), (7, 7)), 0.05, 0.05, "pixels255"),
     "cifar": Workload("cifar", 16, 24, 45, 4, 5, (3072, 128, 10), 8, 3, (0.0, 1.0), 31, None,
                       ((7, 7), (7, 7)), 0.05, 0.05, "pixels"),
+    # the paper's toy example of the basis construction (g = 2, k = 1): g+2k = 4
+    # repeat-packed copies, one block short of the g+2k+1 a shared second
+    # comparison needs, so the first layer runs Algorithm 2 with both PolyComps
+    "toy": Workload("toy", 13, 7, 40, 1, 1, (2, 3, 1), 2, 1, (-1.0, 1.0), 15, (-4.0, 4.0),
+                    ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True, False),
     # the tiny parameters with a first layer too wide for one ciphertext
     # (384 x 16 repeat-packed slots > 4096): two input ciphertexts
     "tinychunk": Workload("tinychunk", 13, 7, 40, 1, 1, (384, 4, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),

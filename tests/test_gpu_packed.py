@@ -42,7 +42,7 @@ def test_tiny_32_vectors_bit_exact():
         octx = O.Context(O.Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w))
         model = ctx.compile(layers, refresh=True, samples=S)
         steps = model.rotation_steps()
-        assert steps == circuit.rotation_steps(layers, octx.p.slots, S)
+        assert steps == circuit.rotation_steps(layers, octx.p.slots, S, circuit.RESTRUCTURED)
         note("keygen", len(steps))
         keys = ctx.keygen(synth.SEED_KEYGEN, steps)
         ev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps))
@@ -53,7 +53,7 @@ def test_tiny_32_vectors_bit_exact():
         for li, L in enumerate(layers):
             note("layer", li)
             out = ctx.eval_kan_layer(model, keys, li, ct)
-            oout, n_blk = circuit.layer_forward(ev, [oct_], L, n_blk, li == 0, S)
+            oout, n_blk = circuit.layer_forward(ev, [oct_], L, n_blk, li == 0, S, circuit.RESTRUCTURED)
             e = out.export()
             assert out.level == oout.level
             assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "layer %d residues differ" % li
@@ -83,7 +83,7 @@ def test_formula_256_vectors_per_request():
     try:
         model = ctx.compile(layers, refresh=True, samples=S)
         steps = model.rotation_steps()
-        assert steps == circuit.rotation_steps(layers, 1 << (wl.logN - 1), S)
+        assert steps == circuit.rotation_steps(layers, 1 << (wl.logN - 1), S, circuit.RESTRUCTURED)
         note("formula keygen", len(steps))
         keys = ctx.keygen(synth.SEED_KEYGEN, steps)
         X = synth.inputs(wl, 256)

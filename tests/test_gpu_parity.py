@@ -216,7 +216,7 @@ def test_kan_tiny_layers_bit_exact_and_accuracy(tiny):
     wl, layers = tiny_model()
     model = ctx.compile(layers, refresh=True)
     steps = model.rotation_steps()
-    assert steps == circuit.rotation_steps(layers, octx.p.slots)
+    assert steps == circuit.rotation_steps(layers, octx.p.slots, circ=circuit.RESTRUCTURED)
     note("tiny keygen", len(steps))
     keys = ctx.keygen(synth.SEED_KEYGEN, steps)
     okeys = O.Keys(octx, synth.SEED_KEYGEN, steps)
@@ -228,7 +228,7 @@ def test_kan_tiny_layers_bit_exact_and_accuracy(tiny):
     for li, L in enumerate(layers):
         note("tiny layer", li)
         out = ctx.eval_kan_layer(model, keys, li, ct)
-        oout, n_blk = circuit.layer_forward(ev, [oct_], L, n_blk, li == 0)
+        oout, n_blk = circuit.layer_forward(ev, [oct_], L, n_blk, li == 0, circ=circuit.RESTRUCTURED)
         e = out.export()
         assert out.level == oout.level
         assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "layer %d residues differ" % li
@@ -251,7 +251,7 @@ def test_kan_image_accuracy(image):
                                [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
     model = ctx.compile(layers)
     steps = model.rotation_steps()
-    assert steps == circuit.rotation_steps(layers, octx.p.slots)
+    assert steps == circuit.rotation_steps(layers, octx.p.slots, circ=circuit.RESTRUCTURED)
     note("image keygen", len(steps))
     keys = ctx.keygen(synth.SEED_KEYGEN, steps)
     x = synth.inputs(wl, 2)
@@ -351,7 +351,7 @@ def test_kan_chunked_first_layer_bit_exact(tiny):
     bounds = model.input_chunks()
     assert bounds == circuit.chunk_bounds(layers[0], octx.p.slots) == [0, 256, 384]
     steps = model.rotation_steps()
-    assert steps == circuit.rotation_steps(layers, octx.p.slots)
+    assert steps == circuit.rotation_steps(layers, octx.p.slots, circ=circuit.RESTRUCTURED)
     note("tinychunk keygen", len(steps))
     keys = ctx.keygen(synth.SEED_KEYGEN, steps)
     okeys = O.Keys(octx, synth.SEED_KEYGEN, steps)
@@ -363,7 +363,7 @@ def test_kan_chunked_first_layer_bit_exact(tiny):
     alone = [ctx.eval_kan_layer_batch(model, keys, 0, [r])[0] for r in reqs]
     note("tinychunk layer 0 oracle")
     ocs = [ev.encrypt(x[0][lo:hi], synth.SEED_ENC + c) for c, (lo, hi) in enumerate(zip(bounds[:-1], bounds[1:]))]
-    oout, _ = circuit.layer_forward(ev, ocs, layers[0], layers[0].n_in, True)
+    oout, _ = circuit.layer_forward(ev, ocs, layers[0], layers[0].n_in, True, circ=circuit.RESTRUCTURED)
     e = alone[0].export()
     assert alone[0].level == oout.level
     assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "chunked layer residues differ"
@@ -389,7 +389,7 @@ def test_kan_cifar_chunked_accuracy_and_batch(image):
     model = ctx.compile(layers)
     assert model.input_chunks() == [0, 2048, 3072]
     steps = model.rotation_steps()
-    assert steps == circuit.rotation_steps(layers, octx.p.slots)
+    assert steps == circuit.rotation_steps(layers, octx.p.slots, circ=circuit.RESTRUCTURED)
     note("cifar keygen", len(steps))
     keys = ctx.keygen(synth.SEED_KEYGEN, steps)
     x = synth.inputs(wl, 2)

@@ -484,29 +484,75 @@ def test_odd_poly_depths_on_simulator():
         assert np.abs(out.v - kan.eval_odd(x, a)).max() < 1e-12
 
 
-@pytest.mark.parametrize("name", ["tiny", "image", "cifar", "tinychunk"])
-def test_circuit_on_simulator_equals_fp64_kan(name):
+_COMPILED = {}
+
+
+def compiled_layers(name, ncal=512):
+    """The workload's HE-friendly layers (oracle compile), computed once per
+    test session (the calibration pass is the slow part)."""
+    if (name, ncal) not in _COMPILED:
+        wl = synth.WORKLOADS[name]
+        raw = synth.raw_weights(wl)
+        _COMPILED[name, ncal] = kan.compile_model(raw, synth.calibration_inputs(wl, ncal),
+                                                  [wl.silu_degree] * len(raw), [list(c) for c in wl.comp_degrees],
+                                                  wl.grid, wl.silu_range, prescale=wl.prescale)
+    return _COMPILED[name, ncal]
+
+
+CIRCUITS = {"paper": circuit.PAPER, "shared": circuit.Circuit(shared_comparison=True),
+            "fused": circuit.Circuit(fused_linear=True), "folded": circuit.Circuit(folded_period=True),
+            "restructured": circuit.RESTRUCTURED}
+
+
+@pytest.mark.parametrize("circ", list(CIRCUITS))
+@pytest.mark.parametrize("name", ["tiny", "toy", "image", "cifar", "tinychunk"])
+def test_circuit_on_simulator_equals_fp64_kan(name, circ):
     """The slot circuit (repeat packing, Algorithm 2 with rotations, fused
     weights W_f = W'P, BSGS matvecs and folding; a first layer too wide for
     one ciphertext split into feature chunks) equals the plain HE-friendly
-    network, and fits the workload's level budget."""
+    network and fits the workload's level budget, in the paper's order and
+    with each restructuring (every one changes no value of the network)."""
     wl = synth.WORKLOADS[name]
-    raw = synth.raw_weights(wl)
-    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * len(raw),
-                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+    cc = CIRCUITS[circ]
+    layers = compiled_layers(name)
     x = synth.inputs(wl, 2)
     sim = SlotSim(1 << (wl.logN - 1))
     bounds = circuit.chunk_bounds(layers[0], sim.ctx.p.slots)
-    assert len(bounds) - 1 == {"tiny": 1, "image": 1, "cifar": 2, "tinychunk": 2}[name]
+    assert len(bounds) - 1 == {"tiny": 1, "toy": 1, "image": 1, "cifar": 2, "tinychunk": 2}[name]
     for row in x:
         ct = [sim.fresh(row[lo:hi], wl.L) for lo, hi in zip(bounds[:-1], bounds[1:])]
         refresh = (lambda c, li: SimCt(wl.L, c.v)) if wl.refresh else None
-        out = circuit.eval_kan(sim, ct, layers, refresh)
+        out = circuit.eval_kan(sim, ct, layers, refresh, circ=cc)
         assert out.level >= 0
         want = kan.he_friendly_kan(row[None], layers)[0]
         assert np.abs(out.v[:len(want)] - want).max() < 1e-8 * max(1, np.abs(want).max())
-    assert sorted(sim.rot_steps) == sorted(set(circuit.rotation_steps(layers, sim.ctx.p.slots)) & sim.rot_steps)
-    assert set(circuit.rotation_steps(layers, sim.ctx.p.slots)) == sim.rot_steps
+    steps = set(circuit.rotation_steps(layers, sim.ctx.p.slots, circ=cc))
+    assert steps == sim.rot_steps
+
+
+def test_restructurings_cut_key_switches():
+    """Each restructuring, alone, needs no more key switches than the paper's
+    order for the [784,64,10] network, and all three together fewer."""
+    wl = synth.WORKLOADS["image"]
+    layers = compiled_layers("image")
+    ks = {}
+    for name, cc in CIRCUITS.items():
+        sim = SlotSim(1 << (wl.logN - 1))
+        circuit.eval_kan(sim, sim.fresh(np.zeros(784), wl.L), layers, circ=cc)
+        ks[name] = sim.count["ks"]
+    assert all(ks[n] <= ks["paper"] for n in ks)
+    assert ks["restructured"] < min(ks["shared"], ks["fused"], ks["folded"])
+
+
+def test_toy_first_layer_takes_both_comparisons():
+    """g = 2, k = 1: 4 repeat-packed copies hold one block fewer than a shared
+    second comparison needs, so Algorithm 2 runs with both PolyComps even when
+    sharing is allowed; hidden layers (periodic inputs) may share."""
+    wl = synth.WORKLOADS["toy"]
+    layers = compiled_layers("toy")
+    slots = 1 << (wl.logN - 1)
+    assert not circuit.shared_comparison(layers[0], layers[0].n_in, True, slots)
+    assert circuit.shared_comparison(layers[1], 4, False, slots)
 
 
 def test_chunk_bounds():
@@ -522,22 +568,38 @@ def test_chunk_bounds():
     assert circuit.chunk_bounds(L, 4096) == [0, 256, 512]
 
 
-def test_oracle_he_kan_tiny_matches_fp64_circuit():
+_ENC_TINY = {}
+
+
+def encrypted_tiny(circ):
+    """Encrypted [2,5,1] inference on the oracle (client-aided refresh between
+    layers) with the given circuit: the decrypted output."""
+    if circ not in _ENC_TINY:
+        wl = synth.WORKLOADS["tiny"]
+        layers = compiled_layers("tiny", 4096)
+        cc = CIRCUITS[circ]
+        prm = Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+        ctx = ckks.Context(prm)
+        keys = ckks.Keys(ctx, synth.SEED_KEYGEN, circuit.rotation_steps(layers, prm.slots, circ=cc))
+        ev = ckks.Oracle(ctx, keys)
+        x = synth.inputs(wl, 1)[0]
+        out = circuit.eval_kan(ev, ev.encrypt(x, synth.SEED_ENC), layers,
+                               lambda c, li: ev.encrypt(ev.decrypt(c, prm.slots), 100 + li), circ=cc)
+        _ENC_TINY[circ] = (ev.decrypt(out, 1), kan.he_friendly_kan(x[None], layers)[0], ev.count["ks"])
+    return _ENC_TINY[circ]
+
+
+@pytest.mark.parametrize("circ", list(CIRCUITS))
+def test_oracle_he_kan_tiny_matches_fp64_circuit(circ):
     """Encrypted inference on the oracle (tiny workload, client-aided refresh
-    between layers) decrypts to the FP64 HE-friendly circuit within 1e-2."""
-    wl = synth.WORKLOADS["tiny"]
-    raw = synth.raw_weights(wl)
-    layers = kan.compile_model(raw, synth.calibration_inputs(wl), [wl.silu_degree] * 2,
-                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
-    prm = Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
-    ctx = ckks.Context(prm)
-    keys = ckks.Keys(ctx, synth.SEED_KEYGEN, circuit.rotation_steps(layers, prm.slots))
-    ev = ckks.Oracle(ctx, keys)
-    x = synth.inputs(wl, 1)[0]
-    out = circuit.eval_kan(ev, ev.encrypt(x, synth.SEED_ENC), layers,
-                           lambda c, li: ev.encrypt(ev.decrypt(c, prm.slots), 100 + li))
-    y = ev.decrypt(out, 1)
-    assert abs(y[0] - kan.he_friendly_kan(x[None], layers)[0, 0]) < 1e-2
+    between layers) decrypts to the FP64 HE-friendly circuit within 1e-2, in
+    the paper's order and with each restructuring; every variant decrypts
+    within 1e-2 of the paper-order encrypted run."""
+    y, want, ks = encrypted_tiny(circ)
+    assert abs(y[0] - want[0]) < 1e-2
+    y0, _, ks0 = encrypted_tiny("paper")
+    assert abs(y[0] - y0[0]) < 1e-2
+    assert ks <= ks0
 
 
 def test_strided_weights_equal_kronecker_product():
@@ -556,22 +618,22 @@ def test_strided_weights_equal_kronecker_product():
     assert (K2[:, 16:28] == np.kron(M2[:, 3:], np.eye(4))).all() and (K2[:, 28:] == 0).all()
 
 
+@pytest.mark.parametrize("circ", ["paper", "restructured"])
 @pytest.mark.parametrize("name,S", [("tiny", 32), ("formula", 64)])
-def test_packed_vectors_on_simulator_equal_fp64_kan(name, S):
+def test_packed_vectors_on_simulator_equal_fp64_kan(name, S, circ):
     """S input vectors in one ciphertext (feature i of vector s in slot i S + s):
     every vector's output equals the FP64 HE-friendly network, within the
     level budget, with the rotation steps the circuit declares."""
     wl = synth.WORKLOADS[name]
-    raw = synth.raw_weights(wl)
-    layers = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * len(raw),
-                               [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+    layers = compiled_layers(name)
     X = synth.inputs(wl, S)
     sim = SlotSim(1 << (wl.logN - 1))
     assert circuit.chunk_bounds(layers[0], sim.ctx.p.slots, S) == [0, wl.shape[0]]
     refresh = (lambda c, li: SimCt(wl.L, c.v)) if wl.refresh else None
-    out = circuit.eval_kan(sim, sim.fresh(circuit.pack_samples(X, S), wl.L), layers, refresh, S)
+    cc = CIRCUITS[circ]
+    out = circuit.eval_kan(sim, sim.fresh(circuit.pack_samples(X, S), wl.L), layers, refresh, S, cc)
     assert out.level >= 0
     want = kan.he_friendly_kan(X, layers)                     # (S, n_out)
     got = out.v[:wl.shape[-1] * S].reshape(wl.shape[-1], S).T
     assert np.abs(got - want).max() < 1e-8 * max(1, np.abs(want).max())
-    assert set(circuit.rotation_steps(layers, sim.ctx.p.slots, S)) == sim.rot_steps
+    assert set(circuit.rotation_steps(layers, sim.ctx.p.slots, S, cc)) == sim.rot_steps
