@@ -20,9 +20,15 @@
  *     NUL-terminated message for the last failure on that context;
  *   - pointers to double/uint64_t/int32_t buffers are HOST pointers owned by
  *     the caller; the library copies what it needs before returning;
- *   - every handle (he_ctx, he_model, he_keys, he_ct) is owned by the library
- *     and released with the matching *_free / he_ctx_destroy; handles keep
- *     their data resident in device memory (HBM);
+ *   - every handle (he_ctx, he_model, he_secret_key, he_eval_keys, he_ct,
+ *     he_graph) is owned by the library and released with the matching
+ *     *_free / he_ctx_destroy; handles keep their data resident in device
+ *     memory (HBM), except the secret key, which stays in host memory;
+ *   - handles may be released in any order: he_ctx_destroy ends the context
+ *     for the caller at once (no further call may pass it), and the library
+ *     releases its device memory when the last handle made from it is freed;
+ *   - a handle passed together with a context must have been made by that
+ *     context (HE_ESTATE otherwise);
  *   - a context is not thread-safe: use one context per host thread; work is
  *     issued on the context's stream and functions that return host data
  *     synchronise that stream;
@@ -52,7 +58,8 @@ enum {
 
 typedef struct he_ctx he_ctx;
 typedef struct he_model he_model;
-typedef struct he_keys he_keys;
+typedef struct he_secret_key he_secret_key;
+typedef struct he_eval_keys he_eval_keys;
 typedef struct he_ct he_ct;
 typedef struct he_graph he_graph;
 
@@ -116,7 +123,28 @@ typedef struct {
      * many.  Every layer must fit: (g+2k) blocks of (previous output period
      * d) S slots within N/2. */
     int32_t samples_per_ct;
+    /* Which restructurings of the paper's layer circuit to apply (a bitwise OR
+     * of HE_CIRCUIT_*; 0 runs the circuit in the paper's order: Algorithm 2
+     * with both PolyComps, W_f times the bases and W_b times the SiLU values
+     * as two products, each folded over all slots).  None changes a value of
+     * the FP64 circuit; each cuts key switches. */
+    int32_t circuit;
 } he_kan_desc;
+
+enum {
+    /* The second comparison S((t_{m+2} - x)/2R) is 1 - S((x - t_{m+2})/2R)
+     * because the composite is odd: 1 minus the first comparison of block
+     * m+1 (one rotation instead of a second PolyComp), where the input holds
+     * g+2k+1 blocks. */
+    HE_CIRCUIT_SHARED_COMPARISON = 1,
+    /* SiLU on the repeat-packed input, its coefficients masked to block g+k,
+     * added to the bases: one product with [W_f | W_b] and one fold. */
+    HE_CIRCUIT_FUSED_LINEAR = 2,
+    /* A hidden layer's block layout repeats with the shortest power-of-two
+     * period that holds its blocks; the fold runs over one period. */
+    HE_CIRCUIT_FOLDED_PERIOD = 4,
+    HE_CIRCUIT_RESTRUCTURED = 7
+};
 
 /* ---------------------------------------------------------------- context */
 
@@ -157,16 +185,15 @@ int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, doubl
  * on one XCD whatever the batch element).  Every configuration computes the
  * same residues; only the time differs.
  * he_ctx_autotune times each configuration at every level 0..L for `batch`
- * elements (one key switch with the relinearisation key of k on a zero input,
+ * elements (one key switch with the relinearisation key of ek on a zero input,
  * the median of `reps` runs after a warm-up), keeps the fastest for that batch
  * size, and writes the choices of levels 0..min(cap, L+1)-1 to choice and L+1
  * to *n.  It synchronises the stream (HE_ESTATE while a graph is being
  * captured on it).  he_ctx_set_keyswitch sets one entry by hand (HE_EINVAL for
  * another config value). */
-int he_ctx_autotune(he_ctx *ctx, const he_keys *k, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
+int he_ctx_autotune(he_ctx *ctx, const he_eval_keys *ek, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
                     size_t *n);
 int he_ctx_set_keyswitch(he_ctx *ctx, int32_t level, int32_t batch, int32_t config);
-
 /* ------------------------------------------------------------------ model */
 
 /* Compile a KAN for encrypted evaluation: checks the layer shapes and their
@@ -196,28 +223,50 @@ int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t
 
 /* -------------------------------------------------------------------- keys */
 
-/* Generate a secret key (ternary, kept host-side inside the handle) and
- * evaluation keys resident in HBM: the relinearisation key and one Galois key
- * per rotation step in steps[0..nsteps).  All randomness is drawn from
+/* The secret key and the evaluation keys are separate handles, as the
+ * paper's threat model separates the parties (Preliminaries, Threat Model):
+ * the client keeps the secret key, the server evaluates with the evaluation
+ * keys alone and never holds the secret.
+ *
+ * he_keygen draws a ternary secret s (kept in host memory inside *sk; a
+ * client operation uploads it to the device for its own duration and clears
+ * that copy before returning) and the evaluation keys resident in HBM (*ek):
+ * the relinearisation key (for s^2) and one Galois key per rotation step in
+ * steps[0..nsteps) (for sigma_{5^t}(s)).  All randomness is drawn from
  * ChaCha20 keyed by `seed`. */
-int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_keys **out);
-int he_keys_free(he_keys *k);
+int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_secret_key **sk,
+              he_eval_keys **ek);
+int he_secret_key_free(he_secret_key *sk);
+int he_eval_keys_free(he_eval_keys *ek);
 
-/* Export one switching-key component in coefficient form for checking:
- * key_id 0 = relinearisation key, otherwise the Galois element 5^t mod 2N;
- * writes [2][L+1+alpha][N] residues (b then a) of digit `digit`. */
-int he_keys_export(he_ctx *ctx, const he_keys *k, uint32_t key_id, int32_t digit, uint64_t *out,
-                   size_t cap);
+/* Key ids held by ek: 0 for the relinearisation key, then the Galois elements
+ * 5^t mod 2N in increasing order.  Writes min(cap, total) ids and the total
+ * to *n. */
+int he_eval_keys_ids(const he_eval_keys *ek, uint32_t *ids, size_t cap, size_t *n);
+
+/* Export one digit of one switching key in coefficient form (what a client
+ * sends to a server): key_id as in he_eval_keys_ids; writes the [2][L+1+alpha][N]
+ * residues (b then a) of digit `digit` (0 <= digit < ceil((L+1) / digit_width)). */
+int he_eval_keys_export(he_ctx *ctx, const he_eval_keys *ek, uint32_t key_id, int32_t digit, uint64_t *out,
+                        size_t cap);
+
+/* Build evaluation keys from exported key material alone (no secret): keys
+ * ids[0..nkeys) (distinct, each 0 or a Galois element), key i given by
+ * data[i] as [dnum][2][L+1+alpha][N] residues in coefficient form, digit
+ * after digit as he_eval_keys_export writes them.  HE_EINVAL for an id that
+ * is not a Galois element, a repeated id or an unreduced residue. */
+int he_eval_keys_import(he_ctx *ctx, const uint32_t *ids, size_t nkeys, const uint64_t *const *data,
+                        he_eval_keys **out);
 
 /* ------------------------------------------------------------- ciphertexts */
 
 /* Encrypt x[0..n) (raster-scanned input, slots n..N/2-1 are zero) under the
  * secret key at the top level: (-a s + e + m, a), with a and e drawn from
  * ChaCha20 keyed by `seed`. */
-int he_encrypt(he_ctx *ctx, const he_keys *k, const double *x, size_t n, uint64_t seed, he_ct **out);
+int he_encrypt(he_ctx *ctx, const he_secret_key *sk, const double *x, size_t n, uint64_t seed, he_ct **out);
 
 /* Decrypt and decode the first n slots into y. */
-int he_decrypt(he_ctx *ctx, const he_keys *k, const he_ct *ct, double *y, size_t n);
+int he_decrypt(he_ctx *ctx, const he_secret_key *sk, const he_ct *ct, double *y, size_t n);
 
 /* Level of a ciphertext (its scale is the canonical S_level). */
 int he_ct_level(const he_ct *ct);
@@ -234,26 +283,26 @@ int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out);
 /* Run the whole network on `in` (server side; no secret key involved) for a
  * model with one input ciphertext (HE_ESHAPE otherwise).  Asynchronous on the
  * context stream; *out is a new ciphertext. */
-int he_eval_kan(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *in, he_ct **out);
+int he_eval_kan(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, const he_ct *in, he_ct **out);
 
 /* The same for any input layout: in[0..n_in) are the input chunks in order
  * (n_in must equal he_model_input_chunks' count, HE_ESHAPE otherwise).  Each
  * chunk runs the first layer's packing, bases and SiLU on its own and is
  * multiplied by its columns of the layer's weights; the partial sums are
  * added before the layer's fold. */
-int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n_in,
+int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, const he_ct *const *in, size_t n_in,
                        he_ct **out);
 
 /* Run layer `layer` only (for client-aided refresh between layers); layer 0
  * of a model with several input chunks needs he_eval_kan_layer_batch. */
-int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer, const he_ct *in,
+int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, int32_t layer, const he_ct *in,
                       he_ct **out);
 
 /* Run the network on n independent requests in one batched pass: every ring
  * kernel processes all requests' limbs in one launch.  in holds n * nc
  * ciphertexts, request-major (request i's chunk c at in[i nc + c], nc = the
  * model's input chunk count); out receives n ciphertexts. */
-int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, const he_ct *const *in, size_t n,
                       he_ct **out);
 
 /* A batched inference (as he_eval_kan_batch) captured once into a HIP graph
@@ -268,7 +317,7 @@ int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he
  * outputs and temporaries allocated until he_graph_free (freeing the handles
  * earlier is allowed); free it before its context.  Errors: HE_EINVAL for
  * null arguments or n = 0, HE_EDEVICE if the runtime refuses the capture. */
-int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, const he_ct *const *in, size_t n,
                                he_ct **out, he_graph **g);
 int he_graph_launch(he_graph *g);
 int he_graph_free(he_graph *g);
@@ -277,7 +326,7 @@ int he_graph_free(he_graph *g);
  * pass: the building block of layer-granular continuous batching.  For layer
  * 0, in holds n * nc ciphertexts laid out as for he_eval_kan_batch; for later
  * layers, n. */
-int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer,
+int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, int32_t layer,
                             const he_ct *const *in, size_t n, he_ct **out);
 
 /* Device memory held by the context's pool: bytes in live buffers, bytes
@@ -290,9 +339,9 @@ int he_ctx_memory(he_ctx *ctx, uint64_t *live, uint64_t *cached, uint64_t *peak,
 /* out = a + b (same level). */
 int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
 /* out = a (x) b: tensor, relinearise (hybrid key switch), rescale (level - 1). */
-int he_ct_mul(he_ctx *ctx, const he_keys *k, const he_ct *a, const he_ct *b, he_ct **out);
+int he_ct_mul(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, const he_ct *b, he_ct **out);
 /* out = rot(a, step): slots move left by step (right if negative). */
-int he_ct_rotate(he_ctx *ctx, const he_keys *k, const he_ct *a, int32_t step, he_ct **out);
+int he_ct_rotate(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, int32_t step, he_ct **out);
 /* out = rescale(a): divide by q_level with rounding, drop one limb. */
 int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
 /* out = sum_i a[i] * z_i landing at level `target` with scale S_target; z_i

@@ -1,4 +1,6 @@
 // extern "C" boundary of the library (declared in include/hekan.h).
+#include <algorithm>
+#include <atomic>
 #include <cstring>
 
 #include "../../include/hekan.h"
@@ -7,15 +9,22 @@
 
 using namespace hk;
 
+// A context lives until it has been destroyed and every handle made from it
+// has been freed (each handle holds one reference, the caller one more).
 struct he_ctx {
     Ctx *c;
     std::string err;
+    std::atomic<long> refs{1};
 };
 struct he_model {
     he_ctx *owner;
     Model *m;
 };
-struct he_keys {
+struct he_secret_key {
+    he_ctx *owner;
+    SecretKey *k;
+};
+struct he_eval_keys {
     he_ctx *owner;
     Keys *k;
 };
@@ -32,6 +41,20 @@ struct he_graph {
 };
 
 namespace {
+he_ctx *retain(he_ctx *h)
+{
+    h->refs.fetch_add(1);
+    return h;
+}
+
+void release(he_ctx *h)
+{
+    if (h->refs.fetch_sub(1) == 1) {
+        delete h->c;
+        delete h;
+    }
+}
+
 template <class F>
 int guard(he_ctx *ctx, F f)
 {
@@ -69,7 +92,7 @@ void need(bool ok, const char *msg)
 he_ct *wrap(he_ctx *ctx, Ct c)
 {
     he_ct *h = new he_ct();
-    h->owner = ctx;
+    h->owner = retain(ctx);
     h->c = std::move(c);
     return h;
 }
@@ -81,6 +104,18 @@ void check_ct(he_ctx *ctx, const he_ct *c)
 {
     need(c != nullptr, "null ciphertext");
     if (c->owner != ctx) throw HeError(HE_ESTATE, "ciphertext belongs to another context");
+}
+
+void check_ek(he_ctx *ctx, const he_eval_keys *k)
+{
+    need(k != nullptr, "null evaluation keys");
+    if (k->owner != ctx) throw HeError(HE_ESTATE, "evaluation keys of another context");
+}
+
+void check_sk(he_ctx *ctx, const he_secret_key *k)
+{
+    need(k != nullptr, "null secret key");
+    if (k->owner != ctx) throw HeError(HE_ESTATE, "secret key of another context");
 }
 }  // namespace
 
@@ -115,8 +150,7 @@ int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out)
 int he_ctx_destroy(he_ctx *ctx)
 {
     if (!ctx) return HE_EINVAL;
-    delete ctx->c;
-    delete ctx;
+    release(ctx);
     return HE_OK;
 }
 
@@ -153,12 +187,13 @@ int he_ctx_profile(he_ctx *ctx, int32_t kernel)
     return guard(ctx, [&]() { ctx->c->profile(kernel); });
 }
 
-int he_ctx_autotune(he_ctx *ctx, const he_keys *k, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
+int he_ctx_autotune(he_ctx *ctx, const he_eval_keys *k, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
                     size_t *n)
 {
     if (!ctx || !k || !n || batch < 1 || reps < 1 || (cap && !choice)) return HE_EINVAL;
     return guard(ctx, [&]() {
-        if (k->owner != ctx) throw HeError(HE_ESTATE, "keys of another context");
+        check_ek(ctx, k);
+        if (!k->k->has_relin) throw HeError(HE_EKEY, "no relinearisation key");
         const std::vector<int> c = ctx->c->autotune_keyswitch(k->k->relin, batch, reps);
         *n = c.size();
         for (size_t i = 0; i < c.size() && i < cap; i++) choice[i] = c[i];
@@ -195,15 +230,17 @@ int he_model_compile(he_ctx *ctx, const he_kan_desc *desc, int32_t refresh, he_m
     return guard(ctx, [&]() {
         need(desc != nullptr, "null model description");
         Model *m = new Model(ctx->c, desc, refresh != 0);
-        *out = new he_model{ctx, m};
+        *out = new he_model{retain(ctx), m};
     });
 }
 
 int he_model_free(he_model *m)
 {
     if (!m) return HE_EINVAL;
+    he_ctx *o = m->owner;
     delete m->m;
     delete m;
+    release(o);
     return HE_OK;
 }
 
@@ -216,78 +253,96 @@ int he_model_rotation_steps(const he_model *m, int32_t *steps, size_t cap, size_
     return HE_OK;
 }
 
-int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_keys **out)
+int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_secret_key **sk,
+              he_eval_keys **ek)
 {
-    if (!ctx || !out) return HE_EINVAL;
-    *out = nullptr;
+    if (!ctx || !sk || !ek) return HE_EINVAL;
+    *sk = nullptr;
+    *ek = nullptr;
     return guard(ctx, [&]() {
         need(nsteps == 0 || steps != nullptr, "null steps");
         std::vector<long> st(steps, steps + nsteps);
-        Keys *k = ctx->c->keygen(seed, st);
-        *out = new he_keys{ctx, k};
+        SecretKey *s = nullptr;
+        Keys *k = nullptr;
+        ctx->c->keygen(seed, st, s, k);
+        *sk = new he_secret_key{retain(ctx), s};
+        *ek = new he_eval_keys{retain(ctx), k};
     });
 }
 
-int he_keys_free(he_keys *k)
+int he_secret_key_free(he_secret_key *k)
 {
     if (!k) return HE_EINVAL;
+    he_ctx *o = k->owner;
+    std::fill(k->k->s.begin(), k->k->s.end(), 0);
     delete k->k;
     delete k;
+    release(o);
     return HE_OK;
 }
 
-int he_keys_export(he_ctx *ctx, const he_keys *k, uint32_t key_id, int32_t digit, uint64_t *out, size_t cap)
+int he_eval_keys_free(he_eval_keys *k)
+{
+    if (!k) return HE_EINVAL;
+    he_ctx *o = k->owner;
+    delete k->k;
+    delete k;
+    release(o);
+    return HE_OK;
+}
+
+int he_eval_keys_ids(const he_eval_keys *k, uint32_t *ids, size_t cap, size_t *n)
+{
+    if (!k || !n || (cap && !ids)) return HE_EINVAL;
+    std::vector<uint32_t> v;
+    if (k->k->has_relin) v.push_back(0);
+    for (auto &g : k->k->galois) v.push_back((uint32_t)g.first);
+    *n = v.size();
+    for (size_t i = 0; i < v.size() && i < cap; i++) ids[i] = v[i];
+    return HE_OK;
+}
+
+int he_eval_keys_export(he_ctx *ctx, const he_eval_keys *k, uint32_t key_id, int32_t digit, uint64_t *out,
+                        size_t cap)
 {
     if (!ctx || !k || !out) return HE_EINVAL;
     return guard(ctx, [&]() {
+        check_ek(ctx, k);
         Ctx &c = *ctx->c;
-        const int ktot = c.L + 1 + c.alpha;
-        need(digit >= 0 && digit < c.dnum_top(), "digit out of range");
-        need(cap >= (size_t)2 * ktot * c.N, "output buffer too small");
-        const SwitchKey *sk = nullptr;
-        if (key_id == 0) sk = &k->k->relin;
-        else {
-            auto it = k->k->galois.find(key_id);
-            if (it == k->k->galois.end()) throw HeError(HE_EKEY, "no such key");
-            sk = &it->second;
-        }
-        Buf tmp = c.alloc((size_t)2 * ktot * c.N);
-        const u64 *src = sk->buf->p + (size_t)digit * 2 * ktot * c.N;
-        if (key_id == 0) {
-            HIP_CHECK(hipMemcpyAsync(tmp->p, src, (size_t)2 * ktot * c.N * 8, hipMemcpyDeviceToDevice, c.st));
-        } else {
-            // Galois keys are stored permuted by sigma^-1: undo it
-            launch_automorph(PolySet{tmp->p, (long)c.N, 0, 2 * ktot, 1}, PolySet{(u64 *)src, (long)c.N, 0, 2 * ktot, 1},
-                             key_id, c.logN, c.st);
-        }
-        // leave Montgomery form: multiply by 2^-64 = REDC(x, 0) via x * (2^-64 mod q)
-        std::vector<u64> inv(2 * ktot);
-        for (int t = 0; t < ktot; t++) {
-            u64 m = c.mods[t];
-            inv[t] = hinv(c.pc[t].r1, m);
-            inv[ktot + t] = shoup_of(inv[t], m);
-        }
-        Buf dinv = c.alloc(inv.size());
-        c.upload(dinv->p, inv.data(), inv.size());
-        LimbMap lm = c.lmap(c.L + 1);
-        PolySet ps{tmp->p, (long)c.N, (long)ktot * c.N, ktot, 2};
-        launch_mul_scalar(c.d_pc, ps, ps, dinv->p, dinv->p + ktot, lm, c.N, c.st);
-        c.ntt(ps, lm, true);
-        c.download(U(out), tmp->p, (size_t)2 * ktot * c.N);
+        need(cap >= (size_t)2 * (c.L + 1 + c.alpha) * c.N, "output buffer too small");
+        c.export_key(*k->k, key_id, digit, U(out));
     });
 }
 
-int he_encrypt(he_ctx *ctx, const he_keys *k, const double *x, size_t n, uint64_t seed, he_ct **out)
+int he_eval_keys_import(he_ctx *ctx, const uint32_t *ids, size_t nkeys, const uint64_t *const *data,
+                        he_eval_keys **out)
+{
+    if (!ctx || !out || (nkeys && (!ids || !data))) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        std::vector<u32> id(ids, ids + nkeys);
+        std::vector<const u64 *> d;
+        for (size_t i = 0; i < nkeys; i++) d.push_back(U(data[i]));
+        Keys *k = ctx->c->import_keys(id, d);
+        *out = new he_eval_keys{retain(ctx), k};
+    });
+}
+
+int he_encrypt(he_ctx *ctx, const he_secret_key *k, const double *x, size_t n, uint64_t seed, he_ct **out)
 {
     if (!ctx || !k || !out || (n && !x)) return HE_EINVAL;
     *out = nullptr;
-    return guard(ctx, [&]() { *out = wrap(ctx, ctx->c->encrypt(*k->k, x, n, seed)); });
+    return guard(ctx, [&]() {
+        check_sk(ctx, k);
+        *out = wrap(ctx, ctx->c->encrypt(*k->k, x, n, seed));
+    });
 }
 
-int he_decrypt(he_ctx *ctx, const he_keys *k, const he_ct *ct, double *y, size_t n)
+int he_decrypt(he_ctx *ctx, const he_secret_key *k, const he_ct *ct, double *y, size_t n)
 {
     if (!ctx || !k || !y) return HE_EINVAL;
     return guard(ctx, [&]() {
+        check_sk(ctx, k);
         check_ct(ctx, ct);
         need(n <= (size_t)ctx->c->N / 2, "too many slots requested");
         ctx->c->decrypt(*k->k, ct->c, y, n);
@@ -299,7 +354,9 @@ int he_ct_level(const he_ct *ct) { return ct ? ct->c.level : HE_EINVAL; }
 int he_ct_free(he_ct *ct)
 {
     if (!ct) return HE_EINVAL;
+    he_ctx *o = ct->owner;
     delete ct;
+    release(o);
     return HE_OK;
 }
 
@@ -357,9 +414,10 @@ static std::vector<Ct> batch_inputs(he_ctx *ctx, const he_ct *const *in, size_t 
     return xs;
 }
 
-static void check_model(he_ctx *ctx, const he_model *m, const he_keys *k)
+static void check_model(he_ctx *ctx, const he_model *m, const he_eval_keys *k)
 {
-    if (m->owner != ctx || k->owner != ctx) throw HeError(HE_ESTATE, "handle of another context");
+    if (m->owner != ctx) throw HeError(HE_ESTATE, "model of another context");
+    check_ek(ctx, k);
 }
 
 int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t *n)
@@ -372,12 +430,12 @@ int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t
     return HE_OK;
 }
 
-int he_eval_kan(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *in, he_ct **out)
+int he_eval_kan(he_ctx *ctx, const he_model *m, const he_eval_keys *k, const he_ct *in, he_ct **out)
 {
     return he_eval_kan_chunks(ctx, m, k, &in, 1, out);
 }
 
-int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n_in,
+int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_eval_keys *k, const he_ct *const *in, size_t n_in,
                        he_ct **out)
 {
     if (!ctx || !m || !k || !out || !in) return HE_EINVAL;
@@ -390,7 +448,7 @@ int he_eval_kan_chunks(he_ctx *ctx, const he_model *m, const he_keys *k, const h
     });
 }
 
-int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer, const he_ct *in,
+int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_eval_keys *k, int32_t layer, const he_ct *in,
                       he_ct **out)
 {
     if (!ctx || !m || !k || !out) return HE_EINVAL;
@@ -398,7 +456,7 @@ int he_eval_kan_layer(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t 
     return he_eval_kan_layer_batch(ctx, m, k, layer, &in, 1, out);
 }
 
-int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *k, const he_ct *const *in, size_t n,
                       he_ct **out)
 {
     if (!ctx || !m || !k || !out || (n && !in)) return HE_EINVAL;
@@ -412,7 +470,7 @@ int he_eval_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he
     });
 }
 
-int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, int32_t layer,
+int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *k, int32_t layer,
                             const he_ct *const *in, size_t n, he_ct **out)
 {
     if (!ctx || !m || !k || !out || (n && !in)) return HE_EINVAL;
@@ -428,7 +486,7 @@ int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_keys *k, in
     });
 }
 
-int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k, const he_ct *const *in, size_t n,
+int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *k, const he_ct *const *in, size_t n,
                                he_ct **out, he_graph **g)
 {
     if (!ctx || !m || !k || !out || !g || !in || n == 0) return HE_EINVAL;
@@ -447,7 +505,7 @@ int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k,
         }
         c.sync();
         std::unique_ptr<he_graph> gr(new he_graph);
-        gr->owner = ctx;
+        gr->owner = ctx;  // retained once the graph is complete
         const int timer = c.timer.target;
         c.timer.target = -1;
         c.pool.hold = &gr->held;
@@ -480,6 +538,7 @@ int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_keys *k,
         for (size_t i = 0; i < n * nin; i++) gr->keep.push_back(in[i]->c);
         for (auto &o : outs) gr->keep.push_back(o);
         for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, outs[i]);
+        retain(ctx);
         *g = gr.release();
     });
 }
@@ -493,15 +552,15 @@ int he_graph_launch(he_graph *g)
 int he_graph_free(he_graph *g)
 {
     if (!g) return HE_EINVAL;
-    return guard(g->owner, [&]() {
-        Ctx &c = *g->owner->c;
-        c.sync();
-        if (g->exec) (void)hipGraphExecDestroy(g->exec);
-        if (g->graph) (void)hipGraphDestroy(g->graph);
-        for (auto &h : g->held) c.pool.put(h.second, h.first);
-        g->keep.clear();
-        delete g;
-    });
+    he_ctx *o = g->owner;
+    const int rc = guard(o, [&]() { o->c->sync(); });
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (auto &h : g->held) o->c->pool.put(h.second, h.first);
+    g->keep.clear();
+    delete g;
+    release(o);
+    return rc;
 }
 
 int he_ctx_memory(he_ctx *ctx, uint64_t *live, uint64_t *cached, uint64_t *peak, int32_t reset_peak)
@@ -525,10 +584,11 @@ int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out)
     });
 }
 
-int he_ct_mul(he_ctx *ctx, const he_keys *k, const he_ct *a, const he_ct *b, he_ct **out)
+int he_ct_mul(he_ctx *ctx, const he_eval_keys *k, const he_ct *a, const he_ct *b, he_ct **out)
 {
     if (!ctx || !k || !out) return HE_EINVAL;
     return guard(ctx, [&]() {
+        check_ek(ctx, k);
         check_ct(ctx, a);
         check_ct(ctx, b);
         need(a->c.level == b->c.level, "operands at different levels");
@@ -537,10 +597,11 @@ int he_ct_mul(he_ctx *ctx, const he_keys *k, const he_ct *a, const he_ct *b, he_
     });
 }
 
-int he_ct_rotate(he_ctx *ctx, const he_keys *k, const he_ct *a, int32_t step, he_ct **out)
+int he_ct_rotate(he_ctx *ctx, const he_eval_keys *k, const he_ct *a, int32_t step, he_ct **out)
 {
     if (!ctx || !k || !out) return HE_EINVAL;
     return guard(ctx, [&]() {
+        check_ek(ctx, k);
         check_ct(ctx, a);
         *out = wrap(ctx, ctx->c->rotate(a->c, step, *k->k));
     });

@@ -527,22 +527,30 @@ const u64 *Ctx::rescale_addend(int l, long k, double c)
     return rescale_add.emplace(key, b).first->second->p;
 }
 
+// the dropped limb to coefficient form (into last, np N words), then the
+// fused transforms of the rescale (intermediate in tmp, l np N words) into o
+static void rescale_launch(Ctx &c, const Ct &a, Ct &o, const Buf &inv, const u64 *cadd, u64 *last, u64 *tmp)
+{
+    const int l = a.level, np = 2 * a.nb;
+    const long N = c.N;
+    c.n_rescale++;
+    launch_intt_from(c.T, PolySet{last, N, N, 1, np}, LimbMap{1, c.L1, l}, a.d() + (size_t)l * 2 * N * a.nb,
+                     2l * N * a.nb, N, 0, nullptr, nullptr, c.st, &c.timer);
+    launch_rescale_ntt(c.T, tmp, l, np, last, c.q[l], a.d(), 2l * N * a.nb, N, o.d(), 2l * N * a.nb, N, inv->p,
+                       inv->p + l, (const TwF *)(inv->p + 2 * l), nullptr, nullptr, cadd, c.L1, c.st, &c.timer);
+    c.n_launch += 4;
+}
+
 Ct Ctx::rescale_affine(const Ct &a, long k, const double *c)
 {
     const int l = a.level, np = 2 * a.nb;
     if (l < 1) throw HeError(-3, "rescale: no level left");
-    n_rescale++;
     Buf last = alloc((size_t)np * N);
-    launch_intt_from(T, PolySet{last->p, (long)N, (long)N, 1, np}, LimbMap{1, L1, l},
-                     a.d() + (size_t)l * 2 * N * a.nb, 2l * N * a.nb, (long)N, 0, nullptr, nullptr, st, &timer);
     Buf tmp = alloc((size_t)l * np * N);
     Ct o = new_ct(l - 1, a.nb);
     const Buf &inv = rescale_table(l, k);
     const u64 *cadd = c ? rescale_addend(l, k, *c) : nullptr;
-    launch_rescale_ntt(T, tmp->p, l, np, last->p, q[l], a.d(), 2l * N * a.nb, (long)N, o.d(), 2l * N * a.nb,
-                       (long)N, inv->p, inv->p + l, (const TwF *)(inv->p + 2 * l), nullptr, nullptr, cadd, L1, st,
-                       &timer);
-    n_launch += 4;
+    rescale_launch(*this, a, o, inv, cadd, last->p, tmp->p);
     return o;
 }
 
@@ -841,6 +849,7 @@ Ct Ctx::relin_rescale(const Tensor &t, const Keys &k, long mul, const double *ca
 {
     const u64 *tb = t.buf->p;
     const long ls = 3l * N * t.nb, es = 3l * N;
+    if (!k.has_relin) throw HeError(-5, "no relinearisation key");
     if (t.level >= 1) {
         Buf acc = keyswitch_acc(tb + 2 * (size_t)N, ls, es, t.level, t.nb, k.relin);
         Ct o = new_ct(t.level - 1, t.nb);
@@ -1039,7 +1048,7 @@ Ct Ctx::unpack(const Ct &b, int e)
 }
 
 // ------------------------------------------------------------------- client
-void Ctx::gen_switch_key(Keys &k, u64 seed, u32 key_id, const u64 *sp_ntt, SwitchKey &out)
+void Ctx::gen_switch_key(const u64 *s_ntt, u64 seed, u32 key_id, const u64 *sp_ntt, SwitchKey &out)
 {
     const int ktot = L + 1 + alpha, dn = dnum_top();
     out.buf = alloc((size_t)dn * 2 * ktot * N);
@@ -1079,7 +1088,7 @@ void Ctx::gen_switch_key(Keys &k, u64 seed, u32 key_id, const u64 *sp_ntt, Switc
         LimbMap lm = lmap(L + 1);
         ntt(PolySet{ka, (long)N, 0, ktot, 1}, lm, false);
         ntt(PolySet{de->p, (long)N, 0, ktot, 1}, lm, false);
-        launch_keygen_b(d_pc, kb, ka, k.s_ntt->p, de->p, sp_ntt, dpf->p, ktot, N, st);
+        launch_keygen_b(d_pc, kb, ka, s_ntt, de->p, sp_ntt, dpf->p, ktot, N, st);
         n_launch++;
     }
     sync();
@@ -1096,52 +1105,157 @@ void Ctx::key_fp(SwitchKey &k)
     n_launch++;
 }
 
-Keys *Ctx::keygen(u64 seed, const std::vector<long> &steps)
+Buf Ctx::secret_ntt(const SecretKey &sk, int nl)
 {
-    const int ktot = L + 1 + alpha;
-    std::unique_ptr<Keys> k(new Keys());
-    k->ctx = this;
-    k->s.resize(N);
-    sample_ternary(seed, 1, 0, 0, N, k->s.data());
+    const int ktot = nl;
     std::vector<u64> sr((size_t)ktot * N);
     for (int t = 0; t < ktot; t++)
         for (int n = 0; n < N; n++) {
-            int64_t v = k->s[n];
+            int64_t v = sk.s[n];
             sr[(size_t)t * N + n] = v < 0 ? mods[t] - 1 : (u64)v;
         }
-    k->s_ntt = alloc(sr.size());
-    upload(k->s_ntt->p, sr.data(), sr.size());
+    Buf b = alloc(sr.size());
+    upload(b->p, sr.data(), sr.size());
+    std::fill(sr.begin(), sr.end(), 0);
+    ntt(PolySet{b->p, (long)N, 0, ktot, 1}, lmap(std::min(nl, L + 1)), false);
+    return b;
+}
+
+void Ctx::wipe(const Buf &b)
+{
+    HIP_CHECK(hipMemsetAsync(b->p, 0, b->words * sizeof(u64), st));
+    sync();
+}
+
+// Galois keys are stored as sigma_g^-1(key), so the inner product needs no permutation
+static void store_galois(Ctx &c, SwitchKey &gk, u64 g)
+{
+    const size_t words = (size_t)c.dnum_top() * 2 * (c.L + 1 + c.alpha) * c.N;
+    Buf perm = c.alloc(words);
+    launch_automorph(PolySet{perm->p, (long)c.N, 0, (int)(words / c.N), 1},
+                     PolySet{gk.buf->p, (long)c.N, 0, (int)(words / c.N), 1}, hinv(g, 2ull * c.N), c.logN, c.st);
+    c.n_launch++;
+    gk.buf = perm;
+    c.key_fp(gk);
+}
+
+void Ctx::keygen(u64 seed, const std::vector<long> &steps, SecretKey *&sk_out, Keys *&ek_out)
+{
+    const int ktot = L + 1 + alpha;
+    std::unique_ptr<SecretKey> sk(new SecretKey());
+    sk->ctx = this;
+    sk->s.resize(N);
+    sample_ternary(seed, 1, 0, 0, N, sk->s.data());
+    std::unique_ptr<Keys> k(new Keys());
+    k->ctx = this;
+    Buf s_ntt = secret_ntt(*sk, ktot);
     LimbMap lm = lmap(L + 1);
-    PolySet sset{k->s_ntt->p, (long)N, 0, ktot, 1};
-    ntt(sset, lm, false);
+    PolySet sset{s_ntt->p, (long)N, 0, ktot, 1};
     // relinearisation key: s' = s^2 (pointwise in the NTT domain)
-    Buf s2 = alloc(sr.size());
+    Buf s2 = alloc((size_t)ktot * N);
     launch_pmul(d_pc, PolySet{s2->p, (long)N, 0, ktot, 1}, sset, sset, lm, N, st);
     n_launch++;
-    gen_switch_key(*k, seed, 0, s2->p, k->relin);
+    gen_switch_key(s_ntt->p, seed, 0, s2->p, k->relin);
+    k->has_relin = true;
     key_fp(k->relin);
     // Galois keys: s' = sigma_g(s), a permutation of NTT slots
-    Buf sg = alloc(sr.size());
+    Buf sg = alloc((size_t)ktot * N);
     for (long step : steps) {
         u64 g = galois_elt(step);
         if (g == 1 || k->galois.count(g)) continue;
         launch_automorph(PolySet{sg->p, (long)N, 0, ktot, 1}, sset, g, logN, st);
         n_launch++;
         SwitchKey &gk = k->galois[g];
-        gen_switch_key(*k, seed, (u32)g, sg->p, gk);
-        // store sigma_g^-1(key) so the inner product needs no permutation
-        const size_t words = (size_t)dnum_top() * 2 * ktot * N;
-        Buf perm = alloc(words);
-        launch_automorph(PolySet{perm->p, (long)N, 0, (int)(words / N), 1}, PolySet{gk.buf->p, (long)N, 0,
-                         (int)(words / N), 1}, hinv(g, 2ull * N), logN, st);
-        n_launch++;
-        gk.buf = perm;
-        key_fp(gk);
+        gen_switch_key(s_ntt->p, seed, (u32)g, sg->p, gk);
+        store_galois(*this, gk, g);
     }
+    wipe(s_ntt);
+    wipe(s2);
+    wipe(sg);
+    sk_out = sk.release();
+    ek_out = k.release();
+}
+
+Keys *Ctx::import_keys(const std::vector<u32> &ids, const std::vector<const u64 *> &data)
+{
+    const int ktot = L + 1 + alpha, dn = dnum_top();
+    const size_t words = (size_t)dn * 2 * ktot * N;
+    std::unique_ptr<Keys> k(new Keys());
+    k->ctx = this;
+    for (size_t i = 0; i < ids.size(); i++) {
+        const u32 id = ids[i];
+        if (id != 0 && ((id & 1) == 0 || id >= 2u * (u32)N))
+            throw HeError(-1, "key id " + std::to_string(id) + " is not a Galois element");
+        if (id == 0 ? k->has_relin : k->galois.count(id) != 0) throw HeError(-1, "repeated key id");
+        const u64 *src = data[i];
+        if (!src) throw HeError(-1, "null key data");
+        for (size_t r = 0; r < (size_t)dn * 2 * ktot; r++) {
+            const u64 m = mods[r % ktot];
+            for (int n = 0; n < N; n++)
+                if (src[r * N + n] >= m) throw HeError(-1, "key residue not reduced");
+        }
+        SwitchKey sw;
+        sw.buf = alloc(words);
+        upload(sw.buf->p, src, words);
+        // coefficient form -> NTT form -> Montgomery form, as keygen leaves them
+        PolySet ps{sw.buf->p, (long)N, (long)ktot * N, ktot, dn * 2};
+        LimbMap lm = lmap(L + 1);
+        ntt(ps, lm, false);
+        launch_to_montgomery(d_pc, sw.buf->p, (long)N, ktot, lm, N, dn * 2, (long)ktot * N, st);
+        n_launch++;
+        if (id == 0) {
+            k->relin = sw;
+            k->has_relin = true;
+            key_fp(k->relin);
+        } else {
+            SwitchKey &gk = k->galois[id];
+            gk = sw;
+            store_galois(*this, gk, id);
+        }
+    }
+    sync();
     return k.release();
 }
 
-Ct Ctx::encrypt(const Keys &k, const double *x, size_t n, u64 seed)
+void Ctx::export_key(const Keys &k, u32 key_id, int digit, u64 *out)
+{
+    const int ktot = L + 1 + alpha;
+    if (digit < 0 || digit >= dnum_top()) throw HeError(-1, "digit out of range");
+    const SwitchKey *sk = nullptr;
+    if (key_id == 0) {
+        if (!k.has_relin) throw HeError(-5, "no relinearisation key");
+        sk = &k.relin;
+    } else {
+        auto it = k.galois.find(key_id);
+        if (it == k.galois.end()) throw HeError(-5, "no such key");
+        sk = &it->second;
+    }
+    Buf tmp = alloc((size_t)2 * ktot * N);
+    const u64 *src = sk->buf->p + (size_t)digit * 2 * ktot * N;
+    if (key_id == 0) {
+        HIP_CHECK(hipMemcpyAsync(tmp->p, src, (size_t)2 * ktot * N * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+        // Galois keys are stored permuted by sigma^-1: undo it
+        launch_automorph(PolySet{tmp->p, (long)N, 0, 2 * ktot, 1}, PolySet{(u64 *)src, (long)N, 0, 2 * ktot, 1},
+                         key_id, logN, st);
+    }
+    // leave Montgomery form: multiply by 2^-64 mod q
+    std::vector<u64> inv(2 * ktot);
+    for (int t = 0; t < ktot; t++) {
+        u64 m = mods[t];
+        inv[t] = hinv(pc[t].r1, m);
+        inv[ktot + t] = shoup_of(inv[t], m);
+    }
+    Buf dinv = alloc(inv.size());
+    upload(dinv->p, inv.data(), inv.size());
+    LimbMap lm = lmap(L + 1);
+    PolySet ps{tmp->p, (long)N, (long)ktot * N, ktot, 2};
+    launch_mul_scalar(d_pc, ps, ps, dinv->p, dinv->p + ktot, lm, N, st);
+    ntt(ps, lm, true);
+    download(out, tmp->p, (size_t)2 * ktot * N);
+}
+
+Ct Ctx::encrypt(const SecretKey &sk, const double *x, size_t n, u64 seed)
 {
     const int nl = L + 1;
     if (n > (size_t)N / 2) throw HeError(-4, "encrypt: more values than slots");
@@ -1166,16 +1280,20 @@ Ct Ctx::encrypt(const Keys &k, const double *x, size_t n, u64 seed)
     ntt(PolySet{da->p, (long)N, 0, nl, 1}, lm, false);
     ntt(PolySet{dem->p, (long)N, 0, nl, 1}, lm, false);
     Ct c = new_ct(L);
+    Buf s_ntt = secret_ntt(sk, nl);
     launch_copy(PolySet{c.d() + N, 2l * N, 0, nl, 1}, PolySet{da->p, (long)N, 0, nl, 1}, N, st);
-    launch_encrypt(d_pc, c.d(), c.d() + N, k.s_ntt->p, dem->p, 2l * N, nl, N, st);
+    launch_encrypt(d_pc, c.d(), c.d() + N, s_ntt->p, dem->p, 2l * N, nl, N, st);
     n_launch += 2;
+    wipe(s_ntt);
     return c;
 }
 
-void Ctx::decrypt(const Keys &k, const Ct &c, double *y, size_t n)
+void Ctx::decrypt(const SecretKey &sk, const Ct &c, double *y, size_t n)
 {
     Buf m = alloc(N);
-    launch_decrypt0(d_pc, m->p, c.d(), c.d() + N, k.s_ntt->p, N, st);
+    Buf s_ntt = secret_ntt(sk, 1);
+    launch_decrypt0(d_pc, m->p, c.d(), c.d() + N, s_ntt->p, N, st);
+    wipe(s_ntt);
     ntt(PolySet{m->p, (long)N, 0, 1, 1}, lmap(1), true);
     std::vector<u64> h(N);
     download(h.data(), m->p, N);

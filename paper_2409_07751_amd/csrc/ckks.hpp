@@ -85,12 +85,18 @@ struct SwitchKey {
     Buf fbuf;  // the same layout in standard form as doubles, filled on FP64 primes (fused ModUp products)
 };
 
+// Evaluation keys (server side): no secret material.
 struct Keys {
     Ctx *ctx;
-    std::vector<int64_t> s;  // ternary secret (client side)
-    Buf s_ntt;               // [L+1+alpha][N] NTT form
     SwitchKey relin;
+    bool has_relin = false;
     std::map<u64, SwitchKey> galois;
+};
+
+// The ternary secret, in host memory (client side).
+struct SecretKey {
+    Ctx *ctx;
+    std::vector<int64_t> s;
 };
 
 // per-level key-switch constants: [2][nq] INTT output scale (inverse hat of
@@ -230,11 +236,19 @@ struct Ctx {
     const u64 *const_residues(double c, double scale);
 
     // client side
-    Keys *keygen(u64 seed, const std::vector<long> &steps);
-    void gen_switch_key(Keys &k, u64 seed, u32 key_id, const u64 *sp_ntt, SwitchKey &out);
+    void keygen(u64 seed, const std::vector<long> &steps, SecretKey *&sk, Keys *&ek);
+    // the secret in NTT form over the first nl limbs of q_0..q_L, p_0.. (nl <= L+1+alpha),
+    // on the device for one client operation
+    Buf secret_ntt(const SecretKey &sk, int nl);
+    void wipe(const Buf &b);  // zero a buffer that held secret material
+    void gen_switch_key(const u64 *s_ntt, u64 seed, u32 key_id, const u64 *sp_ntt, SwitchKey &out);
     void key_fp(SwitchKey &k);
-    Ct encrypt(const Keys &k, const double *x, size_t n, u64 seed);
-    void decrypt(const Keys &k, const Ct &c, double *y, size_t n);
+    Ct encrypt(const SecretKey &sk, const double *x, size_t n, u64 seed);
+    void decrypt(const SecretKey &sk, const Ct &c, double *y, size_t n);
+    // server side: evaluation keys from exported material (coefficient form,
+    // [dnum][2][L+1+alpha][N] per key), and one digit of a key back out
+    Keys *import_keys(const std::vector<u32> &ids, const std::vector<const u64 *> &data);
+    void export_key(const Keys &k, u32 key_id, int digit, u64 *out);
 
     // transfers
     void upload(u64 *dst, const u64 *src, size_t words);

@@ -30,6 +30,8 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
     const long slots = ctx->N / 2;
     S = d->samples_per_ct <= 0 ? 1 : d->samples_per_ct;
     if ((S & (S - 1)) != 0 || S > slots) throw HeError(-1, "model: samples per ciphertext must be a power of two");
+    circ = d->circuit;
+    if (circ & ~HE_CIRCUIT_RESTRUCTURED) throw HeError(-1, "model: unknown circuit option");
     long n_blk = 0;
     for (int li = 0; li < d->n_layers; li++) {
         const he_kan_layer &s = d->layers[li];
@@ -82,21 +84,29 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
             // part's inputs; their slot layout (block m at m n_blk, input i of
             // vector v at i S + v) is formed when the diagonals are
             P.W.assign((size_t)s.n_out * (nb + 1) * P.n_in, 0.0);
+            P.Wf.assign((size_t)s.n_out * nb * P.n_in, 0.0);
+            P.Wb.assign((size_t)s.n_out * P.n_in, 0.0);
             for (int o = 0; o < s.n_out; o++)
                 for (int i = 0; i < P.n_in; i++) {
                     const size_t e = (size_t)o * s.n_in + P.lo + i;
                     const double ws = s.ws[e];
-                    for (int m = 0; m < nb; m++)
+                    for (int m = 0; m < nb; m++) {
                         P.W[((size_t)o * (nb + 1) + m) * P.n_in + i] = ws * s.c[e * nb + m];
+                        P.Wf[((size_t)o * nb + m) * P.n_in + i] = ws * s.c[e * nb + m];
+                    }
                     P.W[((size_t)o * (nb + 1) + nb) * P.n_in + i] = s.wb[e];
+                    P.Wb[(size_t)o * P.n_in + i] = s.wb[e];
                 }
             L.parts.push_back(std::move(P));
         }
         // a hidden layer's input repeats every n_blk slots, so its whole block
-        // layout (g+2k+1 blocks: comparisons, bases, masked SiLU) can repeat
-        // every next power of two of that many slots; the product then repeats
-        // likewise and the fold runs over one period
-        L.period = li == 0 ? slots : std::min(slots, pow2ceil((long)r * n_blk));
+        // layout (g+2k comparison blocks, g+2k+1 when the second comparison is
+        // shared or the masked SiLU needs block g of a k = 0 layer) can repeat
+        // every next power of two of that many slots; the products then repeat
+        // likewise and the fold runs over one period.  Otherwise the layout
+        // spans all slots.
+        const long nblocks = (shared_cmp() || (fused() && s.k == 0)) ? r : r - 1;
+        L.period = (li == 0 || !folded()) ? slots : std::min(slots, pow2ceil(nblocks * n_blk));
         layers.push_back(std::move(L));
         n_blk = layers.back().d * S;
     }
@@ -500,8 +510,11 @@ struct Eval {
         return z;
     }
 
-    // both branches of the layer on one part's ciphertext, before the fold
-    Ct part(const Ct &x, size_t li, size_t pc)
+    // both branches of the layer on one part's ciphertext, before the fold:
+    // fused, one product with [W_f | W_b] of the bases plus the masked SiLU
+    // values; otherwise W_f times the bases and W_b times the SiLU values of
+    // x (the paper's two linear layers), both at the same level
+    std::vector<Ct> part(const Ct &x, size_t li, size_t pc)
     {
         const LayerC &L = m.layers[li];
         const Part &P = L.parts[pc];
@@ -513,22 +526,30 @@ struct Eval {
         // blocks of the input xr holds: the first layer's 2^ceil(log2(g+2k))
         // copies, or a periodic hidden input
         const long blocks = li == 0 ? pow2ceil(r - 1) : slots / P.n_blk;
-        const bool shared = blocks >= r && (long)r * P.n_blk <= slots;
+        const bool shared = m.shared_cmp() && blocks >= r && (long)r * P.n_blk <= slots;
         Ct b = bspline(xr, L, P, tag, shared);
-        // SiLU on the repeat-packed input, masked to block g+k (the first block
-        // the g+k bases leave free), added to the bases: one product with
-        // [W_f | W_b] computes both linear layers
-        std::vector<double> mask(slots, 0.0);
-        for (long i = 0; i < P.width; i++) mask[(size_t)nb * P.n_blk + i] = 1.0;
-        tile(mask, L.period);
-        Ct s = cheb_eval(xr, L.silu, L.silu_lo, L.silu_hi, &mask, tag + "S");
+        if (m.fused()) {
+            // SiLU on the repeat-packed input, masked to block g+k (the first
+            // block the g+k bases leave free), added to the bases
+            std::vector<double> mask(slots, 0.0);
+            for (long i = 0; i < P.width; i++) mask[(size_t)nb * P.n_blk + i] = 1.0;
+            tile(mask, L.period);
+            Ct s = cheb_eval(xr, L.silu, L.silu_lo, L.silu_hi, &mask, tag + "S");
+            int t = std::min(b.level, s.level) - 1;
+            if (t < 0) throw HeError(-3, "layer does not fit the level budget");
+            Ct z = c.add(c.mod_drop(b, t + 1), c.mod_drop(s, t + 1));
+            return {matvec(z, SlotMatrix{P.W, L.n_out, nb + 1, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "W")};
+        }
+        Ct s = cheb_eval(x, L.silu, L.silu_lo, L.silu_hi, nullptr, tag + "S");
         int t = std::min(b.level, s.level) - 1;
         if (t < 0) throw HeError(-3, "layer does not fit the level budget");
-        Ct z = c.add(c.mod_drop(b, t + 1), c.mod_drop(s, t + 1));
-        return matvec(z, SlotMatrix{P.W, L.n_out, nb + 1, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "W");
+        Ct zf = matvec(b, SlotMatrix{P.Wf, L.n_out, nb, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "Wf");
+        Ct zb = matvec(s, SlotMatrix{P.Wb, L.n_out, 1, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "Wb");
+        return {zf, zb};
     }
 
-    // the parts' partial sums share one layout: add them, then fold once
+    // the parts' partial sums share one layout: add them (per product), then
+    // fold each sum once; the layer output is the sum of the folded products
     Ct layer(const std::vector<Ct> &xs, size_t li)
     {
         const LayerC &L = m.layers[li];
@@ -538,9 +559,14 @@ struct Eval {
         for (size_t pc = 1; pc < xs.size(); pc++)
             if (xs[pc].level != xs[0].level || xs[pc].nb != xs[0].nb)
                 throw HeError(-1, "input ciphertexts differ in level or batch size");
-        Ct z = part(xs[0], li, 0);
-        for (size_t pc = 1; pc < xs.size(); pc++) z = c.add(z, part(xs[pc], li, pc));
-        return fold(z, L.d * m.S, L.period);
+        std::vector<Ct> z = part(xs[0], li, 0);
+        for (size_t pc = 1; pc < xs.size(); pc++) {
+            std::vector<Ct> zc = part(xs[pc], li, pc);
+            for (size_t j = 0; j < z.size(); j++) z[j] = c.add(z[j], zc[j]);
+        }
+        Ct y = fold(z[0], L.d * m.S, L.period);
+        for (size_t j = 1; j < z.size(); j++) y = c.add(y, fold(z[j], L.d * m.S, L.period));
+        return y;
     }
 };
 

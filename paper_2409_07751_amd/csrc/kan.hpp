@@ -17,6 +17,9 @@ struct Part {
     // n_out x (g+k+1) x n_in: blocks m < g+k hold W_f[o][m][i] = w_s[o][i] c[o][i][m],
     // block g+k holds W_b[o][i] (both linear layers as one product)
     std::vector<double> W;
+    // the same weights as two matrices (the paper's two products):
+    // n_out x (g+k) x n_in for W_f and n_out x 1 x n_in for W_b
+    std::vector<double> Wf, Wb;
 };
 
 struct LayerC {
@@ -35,7 +38,11 @@ struct LayerC {
 struct Model {
     Ctx *ctx;
     bool refresh;
-    long S;  // input vectors per ciphertext
+    long S;    // input vectors per ciphertext
+    int circ;  // HE_CIRCUIT_* restructurings (0: the paper's order)
+    bool shared_cmp() const { return (circ & HE_CIRCUIT_SHARED_COMPARISON) != 0; }
+    bool fused() const { return (circ & HE_CIRCUIT_FUSED_LINEAR) != 0; }
+    bool folded() const { return (circ & HE_CIRCUIT_FOLDED_PERIOD) != 0; }
     std::vector<LayerC> layers;
     std::vector<long> steps;
     std::unordered_map<std::string, Pt> pt_cache;   // Montgomery NTT plaintexts for lincombs

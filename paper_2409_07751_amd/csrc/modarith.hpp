@@ -70,11 +70,14 @@ __device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return 
 // exactly in a double; FP64 FMA runs at the full vector rate while 64-bit
 // integer multiplies take several instructions.  Values are kept in a signed
 // ("balanced") range and reduced only when they leave the transform.
+// These helpers are host-callable as well (compiler builtins only, the same
+// IEEE operations on both sides), so the bounds below can be checked on the
+// CPU against exact integer arithmetic.
 
 // u64 below 2^52 -> the same integer as a double
-__device__ __forceinline__ double u2d(u64 v)
+__host__ __device__ __forceinline__ double u2d(u64 v)
 {
-    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
+    return __builtin_bit_cast(double, v | 0x4330000000000000ull) - 4503599627370496.0;
 }
 
 // the bits of a double holding an integer in [0, 2^52) -> that integer
@@ -84,23 +87,24 @@ __device__ __forceinline__ u64 d2u_exact(u64 bits)
 }
 
 // integer-valued double with |v| < 2^52 -> v mod q in [0, q)
-__device__ __forceinline__ u64 d2u_mod(double v, double q, double qi)
+__host__ __device__ __forceinline__ u64 d2u_mod(double v, double q, double qi)
 {
-    double r = __fma_rn(-rint(v * qi), q, v);  // exact, |r| <= q/2 + 1
+    double r = __builtin_fma(-__builtin_rint(v * qi), q, v);  // exact, |r| <= q/2 + 1
     r = r < 0.0 ? r + q : r;
-    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0xFFFFFFFFFFFFFull;
+    return __builtin_bit_cast(u64, r + 4503599627370496.0) & 0xFFFFFFFFFFFFFull;
 }
 
-// y w mod q up to sign, |result| <= 3q/4, for |y| <= 2^50, 0 <= w < q < 2^46,
-// c = fl(w / q): the quotient estimate t = rint(y c) is within 3/4 of y w / q,
+// y w mod q up to sign, |result| <= 3q/4, for |y| <= 2^50, |w| < q < 2^46,
+// c = w / q rounded (fl(w / q), or fl(w fl(1 / q)) for a twiddle formed on
+// the fly): the quotient estimate t = rint(y c) is within 3/4 of y w / q,
 // p + e = y w exactly (e = the rounding error of p, exact by FMA), and
 // p - t q is an integer below 2^47 in magnitude, so the FMA is exact too
-__device__ __forceinline__ double mulm_fp(double y, double w, double c, double q)
+__host__ __device__ __forceinline__ double mulm_fp(double y, double w, double c, double q)
 {
-    const double t = rint(y * c);
+    const double t = __builtin_rint(y * c);
     const double p = y * w;
-    const double e = __fma_rn(y, w, -p);
-    return __fma_rn(-t, q, p) + e;
+    const double e = __builtin_fma(y, w, -p);
+    return __builtin_fma(-t, q, p) + e;
 }
 
 }  // namespace hk

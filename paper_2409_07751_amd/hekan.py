@@ -42,7 +42,13 @@ class he_kan_layer(ctypes.Structure):
 
 class he_kan_desc(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(he_kan_layer)),
-                ("samples_per_ct", ctypes.c_int32)]
+                ("samples_per_ct", ctypes.c_int32), ("circuit", ctypes.c_int32)]
+
+
+# he_kan_desc.circuit: restructurings of the paper's layer circuit (0 = the paper's order)
+CIRCUIT_PAPER = 0
+CIRCUIT_SHARED_COMPARISON, CIRCUIT_FUSED_LINEAR, CIRCUIT_FOLDED_PERIOD = 1, 2, 4
+CIRCUIT_RESTRUCTURED = 7
 
 
 _lib = None
@@ -67,9 +73,16 @@ _SIGS = {
     "he_model_free": [ctypes.c_void_p],
     "he_model_rotation_steps": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "he_model_input_chunks": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
-    "he_keygen": [ctypes.c_void_p, ctypes.c_uint64, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
-    "he_keys_free": [ctypes.c_void_p],
-    "he_keys_export": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, _u64p, ctypes.c_size_t],
+    "he_keygen": [ctypes.c_void_p, ctypes.c_uint64, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p),
+                  ctypes.POINTER(ctypes.c_void_p)],
+    "he_secret_key_free": [ctypes.c_void_p],
+    "he_eval_keys_free": [ctypes.c_void_p],
+    "he_eval_keys_ids": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_size_t,
+                         ctypes.POINTER(ctypes.c_size_t)],
+    "he_eval_keys_export": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, _u64p,
+                            ctypes.c_size_t],
+    "he_eval_keys_import": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_size_t,
+                            ctypes.POINTER(_u64p), ctypes.POINTER(ctypes.c_void_p)],
     "he_encrypt": [ctypes.c_void_p, ctypes.c_void_p, _dp, ctypes.c_size_t, ctypes.c_uint64,
                    ctypes.POINTER(ctypes.c_void_p)],
     "he_decrypt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp, ctypes.c_size_t],
@@ -174,7 +187,7 @@ class Context:
         0..L for this batch size (0 unfused; 1, 8, 32 fused with that span)."""
         choice = (ctypes.c_int32 * (self.L + 1))()
         n = ctypes.c_size_t()
-        self.check(self.lib.he_ctx_autotune(self.h, keys.h, batch, reps, choice, self.L + 1, ctypes.byref(n)))
+        self.check(self.lib.he_ctx_autotune(self.h, _ek(keys), batch, reps, choice, self.L + 1, ctypes.byref(n)))
         return [int(choice[i]) for i in range(n.value)]
 
     def set_keyswitch(self, level, batch, config):
@@ -193,20 +206,34 @@ class Context:
 
     # -- keys, ciphertexts --------------------------------------------------
     def keygen(self, seed, steps):
+        """he_keygen: a client's key pair (Keys: .sk the secret key, .ek the
+        evaluation keys); calls below take the handle their role needs."""
         s = _arr(list(steps), np.int32)
+        sk, ek = ctypes.c_void_p(), ctypes.c_void_p()
+        self.check(self.lib.he_keygen(self.h, seed, _ptr(s) if len(s) else None, len(s), ctypes.byref(sk),
+                                      ctypes.byref(ek)))
+        return Keys(SecretKey(self, sk), EvalKeys(self, ek))
+
+    def import_eval_keys(self, material):
+        """he_eval_keys_import: evaluation keys from exported material alone
+        ({key id: [dnum][2][L+1+alpha][N] residues}, e.g. EvalKeys.export_all())."""
+        ids = sorted(material)
+        arrs = [_arr(material[i], np.uint64) for i in ids]
+        idv = (ctypes.c_uint32 * len(ids))(*ids)
+        ptrs = (_u64p * len(ids))(*[_ptr(a) for a in arrs])
         h = ctypes.c_void_p()
-        self.check(self.lib.he_keygen(self.h, seed, _ptr(s) if len(s) else None, len(s), ctypes.byref(h)))
-        return Keys(self, h)
+        self.check(self.lib.he_eval_keys_import(self.h, idv, len(ids), ptrs, ctypes.byref(h)))
+        return EvalKeys(self, h)
 
     def encrypt(self, keys, x, seed):
         x = _arr(x, np.float64)
         h = ctypes.c_void_p()
-        self.check(self.lib.he_encrypt(self.h, keys.h, _ptr(x), len(x), seed, ctypes.byref(h)))
+        self.check(self.lib.he_encrypt(self.h, _sk(keys), _ptr(x), len(x), seed, ctypes.byref(h)))
         return Ciphertext(self, h)
 
     def decrypt(self, keys, ct, n):
         y = np.zeros(n, np.float64)
-        self.check(self.lib.he_decrypt(self.h, keys.h, ct.h, _ptr(y), n))
+        self.check(self.lib.he_decrypt(self.h, _sk(keys), ct.h, _ptr(y), n))
         return y
 
     def import_ct(self, res, level):
@@ -225,10 +252,10 @@ class Context:
         return self._new(self.lib.he_ct_add, a.h, b.h)
 
     def mul(self, keys, a, b):
-        return self._new(self.lib.he_ct_mul, keys.h, a.h, b.h)
+        return self._new(self.lib.he_ct_mul, _ek(keys), a.h, b.h)
 
     def rotate(self, keys, a, step):
-        return self._new(self.lib.he_ct_rotate, keys.h, a.h, step)
+        return self._new(self.lib.he_ct_rotate, _ek(keys), a.h, step)
 
     def rescale(self, a):
         return self._new(self.lib.he_ct_rescale, a.h)
@@ -260,8 +287,10 @@ class Context:
         return out
 
     # -- inference ------------------------------------------------------------
-    def compile(self, layers, refresh=False, samples=1):
-        return Model(self, layers, refresh, samples)
+    def compile(self, layers, refresh=False, samples=1, circuit=CIRCUIT_RESTRUCTURED):
+        """he_model_compile; `circuit` is he_kan_desc.circuit (CIRCUIT_PAPER runs
+        the paper's order, the default applies every restructuring)."""
+        return Model(self, layers, refresh, samples, circuit)
 
     def encrypt_input(self, model, keys, x, seed):
         """Encrypt one request's input in the model's layout: one ciphertext per
@@ -285,14 +314,14 @@ class Context:
         """ct: one ciphertext, or the list of a request's input chunks."""
         if isinstance(ct, (list, tuple)):
             arr = (ctypes.c_void_p * len(ct))(*[c.h.value for c in ct])
-            return self._new(self.lib.he_eval_kan_chunks, model.h, keys.h, arr, len(ct))
-        return self._new(self.lib.he_eval_kan, model.h, keys.h, ct.h)
+            return self._new(self.lib.he_eval_kan_chunks, model.h, _ek(keys), arr, len(ct))
+        return self._new(self.lib.he_eval_kan, model.h, _ek(keys), ct.h)
 
     def eval_kan_chunks(self, model, keys, cts):
         return self.eval_kan(model, keys, list(cts))
 
     def eval_kan_layer(self, model, keys, layer, ct):
-        return self._new(self.lib.he_eval_kan_layer, model.h, keys.h, layer, ct.h)
+        return self._new(self.lib.he_eval_kan_layer, model.h, _ek(keys), layer, ct.h)
 
     @staticmethod
     def _flat(cts):
@@ -304,7 +333,7 @@ class Context:
         flat = self._flat(cts)
         arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
         outs = (ctypes.c_void_p * n)()
-        self.check(self.lib.he_eval_kan_layer_batch(self.h, model.h, keys.h, layer, arr, n, outs))
+        self.check(self.lib.he_eval_kan_layer_batch(self.h, model.h, _ek(keys), layer, arr, n, outs))
         return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
 
     def memory(self, reset_peak=False):
@@ -317,7 +346,7 @@ class Context:
         flat = self._flat(cts)
         arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
         outs = (ctypes.c_void_p * n)()
-        self.check(self.lib.he_eval_kan_batch(self.h, model.h, keys.h, arr, n, outs))
+        self.check(self.lib.he_eval_kan_batch(self.h, model.h, _ek(keys), arr, n, outs))
         return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
 
     def capture_kan_batch(self, model, keys, cts):
@@ -328,7 +357,7 @@ class Context:
         arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
         outs = (ctypes.c_void_p * n)()
         g = ctypes.c_void_p()
-        self.check(self.lib.he_graph_capture_kan_batch(self.h, model.h, keys.h, arr, n, outs, ctypes.byref(g)))
+        self.check(self.lib.he_graph_capture_kan_batch(self.h, model.h, _ek(keys), arr, n, outs, ctypes.byref(g)))
         return Graph(self, g), [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
 
 
@@ -347,21 +376,74 @@ class Graph:
             self.h = None
 
 
-class Keys:
+class SecretKey:
+    """he_secret_key (client side, host memory)."""
+
     def __init__(self, ctx, h):
-        self.ctx, self.h = ctx, h
+        self.ctx, self.h, self.lib = ctx, h, ctx.lib
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.he_secret_key_free(self.h)
+            self.h = None
+
+
+class EvalKeys:
+    """he_eval_keys (server side: relinearisation and Galois keys, no secret)."""
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h, self.lib = ctx, h, ctx.lib
+
+    def ids(self):
+        n = ctypes.c_size_t()
+        self.ctx.check(self.lib.he_eval_keys_ids(self.h, None, 0, ctypes.byref(n)))
+        v = (ctypes.c_uint32 * max(1, n.value))()
+        self.ctx.check(self.lib.he_eval_keys_ids(self.h, v, n.value, ctypes.byref(n)))
+        return [int(v[i]) for i in range(n.value)]
 
     def export(self, key_id, digit):
         c = self.ctx
         ktot = c.L + 1 + c.alpha
         out = np.zeros((2, ktot, c.N), np.uint64)
-        c.check(c.lib.he_keys_export(c.h, self.h, key_id, digit, _ptr(out), out.size))
+        c.check(self.lib.he_eval_keys_export(c.h, self.h, key_id, digit, _ptr(out), out.size))
         return out
 
+    def export_all(self):
+        """{key id: [dnum][2][L+1+alpha][N] residues}: what a client sends a server."""
+        c = self.ctx
+        dnum = (c.L + 1 + c.w - 1) // c.w
+        return {i: np.stack([self.export(i, j) for j in range(dnum)]) for i in self.ids()}
+
     def __del__(self):
-        if getattr(self, "h", None) and self.ctx.h:
-            self.ctx.lib.he_keys_free(self.h)
+        if getattr(self, "h", None):
+            self.lib.he_eval_keys_free(self.h)
             self.h = None
+
+
+class Keys:
+    """A client's key pair from keygen: .sk and .ek; export() reads the
+    evaluation keys."""
+
+    def __init__(self, sk, ek):
+        self.sk, self.ek = sk, ek
+        self.ctx = ek.ctx
+
+    def export(self, key_id, digit):
+        return self.ek.export(key_id, digit)
+
+
+def _sk(keys):
+    k = keys.sk if isinstance(keys, Keys) else keys
+    if not isinstance(k, SecretKey):
+        raise TypeError("a secret key is needed")
+    return k.h
+
+
+def _ek(keys):
+    k = keys.ek if isinstance(keys, Keys) else keys
+    if not isinstance(k, EvalKeys):
+        raise TypeError("evaluation keys are needed")
+    return k.h
 
 
 class Ciphertext:
@@ -380,15 +462,16 @@ class Ciphertext:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None) and self.ctx.h:
+        if getattr(self, "h", None):
             self.ctx.lib.he_ct_free(self.h)
             self.h = None
 
 
 class Model:
-    def __init__(self, ctx, layers, refresh=False, samples=1):
+    def __init__(self, ctx, layers, refresh=False, samples=1, circuit=CIRCUIT_RESTRUCTURED):
         self.ctx = ctx
         self.samples = samples
+        self.circuit = circuit
         keep = []
         arr = (he_kan_layer * len(layers))()
         for i, L in enumerate(layers):
@@ -401,7 +484,7 @@ class Model:
             arr[i] = he_kan_layer(L.n_in, L.n_out, L.g, L.k, _ptr(knots), _ptr(wb), _ptr(ws), _ptr(c),
                                   len(sc) - 1, _ptr(sc), L.silu_lo, L.silu_hi, len(L.comp), _ptr(lens), _ptr(cc),
                                   float(getattr(L, "comp_prescale", 0.0)))
-        desc = he_kan_desc(len(layers), arr, samples)
+        desc = he_kan_desc(len(layers), arr, samples, circuit)
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.he_model_compile(ctx.h, ctypes.byref(desc), 1 if refresh else 0, ctypes.byref(h)))
         self.h = h
@@ -423,6 +506,6 @@ class Model:
         return [int(v) for v in s]
 
     def __del__(self):
-        if getattr(self, "h", None) and self.ctx.h:
+        if getattr(self, "h", None):
             self.ctx.lib.he_model_free(self.h)
             self.h = None

@@ -81,19 +81,64 @@ def test_rejected_arguments(hk, tiny):
 
 
 def test_handles_of_another_context(hk, tiny):
+    """Keys and ciphertexts of another context are refused with HE_ESTATE by
+    every entry point that takes them, before any kernel runs: a context of
+    the same size (the same seeds give the same ciphertext there) and one of
+    a different size (N = 2^12, other limb counts), whose keys a kernel of
+    this context must never read."""
     wl, layers, ctx, model, keys = tiny
-    other = hk.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+    same = hk.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+    small = hk.Context(12, 3, 30, 1, 1)
     try:
-        ok = other.keygen(synth.SEED_KEYGEN, [])
-        ct = other.encrypt(ok, synth.inputs(wl, 1)[0], 9)
-        note("handles of another context")
-        raises(hk, hk.HE_ESTATE, ctx.eval_kan, model, keys, ct)      # ciphertext of another context
-        mine = ctx.encrypt(keys, synth.inputs(wl, 1)[0], 9)
-        raises(hk, hk.HE_ESTATE, ctx.eval_kan, model, ok, mine)      # keys of another context
-        # the same seeds give the same ciphertext in both contexts
+        x = synth.inputs(wl, 1)[0]
+        mine = ctx.encrypt(keys, x, 9)
+        ok = same.keygen(synth.SEED_KEYGEN, [])
+        ct = same.encrypt(ok, x, 9)
         assert (ct.export() == mine.export()).all()
+        sk = small.keygen(synth.SEED_KEYGEN, [1])
+        sct = small.encrypt(sk, x, 9)
+        for other_keys, other_ct in ((ok, ct), (sk, sct)):
+            note("handles of another context", other_ct.ctx.N)
+            raises(hk, hk.HE_ESTATE, ctx.eval_kan, model, keys, other_ct)           # ciphertext
+            raises(hk, hk.HE_ESTATE, ctx.eval_kan, model, other_keys, mine)         # evaluation keys
+            raises(hk, hk.HE_ESTATE, ctx.eval_kan_batch, model, other_keys, [mine])
+            raises(hk, hk.HE_ESTATE, ctx.eval_kan_layer, model, other_keys, 0, mine)
+            raises(hk, hk.HE_ESTATE, ctx.eval_kan_layer_batch, model, other_keys, 0, [mine])
+            raises(hk, hk.HE_ESTATE, ctx.capture_kan_batch, model, other_keys, [mine])
+            raises(hk, hk.HE_ESTATE, ctx.encrypt, other_keys, x, 1)                 # secret key
+            raises(hk, hk.HE_ESTATE, ctx.decrypt, other_keys, mine, 4)
+            raises(hk, hk.HE_ESTATE, ctx.decrypt, keys, other_ct, 4)
+            raises(hk, hk.HE_ESTATE, ctx.mul, other_keys, mine, mine)
+            raises(hk, hk.HE_ESTATE, ctx.mul, keys, mine, other_ct)
+            raises(hk, hk.HE_ESTATE, ctx.rotate, other_keys, mine, 1)
+            raises(hk, hk.HE_ESTATE, ctx.rotate, keys, other_ct, 1)
+            raises(hk, hk.HE_ESTATE, ctx.add, mine, other_ct)
+            raises(hk, hk.HE_ESTATE, ctx.rescale, other_ct)
+            raises(hk, hk.HE_ESTATE, ctx.lincomb, [mine, other_ct], [1.0, 2.0], 3)
+            raises(hk, hk.HE_ESTATE, ctx.autotune, other_keys, 1)
+            c = ctx
+            with pytest.raises(hk.HeError) as e:
+                c.check(c.lib.he_eval_keys_export(c.h, other_keys.ek.h, 0, 0, hk._ptr(np.zeros(1, np.uint64)), 1))
+            assert e.value.code == hk.HE_ESTATE
+        # the context is still usable and exact
+        assert (ctx.rotate(keys, mine, 1).export() == ctx.rotate(keys, mine, 1).export()).all()
     finally:
-        other.close()
+        same.close()
+        small.close()
+
+
+def test_handles_outlive_their_context(hk):
+    """Handles may be freed after he_ctx_destroy: the library releases the
+    context's device memory when the last handle made from it goes."""
+    wl = synth.WORKLOADS["tiny"]
+    c = hk.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+    keys = c.keygen(synth.SEED_KEYGEN, [1])
+    ct = c.encrypt(keys, np.arange(4.0), 3)
+    r = c.rotate(keys, ct, 1)
+    c.close()                 # the caller's reference ends; the handles still hold the context
+    del keys, ct
+    assert r.level == wl.L    # a handle still reads its own state
+    del r                     # the last handle: the context goes with it
 
 
 def test_layer_deeper_than_its_input(hk, tiny):

@@ -104,3 +104,55 @@ def test_formula_256_vectors_per_request():
         assert np.abs(Y - want).max() < 1e-2
     finally:
         ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_formula_layers_bit_exact():
+    """[4,10,10,1] at N = 2^15 (17 Q limbs, 2 special primes, 2-limb digits)
+    on one ciphertext of 64 vectors, layer by layer with the client-aided
+    refresh: every layer's residues equal the oracle's (the two-PolyComp
+    branch of Algorithm 2 on the 16 repeat-packed copies, the degree-7
+    composite stages, the degree-27 SiLU series, the N = 2^15 transforms),
+    with the default restructurings; the first layer in the paper's order
+    too."""
+    from paper_2409_07751_amd import hekan
+    wl = synth.WORKLOADS["formula"]
+    S = 64
+    layers = compiled(wl)
+    ctx = context(wl)
+    try:
+        octx = O.Context(O.Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w))
+        model = ctx.compile(layers, refresh=True, samples=S)
+        paper = ctx.compile(layers, refresh=True, samples=S, circuit=hekan.CIRCUIT_PAPER)
+        steps = sorted(set(model.rotation_steps()) | set(paper.rotation_steps()))
+        assert paper.rotation_steps() == circuit.rotation_steps(layers, octx.p.slots, S, circuit.PAPER)
+        note("formula keygen", len(steps))
+        keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+        ev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps))
+        X = synth.inputs(wl, 256)[:S]
+        x = circuit.pack_samples(X, S)
+        ct = ctx.encrypt(keys, x, synth.SEED_ENC)
+        oct_ = ev.encrypt(x, synth.SEED_ENC)
+        assert (ct.export() == np.stack([oct_.c0, oct_.c1])).all()
+        note("formula layer 0, paper order")
+        out = ctx.eval_kan_layer(paper, keys, 0, ct)
+        oout, _ = circuit.layer_forward(ev, [oct_], layers[0], 0, True, S, circuit.PAPER)
+        e = out.export()
+        assert out.level == oout.level
+        assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "paper-order layer 0 residues differ"
+        n_blk = 0
+        for li, L in enumerate(layers):
+            note("formula layer", li)
+            out = ctx.eval_kan_layer(model, keys, li, ct)
+            oout, n_blk = circuit.layer_forward(ev, [oct_], L, n_blk, li == 0, S, circuit.RESTRUCTURED)
+            e = out.export()
+            assert out.level == oout.level
+            assert (e[0] == oout.c0).all() and (e[1] == oout.c1).all(), "layer %d residues differ" % li
+            if li + 1 < len(layers):
+                v = ev.decrypt(oout, octx.p.slots)
+                ct = ctx.encrypt(keys, v, 300 + li)
+                oct_ = ev.encrypt(v, 300 + li)
+        Y = ctx.decrypt_output(model, keys, out, 1)
+        assert np.abs(Y - kan.he_friendly_kan(X, layers)).max() < 1e-2
+    finally:
+        ctx.close()

@@ -43,6 +43,16 @@ def tiny(hk):
 
 
 @pytest.fixture(scope="module")
+def formula(hk):
+    wl = synth.WORKLOADS["formula"]
+    note("formula context")
+    ctx = make_ctx(hk, wl)
+    octx = O.Context(wl_params(wl))
+    yield wl, ctx, octx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
 def image(hk):
     wl = synth.WORKLOADS["image"]
     note("image context")
@@ -60,14 +70,14 @@ def rand_ct(octx, level, seed):
 
 
 # ---------------------------------------------------------------- ring layer
-@pytest.mark.parametrize("which", ["tiny", "image"])
+@pytest.mark.parametrize("which", ["tiny", "formula", "image"])
 def test_primes_and_scales(which, request):
     wl, ctx, octx = request.getfixturevalue(which)
     q, p, S = ctx.primes()
     assert (q == octx.q).all() and (p == octx.pm).all() and (S == octx.S).all()
 
 
-@pytest.mark.parametrize("which", ["tiny", "image"])
+@pytest.mark.parametrize("which", ["tiny", "formula", "image"])
 def test_negacyclic_product(which, request):
     wl, ctx, octx = request.getfixturevalue(which)
     nl = 3
@@ -81,7 +91,7 @@ def test_negacyclic_product(which, request):
     assert (got == want).all()
 
 
-@pytest.mark.parametrize("which", ["tiny", "image"])
+@pytest.mark.parametrize("which", ["tiny", "formula", "image"])
 def test_encoder(which, request):
     wl, ctx, octx = request.getfixturevalue(which)
     ev = O.Oracle(octx)
@@ -125,9 +135,28 @@ def tiny_keys(tiny):
 def test_ops_bit_exact_tiny(tiny, tiny_keys):
     wl, ctx, octx = tiny
     keys, okeys = tiny_keys
+    ops_bit_exact(ctx, octx, keys, okeys, (wl.L, 3, 1))
+
+
+@pytest.mark.timeout(600)
+def test_ops_bit_exact_formula(formula):
+    """N = 2^15, 17 Q limbs, 2 special primes, 2-limb digits: the same ops at
+    the top level, a middle level and level 1 (then level 0)."""
+    wl, ctx, octx = formula
+    steps = [1, 2, -1, -5, 7, 1024]
+    note("formula keygen", len(steps))
+    keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    okeys = O.Keys(octx, synth.SEED_KEYGEN, steps)
+    ops_bit_exact(ctx, octx, keys, okeys, (wl.L, 8, 1))
+
+
+def ops_bit_exact(ctx, octx, keys, okeys, levels):
+    """add, rescale, relinearised product, rotations and linear combinations
+    at each level, residues equal to the oracle's; at level 1 also the level-0
+    addition and rotations."""
     ev = O.Oracle(octx, okeys)
-    for lvl in (wl.L, 3, 1):
-        note("ops tiny level", lvl)
+    for lvl in levels:
+        note("ops level", lvl, "N", octx.p.N)
         A, B = rand_ct(octx, lvl, 10 + lvl), rand_ct(octx, lvl, 20 + lvl)
         ca, cb = ctx.import_ct(A, lvl), ctx.import_ct(B, lvl)
         oa, ob = O.Ciphertext(lvl, A[0], A[1]), O.Ciphertext(lvl, B[0], B[1])
@@ -404,3 +433,41 @@ def test_kan_cifar_chunked_accuracy_and_batch(image):
         want = kan.he_friendly_kan(x[i][None], layers)[0]
         note("max err", np.abs(y - want).max(), "level", one.level)
         assert np.abs(y - want).max() < 1e-2
+
+
+@pytest.mark.timeout(900)
+def test_kan_image_residues_equal_oracle(image):
+    """Encrypted [784,64,10] inference at N = 2^16 (25 Q limbs, 4 special
+    primes, 5-limb digits), in the paper's order and restructured: both
+    layers' output residues equal the oracle's.  The oracle's residues are
+    held as SHA-256 digests (and sampled residues) in
+    tests/golden/image_digests.json, written by make_image_digests.py in the
+    same folder, which runs only the CPU oracle on the same seeded inputs
+    (a whole inference takes the oracle minutes)."""
+    import hashlib
+    import json
+    import os
+    from paper_2409_07751_amd import hekan
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "image_digests.json")))
+    wl, ctx, octx = image
+    layers = kan.compile_model(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
+                               [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
+    x = synth.inputs(wl, 1)[0]
+    for name, flags in (("paper", hekan.CIRCUIT_PAPER), ("restructured", hekan.CIRCUIT_RESTRUCTURED)):
+        want = golden[name]
+        model = ctx.compile(layers, circuit=flags)
+        assert model.rotation_steps() == want["steps"]
+        note("image", name, "keygen", len(want["steps"]))
+        keys = ctx.keygen(synth.SEED_KEYGEN, want["steps"])
+        ct = ctx.encrypt(keys, x, synth.SEED_ENC)
+        for li, w in enumerate(want["layers"]):
+            note("image", name, "layer", li)
+            ct = ctx.eval_kan_layer(model, keys, li, ct)
+            e = ct.export()
+            assert ct.level == w["level"]
+            got = [int(e[p][l][n]) for p, l, n in w["positions"]]
+            assert got == w["sampled"], (name, li, "sampled residues")
+            assert hashlib.sha256(np.ascontiguousarray(e.astype("<u8")).tobytes()).hexdigest() == w["sha256"], \
+                (name, li)
+        y = ctx.decrypt(keys, ct, 10)
+        assert np.abs(y - kan.he_friendly_kan(x[None], layers)[0]).max() < 1e-2

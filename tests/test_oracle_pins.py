@@ -637,3 +637,19 @@ def test_packed_vectors_on_simulator_equal_fp64_kan(name, S, circ):
     got = out.v[:wl.shape[-1] * S].reshape(wl.shape[-1], S).T
     assert np.abs(got - want).max() < 1e-8 * max(1, np.abs(want).max())
     assert set(circuit.rotation_steps(layers, sim.ctx.p.slots, S, cc)) == sim.rot_steps
+
+
+def test_image_digests_golden_matches_the_circuit():
+    """The stored oracle digests of the [784,64,10] inference (written by
+    tests/golden/make_image_digests.py) were taken for the circuits the oracle
+    runs now: rotation steps per circuit, levels, well-formed digests."""
+    import json
+    from oracle import circuit as C
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "image_digests.json")))
+    wl = synth.WORKLOADS["image"]
+    layers = kan.compile_model(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
+                               [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
+    for name, circ in (("paper", C.PAPER), ("restructured", C.RESTRUCTURED)):
+        assert g[name]["steps"] == C.rotation_steps(layers, 1 << (wl.logN - 1), circ=circ)
+        assert [l["level"] for l in g[name]["layers"]] == [12, 0]
+        assert all(len(l["sha256"]) == 64 and len(l["sampled"]) == len(l["positions"]) for l in g[name]["layers"])
