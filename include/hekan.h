@@ -344,6 +344,21 @@ int he_ct_mul(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, const he_ct *
 int he_ct_rotate(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, int32_t step, he_ct **out);
 /* out = rescale(a): divide by q_level with rounding, drop one limb. */
 int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): he_ct_rescale into an
+ * existing ciphertext, calling no allocator.  out must be a ciphertext of the
+ * same context at level a.level - 1 (a result of an earlier call, or
+ * he_ct_import); its residues are overwritten with rescale(a), the same
+ * residues he_ct_rescale returns.  The staging between the rescale's passes
+ * lives in a device array of 32 MiB that the library holds on every device it
+ * runs on until the process ends, shared by all contexts there: a rescale
+ * needs (level + 1) 2 N 8 bytes of it, and a larger one returns HE_ENOMEM
+ * with nothing launched (at N = 2^16 up to level 31).  Calls that overlap
+ * on one device race for that array.  Errors: HE_EINVAL (null, batched,
+ * wrong output level, output sharing memory with a), HE_EDEPTH (a at level
+ * 0), HE_ESTATE (handles of another context). */
+int he_ct_rescale_noalloc(he_ctx *ctx, const he_ct *a, he_ct *out);
+
 /* out = sum_i a[i] * z_i landing at level `target` with scale S_target; z_i
  * is the slot vector z + i*slots (n_slots values each) or, when n_slots == 1,
  * the constant z[i]. */

@@ -616,6 +616,30 @@ int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out)
     });
 }
 
+int he_ct_rescale_noalloc(he_ctx *ctx, const he_ct *a, he_ct *out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        check_ct(ctx, out);
+        Ctx &c = *ctx->c;
+        need(a->c.nb == 1 && out->c.nb == 1, "batched ciphertext");
+        if (a->c.level < 1) throw HeError(HE_EDEPTH, "rescale: no level left");
+        need(out->c.level == a->c.level - 1, "output level must be the input level - 1");
+        const size_t need_words = (size_t)(a->c.level + 1) * 2 * c.N;
+        if (need_words * sizeof(u64) > kNoAllocScratchBytes)
+            throw HeError(HE_ENOMEM, "rescale of " + std::to_string(a->c.level + 1) + " limbs of N = " +
+                                         std::to_string(c.N) + " needs " + std::to_string(need_words * 8) +
+                                         " bytes of scratch, more than the " +
+                                         std::to_string(kNoAllocScratchBytes) + " the library holds");
+        const u64 *ab = a->c.buf->p, *ob = out->c.buf->p;
+        const size_t aw = (size_t)(a->c.level + 1) * 2 * c.N, ow = (size_t)(out->c.level + 1) * 2 * c.N;
+        need(ob + ow <= ab || ab + aw <= ob, "output shares memory with the input");
+        if (!c.scratch) throw HeError(HE_ESTATE, "no scratch on this device");
+        c.rescale_into(a->c, out->c, c.scratch);
+    });
+}
+
 int he_ct_lincomb(he_ctx *ctx, const he_ct *const *a, size_t n, const double *z, size_t n_slots, int32_t target,
                   he_ct **out)
 {

@@ -295,6 +295,10 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
     }
     md_tab = alloc(md.size());
     upload(md_tab->p, md.data(), md.size());
+    // the entry points that allocate nothing: every level's rescale table now,
+    // and this device's scratch address
+    for (int l = 1; l <= L; l++) (void)rescale_table(l, 1);
+    scratch = noalloc_scratch_setup();
 }
 
 Ctx::~Ctx()
@@ -552,6 +556,16 @@ Ct Ctx::rescale_affine(const Ct &a, long k, const double *c)
     const u64 *cadd = c ? rescale_addend(l, k, *c) : nullptr;
     rescale_launch(*this, a, o, inv, cadd, last->p, tmp->p);
     return o;
+}
+
+void Ctx::rescale_into(const Ct &a, Ct &o, u64 *scr)
+{
+    const int l = a.level;
+    if (l < 1) throw HeError(-3, "rescale: no level left");
+    if (a.nb != 1 || o.nb != 1 || o.level != l - 1) throw HeError(-1, "rescale_into: shapes do not match");
+    auto it = rescale_inv.find(std::make_pair(l, 1l));
+    if (it == rescale_inv.end()) throw HeError(-7, "rescale_into: no table for this level");
+    rescale_launch(*this, a, o, it->second, nullptr, scr, scr + (size_t)2 * N);
 }
 
 // ----------------------------------------------------------- key switching

@@ -29,6 +29,12 @@ struct HeError : std::runtime_error {
 
 struct Ctx;
 
+// Size of the device array behind the entry points that allocate nothing (one
+// copy per device), and its set-up: looks up the array's device address for
+// the current device (once per device) and returns it.
+constexpr size_t kNoAllocScratchBytes = 32ull << 20;
+u64 *noalloc_scratch_setup();
+
 // Caching device allocator: buffers go back to per-size free lists and are
 // reused in stream order (all work of a context runs on one stream).
 struct Pool {
@@ -171,6 +177,11 @@ struct Ctx {
     // scale) are applied in the rescale's last pass; same residues as
     // add_const(mul_int(rescale(a), k), c)
     Ct rescale_affine(const Ct &a, long k, const double *c);
+    // rescale(a) into the existing single ciphertext o (level a.level - 1),
+    // staging through `scr` ((a.level + 1) 2 N words): no allocation; the
+    // level's table must exist (the constructor builds every level's)
+    void rescale_into(const Ct &a, Ct &o, u64 *scr);
+    u64 *scratch = nullptr;  // this device's no-allocation scratch (kNoAllocScratchBytes)
     // rescale to level t of C a (C the constant plaintext pt, a at level >= t + 1) [+ c]:
     // the product happens in the rescale's passes; same residues as
     // rescale(lincomb({a, pt}, t)) [+ c]

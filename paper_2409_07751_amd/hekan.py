@@ -107,6 +107,7 @@ _SIGS = {
     "he_ct_rotate": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                      ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_rescale": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_rescale_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "he_ct_lincomb": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, _dp, ctypes.c_size_t,
                       ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
     "he_poly_mul": [ctypes.c_void_p, _u64p, _u64p, ctypes.c_int32, _u64p],
@@ -259,6 +260,12 @@ class Context:
 
     def rescale(self, a):
         return self._new(self.lib.he_ct_rescale, a.h)
+
+    def rescale_noalloc(self, a, out):
+        """he_ct_rescale_noalloc: rescale(a) written into the existing
+        ciphertext `out` (level a.level - 1), no device allocation."""
+        self.check(self.lib.he_ct_rescale_noalloc(self.h, a.h, out.h))
+        return out
 
     def lincomb(self, cts, zs, target):
         """sum_i cts[i] * zs[i] at level target; zs: list of scalars or of slot vectors."""
