@@ -40,6 +40,17 @@ NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1
 # launches are the same in every configuration, the row pass's are not);
 # emptied whenever the kernel changes until the counters are taken again
 TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 306800000, "ntt_fwd_pass2": 490580000}
+TRAFFIC_SOURCE = "profiles/%s_image_b16_hbm_traffic.md (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a copy)"
+# Instruction issue of the same launches: wave64 VALU instructions per launch
+# (rocprofv3 SQ_INSTS_VALU summed over the class's dispatches of one timed
+# step, over their number) against the issue peak: each of a CU's 4 SIMDs
+# starts one wave64 VALU instruction every 4 cycles (16 lanes a cycle; the
+# FP64 FMA peak of 78.6 TFLOP/s = 2 x 64 lanes x this rate), i.e.
+# 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G instructions/s.  Emptied whenever
+# the kernel changes until the counters are taken again.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+VALU_INSTS_PER_LAUNCH = {}
+VALU_SOURCE = "profiles/%s_image_b16_valu.md (rocprofv3 SQ_INSTS_VALU)"
 
 
 def roofline(kernel, prof, batch):
@@ -53,8 +64,16 @@ def roofline(kernel, prof, batch):
          "traffic": TRAFFIC_BYTES_PER_LAUNCH.get(kernel) if batch == 16 else None,
          "algorithmic_bytes_per_launch": round(prof["bytes"] / prof["launches"]),
          "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 3), "launches": prof["launches"]}
+    if r["traffic"] is not None:
+        r["traffic_source"] = TRAFFIC_SOURCE % kernel
     if kernel in NTT_KERNELS:
         r["butterflies_per_s"] = round(prof["ops"] / secs, -6)
+    insts = VALU_INSTS_PER_LAUNCH.get(kernel) if batch == 16 else None
+    if insts:
+        rate = insts / (secs / prof["launches"])
+        r["compute"] = {"bound": "valu_issue", "insts_per_launch": insts, "achieved": round(rate / 1e9, 1),
+                        "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G wave64 VALU instructions/s",
+                        "frac": round(rate / VALU_ISSUE_PEAK, 4), "source": VALU_SOURCE % kernel}
     return r
 
 
@@ -75,97 +94,156 @@ def copy_probe(mib):
     log("copy probe: %d MiB device-to-device" % mib)
 
 
-def cpu_baseline(wl, budget):
-    """The CPU oracle (plain C + Python, one thread) on a bounded sample of the
-    same workload: it runs the [784,64,10] encrypted inference from its start
-    for `budget` seconds (key generation excluded) and the throughput is
-    extrapolated from the fraction of the inference's key-switch work done,
-    weighting a key switch at level l by its limb-digit count
-    ceil((l+1)/w) (l+1+alpha)."""
+def cpu_baseline(wl):
+    """The CPU oracle as it stands (plain C + Python, OpenMP over RNS limbs) on
+    the host cores: one whole encrypted [784,64,10] inference of the
+    benchmark's circuit on one input (key generation timed apart, outside the
+    inference), with every host thread the oracle uses; then, on one thread
+    (the paper's single-thread setting), one forward limb NTT at N = 2^13,
+    2^15 and 2^16 and one relinearised product and one rotation at the top
+    level."""
     from oracle import ckks as O, circuit, kan
-    from oracle.slotsim import SlotSim
     from paper_2409_07751_amd import synth
 
     layers = kan.compile_model(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024),
                                [wl.silu_degree] * (len(wl.shape) - 1), [list(c) for c in wl.comp_degrees],
                                wl.grid, wl.silu_range, prescale=wl.prescale)
     prm = O.Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
-
-    def work(l):
-        return ((l + 1 + wl.w - 1) // wl.w) * (l + 1 + wl.alpha)
-
-    class Rec(SlotSim):
-        def __init__(self, slots):
-            super().__init__(slots)
-            self.w = 0
-
-        def relin_rescale(self, t):
-            self.w += work(t[0])
-            return super().relin_rescale(t)
-
-        def rotate(self, a, t):
-            if t % self.ctx.p.slots:
-                self.w += work(a.level)
-            return super().rotate(a, t)
-
-    sim = Rec(prm.slots)
-    circuit.eval_kan(sim, sim.fresh(np.zeros(wl.shape[0]), wl.L), layers, circ=circuit.RESTRUCTURED)
-    total_work = sim.w
-
     ctx = O.Context(prm)
-    keys = O.Keys.__new__(O.Keys)
-    keys.ctx = ctx
-    L = O.lib()
-    s = np.zeros(prm.N, np.int64)
-    L.oc_sample_ternary(3, 1, 0, 0, prm.logN, O.P(s))
-    ktot = prm.L + 1 + prm.alpha
-    keys.s_res = np.zeros((ktot, prm.N), np.uint64)
-    L.oc_small_to_rns(O.P(s), O.P(keys.s_res), ktot, prm.logN, O.P(ctx.all_mods))
-    dnum = (prm.L + 1 + prm.w - 1) // prm.w
-    state = {"keygen": 0.0, "work": 0, "t0": None}
-
-    class LazyKeys(dict):
-        def __missing__(self, g):
-            t0 = time.perf_counter()
-            sp = np.zeros_like(keys.s_res)
-            if g == 0:
-                L.oc_poly_mul(O.P(keys.s_res), O.P(keys.s_res), O.P(sp), ktot, prm.logN, O.P(ctx.all_mods))
-            else:
-                L.oc_automorph(O.P(keys.s_res), O.P(sp), ktot, prm.logN, O.P(ctx.all_mods), g)
-            self[g] = keys._gen(3, g, sp, dnum)
-            state["keygen"] += time.perf_counter() - t0
-            return self[g]
-
-    keys.keys = LazyKeys()
-
-    class Stop(Exception):
-        pass
-
-    class Timed(O.Oracle):
-        def keyswitch(self, d, l, key_id, galois=0):
-            keys.keys[key_id]  # generate outside the measured time
-            if time.perf_counter() - state["t0"] - state["keygen"] > budget:
-                raise Stop()
-            r = super().keyswitch(d, l, key_id, galois)
-            state["work"] += work(l)
-            return r
-
-    ev = Timed(ctx, keys)
+    O.set_threads(0)
+    threads = O.get_threads()
+    steps = circuit.rotation_steps(layers, prm.slots, circ=circuit.RESTRUCTURED)
+    t0 = time.perf_counter()
+    ev = O.Oracle(ctx, O.Keys(ctx, synth.SEED_KEYGEN, steps))
+    keygen_s = time.perf_counter() - t0
     x = synth.inputs(wl, 1)[0]
     ct = ev.encrypt(x, synth.SEED_ENC)
-    log("cpu baseline: oracle running the inference for %.0f s" % budget)
-    state["t0"] = time.perf_counter()
-    try:
-        circuit.eval_kan(ev, ct, layers, circ=circuit.RESTRUCTURED)
-    except Stop:
-        pass
-    elapsed = time.perf_counter() - state["t0"] - state["keygen"]
-    frac = state["work"] / total_work
-    log("cpu baseline: %.4f of the key-switch work in %.1f s" % (frac, elapsed))
-    return {"value": round(frac / elapsed, 6), "unit": "inferences/s", "cores": 1, "kind": "oracle",
-            "sample": "first %.0f s of one [784,64,10] inference on the single-threaded CPU oracle "
-                      "(%d key switches, %.2f%% of the inference's key-switch work, key generation excluded); "
-                      "extrapolated by key-switch work" % (elapsed, ev.count["ks"], 100 * frac)}
+    log("cpu baseline: oracle inference on %d threads (keygen %.1f s)" % (threads, keygen_s))
+    t0 = time.perf_counter()
+    out = circuit.eval_kan(ev, ct, layers, circ=circuit.RESTRUCTURED)
+    inf_s = time.perf_counter() - t0
+    n_ks = ev.count["ks"]
+    y = ev.decrypt(out, wl.shape[-1])
+    err = float(np.abs(y - kan.he_friendly_kan(x[None], layers)[0]).max())
+    log("cpu baseline: one inference in %.1f s (%d key switches), max err %.2e" % (inf_s, n_ks, err))
+    # one thread
+    O.set_threads(1)
+    L = O.lib()
+    ntt = {}
+    for logn in (13, 15, 16):
+        q = int(O.Context(O.Params(logn, 1, 40, 1, 1)).q[1])
+        a = np.random.default_rng(logn).integers(0, q, 1 << logn, dtype=np.uint64)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            L.oc_ntt_fwd(O.P(a), logn, q)
+        ntt["2^%d" % logn] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+    rng = np.random.default_rng(7)
+    A = [np.array([rng.integers(0, int(ctx.q[l]), prm.N, dtype=np.uint64) for l in range(prm.L + 1)])
+         for _ in range(4)]
+    ca, cb = O.Ciphertext(prm.L, A[0], A[1]), O.Ciphertext(prm.L, A[2], A[3])
+    t0 = time.perf_counter()
+    ev.mul(ca, cb)
+    mul_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ev.rotate(ca, steps[-1] if steps[-1] > 0 else 1)
+    rot_s = time.perf_counter() - t0
+    O.set_threads(0)
+    log("cpu baseline, one thread: top-level product %.2f s, rotation %.2f s" % (mul_s, rot_s))
+    return {"value": round(1.0 / inf_s, 6), "unit": "inferences/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(),
+            "sample": "one whole [784,64,10] encrypted inference (batch 1, the benchmark's circuit: %d key switches) "
+                      "on the CPU oracle with %d OpenMP threads over RNS limbs; key generation (%.1f s) "
+                      "excluded; decrypted within %.1e of the FP64 circuit" % (n_ks, threads, keygen_s, err),
+            "inference_s": round(inf_s, 2), "keygen_s": round(keygen_s, 2),
+            "single_thread": {"ntt_ms": ntt, "relinearised_product_top_level_s": round(mul_s, 3),
+                              "rotation_top_level_s": round(rot_s, 3)}}
+
+
+def word_study(args, layers, wl, x, want):
+    """The batched inference (one engine, batch 16) with the default words
+    (primes below 2^46 in exact FP64 arithmetic, the 60-bit primes on 64-bit
+    integer words) and with every prime on 64-bit integer words (Shoup
+    butterflies, Barrett and Montgomery products; the FP64 path off):
+    inferences/s of each.  Both compute the same residues."""
+    from paper_2409_07751_amd import hekan, synth
+    out = {"batch": 16}
+    for name, iw in (("fp64_path", False), ("integer_words", True)):
+        ctx = hekan.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w, integer_words=iw)
+        model = ctx.compile(layers)
+        keys = ctx.keygen(synth.SEED_KEYGEN, model.rotation_steps())
+        cts = [ctx.encrypt(keys, x[i], synth.SEED_ENC + i) for i in range(16)]
+        outs = ctx.eval_kan_batch(model, keys, cts)
+        ctx.sync()
+        err = max(float(np.abs(ctx.decrypt(keys, outs[i], wl.shape[-1]) - want[i]).max()) for i in range(16))
+        del outs
+        steps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            outs = ctx.eval_kan_batch(model, keys, cts)
+            del outs
+        ctx.sync()
+        el = time.perf_counter() - t0
+        out[name] = {"inferences_per_s": round(16 * steps / el, 4), "steps": steps, "max_abs_err_vs_fp64_circuit": err}
+        del cts, keys, model
+        ctx.close()
+    return out
+
+
+def silu_fits():
+    """The SiLU approximation comparators (host side): the weighted
+    least-squares fit, ordinary least squares and Remez minimax at one degree
+    and range, measured by the RMSE over the range and over a synthetic
+    activation distribution.  Ranges and degrees are the ones the paper's
+    experiments state for its three image data sets (5-sigma ranges; degrees
+    10, 10, 15), with normal activations of that mean and sigma; plus the
+    hidden-layer activations of the [784,64,10] model (calibration inputs
+    through its first layer) at its degree 31."""
+    from paper_2409_07751_amd import compile as pc
+    from paper_2409_07751_amd import synth
+    out = {}
+    for name, (lo, hi, deg) in (("range_mnist", (-12.4, 14.74, 10)), ("range_fmnist", (-9.77, 11.01, 10)),
+                                ("range_cifar10", (-11.90, 10.99, 15))):
+        mu, sd = (lo + hi) / 2, (hi - lo) / 10
+        samples = np.random.default_rng(synth.SEED_CALIB).normal(mu, sd, 200000)
+        out[name] = {"lo": lo, "hi": hi, "degree": deg, "fits": pc.silu_fit_comparison(lo, hi, deg, samples)}
+    wl = synth.WORKLOADS["image"]
+    raw = synth.raw_weights(wl)
+    calib = synth.calibration_inputs(wl, 1024)
+    layers = pc.compile_kan(raw, calib, wl.silu_degree, [list(c) for c in wl.comp_degrees], wl.grid,
+                            wl.silu_range, prescale=wl.prescale)
+    h = pc.plain_layer(calib, layers[0]).ravel()
+    L1 = layers[1]
+    out["image_hidden_layer"] = {"lo": L1.silu_lo, "hi": L1.silu_hi, "degree": wl.silu_degree,
+                                 "fits": pc.silu_fit_comparison(L1.silu_lo, L1.silu_hi, wl.silu_degree, h)}
+    for v in out.values():
+        for f in v["fits"].values():
+            for k in f:
+                f[k] = float("%.5g" % f[k])
+    return out
+
+
+def ks_bench(ctx, keys, wl):
+    """Key switches of B = 1, 8 and 64 ciphertexts sharing one key, at every
+    level: the relinearisation of a product (with its rescale, as the library
+    runs it) and a rotation by one slot; key switches per second and the
+    median time of one batch (HIP events on the library stream)."""
+    out = {"unit": "keyswitches/s", "levels": list(range(wl.L, -1, -1)), "reps": 5}
+    for B in (1, 8, 64):
+        row = {}
+        for kind, st in (("relinearisation", 0), ("rotation", 1)):
+            rate = []
+            for lvl in out["levels"]:
+                if st == 0 and lvl == 0:
+                    rate.append(None)
+                    continue
+                ms = ctx.bench_keyswitch(keys, st, lvl, B, 5)
+                rate.append(round(B / (ms * 1e-3), 1))
+            row[kind] = rate
+        row["top_level_us_per_keyswitch"] = {k: round(1e6 / v[0], 2) for k, v in row.items()}
+        out["batch_%d" % B] = row
+        log("keyswitch bench B=%d top level: %s keyswitches/s" % (B, {k: v[0] for k, v in row.items()
+                                                                      if isinstance(v, list)}))
+    return out
 
 
 def plain_path(ctx, model, keys, ct, steps):
@@ -203,76 +281,165 @@ def graph_path(ctx, model, keys, cts, steps, want, n_out):
 
 
 SERVE_MIX = (("formula16", 0.5), ("image", 0.3), ("cifar", 0.2))
+# the batched configuration's own mix: uniform over three uneven shapes
+MIX64 = (("tiny16", 1 / 3), ("formula16", 1 / 3), ("cifar", 1 / 3))
 
 
-def serve_run(args, batched_rate):
-    """Requests drawn from the serving mix on one context with every model's
-    keys resident: (1) Poisson arrivals at 0.7x the measured batched image
-    throughput, served with layer-granular continuous batching under an HBM
-    budget (p50/p99 latency, inferences/s); (2) the mixed batch: 64 requests
-    present at once under a 96 GiB budget, grouped by (model, layer) into
-    launches of up to 32."""
+def serve_run(args):
+    """Serving on engines (contexts with their own HIP stream and resident
+    copy of every model's evaluation keys) driven by one host thread each,
+    requests bound to engines round-robin:
+      (1) the serving mix 50/30/20 of [4,10,10,1] / [784,64,10] /
+          [3072,128,10], all requests present at once: its saturation
+          throughput;
+      (2) Poisson arrivals of the same mix at 0.7 x that throughput, served
+          with layer-granular continuous batching under an HBM budget:
+          per-request p50/p99 latency and inferences/s in steady state (the
+          first 10% of the requests by arrival left out);
+      (3) the batched configuration's mix: 64 requests drawn uniformly from
+          [2,5,1] / [4,10,10,1] / [3072,128,10] (seed 5), all present at
+          once, in launches of up to 32 per (model, layer) group."""
     from paper_2409_07751_amd import compile as pc
     from paper_2409_07751_amd import hekan, synth
-    from paper_2409_07751_amd.serve import GpuEngine, Request, Server, latency_report
+    from paper_2409_07751_amd.serve import ConcurrentServer, GpuEngine, Request, latency_report
 
-    names = [n for n, _ in SERVE_MIX]
-    probs = np.array([p for _, p in SERVE_MIX])
+    names = sorted(set(n for n, _ in SERVE_MIX + MIX64))
     wl0 = synth.WORKLOADS["image"]
-    ctx = hekan.Context(wl0.logN, wl0.L, wl0.scale_bits, wl0.alpha, wl0.w)
-    layers, models = {}, {}
+    layers = {}
     for n in names:
         wl = synth.WORKLOADS[n]
         layers[n] = pc.compile_kan(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024), wl.silu_degree,
                                    [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
-        models[n] = ctx.compile(layers[n])
-    steps = sorted(set(s for m in models.values() for s in m.rotation_steps()))
-    t0 = time.time()
-    keys = ctx.keygen(synth.SEED_KEYGEN, steps)
-    ctx.sync()
-    log("serving keygen %.1fs (%d Galois keys)" % (time.time() - t0, len(steps)))
-    eng = GpuEngine(ctx, keys, models)
-    for n in names:
-        x = synth.inputs(synth.WORKLOADS[n], 1, stream=3)[0]
-        eng.calibrate(n, ctx.encrypt_input(models[n], keys, x, 7))
-    free = ctx.memory()
-    budget = 40 * 2 ** 30
+    engines = []
+    for e in range(args.serve_engines):
+        ctx = hekan.Context(wl0.logN, wl0.L, wl0.scale_bits, wl0.alpha, wl0.w)
+        models = {n: ctx.compile(layers[n]) for n in names}
+        steps = sorted(set(s for m in models.values() for s in m.rotation_steps()))
+        t0 = time.time()
+        keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+        ctx.sync()
+        log("serving engine %d: keygen %.1fs (%d Galois keys)" % (e, time.time() - t0, len(steps)))
+        eng = GpuEngine(ctx, keys, models)
+        for n in names:
+            x = synth.inputs(synth.WORKLOADS[n], 1, stream=3)[0]
+            eng.calibrate(n, ctx.encrypt_input(models[n], keys, x, 7))
+        engines.append(eng)
 
-    def make(nreq, arrivals, stream0):
-        kinds = synth.request_mix(nreq, names, probs, seed=synth.SEED_ARRIVALS + stream0)
+    def make(nreq, arrivals, mix, stream0):
+        kinds = synth.request_mix(nreq, [n for n, _ in mix], np.array([p for _, p in mix]),
+                                  seed=synth.SEED_ARRIVALS + stream0)
         reqs = []
         for i, n in enumerate(kinds):
+            eng = engines[i % len(engines)]
             x = synth.inputs(synth.WORKLOADS[n], 1, stream=stream0 + i)[0]
-            reqs.append(Request(i, n, ctx.encrypt_input(models[n], keys, x, 1000 + 10 * i), float(arrivals[i])))
-        ctx.sync()
+            ct = eng.ctx.encrypt_input(eng.models[n], eng.keys, x, 1000 + 10 * i)
+            reqs.append(Request(i, n, ct, float(arrivals[i]), engine=i % len(engines)))
+        for eng in engines:
+            eng.ctx.sync()
         return reqs
 
-    rate = 0.7 * batched_rate
+    def saturated(nreq, mix, stream0, max_batch):
+        reqs = make(nreq, np.zeros(nreq), mix, stream0)
+        t0 = time.perf_counter()
+        done = ConcurrentServer(engines, 96 * 2 ** 30, max_batch=max_batch).run(reqs)
+        span = time.perf_counter() - t0
+        out = {"requests": len(done), "inferences_per_s": round(len(done) / span, 3), "span_s": round(span, 3),
+               "mean_batch": latency_report(done)["mean_batch"],
+               "per_model": {n: sum(1 for r in done if r.model == n) for n, _ in mix},
+               "engines": len(engines)}
+        del reqs, done
+        return out
+
+    # each measurement follows a warm-up pass of the same requests (the
+    # engines' buffer pools and plaintext caches as in steady state)
+    log("serving mix, saturation: %d requests at once" % args.serve_saturation)
+    saturated(args.serve_saturation, SERVE_MIX, 3000, args.serve_batch)
+    sat = saturated(args.serve_saturation, SERVE_MIX, 3000, args.serve_batch)
+    log("serving mix saturation:", sat)
+    rate = 0.7 * sat["inferences_per_s"]
     nreq = args.serve_requests
-    reqs = make(nreq, synth.poisson_arrivals(rate, nreq), 100)
-    log("serving %d requests at %.1f/s, budget %.1f GiB (pool live %.1f GiB)" % (nreq, rate, budget / 2 ** 30,
-                                                                                 free["live"] / 2 ** 30))
-    done = Server(eng, budget, max_batch=args.serve_batch).run(reqs)
-    rep = latency_report(done)
-    rep.update({"arrival_rate_per_s": round(rate, 3), "mix": {n: float(p) for n, p in zip(names, probs)},
-                "hbm_budget_GiB": budget / 2 ** 30,
-                "working_MiB_per_request": {n: round(eng.work[n] / 2 ** 20, 1) for n in names}})
+    budget = 40 * 2 ** 30
+    reqs = make(nreq, synth.poisson_arrivals(rate, nreq), SERVE_MIX, 100)
+    log("serving %d requests at %.1f/s, budget %.1f GiB" % (nreq, rate, budget / 2 ** 30))
+    done = ConcurrentServer(engines, budget, max_batch=args.serve_batch).run(reqs)
+    rep = latency_report(done, skip=nreq // 10)
+    rep.update({"arrival_rate_per_s": round(rate, 3), "saturation_inferences_per_s": sat["inferences_per_s"],
+                "mix": {n: float(p) for n, p in SERVE_MIX}, "hbm_budget_GiB": budget / 2 ** 30,
+                "engines": len(engines), "warmup_requests_excluded": nreq // 10,
+                "latency": "per request, arrival to completion",
+                "working_MiB_per_request": {n: round(engines[0].work[n] / 2 ** 20, 1) for n, _ in SERVE_MIX}})
     log("serving:", rep)
     del reqs, done
 
-    reqs = make(64, np.zeros(64), 5000)
-    log("mixed batch of 64 requests")
-    t0 = time.perf_counter()
-    done = Server(eng, 96 * 2 ** 30, max_batch=32).run(reqs)
-    ctx.sync()
-    span = time.perf_counter() - t0
-    kinds = {n: sum(1 for r in done if r.model == n) for n in names}
-    mixed = {"requests": len(done), "inferences_per_s": round(len(done) / span, 3), "span_s": round(span, 3),
-             "mean_batch": latency_report(done)["mean_batch"], "per_model": kinds}
-    log("mixed batch:", mixed)
-    del reqs, done, keys, models, eng
-    ctx.close()
+    log("batched mix of 64 requests of uneven shapes")
+    saturated(64, MIX64, 5000, 32)
+    mixed = saturated(64, MIX64, 5000, 32)
+    log("batched mix:", mixed)
+    for eng in engines:
+        ctx = eng.ctx
+        del eng.keys, eng.models
+        ctx.close()
     return rep, mixed
+
+
+TABLE3_SHAPES = ((64, 3, 2), (128, 5, 3), (256, 5, 3), (256, 10, 3), (256, 10, 5))
+
+
+def table3(args):
+    """The paper's comparison of the basis approximation with and without
+    lazy combination, on one GPU: for each (n_i, g, k) a one-layer KAN
+    [n_i, n_o = 10] on U[0,1] inputs, grid [0,1], at the N = 2^16 parameters,
+    evaluated for one encrypted input (batch 1, as the paper's latencies)
+    (a) in the paper's order (lazy combination: W_f = W'P applied to the
+    ColTile bases) and (b) without lazy combination (the bases permuted into
+    row order by a homomorphic permutation, then W'); also (c) with the
+    restructurings.  Median of `--table3-reps` timed evaluations after a
+    warm-up (plaintext caches filled); every variant decrypts within 1e-2 of
+    the FP64 circuit."""
+    from paper_2409_07751_amd import compile as pc
+    from paper_2409_07751_amd import hekan, synth
+    wl0 = synth.WORKLOADS["image"]
+    ctx = hekan.Context(wl0.logN, wl0.L, wl0.scale_bits, wl0.alpha, wl0.w)
+    rows = []
+    for n_i, g, k in TABLE3_SHAPES:
+        wl = synth.Workload("t3", wl0.logN, wl0.L, wl0.scale_bits, wl0.alpha, wl0.w, (n_i, 10), g, k, (0.0, 1.0),
+                            31, None, ((7, 7),), 0.05, 0.05, "pixels")
+        layers = pc.compile_kan(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024), wl.silu_degree,
+                                [list(c) for c in wl.comp_degrees], wl.grid, None, prescale=True)
+        x = synth.inputs(wl, 1)[0]
+        want = pc.plain_forward(x[None], layers)[0]
+        row = {"n_i": n_i, "g": g, "k": k, "n_o": 10}
+        for name, flags in (("lazy", hekan.CIRCUIT_PAPER), ("naive", hekan.CIRCUIT_NAIVE_PERMUTATION),
+                            ("restructured", hekan.CIRCUIT_RESTRUCTURED)):
+            model = ctx.compile(layers, circuit=flags)
+            t0 = time.time()
+            keys = ctx.keygen(synth.SEED_KEYGEN, model.rotation_steps())
+            ct = ctx.encrypt(keys, x, synth.SEED_ENC)
+            out = ctx.eval_kan(model, keys, ct)
+            ctx.sync()
+            setup = time.time() - t0
+            err = float(np.abs(ctx.decrypt(keys, out, 10) - want).max())
+            c0 = ctx.counters()
+            lat = []
+            for _ in range(args.table3_reps):
+                t0 = time.perf_counter()
+                out = ctx.eval_kan(model, keys, ct)
+                ctx.sync()
+                lat.append(time.perf_counter() - t0)
+            c1 = ctx.counters()
+            row[name] = {"ms": round(float(np.median(lat)) * 1e3, 3),
+                         "keyswitches": (c1["keyswitches"] - c0["keyswitches"]) // args.table3_reps,
+                         "rotation_keys": len(model.rotation_steps()), "max_abs_err_vs_fp64_circuit": err,
+                         "setup_s": round(setup, 1)}
+            log("table3 %s %s: %s" % ((n_i, g, k), name, row[name]))
+            del out, ct, keys, model
+        row["speedup_lazy_vs_naive"] = round(row["naive"]["ms"] / row["lazy"]["ms"], 3)
+        rows.append(row)
+    ctx.close()
+    return {"metric": "encrypted KAN layer latency, basis approximation with and without lazy combination",
+            "unit": "ms", "n_gpus": 1, "batch": 1, "data": "synthetic",
+            "config": {"workload": "one-layer KAN [n_i,10], k, G=g on [0,1], RNS-CKKS N=2^16, L=24, "
+                                   "4 special primes, 5-limb digits"}, "rows": rows}
 
 
 def main():
@@ -280,22 +447,35 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=16, help="requests per step, split evenly over the engines")
+    ap.add_argument("--engines", type=int, default=1,
+                    help="contexts (HIP streams, copies of the keys) evaluating parts of the batch concurrently")
     ap.add_argument("--plain-steps", type=int, default=10,
                     help="steps of the plain per-ciphertext path (batch 1) timed for comparison; 0 skips")
     ap.add_argument("--workload", default="image")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="replays of the inference captured into a HIP graph, at the batch and at batch 1 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--roofline-steps", type=int, default=3,
+                    help="steps run after the timed region with the roofline kernel's launches timed")
+    ap.add_argument("--no-ks-bench", action="store_true", help="skip the key-switch microbenchmark")
+    ap.add_argument("--no-word-study", action="store_true",
+                    help="skip the integer-words run (every prime on 64-bit integer arithmetic)")
     ap.add_argument("--roofline-kernel", default="ntt_fwd_pass1")
     ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching server run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default key-switch configuration (fused, spans of 8) at every level")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-saturation", type=int, default=96,
+                    help="requests of the serving mix present at once to measure its saturation throughput")
     ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--serve-engines", type=int, default=2,
+                    help="serving engines (contexts with their own stream and copy of the keys)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--table3", action="store_true",
+                    help="run only the basis-approximation comparison (lazy combination vs the naive permutation)")
+    ap.add_argument("--table3-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (--gpus 1): requests are independent, so N GPUs would "
@@ -306,6 +486,9 @@ def main():
     from paper_2409_07751_amd import compile as pc
     from paper_2409_07751_amd import hekan, synth
 
+    if args.table3:
+        print(json.dumps(table3(args)), flush=True)
+        return
     wl = synth.WORKLOADS[args.workload]
     log("workload", wl.name, "N=2^%d" % wl.logN, "L=%d" % wl.L, "shape", wl.shape)
     raw = synth.raw_weights(wl)
@@ -318,23 +501,48 @@ def main():
     keys = ctx.keygen(synth.SEED_KEYGEN, steps)
     ctx.sync()
     log("keygen %.1fs (%d Galois keys)" % (time.time() - t0, len(steps)))
-    B = args.batch
+    B, E = args.batch, args.engines
+    if B % E:
+        raise SystemExit("--batch must be a multiple of --engines")
+    Be = B // E
     x = synth.inputs(wl, B)
-    cts = [ctx.encrypt(keys, x[i], synth.SEED_ENC + i) for i in range(B)]
-    ctx.sync()
+    # engines: contexts with their own HIP stream and copy of the evaluation
+    # keys (same seed), each evaluating B / E of the requests from its own host
+    # thread, so that their kernels overlap on the device
+    engines = [(ctx, model, keys)]
+    for e in range(1, E):
+        c2 = hekan.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+        m2 = c2.compile(layers)
+        engines.append((c2, m2, c2.keygen(synth.SEED_KEYGEN, steps)))
+    parts = [[c.encrypt(k, x[i], synth.SEED_ENC + i) for i in range(e * Be, (e + 1) * Be)]
+             for e, (c, m, k) in enumerate(engines)]
+    for c, _, _ in engines:
+        c.sync()
+    cts = parts[0] if E == 1 else [ct for p in parts for ct in p]
+    from concurrent.futures import ThreadPoolExecutor
+    workers = ThreadPoolExecutor(max_workers=E)
 
-    def step():
-        outs = ctx.eval_kan_batch(model, keys, cts)
-        ctx.sync()
+    def run_engine(e):
+        c, m, k = engines[e]
+        outs = c.eval_kan_batch(m, k, parts[e])
+        c.sync()
         return outs
 
-    # key-switch configuration per level, chosen by measurement for the timed
-    # batch and for the plain path's batch of one
+    def step():
+        if E == 1:
+            return run_engine(0)
+        futs = [workers.submit(run_engine, e) for e in range(E)]
+        return [o for f in futs for o in f.result()]
+
+    # key-switch configuration per level, chosen by measurement for each
+    # engine's batch and for the plain path's batch of one
     tune = {}
     if not args.no_autotune:
         t0 = time.time()
-        for nb in sorted({B, 1}):
+        for nb in sorted({Be, 1}):
             tune[str(nb)] = ctx.autotune(keys, nb)
+        for c, _, k in engines[1:]:
+            c.autotune(k, Be)
         log("key-switch autotune %.1fs: %s" % (time.time() - t0, tune))
 
     for w in range(args.warmup):
@@ -343,28 +551,44 @@ def main():
         log("warmup %d: %.3fs" % (w, time.time() - t0))
     # accuracy check of the last warmup output against the plain FP64 circuit
     want = pc.plain_forward(x, layers)
-    err = max(float(np.abs(ctx.decrypt(keys, outs[i], wl.shape[-1]) - want[i]).max()) for i in range(B))
+    err = max(float(np.abs(engines[i // Be][0].decrypt(engines[i // Be][2], outs[i], wl.shape[-1]) - want[i]).max())
+              for i in range(B))
     log("max |decrypt - fp64 circuit| = %.3e" % err)
     del outs
 
-    c0 = ctx.counters()
+    def counters():
+        cs = [c.counters() for c, _, _ in engines]
+        return {k: sum(v[k] for v in cs) for k in cs[0]}
+
+    # the timed steps: no kernel timer (no events between launches)
+    c0 = counters()
     lat = []
-    ctx.sync()
-    ctx.profile(args.roofline_kernel)
+    for c, _, _ in engines:
+        c.sync()
     t_start = time.perf_counter()
     for s in range(args.steps):
         t0 = time.perf_counter()
         outs = step()
         lat.append(time.perf_counter() - t0)
         del outs
-    ctx.sync()
+    for c, _, _ in engines:
+        c.sync()
     elapsed = time.perf_counter() - t_start
+    c1 = counters()
+    # the roofline's kernel timing in separate steps after the timed ones, on
+    # engine 0 alone (its batch of B / E)
+    ctx.profile(args.roofline_kernel)
+    for s in range(args.roofline_steps):
+        del_outs = run_engine(0)
+        del del_outs
     prof = ctx.profile_read()
     ctx.profile(None)
-    c1 = ctx.counters()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
-    roof = roofline(args.roofline_kernel, prof, B)
+    roof = roofline(args.roofline_kernel, prof, Be)
+    if roof is not None:
+        roof["timed_in"] = "%d separate steps after the timed region (HIP events around each launch)" % \
+            args.roofline_steps
     ks_per_step = (c1["keyswitches"] - c0["keyswitches"]) / args.steps
     inf_s = B * args.steps / elapsed
     lat_ms = np.array(lat) * 1e3
@@ -382,7 +606,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "KAN [784,64,10] encrypted inference, RNS-CKKS N=2^16, L=24, 4 special primes, "
-                               "5-limb digits", "batch": B, "levels": wl.L, "log_n": wl.logN},
+                               "5-limb digits", "batch": B, "engines": E, "batch_per_engine": Be,
+                   "levels": wl.L, "log_n": wl.logN},
         "keyswitches_per_s": round(ks_per_step * args.steps / elapsed, 1),
         "keyswitches_per_inference": ks_per_step / B,
         "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
@@ -395,14 +620,24 @@ def main():
     if args.plain_steps:
         res["plain_path"] = plain_path(ctx, model, keys, cts[0], args.plain_steps)
         res["batched_vs_plain"] = round(res["value"] / res["plain_path"]["inferences_per_s"], 3)
+    if not args.no_ks_bench:
+        res["keyswitch_bench"] = ks_bench(ctx, keys, wl)
     if args.graph_steps:
         res["graph_path"] = [graph_path(ctx, model, keys, c, args.graph_steps, want, wl.shape[-1])
-                             for c in (cts, cts[:1])]
+                             for c in (parts[0], parts[0][:1])]
     if not args.no_serve:
-        res["serving"], res["batched_mix"] = serve_run(args, res["value"])
+        res["serving"], res["batched_mix"] = serve_run(args)
+    if not args.no_word_study:
+        res["word_size_study"] = word_study(args, layers, wl, x, want)
+        log("word-size study:", res["word_size_study"])
+    res["silu_fit_comparison"] = silu_fits()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
-    del cts, keys, model
+        res["cpu_baseline"] = cpu_baseline(wl)
+    workers.shutdown()
+    del cts, parts, keys, model
+    for c, _, _ in engines[1:]:
+        c.close()
+    del engines
     ctx.close()
     print(json.dumps(res), flush=True)
 

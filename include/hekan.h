@@ -81,6 +81,11 @@ typedef struct {
     int32_t digit_width;    /* Q limbs per hybrid key-switching digit, 1..8, with   */
                             /* ceil((levels + 1) / digit_width) <= 16 digits        */
     double sigma;           /* standard deviation of the rounded Gaussian error     */
+    int32_t integer_words;  /* 0: primes below 2^46 run their transforms, basis     */
+                            /* conversions and rescale tails in exact FP64          */
+                            /* arithmetic, the others on 64-bit integer words; 1:  */
+                            /* every prime on 64-bit integer words (Shoup, Barrett, */
+                            /* Montgomery).  Both give the same residues.           */
 } he_params;
 
 /*
@@ -143,7 +148,15 @@ enum {
     /* A hidden layer's block layout repeats with the shortest power-of-two
      * period that holds its blocks; the fold runs over one period. */
     HE_CIRCUIT_FOLDED_PERIOD = 4,
-    HE_CIRCUIT_RESTRUCTURED = 7
+    HE_CIRCUIT_RESTRUCTURED = 7,
+    /* Not a restructuring: the comparison method of the paper's experiments
+     * on the basis approximation, without lazy combination.  The bases are
+     * moved from ColTile order into row order by a homomorphic permutation
+     * (Algorithm 3's P applied to the ciphertext: one ciphertext-plaintext
+     * product per distinct slot offset, baby-step giant-step rotations) and
+     * multiplied by W' itself.  Costs one more level per layer; excludes
+     * HE_CIRCUIT_FUSED_LINEAR and HE_CIRCUIT_FOLDED_PERIOD (HE_EINVAL). */
+    HE_CIRCUIT_NAIVE_PERMUTATION = 8
 };
 
 /* ---------------------------------------------------------------- context */
@@ -194,6 +207,20 @@ int he_ctx_profile_read(he_ctx *ctx, double *total_ms, uint64_t *launches, doubl
 int he_ctx_autotune(he_ctx *ctx, const he_eval_keys *ek, int32_t batch, int32_t reps, int32_t *choice, size_t cap,
                     size_t *n);
 int he_ctx_set_keyswitch(he_ctx *ctx, int32_t level, int32_t batch, int32_t config);
+
+/* Key-switch microbenchmark (measurement): `batch` ciphertexts at `level`
+ * sharing one key, key-switched together `reps` times after one warm-up, each
+ * repetition timed with HIP events on the context stream; writes the median
+ * milliseconds of one repetition (one launch sequence for the whole batch).
+ * step == 0 times the relinearisation of a ciphertext product as the library
+ * runs it (key switch of d2 with ModDown and the following rescale in one
+ * transform per limb; level >= 1); otherwise a rotation by `step` (automorphism
+ * and key switch).  Operands are zero: the kernels' work does not depend on
+ * the values.  Errors: HE_EKEY without the key, HE_EDEPTH for a product at
+ * level 0, HE_EINVAL for other bad arguments. */
+int he_ctx_bench_keyswitch(he_ctx *ctx, const he_eval_keys *ek, int32_t step, int32_t level, int32_t batch,
+                           int32_t reps, double *ms);
+
 /* ------------------------------------------------------------------ model */
 
 /* Compile a KAN for encrypted evaluation: checks the layer shapes and their
@@ -355,8 +382,9 @@ int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
  * needs (level + 1) 2 N 8 bytes of it, and a larger one returns HE_ENOMEM
  * with nothing launched (at N = 2^16 up to level 31).  Calls that overlap
  * on one device race for that array.  Errors: HE_EINVAL (null, batched,
- * wrong output level, output sharing memory with a), HE_EDEPTH (a at level
- * 0), HE_ESTATE (handles of another context). */
+ * wrong output level, output sharing memory with a or with any other
+ * ciphertext or graph), HE_EDEPTH (a at level 0), HE_ESTATE (handles of
+ * another context). */
 int he_ct_rescale_noalloc(he_ctx *ctx, const he_ct *a, he_ct *out);
 
 /* out = sum_i a[i] * z_i landing at level `target` with scale S_target; z_i

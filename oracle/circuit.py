@@ -48,16 +48,21 @@ import math
 
 import numpy as np
 
-from .kan import fused_weights
+from .kan import fused_weights, lazy_weights
 
 
 @dataclasses.dataclass(frozen=True)
 class Circuit:
     """Which restructurings of the paper's circuit are applied (all off: the
-    paper's order)."""
+    paper's order).  naive_permutation is the comparison method of the
+    paper's basis-approximation experiments instead: no lazy combination of
+    the permutation, the bases are permuted from ColTile order into row order
+    by a homomorphic permutation and multiplied by W' itself (it excludes
+    fused_linear and folded_period)."""
     shared_comparison: bool = False
     fused_linear: bool = False
     folded_period: bool = False
+    naive_permutation: bool = False
 
 
 PAPER = Circuit()
@@ -340,6 +345,59 @@ def fold(ev, z, d, period=None):
     return z
 
 
+def permutation_offsets(L, n_blk, S, slots):
+    """The homomorphic permutation of the naive method (Algorithm 3's P applied
+    to the ciphertext): slot (i (g+k) + m) S + s receives slot
+    m n_blk + i S + s (basis m of input i of vector s).  Returns the signed
+    offset src - dst of every destination (in (-slots/2, slots/2]) and the
+    baby-step width b1 = the power of two >= sqrt(2 R + 1), R the largest
+    |offset|; offset o = g b1 + b splits into giant g (floor) and baby
+    b in [0, b1)."""
+    nb = L.g + L.k
+    dst, off = [], []
+    for i in range(L.n_in):
+        for m in range(nb):
+            for s in range(S):
+                d = (i * nb + m) * S + s
+                o = (m * n_blk + i * S + s - d) % slots
+                if o > slots // 2:
+                    o -= slots
+                dst.append(d)
+                off.append(o)
+    R = max(abs(o) for o in off)
+    b1 = pow2ceil(int(math.ceil(math.sqrt(2 * R + 1))))
+    return np.array(dst), np.array(off), b1
+
+
+def permute(ev, x, L, n_blk, S, t):
+    """z[d] = x[src(d)] for the naive method's permutation, zero elsewhere, at
+    level t, by the diagonal method with baby-step giant-step rotations:
+    z = sum_g rot( sum_b rot(diag_(g b1 + b), -g b1) * rot(x, b), g b1 ),
+    diag_o the 0/1 vector of the destinations with offset o (one ct x pt
+    product per non-zero diagonal)."""
+    slots = ev.ctx.p.slots
+    dst, off, b1 = permutation_offsets(L, n_blk, S, slots)
+    giants = sorted(set(int(o) // b1 for o in off))
+    babies = sorted(set(int(o) - (int(o) // b1) * b1 for o in off))
+    xd = ev.mod_drop(x, t + 1)
+    rots = {b: (xd if b == 0 else ev.rotate(xd, b)) for b in babies}
+    z = None
+    for g in giants:
+        terms = []
+        for b in babies:
+            sel = dst[off == g * b1 + b]
+            if len(sel) == 0:
+                continue
+            dv = np.zeros(slots)
+            dv[sel] = 1.0
+            terms.append((rots[b], np.roll(dv, g * b1)))
+        inner = ev.lincomb(terms, t)
+        if g:
+            inner = ev.rotate(inner, g * b1)
+        z = inner if z is None else ev.add(z, inner)
+    return z
+
+
 def chunk_bounds(L, slots, S=1):
     """Feature ranges [b_c, b_{c+1}) of the first layer's input ciphertexts:
     each chunk holds as many consecutive features as its repeat-packed
@@ -410,6 +468,8 @@ def layer_part(ev, x, L, n_blk, first, d, S=1, circ=PAPER):
     slots = ev.ctx.p.slots
     nb = L.g + L.k
     width = L.n_in * S
+    if circ.naive_permutation and (circ.fused_linear or circ.folded_period):
+        raise ValueError("the naive permutation excludes the fused linear layers and the folded period")
     period = slots if first else hidden_period(L, n_blk, slots, circ)
     xr = repeat_pack(ev, x, n_blk, clog2(L.g + 2 * L.k)) if first else x
     shared = circ.shared_comparison and shared_comparison(L, n_blk, first, slots)
@@ -423,9 +483,15 @@ def layer_part(ev, x, L, n_blk, first, d, S=1, circ=PAPER):
         W = strided(np.hstack([fused_weights(L, L.n_in), L.wb]), S, nb + 1, n_blk)
         return [matvec_partial(ev, z, W, d, t, S, period)]
     s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
+    Wb = strided(L.wb, S, 1, n_blk)
+    if circ.naive_permutation:
+        # no lazy combination: the bases permuted into row order, then W'
+        bp = permute(ev, b, L, n_blk, S, b.level - 1)
+        t = min(bp.level, s.level) - 1
+        Wr = strided(lazy_weights(L), S, 1, L.n_in * nb * S)
+        return [matvec_partial(ev, bp, Wr, d, t, S, period), matvec_partial(ev, s, Wb, d, t, S, period)]
     t = min(b.level, s.level) - 1
     Wf = strided(fused_weights(L, L.n_in), S, nb, n_blk)
-    Wb = strided(L.wb, S, 1, n_blk)
     return [matvec_partial(ev, b, Wf, d, t, S, period), matvec_partial(ev, s, Wb, d, t, S, period)]
 
 
@@ -487,6 +553,18 @@ def rotation_steps(layers, slots, S=1, circ=PAPER):
                 steps.add(nb)
         else:
             steps.add(n_blk)
+        if circ.naive_permutation:
+            parts = ([(sub_layer(L, lo, hi), (hi - lo) * S) for lo, hi in
+                      zip(chunk_bounds(L, slots, S)[:-1], chunk_bounds(L, slots, S)[1:])] if li == 0
+                     else [(L, n_blk)])
+            for Lc, nbk in parts:
+                _, off, pb1 = permutation_offsets(Lc, nbk, S, slots)
+                for o in set(int(v) for v in off):
+                    g, b = o // pb1, o - (o // pb1) * pb1
+                    if b:
+                        steps.add(b)
+                    if g:
+                        steps.add(g * pb1)
         b1, g1 = bsgs_split(d)
         steps.update(bi * S for bi in range(1, b1))
         steps.update(gi * b1 * S for gi in range(1, g1))

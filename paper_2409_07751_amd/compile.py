@@ -68,12 +68,92 @@ def silu_range(mu, sd, lo, hi):
     return max(mu - 5.0 * sd, lo), min(mu + 5.0 * sd, hi)
 
 
+def silu(x):
+    return x / (1.0 + np.exp(-x))
+
+
+def _u(x, lo, hi):
+    return (2.0 * x - (lo + hi)) / (hi - lo)
+
+
 def fit_silu(lo, hi, degree, mu, sd, n=4001):
+    """The paper's fit (SiLU Approximation): weighted least squares on n uniform
+    samples of the range, weight 10 inside mu +- 3 sigma and 1 outside."""
     x = np.linspace(lo, hi, n)
-    y = x / (1.0 + np.exp(-x))
     sw = np.sqrt(np.where(np.abs(x - mu) <= 3.0 * sd, 10.0, 1.0))
-    A = cheb.chebvander((2.0 * x - (lo + hi)) / (hi - lo), degree) * sw[:, None]
-    return np.linalg.lstsq(A, y * sw, rcond=None)[0]
+    A = cheb.chebvander(_u(x, lo, hi), degree) * sw[:, None]
+    return np.linalg.lstsq(A, silu(x) * sw, rcond=None)[0]
+
+
+def fit_silu_ols(lo, hi, degree, n=4001):
+    """Ordinary least squares on the same uniform samples (every weight 1):
+    the least-squares comparator of the SiLU Approximation experiments."""
+    x = np.linspace(lo, hi, n)
+    return np.linalg.lstsq(cheb.chebvander(_u(x, lo, hi), degree), silu(x), rcond=None)[0]
+
+
+def remez(f, lo, hi, degree, grid=100001, iters=60, tol=1e-12):
+    """Minimax polynomial of `degree` for f on [lo, hi] in the Chebyshev basis
+    of the range, by the Remez exchange: solve p(x_j) + (-1)^j E = f(x_j) on
+    degree + 2 reference points, move the references to the alternating
+    extrema of the error on a dense grid, repeat until the largest error
+    equals |E| to `tol` (relative).  Returns (coefficients, max error)."""
+    n = degree
+    j = np.arange(n + 2)
+    ref = np.sort(np.cos(np.pi * j / (n + 1)))            # Chebyshev extrema in [-1, 1]
+    xs = np.linspace(-1.0, 1.0, grid)
+    fx = f(lo + (xs + 1.0) * (hi - lo) / 2.0)
+    c, err = None, None
+    for _ in range(iters):
+        fr = f(lo + (ref + 1.0) * (hi - lo) / 2.0)
+        A = np.hstack([cheb.chebvander(ref, n), ((-1.0) ** j)[:, None]])
+        sol = np.linalg.solve(A, fr)
+        c, E = sol[:-1], sol[-1]
+        e = fx - cheb.chebval(xs, c)
+        err = float(np.abs(e).max())
+        if err - abs(E) <= tol * err:
+            break
+        # one extremum per run of equal sign, then keep n + 2 alternating ones
+        # around the largest (multi-point exchange)
+        sgn = np.sign(e)
+        sgn[sgn == 0] = 1.0
+        cut = np.flatnonzero(np.diff(sgn) != 0) + 1
+        runs = np.split(np.arange(grid), cut)
+        ext = np.array([r[np.argmax(np.abs(e[r]))] for r in runs])
+        while len(ext) > n + 2:
+            # drop the smaller end, never the global maximum
+            if abs(e[ext[0]]) <= abs(e[ext[-1]]):
+                ext = ext[1:]
+            else:
+                ext = ext[:-1]
+        if len(ext) < n + 2:
+            break
+        ref = xs[ext]
+    return c, err
+
+
+def fit_silu_remez(lo, hi, degree):
+    """Minimax (Remez) fit of SiLU on the range: the Remez comparator."""
+    return remez(silu, lo, hi, degree)[0]
+
+
+def silu_fit_comparison(lo, hi, degree, samples, n=4001):
+    """Weighted least squares (mu, sigma of `samples`), ordinary least squares
+    and Remez minimax at one degree and range, each measured by the RMSE over
+    the range's n uniform points, the RMSE over `samples` (the activation
+    distribution) and the largest error on the range."""
+    samples = np.asarray(samples, np.float64)
+    mu, sd = float(samples.mean()), float(samples.std())
+    x = np.linspace(lo, hi, n)
+    inside = samples[(samples >= lo) & (samples <= hi)]
+    out = {}
+    for name, c in (("wls", fit_silu(lo, hi, degree, mu, sd, n)), ("ols", fit_silu_ols(lo, hi, degree, n)),
+                    ("remez", fit_silu_remez(lo, hi, degree))):
+        eu = cheb.chebval(_u(x, lo, hi), c) - silu(x)
+        ed = cheb.chebval(_u(inside, lo, hi), c) - silu(inside)
+        out[name] = {"rmse_uniform": float(np.sqrt(np.mean(eu ** 2))),
+                     "rmse_data": float(np.sqrt(np.mean(ed ** 2))), "max_err": float(np.abs(eu).max())}
+    return out
 
 
 def _soft_step(v, stages):

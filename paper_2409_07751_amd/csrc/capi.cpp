@@ -137,7 +137,7 @@ int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out)
         need((p->levels + p->digit_width) / p->digit_width <= 16, "more than 16 key-switch digits");
         need(p->sigma > 0 && p->sigma < 100, "sigma out of range");
         h->c = new Ctx(p->log_n, p->levels, p->scale_bits, p->base_bits, p->special_count, p->special_bits,
-                       p->digit_width, p->sigma, (hipStream_t)hip_stream);
+                       p->digit_width, p->sigma, (hipStream_t)hip_stream, p->integer_words != 0);
     });
     if (rc != HE_OK) {
         delete h;
@@ -197,6 +197,58 @@ int he_ctx_autotune(he_ctx *ctx, const he_eval_keys *k, int32_t batch, int32_t r
         const std::vector<int> c = ctx->c->autotune_keyswitch(k->k->relin, batch, reps);
         *n = c.size();
         for (size_t i = 0; i < c.size() && i < cap; i++) choice[i] = c[i];
+    });
+}
+
+int he_ctx_bench_keyswitch(he_ctx *ctx, const he_eval_keys *k, int32_t step, int32_t level, int32_t batch,
+                           int32_t reps, double *ms)
+{
+    if (!ctx || !k || !ms || batch < 1 || reps < 1) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ek(ctx, k);
+        Ctx &c = *ctx->c;
+        need(level >= 0 && level <= c.L, "level out of range");
+        if (step == 0) {
+            if (level < 1) throw HeError(HE_EDEPTH, "a relinearised product needs level >= 1");
+            if (!k->k->has_relin) throw HeError(HE_EKEY, "no relinearisation key");
+        } else if (!k->k->galois.count(c.galois_elt(step))) {
+            throw HeError(HE_EKEY, "no Galois key for this step");
+        }
+        // zero operands: the kernels' work does not depend on the values
+        Tensor t;
+        Ct a;
+        if (step == 0) {
+            t.level = level;
+            t.nb = batch;
+            t.buf = c.alloc((size_t)(level + 1) * 3 * c.N * batch);
+            HIP_CHECK(hipMemsetAsync(t.buf->p, 0, t.buf->words * 8, c.st));
+        } else {
+            a = c.new_ct(level, batch);
+            HIP_CHECK(hipMemsetAsync(a.d(), 0, a.buf->words * 8, c.st));
+        }
+        auto once = [&]() {
+            if (step == 0) (void)c.relin_rescale(t, *k->k);
+            else (void)c.rotate(a, step, *k->k);
+        };
+        once();  // warm-up: tables, caches and the pool's buffers
+        std::vector<hipEvent_t> ev(reps + 1);
+        for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
+        std::vector<float> t_ms(reps);
+        try {
+            HIP_CHECK(hipEventRecord(ev[0], c.st));
+            for (int r = 0; r < reps; r++) {
+                once();
+                HIP_CHECK(hipEventRecord(ev[r + 1], c.st));
+            }
+            HIP_CHECK(hipEventSynchronize(ev[reps]));
+            for (int r = 0; r < reps; r++) HIP_CHECK(hipEventElapsedTime(&t_ms[r], ev[r], ev[r + 1]));
+        } catch (...) {
+            for (auto &e : ev) (void)hipEventDestroy(e);
+            throw;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        std::sort(t_ms.begin(), t_ms.end());
+        *ms = reps % 2 ? t_ms[reps / 2] : 0.5 * (t_ms[reps / 2 - 1] + t_ms[reps / 2]);
     });
 }
 
@@ -635,6 +687,9 @@ int he_ct_rescale_noalloc(he_ctx *ctx, const he_ct *a, he_ct *out)
         const u64 *ab = a->c.buf->p, *ob = out->c.buf->p;
         const size_t aw = (size_t)(a->c.level + 1) * 2 * c.N, ow = (size_t)(out->c.level + 1) * 2 * c.N;
         need(ob + ow <= ab || ab + aw <= ob, "output shares memory with the input");
+        // another handle (a rotation by 0 returns its input's memory) or a
+        // graph holding the same buffer would see its residues overwritten
+        need(out->c.buf.use_count() == 1, "output shares memory with another ciphertext");
         if (!c.scratch) throw HeError(HE_ESTATE, "no scratch on this device");
         c.rescale_into(a->c, out->c, c.scratch);
     });

@@ -4,14 +4,28 @@
 
 #include <algorithm>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <thread>
 
 namespace hk {
 
 // ------------------------------------------------------------------- memory
-void *Pool::get(size_t bytes)
+// Allocation sizes are rounded up to size classes (256 B granules up to
+// 1 MiB, then eighths of the power of two below the size: at most 12.5% more)
+// so that buffers freed by a batch of one size serve batches of nearby sizes.
+static size_t size_class(size_t bytes)
 {
     bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes <= ((size_t)1 << 20)) return bytes;
+    size_t p = (size_t)1 << (63 - __builtin_clzll(bytes));
+    const size_t g = p >> 3;
+    return (bytes + g - 1) / g * g;
+}
+
+void *Pool::get(size_t bytes)
+{
+    bytes = size_class(bytes);
     void *p = nullptr;
     if (hold) {
         auto h = hold->find(bytes);
@@ -45,7 +59,7 @@ void *Pool::get(size_t bytes)
 
 void Pool::put(void *p, size_t bytes)
 {
-    bytes = (bytes + 255) & ~(size_t)255;
+    bytes = size_class(bytes);
     live -= bytes;
     if (hold) {
         hold->emplace(bytes, p);
@@ -135,7 +149,7 @@ void Ctx::profile_read(double &ms, u64 &launches, double &bytes, double &ops)
 
 // ------------------------------------------------------------------ context
 Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int special_bits, int w_, double sigma_,
-         hipStream_t stream)
+         hipStream_t stream, bool integer_words)
     : logN(logN_), N(1 << logN_), L(L_), alpha(alpha_), w(w_), L1(L_ + 1), sigma(sigma_)
 {
     make_chain(logN, base_bits, L, scale_bits, alpha, special_bits, q, p, S);
@@ -164,7 +178,7 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
         c.r1p = shoup_of(c.r1, m);
         c.ninv = hinv((u64)N % m, m);
         c.ninvp = shoup_of(c.ninv, m);
-        c.fp = c.bits <= 46;
+        c.fp = c.bits <= 46 && !integer_words;
         c.qd = (double)m;
         c.qinvd = 1.0 / (double)m;
         const u64 r32 = (u64)(((u128)1 << 32) % m);
@@ -986,6 +1000,43 @@ Pt Ctx::vec_pt(const double *z, size_t n, double scale, int nl)
     p.nl = nl;
     p.buf = encode_ntt(z, n, scale, nl, true);
     return p;
+}
+
+std::vector<Pt> Ctx::vec_pts(const std::vector<const std::vector<double> *> &zs, double scale, int nl)
+{
+    const size_t n = zs.size();
+    std::vector<std::vector<u64>> host(n);
+    std::vector<std::thread> th;
+    std::exception_ptr err;
+    std::mutex mu;
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (unsigned tid = 0; tid < nth; tid++)
+        th.emplace_back([&, tid]() {
+            try {
+                for (size_t i = tid; i < n; i += nth) {
+                    host[i].resize((size_t)nl * N);
+                    encode_rns(zs[i]->data(), zs[i]->size(), scale, logN, mods.data(), nl, host[i].data());
+                }
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                err = std::current_exception();
+            }
+        });
+    for (auto &t : th) t.join();
+    if (err) std::rethrow_exception(err);
+    std::vector<Pt> out(n);
+    for (size_t i = 0; i < n; i++) {
+        Buf b = alloc(host[i].size());
+        upload(b->p, host[i].data(), host[i].size());
+        PolySet ps{b->p, (long)N, 0, nl, 1};
+        ntt(ps, lmap(nl), false);
+        launch_to_montgomery(d_pc, b->p, (long)N, nl, lmap(nl), N, 1, 0, st);
+        n_launch++;
+        out[i].is_const = false;
+        out[i].nl = nl;
+        out[i].buf = b;
+    }
+    return out;
 }
 
 // sum_i ct_i * z_i landing at level t: every ct_i is read on limbs 0..t+1

@@ -148,7 +148,7 @@ struct Ctx {
     void profile_read(double &ms, u64 &launches, double &bytes, double &ops);
 
     Ctx(int logN, int L, int scale_bits, int base_bits, int alpha, int special_bits, int w, double sigma,
-        hipStream_t stream);
+        hipStream_t stream, bool integer_words = false);
     ~Ctx();
 
     Buf alloc(size_t words);
@@ -238,6 +238,9 @@ struct Ctx {
     Buf encode_ntt(const double *z, size_t n, double scale, int nl, bool montgomery);
     Pt const_pt(double c, double scale, int nl);
     Pt vec_pt(const double *z, size_t n, double scale, int nl);
+    // several slot-vector plaintexts at once: the host encodings run on
+    // parallel threads, then each is uploaded and transformed
+    std::vector<Pt> vec_pts(const std::vector<const std::vector<double> *> &zs, double scale, int nl);
 
     // tables
     const KsTable &ks_table(int l);

@@ -5,6 +5,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <stdexcept>
 
 namespace hk {
@@ -334,10 +337,46 @@ void put_residues(i128 v, const u64 *mods, int nl, u64 *out, long stride)
 }
 }  // namespace
 
+// The encoder's double-double tables for one ring degree: the FFT twiddles
+// zeta^(-4 r) (r < M/2), the final factors zeta^(-i) (i < M) and the
+// bit-reversal of the M-point FFT.  Built once per degree (the series that
+// give each entry dominate an encode's cost) and kept for the process.
+struct EncTables {
+    std::vector<CDD> tw, zinv;
+    std::vector<long> brv;
+};
+
+static const EncTables &enc_tables(int logN)
+{
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<EncTables>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    std::unique_ptr<EncTables> &t = cache[logN];
+    if (!t) {
+        const long N = 1l << logN, M = N / 2;
+        t.reset(new EncTables());
+        t->tw.resize(M / 2 > 0 ? M / 2 : 1);
+        for (long r = 0; r < M / 2; r++) t->tw[r] = zeta_pow(-4 * r, N);
+        t->zinv.resize(M);
+        for (long i = 0; i < M; i++) t->zinv[i] = zeta_pow(-i, N);
+        int lm = 0;
+        while ((1l << lm) < M) lm++;
+        t->brv.resize(M);
+        for (long i = 0; i < M; i++) {
+            long src = 0;
+            for (int b = 0; b < lm; b++)
+                if (i >> b & 1) src |= 1l << (lm - 1 - b);
+            t->brv[i] = src;
+        }
+    }
+    return *t;
+}
+
 void encode_rns(const double *z, size_t n, double scale, int logN, const u64 *mods, int nl, u64 *out)
 {
     const long N = 1l << logN, M = N / 2, twoN = 2 * N;
     if ((long)n > M) throw std::runtime_error("encode: too many slots");
+    const EncTables &T = enc_tables(logN);
     // w_k = z_j where 5^j = 4k + 1 (mod 2N)
     std::vector<CDD> w(M, CDD{{0, 0}, {0, 0}});
     long e = 1;
@@ -347,8 +386,7 @@ void encode_rns(const double *z, size_t n, double scale, int logN, const u64 *mo
     }
     // in-place iterative radix-2 DIF with twiddles omega^-r, omega = zeta^4,
     // natural order in, bit-reversed out
-    std::vector<CDD> tw(M / 2 > 0 ? M / 2 : 1);
-    for (long r = 0; r < M / 2; r++) tw[r] = zeta_pow(-4 * r, N);
+    const std::vector<CDD> &tw = T.tw;
     for (long len = M; len >= 2; len >>= 1) {
         long half = len / 2, step = M / len;
         for (long b = 0; b < M; b += len)
@@ -358,15 +396,10 @@ void encode_rns(const double *z, size_t n, double scale, int logN, const u64 *mo
                 w[b + j + half] = (u - v) * tw[j * step];
             }
     }
-    int lm = 0;
-    while ((1l << lm) < M) lm++;
     // u_i = (2/N) zeta^-i W_i,  m_i = Re u_i * scale,  m_{i+M} = Im u_i * scale
     const double f = 2.0 * scale / (double)N;
     for (long i = 0; i < M; i++) {
-        long src = 0;
-        for (int b = 0; b < lm; b++)
-            if (i >> b & 1) src |= 1l << (lm - 1 - b);
-        CDD u = w[src] * zeta_pow(-i, N);
+        CDD u = w[T.brv[i]] * T.zinv[i];
         put_residues(round_even(u.re * f), mods, nl, out + i, N);
         put_residues(round_even(u.im * f), mods, nl, out + i + M, N);
     }

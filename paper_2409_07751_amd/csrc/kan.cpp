@@ -22,6 +22,28 @@ static int clog2i(long n)
     return r;
 }
 static long pow2ceil(long n) { return 1l << clog2i(n); }
+static long floordiv(long a, long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+PermPlan perm_plan(const LayerC &L, const Part &P, long S, long slots)
+{
+    const long nb = L.g + L.k;
+    PermPlan pp;
+    long R = 0;
+    for (long i = 0; i < P.n_in; i++)
+        for (long m = 0; m < nb; m++)
+            for (long s = 0; s < S; s++) {
+                const long d = (i * nb + m) * S + s;
+                long o = ((m * P.n_blk + i * S + s - d) % slots + slots) % slots;
+                if (o > slots / 2) o -= slots;
+                pp.dst.push_back(d);
+                pp.off.push_back(o);
+                R = std::max(R, std::labs(o));
+            }
+    long b = 1;
+    while (b * b < 2 * R + 1) b++;
+    pp.b1 = pow2ceil(b);
+    return pp;
+}
 
 // ------------------------------------------------------------------- model
 Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refresh_)
@@ -31,7 +53,10 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
     S = d->samples_per_ct <= 0 ? 1 : d->samples_per_ct;
     if ((S & (S - 1)) != 0 || S > slots) throw HeError(-1, "model: samples per ciphertext must be a power of two");
     circ = d->circuit;
-    if (circ & ~HE_CIRCUIT_RESTRUCTURED) throw HeError(-1, "model: unknown circuit option");
+    if (circ & ~(HE_CIRCUIT_RESTRUCTURED | HE_CIRCUIT_NAIVE_PERMUTATION))
+        throw HeError(-1, "model: unknown circuit option");
+    if (naive() && (fused() || folded()))
+        throw HeError(-1, "model: the naive permutation excludes the fused linear layers and the folded period");
     long n_blk = 0;
     for (int li = 0; li < d->n_layers; li++) {
         const he_kan_layer &s = d->layers[li];
@@ -97,6 +122,14 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
                     P.W[((size_t)o * (nb + 1) + nb) * P.n_in + i] = s.wb[e];
                     P.Wb[(size_t)o * P.n_in + i] = s.wb[e];
                 }
+            if (naive()) {
+                P.Wrow.assign((size_t)s.n_out * P.n_in * nb, 0.0);
+                for (int o = 0; o < s.n_out; o++)
+                    for (int i = 0; i < P.n_in; i++)
+                        for (int m = 0; m < nb; m++)
+                            P.Wrow[((size_t)o * P.n_in + i) * nb + m] = s.ws[(size_t)o * s.n_in + P.lo + i] *
+                                                                        s.c[((size_t)o * s.n_in + P.lo + i) * nb + m];
+            }
             L.parts.push_back(std::move(P));
         }
         // a hidden layer's input repeats every n_blk slots, so its whole block
@@ -118,6 +151,14 @@ Model::Model(Ctx *c, const he_kan_desc *d, bool refresh_) : ctx(c), refresh(refr
             if (li == 0)
                 for (int j = 1; j <= clog2i(L.g + 2 * L.k); j++) st.push_back(-P.n_blk * (1l << (j - 1)));
             st.push_back(P.n_blk);
+            if (naive()) {
+                const PermPlan pp = perm_plan(L, P, S, slots);
+                for (long o : pp.off) {
+                    const long g = floordiv(o, pp.b1), b = o - g * pp.b1;
+                    if (b) st.push_back(b);
+                    if (g) st.push_back(g * pp.b1);
+                }
+            }
         }
         const long D = L.d * S;
         int b1 = 1 << ((clog2i(L.d) + 1) / 2);
@@ -503,6 +544,71 @@ struct Eval {
         return z;
     }
 
+    // the naive method's permutation of the bases b into row order at level t
+    // (zeros outside the n_in (g+k) S destinations): diagonal method with
+    // baby-step giant-step rotations, one plaintext per distinct offset,
+    // z = sum_g rot(sum_b rot(diag_(g b1 + b), -g b1) * rot(b, b), g b1)
+    Ct permute(const Ct &x, const LayerC &L, const Part &P, int t, const std::string &tag)
+    {
+        const long slots = c.N / 2;
+        const PermPlan pp = perm_plan(L, P, m.S, slots);
+        std::map<long, std::map<long, std::vector<long>>> groups;  // giant -> baby -> destinations
+        for (size_t k2 = 0; k2 < pp.off.size(); k2++) {
+            const long g = floordiv(pp.off[k2], pp.b1);
+            groups[g][pp.off[k2] - g * pp.b1].push_back(pp.dst[k2]);
+        }
+        std::vector<long> babies;
+        for (auto &gg : groups)
+            for (auto &bb : gg.second) babies.push_back(bb.first);
+        std::sort(babies.begin(), babies.end());
+        babies.erase(std::unique(babies.begin(), babies.end()), babies.end());
+        Ct xd = c.mod_drop(x, t + 1);
+        auto full_key = [&](long g, long b) {
+            return tag + "g" + std::to_string(g) + "b" + std::to_string(b) + "|" + std::to_string(t) + "|" +
+                   std::to_string(xd.level);
+        };
+        // the diagonals not cached yet, encoded together (host encodings in parallel)
+        {
+            std::vector<std::string> keys;
+            std::vector<std::vector<double>> dvs;
+            for (auto &gg : groups)
+                for (auto &bb : gg.second) {
+                    const std::string fk = full_key(gg.first, bb.first);
+                    if (m.pt_cache.count(fk)) continue;
+                    std::vector<double> dv(slots, 0.0);
+                    for (long d : bb.second) dv[(size_t)(((d + gg.first * pp.b1) % slots + slots) % slots)] = 1.0;
+                    keys.push_back(fk);
+                    dvs.push_back(std::move(dv));
+                }
+            std::vector<const std::vector<double> *> zp;
+            for (auto &v : dvs) zp.push_back(&v);
+            if (!zp.empty()) {
+                std::vector<Pt> pts = c.vec_pts(zp, X(t, xd.level), t + 2);
+                for (size_t i = 0; i < pts.size(); i++) m.pt_cache.emplace(keys[i], pts[i]);
+            }
+        }
+        std::vector<Ct> rots = c.rotate_many(xd, babies, k);
+        Ct z;
+        bool have = false;
+        for (auto &gg : groups) {
+            const long g = gg.first;
+            std::vector<std::pair<const Ct *, const Pt *>> terms;
+            for (auto &bb : gg.second) {
+                const Pt *pt = &m.pt_cache.at(full_key(g, bb.first));
+                const size_t bi = std::lower_bound(babies.begin(), babies.end(), bb.first) - babies.begin();
+                terms.push_back({&rots[bi], pt});
+            }
+            Ct inner = c.lincomb(terms, t);
+            if (!have) {
+                z = g ? c.rotate(inner, g * pp.b1, k) : inner;
+                have = true;
+            } else {
+                z = g ? c.rotate_add(inner, g * pp.b1, z, k) : c.add(z, inner);
+            }
+        }
+        return z;
+    }
+
     // z <- z + rot(z, s) for s = period/2, ..., d
     Ct fold(Ct z, long d, long period)
     {
@@ -541,6 +647,17 @@ struct Eval {
             return {matvec(z, SlotMatrix{P.W, L.n_out, nb + 1, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "W")};
         }
         Ct s = cheb_eval(x, L.silu, L.silu_lo, L.silu_hi, nullptr, tag + "S");
+        if (m.naive()) {
+            // no lazy combination: the bases permuted into row order, then W'
+            if (b.level < 1) throw HeError(-3, "layer does not fit the level budget");
+            Ct bp = permute(b, L, P, b.level - 1, tag + "P");
+            const int t = std::min(bp.level, s.level) - 1;
+            if (t < 0) throw HeError(-3, "layer does not fit the level budget");
+            const long nq = (long)P.n_in * nb;
+            Ct zr = matvec(bp, SlotMatrix{P.Wrow, L.n_out, 1, nq, nq * m.S, m.S}, L.d, t, L.period, tag + "Wr");
+            Ct zb = matvec(s, SlotMatrix{P.Wb, L.n_out, 1, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "Wb");
+            return {zr, zb};
+        }
         int t = std::min(b.level, s.level) - 1;
         if (t < 0) throw HeError(-3, "layer does not fit the level budget");
         Ct zf = matvec(b, SlotMatrix{P.Wf, L.n_out, nb, P.n_in, P.n_blk, m.S}, L.d, t, L.period, tag + "Wf");

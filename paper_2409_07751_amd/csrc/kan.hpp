@@ -20,6 +20,9 @@ struct Part {
     // the same weights as two matrices (the paper's two products):
     // n_out x (g+k) x n_in for W_f and n_out x 1 x n_in for W_b
     std::vector<double> Wf, Wb;
+    // without lazy combination: W' in row order, n_out x (n_in (g+k)),
+    // column i (g+k) + m = w_s[o][i] c[o][i][m]
+    std::vector<double> Wrow;
 };
 
 struct LayerC {
@@ -43,6 +46,7 @@ struct Model {
     bool shared_cmp() const { return (circ & HE_CIRCUIT_SHARED_COMPARISON) != 0; }
     bool fused() const { return (circ & HE_CIRCUIT_FUSED_LINEAR) != 0; }
     bool folded() const { return (circ & HE_CIRCUIT_FOLDED_PERIOD) != 0; }
+    bool naive() const { return (circ & HE_CIRCUIT_NAIVE_PERMUTATION) != 0; }
     std::vector<LayerC> layers;
     std::vector<long> steps;
     std::unordered_map<std::string, Pt> pt_cache;   // Montgomery NTT plaintexts for lincombs
@@ -50,6 +54,16 @@ struct Model {
     Model(Ctx *c, const he_kan_desc *d, bool refresh);
     size_t n_inputs() const { return layers[0].parts.size(); }
 };
+
+// The naive method's permutation of one part's bases: slot (i (g+k) + m) S + s
+// receives slot m n_blk + i S + s; off[k] is the signed offset src - dst of
+// destination dst[k] (in (-N/4, N/4]), b1 the baby-step width (the power of
+// two >= sqrt(2 max|off| + 1)); an offset o = g b1 + b, g = floor(o / b1).
+struct PermPlan {
+    std::vector<long> dst, off;
+    long b1;
+};
+PermPlan perm_plan(const LayerC &L, const Part &P, long S, long slots);
 
 // in: one ciphertext per part of the layer (the first layer's feature
 // chunks, or the previous layer's output)

@@ -24,7 +24,8 @@ class HeError(RuntimeError):
 class he_params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_int32), ("levels", ctypes.c_int32), ("scale_bits", ctypes.c_int32),
                 ("base_bits", ctypes.c_int32), ("special_count", ctypes.c_int32),
-                ("special_bits", ctypes.c_int32), ("digit_width", ctypes.c_int32), ("sigma", ctypes.c_double)]
+                ("special_bits", ctypes.c_int32), ("digit_width", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("integer_words", ctypes.c_int32)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -49,6 +50,7 @@ class he_kan_desc(ctypes.Structure):
 CIRCUIT_PAPER = 0
 CIRCUIT_SHARED_COMPARISON, CIRCUIT_FUSED_LINEAR, CIRCUIT_FOLDED_PERIOD = 1, 2, 4
 CIRCUIT_RESTRUCTURED = 7
+CIRCUIT_NAIVE_PERMUTATION = 8
 
 
 _lib = None
@@ -63,6 +65,8 @@ _SIGS = {
     "he_ctx_autotune": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                         ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "he_ctx_set_keyswitch": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "he_ctx_bench_keyswitch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, _dp],
     "he_graph_capture_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
     "he_graph_launch": [ctypes.c_void_p],
@@ -145,9 +149,10 @@ class Context:
     """RNS-CKKS context on the current HIP device (see he_params)."""
 
     def __init__(self, log_n, levels, scale_bits, special_count, digit_width, base_bits=60, special_bits=60,
-                 sigma=3.2, stream=None):
+                 sigma=3.2, stream=None, integer_words=False):
         self.lib = lib()
-        p = he_params(log_n, levels, scale_bits, base_bits, special_count, special_bits, digit_width, sigma)
+        p = he_params(log_n, levels, scale_bits, base_bits, special_count, special_bits, digit_width, sigma,
+                      1 if integer_words else 0)
         h = ctypes.c_void_p()
         rc = self.lib.he_ctx_create(ctypes.byref(p), ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
         if rc != HE_OK:
@@ -190,6 +195,14 @@ class Context:
         n = ctypes.c_size_t()
         self.check(self.lib.he_ctx_autotune(self.h, _ek(keys), batch, reps, choice, self.L + 1, ctypes.byref(n)))
         return [int(choice[i]) for i in range(n.value)]
+
+    def bench_keyswitch(self, keys, step, level, batch, reps=5):
+        """he_ctx_bench_keyswitch: median ms of one key switch of `batch`
+        ciphertexts at `level` (step 0: relinearisation with its rescale;
+        otherwise a rotation by `step`)."""
+        ms = ctypes.c_double()
+        self.check(self.lib.he_ctx_bench_keyswitch(self.h, _ek(keys), step, level, batch, reps, ctypes.byref(ms)))
+        return ms.value
 
     def set_keyswitch(self, level, batch, config):
         self.check(self.lib.he_ctx_set_keyswitch(self.h, level, batch, config))

@@ -15,6 +15,7 @@ The engine interface (`run_layer`, `working_bytes`) is implemented by
 `GpuEngine` over the C ABI; tests substitute a host-only engine to check the
 scheduler.
 """
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -31,6 +32,7 @@ class Request:
     admitted: float = None
     done: float = None
     batches: list = field(default_factory=list)  # batch sizes this request ran in
+    engine: int = 0          # the engine (context) its ciphertext lives in
 
 
 class GpuEngine:
@@ -128,11 +130,103 @@ class Server:
         return self.finished
 
 
-def latency_report(finished):
-    lat = np.array([r.done - r.arrival for r in finished])
-    span = max(r.done for r in finished) - min(r.arrival for r in finished)
-    sizes = [b for r in finished for b in r.batches]
-    return {"requests": len(finished), "inferences_per_s": round(len(finished) / span, 4),
+class ConcurrentServer:
+    """The same scheduling over several engines, each with its own context,
+    HIP stream and resident copy of the evaluation keys, driven by one host
+    thread each: a request is bound to the engine its ciphertext was
+    encrypted in (`Request.engine`); every thread repeatedly runs the oldest
+    (model, layer) group of its own requests as one batch and waits for its
+    own stream only, so groups on different engines overlap on the device
+    (the library releases the interpreter lock inside every call).
+    Admission is shared: one FIFO and one HBM budget for all engines, a
+    request entering as soon as memory frees up anywhere."""
+
+    def __init__(self, engines, hbm_budget, max_batch=16):
+        self.engines, self.budget, self.max_batch = list(engines), hbm_budget, max_batch
+        self.waiting, self.finished = [], []
+        self.active = [[] for _ in self.engines]
+        self.in_use = 0
+        self.trace = []  # (time, engine, model, layer, batch size)
+        self.cv = threading.Condition()
+        self.error = None
+
+    def _admit(self, now):
+        while self.waiting and self.waiting[0].arrival <= now:
+            r = self.waiting[0]
+            need = self.engines[r.engine].working_bytes(r.model)
+            if any(self.active) and self.in_use + need > self.budget:
+                break
+            self.waiting.pop(0)
+            r.admitted = now
+            self.in_use += need
+            self.active[r.engine].append(r)
+
+    def _worker(self, e, now_fn):
+        eng = self.engines[e]
+        try:
+            while True:
+                with self.cv:
+                    while True:
+                        if self.error is not None:
+                            return
+                        self._admit(now_fn())
+                        if self.active[e]:
+                            break
+                        if not self.waiting and not any(self.active):
+                            self.cv.notify_all()
+                            return
+                        # sleep until the next arrival, or (nothing left to arrive, or the
+                        # head of the queue waiting for memory) until another engine finishes
+                        nxt = self.waiting[0].arrival - now_fn() if self.waiting else None
+                        self.cv.wait(timeout=None if nxt is None or nxt <= 0 else nxt + 1e-4)
+                    act = self.active[e]
+                    oldest = min(act, key=lambda r: (r.arrival, r.rid))
+                    group = sorted((r for r in act if r.model == oldest.model and r.layer == oldest.layer),
+                                   key=lambda r: (r.arrival, r.rid))
+                    batch = group[: self.max_batch]
+                outs = eng.run_layer(oldest.model, oldest.layer, [r.ct for r in batch])
+                eng.sync()
+                with self.cv:
+                    t = now_fn()
+                    self.trace.append((t, e, oldest.model, oldest.layer, len(batch)))
+                    for r, o in zip(batch, outs):
+                        r.ct = o
+                        r.layer += 1
+                        r.batches.append(len(batch))
+                        if r.layer == eng.n_layers(r.model):
+                            r.done = t
+                            act.remove(r)
+                            self.in_use -= eng.working_bytes(r.model)
+                            self.finished.append(r)
+                    self.cv.notify_all()
+        except BaseException as ex:  # stop every worker, re-raised by run()
+            with self.cv:
+                self.error = ex
+                self.cv.notify_all()
+
+    def run(self, requests):
+        t0 = time.perf_counter()
+        now_fn = lambda: time.perf_counter() - t0
+        self.waiting = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        th = [threading.Thread(target=self._worker, args=(e, now_fn)) for e in range(len(self.engines))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        if self.error is not None:
+            raise self.error
+        return self.finished
+
+
+def latency_report(finished, skip=0):
+    """Per-request latency (arrival to completion) and throughput; `skip`
+    leaves out the first requests by arrival (the warm-up before a steady
+    state), both from the percentiles and from the throughput window."""
+    fin = sorted(finished, key=lambda r: (r.arrival, r.rid))[skip:]
+    lat = np.array([r.done - r.arrival for r in fin])
+    span = max(r.done for r in fin) - min(r.arrival for r in fin)
+    sizes = [b for r in fin for b in r.batches]
+    return {"requests": len(fin), "inferences_per_s": round(len(fin) / span, 4),
             "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
             "mean_batch": round(float(np.mean(sizes)), 2), "span_s": round(span, 3)}

@@ -17,7 +17,8 @@ their shapes and value ranges):
   cifar   same parameters, KAN [3072,128,10] on 32x32x3 images (the CIFAR-10
           shape), pixels U[0,1];
   toy     the tiny parameters, KAN [2,3,1] with g=2, k=1 (the grid of the
-          paper's toy example of the basis construction).
+          paper's toy example of the basis construction);
+  tiny16  the tiny KAN [2,5,1] at the image parameters (uneven-shape mix).
 Seeds: weights 1, inputs 2, keygen 3, encryption 4, arrivals 5, calibration 6.
 """
 from dataclasses import dataclass, field
@@ -61,6 +62,10 @@ WORKLOADS = {
     # three 8-level layers, f_3 with 1/(2R) folded (R is small on [-1, 1])
     "formula16": Workload("formula16", 16, 24, 45, 4, 5, (4, 10, 10, 1), 10, 3, (-1.0, 1.0), 27, None,
                           ((7,), (7,), (7,)), 0.3, 0.1, "uniform_pm1", False, False),
+    # the [2,5,1] tiny KAN at the image parameters (the batched mix of uneven
+    # shapes): two 7-level layers fit the 24 levels without a refresh
+    "tiny16": Workload("tiny16", 16, 24, 45, 4, 5, (2, 5, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
+                       ((3,), (3,)), 0.3, 0.1, "uniform_pm1", False, False),
     "image": Workload("image", 16, 24, 45, 4, 5, (784, 64, 10), 8, 3, (0.0, 1.0), 31, None,
                       ((7, 7), (7, 7)), 0.05, 0.05, "pixels255"),
     "cifar": Workload("cifar", 16, 24, 45, 4, 5, (3072, 128, 10), 8, 3, (0.0, 1.0), 31, None,

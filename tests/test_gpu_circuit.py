@@ -19,7 +19,8 @@ from paper_2409_07751_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-# he_kan_desc.circuit bits: 1 shared comparison, 2 fused linear layers, 4 folded period
+# he_kan_desc.circuit bits: 1 shared comparison, 2 fused linear layers, 4 folded period,
+# 8 no lazy combination (the naive permutation)
 VARIANTS = [0, 1, 2, 4, 7]
 
 
@@ -29,7 +30,7 @@ def note(*a):
 
 
 def oracle_circuit(flags):
-    return circuit.Circuit(bool(flags & 1), bool(flags & 2), bool(flags & 4))
+    return circuit.Circuit(bool(flags & 1), bool(flags & 2), bool(flags & 4), bool(flags & 8))
 
 
 def model_layers(wl):
@@ -94,3 +95,10 @@ def test_toy_two_polycomp_branch_bit_exact(hk):
     # the first layer cannot share the comparison: 4 copies < g+2k+1 = 5 blocks
     assert (1 << (wl.g + 2 * wl.k - 1).bit_length()) < wl.g + 2 * wl.k + 1
     run_variants(hk, "toy", [0, 7])
+
+
+def test_toy_without_lazy_combination_bit_exact(hk):
+    """The comparison method of the paper's basis experiments (bit 8: the
+    bases permuted into row order by a homomorphic permutation, then W'),
+    alone and with the shared comparison, bit-exact against the oracle."""
+    run_variants(hk, "toy", [8, 9])

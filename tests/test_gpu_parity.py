@@ -471,3 +471,40 @@ def test_kan_image_residues_equal_oracle(image):
                 (name, li)
         y = ctx.decrypt(keys, ct, 10)
         assert np.abs(y - kan.he_friendly_kan(x[None], layers)[0]).max() < 1e-2
+
+
+@pytest.mark.timeout(900)
+def test_integer_words_give_the_same_residues(hk, tiny):
+    """With every prime on 64-bit integer words (he_params.integer_words, the
+    exact FP64 path off): the N = 2^13 ops at levels 7, 3, 1 and 0 are
+    bit-exact against the oracle, and the first [784,64,10] layer at
+    N = 2^16 has the oracle's residues (the same digest as with FP64)."""
+    import hashlib
+    import json
+    import os
+    wl, _, octx = tiny
+    ctx = hk.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w, integer_words=True)
+    try:
+        steps = [1, 2, -1, -5, 7, 1024]
+        keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+        ops_bit_exact(ctx, octx, keys, O.Keys(octx, synth.SEED_KEYGEN, steps), (wl.L, 3, 1))
+    finally:
+        ctx.close()
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "image_digests.json")))
+    wi = synth.WORKLOADS["image"]
+    layers = kan.compile_model(synth.raw_weights(wi), synth.calibration_inputs(wi, 1024), [wi.silu_degree] * 2,
+                               [list(c) for c in wi.comp_degrees], wi.grid, prescale=wi.prescale)
+    ctx = hk.Context(wi.logN, wi.L, wi.scale_bits, wi.alpha, wi.w, integer_words=True)
+    try:
+        model = ctx.compile(layers)
+        want = golden["restructured"]
+        assert model.rotation_steps() == want["steps"]
+        keys = ctx.keygen(synth.SEED_KEYGEN, want["steps"])
+        note("image layer 0 on integer words")
+        out = ctx.eval_kan_layer(model, keys, 0, ctx.encrypt(keys, synth.inputs(wi, 1)[0], synth.SEED_ENC))
+        e = out.export()
+        assert out.level == want["layers"][0]["level"]
+        assert hashlib.sha256(np.ascontiguousarray(e.astype("<u8")).tobytes()).hexdigest() == \
+            want["layers"][0]["sha256"]
+    finally:
+        ctx.close()

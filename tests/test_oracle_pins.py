@@ -653,3 +653,96 @@ def test_image_digests_golden_matches_the_circuit():
         assert g[name]["steps"] == C.rotation_steps(layers, 1 << (wl.logN - 1), circ=circ)
         assert [l["level"] for l in g[name]["layers"]] == [12, 0]
         assert all(len(l["sha256"]) == 64 and len(l["sampled"]) == len(l["positions"]) for l in g[name]["layers"])
+
+
+# the shapes (n_i, g, k) of the paper's comparison of the basis approximation
+# with and without lazy combination
+TABLE3_SHAPES = [(64, 3, 2), (128, 5, 3), (256, 5, 3), (256, 10, 3), (256, 10, 5)]
+
+
+@pytest.mark.parametrize("n_in,g,k", TABLE3_SHAPES + [(2, 2, 1), (3, 5, 3)])
+@pytest.mark.parametrize("S", [1, 4])
+def test_naive_permutation_moves_coltile_to_row_order(n_in, g, k, S):
+    """The naive method's homomorphic permutation on the slot simulator: a
+    vector in ColTile layout (basis m of input i of vector s in slot
+    m n_blk + i S + s) comes out in row order (slot (i (g+k) + m) S + s),
+    exactly Algorithm 3's P applied to the data, with zeros elsewhere; one
+    ct x pt product per distinct offset and about 2 sqrt(#offsets) rotations."""
+    slots = 1 << 15
+    L = kan.Layer(n_in, 1, g, k, np.zeros(g + 2 * k + 1), np.zeros((1, n_in)), np.zeros((1, n_in)),
+                  np.zeros((1, n_in, g + k)), np.zeros(2), 0.0, 1.0, 1.0)
+    nb = g + k
+    n_blk = n_in * S + (3 if S == 4 else 0)       # a hidden layer's block may be wider than its inputs
+    if nb * n_blk > slots:
+        pytest.skip("does not fit the slots")
+    rng = np.random.default_rng(n_in * 100 + g * 10 + k)
+    B = rng.normal(size=(n_in, nb, S))             # basis m of input i of vector s
+    v = np.zeros(slots)
+    for m in range(nb):
+        for i in range(n_in):
+            v[m * n_blk + i * S:m * n_blk + i * S + S] = B[i, m]
+    sim = SlotSim(slots)
+    out = circuit.permute(sim, SimCt(5, v), L, n_blk, S, 4)
+    want = np.zeros(slots)
+    want[:n_in * nb * S] = B.reshape(-1)           # (i nb + m) S + s
+    assert out.level == 4
+    assert np.array_equal(out.v, want)
+    # the column order of Algorithm 3: vec_row = P vec_col
+    _, off, b1 = circuit.permutation_offsets(L, n_blk, S, slots)
+    n_off = len(set(off.tolist()))
+    assert sim.count["rot"] <= 2 * b1 + 2 * (2 * max(abs(off)) + 1) // b1 + 2
+    assert n_off <= n_in * nb * S
+
+
+NAIVE = circuit.Circuit(naive_permutation=True)
+
+
+@pytest.mark.parametrize("name,nl", [("toy", 2), ("image", 1), ("cifar", 1)])
+def test_naive_circuit_on_simulator_equals_fp64_kan(name, nl):
+    """Without lazy combination (bases permuted into row order, then W') the
+    circuit still computes the HE-friendly network (the image models' first
+    layer: the permutation takes the level the second layer would need),
+    within the level budget, with the rotation steps it declares, and it
+    needs more key switches than the paper's lazy combination."""
+    wl = synth.WORKLOADS[name]
+    layers = compiled_layers(name)[:nl]
+    x = synth.inputs(wl, 1)[0]
+    ks = {}
+    for cname, cc in (("naive", NAIVE), ("paper", circuit.PAPER)):
+        sim = SlotSim(1 << (wl.logN - 1))
+        bounds = circuit.chunk_bounds(layers[0], sim.ctx.p.slots)
+        ct = [sim.fresh(x[lo:hi], wl.L) for lo, hi in zip(bounds[:-1], bounds[1:])]
+        refresh = (lambda c, li: SimCt(wl.L, c.v)) if wl.refresh else None
+        out = circuit.eval_kan(sim, ct, layers, refresh, circ=cc)
+        assert out.level >= 0
+        want = kan.he_friendly_kan(x[None], layers)[0]
+        assert np.abs(out.v[:len(want)] - want).max() < 1e-8 * max(1, np.abs(want).max())
+        assert set(circuit.rotation_steps(layers, sim.ctx.p.slots, circ=cc)) == sim.rot_steps
+        ks[cname] = sim.count["ks"]
+    assert ks["naive"] > ks["paper"]
+
+
+def test_naive_excludes_fused_and_folded():
+    wl = synth.WORKLOADS["toy"]
+    layers = compiled_layers("toy")
+    sim = SlotSim(1 << (wl.logN - 1))
+    with pytest.raises(ValueError):
+        circuit.eval_kan(sim, sim.fresh(np.zeros(2), wl.L), layers, circ=circuit.Circuit(True, True, False, True))
+
+
+def test_oracle_he_kan_toy_naive_matches_lazy():
+    """Encrypted toy inference on the oracle without lazy combination decrypts
+    within 1e-2 of the FP64 circuit and of the lazy-combination run."""
+    wl = synth.WORKLOADS["toy"]
+    layers = compiled_layers("toy", 4096)
+    prm = Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+    ctx = ckks.Context(prm)
+    x = synth.inputs(wl, 1)[0]
+    ys = {}
+    for cname, cc in (("naive", NAIVE), ("paper", circuit.PAPER)):
+        ev = ckks.Oracle(ctx, ckks.Keys(ctx, synth.SEED_KEYGEN, circuit.rotation_steps(layers, prm.slots, circ=cc)))
+        out = circuit.eval_kan(ev, ev.encrypt(x, synth.SEED_ENC), layers,
+                               lambda c, li: ev.encrypt(ev.decrypt(c, prm.slots), 100 + li), circ=cc)
+        ys[cname] = ev.decrypt(out, 1)
+    want = kan.he_friendly_kan(x[None], layers)[0]
+    assert abs(ys["naive"][0] - want[0]) < 1e-2 and abs(ys["naive"][0] - ys["paper"][0]) < 1e-2

@@ -84,3 +84,59 @@ def test_single_request_bigger_than_budget_still_runs_alone():
     eng = FakeEngine(clock, {"a": 1}, {"a": 1.0}, {"a": 500})
     done = Server(eng, hbm_budget=100).run(make(3, clock, ["a"], 0.0), clock=clock)
     assert len(done) == 3 and all(n == 1 for _, _, n in eng.calls)
+
+
+class SleepEngine:
+    """A host-only engine whose layers take real time (the concurrent server
+    runs one thread per engine on the wall clock)."""
+
+    def __init__(self, layers, cost, work):
+        self.layers, self.cost, self.work = layers, cost, work
+        self.calls = []
+
+    def n_layers(self, m):
+        return self.layers[m]
+
+    def run_layer(self, m, layer, cts):
+        import time
+        t0 = time.perf_counter()
+        time.sleep(self.cost[m])
+        self.calls.append((t0, time.perf_counter(), m, layer, len(cts)))
+        return [c + [(m, layer)] for c in cts]
+
+    def sync(self):
+        pass
+
+    def working_bytes(self, m):
+        return self.work[m]
+
+
+def test_concurrent_server_overlaps_engines_under_one_budget():
+    from paper_2409_07751_amd.serve import ConcurrentServer
+    engs = [SleepEngine({"a": 3, "b": 2}, {"a": 0.004, "b": 0.006}, {"a": 10, "b": 20}) for _ in range(2)]
+    reqs = [Request(i, "ab"[i % 2], [], arrival=0.002 * i, engine=(i // 2) % 2) for i in range(24)]
+    srv = ConcurrentServer(engs, hbm_budget=80, max_batch=4)
+    peak = []
+    orig = srv._admit
+
+    def admit(now):
+        orig(now)
+        peak.append(srv.in_use)
+
+    srv._admit = admit
+    done = srv.run(reqs)
+    assert max(peak) <= 80 and max(peak) > 20
+    assert len(done) == 24
+    for r in done:
+        assert r.ct == [(r.model, i) for i in range(engs[r.engine].layers[r.model])]
+        assert r.done >= r.arrival
+    # each engine ran only its own requests, in batches of at most 4
+    for e in engs:
+        assert all(n <= 4 for *_, n in e.calls)
+    assert sum(n for e in engs for *_, n in e.calls) == sum(e.layers[r.model] for r in done for e in engs[:1])
+    # the two engines' layers overlapped in time
+    a, b = engs[0].calls, engs[1].calls
+    assert any(s0 < e1 and s1 < e0 for s0, e0, *_ in a for s1, e1, *_ in b)
+    assert srv.in_use == 0
+    rep = latency_report(done, skip=4)
+    assert rep["requests"] == 20

@@ -63,3 +63,51 @@ def test_served_results_equal_solo_results():
             assert np.abs(y - kan.he_friendly_kan(x[None], layers[n])[0]).max() < 1e-2
     finally:
         ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_concurrent_engines_results_equal_solo_results():
+    """Two engines (contexts with their own stream and keys, one host thread
+    each) serving Poisson arrivals of two models: every request's result has
+    exactly the residues of the same request evaluated alone, and decrypts
+    within 1e-2 of the FP64 circuit."""
+    from paper_2409_07751_amd import hekan
+    from paper_2409_07751_amd.serve import ConcurrentServer
+    wl = synth.WORKLOADS["image"]
+    names = ["formula16", "tiny16"]
+    layers = {n: oracle_layers(n) for n in names}
+    engines = []
+    try:
+        for e in range(2):
+            ctx = hekan.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w)
+            models = {n: ctx.compile(layers[n]) for n in names}
+            steps = sorted(set(s for m in models.values() for s in m.rotation_steps()))
+            note("engine", e, "keygen", len(steps))
+            eng = GpuEngine(ctx, ctx.keygen(synth.SEED_KEYGEN, steps), models)
+            for n in names:
+                eng.calibrate(n, ctx.encrypt(eng.keys, synth.inputs(synth.WORKLOADS[n], 1, stream=12)[0], 998))
+            engines.append(eng)
+        xs = {n: synth.inputs(synth.WORKLOADS[n], 6, stream=13) for n in names}
+        arrivals = synth.poisson_arrivals(60.0, 12)
+        reqs, inputs = [], []
+        for i in range(12):
+            n, e = names[i % 2], (i // 2) % 2
+            x = xs[n][i // 2]
+            eng = engines[e]
+            reqs.append(Request(i, n, eng.ctx.encrypt(eng.keys, x, 300 + i), float(arrivals[i]), engine=e))
+            inputs.append((n, x))
+        budget = 4 * max(engines[0].work.values())
+        note("serving 12 requests on 2 engines, budget", budget)
+        done = ConcurrentServer(engines, budget, max_batch=4).run(reqs)
+        note(latency_report(done))
+        assert len(done) == 12
+        for r in sorted(done, key=lambda r: r.rid):
+            n, x = inputs[r.rid]
+            eng = engines[r.engine]
+            solo = eng.ctx.eval_kan(eng.models[n], eng.keys, eng.ctx.encrypt(eng.keys, x, 300 + r.rid))
+            assert (r.ct.export() == solo.export()).all(), "request %d differs from its solo run" % r.rid
+            y = eng.ctx.decrypt(eng.keys, r.ct, layers[n][-1].n_out)
+            assert np.abs(y - kan.he_friendly_kan(x[None], layers[n])[0]).max() < 1e-2
+    finally:
+        for eng in engines:
+            eng.ctx.close()

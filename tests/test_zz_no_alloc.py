@@ -59,6 +59,13 @@ def test_noalloc_rescale_tiny(hk):
         with pytest.raises(hk.HeError) as e:  # output one level too high
             ctx.rescale_noalloc(a, ctx.import_ct(rand_res(ctx, q, 3, 2), 3))
         assert e.value.code == hk.HE_EINVAL
+        # an output whose memory another ciphertext shares (a rotation by 0 returns its input)
+        keys = ctx.keygen(synth.SEED_KEYGEN, [])
+        o = ctx.import_ct(rand_res(ctx, q, 2, 4), 2)
+        same = ctx.rotate(keys, o, 0)
+        with pytest.raises(hk.HeError) as e:
+            ctx.rescale_noalloc(a, same)
+        assert e.value.code == hk.HE_EINVAL
         z = ctx.import_ct(rand_res(ctx, q, 0, 3), 0)
         with pytest.raises(hk.HeError) as e:  # nothing left to drop
             ctx.rescale_noalloc(z, z)
