@@ -49,7 +49,7 @@ TRAFFIC_SOURCE = "profiles/%s_image_b16_hbm_traffic.md (rocprofv3 FETCH_SIZE + W
 # 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G instructions/s.  Emptied whenever
 # the kernel changes until the counters are taken again.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
-VALU_INSTS_PER_LAUNCH = {}
+VALU_INSTS_PER_LAUNCH = {"ntt_fwd_pass1": 62366602, "ntt_fwd_pass2": 36515880}
 VALU_SOURCE = "profiles/%s_image_b16_valu.md (rocprofv3 SQ_INSTS_VALU)"
 
 
@@ -222,7 +222,7 @@ def silu_fits():
     return out
 
 
-def ks_bench(ctx, keys, wl):
+def ks_bench(ctx, keys, wl, keys_steps):
     """Key switches of B = 1, 8 and 64 ciphertexts sharing one key, at every
     level: the relinearisation of a product (with its rescale, as the library
     runs it) and a rotation by one slot; key switches per second and the
@@ -243,6 +243,23 @@ def ks_bench(ctx, keys, wl):
         out["batch_%d" % B] = row
         log("keyswitch bench B=%d top level: %s keyswitches/s" % (B, {k: v[0] for k, v in row.items()
                                                                       if isinstance(v, list)}))
+    # B = 8 distinct keys: one top-level ciphertext rotated by 8 different steps,
+    # one key switch (one launch sequence) per key
+    from paper_2409_07751_amd import synth
+    steps = [s for s in keys_steps if s > 0][:8]
+    ct = ctx.encrypt(keys, np.zeros(4), synth.SEED_ENC)
+    for s in steps:
+        ctx.rotate(keys, ct, s)
+    ctx.sync()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs = [ctx.rotate(keys, ct, s) for s in steps]
+        del outs
+    ctx.sync()
+    el = time.perf_counter() - t0
+    out["distinct_keys_8_top_level"] = {"rotation_keyswitches_per_s": round(reps * len(steps) / el, 1),
+                                        "steps": steps, "note": "one ciphertext, 8 keys, one key switch each"}
     return out
 
 
@@ -301,7 +318,7 @@ def serve_run(args):
           once, in launches of up to 32 per (model, layer) group."""
     from paper_2409_07751_amd import compile as pc
     from paper_2409_07751_amd import hekan, synth
-    from paper_2409_07751_amd.serve import ConcurrentServer, GpuEngine, Request, latency_report
+    from paper_2409_07751_amd.serve import ConcurrentServer, GpuEngine, Request, hbm_budget, latency_report
 
     names = sorted(set(n for n, _ in SERVE_MIX + MIX64))
     wl0 = synth.WORKLOADS["image"]
@@ -341,7 +358,7 @@ def serve_run(args):
     def saturated(nreq, mix, stream0, max_batch):
         reqs = make(nreq, np.zeros(nreq), mix, stream0)
         t0 = time.perf_counter()
-        done = ConcurrentServer(engines, 96 * 2 ** 30, max_batch=max_batch).run(reqs)
+        done = ConcurrentServer(engines, hbm_budget(engines), max_batch=max_batch).run(reqs)
         span = time.perf_counter() - t0
         out = {"requests": len(done), "inferences_per_s": round(len(done) / span, 3), "span_s": round(span, 3),
                "mean_batch": latency_report(done)["mean_batch"],
@@ -358,18 +375,60 @@ def serve_run(args):
     log("serving mix saturation:", sat)
     rate = 0.7 * sat["inferences_per_s"]
     nreq = args.serve_requests
-    budget = 40 * 2 ** 30
+    budget = hbm_budget(engines)
     reqs = make(nreq, synth.poisson_arrivals(rate, nreq), SERVE_MIX, 100)
     log("serving %d requests at %.1f/s, budget %.1f GiB" % (nreq, rate, budget / 2 ** 30))
     done = ConcurrentServer(engines, budget, max_batch=args.serve_batch).run(reqs)
     rep = latency_report(done, skip=nreq // 10)
     rep.update({"arrival_rate_per_s": round(rate, 3), "saturation_inferences_per_s": sat["inferences_per_s"],
-                "mix": {n: float(p) for n, p in SERVE_MIX}, "hbm_budget_GiB": budget / 2 ** 30,
+                "mix": {n: float(p) for n, p in SERVE_MIX}, "hbm_budget_GiB": round(budget / 2 ** 30, 1),
+                "hbm_budget": "0.8 of the device memory free with every engine's keys resident",
                 "engines": len(engines), "warmup_requests_excluded": nreq // 10,
                 "latency": "per request, arrival to completion",
                 "working_MiB_per_request": {n: round(engines[0].work[n] / 2 ** 20, 1) for n, _ in SERVE_MIX}})
     log("serving:", rep)
     del reqs, done
+
+    # the library's native server (he_submit / he_poll) on engine 0: the same
+    # mix at once, then Poisson arrivals at 0.7 of its saturation
+    eng = engines[0]
+    ctx0 = eng.ctx
+
+    def native(nreq, arrivals, stream0):
+        kinds = synth.request_mix(nreq, [n for n, _ in SERVE_MIX], np.array([p for _, p in SERVE_MIX]),
+                                  seed=synth.SEED_ARRIVALS + stream0)
+        cts = [ctx0.encrypt_input(eng.models[n], eng.keys, synth.inputs(synth.WORKLOADS[n], 1, stream=stream0 + i)[0],
+                                  1000 + 10 * i) for i, n in enumerate(kinds)]
+        ctx0.sync()
+        srv = hekan.NativeServer(ctx0, eng.keys, max_batch=args.serve_batch, hbm_budget=hbm_budget(engines[:1]))
+        t0 = time.perf_counter()
+        tags = []
+        for i, n in enumerate(kinds):
+            dt = arrivals[i] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tags.append(srv.submit(eng.models[n], cts[i]))
+        lat = [srv.poll(t, wait_ms=600000)[1] for t in tags]
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        skip = nreq // 10 if arrivals[-1] > 0 else 0
+        lat = np.array(lat[skip:])
+        return {"requests": nreq, "inferences_per_s": round(nreq / span, 3), "span_s": round(span, 3),
+                "latency_ms_p50": round(float(np.percentile(lat, 50)), 2),
+                "latency_ms_p99": round(float(np.percentile(lat, 99)), 2),
+                "mean_batch": round(st["layer_runs"] / max(1, st["layer_batches"]), 2)}
+
+    native(args.serve_saturation, np.zeros(args.serve_saturation), 3000)
+    nsat = native(args.serve_saturation, np.zeros(args.serve_saturation), 3000)
+    nrate = 0.7 * nsat["inferences_per_s"]
+    nserve = native(args.native_requests, synth.poisson_arrivals(nrate, args.native_requests, seed=synth.SEED_ARRIVALS + 7),
+                    7000)
+    nserve.update({"arrival_rate_per_s": round(nrate, 3), "saturation_inferences_per_s": nsat["inferences_per_s"],
+                   "engines": 1, "latency": "per request, submission to completion (measured by the library)",
+                   "warmup_requests_excluded": args.native_requests // 10})
+    rep["native_server"] = nserve
+    log("native server:", nserve)
 
     log("batched mix of 64 requests of uneven shapes")
     saturated(64, MIX64, 5000, 32)
@@ -469,6 +528,8 @@ def main():
     ap.add_argument("--serve-saturation", type=int, default=96,
                     help="requests of the serving mix present at once to measure its saturation throughput")
     ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--native-requests", type=int, default=300,
+                    help="Poisson arrivals served by the library's native server (he_submit / he_poll)")
     ap.add_argument("--serve-engines", type=int, default=2,
                     help="serving engines (contexts with their own stream and copy of the keys)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -612,6 +673,7 @@ def main():
         "keyswitches_per_inference": ks_per_step / B,
         "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
         "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+        "latency": "per timed step (one batch of all requests; per-request latency: serving)",
         "max_abs_err_vs_fp64_circuit": err,
         "launches_per_step": (c1["launches"] - c0["launches"]) / args.steps,
         "roofline": roof,
@@ -621,7 +683,7 @@ def main():
         res["plain_path"] = plain_path(ctx, model, keys, cts[0], args.plain_steps)
         res["batched_vs_plain"] = round(res["value"] / res["plain_path"]["inferences_per_s"], 3)
     if not args.no_ks_bench:
-        res["keyswitch_bench"] = ks_bench(ctx, keys, wl)
+        res["keyswitch_bench"] = ks_bench(ctx, keys, wl, steps)
     if args.graph_steps:
         res["graph_path"] = [graph_path(ctx, model, keys, c, args.graph_steps, want, wl.shape[-1])
                              for c in (parts[0], parts[0][:1])]

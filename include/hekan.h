@@ -53,7 +53,8 @@ enum {
     HE_ESHAPE = -4,  /* packing impossible: n_in (g+2k) slots exceed N/2       */
     HE_EKEY = -5,    /* a Galois key needed for a rotation was not generated    */
     HE_EDEVICE = -6, /* a HIP call or a kernel launch failed                    */
-    HE_ESTATE = -7   /* handle used with the wrong context or in a bad state    */
+    HE_ESTATE = -7,  /* handle used with the wrong context or in a bad state    */
+    HE_EAGAIN = -8   /* he_poll: the request has not finished yet               */
 };
 
 typedef struct he_ctx he_ctx;
@@ -62,6 +63,7 @@ typedef struct he_secret_key he_secret_key;
 typedef struct he_eval_keys he_eval_keys;
 typedef struct he_ct he_ct;
 typedef struct he_graph he_graph;
+typedef struct he_server he_server;
 
 /*
  * RNS-CKKS parameters (the paper's Experiment Setup fixes N = 2^16 with a
@@ -356,10 +358,43 @@ int he_graph_free(he_graph *g);
 int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *ek, int32_t layer,
                             const he_ct *const *in, size_t n, he_ct **out);
 
+/* Native continuous batching (a project addition; the paper evaluates one
+ * request at a time).  A server owns a worker thread that runs submitted
+ * requests layer by layer on the context's stream: it admits them in
+ * submission order while their models' working memory fits hbm_budget bytes
+ * (a model's first request runs alone, and its peak pool growth is taken as
+ * the model's working memory; the pool's peak counter is reset for that),
+ * then repeatedly evaluates the (model, layer) group of the oldest admitted
+ * request as one batch of up to max_batch requests, so requests submitted
+ * while others run share launches with them.  While a server exists no other
+ * thread may issue work on its context (he_submit and he_poll may be called
+ * from any thread).  he_submit queues one request (in[0..n_in): its input
+ * chunks as for he_eval_kan_chunks, single ciphertexts of the server's
+ * context at one level; the server keeps its own reference, so the caller may
+ * free them) and writes its tag.  he_poll returns HE_OK with the request's
+ * output in *out (a new ciphertext) and the time from submission to
+ * completion in *latency_ms (may be NULL), HE_EAGAIN if it has not finished
+ * within wait_ms milliseconds (0: do not wait), the error code of the failed
+ * evaluation, or HE_EINVAL for a tag that is not pending (never submitted or
+ * already taken).  he_server_stats: requests finished, layer batches run and
+ * the requests they held (mean batch = runs / batches).  he_server_destroy
+ * finishes every submitted request, frees the results not taken, and joins
+ * the worker. */
+int he_server_create(he_ctx *ctx, const he_eval_keys *ek, int32_t max_batch, uint64_t hbm_budget, he_server **out);
+int he_submit(he_server *s, const he_model *m, const he_ct *const *in, size_t n_in, uint64_t *tag);
+int he_poll(he_server *s, uint64_t tag, int32_t wait_ms, he_ct **out, double *latency_ms);
+int he_server_stats(he_server *s, uint64_t *completed, uint64_t *layer_batches, uint64_t *layer_runs);
+int he_server_destroy(he_server *s);
+
 /* Device memory held by the context's pool: bytes in live buffers, bytes
  * cached for reuse, and the peak of live bytes since the last reset
  * (reset_peak != 0 resets it to the current live bytes). */
 int he_ctx_memory(he_ctx *ctx, uint64_t *live, uint64_t *cached, uint64_t *peak, int32_t reset_peak);
+
+/* Free and total device memory of the context's device as the runtime
+ * reports them (hipMemGetInfo); the bytes the context's pool caches count as
+ * used.  For admission budgets. */
+int he_ctx_device_memory(he_ctx *ctx, uint64_t *free_bytes, uint64_t *total_bytes);
 
 /* ------------------------------------------------ individual homomorphic ops */
 

@@ -10,9 +10,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhekan.so")
 
-HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEPTH, HE_ESHAPE, HE_EKEY, HE_EDEVICE, HE_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+HE_OK, HE_EINVAL, HE_ENOMEM, HE_EDEPTH, HE_ESHAPE, HE_EKEY, HE_EDEVICE, HE_ESTATE, HE_EAGAIN = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 _NAMES = {-1: "HE_EINVAL", -2: "HE_ENOMEM", -3: "HE_EDEPTH", -4: "HE_ESHAPE", -5: "HE_EKEY", -6: "HE_EDEVICE",
-          -7: "HE_ESTATE"}
+          -7: "HE_ESTATE", -8: "HE_EAGAIN"}
 
 
 class HeError(RuntimeError):
@@ -105,6 +106,14 @@ _SIGS = {
     "he_eval_kan_layer_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_ctx_memory": [ctypes.c_void_p, _u64p, _u64p, _u64p, ctypes.c_int32],
+    "he_server_create": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
+                         ctypes.POINTER(ctypes.c_void_p)],
+    "he_submit": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t,
+                  ctypes.POINTER(ctypes.c_uint64)],
+    "he_poll": [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), _dp],
+    "he_server_stats": [ctypes.c_void_p, _u64p, _u64p, _u64p],
+    "he_server_destroy": [ctypes.c_void_p],
+    "he_ctx_device_memory": [ctypes.c_void_p, _u64p, _u64p],
     "he_ct_add": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_mul": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.POINTER(ctypes.c_void_p)],
@@ -361,6 +370,12 @@ class Context:
         self.check(self.lib.he_ctx_memory(self.h, *[ctypes.byref(x) for x in v], 1 if reset_peak else 0))
         return {"live": v[0].value, "cached": v[1].value, "peak": v[2].value}
 
+    def device_memory(self):
+        """he_ctx_device_memory: {"free": bytes, "total": bytes} of the device."""
+        f, t = ctypes.c_uint64(), ctypes.c_uint64()
+        self.check(self.lib.he_ctx_device_memory(self.h, ctypes.byref(f), ctypes.byref(t)))
+        return {"free": f.value, "total": t.value}
+
     def eval_kan_batch(self, model, keys, cts):
         n = len(cts)
         flat = self._flat(cts)
@@ -379,6 +394,51 @@ class Context:
         g = ctypes.c_void_p()
         self.check(self.lib.he_graph_capture_kan_batch(self.h, model.h, _ek(keys), arr, n, outs, ctypes.byref(g)))
         return Graph(self, g), [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+class NativeServer:
+    """he_server_*: continuous batching by the library's own worker thread on
+    the context's stream (no other thread may issue work on that context
+    while the server exists)."""
+
+    def __init__(self, ctx, keys, max_batch=16, hbm_budget=(1 << 64) - 1):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = ctypes.c_void_p()
+        ctx.check(self.lib.he_server_create(ctx.h, _ek(keys), max_batch, hbm_budget, ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, model, cts):
+        """One request: its ciphertext, or the list of its input chunks; returns the tag."""
+        cts = list(cts) if isinstance(cts, (list, tuple)) else [cts]
+        arr = (ctypes.c_void_p * len(cts))(*[c.h.value for c in cts])
+        tag = ctypes.c_uint64()
+        self.ctx.check(self.lib.he_submit(self.h, model.h, arr, len(cts), ctypes.byref(tag)))
+        return tag.value
+
+    def poll(self, tag, wait_ms=0):
+        """(output ciphertext, ms from submission to completion), or None if
+        the request has not finished within wait_ms."""
+        out = ctypes.c_void_p()
+        lat = ctypes.c_double()
+        rc = self.lib.he_poll(self.h, tag, wait_ms, ctypes.byref(out), ctypes.byref(lat))
+        if rc == HE_EAGAIN:
+            return None
+        if rc != HE_OK:
+            raise HeError(rc, "request %d failed" % tag)
+        return Ciphertext(self.ctx, out), lat.value
+
+    def stats(self):
+        v = [ctypes.c_uint64() for _ in range(3)]
+        self.ctx.check(self.lib.he_server_stats(self.h, *[ctypes.byref(x) for x in v]))
+        return {"completed": v[0].value, "layer_batches": v[1].value, "layer_runs": v[2].value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.he_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Graph:

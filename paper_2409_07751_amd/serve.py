@@ -218,6 +218,16 @@ class ConcurrentServer:
         return self.finished
 
 
+def hbm_budget(engines, fraction=0.8):
+    """An admission budget from the device itself: `fraction` of the memory
+    not yet in use once every engine's evaluation keys and plaintext caches
+    are resident (the device's free bytes plus the bytes the engines' pools
+    hold for reuse)."""
+    free = engines[0].ctx.device_memory()["free"]
+    cached = sum(e.ctx.memory()["cached"] for e in engines)
+    return int(fraction * (free + cached))
+
+
 def latency_report(finished, skip=0):
     """Per-request latency (arrival to completion) and throughput; `skip`
     leaves out the first requests by arrival (the warm-up before a steady

@@ -1,6 +1,7 @@
 """Write tests/golden/image_digests.json: digests of the oracle's residues for
 the encrypted [784,64,10] inference at N = 2^16 (25 Q limbs, 4 special primes,
-5-limb digits), which the GPU parity test compares against.
+5-limb digits), and for the first layer of [3072,128,10] at the same
+parameters (`--cifar`), which the GPU parity tests compare against.
 
 Runs only the CPU oracle (oracle/) on the seeded synthetic inputs of
 paper_2409_07751_amd.synth; nothing here touches the GPU path.  For each
@@ -10,6 +11,7 @@ little-endian uint64 array [2][level+1][N] (c0 then c1, limb-major), and a
 few sampled residues for diagnosis.  Takes a few minutes per circuit.
 
     python tests/golden/make_image_digests.py [--circuits paper,restructured]
+    python tests/golden/make_image_digests.py --cifar
 """
 import argparse
 import hashlib
@@ -42,10 +44,42 @@ def image_layers(wl):
                              [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
 
 
+def cifar_first_layer(res):
+    """The [3072,128,10] model's first layer at the same parameters, restructured: its input in two
+    ciphertexts (features [0, 2048) and [2048, 3072), encrypted with seeds SEED_ENC and SEED_ENC + 1),
+    both chunks packed, expanded and multiplied by their columns, summed and folded."""
+    wl = synth.WORKLOADS["cifar"]
+    layers = image_layers(wl)
+    octx = O.Context(O.Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w))
+    circ = circuit.RESTRUCTURED
+    steps = circuit.rotation_steps(layers[:1], octx.p.slots, circ=circ)
+    ev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps))
+    x = synth.inputs(wl, 1)[0]
+    bounds = circuit.chunk_bounds(layers[0], octx.p.slots)
+    cts = [ev.encrypt(x[lo:hi], synth.SEED_ENC + c) for c, (lo, hi) in enumerate(zip(bounds[:-1], bounds[1:]))]
+    t0 = time.time()
+    ct, _ = circuit.layer_forward(ev, cts, layers[0], 0, True, circ=circ)
+    pos = [(p, l % (ct.level + 1), n) for p, l, n in SAMPLES]
+    res["cifar"] = {"workload": "cifar: KAN [3072,128,10], first layer, N=2^16, L=24, 4 special primes, 5-limb digits",
+                    "input": "synth.inputs(cifar, 1)[0] in chunks %s, chunk c encrypted with seed SEED_ENC + c" % bounds,
+                    "restructured": {"steps": steps, "bounds": bounds,
+                                     "layers": [{"level": int(ct.level), "sha256": digest(ct), "positions": pos,
+                                                 "sampled": [int((ct.c0, ct.c1)[p][l][n]) for p, l, n in pos]}]}}
+    print("cifar first layer: level %d in %.0f s" % (ct.level, time.time() - t0), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--circuits", default="paper,restructured")
+    ap.add_argument("--cifar", action="store_true", help="only (re)write the [3072,128,10] first-layer digest")
     args = ap.parse_args()
+    if args.cifar:
+        res = json.load(open(OUT))
+        cifar_first_layer(res)
+        with open(OUT, "w") as f:
+            json.dump(res, f, indent=1)
+        print("wrote", OUT)
+        return
     wl = synth.WORKLOADS["image"]
     layers = image_layers(wl)
     octx = O.Context(O.Params(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w))

@@ -508,3 +508,34 @@ def test_integer_words_give_the_same_residues(hk, tiny):
             want["layers"][0]["sha256"]
     finally:
         ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_kan_cifar_first_layer_residues_equal_oracle(image):
+    """The first layer of [3072,128,10] at N = 2^16 with its input in two
+    ciphertexts (2048 + 1024 features), restructured: the output residues
+    equal the oracle's (SHA-256 digest and sampled residues written by
+    tests/golden/make_image_digests.py --cifar, oracle only)."""
+    import hashlib
+    import json
+    import os
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "image_digests.json")))["cifar"]
+    want = golden["restructured"]
+    wl, ctx, octx = image
+    wc = synth.WORKLOADS["cifar"]
+    layers = kan.compile_model(synth.raw_weights(wc), synth.calibration_inputs(wc, 1024), [wc.silu_degree] * 2,
+                               [list(c) for c in wc.comp_degrees], wc.grid, prescale=wc.prescale)
+    model = ctx.compile(layers[:1])
+    assert model.input_chunks() == want["bounds"]
+    assert model.rotation_steps() == want["steps"]
+    keys = ctx.keygen(synth.SEED_KEYGEN, want["steps"])
+    x = synth.inputs(wc, 1)[0]
+    b = want["bounds"]
+    cts = [ctx.encrypt(keys, x[lo:hi], synth.SEED_ENC + c) for c, (lo, hi) in enumerate(zip(b[:-1], b[1:]))]
+    note("cifar first layer, two chunks")
+    out = ctx.eval_kan_layer_batch(model, keys, 0, [cts])[0]
+    e = out.export()
+    w = want["layers"][0]
+    assert out.level == w["level"]
+    assert [int(e[p][l][n]) for p, l, n in w["positions"]] == w["sampled"]
+    assert hashlib.sha256(np.ascontiguousarray(e.astype("<u8")).tobytes()).hexdigest() == w["sha256"]

@@ -640,19 +640,25 @@ def test_packed_vectors_on_simulator_equal_fp64_kan(name, S, circ):
 
 
 def test_image_digests_golden_matches_the_circuit():
-    """The stored oracle digests of the [784,64,10] inference (written by
-    tests/golden/make_image_digests.py) were taken for the circuits the oracle
-    runs now: rotation steps per circuit, levels, well-formed digests."""
+    """The stored oracle digests of the [784,64,10] inference and of the
+    [3072,128,10] first layer (written by tests/golden/make_image_digests.py)
+    were taken for the circuits the oracle runs now: rotation steps per
+    circuit, chunk bounds, levels, well-formed digests."""
     import json
     from oracle import circuit as C
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "image_digests.json")))
     wl = synth.WORKLOADS["image"]
-    layers = kan.compile_model(synth.raw_weights(wl), synth.calibration_inputs(wl, 1024), [wl.silu_degree] * 2,
-                               [list(c) for c in wl.comp_degrees], wl.grid, prescale=wl.prescale)
+    layers = compiled_layers("image", 8)  # the rotation steps depend on the shapes only
     for name, circ in (("paper", C.PAPER), ("restructured", C.RESTRUCTURED)):
         assert g[name]["steps"] == C.rotation_steps(layers, 1 << (wl.logN - 1), circ=circ)
         assert [l["level"] for l in g[name]["layers"]] == [12, 0]
         assert all(len(l["sha256"]) == 64 and len(l["sampled"]) == len(l["positions"]) for l in g[name]["layers"])
+    wc = synth.WORKLOADS["cifar"]
+    lc = compiled_layers("cifar", 8)
+    gc = g["cifar"]["restructured"]
+    assert gc["steps"] == C.rotation_steps(lc[:1], 1 << (wc.logN - 1), circ=C.RESTRUCTURED)
+    assert gc["bounds"] == C.chunk_bounds(lc[0], 1 << (wc.logN - 1)) == [0, 2048, 3072]
+    assert len(gc["layers"]) == 1 and len(gc["layers"][0]["sha256"]) == 64
 
 
 # the shapes (n_i, g, k) of the paper's comparison of the basis approximation
