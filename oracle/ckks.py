@@ -48,7 +48,7 @@ def lib():
             "oc_powm": (u64, [u64, u64, u64]),
             "oc_invm": (u64, [u64, u64]),
             "oc_is_prime": (i32, [u64]),
-            "oc_gen_primes": (i32, [i32, i32, i32, i32, i32, i32, _u64p, _u64p, _dp]),
+            "oc_gen_primes": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, _u64p, _u64p, _dp]),
             "oc_find_psi": (u64, [u64, i32]),
             "oc_ntt_fwd": (None, [_u64p, i32, u64]),
             "oc_ntt_inv": (None, [_u64p, i32, u64]),
@@ -66,11 +66,16 @@ def lib():
             "oc_chacha20_block": (None, [_u32p, u32, _u32p, _u32p]),
             "oc_sample_uniform": (None, [u64, u32, u32, u32, u64, i32, _u64p]),
             "oc_sample_ternary": (None, [u64, u32, u32, u32, i32, _i64p]),
+            "oc_sample_sparse_ternary": (None, [u64, u32, u32, u32, i32, i32, _i64p]),
             "oc_sample_gauss": (None, [u64, u32, u32, u32, d, i32, _i64p]),
             "oc_gauss_table": (None, [d, _u64p]),
             "oc_small_to_rns": (None, [_i64p, _u64p, i32, i32, _u64p]),
             "oc_gen_switch_key": (None, [u64, u32, _u64p, _u64p, i32, i32, i32, _u64p, _u64p, i32, d, _u64p]),
             "oc_encode": (None, [_dp, i32, d, i32, _u64p, i32, _u64p]),
+            "oc_encode_c": (None, [_dp, _dp, i32, d, i32, _u64p, i32, _u64p]),
+            "oc_decode_c": (None, [_u64p, u64, d, i32, i32, _dp, _dp]),
+            "oc_root_table": (None, [i32, _dp, _dp]),
+            "oc_encode_coeff_direct_c": (d, [_dp, _dp, i32, d, i32, u64]),
             "oc_encode_const": (None, [d, d, _u64p, i32, _u64p]),
             "oc_encode_coeffs_dd": (None, [_dp, i32, d, i32, _dp, _dp]),
             "oc_decode": (None, [_u64p, u64, d, i32, i32, _dp]),
@@ -121,7 +126,11 @@ def u64a(x):
 class Params:
     """RNS-CKKS parameter set: ring degree 2^logN, base prime bits, L scale
     primes of scale_bits, alpha special primes, key-switch digits of `w`
-    consecutive Q limbs, Gaussian sigma."""
+    consecutive Q limbs, Gaussian sigma.  boot_levels > 0 makes the top
+    boot_levels primes (the levels a bootstrapping consumes) boot_bits wide,
+    with canonical scales near 2^boot_bits there; h > 0 draws a sparse
+    ternary secret with exactly h non-zero coefficients (uniform ternary
+    otherwise)."""
     logN: int
     L: int
     scale_bits: int
@@ -130,6 +139,9 @@ class Params:
     base_bits: int = 60
     special_bits: int = 60
     sigma: float = 3.2
+    boot_levels: int = 0
+    boot_bits: int = 0
+    h: int = 0
 
     @property
     def N(self):
@@ -138,6 +150,16 @@ class Params:
     @property
     def slots(self):
         return self.N // 2
+
+    @property
+    def top_level(self):
+        """the top computation level (fresh encryptions and bootstrapping
+        results start here)"""
+        return self.L - self.boot_levels
+
+
+# rotation "step" naming the complex conjugation (Galois element 2N - 1)
+STEP_CONJUGATE = -(1 << 31)
 
 
 class Context:
@@ -150,15 +172,18 @@ class Context:
         pp = np.zeros(params.alpha, np.uint64)
         S = np.zeros(params.L + 1, np.float64)
         L.oc_gen_primes(params.logN, params.base_bits, params.L, params.scale_bits, params.alpha,
-                        params.special_bits, P(q), P(pp), P(S))
+                        params.special_bits, params.boot_levels, params.boot_bits, P(q), P(pp), P(S))
         self.q = q
         self.pm = pp
         self.S = S
         self.all_mods = u64a(list(q) + list(pp))
 
     def galois_elt(self, t):
-        """Galois element 5^t mod 2N for a left rotation by t slots."""
+        """Galois element 5^t mod 2N for a left rotation by t slots
+        (2N - 1, the complex conjugation, for STEP_CONJUGATE)."""
         N = self.p.N
+        if t == STEP_CONJUGATE:
+            return 2 * N - 1
         t %= N // 2
         return pow(5, t, 2 * N)
 
@@ -185,7 +210,10 @@ class Keys:
         N = p.N
         L = lib()
         s = np.zeros(N, np.int64)
-        L.oc_sample_ternary(seed, 1, 0, 0, p.logN, P(s))
+        if p.h > 0:
+            L.oc_sample_sparse_ternary(seed, 1, 0, 0, p.logN, p.h, P(s))
+        else:
+            L.oc_sample_ternary(seed, 1, 0, 0, p.logN, P(s))
         self.s_small = s
         ktot = p.L + 1 + p.alpha
         self.s_res = np.zeros((ktot, N), np.uint64)
@@ -229,9 +257,16 @@ class Oracle:
 
     # -- encoding ----------------------------------------------------------
     def encode(self, z, scale, nl):
+        """round(scale tau^-1(z)) over nl limbs; z real or complex"""
         p = self.ctx.p
-        z = np.ascontiguousarray(np.asarray(z, np.float64))
         out = np.zeros((nl, p.N), np.uint64)
+        if np.iscomplexobj(z):
+            re = np.ascontiguousarray(np.real(z), np.float64)
+            im = np.ascontiguousarray(np.imag(z), np.float64)
+            self.lib.oc_encode_c(P(re), P(im), len(re), scale, p.logN, P(self.ctx.all_mods[:nl].copy()), nl,
+                                 P(out))
+            return out
+        z = np.ascontiguousarray(np.asarray(z, np.float64))
         self.lib.oc_encode(P(z), len(z), scale, p.logN, P(self.ctx.all_mods[:nl].copy()), nl, P(out))
         return out
 
@@ -239,6 +274,14 @@ class Oracle:
         out = np.zeros(nl, np.uint64)
         self.lib.oc_encode_const(float(c), scale, P(self.ctx.all_mods[:nl].copy()), nl, P(out))
         return out
+
+    def decode_c(self, c_limb0, scale, nz):
+        """complex slots of a centred limb-0 polynomial"""
+        p = self.ctx.p
+        re = np.zeros(nz, np.float64)
+        im = np.zeros(nz, np.float64)
+        self.lib.oc_decode_c(P(np.ascontiguousarray(c_limb0)), int(self.ctx.q[0]), scale, p.logN, nz, P(re), P(im))
+        return re + 1j * im
 
     def decode(self, c_limb0, scale, nz):
         p = self.ctx.p
@@ -248,10 +291,10 @@ class Oracle:
 
     # -- client side ----------------------------------------------------------
     def encrypt(self, z, seed, level=None):
-        """Secret-key encryption (-a*s + e + m, a) at the top level (the client
-        holds s, as in the paper's threat model)."""
+        """Secret-key encryption (-a*s + e + m, a) at the top computation level
+        (the client holds s, as in the paper's threat model)."""
         ctx, p = self.ctx, self.ctx.p
-        l = p.L if level is None else level
+        l = p.top_level if level is None else level
         nl = l + 1
         m = self.encode(z, ctx.S[l], nl)
         a = np.zeros((nl, p.N), np.uint64)
@@ -269,6 +312,20 @@ class Oracle:
         self.lib.oc_poly_sub(P(er), P(as_), P(c0), nl, p.logN, P(mods))
         self.lib.oc_poly_add(P(c0), P(m), P(c0), nl, p.logN, P(mods))
         return Ciphertext(l, c0, a)
+
+    def phase(self, ct):
+        """c0 + c1*s on limb q0, coefficient form"""
+        p = self.ctx.p
+        q0 = u64a([self.ctx.q[0]])
+        m = np.zeros((1, p.N), np.uint64)
+        self.lib.oc_poly_mul(P(np.ascontiguousarray(ct.c1[:1])), P(np.ascontiguousarray(self.keys.s_res[:1])),
+                             P(m), 1, p.logN, P(q0))
+        self.lib.oc_poly_add(P(m), P(np.ascontiguousarray(ct.c0[:1])), P(m), 1, p.logN, P(q0))
+        return m[0]
+
+    def decrypt_c(self, ct, nz):
+        """complex slots of the decryption"""
+        return self.decode_c(self.phase(ct), self.ctx.S[ct.level], nz)
 
     def decrypt(self, ct, nz):
         """m = c0 + c1*s on limb q0 (|m| < q0/2), then decode at S[level]."""
@@ -330,6 +387,39 @@ class Oracle:
         nl = a.level + 1
         m = self.encode(z, self.ctx.S[a.level], nl)
         return Ciphertext(a.level, self._binop(self.lib.oc_poly_add, a.c0, m, nl), a.c1.copy())
+
+    def mul_i(self, a):
+        """multiply by the monomial X^(N/2): every slot times i (zeta^(5^j N/2)
+        = i because 5^j = 1 mod 4); a negacyclic shift, exact"""
+        N = self.ctx.p.N
+        h = N // 2
+        mods = self.ctx.mods(a.level)[:, None]
+        outs = []
+        for c in (a.c0, a.c1):
+            o = np.empty_like(c)
+            o[:, h:] = c[:, :h]
+            lo = c[:, h:]
+            o[:, :h] = np.where(lo == 0, np.uint64(0), mods - lo)
+            outs.append(o)
+        return Ciphertext(a.level, outs[0], outs[1])
+
+    def mod_raise(self, a):
+        """ModRaise: the residues mod q_0 of a level-0 ciphertext, read as
+        centred integers in (-q_0/2, q_0/2), lifted to every prime of the top
+        level L (the plaintext becomes m + q_0 I for a small integer
+        polynomial I)"""
+        assert a.level == 0
+        p = self.ctx.p
+        q0 = int(self.ctx.q[0])
+        mods = self.ctx.mods(p.L)
+        outs = []
+        for c in (a.c0, a.c1):
+            v = c[0].astype(np.int64)
+            v = np.where(2 * c[0] > np.uint64(q0), v - np.int64(q0), v)
+            o = np.zeros((p.L + 1, p.N), np.uint64)
+            self.lib.oc_small_to_rns(P(np.ascontiguousarray(v)), P(o), p.L + 1, p.logN, P(mods))
+            outs.append(o)
+        return Ciphertext(p.L, outs[0], outs[1])
 
     def mod_drop(self, a, l):
         assert l <= a.level

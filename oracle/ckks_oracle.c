@@ -124,12 +124,15 @@ static u64 nearest_prime(double T, u64 M, const u64 *used, int nused)
  *   q[0]      : largest prime below 2^base_bits;
  *   p[0..a-1] : the next largest primes below 2^special_bits (distinct);
  *   q[L..1]   : chosen top-down so that every level keeps a canonical scale
- *               close to Delta = 2^scale_bits:  S_L = Delta,
- *               q_l = prime nearest (S_l*S_l)/Delta,  S_{l-1} = (S_l*S_l)/q_l.
+ *               close to Delta_l = 2^bits_l:  S_L = Delta_L,
+ *               q_l = prime nearest (S_l*S_l)/Delta_l,  S_{l-1} = (S_l*S_l)/q_l,
+ *               where bits_l = boot_bits for the top n_boot levels (l > L - n_boot,
+ *               the levels a bootstrapping consumes) and scale_bits below;
+ *               the top computation level takes S_{L-n_boot} = 2^scale_bits.
  * Writes S[0..L] (canonical scale of each level).  Returns 0.
  */
 int oc_gen_primes(int logN, int base_bits, int n_scale, int scale_bits, int n_special,
-                  int special_bits, u64 *q, u64 *p, double *S)
+                  int special_bits, int n_boot, int boot_bits, u64 *q, u64 *p, double *S)
 {
     u64 M = 2ULL << logN;
     u64 used[256];
@@ -145,14 +148,15 @@ int oc_gen_primes(int logN, int base_bits, int n_scale, int scale_bits, int n_sp
         used[nused++] = p[i];
         ks--;
     }
-    double delta = ldexp(1.0, scale_bits);
-    double s = delta;
+    int top_c = n_scale - n_boot; /* top computation level */
+    double s = ldexp(1.0, n_boot > 0 ? boot_bits : scale_bits);
     S[n_scale] = s;
     for (int l = n_scale; l >= 1; l--) {
+        double delta = ldexp(1.0, l > top_c ? boot_bits : scale_bits);
         double T = (s * s) / delta;
         q[l] = nearest_prime(T, M, used, nused);
         used[nused++] = q[l];
-        s = (s * s) / (double)q[l];
+        s = (n_boot > 0 && l == top_c + 1) ? ldexp(1.0, scale_bits) : (s * s) / (double)q[l];
         S[l - 1] = s;
     }
     return 0;
@@ -592,6 +596,27 @@ void oc_sample_ternary(u64 seed, u32 purpose, u32 id, u32 sub, int logN, int64_t
 }
 
 /*
+ * Sparse ternary secret: exactly h coefficients in {-1, 1}, the others 0.
+ * Each 32-bit word w of the stream proposes position w mod N (the low logN
+ * bits) with sign w >> 31 (1: -1); a position already taken is skipped.
+ * Requires 0 <= h <= N and logN <= 16 (position and sign bits are disjoint).
+ */
+void oc_sample_sparse_ternary(u64 seed, u32 purpose, u32 id, u32 sub, int logN, int h, int64_t *out)
+{
+    u64 N = 1ULL << logN;
+    memset(out, 0, N * sizeof(int64_t));
+    stream s;
+    stream_init(&s, seed, purpose, id, sub);
+    for (int placed = 0; placed < h;) {
+        u32 w = next32(&s);
+        u64 pos = w & (N - 1);
+        if (out[pos]) continue;
+        out[pos] = (w >> 31) ? -1 : 1;
+        placed++;
+    }
+}
+
+/*
  * Rounded Gaussian, sigma given, truncated to |e| <= 19: 39 thresholds
  * T[i] = floor(2^64 * sum_{k<=i-19} rho(k) / sum rho), rho(k) = exp(-k^2/(2 sigma^2)),
  * T[38] = 2^64-1.  A 64-bit word v maps to e = (first i with v < T[i]) - 19.
@@ -844,6 +869,9 @@ static i128 dd_round(dd v)
     return n;
 }
 
+void oc_encode_c(const double *re, const double *im, int nz, double scale, int logN, const u64 *m, int nl,
+                 u64 *out);
+
 /*
  * Encode real slot values z[0..nz) (the remaining of the N/2 slots are 0) at
  * scale `scale`: m(X) = round(scale * tau^-1(z)), with slot j <-> root
@@ -851,15 +879,27 @@ static i128 dd_round(dd v)
  */
 void oc_encode(const double *z, int nz, double scale, int logN, const u64 *m, int nl, u64 *out)
 {
+    oc_encode_c(z, NULL, nz, scale, logN, m, nl, out);
+}
+
+/* Complex slots z_j = re[j] + i im[j] (im may be NULL: real slots): the value
+ * at root zeta^(5^j) is z_j and at its conjugate root conj(z_j), so the
+ * coefficients are real. */
+void oc_encode_c(const double *re, const double *im, int nz, double scale, int logN, const u64 *m, int nl,
+                 u64 *out)
+{
     u64 N = 1ULL << logN, twoN = 2 * N;
     cdd *roots = make_roots(N);
     cdd *A = calloc(N, sizeof(cdd));
     u64 e = 1;
     for (u64 j = 0; j < N / 2; j++) {
-        double v = j < (u64)nz ? z[j] : 0.0;
+        double v = j < (u64)nz ? re[j] : 0.0;
+        double w = (im && j < (u64)nz) ? im[j] : 0.0;
         u64 k = (e - 1) / 2, kc = (twoN - e - 1) / 2;
         A[k].re = dd_from(v);
+        A[k].im = dd_from(w);
         A[kc].re = dd_from(v);
+        A[kc].im = dd_from(-w);
         e = (e * 5) % twoN;
     }
     /* B_i = sum_k A_k omega^(-ik),  m_i = Re(B_i zeta^-i) * scale / N */
@@ -960,6 +1000,65 @@ double oc_encode_coeff_direct(const double *z, int nz, double scale, int logN, u
         u64 ang = (u64)(((u128)i * e) % twoN);
         cdd r = root_pow(ang, N);
         acc = dd_add(acc, dd_mul_d(r.re, v));
+        e = (e * 5) % twoN;
+    }
+    acc = dd_mul_d(acc, 2.0 * scale / (double)N);
+    return acc.hi + acc.lo;
+}
+
+/* Decode to complex slots: re[j] + i im[j] = m(zeta^(5^j)) / scale, j < nz. */
+void oc_decode_c(const u64 *c, u64 q0, double scale, int logN, int nz, double *re, double *im)
+{
+    u64 N = 1ULL << logN, twoN = 2 * N;
+    cdd *roots = make_roots(N);
+    cdd *A = calloc(N, sizeof(cdd));
+    for (u64 i = 0; i < N; i++) {
+        int64_t v = c[i] > q0 / 2 ? -(int64_t)(q0 - c[i]) : (int64_t)c[i];
+        double hi = (double)v;
+        double lo = (double)(v - (int64_t)hi);
+        dd m = {hi, lo};
+        A[i].re = dd_mul(m, roots[i].re);
+        A[i].im = dd_mul(m, roots[i].im);
+    }
+    cdd_dft(A, N, +1, roots);
+    u64 e = 1;
+    for (int j = 0; j < nz; j++) {
+        cdd v = A[(e - 1) / 2];
+        re[j] = (v.re.hi + v.re.lo) / scale;
+        im[j] = (v.im.hi + v.im.lo) / scale;
+        e = (e * 5) % twoN;
+    }
+    free(A);
+    free(roots);
+}
+
+/* zeta^e (zeta = exp(i pi / N)) for every e < 2N, each part rounded to the
+ * nearest double (from its double-double value). */
+void oc_root_table(int logN, double *re, double *im)
+{
+    u64 N = 1ULL << logN;
+    for (u64 e = 0; e < 2 * N; e++) {
+        cdd r = root_pow(e, N);
+        re[e] = r.re.hi + r.re.lo;
+        im[e] = r.im.hi + r.im.lo;
+    }
+}
+
+/* direct O(N) evaluation of one encoder coefficient for complex slots:
+ * (2 scale / N) sum_j (re_j cos(pi a_j / N) + im_j sin(pi a_j / N)),
+ * a_j = i 5^j mod 2N (the real part of (2/N) sum_j z_j zeta^(-i 5^j)) */
+double oc_encode_coeff_direct_c(const double *re, const double *im, int nz, double scale, int logN, u64 i)
+{
+    u64 N = 1ULL << logN, twoN = 2 * N;
+    dd acc = dd_from(0.0);
+    u64 e = 1;
+    for (u64 j = 0; j < N / 2; j++) {
+        if (j < (u64)nz) {
+            u64 ang = (u64)(((u128)i * e) % twoN);
+            cdd r = root_pow(ang, N);
+            acc = dd_add(acc, dd_mul_d(r.re, re[j]));
+            acc = dd_add(acc, dd_mul_d(r.im, im[j]));
+        }
         e = (e * 5) % twoN;
     }
     acc = dd_mul_d(acc, 2.0 * scale / (double)N);

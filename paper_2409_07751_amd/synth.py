@@ -19,6 +19,7 @@ their shapes and value ranges):
   toy     the tiny parameters, KAN [2,3,1] with g=2, k=1 (the grid of the
           paper's toy example of the basis construction);
   tiny16  the tiny KAN [2,5,1] at the image parameters (uneven-shape mix).
+Bootstrappable parameter sets (BOOTSETS) carry their own chains.
 Seeds: weights 1, inputs 2, keygen 3, encryption 4, arrivals 5, calibration 6.
 """
 from dataclasses import dataclass, field
@@ -80,6 +81,52 @@ WORKLOADS = {
     "tinychunk": Workload("tinychunk", 13, 7, 40, 1, 1, (384, 4, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
                           ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True, False),
 }
+
+
+@dataclass(frozen=True)
+class BootSet:
+    """A bootstrappable parameter set: computation levels 1..Lc with primes
+    of scale_bits under boot_levels primes of boot_bits (the levels a
+    bootstrapping consumes), a sparse ternary secret of Hamming weight h, and
+    the bootstrapping's shape: stage groups (levels) of CoeffToSlot and
+    SlotToCoeff, EvalMod's input range [-K, K], r double-angle steps and the
+    degree of its cosine series."""
+    name: str
+    logN: int
+    Lc: int
+    boot_levels: int
+    scale_bits: int
+    boot_bits: int
+    alpha: int
+    w: int
+    h: int
+    cts: int
+    stc: int
+    K: float
+    r: int
+    degree: int
+    base_bits: int = 60
+    special_bits: int = 60
+    sigma: float = 3.2
+
+    @property
+    def L(self):
+        return self.Lc + self.boot_levels
+
+
+# boot11: N=2^11, 60 + 2x45 + 14x58 bits, 2 special primes, 2-limb digits,
+#   h = 32 (|I| <= 12 holds with margin: std sqrt(33/12) = 1.7);
+# boot16: N=2^16, 60 + 10x45 + 17x58 bits, 4 special primes, 4-limb digits,
+#   h = 192 (|I| <= 32 is 8 standard deviations of sqrt(193/12) = 4.0)
+BOOTSETS = {
+    "boot11": BootSet("boot11", 11, 2, 14, 45, 58, 2, 2, 32, 2, 2, 12.0, 4, 23),
+    "boot16": BootSet("boot16", 16, 10, 17, 45, 58, 4, 4, 192, 3, 3, 32.0, 5, 31),
+}
+
+
+def boot_inputs(bs: BootSet, n, stream=0):
+    """n real slot vectors (all N/2 slots) with values U[-1, 1]."""
+    return _rng(SEED_INPUTS, 100 + stream).uniform(-1.0, 1.0, (n, 1 << (bs.logN - 1)))
 
 
 def _rng(*key):
