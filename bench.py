@@ -444,6 +444,85 @@ def serve_run(args):
 TABLE3_SHAPES = ((64, 3, 2), (128, 5, 3), (256, 5, 3), (256, 10, 3), (256, 10, 5))
 
 
+def boot_bench(args):
+    """CKKS bootstrapping at N = 2^16 (the boot16 parameter set): ms per refresh
+    of one ciphertext and refreshes/s in batches, its key switches and levels,
+    the decrypted error, and the [4,10,10,1] formula KAN with a bootstrapping
+    between layers (the whole inference on the server) against the FP64
+    circuit."""
+    from paper_2409_07751_amd import compile as pc
+    from paper_2409_07751_amd import hekan, synth
+    bs = synth.BOOTSETS["boot16"]
+    ctx = hekan.Context(bs.logN, bs.L, bs.scale_bits, bs.alpha, bs.w, base_bits=bs.base_bits,
+                        special_bits=bs.special_bits, sigma=bs.sigma, boot_levels=bs.boot_levels,
+                        boot_bits=bs.boot_bits, hamming_weight=bs.h)
+    plan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree))
+    wl = synth.WORKLOADS["formula16"]
+    raw = synth.raw_weights(wl)
+    layers = pc.compile_kan(raw, synth.calibration_inputs(wl, 1024), wl.silu_degree,
+                            [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+    model = ctx.compile(layers, refresh=True, circuit=hekan.CIRCUIT_RESTRUCTURED)
+    t0 = time.time()
+    keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(plan.rotation_steps()) | set(model.rotation_steps())))
+    ctx.sync()
+    log("bootstrapping: keygen %.1fs" % (time.time() - t0))
+    B = args.boot_batch
+    z = synth.boot_inputs(bs, B)
+    cts = [ctx.encrypt(keys, z[i], synth.SEED_ENC + i) for i in range(B)]
+    t0 = time.time()
+    out = ctx.bootstrap(plan, keys, cts[0])
+    ctx.sync()
+    first = time.time() - t0
+    err = float(np.abs(ctx.decrypt(keys, out, z.shape[1]) - z[0]).max())
+    k0 = ctx.counters()["keyswitches"]
+    ctx.sync()
+    t0 = time.time()
+    for _ in range(args.boot_reps):
+        out = ctx.bootstrap(plan, keys, cts[0])
+    ctx.sync()
+    single = (time.time() - t0) / args.boot_reps
+    ks = (ctx.counters()["keyswitches"] - k0) / args.boot_reps
+    outs = ctx.bootstrap_batch(plan, keys, cts)
+    ctx.sync()
+    t0 = time.time()
+    for _ in range(args.boot_reps):
+        outs = ctx.bootstrap_batch(plan, keys, cts)
+    ctx.sync()
+    batched = (time.time() - t0) / args.boot_reps
+    errb = max(float(np.abs(ctx.decrypt(keys, o, z.shape[1]) - z[i]).max()) for i, o in enumerate(outs))
+    del outs, out
+    # the formula KAN with a bootstrapping between layers
+    x = synth.inputs(wl, B)
+    want = pc.plain_forward(x, layers)
+    kin = [ctx.encrypt(keys, x[i], synth.SEED_ENC + 100 + i) for i in range(B)]
+    kout = ctx.eval_kan_boot(model, plan, keys, kin)
+    ctx.sync()
+    t0 = time.time()
+    for _ in range(args.boot_reps):
+        kout = ctx.eval_kan_boot(model, plan, keys, kin)
+    ctx.sync()
+    kan_s = (time.time() - t0) / args.boot_reps
+    kerr = max(float(np.abs(ctx.decrypt(keys, o, wl.shape[-1]) - want[i]).max()) for i, o in enumerate(kout))
+    res = {"parameters": "boot16: N=2^16, 51 + 10x45 + 17x58-bit primes, 4 special primes, 4-limb digits, h=192",
+           "plan": {"cts_levels": bs.cts, "stc_levels": bs.stc, "K": bs.K, "double_angles": bs.r,
+                    "cos_degree": bs.degree, "levels": "%d -> %d" % (bs.L, bs.Lc)},
+           "first_call_s": round(first, 3),
+           "ms_per_bootstrap_b1": round(single * 1e3, 3),
+           "bootstraps_per_s_b1": round(1.0 / single, 2),
+           "batch": B, "ms_per_batch": round(batched * 1e3, 3),
+           "bootstraps_per_s_batched": round(B / batched, 2),
+           "keyswitches_per_bootstrap": ks,
+           "max_abs_err": max(err, errb),
+           "kan_formula_with_bootstrapping": {
+               "model": "KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B,
+               "inferences_per_s": round(B / kan_s, 3), "ms_per_batch": round(kan_s * 1e3, 1),
+               "max_abs_err_vs_fp64_circuit": kerr}}
+    log("bootstrapping:", res)
+    del kout, kin, cts, keys, model, plan
+    ctx.close()
+    return res
+
+
 def table3(args):
     """The paper's comparison of the basis approximation with and without
     lazy combination, on one GPU: for each (n_i, g, k) a one-layer KAN
@@ -534,6 +613,9 @@ def main():
                     help="serving engines (contexts with their own stream and copy of the keys)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--no-boot", action="store_true", help="skip the bootstrapping measurement")
+    ap.add_argument("--boot-batch", type=int, default=8)
+    ap.add_argument("--boot-reps", type=int, default=3)
     ap.add_argument("--table3", action="store_true",
                     help="run only the basis-approximation comparison (lazy combination vs the naive permutation)")
     ap.add_argument("--table3-reps", type=int, default=5)
@@ -701,6 +783,8 @@ def main():
         c.close()
     del engines
     ctx.close()
+    if not args.no_boot:
+        res["bootstrapping"] = boot_bench(args)
     print(json.dumps(res), flush=True)
 
 

@@ -88,6 +88,19 @@ typedef struct {
                             /* arithmetic, the others on 64-bit integer words; 1:  */
                             /* every prime on 64-bit integer words (Shoup, Barrett, */
                             /* Montgomery).  Both give the same residues.           */
+    int32_t boot_levels;    /* levels kept for bootstrapping (0: none): the top     */
+                            /* boot_levels primes have boot_bits bits and the       */
+                            /* canonical scales there stay near 2^boot_bits (S_L =  */
+                            /* 2^boot_bits); the computation levels below keep      */
+                            /* scale_bits, their top level L_c = levels -           */
+                            /* boot_levels with S = 2^scale_bits.  Fresh            */
+                            /* encryptions and bootstrapping results are at L_c.    */
+    int32_t boot_bits;      /* <= 58; digits must stay within the special primes'   */
+                            /* product for the key-switch noise to stay small       */
+    int32_t secret_hamming_weight; /* h > 0: the secret has exactly h non-zero      */
+                            /* coefficients in {-1, 1} (sparse ternary, which keeps */
+                            /* bootstrapping's overflow |I| small); 0: uniform      */
+                            /* ternary                                              */
 } he_params;
 
 /*
@@ -261,8 +274,10 @@ int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t
  * client operation uploads it to the device for its own duration and clears
  * that copy before returning) and the evaluation keys resident in HBM (*ek):
  * the relinearisation key (for s^2) and one Galois key per rotation step in
- * steps[0..nsteps) (for sigma_{5^t}(s)).  All randomness is drawn from
- * ChaCha20 keyed by `seed`. */
+ * steps[0..nsteps) (for sigma_{5^t}(s); HE_STEP_CONJUGATE for the complex
+ * conjugation sigma_{2N-1}(s)).  The secret is uniform ternary, or sparse
+ * ternary of the context's secret_hamming_weight.  All randomness is drawn
+ * from ChaCha20 keyed by `seed`. */
 int he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *steps, size_t nsteps, he_secret_key **sk,
               he_eval_keys **ek);
 int he_secret_key_free(he_secret_key *sk);
@@ -290,8 +305,8 @@ int he_eval_keys_import(he_ctx *ctx, const uint32_t *ids, size_t nkeys, const ui
 /* ------------------------------------------------------------- ciphertexts */
 
 /* Encrypt x[0..n) (raster-scanned input, slots n..N/2-1 are zero) under the
- * secret key at the top level: (-a s + e + m, a), with a and e drawn from
- * ChaCha20 keyed by `seed`. */
+ * secret key at the top computation level L_c (levels - boot_levels):
+ * (-a s + e + m, a), with a and e drawn from ChaCha20 keyed by `seed`. */
 int he_encrypt(he_ctx *ctx, const he_secret_key *sk, const double *x, size_t n, uint64_t seed, he_ct **out);
 
 /* Decrypt and decode the first n slots into y. */
@@ -306,6 +321,90 @@ int he_ct_export(he_ctx *ctx, const he_ct *ct, uint64_t *out, size_t cap);
 
 /* Import a ciphertext given in coefficient form [2][level+1][N]. */
 int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out);
+
+/* ------------------------------------------------------------ bootstrapping */
+
+/* The rotation "step" naming the complex conjugation (Galois element 2N - 1):
+ * he_keygen makes its key when steps holds it; he_boot_rotation_steps lists it. */
+#define HE_STEP_CONJUGATE INT32_MIN
+
+/*
+ * CKKS bootstrapping, the refresh the paper relies on (Experiments,
+ * Experiment Setup: multiplicative depth 20 with bootstrapping in the
+ * settings of Lee et al. 2022; the paper does not restate the procedure).
+ * The library runs the full-slot RNS-CKKS bootstrapping on a context with
+ * boot_levels > 0:
+ *   ModRaise (the level-0 residues as centred integers, lifted to level L),
+ *   CoeffToSlot (the inverse of the encoding's special DFT, its butterfly
+ *     stages merged into cts_levels groups, each one baby-step giant-step
+ *     product with the group's diagonals: one level each),
+ *   the real/imaginary split by conjugation,
+ *   EvalMod on both halves (the Chebyshev series cos_coeffs of
+ *     cos(2 pi (y - 1/4) / 2^double_angles) on [-k_range, k_range], then
+ *     double_angles steps c <- 2 c^2 - 1, giving sin(2 pi y)),
+ *   SlotToCoeff (the special DFT in stc_levels groups, the last landing at
+ *     the top computation level L_c).
+ * k_range must bound |I| + 1/2, where the ModRaise plaintext is m + q_0 I
+ * (|I| <= (h + 1) / 2 for a sparse secret of weight h; in practice a few
+ * standard deviations of sqrt((h + 1) / 12)).  The levels used are
+ * cts_levels + the series' depth + double_angles + stc_levels and must fit
+ * in boot_levels (HE_EDEPTH at evaluation otherwise).
+ */
+typedef struct {
+    int32_t cts_levels;        /* 1 .. log_n - 1 */
+    int32_t stc_levels;        /* 1 .. log_n - 1 */
+    double k_range;            /* K > 0 */
+    int32_t double_angles;     /* r >= 0 */
+    int32_t cos_degree;        /* >= 1 */
+    const double *cos_coeffs;  /* cos_degree + 1 Chebyshev coefficients */
+} he_boot_desc;
+
+typedef struct he_boot he_boot;
+
+/* Build the bootstrapping plan (the merged diagonals of every stage group;
+ * their plaintexts are encoded on first use and kept in HBM with the plan). */
+int he_boot_create(he_ctx *ctx, const he_boot_desc *desc, he_boot **out);
+int he_boot_free(he_boot *b);
+
+/* Rotation steps the bootstrapping needs keys for, HE_STEP_CONJUGATE
+ * included.  Writes min(cap, total) steps and the total to *n. */
+int he_boot_rotation_steps(const he_boot *b, int32_t *steps, size_t cap, size_t *n);
+
+/* Refresh in (at a computation level <= L_c, values with |m| well below
+ * q_0 / 2): *out is a new ciphertext at L_c with the same slot values (up to
+ * the approximation error).  Asynchronous on the context stream.  Errors:
+ * HE_EKEY without a needed key, HE_EDEPTH if the plan does not fit the boot
+ * levels, HE_EINVAL for an input above L_c. */
+int he_bootstrap(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he_ct *in, he_ct **out);
+
+/* The same for n ciphertexts at one level in one batched pass (every ring
+ * kernel covers all of them); out receives n ciphertexts. */
+int he_bootstrap_batch(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he_ct *const *in, size_t n,
+                       he_ct **out);
+
+/* The network on n requests (as he_eval_kan_batch: in holds n * nc input
+ * chunks, request-major) with a bootstrapping of every layer's output before
+ * the next layer, in place of the client-aided refresh: the whole inference
+ * runs on the server.  Each layer must fit the computation levels (HE_EDEPTH
+ * otherwise); the model is compiled with refresh_between_layers = 1. */
+int he_eval_kan_boot(he_ctx *ctx, const he_model *m, he_boot *b, const he_eval_keys *ek, const he_ct *const *in,
+                     size_t n, he_ct **out);
+
+/* The stages of he_bootstrap, each as it runs there:
+ *   he_boot_coeff_to_slot: ModRaise of in (taken at level 0) and CoeffToSlot,
+ *     the result at level L - cts_levels holding (t_k + i t_{k+N/2}) / (2 q_0)
+ *     in bit-reversed slot order k;
+ *   he_boot_eval_mod: EvalMod of in (slots in [-k_range, k_range]);
+ *   he_boot_slot_to_coeff: SlotToCoeff of in for a bootstrapping input that
+ *     was at source_level (its scale enters SlotToCoeff's constant), the
+ *     result at L_c.
+ * he_bootstrap splits the first result w into w + conj(w) and
+ * i (conj(w) - w) (he_ct_rotate with HE_STEP_CONJUGATE, he_ct_mul_i), runs
+ * both through EvalMod as one batch and recombines u_0 + i u_1. */
+int he_boot_coeff_to_slot(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he_ct *in, he_ct **out);
+int he_boot_eval_mod(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he_ct *in, he_ct **out);
+int he_boot_slot_to_coeff(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he_ct *in, int32_t source_level,
+                          he_ct **out);
 
 /* ------------------------------------------------------- encrypted inference */
 
@@ -400,6 +499,13 @@ int he_ctx_device_memory(he_ctx *ctx, uint64_t *free_bytes, uint64_t *total_byte
 
 /* out = a + b (same level). */
 int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+/* out = a - b (same level). */
+int he_ct_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+/* out = a X^(N/2): every slot times i (zeta^(5^j N/2) = i); exact, no level. */
+int he_ct_mul_i(he_ctx *ctx, const he_ct *a, he_ct **out);
+/* ModRaise (bootstrapping's first step): a at level 0, its residues mod q_0
+ * read as centred integers and lifted to every prime of level L. */
+int he_ct_mod_raise(he_ctx *ctx, const he_ct *a, he_ct **out);
 /* out = a (x) b: tensor, relinearise (hybrid key switch), rescale (level - 1). */
 int he_ct_mul(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, const he_ct *b, he_ct **out);
 /* out = rot(a, step): slots move left by step (right if negative). */

@@ -13,7 +13,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhekan.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "ntt.hip", "noalloc.hip", "hostmath.cpp", "ckks.cpp", "kan.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "ntt.hip", "noalloc.hip", "hostmath.cpp", "ckks.cpp", "kan.cpp", "boot.cpp", "capi.cpp",
+           "server.cpp"]
 
 COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-ffp-contract=off", "-I" + os.path.join(HERE, "..", "include")]
 # every HIP compilation: gfx950 only, and no packed-FP32 instructions

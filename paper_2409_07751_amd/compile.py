@@ -64,6 +64,14 @@ def comparison_stages(degrees, R, fold=True):
     return [np.asarray(s, np.float64) for s in stages]
 
 
+def boot_cos_coeffs(K, r, degree):
+    """EvalMod's series for a bootstrapping plan (he_boot_desc): the Chebyshev
+    interpolant of cos(2 pi (y - 1/4) / 2^r) on [-K, K] at the degree + 1
+    Chebyshev points (chebinterpolate), so that r double-angle steps give
+    sin(2 pi y)."""
+    return list(cheb.chebinterpolate(lambda u: np.cos(2.0 * np.pi * (K * u - 0.25) / 2.0 ** r), degree))
+
+
 def silu_range(mu, sd, lo, hi):
     return max(mu - 5.0 * sd, lo), min(mu + 5.0 * sd, hi)
 

@@ -21,8 +21,13 @@ int he_ctx_create(const he_params *p, void *hip_stream, he_ctx **out)
         need(p->digit_width >= 1 && p->digit_width <= 8, "digit_width out of range");
         need((p->levels + p->digit_width) / p->digit_width <= 16, "more than 16 key-switch digits");
         need(p->sigma > 0 && p->sigma < 100, "sigma out of range");
+        need(p->boot_levels >= 0 && p->boot_levels < p->levels, "boot_levels out of range");
+        need(p->boot_levels == 0 || (p->boot_bits >= 20 && p->boot_bits <= 58), "boot_bits out of range");
+        need(p->secret_hamming_weight >= 0 && p->secret_hamming_weight <= (1 << p->log_n),
+             "secret_hamming_weight out of range");
         h->c = new Ctx(p->log_n, p->levels, p->scale_bits, p->base_bits, p->special_count, p->special_bits,
-                       p->digit_width, p->sigma, (hipStream_t)hip_stream, p->integer_words != 0);
+                       p->digit_width, p->sigma, (hipStream_t)hip_stream, p->integer_words != 0, p->boot_levels,
+                       p->boot_bits, p->secret_hamming_weight);
     });
     if (rc != HE_OK) {
         delete h;
@@ -367,6 +372,108 @@ int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t
     return HE_OK;
 }
 
+int he_boot_create(he_ctx *ctx, const he_boot_desc *d, he_boot **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        need(d != nullptr && d->cos_coeffs != nullptr && d->cos_degree >= 1, "missing bootstrapping description");
+        need(ctx->c->top < ctx->c->L, "the context has no boot levels");
+        std::vector<double> cf(d->cos_coeffs, d->cos_coeffs + d->cos_degree + 1);
+        Boot *b = new Boot(ctx->c, d->cts_levels, d->stc_levels, d->k_range, d->double_angles, cf);
+        *out = new he_boot{retain(ctx), b};
+    });
+}
+
+int he_boot_free(he_boot *b)
+{
+    if (!b) return HE_EINVAL;
+    he_ctx *o = b->owner;
+    delete b->b;
+    delete b;
+    release(o);
+    return HE_OK;
+}
+
+int he_boot_rotation_steps(const he_boot *b, int32_t *steps, size_t cap, size_t *n)
+{
+    if (!b || !n) return HE_EINVAL;
+    const auto &s = b->b->steps;
+    *n = s.size();
+    for (size_t i = 0; i < s.size() && i < cap && steps; i++) steps[i] = (int32_t)s[i];
+    return HE_OK;
+}
+
+int he_bootstrap(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *in, he_ct **out)
+{
+    return he_bootstrap_batch(ctx, b, k, &in, 1, out);
+}
+
+int he_bootstrap_batch(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *const *in, size_t n,
+                       he_ct **out)
+{
+    if (!ctx || !b || !k || !out || (n && !in)) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+        if (n == 0) return;
+        if (b->owner != ctx) throw HeError(HE_ESTATE, "bootstrapping plan of another context");
+        check_ek(ctx, k);
+        Ctx &c = *ctx->c;
+        Ct res = bootstrap(c, *b->b, *k->k, batch_inputs(ctx, in, n, 1)[0]);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, n == 1 ? res : c.unpack(res, (int)i));
+    });
+}
+
+int he_eval_kan_boot(he_ctx *ctx, const he_model *m, he_boot *b, const he_eval_keys *k, const he_ct *const *in,
+                     size_t n, he_ct **out)
+{
+    if (!ctx || !m || !b || !k || !out || (n && !in)) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+        if (n == 0) return;
+        check_model(ctx, m, k);
+        if (b->owner != ctx) throw HeError(HE_ESTATE, "bootstrapping plan of another context");
+        Ctx &c = *ctx->c;
+        Model &md = *m->m;
+        Ct x = eval_layer(c, md, *k->k, batch_inputs(ctx, in, n, md.n_inputs()), 0);
+        for (size_t li = 1; li < md.layers.size(); li++)
+            x = eval_layer(c, md, *k->k, {bootstrap(c, *b->b, *k->k, x)}, li);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, n == 1 ? x : c.unpack(x, (int)i));
+    });
+}
+
+static int boot_stage(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *in, he_ct **out, int stage,
+                      int src_level)
+{
+    if (!ctx || !b || !k || !out) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        if (b->owner != ctx) throw HeError(HE_ESTATE, "bootstrapping plan of another context");
+        check_ek(ctx, k);
+        check_ct(ctx, in);
+        Ctx &c = *ctx->c;
+        if (stage == 0) *out = wrap(ctx, boot_coeff_to_slot(c, *b->b, *k->k, in->c));
+        if (stage == 1) *out = wrap(ctx, boot_eval_mod(c, *b->b, *k->k, in->c));
+        if (stage == 2) *out = wrap(ctx, boot_slot_to_coeff(c, *b->b, *k->k, in->c, src_level));
+    });
+}
+
+int he_boot_coeff_to_slot(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *in, he_ct **out)
+{
+    return boot_stage(ctx, b, k, in, out, 0, 0);
+}
+
+int he_boot_eval_mod(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *in, he_ct **out)
+{
+    return boot_stage(ctx, b, k, in, out, 1, 0);
+}
+
+int he_boot_slot_to_coeff(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *in, int32_t source_level,
+                          he_ct **out)
+{
+    return boot_stage(ctx, b, k, in, out, 2, source_level);
+}
+
 int he_eval_kan(he_ctx *ctx, const he_model *m, const he_eval_keys *k, const he_ct *in, he_ct **out)
 {
     return he_eval_kan_chunks(ctx, m, k, &in, 1, out);
@@ -552,6 +659,35 @@ int he_ct_rotate(he_ctx *ctx, const he_eval_keys *k, const he_ct *a, int32_t ste
         check_ek(ctx, k);
         check_ct(ctx, a);
         *out = wrap(ctx, ctx->c->rotate(a->c, step, *k->k));
+    });
+}
+
+int he_ct_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        check_ct(ctx, b);
+        *out = wrap(ctx, ctx->c->sub(a->c, b->c));
+    });
+}
+
+int he_ct_mul_i(he_ctx *ctx, const he_ct *a, he_ct **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        *out = wrap(ctx, ctx->c->mul_i(a->c));
+    });
+}
+
+int he_ct_mod_raise(he_ctx *ctx, const he_ct *a, he_ct **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        need(a->c.level == 0, "mod_raise: the input must be at level 0");
+        *out = wrap(ctx, ctx->c->mod_raise(a->c));
     });
 }
 

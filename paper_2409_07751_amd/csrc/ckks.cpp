@@ -149,10 +149,11 @@ void Ctx::profile_read(double &ms, u64 &launches, double &bytes, double &ops)
 
 // ------------------------------------------------------------------ context
 Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int special_bits, int w_, double sigma_,
-         hipStream_t stream, bool integer_words)
-    : logN(logN_), N(1 << logN_), L(L_), alpha(alpha_), w(w_), L1(L_ + 1), sigma(sigma_)
+         hipStream_t stream, bool integer_words, int boot_levels, int boot_bits, int hamming_)
+    : logN(logN_), N(1 << logN_), L(L_), alpha(alpha_), w(w_), L1(L_ + 1), top(L_ - boot_levels), hamming(hamming_),
+      sigma(sigma_)
 {
-    make_chain(logN, base_bits, L, scale_bits, alpha, special_bits, q, p, S);
+    make_chain(logN, base_bits, L, scale_bits, alpha, special_bits, boot_levels, boot_bits, q, p, S);
     mods = q;
     mods.insert(mods.end(), p.begin(), p.end());
     if (stream) {
@@ -345,6 +346,7 @@ Ctx::~Ctx()
 
 u64 Ctx::galois_elt(long step) const
 {
+    if (step == kStepConjugate) return 2ull * N - 1;
     long slots = N / 2;
     long t = ((step % slots) + slots) % slots;
     return hpow(5, (u64)t, 2ull * N);
@@ -472,6 +474,37 @@ Ct Ctx::mod_drop(const Ct &a, int l) const
     if (l > a.level || l < 0) throw HeError(-1, "mod_drop: bad level");
     Ct o = a;
     o.level = l;
+    return o;
+}
+
+Ct Ctx::mod_raise(const Ct &a)
+{
+    if (a.level != 0) throw HeError(-1, "mod_raise: the input must be at level 0");
+    const int np = 2 * a.nb;
+    Buf tmp = alloc((size_t)np * N);
+    PolySet t{tmp->p, (long)np * N, (long)N, 1, np};
+    launch_copy(t, PolySet{a.d(), 2l * N * a.nb, (long)N, 1, np}, N, st);
+    ntt(t, lmap(1), true);
+    Ct o = new_ct(L, a.nb);
+    launch_modraise(d_pc, ctset(o), tmp->p, lmap(L + 1), N, st);
+    ntt(ctset(o), lmap(L + 1), false);
+    n_launch += 2;
+    return o;
+}
+
+Ct Ctx::mul_i(const Ct &a)
+{
+    if (!mono_half) {
+        std::vector<u64> h((size_t)(L + 1) * N, 0);
+        for (int t = 0; t <= L; t++) h[(size_t)t * N + N / 2] = 1;
+        mono_half = alloc(h.size());
+        upload(mono_half->p, h.data(), h.size());
+        ntt(PolySet{mono_half->p, (long)N, 0, L + 1, 1}, lmap(L + 1), false);
+    }
+    Ct o = new_ct(a.level, a.nb);
+    launch_pmul(d_pc, ctset(o), ctset(a), PolySet{mono_half->p, (long)N, 0, a.level + 1, 2 * a.nb},
+                lmap(a.level + 1), N, st);
+    n_launch++;
     return o;
 }
 
@@ -1002,8 +1035,10 @@ Pt Ctx::vec_pt(const double *z, size_t n, double scale, int nl)
     return p;
 }
 
-std::vector<Pt> Ctx::vec_pts(const std::vector<const std::vector<double> *> &zs, double scale, int nl)
+std::vector<Pt> Ctx::vec_pts(const std::vector<const std::vector<double> *> &zs, double scale, int nl,
+                             const std::vector<const std::vector<double> *> *ims)
 {
+    if (ims && ims->size() != zs.size()) throw HeError(-1, "vec_pts: real and imaginary parts differ in count");
     const size_t n = zs.size();
     std::vector<std::vector<u64>> host(n);
     std::vector<std::thread> th;
@@ -1015,7 +1050,12 @@ std::vector<Pt> Ctx::vec_pts(const std::vector<const std::vector<double> *> &zs,
             try {
                 for (size_t i = tid; i < n; i += nth) {
                     host[i].resize((size_t)nl * N);
-                    encode_rns(zs[i]->data(), zs[i]->size(), scale, logN, mods.data(), nl, host[i].data());
+                    const double *im = nullptr;
+                    if (ims) {
+                        if ((*ims)[i]->size() != zs[i]->size()) throw HeError(-1, "vec_pts: part sizes differ");
+                        im = (*ims)[i]->data();
+                    }
+                    encode_rns_c(zs[i]->data(), im, zs[i]->size(), scale, logN, mods.data(), nl, host[i].data());
                 }
             } catch (...) {
                 std::lock_guard<std::mutex> lk(mu);
@@ -1210,7 +1250,10 @@ void Ctx::keygen(u64 seed, const std::vector<long> &steps, SecretKey *&sk_out, K
     std::unique_ptr<SecretKey> sk(new SecretKey());
     sk->ctx = this;
     sk->s.resize(N);
-    sample_ternary(seed, 1, 0, 0, N, sk->s.data());
+    if (hamming > 0)
+        sample_sparse_ternary(seed, 1, 0, 0, N, hamming, sk->s.data());
+    else
+        sample_ternary(seed, 1, 0, 0, N, sk->s.data());
     std::unique_ptr<Keys> k(new Keys());
     k->ctx = this;
     Buf s_ntt = secret_ntt(*sk, ktot);
@@ -1322,10 +1365,10 @@ void Ctx::export_key(const Keys &k, u32 key_id, int digit, u64 *out)
 
 Ct Ctx::encrypt(const SecretKey &sk, const double *x, size_t n, u64 seed)
 {
-    const int nl = L + 1;
+    const int nl = top + 1;
     if (n > (size_t)N / 2) throw HeError(-4, "encrypt: more values than slots");
     std::vector<u64> em((size_t)nl * N), a((size_t)nl * N);
-    encode_rns(x, n, S[L], logN, q.data(), nl, em.data());
+    encode_rns(x, n, S[top], logN, q.data(), nl, em.data());
     std::vector<int64_t> e(N);
     sample_gauss(seed, 5, 0, 0, sigma, N, e.data());
     for (int t = 0; t < nl; t++) {
@@ -1344,7 +1387,7 @@ Ct Ctx::encrypt(const SecretKey &sk, const double *x, size_t n, u64 seed)
     LimbMap lm = lmap(nl);
     ntt(PolySet{da->p, (long)N, 0, nl, 1}, lm, false);
     ntt(PolySet{dem->p, (long)N, 0, nl, 1}, lm, false);
-    Ct c = new_ct(L);
+    Ct c = new_ct(top);
     Buf s_ntt = secret_ntt(sk, nl);
     launch_copy(PolySet{c.d() + N, 2l * N, 0, nl, 1}, PolySet{da->p, (long)N, 0, nl, 1}, N, st);
     launch_encrypt(d_pc, c.d(), c.d() + N, s_ntt->p, dem->p, 2l * N, nl, N, st);

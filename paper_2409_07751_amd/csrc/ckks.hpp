@@ -2,6 +2,7 @@
 #pragma once
 #include <map>
 #include <memory>
+#include <stdexcept>
 #include <string>
 #include <tuple>
 #include <unordered_map>
@@ -28,6 +29,9 @@ struct HeError : std::runtime_error {
     } while (0)
 
 struct Ctx;
+
+// The rotation "step" that names the complex conjugation (Galois element 2N - 1).
+constexpr long kStepConjugate = -(1l << 31);
 
 // Size of the device array behind the entry points that allocate nothing (one
 // copy per device), and its set-up: looks up the array's device address for
@@ -119,6 +123,8 @@ struct KsTable {
 
 struct Ctx {
     int logN, N, L, alpha, w, L1;
+    int top;      // top computation level: L minus the levels kept for bootstrapping
+    int hamming;  // Hamming weight of a sparse ternary secret (0: uniform ternary)
     double sigma;
     std::vector<u64> q, p, mods;  // mods = q ++ p
     std::vector<double> S;
@@ -148,7 +154,7 @@ struct Ctx {
     void profile_read(double &ms, u64 &launches, double &bytes, double &ops);
 
     Ctx(int logN, int L, int scale_bits, int base_bits, int alpha, int special_bits, int w, double sigma,
-        hipStream_t stream, bool integer_words = false);
+        hipStream_t stream, bool integer_words = false, int boot_levels = 0, int boot_bits = 0, int hamming = 0);
     ~Ctx();
 
     Buf alloc(size_t words);
@@ -172,6 +178,12 @@ struct Ctx {
     // k a [+ *c | + *pt] in one pass; same residues as mul_int then add_const / add_plain
     Ct affine(const Ct &a, long k, const double *c, const Buf *pt);
     Ct mod_drop(const Ct &a, int l) const;
+    // ModRaise of a level-0 ciphertext: its residues mod q_0 as centred
+    // integers, lifted to every prime of level L
+    Ct mod_raise(const Ct &a);
+    // every slot times i: the product with the monomial X^(N/2) (exact)
+    Ct mul_i(const Ct &a);
+    Buf mono_half;  // NTT of X^(N/2) over the L+1 Q primes
     Ct rescale(const Ct &a);
     // k rescale(a) [+ c]: the integer factor and the constant (at the result's
     // scale) are applied in the rescale's last pass; same residues as
@@ -240,7 +252,8 @@ struct Ctx {
     Pt vec_pt(const double *z, size_t n, double scale, int nl);
     // several slot-vector plaintexts at once: the host encodings run on
     // parallel threads, then each is uploaded and transformed
-    std::vector<Pt> vec_pts(const std::vector<const std::vector<double> *> &zs, double scale, int nl);
+    std::vector<Pt> vec_pts(const std::vector<const std::vector<double> *> &zs, double scale, int nl,
+                            const std::vector<const std::vector<double> *> *ims = nullptr);
 
     // tables
     const KsTable &ks_table(int l);

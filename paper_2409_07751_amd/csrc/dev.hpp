@@ -206,6 +206,9 @@ void launch_rescale_ntt(const NttTables &t, u64 *tmp, int l, int npoly, const u6
                         KernelTimer *tm = nullptr);
 // copy limbs
 void launch_copy(PolySet out, PolySet in, int N, hipStream_t s);
+// ModRaise: polynomial p of `in` ([npoly][N], coefficients mod q_0) read as
+// centred integers and reduced mod the prime of every limb of out
+void launch_modraise(const PrimeConst *pc, PolySet out, const u64 *in, LimbMap lm, int N, hipStream_t s);
 // pointwise product out = a * b (single polynomials, Barrett)
 void launch_pmul(const PrimeConst *pc, PolySet out, PolySet a, PolySet b, LimbMap lm, int N, hipStream_t s);
 // switching-key body b = e - a s + pfac s' (NTT domain); b and a leave in Montgomery form

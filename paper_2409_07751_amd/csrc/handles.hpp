@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/hekan.h"
+#include "boot.hpp"
 #include "ckks.hpp"
 #include "kan.hpp"
 
@@ -23,6 +24,10 @@ struct he_ctx {
 struct he_model {
     he_ctx *owner;
     Model *m;
+};
+struct he_boot {
+    he_ctx *owner;
+    Boot *b;
 };
 struct he_secret_key {
     he_ctx *owner;

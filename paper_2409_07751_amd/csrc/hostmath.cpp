@@ -2,6 +2,7 @@
 // encoder of the GPU library (client side and offline model compile).
 #include "hostmath.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -70,8 +71,8 @@ static bool used_before(const std::vector<u64> &v, u64 c)
     return false;
 }
 
-void make_chain(int logN, int base_bits, int L, int scale_bits, int alpha, int special_bits,
-                std::vector<u64> &q, std::vector<u64> &p, std::vector<double> &S)
+void make_chain(int logN, int base_bits, int L, int scale_bits, int alpha, int special_bits, int boot_levels,
+                int boot_bits, std::vector<u64> &q, std::vector<u64> &p, std::vector<double> &S)
 {
     const u64 M = 2ull << logN;
     std::vector<u64> used;
@@ -91,11 +92,15 @@ void make_chain(int logN, int base_bits, int L, int scale_bits, int alpha, int s
         used.push_back(c);
         c -= M;
     }
-    // scale primes top-down keeping the canonical scale near Delta
-    const double delta = std::ldexp(1.0, scale_bits);
-    double s = delta;
+    // scale primes top-down keeping the canonical scale near Delta_l: the
+    // top boot_levels levels (those a bootstrapping consumes) near
+    // 2^boot_bits, the computation levels below near 2^scale_bits, whose
+    // top level takes S = 2^scale_bits
+    const int top_c = L - boot_levels;
+    double s = std::ldexp(1.0, boot_levels > 0 ? boot_bits : scale_bits);
     S[L] = s;
     for (int l = L; l >= 1; l--) {
+        const double delta = std::ldexp(1.0, l > top_c ? boot_bits : scale_bits);
         const double target = (s * s) / delta;
         u64 below = (u64)std::floor((target - 1.0) / (double)M) * M + 1;  // <= target
         u64 above = below + M;
@@ -112,7 +117,7 @@ void make_chain(int logN, int base_bits, int L, int scale_bits, int alpha, int s
         }
         q[l] = pick;
         used.push_back(pick);
-        s = (s * s) / (double)pick;
+        s = (boot_levels > 0 && l == top_c + 1) ? std::ldexp(1.0, scale_bits) : (s * s) / (double)pick;
         S[l - 1] = s;
     }
 }
@@ -196,6 +201,22 @@ void sample_ternary(u64 seed, u32 purpose, u32 id, u32 sub, int N, int64_t *out)
         u32 v = st.next32() & 3u;
         while (v == 3u) v = st.next32() & 3u;
         out[i] = (int64_t)v - 1;
+    }
+}
+
+// exactly h coefficients in {-1, 1}: each word w proposes position w mod N
+// with sign w >> 31 (1: -1); taken positions are skipped
+void sample_sparse_ternary(u64 seed, u32 purpose, u32 id, u32 sub, int N, int h, int64_t *out)
+{
+    if (h < 0 || h > N || N > (1 << 16)) throw std::runtime_error("sparse secret: bad Hamming weight");
+    ChaChaStream st(seed, purpose, id, sub);
+    std::fill(out, out + N, (int64_t)0);
+    for (int placed = 0; placed < h;) {
+        const u32 w = st.next32();
+        const u32 pos = w & (u32)(N - 1);
+        if (out[pos]) continue;
+        out[pos] = (w >> 31) ? -1 : 1;
+        placed++;
     }
 }
 
@@ -374,14 +395,21 @@ static const EncTables &enc_tables(int logN)
 
 void encode_rns(const double *z, size_t n, double scale, int logN, const u64 *mods, int nl, u64 *out)
 {
+    encode_rns_c(z, nullptr, n, scale, logN, mods, nl, out);
+}
+
+void encode_rns_c(const double *re, const double *im, size_t n, double scale, int logN, const u64 *mods, int nl,
+                  u64 *out)
+{
     const long N = 1l << logN, M = N / 2, twoN = 2 * N;
     if ((long)n > M) throw std::runtime_error("encode: too many slots");
     const EncTables &T = enc_tables(logN);
-    // w_k = z_j where 5^j = 4k + 1 (mod 2N)
+    // w_k = z_j where 5^j = 4k + 1 (mod 2N); the values at the conjugate
+    // roots are the conjugates, so only these M enter (see below)
     std::vector<CDD> w(M, CDD{{0, 0}, {0, 0}});
     long e = 1;
     for (long j = 0; j < M; j++) {
-        if ((size_t)j < n) w[(e - 1) / 4].re = DD{z[j], 0.0};
+        if ((size_t)j < n) w[(e - 1) / 4] = CDD{DD{re[j], 0.0}, DD{im ? im[j] : 0.0, 0.0}};
         e = e * 5 % twoN;
     }
     // in-place iterative radix-2 DIF with twiddles omega^-r, omega = zeta^4,
@@ -402,6 +430,16 @@ void encode_rns(const double *z, size_t n, double scale, int logN, const u64 *mo
         CDD u = w[T.brv[i]] * T.zinv[i];
         put_residues(round_even(u.re * f), mods, nl, out + i, N);
         put_residues(round_even(u.im * f), mods, nl, out + i + M, N);
+    }
+}
+
+void zeta_table(int logN, double *re, double *im)
+{
+    const long N = 1l << logN;
+    for (long e = 0; e < 2 * N; e++) {
+        const CDD r = zeta_pow(e, N);
+        re[e] = r.re.hi + r.re.lo;
+        im[e] = r.im.hi + r.im.lo;
     }
 }
 

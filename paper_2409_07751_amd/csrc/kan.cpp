@@ -367,7 +367,7 @@ struct Eval {
         int t = ch.T.at(1).level - 1;
         while (!ch.feasible(cf, t)) {
             t--;
-            if (t < 0) throw HeError(-3, "SiLU polynomial does not fit the level budget");
+            if (t < 0) throw HeError(-3, "Chebyshev series does not fit the level budget");
         }
         return ch.rec(cf, t);
     }
@@ -691,6 +691,13 @@ Ct eval_layer(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in, size_t
 {
     Eval e(c, k, m);
     return e.layer(in, li);
+}
+
+Ct cheb_series(Ctx &c, const Keys &k, const Ct &x, const std::vector<double> &cf, double lo, double hi)
+{
+    Model none;
+    Eval e(c, k, none);
+    return e.cheb_eval(x, cf, lo, hi);
 }
 
 Ct eval_model(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in)

@@ -52,6 +52,7 @@ struct Model {
     std::unordered_map<std::string, Pt> pt_cache;   // Montgomery NTT plaintexts for lincombs
     std::unordered_map<std::string, Buf> add_cache; // NTT plaintexts added to ciphertexts
     Model(Ctx *c, const he_kan_desc *d, bool refresh);
+    Model() : ctx(nullptr), refresh(false), S(1), circ(0) {}  // no layers (the evaluators alone)
     size_t n_inputs() const { return layers[0].parts.size(); }
 };
 
@@ -69,5 +70,9 @@ PermPlan perm_plan(const LayerC &L, const Part &P, long S, long slots);
 // chunks, or the previous layer's output)
 Ct eval_layer(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in, size_t li);
 Ct eval_model(Ctx &c, Model &m, const Keys &k, const std::vector<Ct> &in);
+
+// the Chebyshev series cf on [lo, hi] of every slot of x by baby-step
+// giant-step (the evaluator of the SiLU approximation)
+Ct cheb_series(Ctx &c, const Keys &k, const Ct &x, const std::vector<double> &cf, double lo, double hi);
 
 }  // namespace hk

@@ -356,4 +356,32 @@ void launch_encrypt(const PrimeConst *pc, u64 *c0, const u64 *a, const u64 *s, c
     hipLaunchKernelGGL(k_encrypt, g, dim3(256), 0, st, pc, c0, a, s, em, c_lstride, N);
 }
 
+
+// ---------------------------------------------------------------- ModRaise
+// coefficient n of polynomial p (mod q_0) as a centred integer, reduced mod
+// the prime of the output limb
+__global__ void k_modraise(const PrimeConst *pc, PolySet out, const u64 *in, LimbMap lm, int N)
+{
+    const int y = blockIdx.y;
+    const int poly = y % out.npoly, limb = y / out.npoly;
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const u64 q0 = pc[0].q, q = pc[lm.prime(limb)].q;
+    const u64 v = in[(long)poly * N + n];
+    u64 r;
+    if (2 * v > q0) {
+        const u64 a = (q0 - v) % q;
+        r = a ? q - a : 0;
+    } else {
+        r = v % q;
+    }
+    out.base[limb * out.lstride + poly * out.pstride + n] = r;
+}
+
+void launch_modraise(const PrimeConst *pc, PolySet out, const u64 *in, LimbMap lm, int N, hipStream_t s)
+{
+    dim3 g((N + 255) / 256, out.nl * out.npoly);
+    hipLaunchKernelGGL(k_modraise, g, dim3(256), 0, s, pc, out, in, lm, N);
+}
+
 }  // namespace hk

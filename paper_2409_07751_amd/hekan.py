@@ -26,7 +26,8 @@ class he_params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_int32), ("levels", ctypes.c_int32), ("scale_bits", ctypes.c_int32),
                 ("base_bits", ctypes.c_int32), ("special_count", ctypes.c_int32),
                 ("special_bits", ctypes.c_int32), ("digit_width", ctypes.c_int32), ("sigma", ctypes.c_double),
-                ("integer_words", ctypes.c_int32)]
+                ("integer_words", ctypes.c_int32), ("boot_levels", ctypes.c_int32), ("boot_bits", ctypes.c_int32),
+                ("secret_hamming_weight", ctypes.c_int32)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -46,6 +47,14 @@ class he_kan_desc(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(he_kan_layer)),
                 ("samples_per_ct", ctypes.c_int32), ("circuit", ctypes.c_int32)]
 
+
+class he_boot_desc(ctypes.Structure):
+    _fields_ = [("cts_levels", ctypes.c_int32), ("stc_levels", ctypes.c_int32), ("k_range", ctypes.c_double),
+                ("double_angles", ctypes.c_int32), ("cos_degree", ctypes.c_int32), ("cos_coeffs", _dp)]
+
+
+# the rotation "step" naming the complex conjugation (HE_STEP_CONJUGATE)
+STEP_CONJUGATE = -(1 << 31)
 
 # he_kan_desc.circuit: restructurings of the paper's layer circuit (0 = the paper's order)
 CIRCUIT_PAPER = 0
@@ -76,6 +85,24 @@ _SIGS = {
     "he_model_compile": [ctypes.c_void_p, ctypes.POINTER(he_kan_desc), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_void_p)],
     "he_model_free": [ctypes.c_void_p],
+    "he_boot_create": [ctypes.c_void_p, ctypes.POINTER(he_boot_desc), ctypes.POINTER(ctypes.c_void_p)],
+    "he_boot_free": [ctypes.c_void_p],
+    "he_boot_rotation_steps": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "he_bootstrap": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.POINTER(ctypes.c_void_p)],
+    "he_boot_coeff_to_slot": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_void_p)],
+    "he_boot_eval_mod": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.POINTER(ctypes.c_void_p)],
+    "he_boot_slot_to_coeff": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_void_p)],
+    "he_eval_kan_boot": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_sub": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_mul_i": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_mod_raise": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_bootstrap_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                           ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_model_rotation_steps": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "he_model_input_chunks": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "he_keygen": [ctypes.c_void_p, ctypes.c_uint64, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p),
@@ -158,10 +185,10 @@ class Context:
     """RNS-CKKS context on the current HIP device (see he_params)."""
 
     def __init__(self, log_n, levels, scale_bits, special_count, digit_width, base_bits=60, special_bits=60,
-                 sigma=3.2, stream=None, integer_words=False):
+                 sigma=3.2, stream=None, integer_words=False, boot_levels=0, boot_bits=0, hamming_weight=0):
         self.lib = lib()
         p = he_params(log_n, levels, scale_bits, base_bits, special_count, special_bits, digit_width, sigma,
-                      1 if integer_words else 0)
+                      1 if integer_words else 0, boot_levels, boot_bits, hamming_weight)
         h = ctypes.c_void_p()
         rc = self.lib.he_ctx_create(ctypes.byref(p), ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
         if rc != HE_OK:
@@ -169,6 +196,7 @@ class Context:
         self.h = h
         self.log_n, self.N, self.L, self.alpha, self.w = log_n, 1 << log_n, levels, special_count, digit_width
         self.slots = self.N // 2
+        self.top = levels - boot_levels  # top computation level
 
     def check(self, rc):
         if rc != HE_OK:
@@ -357,6 +385,48 @@ class Context:
         # requests given as ciphertexts or as lists of input chunks, request-major
         return [c for r in cts for c in (r if isinstance(r, (list, tuple)) else [r])]
 
+    def boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs):
+        """he_boot_create: a bootstrapping plan (see he_boot_desc)"""
+        return Boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs)
+
+    def bootstrap(self, boot, keys, ct):
+        return self._new(self.lib.he_bootstrap, boot.h, _ek(keys), ct.h)
+
+    def eval_kan_boot(self, model, boot, keys, cts):
+        """he_eval_kan_boot: requests (ciphertexts or lists of input chunks)
+        through the network with a bootstrapping between layers"""
+        n = len(cts)
+        flat = self._flat(cts)
+        arr = (ctypes.c_void_p * len(flat))(*[c.h.value for c in flat])
+        outs = (ctypes.c_void_p * n)()
+        self.check(self.lib.he_eval_kan_boot(self.h, model.h, boot.h, _ek(keys), arr, n, outs))
+        return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+    def boot_coeff_to_slot(self, boot, keys, ct):
+        return self._new(self.lib.he_boot_coeff_to_slot, boot.h, _ek(keys), ct.h)
+
+    def boot_eval_mod(self, boot, keys, ct):
+        return self._new(self.lib.he_boot_eval_mod, boot.h, _ek(keys), ct.h)
+
+    def boot_slot_to_coeff(self, boot, keys, ct, source_level):
+        return self._new(self.lib.he_boot_slot_to_coeff, boot.h, _ek(keys), ct.h, source_level)
+
+    def sub(self, a, b):
+        return self._new(self.lib.he_ct_sub, a.h, b.h)
+
+    def mul_i(self, a):
+        return self._new(self.lib.he_ct_mul_i, a.h)
+
+    def mod_raise(self, a):
+        return self._new(self.lib.he_ct_mod_raise, a.h)
+
+    def bootstrap_batch(self, boot, keys, cts):
+        n = len(cts)
+        arr = (ctypes.c_void_p * n)(*[c.h.value for c in cts])
+        outs = (ctypes.c_void_p * n)()
+        self.check(self.lib.he_bootstrap_batch(self.h, boot.h, _ek(keys), arr, n, outs))
+        return [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
     def eval_kan_layer_batch(self, model, keys, layer, cts):
         n = len(cts)
         flat = self._flat(cts)
@@ -544,6 +614,30 @@ class Ciphertext:
     def __del__(self):
         if getattr(self, "h", None):
             self.ctx.lib.he_ct_free(self.h)
+            self.h = None
+
+
+class Boot:
+    """A bootstrapping plan (he_boot_create)."""
+
+    def __init__(self, ctx, cts_levels, stc_levels, k_range, double_angles, cos_coeffs):
+        self.ctx = ctx
+        cf = _arr(cos_coeffs, np.float64)
+        desc = he_boot_desc(cts_levels, stc_levels, float(k_range), double_angles, len(cf) - 1, _ptr(cf))
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.he_boot_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)))
+        self.h = h
+
+    def rotation_steps(self):
+        n = ctypes.c_size_t()
+        self.ctx.check(self.ctx.lib.he_boot_rotation_steps(self.h, None, 0, ctypes.byref(n)))
+        s = np.zeros(n.value, np.int32)
+        self.ctx.check(self.ctx.lib.he_boot_rotation_steps(self.h, _ptr(s), n.value, ctypes.byref(n)))
+        return [int(v) for v in s]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.he_boot_free(self.h)
             self.h = None
 
 

@@ -114,13 +114,20 @@ class BootSet:
         return self.Lc + self.boot_levels
 
 
-# boot11: N=2^11, 60 + 2x45 + 14x58 bits, 2 special primes, 2-limb digits,
-#   h = 32 (|I| <= 12 holds with margin: std sqrt(33/12) = 1.7);
-# boot16: N=2^16, 60 + 10x45 + 17x58 bits, 4 special primes, 4-limb digits,
-#   h = 192 (|I| <= 32 is 8 standard deviations of sqrt(193/12) = 4.0)
+# boot11: N=2^11, 55 + 8x45 + 14x58 bits, 2 special primes, 2-limb digits,
+#   h = 32 (|I| <= 12 holds with margin: std sqrt(33/12) = 1.7); the 8
+#   computation levels hold one layer of the [4,10,10,1] formula KAN;
+# boot16: N=2^16, 51 + 10x45 + 17x58 bits, 4 special primes, 4-limb digits,
+#   h = 192 (|I| <= 32 is 8 standard deviations of sqrt(193/12) = 4.0).
+# The base prime's size balances EvalMod's two errors: a smaller q_0 raises
+# the message against the rounding in CoeffToSlot (whose slots carry q_0 I),
+# a larger one keeps sin(2 pi m/q_0) closer to 2 pi m/q_0 (measured on the
+# oracle at |z| <= 1: q_0 of 60 bits 3.4e-5, 55 bits 1.1e-6, 53 bits 3.3e-7,
+# 51 bits 1.1e-7 at N=2^16; 60 bits 2.1e-7, 55 bits 9.6e-9, 52 bits 3.2e-7
+# at N=2^11)
 BOOTSETS = {
-    "boot11": BootSet("boot11", 11, 2, 14, 45, 58, 2, 2, 32, 2, 2, 12.0, 4, 23),
-    "boot16": BootSet("boot16", 16, 10, 17, 45, 58, 4, 4, 192, 3, 3, 32.0, 5, 31),
+    "boot11": BootSet("boot11", 11, 8, 14, 45, 58, 2, 2, 32, 2, 2, 12.0, 4, 23, base_bits=55),
+    "boot16": BootSet("boot16", 16, 10, 17, 45, 58, 4, 4, 192, 3, 3, 32.0, 5, 27, base_bits=51),
 }
 
 

@@ -130,6 +130,20 @@ def test_cosine_series_and_evalmod_closed_form():
         assert np.abs(boot.evalmod_plain(y, bp) - np.sin(2 * np.pi * y)).max() < 1e-11
 
 
+@pytest.mark.parametrize("name", sorted(synth.BOOTSETS))
+def test_boot_level_plan_fits_the_boot_levels(name):
+    """CoeffToSlot, EvalMod and SlotToCoeff of each bootstrappable parameter set
+    use exactly its boot levels (levels traced on the slot simulator)."""
+    from oracle.slotsim import SlotSim
+    bs = synth.BOOTSETS[name]
+    bp = bootset_bp(bs)
+    sim = SlotSim(16)
+    y = sim.fresh(np.linspace(-bs.K + 0.5, bs.K - 0.5, 16), bs.L - bs.cts)
+    u = boot.eval_mod(sim, y, bp)
+    assert np.abs(u.v - np.sin(2 * np.pi * y.v)).max() < 1e-10
+    assert bs.cts + (bs.L - bs.cts - u.level) + bs.stc == bs.boot_levels
+
+
 def test_sparse_ternary_secret():
     L = lib()
     s = np.zeros(1 << 11, np.int64)
@@ -164,7 +178,7 @@ def test_boot_chain():
         if l != top + 1:
             assert ctx.S[l - 1] == ctx.S[l] * ctx.S[l] / float(ctx.q[l])
     # without boot levels the chain is the computation chain alone
-    plain = ckks.Context(Params(bs.logN, bs.Lc, bs.scale_bits, bs.alpha, bs.w))
+    plain = ckks.Context(Params(bs.logN, bs.Lc, bs.scale_bits, bs.alpha, bs.w, bs.base_bits))
     assert [int(v) for v in plain.q] == [int(v) for v in ctx.q[:1]] + [int(v) for v in plain.q[1:]]
 
 
@@ -244,6 +258,37 @@ def test_mod_raise_adds_a_multiple_of_q0(boot11):
     assert max(abs(int(v)) for v in I) <= bs.K
 
 
+def decrypt_wide(ev, ct, nlimbs=2):
+    """complex slots of a ciphertext whose message exceeds q_0 / 2: the phase
+    reconstructed over the first nlimbs limbs (CRT), centred, then decoded"""
+    ctx, p = ev.ctx, ev.ctx.p
+    mods = [int(v) for v in ctx.q[:nlimbs]]
+    res = []
+    for t in range(nlimbs):
+        a = np.zeros((1, p.N), np.uint64)
+        m = ckks.u64a([mods[t]])
+        lib().oc_poly_mul(P(np.ascontiguousarray(ct.c1[t:t + 1])), P(np.ascontiguousarray(ev.keys.s_res[t:t + 1])),
+                          P(a), 1, p.logN, P(m))
+        lib().oc_poly_add(P(a), P(np.ascontiguousarray(ct.c0[t:t + 1])), P(a), 1, p.logN, P(m))
+        res.append(a[0])
+    Q = math.prod(mods)
+    big = []
+    for k in range(p.N):
+        x = sum(int(r[k]) * (Q // mm) * pow(Q // mm, -1, mm) for r, mm in zip(res, mods)) % Q
+        x = x - Q if x > Q // 2 else x
+        assert abs(x) < 2 ** 62
+        big.append(x % 2 ** 63)
+    return _decode63(ev, big, ct)
+
+
+def _decode63(ev, big, ct):
+    p = ev.ctx.p
+    re = np.zeros(p.slots)
+    im = np.zeros(p.slots)
+    lib().oc_decode_c(P(np.array(big, np.uint64)), 2 ** 63, ev.ctx.S[ct.level], p.logN, p.slots, P(re), P(im))
+    return re + 1j * im
+
+
 def test_bootstrap_refreshes_to_the_top_computation_level(boot11):
     bs, p, ctx, bp, keys, ev = boot11
     z = synth.boot_inputs(bs, 1)[0]
@@ -261,7 +306,7 @@ def test_bootstrap_refreshes_to_the_top_computation_level(boot11):
     assert np.abs(ev.decrypt(sq, p.slots) - want * want).max() < 1e-5
     # CoeffToSlot puts (t_k + i t_{k+N/2}) / (2 q0) in bit-reversed slot k: its
     # real parts near integers plus m_k / (2 q0), all within [-K/2, K/2]
-    w = ev.decrypt_c(tr["cts"], p.slots)
+    w = decrypt_wide(ev, tr["cts"])
     assert np.abs(w.real).max() <= bs.K / 2 and np.abs(w.imag).max() <= bs.K / 2
     frac = 2 * w.real - np.round(2 * w.real)
     assert np.abs(frac).max() < 1e-3

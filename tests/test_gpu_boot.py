@@ -1,0 +1,264 @@
+"""CKKS bootstrapping on the GPU against the oracle's, bit for bit: key
+material of the sparse secret, encryption at the top computation level,
+ModRaise, multiplication by i, conjugation, CoeffToSlot, EvalMod,
+SlotToCoeff and the whole refresh (single and batched) on the N = 2^11
+bootstrappable parameter set; the refreshed ciphertext decrypts to its input
+and computes.  All GPU work goes through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import boot as OB
+from oracle import ckks as O
+from paper_2409_07751_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[gpu-boot]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def oparams(bs):
+    return O.Params(bs.logN, bs.L, bs.scale_bits, bs.alpha, bs.w, bs.base_bits, bs.special_bits, bs.sigma,
+                    bs.boot_levels, bs.boot_bits, bs.h)
+
+
+def hctx(hk, bs):
+    return hk.Context(bs.logN, bs.L, bs.scale_bits, bs.alpha, bs.w, base_bits=bs.base_bits,
+                      special_bits=bs.special_bits, sigma=bs.sigma, boot_levels=bs.boot_levels,
+                      boot_bits=bs.boot_bits, hamming_weight=bs.h)
+
+
+def as_ct(c):
+    return np.stack([c.c0, c.c1])
+
+
+def imp(ctx, c):
+    return ctx.import_ct(np.ascontiguousarray(as_ct(c)), c.level)
+
+
+@pytest.fixture(scope="module")
+def b11():
+    from paper_2409_07751_amd import hekan
+    bs = synth.BOOTSETS["boot11"]
+    bp = OB.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree)
+    note("boot11 contexts")
+    ctx = hctx(hekan, bs)
+    octx = O.Context(oparams(bs))
+    plan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, bp.coeffs)
+    steps = plan.rotation_steps()
+    assert sorted(steps) == OB.rotation_steps(bs.logN, bp)
+    keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    okeys = O.Keys(octx, synth.SEED_KEYGEN, steps)
+    ev = O.Oracle(octx, okeys)
+    yield hekan, bs, bp, ctx, octx, plan, keys, ev
+    del plan
+    ctx.close()
+
+
+def test_boot_chain_and_keys_equal_oracle(b11):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    q, p, S = ctx.primes()
+    assert (q == octx.q).all() and (p == octx.pm).all() and (S == octx.S).all()
+    g = 2 * octx.p.N - 1
+    assert g in keys.ek.ids()
+    for kid in (0, g):
+        for d in (0, 3):
+            got = keys.ek.export(kid, d)
+            assert (got == okeys_digit(ev, kid, d)).all(), (kid, d)
+
+
+def okeys_digit(ev, kid, d):
+    return ev.keys.keys[kid][d]
+
+
+def test_encrypt_at_top_computation_level(b11):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    z = synth.boot_inputs(bs, 1, stream=1)[0]
+    ct = ctx.encrypt(keys, z, 77)
+    assert ct.level == bs.Lc
+    oc = ev.encrypt(z, 77)
+    assert (ct.export() == as_ct(oc)).all()
+
+
+def test_mod_raise_mul_i_conjugate_bit_exact(b11):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    oc = ev.mod_drop(ev.encrypt(synth.boot_inputs(bs, 1, stream=2)[0], 78), 0)
+    up = ctx.mod_raise(imp(ctx, oc))
+    oup = ev.mod_raise(oc)
+    assert up.level == bs.L and (up.export() == as_ct(oup)).all()
+    assert (ctx.mul_i(up).export() == as_ct(ev.mul_i(oup))).all()
+    low = ev.mod_drop(oup, 5)
+    assert (ctx.rotate(keys, imp(ctx, low), hk.STEP_CONJUGATE).export() ==
+            as_ct(ev.rotate(low, O.STEP_CONJUGATE))).all()
+    assert (ctx.sub(imp(ctx, low), ctx.mul_i(imp(ctx, low))).export() == as_ct(ev.sub(low, ev.mul_i(low)))).all()
+
+
+@pytest.fixture(scope="module")
+def trace(b11):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    oc = ev.mod_drop(ev.encrypt(synth.boot_inputs(bs, 1, stream=3)[0], 79), 1)
+    tr = {}
+    note("oracle bootstrap")
+    out = OB.bootstrap(ev, oc, bp, tr)
+    return oc, tr, out
+
+
+def test_coeff_to_slot_bit_exact(b11, trace):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    oc, tr, _ = trace
+    got = ctx.boot_coeff_to_slot(plan, keys, imp(ctx, oc))
+    assert got.level == tr["cts"].level == bs.L - bs.cts
+    assert (got.export() == as_ct(tr["cts"])).all()
+
+
+def test_eval_mod_bit_exact(b11, trace):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    _, tr, _ = trace
+    for y, u in zip(tr["split"], tr["evalmod"]):
+        got = ctx.boot_eval_mod(plan, keys, imp(ctx, y))
+        assert got.level == u.level
+        assert (got.export() == as_ct(u)).all()
+
+
+def test_slot_to_coeff_bit_exact(b11, trace):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    oc, tr, out = trace
+    got = ctx.boot_slot_to_coeff(plan, keys, imp(ctx, tr["recombined"]), oc.level)
+    assert got.level == out.level == bs.Lc
+    assert (got.export() == as_ct(out)).all()
+
+
+def test_bootstrap_bit_exact_and_accurate(b11, trace):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    oc, tr, out = trace
+    got = ctx.bootstrap(plan, keys, imp(ctx, oc))
+    assert got.level == bs.Lc
+    assert (got.export() == as_ct(out)).all()
+    want = ev.decrypt(oc, octx.p.slots)
+    y = ctx.decrypt(keys, got, octx.p.slots)
+    assert np.abs(y - want).max() < 1e-5
+    # the refreshed ciphertext computes
+    sq = ctx.mul(keys, got, got)
+    assert np.abs(ctx.decrypt(keys, sq, octx.p.slots) - want * want).max() < 1e-5
+
+
+def test_bootstrap_batch_equals_single(b11):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    zs = synth.boot_inputs(bs, 3, stream=4)
+    cts = [ctx.encrypt(keys, z, 90 + i) for i, z in enumerate(zs)]
+    # one at level 0, as bootstrapping inputs usually arrive
+    lows = [imp(ctx, ev.mod_drop(ev.encrypt(z, 90 + i), 0)) for i, z in enumerate(zs)]
+    for group in (cts, lows):
+        outs = ctx.bootstrap_batch(plan, keys, group)
+        for c, o in zip(group, outs):
+            assert (o.export() == ctx.bootstrap(plan, keys, c).export()).all()
+    for z, o in zip(zs, ctx.bootstrap_batch(plan, keys, lows)):
+        assert np.abs(ctx.decrypt(keys, o, len(z)) - z).max() < 1e-4
+
+
+def test_bootstrap_errors(b11):
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    top = imp(ctx, ev.mod_raise(ev.mod_drop(ev.encrypt(np.zeros(4), 5), 0)))
+    with pytest.raises(hk.HeError) as e:
+        ctx.bootstrap(plan, keys, top)
+    assert e.value.code == hk.HE_EINVAL
+    nokeys = ctx.keygen(1, [1])
+    with pytest.raises(hk.HeError) as e:
+        ctx.bootstrap(plan, nokeys, ctx.encrypt(keys, np.zeros(4), 6))
+    assert e.value.code == hk.HE_EKEY
+    # a context without boot levels refuses a plan
+    plain = hk.Context(bs.logN, bs.Lc, bs.scale_bits, bs.alpha, bs.w)
+    try:
+        with pytest.raises(hk.HeError) as e:
+            plain.boot(bs.cts, bs.stc, bs.K, bs.r, bp.coeffs)
+        assert e.value.code == hk.HE_EINVAL
+    finally:
+        plain.close()
+    # a plan that needs more levels than the chain keeps
+    deep = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, OB.cos_coeffs(bs.K, bs.r, 255))
+    with pytest.raises(hk.HeError) as e:
+        ctx.bootstrap(deep, keys, ctx.encrypt(keys, np.zeros(4), 7))
+    assert e.value.code == hk.HE_EDEPTH
+
+
+def kan_layers(name):
+    from oracle import kan
+    wl = synth.WORKLOADS[name]
+    raw = synth.raw_weights(wl)
+    return wl, kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * len(raw),
+                                 [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+
+
+def test_kan_with_bootstrapping_between_layers_bit_exact(b11):
+    """The [2,5,1] KAN with a bootstrapping in place of the client-aided
+    refresh: the whole inference on the server, residues equal to the
+    oracle's, decrypted output within 1e-2 of the FP64 circuit."""
+    from oracle import circuit, kan
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    wl, layers = kan_layers("tiny16")
+    model = ctx.compile(layers, refresh=True, circuit=hk.CIRCUIT_PAPER)
+    steps = sorted(set(model.rotation_steps()) | set(plan.rotation_steps()))
+    mkeys = ctx.keygen(synth.SEED_KEYGEN, steps)
+    mev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps))
+    x = synth.inputs(wl, 1)[0]
+    ct = ctx.encrypt(mkeys, x, synth.SEED_ENC)
+    note("oracle KAN with bootstrapping")
+    want = circuit.eval_kan(mev, mev.encrypt(x, synth.SEED_ENC), layers,
+                            refresh=lambda c, li: OB.bootstrap(mev, c, bp))
+    got = ctx.eval_kan_boot(model, plan, mkeys, [ct])[0]
+    assert got.level == want.level
+    assert (got.export() == as_ct(want)).all()
+    y = ctx.decrypt(mkeys, got, 1)
+    assert abs(y[0] - kan.he_friendly_kan(x[None], layers)[0][0]) < 1e-2
+
+
+def digest(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a.astype("<u8")).tobytes()).hexdigest()
+
+
+@pytest.mark.timeout(900)
+def test_boot16_full_size_equals_oracle_digests():
+    """One bootstrapping at N = 2^16 (boot16) against the digests of the
+    oracle's residues (tests/golden/boot_digests.json, written by
+    make_boot_digests.py from the oracle alone): the encrypted input,
+    CoeffToSlot and the refreshed output, bit for bit, then batched runs
+    against the single one, and the decrypted error."""
+    import json
+    import os
+    import time
+    from paper_2409_07751_amd import hekan as hk
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "boot_digests.json")))
+    bs = synth.BOOTSETS["boot16"]
+    bp = OB.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree)
+    note("boot16 context")
+    ctx = hctx(hk, bs)
+    try:
+        plan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, bp.coeffs)
+        steps = plan.rotation_steps()
+        assert sorted(steps) == gold["steps"]
+        keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+        z = synth.boot_inputs(bs, 1)[0]
+        ct = ctx.encrypt(keys, z, synth.SEED_ENC)
+        st = gold["stages"]
+        assert ct.level == st["input"]["level"] and digest(ct.export()) == st["input"]["sha256"]
+        cts = ctx.boot_coeff_to_slot(plan, keys, ct)
+        assert cts.level == st["cts"]["level"] and digest(cts.export()) == st["cts"]["sha256"]
+        t = time.time()
+        out = ctx.bootstrap(plan, keys, ct)
+        ctx.sync()
+        note("first bootstrap %.2f s (plaintexts encoded)" % (time.time() - t))
+        e = out.export()
+        for (p, l, n), v in zip(st["output"]["positions"], st["output"]["sampled"]):
+            assert int(e[p][l][n]) == v, (p, l, n)
+        assert out.level == st["output"]["level"] and digest(e) == st["output"]["sha256"]
+        y = ctx.decrypt(keys, out, len(z))
+        assert np.abs(y - z).max() < max(4 * gold["max_abs_err"], 1e-6)
+        outs = ctx.bootstrap_batch(plan, keys, [ct, ct])
+        assert all(digest(o.export()) == st["output"]["sha256"] for o in outs)
+    finally:
+        ctx.close()
