@@ -473,6 +473,18 @@ def boot_bench(args):
     out = ctx.bootstrap(plan, keys, cts[0])
     ctx.sync()
     first = time.time() - t0
+    if args.boot_profile:
+        # refreshes of one ciphertext separated by idle gaps (for a kernel trace)
+        l0 = ctx.counters()["launches"]
+        for _ in range(args.boot_reps):
+            time.sleep(0.2)
+            out = ctx.bootstrap(plan, keys, cts[0])
+            ctx.sync()
+        log("bootstrapping profile: %d refreshes, %.0f launches each" %
+            (args.boot_reps, (ctx.counters()["launches"] - l0) / args.boot_reps))
+        del out, cts, keys, model, plan
+        ctx.close()
+        return {"profile_refreshes": args.boot_reps}
     err = float(np.abs(ctx.decrypt(keys, out, z.shape[1]) - z[0]).max())
     k0 = ctx.counters()["keyswitches"]
     ctx.sync()
@@ -614,6 +626,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--no-boot", action="store_true", help="skip the bootstrapping measurement")
+    ap.add_argument("--boot-only", action="store_true", help="only the bootstrapping measurement (its own JSON line)")
+    ap.add_argument("--boot-profile", action="store_true",
+                    help="with --boot-only: refreshes of one ciphertext separated by 0.2 s idle gaps, for a trace")
     ap.add_argument("--boot-batch", type=int, default=8)
     ap.add_argument("--boot-reps", type=int, default=3)
     ap.add_argument("--table3", action="store_true",
@@ -631,6 +646,9 @@ def main():
 
     if args.table3:
         print(json.dumps(table3(args)), flush=True)
+        return
+    if args.boot_only:
+        print(json.dumps({"bootstrapping": boot_bench(args)}), flush=True)
         return
     wl = synth.WORKLOADS[args.workload]
     log("workload", wl.name, "N=2^%d" % wl.logN, "L=%d" % wl.L, "shape", wl.shape)
