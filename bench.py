@@ -494,6 +494,22 @@ def boot_bench(args):
     ctx.sync()
     single = (time.time() - t0) / args.boot_reps
     ks = (ctx.counters()["keyswitches"] - k0) / args.boot_reps
+    # the stages on their own (CoeffToSlot of the input; EvalMod and SlotToCoeff
+    # of ciphertexts at the levels they take in a refresh)
+    stages = {}
+    w = ctx.boot_coeff_to_slot(plan, keys, cts[0])
+    y = ctx.boot_eval_mod(plan, keys, w)
+    r = None
+    for name, fn in (("coeff_to_slot", lambda: ctx.boot_coeff_to_slot(plan, keys, cts[0])),
+                     ("eval_mod_one_half", lambda: ctx.boot_eval_mod(plan, keys, w)),
+                     ("slot_to_coeff", lambda: ctx.boot_slot_to_coeff(plan, keys, y, cts[0].level))):
+        ctx.sync()
+        t0 = time.time()
+        for _ in range(args.boot_reps):
+            r = fn()
+        ctx.sync()
+        stages[name] = round((time.time() - t0) / args.boot_reps * 1e3, 3)
+    del w, y, r
     outs = ctx.bootstrap_batch(plan, keys, cts)
     ctx.sync()
     t0 = time.time()
@@ -524,6 +540,7 @@ def boot_bench(args):
            "batch": B, "ms_per_batch": round(batched * 1e3, 3),
            "bootstraps_per_s_batched": round(B / batched, 2),
            "keyswitches_per_bootstrap": ks,
+           "stage_ms_b1": stages,
            "max_abs_err": max(err, errb),
            "kan_formula_with_bootstrapping": {
                "model": "KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B,
