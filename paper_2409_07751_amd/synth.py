@@ -18,7 +18,9 @@ their shapes and value ranges):
           shape), pixels U[0,1];
   toy     the tiny parameters, KAN [2,3,1] with g=2, k=1 (the grid of the
           paper's toy example of the basis construction);
-  tiny16  the tiny KAN [2,5,1] at the image parameters (uneven-shape mix).
+  tiny16  the tiny KAN [2,5,1] at the image parameters (uneven-shape mix);
+  tinydeep the tiny KAN with a depth-12 comparison composite, run with
+          bootstrapping between layers (boot11deep).
 Bootstrappable parameter sets (BOOTSETS) carry their own chains.
 Seeds: weights 1, inputs 2, keygen 3, encryption 4, arrivals 5, calibration 6.
 """
@@ -76,6 +78,12 @@ WORKLOADS = {
     # comparison needs, so the first layer runs Algorithm 2 with both PolyComps
     "toy": Workload("toy", 13, 7, 40, 1, 1, (2, 3, 1), 2, 1, (-1.0, 1.0), 15, (-4.0, 4.0),
                     ((3,), (3,)), 0.3, 0.1, "uniform_pm1", True, False),
+    # the tiny KAN with a depth-12 comparison composite (f_3 four times, 1/(2R)
+    # folded): 17 levels per layer, which the bootstrappable set boot11deep
+    # holds between refreshes; its HE-friendly network is within 1e-2 of the
+    # exact KAN (the shallow composites of the other workloads are not)
+    "tinydeep": Workload("tinydeep", 11, 17, 45, 3, 3, (2, 5, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
+                         ((7, 7, 7, 7), (7, 7, 7, 7)), 0.3, 0.1, "uniform_pm1", False, False, 55),
     # the tiny parameters with a first layer too wide for one ciphertext
     # (384 x 16 repeat-packed slots > 4096): two input ciphertexts
     "tinychunk": Workload("tinychunk", 13, 7, 40, 1, 1, (384, 4, 1), 5, 3, (-1.0, 1.0), 15, (-4.0, 4.0),
@@ -128,6 +136,8 @@ class BootSet:
 BOOTSETS = {
     "boot11": BootSet("boot11", 11, 8, 14, 45, 58, 2, 2, 32, 2, 2, 12.0, 4, 23, base_bits=55),
     "boot16": BootSet("boot16", 16, 10, 17, 45, 58, 4, 4, 192, 3, 3, 32.0, 5, 27, base_bits=51),
+    # boot11's refresh under 17 computation levels (3 special primes, 3-limb digits)
+    "boot11deep": BootSet("boot11deep", 11, 17, 14, 45, 58, 3, 3, 32, 2, 2, 12.0, 4, 23, base_bits=55),
 }
 
 

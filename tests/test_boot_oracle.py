@@ -326,3 +326,28 @@ def test_bootstrap_rotation_steps_cover_its_rotations(boot11):
     spy = Spy(ctx, keys)
     boot.bootstrap(spy, spy.mod_drop(spy.encrypt(np.zeros(4), 1), 0), bp)
     assert set(used) <= set(steps) and ckks.STEP_CONJUGATE in used
+
+
+def test_deep_composite_brings_the_circuit_within_1e2_of_the_exact_kan():
+    """Bootstrapping lets a layer spend its levels on a deep comparison: with
+    f_3 four times (depth 12) the HE-friendly tiny network is within 1e-2 of
+    the exact KAN, where the 7-level layers' f_1 is not; its layers take 17
+    levels, which boot11deep keeps between refreshes (slot simulator)."""
+    from oracle import circuit, kan
+    from oracle.slotsim import SlotSim
+    wl = synth.WORKLOADS["tinydeep"]
+    raw = synth.raw_weights(wl)
+    x = synth.inputs(wl, 200)
+    deep = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * 2,
+                             [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
+    shallow = kan.compile_model(raw, synth.calibration_inputs(wl, 512), [wl.silu_degree] * 2, [[3], [3]], wl.grid,
+                                wl.silu_range, prescale=False)
+    assert np.abs(kan.he_friendly_kan(x, deep) - kan.exact_kan(x, deep)).max() < 1e-2
+    assert np.abs(kan.he_friendly_kan(x, shallow) - kan.exact_kan(x, shallow)).max() > 0.1
+    bs = synth.BOOTSETS["boot11deep"]
+    sim = SlotSim(1 << (bs.logN - 1))
+    ct = sim.fresh(x[0], bs.Lc)
+    y, nb = circuit.layer_forward(sim, [ct], deep[0], 0, True)
+    assert y.level >= 0
+    y2, _ = circuit.layer_forward(sim, [sim.fresh(y.v, bs.Lc)], deep[1], nb, False)
+    assert y2.level >= 0 and bs.Lc - y.level == 17

@@ -262,3 +262,39 @@ def test_boot16_full_size_equals_oracle_digests():
         assert all(digest(o.export()) == st["output"]["sha256"] for o in outs)
     finally:
         ctx.close()
+
+
+def test_deep_comparison_kan_with_bootstrapping_reaches_the_exact_kan():
+    """What bootstrapping buys: the tiny KAN with a depth-12 comparison
+    composite (17 levels per layer, more than any client-refresh budget here)
+    runs whole on the server with a refresh between layers (boot11deep); the
+    first request's residues equal the oracle's, and every request decrypts
+    within 1e-4 of its FP64 circuit and within 1e-2 of the exact KAN."""
+    from oracle import circuit, kan
+    from paper_2409_07751_amd import hekan as hk
+    bs = synth.BOOTSETS["boot11deep"]
+    bp = OB.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree)
+    wl, layers = kan_layers("tinydeep")
+    ctx = hctx(hk, bs)
+    octx = O.Context(oparams(bs))
+    try:
+        plan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, bp.coeffs)
+        model = ctx.compile(layers, refresh=True, circuit=hk.CIRCUIT_PAPER)
+        steps = sorted(set(model.rotation_steps()) | set(plan.rotation_steps()))
+        keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+        ev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps))
+        xs = synth.inputs(wl, 4, stream=5)
+        cts = [ctx.encrypt(keys, x, synth.SEED_ENC + i) for i, x in enumerate(xs)]
+        outs = ctx.eval_kan_boot(model, plan, keys, cts)
+        note("oracle deep KAN with bootstrapping")
+        want = circuit.eval_kan(ev, ev.encrypt(xs[0], synth.SEED_ENC), layers,
+                                refresh=lambda c, li: OB.bootstrap(ev, c, bp))
+        assert outs[0].level == want.level and (outs[0].export() == as_ct(want)).all()
+        o2 = kan.he_friendly_kan(xs, layers)[:, 0]
+        o3 = kan.exact_kan(xs, layers)[:, 0]
+        y = np.array([ctx.decrypt(keys, o, 1)[0] for o in outs])
+        note("|y - O2| %.3g, |y - O3| %.3g" % (np.abs(y - o2).max(), np.abs(y - o3).max()))
+        assert np.abs(y - o2).max() < 1e-4 and np.abs(y - o3).max() < 1e-2
+        del outs, cts, keys, model, plan
+    finally:
+        ctx.close()
