@@ -510,6 +510,17 @@ def boot_bench(args):
         ctx.sync()
         stages[name] = round((time.time() - t0) / args.boot_reps * 1e3, 3)
     del w, y, r
+    # the refresh's largest kernel class against HBM: its launches in one
+    # refresh timed with HIP events, algorithmic bytes from the library
+    ctx.profile("ntt_fwd_pass1")
+    out = ctx.bootstrap(plan, keys, cts[0])
+    prof = ctx.profile_read()
+    ctx.profile(None)
+    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] else 0.0
+    boot_roof = {"kernel": "ntt_fwd_pass1", "bound": "hbm", "launches": prof["launches"],
+                 "avg_launch_us": round(prof["ms"] * 1e3 / max(1, prof["launches"]), 3),
+                 "algorithmic_bytes_per_launch": round(prof["bytes"] / max(1, prof["launches"])),
+                 "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 4)}
     outs = ctx.bootstrap_batch(plan, keys, cts)
     ctx.sync()
     t0 = time.time()
@@ -541,6 +552,7 @@ def boot_bench(args):
            "bootstraps_per_s_batched": round(B / batched, 2),
            "keyswitches_per_bootstrap": ks,
            "stage_ms_b1": stages,
+           "roofline_b1": boot_roof,
            "max_abs_err": max(err, errb),
            "kan_formula_with_bootstrapping": {
                "model": "KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B,

@@ -362,7 +362,9 @@ typedef struct {
 typedef struct he_boot he_boot;
 
 /* Build the bootstrapping plan (the merged diagonals of every stage group;
- * their plaintexts are encoded on first use and kept in HBM with the plan). */
+ * their plaintexts are encoded on first use and kept in HBM with the plan
+ * until he_boot_free; SlotToCoeff's first group carries the input's scale, so
+ * its plaintexts are kept once per input level used). */
 int he_boot_create(he_ctx *ctx, const he_boot_desc *desc, he_boot **out);
 int he_boot_free(he_boot *b);
 

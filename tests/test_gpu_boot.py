@@ -298,3 +298,33 @@ def test_deep_comparison_kan_with_bootstrapping_reaches_the_exact_kan():
         del outs, cts, keys, model, plan
     finally:
         ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_formula_kan_with_bootstrapping_at_n16():
+    """The [4,10,10,1] formula KAN (restructured, three 8-level layers) at
+    N = 2^16 with a refresh between layers (boot16): four requests in one
+    batch decrypt within 1e-2 of the FP64 circuit, and the batch equals the
+    requests run one at a time, bit for bit."""
+    from oracle import kan
+    from paper_2409_07751_amd import hekan as hk
+    bs = synth.BOOTSETS["boot16"]
+    bp = OB.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree)
+    wl, layers = kan_layers("formula16")
+    ctx = hctx(hk, bs)
+    try:
+        plan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, bp.coeffs)
+        model = ctx.compile(layers, refresh=True, circuit=hk.CIRCUIT_RESTRUCTURED)
+        keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(model.rotation_steps()) | set(plan.rotation_steps())))
+        xs = synth.inputs(wl, 4, stream=6)
+        cts = [ctx.encrypt(keys, x, synth.SEED_ENC + i) for i, x in enumerate(xs)]
+        outs = ctx.eval_kan_boot(model, plan, keys, cts)
+        y = np.array([ctx.decrypt(keys, o, 1)[0] for o in outs])
+        want = kan.he_friendly_kan(xs, layers)[:, 0]
+        note("formula16 with bootstrapping: max |y - FP64 circuit| %.3g" % np.abs(y - want).max())
+        assert np.abs(y - want).max() < 1e-2
+        for c, o in zip(cts[:2], outs[:2]):
+            assert (ctx.eval_kan_boot(model, plan, keys, [c])[0].export() == o.export()).all()
+        del outs, cts, keys, model, plan
+    finally:
+        ctx.close()
