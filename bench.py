@@ -98,7 +98,9 @@ def cpu_baseline(wl):
     """The CPU oracle as it stands (plain C + Python, OpenMP over RNS limbs) on
     the host cores: one whole encrypted [784,64,10] inference of the
     benchmark's circuit on one input (key generation timed apart, outside the
-    inference), with every host thread the oracle uses; then, on one thread
+    inference), with every host thread the oracle uses; the [2,5,1] (one
+    input) and [4,10,10,1] (64 vectors in one ciphertext) inferences at their
+    own parameters with the client-aided refresh, likewise; then, on one thread
     (the paper's single-thread setting), one forward limb NTT at N = 2^13,
     2^15 and 2^16 and one relinearised product and one rotation at the top
     level."""
@@ -126,6 +128,26 @@ def cpu_baseline(wl):
     y = ev.decrypt(out, wl.shape[-1])
     err = float(np.abs(y - kan.he_friendly_kan(x[None], layers)[0]).max())
     log("cpu baseline: one inference in %.1f s (%d key switches), max err %.2e" % (inf_s, n_ks, err))
+    # the two smaller configurations run fully (client-aided refresh between
+    # layers, as on the GPU at their parameters), all threads
+    full = {}
+    for name, S in (("tiny", 1), ("formula", 64)):
+        w2 = synth.WORKLOADS[name]
+        lay = kan.compile_model(synth.raw_weights(w2), synth.calibration_inputs(w2, 1024),
+                                [w2.silu_degree] * (len(w2.shape) - 1), [list(c) for c in w2.comp_degrees],
+                                w2.grid, w2.silu_range, prescale=w2.prescale)
+        c2 = O.Context(O.Params(w2.logN, w2.L, w2.scale_bits, w2.alpha, w2.w))
+        e2 = O.Oracle(c2, O.Keys(c2, synth.SEED_KEYGEN,
+                                 circuit.rotation_steps(lay, c2.p.slots, S, circ=circuit.RESTRUCTURED)))
+        X = synth.inputs(w2, S)
+        c_in = e2.encrypt(circuit.pack_samples(X, S) if S > 1 else X[0], synth.SEED_ENC)
+        t0 = time.perf_counter()
+        o2 = circuit.eval_kan(e2, c_in, lay, S=S, circ=circuit.RESTRUCTURED,
+                              refresh=lambda c, li: e2.encrypt(e2.decrypt(c, c2.p.slots), 300 + li))
+        full[name] = {"s": round(time.perf_counter() - t0, 2), "vectors": S, "key_switches": e2.count["ks"],
+                      "n": 1 << w2.logN}
+        del e2, c2, o2
+    log("cpu baseline, configurations 0-1 in full:", full)
     # one thread
     O.set_threads(1)
     L = O.lib()
@@ -156,7 +178,8 @@ def cpu_baseline(wl):
                       "excluded; decrypted within %.1e of the FP64 circuit" % (n_ks, threads, keygen_s, err),
             "inference_s": round(inf_s, 2), "keygen_s": round(keygen_s, 2),
             "single_thread": {"ntt_ms": ntt, "relinearised_product_top_level_s": round(mul_s, 3),
-                              "rotation_top_level_s": round(rot_s, 3)}}
+                              "rotation_top_level_s": round(rot_s, 3)},
+            "configs_0_1_full_inference": full}
 
 
 def word_study(args, layers, wl, x, want):
