@@ -357,6 +357,15 @@ typedef struct {
     int32_t double_angles;     /* r >= 0 */
     int32_t cos_degree;        /* >= 1 */
     const double *cos_coeffs;  /* cos_degree + 1 Chebyshev coefficients */
+    /* 0: the full-slot refresh above (complex slot values kept).  1: real slot
+     * values, SlotToCoeff first (Chen, Chillotti, Song 2019): the special DFT
+     * runs on the input's own limbs (the input must be at level >= stc_levels;
+     * it puts the slots, times 2^-7, into the low coefficients), then ModRaise,
+     * CoeffToSlot, the real half w + conj(w) through one EvalMod, and one
+     * product by q_0 / (2 pi S 2^-7) (S the scale after SlotToCoeff) landing at
+     * L_c.  The result holds the real parts of the slots; it uses
+     * cts_levels + the series' depth + double_angles + 1 boot levels. */
+    int32_t real_slots;
 } he_boot_desc;
 
 typedef struct he_boot he_boot;
@@ -503,6 +512,9 @@ int he_ctx_device_memory(he_ctx *ctx, uint64_t *free_bytes, uint64_t *total_byte
 int he_ct_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
 /* out = a - b (same level). */
 int he_ct_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+/* out = a with its limbs above `level` dropped (0 <= level <= a's level): the
+ * same plaintext, read at the canonical scale of the lower level. */
+int he_ct_mod_drop(he_ctx *ctx, const he_ct *a, int32_t level, he_ct **out);
 /* out = a X^(N/2): every slot times i (zeta^(5^j N/2) = i); exact, no level. */
 int he_ct_mul_i(he_ctx *ctx, const he_ct *a, he_ct **out);
 /* ModRaise (bootstrapping's first step): a at level 0, its residues mod q_0

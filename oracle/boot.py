@@ -57,12 +57,18 @@ from .circuit import cheb_eval, pow2ceil
 class BootParams:
     """cts_levels / stc_levels: stage groups (levels) of CoeffToSlot and
     SlotToCoeff; K: EvalMod's input range [-K, K]; r: double-angle steps;
-    coeffs: Chebyshev coefficients of cos(2 pi (y - 1/4) / 2^r) on [-K, K]."""
+    coeffs: Chebyshev coefficients of cos(2 pi (y - 1/4) / 2^r) on [-K, K];
+    real_slots: refresh real slot values with SlotToCoeff first (below)."""
     cts_levels: int
     stc_levels: int
     K: float
     r: int
     coeffs: tuple
+    real_slots: bool = False
+
+
+# SlotToCoeff-first refresh: the coefficients it writes are c1 times the slots
+REAL_C1 = 2.0 ** -7
 
 
 def cos_coeffs(K, r, degree):
@@ -77,8 +83,8 @@ def cos_coeffs(K, r, degree):
     return tuple(float(v) for v in c)
 
 
-def make_params(cts_levels, stc_levels, K, r, degree):
-    return BootParams(cts_levels, stc_levels, float(K), r, cos_coeffs(K, r, degree))
+def make_params(cts_levels, stc_levels, K, r, degree, real_slots=False):
+    return BootParams(cts_levels, stc_levels, float(K), r, cos_coeffs(K, r, degree), real_slots)
 
 
 def evalmod_plain(y, bp):
@@ -265,9 +271,50 @@ def eval_mod(ev, y, bp):
     return c
 
 
+def bootstrap_real(ev, ct, bp, trace=None):
+    """Refresh of real slot values with SlotToCoeff first (Chen, Chillotti,
+    Song 2019: the special DFT runs on the input, at its own few limbs):
+      1. F_{m-1} ... F_0 times c1 on the slots z (stc_levels groups, F_0 first,
+         landing stc_levels below the input): the plaintext's low N/2
+         coefficients become S c1 R z (S the scale there; high half: the
+         imaginary parts, zero for real z);
+      2. ModRaise and CoeffToSlot as in the full refresh: the slots hold
+         (R t_lo + i R t_hi) / (2 q_0) with R t_lo = S c1 z + q_0 R I_lo;
+      3. y = w + conj(w) = S c1 z / q_0 + integers; EvalMod gives
+         sin(2 pi y) ~ 2 pi S c1 z / q_0 (one EvalMod: the imaginary half,
+         which holds no message, is dropped);
+      4. one product by q_0 / (2 pi S c1) lands at the top computation level.
+    The input must hold stc_levels levels; the result's slots are Re z."""
+    ctx, p = ev.ctx, ev.ctx.p
+    if ct.level > p.top_level or ct.level < bp.stc_levels:
+        raise ValueError("real-slot bootstrapping input must be at a computation level >= stc_levels")
+    x = ct
+    for gi, st in enumerate(stage_groups(p.logN - 1, bp.stc_levels, ascending=True)):
+        x = linear_transform(ev, x, group_diagonals(p.logN, st, False, REAL_C1 if gi == 0 else 1.0), 1 << min(st),
+                             x.level - 1)
+    if trace is not None:
+        trace["stc_first"] = x
+    lp = x.level
+    x = ev.mod_raise(ev.mod_drop(x, 0))
+    for gi, st in enumerate(stage_groups(p.logN - 1, bp.cts_levels, ascending=False)):
+        cst = float(ctx.S[p.L]) / (2.0 * float(ctx.q[0])) if gi == 0 else 1.0
+        x = linear_transform(ev, x, group_diagonals(p.logN, st, True, cst), 1 << min(st), x.level - 1)
+    if trace is not None:
+        trace["cts"] = x
+    y = ev.add(x, ev.rotate(x, ckks.STEP_CONJUGATE))
+    u = eval_mod(ev, y, bp)
+    if trace is not None:
+        trace["evalmod"] = u
+    if u.level <= p.top_level:
+        raise ValueError("bootstrapping does not fit the boot levels")
+    return ev.lincomb([(u, float(ctx.q[0]) / (2.0 * math.pi * float(ctx.S[lp]) * REAL_C1))], p.top_level)
+
+
 def bootstrap(ev, ct, bp, trace=None):
     """The refreshed ciphertext at the top computation level (steps above).
     trace: optional dict receiving the intermediate ciphertexts."""
+    if bp.real_slots:
+        return bootstrap_real(ev, ct, bp, trace)
     ctx, p = ev.ctx, ev.ctx.p
     if ct.level > p.top_level:
         raise ValueError("bootstrapping input above the top computation level")

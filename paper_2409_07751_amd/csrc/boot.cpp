@@ -121,8 +121,8 @@ BootGroup boot_group(int logN, const std::vector<int> &stages, bool inverse, con
     return G;
 }
 
-Boot::Boot(Ctx *c, int cts, int stc, double K_, int r_, const std::vector<double> &cf_)
-    : ctx(c), cts_levels(cts), stc_levels(stc), r(r_), K(K_), cf(cf_)
+Boot::Boot(Ctx *c, int cts, int stc, double K_, int r_, const std::vector<double> &cf_, bool real_)
+    : ctx(c), cts_levels(cts), stc_levels(stc), r(r_), real(real_), K(K_), cf(cf_)
 {
     const int m = c->logN - 1;
     if (!(K > 0.0) || r < 0 || cf.size() < 2) throw HeError(-1, "bootstrapping: bad EvalMod parameters");
@@ -278,8 +278,32 @@ Ct boot_slot_to_coeff(Ctx &c, Boot &b, const Keys &k, const Ct &w_in, int src_le
     return w;
 }
 
+// Real slot values with SlotToCoeff first (Chen-Chillotti-Song 2019): the
+// special DFT F_{m-1} ... F_0 times kRealC1 runs on the input's own limbs, so
+// the plaintext's low coefficients become S kRealC1 R z (S the scale there);
+// after ModRaise and CoeffToSlot, w + conj(w) = S kRealC1 z / q_0 + integers
+// in natural slot order, one EvalMod gives 2 pi S kRealC1 z / q_0 (the
+// imaginary half holds no message and is dropped), and one product by
+// q_0 / (2 pi S kRealC1) lands at the top computation level.
+static Ct bootstrap_real(Ctx &c, Boot &b, const Keys &k, const Ct &in)
+{
+    if (in.level > c.top || in.level < (int)b.stc.size())
+        throw HeError(-1, "real-slot bootstrapping: the input must be at a computation level of at least stc_levels");
+    Ct x = in;
+    for (size_t gi = 0; gi < b.stc.size(); gi++)
+        x = lintrans(c, b, k, b.stc[gi], "F" + std::to_string(gi), gi == 0 ? kRealC1 : 1.0, x, x.level - 1);
+    const int lp = x.level;
+    Ct w = boot_coeff_to_slot(c, b, k, x);
+    Ct u = boot_eval_mod(c, b, k, c.add(w, c.rotate(w, kStepConjugate, k)));
+    if (u.level <= c.top) throw HeError(-3, "bootstrapping does not fit the levels");
+    const double kinv = (double)c.q[0] / (2.0 * M_PI * c.S[lp] * kRealC1);
+    Pt p = c.const_pt(kinv, c.S[c.top] * (double)c.q[c.top + 1] / c.S[u.level], c.top + 2);
+    return c.lincomb({{&u, &p}}, c.top);
+}
+
 Ct bootstrap(Ctx &c, Boot &b, const Keys &k, const Ct &in)
 {
+    if (b.real) return bootstrap_real(c, b, k, in);
     Ct x = boot_coeff_to_slot(c, b, k, in);
     Ct xc = c.rotate(x, kStepConjugate, k);
     // both halves through EvalMod in one batch

@@ -25,17 +25,21 @@ BootGroup boot_group(int logN, const std::vector<int> &stages, bool inverse, con
 struct Boot {
     Ctx *ctx;
     int cts_levels, stc_levels, r;
+    bool real;  // real slot values, SlotToCoeff first (bootstrap_real)
     double K;
     std::vector<double> cf;  // Chebyshev series of cos(2 pi (y - 1/4) / 2^r) on [-K, K]
     std::vector<BootGroup> cts, stc;
     std::vector<long> steps;  // rotation steps, with kStepConjugate
     std::map<std::string, Pt> pt_cache;
-    Boot(Ctx *c, int cts_levels, int stc_levels, double K, int r, const std::vector<double> &cf);
+    Boot(Ctx *c, int cts_levels, int stc_levels, double K, int r, const std::vector<double> &cf, bool real = false);
 };
 
 // refresh of nb ciphertexts (one batch) at a computation level: the result is
-// at the top computation level with the same slot values
+// at the top computation level with the same slot values (with b.real: their
+// real parts, the input at stc_levels or above)
 Ct bootstrap(Ctx &c, Boot &b, const Keys &k, const Ct &in);
+// SlotToCoeff scales the slots by this before ModRaise in the real-slot refresh
+constexpr double kRealC1 = 1.0 / 128.0;
 // its stages: ModRaise and CoeffToSlot of `in`; EvalMod of y; SlotToCoeff of
 // the recombined w for an input that was at src_level
 Ct boot_coeff_to_slot(Ctx &c, Boot &b, const Keys &k, const Ct &in);

@@ -380,7 +380,8 @@ int he_boot_create(he_ctx *ctx, const he_boot_desc *d, he_boot **out)
         need(d != nullptr && d->cos_coeffs != nullptr && d->cos_degree >= 1, "missing bootstrapping description");
         need(ctx->c->top < ctx->c->L, "the context has no boot levels");
         std::vector<double> cf(d->cos_coeffs, d->cos_coeffs + d->cos_degree + 1);
-        Boot *b = new Boot(ctx->c, d->cts_levels, d->stc_levels, d->k_range, d->double_angles, cf);
+        need(d->real_slots == 0 || d->real_slots == 1, "real_slots must be 0 or 1");
+        Boot *b = new Boot(ctx->c, d->cts_levels, d->stc_levels, d->k_range, d->double_angles, cf, d->real_slots != 0);
         *out = new he_boot{retain(ctx), b};
     });
 }
@@ -669,6 +670,16 @@ int he_ct_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out)
         check_ct(ctx, a);
         check_ct(ctx, b);
         *out = wrap(ctx, ctx->c->sub(a->c, b->c));
+    });
+}
+
+int he_ct_mod_drop(he_ctx *ctx, const he_ct *a, int32_t level, he_ct **out)
+{
+    if (!ctx || !out) return HE_EINVAL;
+    return guard(ctx, [&]() {
+        check_ct(ctx, a);
+        need(level >= 0 && level <= a->c.level, "mod_drop: level out of range");
+        *out = wrap(ctx, ctx->c->mod_drop(a->c, level));
     });
 }
 

@@ -50,7 +50,8 @@ class he_kan_desc(ctypes.Structure):
 
 class he_boot_desc(ctypes.Structure):
     _fields_ = [("cts_levels", ctypes.c_int32), ("stc_levels", ctypes.c_int32), ("k_range", ctypes.c_double),
-                ("double_angles", ctypes.c_int32), ("cos_degree", ctypes.c_int32), ("cos_coeffs", _dp)]
+                ("double_angles", ctypes.c_int32), ("cos_degree", ctypes.c_int32), ("cos_coeffs", _dp),
+                ("real_slots", ctypes.c_int32)]
 
 
 # the rotation "step" naming the complex conjugation (HE_STEP_CONJUGATE)
@@ -100,6 +101,7 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_sub": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_mul_i": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_mod_drop": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_mod_raise": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
     "he_bootstrap_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                            ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
@@ -385,9 +387,9 @@ class Context:
         # requests given as ciphertexts or as lists of input chunks, request-major
         return [c for r in cts for c in (r if isinstance(r, (list, tuple)) else [r])]
 
-    def boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs):
+    def boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots=False):
         """he_boot_create: a bootstrapping plan (see he_boot_desc)"""
-        return Boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs)
+        return Boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots)
 
     def bootstrap(self, boot, keys, ct):
         return self._new(self.lib.he_bootstrap, boot.h, _ek(keys), ct.h)
@@ -416,6 +418,9 @@ class Context:
 
     def mul_i(self, a):
         return self._new(self.lib.he_ct_mul_i, a.h)
+
+    def mod_drop(self, a, level):
+        return self._new(self.lib.he_ct_mod_drop, a.h, level)
 
     def mod_raise(self, a):
         return self._new(self.lib.he_ct_mod_raise, a.h)
@@ -620,10 +625,11 @@ class Ciphertext:
 class Boot:
     """A bootstrapping plan (he_boot_create)."""
 
-    def __init__(self, ctx, cts_levels, stc_levels, k_range, double_angles, cos_coeffs):
+    def __init__(self, ctx, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots=False):
         self.ctx = ctx
         cf = _arr(cos_coeffs, np.float64)
-        desc = he_boot_desc(cts_levels, stc_levels, float(k_range), double_angles, len(cf) - 1, _ptr(cf))
+        desc = he_boot_desc(cts_levels, stc_levels, float(k_range), double_angles, len(cf) - 1, _ptr(cf),
+                            1 if real_slots else 0)
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.he_boot_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)))
         self.h = h

@@ -116,6 +116,7 @@ class BootSet:
     base_bits: int = 60
     special_bits: int = 60
     sigma: float = 3.2
+    real_stc: int = 2  # SlotToCoeff groups of the real-slot refresh (levels it takes from its input)
 
     @property
     def L(self):

@@ -2,7 +2,8 @@
 one CKKS bootstrapping on the N = 2^16 bootstrappable parameter set (boot16 of
 paper_2409_07751_amd.synth: 51 + 10x45 + 17x58-bit primes, 4 special primes,
 4-limb digits, sparse secret of weight 192), which the GPU parity tests
-compare against.
+compare against; and the same for the real-slot refresh with SlotToCoeff
+first (`real`).
 
 Runs only the CPU oracle (oracle/) on seeded synthetic inputs; nothing here
 touches the GPU path.  The input is synth.boot_inputs(boot16, 1)[0]
@@ -49,8 +50,10 @@ def main():
     ctx = O.Context(p)
     bp = boot.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree)
     steps = boot.rotation_steps(bs.logN, bp)
+    rbp = boot.make_params(bs.cts, bs.real_stc, bs.K, bs.r, bs.degree, real_slots=True)
+    rsteps = boot.rotation_steps(bs.logN, rbp)
     t0 = time.time()
-    ev = O.Oracle(ctx, O.Keys(ctx, synth.SEED_KEYGEN, steps))
+    ev = O.Oracle(ctx, O.Keys(ctx, synth.SEED_KEYGEN, sorted(set(steps) | set(rsteps))))
     print("keygen %.0f s (%d keys)" % (time.time() - t0, len(steps)), flush=True)
     z = synth.boot_inputs(bs, 1)[0]
     ct = ev.encrypt(z, synth.SEED_ENC)
@@ -67,6 +70,18 @@ def main():
            "stages": {"input": entry(ct), "cts": entry(tr["cts"]), "evalmod_lo": entry(tr["evalmod"][0]),
                       "evalmod_hi": entry(tr["evalmod"][1]), "recombined": entry(tr["recombined"]),
                       "output": entry(out)}}
+    # the real-slot refresh (SlotToCoeff first) of the same input
+    tr = {}
+    t0 = time.time()
+    rout = boot.bootstrap(ev, ct, rbp, tr)
+    print("real-slot bootstrap %.0f s" % (time.time() - t0), flush=True)
+    rerr = float(np.abs(ev.decrypt(rout, p.slots) - ev.decrypt(ct, p.slots)).max())
+    res["real"] = {"plan": "SlotToCoeff first in %d groups, CoeffToSlot in %d, one EvalMod (K=%g, r=%d, degree %d)"
+                           % (bs.real_stc, bs.cts, bs.K, bs.r, bs.degree),
+                   "steps": rsteps, "max_abs_err": rerr,
+                   "stages": {"stc_first": entry(tr["stc_first"]), "cts": entry(tr["cts"]),
+                              "evalmod": entry(tr["evalmod"]), "output": entry(rout)}}
+    print("real-slot: max |decrypt(out) - decrypt(in)| = %.3g" % rerr, flush=True)
     with open(OUT, "w") as f:
         json.dump(res, f, indent=1)
     print("max |decrypt(out) - decrypt(in)| = %.3g; wrote %s" % (err, OUT), flush=True)

@@ -351,3 +351,41 @@ def test_deep_composite_brings_the_circuit_within_1e2_of_the_exact_kan():
     assert y.level >= 0
     y2, _ = circuit.layer_forward(sim, [sim.fresh(y.v, bs.Lc)], deep[1], nb, False)
     assert y2.level >= 0 and bs.Lc - y.level == 17
+
+
+@pytest.fixture(scope="module")
+def boot11_real(boot11):
+    bs, p, ctx, bp, keys, ev = boot11
+    return bs, p, ctx, boot.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree, real_slots=True), keys, ev
+
+
+def test_real_slot_refresh_with_slot_to_coeff_first(boot11_real):
+    """SlotToCoeff first: its output's low coefficients are c1 S R z (exactly
+    the slots, bit-reversed, up to rounding); the refresh decrypts to the
+    input's real parts from the lowest allowed level and from the top, with
+    one EvalMod and fewer key switches than the full refresh."""
+    bs, p, ctx, bp, keys, ev = boot11_real
+    z = synth.boot_inputs(bs, 1, stream=7)[0]
+    m = p.logN - 1
+    R = np.array([int(format(i, "0%db" % m)[::-1], 2) for i in range(p.slots)])
+    for lvl in (bs.stc, p.top_level):
+        ct = ev.mod_drop(ev.encrypt(z, 31), lvl)
+        tr = {}
+        before = dict(ev.count)
+        out = boot.bootstrap(ev, ct, bp, tr)
+        ks = ev.count["ks"] - before["ks"]
+        x = tr["stc_first"]
+        c = ev.phase(x).astype(object)
+        q0 = int(ctx.q[0])
+        coef = np.array([int(v) - q0 if int(v) > q0 // 2 else int(v) for v in c], dtype=np.float64)
+        S = ctx.S[x.level]
+        assert np.abs(coef[:p.slots] / (S * boot.REAL_C1) - z[R]).max() < 1e-4
+        assert np.abs(coef[p.slots:] / (S * boot.REAL_C1)).max() < 1e-4
+        got = ev.decrypt_c(out, p.slots)
+        assert out.level == p.top_level
+        assert np.abs(got.real - ev.decrypt(ct, p.slots)).max() < 1e-6 and np.abs(got.imag).max() < 1e-6
+    full = dict(ev.count)
+    boot.bootstrap(ev, ev.mod_drop(ev.encrypt(z, 32), 1), boot.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree))
+    assert ks < ev.count["ks"] - full["ks"]
+    with pytest.raises(ValueError):
+        boot.bootstrap(ev, ev.mod_drop(ev.encrypt(z, 33), bs.stc - 1), bp)

@@ -260,6 +260,22 @@ def test_boot16_full_size_equals_oracle_digests():
         assert np.abs(y - z).max() < max(4 * gold["max_abs_err"], 1e-6)
         outs = ctx.bootstrap_batch(plan, keys, [ct, ct])
         assert all(digest(o.export()) == st["output"]["sha256"] for o in outs)
+        del outs, out, cts, keys, plan
+        # the real-slot refresh (SlotToCoeff first) of the same input
+        rg = gold["real"]
+        rbp = OB.make_params(bs.cts, bs.real_stc, bs.K, bs.r, bs.degree, real_slots=True)
+        rplan = ctx.boot(bs.cts, bs.real_stc, bs.K, bs.r, rbp.coeffs, real_slots=True)
+        assert sorted(rplan.rotation_steps()) == rg["steps"]
+        rkeys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(steps) | set(rg["steps"])))
+        rct = ctx.encrypt(rkeys, z, synth.SEED_ENC)
+        assert digest(rct.export()) == st["input"]["sha256"]
+        rout = ctx.bootstrap(rplan, rkeys, rct)
+        e = rout.export()
+        for (p, l, n), v in zip(rg["stages"]["output"]["positions"], rg["stages"]["output"]["sampled"]):
+            assert int(e[p][l][n]) == v, (p, l, n)
+        assert rout.level == rg["stages"]["output"]["level"] and digest(e) == rg["stages"]["output"]["sha256"]
+        y = ctx.decrypt(rkeys, rout, len(z))
+        assert np.abs(y - z).max() < max(4 * rg["max_abs_err"], 1e-6)
     finally:
         ctx.close()
 
@@ -301,10 +317,12 @@ def test_deep_comparison_kan_with_bootstrapping_reaches_the_exact_kan():
 
 
 @pytest.mark.timeout(600)
-def test_formula_kan_with_bootstrapping_at_n16():
+@pytest.mark.parametrize("real", [False, True])
+def test_formula_kan_with_bootstrapping_at_n16(real):
     """The [4,10,10,1] formula KAN (restructured, three 8-level layers) at
-    N = 2^16 with a refresh between layers (boot16): four requests in one
-    batch decrypt within 1e-2 of the FP64 circuit, and the batch equals the
+    N = 2^16 with a refresh between layers (boot16, the full-slot refresh or
+    the real-slot one with SlotToCoeff first): four requests in one batch
+    decrypt within 1e-2 of the FP64 circuit, and the batch equals the
     requests run one at a time, bit for bit."""
     from oracle import kan
     from paper_2409_07751_amd import hekan as hk
@@ -313,7 +331,7 @@ def test_formula_kan_with_bootstrapping_at_n16():
     wl, layers = kan_layers("formula16")
     ctx = hctx(hk, bs)
     try:
-        plan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, bp.coeffs)
+        plan = ctx.boot(bs.cts, bs.real_stc if real else bs.stc, bs.K, bs.r, bp.coeffs, real_slots=real)
         model = ctx.compile(layers, refresh=True, circuit=hk.CIRCUIT_RESTRUCTURED)
         keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(model.rotation_steps()) | set(plan.rotation_steps())))
         xs = synth.inputs(wl, 4, stream=6)
@@ -328,3 +346,34 @@ def test_formula_kan_with_bootstrapping_at_n16():
         del outs, cts, keys, model, plan
     finally:
         ctx.close()
+
+
+
+def test_real_slot_refresh_bit_exact(b11):
+    """The real-slot refresh with SlotToCoeff first (he_boot_desc.real_slots)
+    against the oracle's, bit for bit, from the lowest level it accepts and
+    from the top computation level; batches equal single refreshes; an input
+    below stc_levels is refused."""
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    rbp = OB.make_params(bs.cts, bs.real_stc, bs.K, bs.r, bs.degree, real_slots=True)
+    rplan = ctx.boot(bs.cts, bs.real_stc, bs.K, bs.r, rbp.coeffs, real_slots=True)
+    assert set(rplan.rotation_steps()) <= set(plan.rotation_steps())  # the keys b11 made
+    zs = synth.boot_inputs(bs, 3, stream=8)
+    for lvl in (bs.real_stc, bs.Lc):
+        ocs = [ev.mod_drop(ev.encrypt(z, 120 + i), lvl) for i, z in enumerate(zs)]
+        want = [OB.bootstrap(ev, oc, rbp) for oc in ocs]
+        got = ctx.bootstrap(rplan, keys, imp(ctx, ocs[0]))
+        assert got.level == bs.Lc and (got.export() == as_ct(want[0])).all()
+        outs = ctx.bootstrap_batch(rplan, keys, [imp(ctx, oc) for oc in ocs])
+        for o, w, oc in zip(outs, want, ocs):
+            assert (o.export() == as_ct(w)).all()
+            assert np.abs(ctx.decrypt(keys, o, octx.p.slots) - ev.decrypt(oc, octx.p.slots)).max() < 1e-6
+    with pytest.raises(hk.HeError) as e:
+        ctx.bootstrap(rplan, keys, imp(ctx, ev.mod_drop(ev.encrypt(zs[0], 5), bs.real_stc - 1)))
+    assert e.value.code == hk.HE_EINVAL
+    # he_ct_mod_drop gives the oracle's mod-drop
+    low = ctx.mod_drop(ctx.encrypt(keys, zs[1], 121), bs.real_stc)
+    assert low.level == bs.real_stc and (low.export() == as_ct(ev.mod_drop(ev.encrypt(zs[1], 121), bs.real_stc))).all()
+    with pytest.raises(hk.HeError) as e:
+        ctx.mod_drop(low, bs.real_stc + 1)
+    assert e.value.code == hk.HE_EINVAL
