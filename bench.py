@@ -485,8 +485,11 @@ def boot_bench(args):
     layers = pc.compile_kan(raw, synth.calibration_inputs(wl, 1024), wl.silu_degree,
                             [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
     model = ctx.compile(layers, refresh=True, circuit=hekan.CIRCUIT_RESTRUCTURED)
+    # the real-slot refresh (SlotToCoeff first)
+    rplan = ctx.boot(bs.cts, bs.real_stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), real_slots=True)
     t0 = time.time()
-    keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(plan.rotation_steps()) | set(model.rotation_steps())))
+    keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(plan.rotation_steps()) | set(rplan.rotation_steps()) |
+                                                set(model.rotation_steps())))
     ctx.sync()
     log("bootstrapping: keygen %.1fs" % (time.time() - t0))
     B = args.boot_batch
@@ -498,6 +501,7 @@ def boot_bench(args):
     first = time.time() - t0
     if args.boot_profile:
         # refreshes of one ciphertext separated by idle gaps (for a kernel trace)
+        del rplan
         l0 = ctx.counters()["launches"]
         for _ in range(args.boot_reps):
             time.sleep(0.2)
@@ -553,18 +557,44 @@ def boot_bench(args):
     batched = (time.time() - t0) / args.boot_reps
     errb = max(float(np.abs(ctx.decrypt(keys, o, z.shape[1]) - z[i]).max()) for i, o in enumerate(outs))
     del outs, out
-    # the formula KAN with a bootstrapping between layers
-    x = synth.inputs(wl, B)
-    want = pc.plain_forward(x, layers)
-    kin = [ctx.encrypt(keys, x[i], synth.SEED_ENC + 100 + i) for i in range(B)]
-    kout = ctx.eval_kan_boot(model, plan, keys, kin)
+    # the real-slot refresh of an input at the lowest level it accepts, alone
+    # and in the batch
+    low = [ctx.mod_drop(c, bs.real_stc) for c in cts]
+    rout = ctx.bootstrap(rplan, keys, low[0])
+    ctx.sync()
+    k0 = ctx.counters()["keyswitches"]
+    t0 = time.time()
+    for _ in range(args.boot_reps):
+        rout = ctx.bootstrap(rplan, keys, low[0])
+    ctx.sync()
+    rsingle = (time.time() - t0) / args.boot_reps
+    rks = (ctx.counters()["keyswitches"] - k0) / args.boot_reps
+    routs = ctx.bootstrap_batch(rplan, keys, low)
     ctx.sync()
     t0 = time.time()
     for _ in range(args.boot_reps):
-        kout = ctx.eval_kan_boot(model, plan, keys, kin)
+        routs = ctx.bootstrap_batch(rplan, keys, low)
     ctx.sync()
-    kan_s = (time.time() - t0) / args.boot_reps
-    kerr = max(float(np.abs(ctx.decrypt(keys, o, wl.shape[-1]) - want[i]).max()) for i, o in enumerate(kout))
+    rbatched = (time.time() - t0) / args.boot_reps
+    rerr = max(float(np.abs(ctx.decrypt(keys, o, z.shape[1]) - z[i]).max()) for i, o in enumerate(routs))
+    del routs, rout, low
+    # the formula KAN with a bootstrapping between layers, with either refresh
+    x = synth.inputs(wl, B)
+    want = pc.plain_forward(x, layers)
+    kin = [ctx.encrypt(keys, x[i], synth.SEED_ENC + 100 + i) for i in range(B)]
+    kan = {}
+    for name, pl in (("full_slot_refresh", plan), ("real_slot_refresh", rplan)):
+        kout = ctx.eval_kan_boot(model, pl, keys, kin)
+        ctx.sync()
+        t0 = time.time()
+        for _ in range(args.boot_reps):
+            kout = ctx.eval_kan_boot(model, pl, keys, kin)
+        ctx.sync()
+        kan_s = (time.time() - t0) / args.boot_reps
+        kerr = max(float(np.abs(ctx.decrypt(keys, o, wl.shape[-1]) - want[i]).max()) for i, o in enumerate(kout))
+        kan[name] = {"inferences_per_s": round(B / kan_s, 3), "ms_per_batch": round(kan_s * 1e3, 1),
+                     "max_abs_err_vs_fp64_circuit": kerr}
+        del kout
     res = {"parameters": "boot16: N=2^16, 51 + 10x45 + 17x58-bit primes, 4 special primes, 4-limb digits, h=192",
            "plan": {"cts_levels": bs.cts, "stc_levels": bs.stc, "K": bs.K, "double_angles": bs.r,
                     "cos_degree": bs.degree, "levels": "%d -> %d" % (bs.L, bs.Lc)},
@@ -577,12 +607,15 @@ def boot_bench(args):
            "stage_ms_b1": stages,
            "roofline_b1": boot_roof,
            "max_abs_err": max(err, errb),
-           "kan_formula_with_bootstrapping": {
-               "model": "KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B,
-               "inferences_per_s": round(B / kan_s, 3), "ms_per_batch": round(kan_s * 1e3, 1),
-               "max_abs_err_vs_fp64_circuit": kerr}}
+           "real_slots": {"plan": "SlotToCoeff first in %d groups on the input's limbs, one EvalMod" % bs.real_stc,
+                          "input_level": bs.real_stc,
+                          "ms_per_bootstrap_b1": round(rsingle * 1e3, 3), "bootstraps_per_s_b1": round(1.0 / rsingle, 2),
+                          "ms_per_batch": round(rbatched * 1e3, 3), "bootstraps_per_s_batched": round(B / rbatched, 2),
+                          "keyswitches_per_bootstrap": rks, "max_abs_err": rerr},
+           "kan_formula_with_bootstrapping": dict(
+               model="KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B, **kan)}
     log("bootstrapping:", res)
-    del kout, kin, cts, keys, model, plan
+    del kin, cts, keys, model, plan, rplan
     ctx.close()
     return res
 
