@@ -577,7 +577,20 @@ def boot_bench(args):
     ctx.sync()
     rbatched = (time.time() - t0) / args.boot_reps
     rerr = max(float(np.abs(ctx.decrypt(keys, o, z.shape[1]) - z[i]).max()) for i, o in enumerate(routs))
-    del routs, rout, low
+    del routs, rout
+    # one refresh of one ciphertext replayed from a HIP graph
+    graph_ms = {}
+    for name, pl, c_in in (("full_slot", plan, cts[0]), ("real_slot", rplan, low[0])):
+        g, gouts = ctx.graph_capture_bootstrap(pl, keys, [c_in])
+        ctx.sync()
+        t0 = time.time()
+        for _ in range(args.boot_reps):
+            g.launch()
+        ctx.sync()
+        graph_ms[name] = round((time.time() - t0) / args.boot_reps * 1e3, 3)
+        g.free()
+        del gouts
+    del low
     # the formula KAN with a bootstrapping between layers, with either refresh
     x = synth.inputs(wl, B)
     want = pc.plain_forward(x, layers)
@@ -612,6 +625,7 @@ def boot_bench(args):
                           "ms_per_bootstrap_b1": round(rsingle * 1e3, 3), "bootstraps_per_s_b1": round(1.0 / rsingle, 2),
                           "ms_per_batch": round(rbatched * 1e3, 3), "bootstraps_per_s_batched": round(B / rbatched, 2),
                           "keyswitches_per_bootstrap": rks, "max_abs_err": rerr},
+           "graph_replay_ms_b1": graph_ms,
            "kan_formula_with_bootstrapping": dict(
                model="KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B, **kan)}
     log("bootstrapping:", res)

@@ -461,6 +461,14 @@ int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_key
 int he_graph_launch(he_graph *g);
 int he_graph_free(he_graph *g);
 
+/* A bootstrapping of n ciphertexts at one level (as he_bootstrap_batch)
+ * captured the same way: one eager run, then a captured run; out receives n
+ * ciphertexts, which each he_graph_launch recomputes in place from the
+ * current contents of the inputs.  Same errors as he_graph_capture_kan_batch
+ * plus those of he_bootstrap. */
+int he_graph_capture_bootstrap(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he_ct *const *in, size_t n,
+                               he_ct **out, he_graph **g);
+
 /* Run layer `layer` on n requests (all at the same level) in one batched
  * pass: the building block of layer-granular continuous batching.  For layer
  * 0, in holds n * nc ciphertexts laid out as for he_eval_kan_batch; for later

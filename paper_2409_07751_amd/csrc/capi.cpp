@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <functional>
+
 #include "handles.hpp"
 
 extern "C" {
@@ -531,6 +533,54 @@ int he_eval_kan_layer_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *
     });
 }
 
+// Capture `run` (which issues the work on the context stream and returns its
+// n outputs) into a graph: one eager run fills every cache and leaves the pool
+// holding the buffers a run needs, so the captured run makes no host transfer
+// and no synchronisation; the graph keeps `inputs` and the outputs alive and
+// owns its temporaries until it is freed.
+static void capture_graph(he_ctx *ctx, const std::function<std::vector<Ct>()> &run, const std::vector<Ct> &inputs,
+                          size_t n, he_ct **out, he_graph **g)
+{
+    Ctx &c = *ctx->c;
+    { std::vector<Ct> warm = run(); }
+    c.sync();
+    std::unique_ptr<he_graph> gr(new he_graph);
+    gr->owner = ctx;  // retained once the graph is complete
+    const int timer = c.timer.target;
+    c.timer.target = -1;
+    c.pool.hold = &gr->held;
+    std::vector<Ct> outs;
+    HIP_CHECK(hipStreamBeginCapture(c.st, hipStreamCaptureModeRelaxed));
+    try {
+        outs = run();
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(c.st, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        c.pool.hold = nullptr;
+        c.timer.target = timer;
+        for (auto &h : gr->held) c.pool.free_.emplace(h.first, h.second), c.pool.cached += h.first;
+        throw;
+    }
+    c.pool.hold = nullptr;
+    c.timer.target = timer;
+    // the graph's temporaries count as live memory until the graph is freed
+    for (auto &h : gr->held) c.pool.live += h.first;
+    const hipError_t ec = hipStreamEndCapture(c.st, &gr->graph);
+    if (ec != hipSuccess || !gr->graph) {
+        for (auto &h : gr->held) c.pool.put(h.second, h.first);
+        throw HeError(HE_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ec));
+    }
+    HIP_CHECK(hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0));
+    // captured launches were recorded, not run: one launch computes the outputs
+    HIP_CHECK(hipGraphLaunch(gr->exec, c.st));
+    for (const Ct &x : inputs) gr->keep.push_back(x);
+    for (auto &o : outs) gr->keep.push_back(o);
+    for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, outs[i]);
+    retain(ctx);
+    *g = gr.release();
+}
+
 int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_keys *k, const he_ct *const *in, size_t n,
                                he_ct **out, he_graph **g)
 {
@@ -541,50 +591,43 @@ int he_graph_capture_kan_batch(he_ctx *ctx, const he_model *m, const he_eval_key
         check_model(ctx, m, k);
         Ctx &c = *ctx->c;
         const size_t nin = m->m->n_inputs();
-        // an eager run fills every cache and leaves the pool holding the buffers a run needs,
-        // so the captured run makes no host transfer and no synchronisation
-        {
+        std::vector<Ct> inputs;
+        for (size_t i = 0; i < n * nin; i++) {
+            check_ct(ctx, in[i]);
+            inputs.push_back(in[i]->c);
+        }
+        auto run = [&]() {
             Ct res = eval_model(c, *m->m, *k->k, batch_inputs(ctx, in, n, nin));
-            if (n > 1)
-                for (size_t i = 0; i < n; i++) (void)c.unpack(res, (int)i);
+            std::vector<Ct> o;
+            for (size_t i = 0; i < n; i++) o.push_back(n == 1 ? res : c.unpack(res, (int)i));
+            return o;
+        };
+        capture_graph(ctx, run, inputs, n, out, g);
+    });
+}
+
+int he_graph_capture_bootstrap(he_ctx *ctx, he_boot *b, const he_eval_keys *k, const he_ct *const *in, size_t n,
+                               he_ct **out, he_graph **g)
+{
+    if (!ctx || !b || !k || !out || !g || !in || n == 0) return HE_EINVAL;
+    *g = nullptr;
+    for (size_t i = 0; i < n; i++) out[i] = nullptr;
+    return guard(ctx, [&]() {
+        if (b->owner != ctx) throw HeError(HE_ESTATE, "bootstrapping plan of another context");
+        check_ek(ctx, k);
+        Ctx &c = *ctx->c;
+        std::vector<Ct> inputs;
+        for (size_t i = 0; i < n; i++) {
+            check_ct(ctx, in[i]);
+            inputs.push_back(in[i]->c);
         }
-        c.sync();
-        std::unique_ptr<he_graph> gr(new he_graph);
-        gr->owner = ctx;  // retained once the graph is complete
-        const int timer = c.timer.target;
-        c.timer.target = -1;
-        c.pool.hold = &gr->held;
-        std::vector<Ct> outs;
-        HIP_CHECK(hipStreamBeginCapture(c.st, hipStreamCaptureModeRelaxed));
-        try {
-            Ct res = eval_model(c, *m->m, *k->k, batch_inputs(ctx, in, n, nin));
-            for (size_t i = 0; i < n; i++) outs.push_back(n == 1 ? res : c.unpack(res, (int)i));
-        } catch (...) {
-            hipGraph_t dead = nullptr;
-            (void)hipStreamEndCapture(c.st, &dead);
-            if (dead) (void)hipGraphDestroy(dead);
-            c.pool.hold = nullptr;
-            c.timer.target = timer;
-            for (auto &h : gr->held) c.pool.free_.emplace(h.first, h.second), c.pool.cached += h.first;
-            throw;
-        }
-        c.pool.hold = nullptr;
-        c.timer.target = timer;
-        // the graph's temporaries count as live memory until the graph is freed
-        for (auto &h : gr->held) c.pool.live += h.first;
-        const hipError_t ec = hipStreamEndCapture(c.st, &gr->graph);
-        if (ec != hipSuccess || !gr->graph) {
-            for (auto &h : gr->held) c.pool.put(h.second, h.first);
-            throw HeError(HE_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ec));
-        }
-        HIP_CHECK(hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0));
-        // captured launches were recorded, not run: one launch computes the outputs
-        HIP_CHECK(hipGraphLaunch(gr->exec, c.st));
-        for (size_t i = 0; i < n * nin; i++) gr->keep.push_back(in[i]->c);
-        for (auto &o : outs) gr->keep.push_back(o);
-        for (size_t i = 0; i < n; i++) out[i] = wrap(ctx, outs[i]);
-        retain(ctx);
-        *g = gr.release();
+        auto run = [&]() {
+            Ct res = bootstrap(c, *b->b, *k->k, batch_inputs(ctx, in, n, 1)[0]);
+            std::vector<Ct> o;
+            for (size_t i = 0; i < n; i++) o.push_back(n == 1 ? res : c.unpack(res, (int)i));
+            return o;
+        };
+        capture_graph(ctx, run, inputs, n, out, g);
     });
 }
 

@@ -80,6 +80,8 @@ _SIGS = {
                                ctypes.c_int32, _dp],
     "he_graph_capture_kan_batch": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "he_graph_capture_bootstrap": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
     "he_graph_launch": [ctypes.c_void_p],
     "he_graph_free": [ctypes.c_void_p],
     "he_ctx_profile_read": [ctypes.c_void_p, _dp, _u64p, _dp, _dp],
@@ -468,6 +470,16 @@ class Context:
         outs = (ctypes.c_void_p * n)()
         g = ctypes.c_void_p()
         self.check(self.lib.he_graph_capture_kan_batch(self.h, model.h, _ek(keys), arr, n, outs, ctypes.byref(g)))
+        return Graph(self, g), [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
+
+    def graph_capture_bootstrap(self, boot, keys, cts):
+        """he_graph_capture_bootstrap: (graph, outputs); each launch refreshes
+        the current contents of cts into the outputs"""
+        n = len(cts)
+        arr = (ctypes.c_void_p * n)(*[c.h.value for c in cts])
+        outs = (ctypes.c_void_p * n)()
+        g = ctypes.c_void_p()
+        self.check(self.lib.he_graph_capture_bootstrap(self.h, boot.h, _ek(keys), arr, n, outs, ctypes.byref(g)))
         return Graph(self, g), [Ciphertext(self, ctypes.c_void_p(outs[i])) for i in range(n)]
 
 

@@ -377,3 +377,31 @@ def test_real_slot_refresh_bit_exact(b11):
     with pytest.raises(hk.HeError) as e:
         ctx.mod_drop(low, bs.real_stc + 1)
     assert e.value.code == hk.HE_EINVAL
+
+
+@pytest.mark.parametrize("real,n", [(False, 2), (True, 1)])
+def test_graph_bootstrap_replays_equal_eager(b11, real, n):
+    """A refresh captured into a HIP graph (he_graph_capture_bootstrap): every
+    replay, with eager work of the same context between replays, reproduces
+    the eager result bit for bit."""
+    hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    stc = bs.real_stc if real else bs.stc
+    pl = ctx.boot(bs.cts, stc, bs.K, bs.r, bp.coeffs, real_slots=real) if real else plan
+    zs = synth.boot_inputs(bs, n, stream=9)
+    ocs = [ev.mod_drop(ev.encrypt(z, 140 + i), 3) for i, z in enumerate(zs)]
+    cts = [imp(ctx, oc) for oc in ocs[:n]]
+    eager = [o.export() for o in ctx.bootstrap_batch(pl, keys, cts)]
+    note("capture bootstrap, real", real, "batch", n)
+    graph, outs = ctx.graph_capture_bootstrap(pl, keys, cts)
+    ctx.sync()
+    for i in range(n):
+        assert (outs[i].export() == eager[i]).all(), "captured run, input %d" % i
+    for rep in range(3):
+        other = ctx.bootstrap_batch(pl, keys, cts[::-1])
+        graph.launch()
+        ctx.sync()
+        for i in range(n):
+            assert (outs[i].export() == eager[i]).all(), "replay %d, input %d" % (rep, i)
+            assert (other[n - 1 - i].export() == eager[i]).all(), "eager run between replays"
+    graph.free()
+    assert (outs[0].export() == eager[0]).all()
