@@ -146,9 +146,12 @@ struct Ctx {
     std::map<int, Buf> int_cache;
     std::string err;
     u64 n_ks = 0, n_rescale = 0, n_launch = 0;
-    // q_0 and the special primes on the integer path, q_1..q_L on FP64: single
-    // key switches fuse the key inner product into ModUp's second pass
+    // q_0, the special primes and any primes above q_fp_top on the integer
+    // path, q_1..q_fp_top on FP64 (fp_top = L unless the chain keeps wider
+    // boot levels on top): single key switches fuse the key inner product into
+    // ModUp's second pass on q_1..q_fp_top
     bool ks_fused = false;
+    int fp_top = 0;
     KernelTimer timer;
     void profile(int kernel_id);  // -1 disables; clears previous records
     void profile_read(double &ms, u64 &launches, double &bytes, double &ops);
