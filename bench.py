@@ -182,22 +182,44 @@ def cpu_baseline(wl):
             "configs_0_1_full_inference": full}
 
 
+# chains of the same ring with every prime below 2^46, so every limb runs on
+# exact FP64 words: 46-bit q_0, 5 special primes of 46 bits and 5-limb digits
+# (the largest digit, 46 + 4 x 45 bits, stays below P's 230 bits).  The
+# logits (up to about 3) exceed what level 0 holds with a 46-bit q_0
+# (q_0 / (2 S) = 1), so either one more 45-bit level keeps the output at
+# level 1 (26 + 5 limbs and 6 digits at the top, against the workload's 25 + 4
+# and 5), or the last layer's weights are scaled by 1/4 and the decrypted
+# logits by 4 (the same 24 levels: 25 + 5 limbs, 5 digits)
+ALL_FP64_CHAINS = ((1, 1.0), (0, 4.0))  # (extra levels, output scale)
+
+
 def word_study(args, layers, wl, x, want):
     """The batched inference (one engine, batch 16) with the default words
     (primes below 2^46 in exact FP64 arithmetic, the 60-bit primes on 64-bit
-    integer words) and with every prime on 64-bit integer words (Shoup
-    butterflies, Barrett and Montgomery products; the FP64 path off):
-    inferences/s of each.  Both compute the same residues."""
+    integer words), with every prime on 64-bit integer words (Shoup
+    butterflies, Barrett and Montgomery products; the FP64 path off), and on
+    chains whose primes are all below 2^46 (ALL_FP64_CHAINS: every limb on
+    FP64, at the price of more limbs): inferences/s of each.  The first two
+    compute the same residues."""
+    import dataclasses
     from paper_2409_07751_amd import hekan, synth
-    out = {"batch": 16}
-    for name, iw in (("fp64_path", False), ("integer_words", True)):
-        ctx = hekan.Context(wl.logN, wl.L, wl.scale_bits, wl.alpha, wl.w, integer_words=iw)
-        model = ctx.compile(layers)
+    out = {"batch": 16, "all_primes_below_2^46": []}
+    variants = [("fp64_path", (wl.L, wl.alpha, wl.w), {}, 1.0),
+                ("integer_words", (wl.L, wl.alpha, wl.w), {"integer_words": True}, 1.0)]
+    variants += [("all_primes_below_2^46", (wl.L + extra, 5, 5), {"base_bits": 46, "special_bits": 46}, osc)
+                 for extra, osc in ALL_FP64_CHAINS]
+    for name, (L, alpha, dw), kw, osc in variants:
+        ctx = hekan.Context(wl.logN, L, wl.scale_bits, alpha, dw, **kw)
+        ls = layers
+        if osc != 1.0:
+            ls = list(layers[:-1]) + [dataclasses.replace(layers[-1], wb=layers[-1].wb / osc, ws=layers[-1].ws / osc)]
+        model = ctx.compile(ls)
         keys = ctx.keygen(synth.SEED_KEYGEN, model.rotation_steps())
         cts = [ctx.encrypt(keys, x[i], synth.SEED_ENC + i) for i in range(16)]
         outs = ctx.eval_kan_batch(model, keys, cts)
         ctx.sync()
-        err = max(float(np.abs(ctx.decrypt(keys, outs[i], wl.shape[-1]) - want[i]).max()) for i in range(16))
+        err = max(float(np.abs(osc * ctx.decrypt(keys, outs[i], wl.shape[-1]) - want[i]).max()) for i in range(16))
+        out_level = outs[0].level
         del outs
         steps = max(3, args.steps // 2)
         t0 = time.perf_counter()
@@ -206,7 +228,17 @@ def word_study(args, layers, wl, x, want):
             del outs
         ctx.sync()
         el = time.perf_counter() - t0
-        out[name] = {"inferences_per_s": round(16 * steps / el, 4), "steps": steps, "max_abs_err_vs_fp64_circuit": err}
+        r = {"inferences_per_s": round(16 * steps / el, 4), "steps": steps, "max_abs_err_vs_fp64_circuit": err}
+        if kw.get("base_bits"):
+            q, pm, _ = ctx.primes()
+            r["chain"] = "%d-bit q_0 + %d x %d-bit, %d x %d-bit special primes, %d-limb digits" % (
+                int(q[0]).bit_length(), L, wl.scale_bits, alpha, int(pm[0]).bit_length(), dw)
+            r["output_level"] = out_level
+            if osc != 1.0:
+                r["output_scale"] = "last layer's weights / %g, decrypted logits x %g" % (osc, osc)
+            out[name].append(r)
+        else:
+            out[name] = r
         del cts, keys, model
         ctx.close()
     return out

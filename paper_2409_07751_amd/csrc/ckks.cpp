@@ -186,10 +186,10 @@ Ctx::Ctx(int logN_, int L_, int scale_bits, int base_bits, int alpha_, int speci
         c.r32d = (double)r32;
         c.r32c = (double)r32 / (double)m;
     }
+    fp_lo = pc[0].fp ? 0 : 1;
     fp_top = 0;
     while (fp_top + 1 <= L && pc[fp_top + 1].fp) fp_top++;
-    ks_fused = fp_top >= 1 && !pc[0].fp;
-    for (int i = fp_top + 1; i < np; i++) ks_fused = ks_fused && !pc[i].fp;
+    ks_fused = fp_top >= 1;
     d_pc_buf = alloc((sizeof(PrimeConst) * np + 7) / 8);
     HIP_CHECK(hipMemcpyAsync(d_pc_buf->p, pc.data(), sizeof(PrimeConst) * np, hipMemcpyHostToDevice, st));
     d_pc = (const PrimeConst *)d_pc_buf->p;
@@ -759,15 +759,16 @@ Buf Ctx::keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const Swit
     // the configuration chosen for this (level, batch), by default fused with spans of 8
     auto tc = ks_tune.find(std::make_pair(l, nb));
     const int cfg = tc == ks_tune.end() ? 8 : tc->second;
-    // the fused kernel handles q_1..q_min(l, fp_top); at level 0 there are none
+    // the fused kernel handles q_fp_lo..q_min(l, fp_top); level 0 takes the
+    // separate path
     if (!ks_fused || !key.fbuf || l == 0 || cfg == 0) return inner_product(modup(d, ls, es, l, nb), key);
     // ModUp with the inner product fused into the second pass on the FP64
-    // limbs [1, fp_hi); the extended digits are stored only on q_0, the limbs
-    // from fp_hi up and the special primes, whose inner product follows
-    // separately
+    // limbs [fp_lo, fp_hi); the extended digits are stored only on the other
+    // limbs (q_0 below fp_lo, the limbs from fp_hi up, the special primes),
+    // whose inner product follows separately
     n_ks += nb;
     const int nq = l + 1, next = nq + alpha, nd = ndig(l), ktot = L + 1 + alpha;
-    const int fp_hi = std::min(nq, fp_top + 1);
+    const int fp_hi = std::min(nq, fp_top + 1), n_out = fp_lo + (nq - fp_hi);
     if (nd > 16) throw HeError(-1, "key switch: " + std::to_string(nd) + " digits (at most 16 supported)");
     const LimbMap lm = lmap(nq);
     const KsTable &kt = ks_table(l);
@@ -776,13 +777,13 @@ Buf Ctx::keyswitch_acc(const u64 *d, long ls, long es, int l, int nb, const Swit
                       kt.scalef, st, &timer);
     Buf ext = alloc((size_t)nb * nd * next * N);
     Buf acc = alloc((size_t)nb * 2 * next * N);
-    ModupKeyipArgs a{1, fp_hi, 1 + (nq - fp_hi), nb, d, ls, es, (const double *)key.fbuf->p, 2l * ktot * N,
+    ModupKeyipArgs a{fp_lo, fp_hi, n_out, nb, d, ls, es, (const double *)key.fbuf->p, 2l * ktot * N,
                      (long)ktot * N, acc->p, 2l * next * N, (long)next * N, cfg};
     launch_modup_keyip(T, ext->p, nd, nq, alpha, w, nb, lm, y->p, kt.hatm, kt.hatf, kt.wide, kt.dbl, a, st, &timer);
     y.reset();
     launch_keyip(d_pc, acc->p, (long)next * N, 2l * next * N, ext->p, (long)next * N, (long)nd * next * N, d, ls, es,
-                 key.buf->p, 2l * ktot * N, (long)ktot * N, nd, 1 + (nq - fp_hi) + alpha, 1, fp_hi, nq, w, nb, lm,
-                 L1, logN, st, &timer);
+                 key.buf->p, 2l * ktot * N, (long)ktot * N, nd, n_out + alpha, fp_lo, fp_hi, nq, w, nb, lm, L1, logN,
+                 st, &timer);
     ext.reset();
     n_launch += 6;
     return acc;

@@ -146,12 +146,14 @@ struct Ctx {
     std::map<int, Buf> int_cache;
     std::string err;
     u64 n_ks = 0, n_rescale = 0, n_launch = 0;
-    // q_0, the special primes and any primes above q_fp_top on the integer
-    // path, q_1..q_fp_top on FP64 (fp_top = L unless the chain keeps wider
-    // boot levels on top): single key switches fuse the key inner product into
-    // ModUp's second pass on q_1..q_fp_top
+    // q_fp_lo..q_fp_top: the run of FP64 primes at the bottom of the chain
+    // (fp_lo = 0 if q_0 is below 2^46, else 1; fp_top = L unless the chain
+    // keeps wider boot levels on top): single key switches fuse the key inner
+    // product into ModUp's second pass on those limbs; the other limbs (q_0
+    // when it is wide, wider primes above q_fp_top, the special primes) take
+    // the stored second pass and the separate inner product
     bool ks_fused = false;
-    int fp_top = 0;
+    int fp_lo = 1, fp_top = 0;
     KernelTimer timer;
     void profile(int kernel_id);  // -1 disables; clears previous records
     void profile_read(double &ms, u64 &launches, double &bytes, double &ops);

@@ -510,6 +510,27 @@ def test_integer_words_give_the_same_residues(hk, tiny):
         ctx.close()
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("alpha,w", [(1, 1), (2, 2)])
+def test_all_fp64_chain_ops_bit_exact(hk, alpha, w):
+    """A chain with every prime below 2^46 (45-bit q_0, scale and special
+    primes at N = 2^13): every limb runs on exact FP64 words, and the fused
+    ModUp/key-product kernel covers q_0 as well.  The ring ops at levels 7, 3,
+    1 and 0 are bit-exact against the oracle, with 1- and 2-limb digits."""
+    p = O.Params(13, 7, 40, alpha, w, 45, 45)
+    octx = O.Context(p)
+    assert max(int(v) for v in list(octx.q) + list(octx.pm)) < 2 ** 46
+    ctx = hk.Context(13, 7, 40, alpha, w, base_bits=45, special_bits=45)
+    try:
+        q, pm, S = ctx.primes()
+        assert (q == octx.q).all() and (pm == octx.pm).all() and (S == octx.S).all()
+        steps = [1, 2, -1, -5, 7, 1024]
+        keys = ctx.keygen(synth.SEED_KEYGEN, steps)
+        ops_bit_exact(ctx, octx, keys, O.Keys(octx, synth.SEED_KEYGEN, steps), (7, 3, 1))
+    finally:
+        ctx.close()
+
+
 @pytest.mark.timeout(900)
 def test_kan_cifar_first_layer_residues_equal_oracle(image):
     """The first layer of [3072,128,10] at N = 2^16 with its input in two
