@@ -58,13 +58,16 @@ class BootParams:
     """cts_levels / stc_levels: stage groups (levels) of CoeffToSlot and
     SlotToCoeff; K: EvalMod's input range [-K, K]; r: double-angle steps;
     coeffs: Chebyshev coefficients of cos(2 pi (y - 1/4) / 2^r) on [-K, K];
-    real_slots: refresh real slot values with SlotToCoeff first (below)."""
+    real_slots: refresh real slot values with SlotToCoeff first (below);
+    hoist_moddown: the giant steps of each baby-step giant-step product
+    share one ModDown (linear_transform)."""
     cts_levels: int
     stc_levels: int
     K: float
     r: int
     coeffs: tuple
     real_slots: bool = False
+    hoist_moddown: bool = True
 
 
 # SlotToCoeff-first refresh: the coefficients it writes are c1 times the slots
@@ -83,8 +86,8 @@ def cos_coeffs(K, r, degree):
     return tuple(float(v) for v in c)
 
 
-def make_params(cts_levels, stc_levels, K, r, degree, real_slots=False):
-    return BootParams(cts_levels, stc_levels, float(K), r, cos_coeffs(K, r, degree), real_slots)
+def make_params(cts_levels, stc_levels, K, r, degree, real_slots=False, hoist_moddown=True):
+    return BootParams(cts_levels, stc_levels, float(K), r, cos_coeffs(K, r, degree), real_slots, hoist_moddown)
 
 
 def evalmod_plain(y, bp):
@@ -204,9 +207,11 @@ def bsgs_width(offsets, u):
     return u * pow2ceil(b)
 
 
-def linear_transform(ev, x, diags, u, t):
+def linear_transform(ev, x, diags, u, t, hoist=True):
     """sum_o diag_o * rot(x, o) at level t by baby-step giant-step:
-    sum_g rot( sum_b rot(diag_(g b1 + b), -g b1) * rot(x, b), g b1 )."""
+    sum_g rot( sum_b rot(diag_(g b1 + b), -g b1) * rot(x, b), g b1 ).
+    hoist: the giant-step rotations share one ModDown (Oracle.rotate_sum);
+    else each giant step is a rotation of its own, added in giant order."""
     offs = sorted(diags)
     b1 = bsgs_width(offs, u)
     giants = sorted(set(o // b1 for o in offs))
@@ -214,6 +219,7 @@ def linear_transform(ev, x, diags, u, t):
     xd = ev.mod_drop(x, t + 1)
     rots = {b: (xd if b == 0 else ev.rotate(xd, b)) for b in babies}
     z = None
+    items = []
     for g in giants:
         terms = []
         for b in babies:
@@ -226,10 +232,13 @@ def linear_transform(ev, x, diags, u, t):
             v.imag = np.roll(im, g * b1)
             terms.append((rots[b], v))
         inner = ev.lincomb(terms, t)
+        if hoist:
+            items.append((inner, g * b1))
+            continue
         if g:
             inner = ev.rotate(inner, g * b1)
         z = inner if z is None else ev.add(z, inner)
-    return z
+    return ev.rotate_sum(items) if hoist else z
 
 
 def transform_plan(logN, bp, S_top, q0, S_in):
@@ -291,14 +300,15 @@ def bootstrap_real(ev, ct, bp, trace=None):
     x = ct
     for gi, st in enumerate(stage_groups(p.logN - 1, bp.stc_levels, ascending=True)):
         x = linear_transform(ev, x, group_diagonals(p.logN, st, False, REAL_C1 if gi == 0 else 1.0), 1 << min(st),
-                             x.level - 1)
+                             x.level - 1, bp.hoist_moddown)
     if trace is not None:
         trace["stc_first"] = x
     lp = x.level
     x = ev.mod_raise(ev.mod_drop(x, 0))
     for gi, st in enumerate(stage_groups(p.logN - 1, bp.cts_levels, ascending=False)):
         cst = float(ctx.S[p.L]) / (2.0 * float(ctx.q[0])) if gi == 0 else 1.0
-        x = linear_transform(ev, x, group_diagonals(p.logN, st, True, cst), 1 << min(st), x.level - 1)
+        x = linear_transform(ev, x, group_diagonals(p.logN, st, True, cst), 1 << min(st), x.level - 1,
+                             bp.hoist_moddown)
     if trace is not None:
         trace["cts"] = x
     y = ev.add(x, ev.rotate(x, ckks.STEP_CONJUGATE))
@@ -323,7 +333,8 @@ def bootstrap(ev, ct, bp, trace=None):
     if trace is not None:
         trace["raised"] = x
     for st, inv, cst in plan[:bp.cts_levels]:
-        x = linear_transform(ev, x, group_diagonals(p.logN, st, inv, cst), 1 << min(st), x.level - 1)
+        x = linear_transform(ev, x, group_diagonals(p.logN, st, inv, cst), 1 << min(st), x.level - 1,
+                             bp.hoist_moddown)
     if trace is not None:
         trace["cts"] = x
     xc = ev.rotate(x, ckks.STEP_CONJUGATE)
@@ -344,5 +355,5 @@ def bootstrap(ev, ct, bp, trace=None):
         t = p.top_level if gi == len(stc) - 1 else w.level - 1
         if t < p.top_level or t >= w.level:
             raise ValueError("bootstrapping does not fit the boot levels")
-        w = linear_transform(ev, w, group_diagonals(p.logN, st, inv, cst), 1 << min(st), t)
+        w = linear_transform(ev, w, group_diagonals(p.logN, st, inv, cst), 1 << min(st), t, bp.hoist_moddown)
     return w

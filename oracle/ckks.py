@@ -63,6 +63,7 @@ def lib():
             "oc_bconv": (None, [_u64p, i32, _u64p, _u64p, i32, _u64p, i32]),
             "oc_moddown": (None, [_u64p, _u64p, i32, i32, i32, _u64p, _u64p]),
             "oc_keyswitch": (None, [_u64p, i32, _u64p, i32, i32, i32, _u64p, _u64p, i32, u64, _u64p, _u64p]),
+            "oc_keyswitch_acc": (None, [_u64p, i32, _u64p, i32, i32, i32, _u64p, _u64p, i32, u64, _u64p, _u64p]),
             "oc_chacha20_block": (None, [_u32p, u32, _u32p, _u32p]),
             "oc_sample_uniform": (None, [u64, u32, u32, u32, u64, i32, _u64p]),
             "oc_sample_ternary": (None, [u64, u32, u32, u32, i32, _i64p]),
@@ -489,6 +490,51 @@ class Oracle:
         mods = self.ctx.mods(l)
         self.lib.oc_automorph(P(np.ascontiguousarray(a.c0[:nl])), P(s0), nl, p.logN, P(mods), g)
         return Ciphertext(l, self._binop(self.lib.oc_poly_add, s0, u0, nl), u1)
+
+    def rotate_sum(self, items):
+        """sum_i rot(x_i, t_i) for (x_i, t_i) in items, all at one level, with
+        a single ModDown: each rotation's key-switch accumulators (over
+        Q_l u P, before ModDown, the automorphism applied to the extended
+        digits as in rotate) are added up and divided by P once, and the
+        rotated c_0 parts and the unrotated terms are added in Q_l (the
+        ModDown hoisted out of a sum of rotations, Bossuat, Mouchet,
+        Troncoso-Pastoriza and Hubaux 2021).  Equal to the sum of the
+        separate rotations up to the rounding of the divisions by P."""
+        p = self.ctx.p
+        l = items[0][0].level
+        nl, next_ = l + 1, l + 1 + p.alpha
+        mods_q = self.ctx.mods(l)
+        mods_qp = u64a(list(self.ctx.q[:nl]) + list(self.ctx.pm))
+        add = self.lib.oc_poly_add
+        b0 = np.zeros((nl, p.N), np.uint64)
+        b1 = np.zeros((nl, p.N), np.uint64)
+        a0 = np.zeros((next_, p.N), np.uint64)
+        a1 = np.zeros((next_, p.N), np.uint64)
+        rotated = False
+        for x, t in items:
+            assert x.level == l, (x.level, l)
+            g = self.ctx.galois_elt(t)
+            if g == 1:
+                add(P(b0), P(np.ascontiguousarray(x.c0[:nl])), P(b0), nl, p.logN, P(mods_q))
+                add(P(b1), P(np.ascontiguousarray(x.c1[:nl])), P(b1), nl, p.logN, P(mods_q))
+                continue
+            self.count["ks"] += 1
+            u0 = np.zeros((next_, p.N), np.uint64)
+            u1 = np.zeros((next_, p.N), np.uint64)
+            self.lib.oc_keyswitch_acc(P(np.ascontiguousarray(x.c1[:nl])), l, P(self.keys.keys[g]), p.L, p.alpha,
+                                      p.w, P(self.ctx.q), P(self.ctx.pm), p.logN, g, P(u0), P(u1))
+            add(P(a0), P(u0), P(a0), next_, p.logN, P(mods_qp))
+            add(P(a1), P(u1), P(a1), next_, p.logN, P(mods_qp))
+            s0 = np.zeros((nl, p.N), np.uint64)
+            self.lib.oc_automorph(P(np.ascontiguousarray(x.c0[:nl])), P(s0), nl, p.logN, P(mods_q), g)
+            add(P(b0), P(s0), P(b0), nl, p.logN, P(mods_q))
+            rotated = True
+        if rotated:
+            for a, b in ((a0, b0), (a1, b1)):
+                u = np.zeros((nl, p.N), np.uint64)
+                self.lib.oc_moddown(P(a), P(u), nl, p.alpha, p.logN, P(self.ctx.q), P(self.ctx.pm))
+                add(P(b), P(u), P(b), nl, p.logN, P(mods_q))
+        return Ciphertext(l, b0, b1)
 
     # -- plaintext products with a target level ------------------------------
     def lincomb(self, terms, t):

@@ -442,8 +442,12 @@ void oc_moddown(const u64 *a, u64 *out, int nq, int alpha, int logN, const u64 *
  * Output (u0, u1) over Q_l, coefficient form:  u0 + u1*s ~= d*s'  (or
  * sigma(d)*s' for rotations).
  */
-void oc_keyswitch(const u64 *d, int l, const u64 *keys, int L, int alpha, int w, const u64 *q,
-                  const u64 *p, int logN, u64 galois, u64 *u0, u64 *u1)
+/* The key switch before its ModDown: acc0, acc1 ([l+1+alpha][N] each, Q_l
+ * then P limbs, coefficient form, zeroed by the caller) receive
+ * sum_j ext_j * key_j over Q_l u P, ext_j the digit's ModUp with the Galois
+ * automorphism applied when galois != 0. */
+void oc_keyswitch_acc(const u64 *d, int l, const u64 *keys, int L, int alpha, int w, const u64 *q,
+                      const u64 *p, int logN, u64 galois, u64 *acc0, u64 *acc1)
 {
     u64 N = 1ULL << logN;
     int nq = l + 1, next = nq + alpha, ktot = L + 1 + alpha;
@@ -453,8 +457,6 @@ void oc_keyswitch(const u64 *d, int l, const u64 *keys, int L, int alpha, int w,
     for (int i = 0; i < alpha; i++) mods[nq + i] = p[i];
     u64 *ext = malloc((size_t)next * N * sizeof(u64));
     u64 *tmp = malloc((size_t)next * N * sizeof(u64));
-    u64 *acc0 = calloc((size_t)next * N, sizeof(u64));
-    u64 *acc1 = calloc((size_t)next * N, sizeof(u64));
     for (int j = 0; j < ndig; j++) {
         int lo = j * w, hi = lo + w < nq ? lo + w : nq;
         int nsrc = hi - lo;
@@ -490,13 +492,23 @@ void oc_keyswitch(const u64 *d, int l, const u64 *keys, int L, int alpha, int w,
             free(prod);
         }
     }
+    free(tmp);
+    free(ext);
+    free(mods);
+}
+
+void oc_keyswitch(const u64 *d, int l, const u64 *keys, int L, int alpha, int w, const u64 *q,
+                  const u64 *p, int logN, u64 galois, u64 *u0, u64 *u1)
+{
+    u64 N = 1ULL << logN;
+    int nq = l + 1, next = nq + alpha;
+    u64 *acc0 = calloc((size_t)next * N, sizeof(u64));
+    u64 *acc1 = calloc((size_t)next * N, sizeof(u64));
+    oc_keyswitch_acc(d, l, keys, L, alpha, w, q, p, logN, galois, acc0, acc1);
     oc_moddown(acc0, u0, nq, alpha, logN, q, p);
     oc_moddown(acc1, u1, nq, alpha, logN, q, p);
     free(acc1);
     free(acc0);
-    free(tmp);
-    free(ext);
-    free(mods);
 }
 
 /* ------------------------------------------------------------------------- */

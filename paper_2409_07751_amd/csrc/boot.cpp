@@ -145,7 +145,7 @@ Boot::Boot(Ctx *c, int cts, int stc, double K_, int r_, const std::vector<double
 
 // sum_o diag_o * rot(x, o) times cst at level t by baby-step giant-step:
 // sum_g rot( sum_b rot(diag_(g b1 + b), -g b1) * rot(x, b), g b1 ); the
-// baby rotations share one ModUp
+// baby rotations share one ModUp, the giant rotations one ModDown
 static Ct lintrans(Ctx &c, Boot &bt, const Keys &k, const BootGroup &G, const std::string &tag, double cst,
                    const Ct &x, int t)
 {
@@ -198,24 +198,19 @@ static Ct lintrans(Ctx &c, Boot &bt, const Keys &k, const BootGroup &G, const st
         }
     }
     std::vector<Ct> rots = c.rotate_many(xd, babies, k);
-    Ct z;
-    bool have = false;
+    std::vector<Ct> inner;
+    inner.reserve(giants.size());
+    std::vector<std::pair<const Ct *, long>> items;
     for (auto &gg : giants) {
         std::vector<std::pair<const Ct *, const Pt *>> terms;
         for (long b : gg.second) {
             const size_t bi = std::lower_bound(babies.begin(), babies.end(), b) - babies.begin();
             terms.push_back({&rots[bi], &bt.pt_cache.at(key(gg.first, b))});
         }
-        Ct inner = c.lincomb(terms, t);
-        const long g = gg.first;
-        if (!have) {
-            z = g ? c.rotate(inner, g * G.b1, k) : inner;
-            have = true;
-        } else {
-            z = g ? c.rotate_add(inner, g * G.b1, z, k) : c.add(z, inner);
-        }
+        inner.push_back(c.lincomb(terms, t));
+        items.push_back({&inner.back(), gg.first * G.b1});
     }
-    return z;
+    return c.rotate_sum(items, k);
 }
 
 // two batches of one level as one: [l+1][nb_a + nb_b][2][N]

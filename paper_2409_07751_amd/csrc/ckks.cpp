@@ -970,6 +970,51 @@ Ct Ctx::rotate_add(const Ct &a, long step, const Ct &addend, const Keys &k)
     return o;
 }
 
+Ct Ctx::rotate_sum(const std::vector<std::pair<const Ct *, long>> &items, const Keys &k)
+{
+    if (items.empty()) throw HeError(-1, "rotate_sum: no terms");
+    const int l = items[0].first->level, nb = items[0].first->nb;
+    for (auto &it : items)
+        if (it.first->level != l || it.first->nb != nb) throw HeError(-1, "rotate_sum: operand shapes differ");
+    const int nq = l + 1, next = nq + alpha;
+    const long ls = 2l * N * nb, es = 2l * N;
+    // the unrotated terms, summed
+    Ct u;
+    bool have_u = false;
+    for (auto &it : items) {
+        if (galois_elt(it.second) != 1) continue;
+        u = have_u ? add(u, *it.first) : *it.first;
+        have_u = true;
+    }
+    // the rotated terms: sigma_g of each accumulator into A (Q_l u P), sigma_g
+    // of each c_0 into b's component 0
+    Buf A;
+    Ct b;
+    for (auto &it : items) {
+        const u64 g = galois_elt(it.second);
+        if (g == 1) continue;
+        auto kit = k.galois.find(g);
+        if (kit == k.galois.end()) throw HeError(-5, "no Galois key for rotation step " + std::to_string(it.second));
+        const Ct &x = *it.first;
+        Buf acc = keyswitch_acc(x.d() + N, ls, es, l, nb, kit->second);
+        const bool first = !A;
+        if (first) {
+            A = alloc((size_t)nb * 2 * next * N);
+            b = new_ct(l, nb);
+        }
+        launch_automorph_acc(d_pc, PolySet{A->p, (long)N, (long)next * N, next, 2 * nb},
+                             PolySet{acc->p, (long)N, (long)next * N, next, 2 * nb}, g, logN, lmap(nq), !first, st);
+        launch_automorph_acc(d_pc, c0set(b), c0set(x), g, logN, lmap(nq), !first, st);
+        n_launch += 2;
+    }
+    if (!A) return u;
+    // ModDown of the summed accumulators, b's component 0 as the base and the
+    // unrotated sum as the addend
+    Ct o = new_ct(l, nb);
+    moddown_into(A, l, nb, 1, b.d(), ls, es, 1, o, have_u ? &u : nullptr);
+    return o;
+}
+
 Ct Ctx::rotate(const Ct &a, long step, const Keys &k)
 {
     u64 g = galois_elt(step);

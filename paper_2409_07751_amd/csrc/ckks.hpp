@@ -212,6 +212,11 @@ struct Ctx {
     Ct rotate(const Ct &a, long step, const Keys &k);
     // addend + rot(a, step) in one key switch (the addition runs in ModDown's last pass)
     Ct rotate_add(const Ct &a, long step, const Ct &addend, const Keys &k);
+    // sum_i rot(x_i, step_i) (one level and batch) with a single ModDown: the
+    // rotations' key-switch accumulators, permuted, are added over Q_l u P and
+    // divided by P once; the rotated c_0 parts and the unrotated terms add in
+    // Q_l (differs from the separate rotations only by ModDown's rounding)
+    Ct rotate_sum(const std::vector<std::pair<const Ct *, long>> &items, const Keys &k);
     // sum of ciphertext x plaintext terms, rescaled to level t [+ the constant *c, added in the rescale]
     Ct lincomb(const std::vector<std::pair<const Ct *, const Pt *>> &terms, int t, const double *c = nullptr);
     Ct level_down(const Ct &a, int t);

@@ -164,6 +164,28 @@ void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s)
     hipLaunchKernelGGL(k_automorph, gr, dim3(256), 0, s, out, a, g, logN);
 }
 
+// out = [out +] sigma_g(a) limb by limb (NTT form: a permutation of the
+// slots), modulo each limb's prime; a and out do not overlap
+__global__ void k_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, u64 g, int logN, LimbMap lm,
+                                int accumulate)
+{
+    const int y = blockIdx.y;
+    const int poly = y % a.npoly, limb = y / a.npoly;
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (1u << logN)) return;
+    const u64 v = a.base[limb * a.lstride + poly * a.pstride + auto_src(j, g, logN)];
+    u64 *o = out.base + limb * out.lstride + poly * out.pstride + j;
+    *o = accumulate ? addm(*o, v, pc[lm.prime(limb)].q) : v;
+}
+
+void launch_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, u64 g, int logN, LimbMap lm, bool accumulate,
+                          hipStream_t s)
+{
+    const int N = 1 << logN;
+    dim3 gr((N + 255) / 256, a.nl * a.npoly);
+    hipLaunchKernelGGL(k_automorph_acc, gr, dim3(256), 0, s, pc, out, a, g, logN, lm, accumulate ? 1 : 0);
+}
+
 __global__ void k_copy(PolySet out, PolySet a, int N)
 {
     EW_INDEX

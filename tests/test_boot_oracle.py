@@ -323,9 +323,68 @@ def test_bootstrap_rotation_steps_cover_its_rotations(boot11):
             used.append(t)
             return super().rotate(a, t)
 
+        def rotate_sum(self, items):
+            used.extend(t for _, t in items if t)
+            return super().rotate_sum(items)
+
     spy = Spy(ctx, keys)
     boot.bootstrap(spy, spy.mod_drop(spy.encrypt(np.zeros(4), 1), 0), bp)
     assert set(used) <= set(steps) and ckks.STEP_CONJUGATE in used
+    assert any(t not in (0, ckks.STEP_CONJUGATE) and abs(t) >= 8 for t in used)  # giant steps seen
+
+
+def _centered(r, q):
+    q = np.asarray(q, np.int64).reshape(-1, 1)
+    v = r.astype(np.int64) % q
+    return np.where(v > q // 2, v - q, v)
+
+
+def test_rotate_sum_is_the_sum_of_rotations_up_to_moddown_rounding(boot11):
+    """One ModDown for a sum of rotations differs from the sum of the
+    separate rotations only by the rounding of the divisions by P: the
+    difference of every component is one small integer polynomial (the same
+    integer in every limb), at most (alpha + 1) per rotated term."""
+    bs, p, ctx, bp, keys, ev = boot11
+    rng = np.random.default_rng(11)
+    steps = [0] + [t for t in boot.rotation_steps(bs.logN, bp) if t != ckks.STEP_CONJUGATE][:4]
+    for l in (p.L, p.top_level, 2):
+        items = []
+        for i, t in enumerate(steps):
+            z = rng.uniform(-1, 1, p.slots)
+            ct = ev.mod_drop(ev.encrypt(z, 40 + i), min(l, p.top_level))
+            if l > p.top_level:
+                ct = ckks.Ciphertext(l, np.array([rng.integers(0, int(ctx.q[j]), p.N, dtype=np.uint64)
+                                                  for j in range(l + 1)]),
+                                     np.array([rng.integers(0, int(ctx.q[j]), p.N, dtype=np.uint64)
+                                               for j in range(l + 1)]))
+            items.append((ct, t))
+        got = ev.rotate_sum(items)
+        ref = None
+        for ct, t in items:
+            r = ev.rotate(ct, t)
+            ref = r if ref is None else ev.add(ref, r)
+        assert got.level == ref.level == l
+        k = sum(1 for _, t in items if t)
+        for a, b in ((got.c0, ref.c0), (got.c1, ref.c1)):
+            d = _centered(a.astype(np.int64) - b.astype(np.int64), ctx.q[: l + 1])
+            assert (d == d[0]).all()
+            assert np.abs(d[0]).max() <= k * (p.alpha + 1)
+        if l <= p.top_level:
+            assert np.abs(ev.decrypt(got, p.slots) - ev.decrypt(ref, p.slots)).max() < 1e-6
+
+
+def test_hoisted_moddown_linear_transform_matches_separate_rotations(boot11):
+    """A CoeffToSlot group with its giant steps sharing one ModDown decrypts
+    to the same slots as with one rotation per giant step."""
+    bs, p, ctx, bp, keys, ev = boot11
+    z = synth.boot_inputs(bs, 1)[0]
+    x = ev.encrypt(z, 5)
+    st = boot.stage_groups(bs.logN - 1, bs.cts, ascending=False)[0]
+    D = boot.group_diagonals(bs.logN, st, True, 1.0)
+    a = boot.linear_transform(ev, x, D, 1 << min(st), x.level - 1, hoist=True)
+    b = boot.linear_transform(ev, x, D, 1 << min(st), x.level - 1, hoist=False)
+    assert a.level == b.level == x.level - 1
+    assert np.abs(ev.decrypt_c(a, p.slots) - ev.decrypt_c(b, p.slots)).max() < 1e-7
 
 
 def test_deep_composite_brings_the_circuit_within_1e2_of_the_exact_kan():
