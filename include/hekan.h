@@ -147,7 +147,7 @@ typedef struct {
      * of HE_CIRCUIT_*; 0 runs the circuit in the paper's order: Algorithm 2
      * with both PolyComps, W_f times the bases and W_b times the SiLU values
      * as two products, each folded over all slots).  None changes a value of
-     * the FP64 circuit; each cuts key switches. */
+     * the FP64 circuit; each cuts key switches or their ModDowns. */
     int32_t circuit;
 } he_kan_desc;
 
@@ -163,7 +163,14 @@ enum {
     /* A hidden layer's block layout repeats with the shortest power-of-two
      * period that holds its blocks; the fold runs over one period. */
     HE_CIRCUIT_FOLDED_PERIOD = 4,
-    HE_CIRCUIT_RESTRUCTURED = 7,
+    /* The giant-step rotations of each baby-step giant-step product share one
+     * ModDown: their key-switch accumulators, each permuted by its
+     * automorphism, are added over Q_l u P and divided by P once (Bossuat,
+     * Mouchet, Troncoso-Pastoriza and Hubaux 2021).  Changes residues only by
+     * the rounding of those divisions. */
+    HE_CIRCUIT_SHARED_MODDOWN = 16,
+    /* every restructuring */
+    HE_CIRCUIT_RESTRUCTURED = 23,
     /* Not a restructuring: the comparison method of the paper's experiments
      * on the basis approximation, without lazy combination.  The bases are
      * moved from ColTile order into row order by a homomorphic permutation

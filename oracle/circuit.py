@@ -17,8 +17,9 @@ the layer input in blocks of n_blk slots, in the paper's order (`PAPER`):
     over all slots, so each output is periodic with period d = next power of
     two >= n_out (the next layer's repeat packing comes for free); the layer
     output is their sum.
-Three restructurings (`Circuit`) change no value of the FP64 circuit and cut
-key switches; each is a named option, checked against the paper's order:
+Four restructurings (`Circuit`) change no value of the FP64 circuit and cut
+key switches or their ModDowns; each is a named option, checked against the
+paper's order:
   * shared_comparison: when the input holds g+2k+1 blocks, the second
     comparison S((t_{m+2} - x)/2R) is 1 - S((x - t_{m+2})/2R) (the composite
     is odd), i.e. 1 minus the first comparison of block m+1: one rotation
@@ -30,6 +31,10 @@ key switches; each is a named option, checked against the paper's order:
   * folded_period: a hidden layer's block layout repeats with the shortest
     power-of-two period that holds its blocks, and the fold runs over one
     period;
+  * shared_moddown: the giant-step rotations of each baby-step giant-step
+    product share one ModDown (Oracle.rotate_sum: their key-switch
+    accumulators are added over Q_l u P and divided by P once), which changes
+    the residues by the rounding of those divisions only;
   * a first layer whose repeat-packed footprint n_i 2^ceil(log2(g+2k))
     exceeds the slot count takes its input as several ciphertexts, one per
     chunk of consecutive features: each chunk is packed and expanded on its
@@ -63,10 +68,11 @@ class Circuit:
     fused_linear: bool = False
     folded_period: bool = False
     naive_permutation: bool = False
+    shared_moddown: bool = False
 
 
 PAPER = Circuit()
-RESTRUCTURED = Circuit(True, True, True)
+RESTRUCTURED = Circuit(True, True, True, False, True)
 
 
 def pow2ceil(n):
@@ -310,29 +316,34 @@ def bsgs_split(d):
     return b1, d // b1
 
 
-def matvec_partial(ev, x, M, d, t, S=1, period=None):
+def matvec_partial(ev, x, M, d, t, S=1, period=None, shared_moddown=False):
     """z = sum_{i<d} diag_{iS} * rot(x, iS) at level t by baby-step giant-step:
     z = sum_gi rot( sum_bi rot(diag_{(gi b1 + bi) S}, -gi b1 S) * rot(x, bi S), gi b1 S ),
     diagonals of M taken with output period d S (for S = 1 every diagonal i < d;
     for M = W (x) I_S the others are zero).  x is mod-dropped to t+1 before
     the baby-step rotations.  If x repeats every `period` slots, so do the
-    diagonals, and z needs folding within one period only."""
+    diagonals, and z needs folding within one period only.  shared_moddown:
+    the giant-step rotations share one ModDown (ev.rotate_sum)."""
     slots = ev.ctx.p.slots
     b1, g1 = bsgs_split(d)
     D = d * S
     xd = ev.mod_drop(x, t + 1)
     rots = [xd] + [ev.rotate(xd, bi * S) for bi in range(1, b1)]
     z = None
+    items = []
     for gi in range(g1):
         terms = []
         for bi in range(b1):
             dv = np.roll(diag_vector(M, D, (gi * b1 + bi) * S, slots, period), gi * b1 * S)
             terms.append((rots[bi], dv))
         inner = ev.lincomb(terms, t)
+        if shared_moddown:
+            items.append((inner, gi * b1 * S))
+            continue
         if gi:
             inner = ev.rotate(inner, gi * b1 * S)
         z = inner if z is None else ev.add(z, inner)
-    return z
+    return ev.rotate_sum(items) if shared_moddown else z
 
 
 def fold(ev, z, d, period=None):
@@ -481,7 +492,7 @@ def layer_part(ev, x, L, n_blk, first, d, S=1, circ=PAPER):
         t = min(b.level, s.level) - 1
         z = ev.add(ev.mod_drop(b, t + 1), ev.mod_drop(s, t + 1))
         W = strided(np.hstack([fused_weights(L, L.n_in), L.wb]), S, nb + 1, n_blk)
-        return [matvec_partial(ev, z, W, d, t, S, period)]
+        return [matvec_partial(ev, z, W, d, t, S, period, circ.shared_moddown)]
     s = cheb_eval(ev, x, L.silu_coeffs, L.silu_lo, L.silu_hi)
     Wb = strided(L.wb, S, 1, n_blk)
     if circ.naive_permutation:
@@ -489,10 +500,12 @@ def layer_part(ev, x, L, n_blk, first, d, S=1, circ=PAPER):
         bp = permute(ev, b, L, n_blk, S, b.level - 1)
         t = min(bp.level, s.level) - 1
         Wr = strided(lazy_weights(L), S, 1, L.n_in * nb * S)
-        return [matvec_partial(ev, bp, Wr, d, t, S, period), matvec_partial(ev, s, Wb, d, t, S, period)]
+        return [matvec_partial(ev, bp, Wr, d, t, S, period, circ.shared_moddown),
+                matvec_partial(ev, s, Wb, d, t, S, period, circ.shared_moddown)]
     t = min(b.level, s.level) - 1
     Wf = strided(fused_weights(L, L.n_in), S, nb, n_blk)
-    return [matvec_partial(ev, b, Wf, d, t, S, period), matvec_partial(ev, s, Wb, d, t, S, period)]
+    return [matvec_partial(ev, b, Wf, d, t, S, period, circ.shared_moddown),
+            matvec_partial(ev, s, Wb, d, t, S, period, circ.shared_moddown)]
 
 
 def layer_forward(ev, xs, L, n_blk, first, S=1, circ=PAPER):

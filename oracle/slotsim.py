@@ -85,6 +85,16 @@ class SlotSim:
         self.rot_steps.add(t)
         return SimCt(a.level, np.roll(a.v, -t))
 
+    def rotate_sum(self, items):
+        """sum_i rot(x_i, t_i), the rotations sharing one ModDown (no
+        difference on plain vectors)."""
+        level = items[0][0].level
+        acc = np.zeros(self.ctx.p.slots)
+        for x, t in items:
+            assert x.level == level
+            acc = acc + self.rotate(x, t).v
+        return SimCt(level, acc)
+
     def lincomb(self, terms, t):
         acc = np.zeros(self.ctx.p.slots)
         for ct, z in terms:

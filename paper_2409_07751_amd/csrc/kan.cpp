@@ -518,6 +518,11 @@ struct Eval {
         std::vector<Ct> rots = c.rotate_many(xd, bsteps, k);
         Ct z;
         bool have = false;
+        // with the shared ModDown: the giant steps' inner sums, rotated and
+        // summed by one rotate_sum
+        std::vector<Ct> inner_g;
+        inner_g.reserve(g1);
+        std::vector<std::pair<const Ct *, long>> items;
         for (long gi = 0; gi < g1; gi++) {
             std::vector<std::pair<const Ct *, const Pt *>> terms;
             for (int bi = 0; bi < b1; bi++) {
@@ -534,6 +539,11 @@ struct Eval {
                 terms.push_back({&rots[bi], pp});
             }
             Ct inner = c.lincomb(terms, t);
+            if (m.shared_moddown()) {
+                inner_g.push_back(inner);
+                items.push_back({&inner_g.back(), gi * b1 * S});
+                continue;
+            }
             if (!have) {
                 z = gi ? c.rotate(inner, gi * b1 * S, k) : inner;
                 have = true;
@@ -541,7 +551,7 @@ struct Eval {
                 z = gi ? c.rotate_add(inner, gi * b1 * S, z, k) : c.add(z, inner);
             }
         }
-        return z;
+        return m.shared_moddown() ? c.rotate_sum(items, k) : z;
     }
 
     // the naive method's permutation of the bases b into row order at level t

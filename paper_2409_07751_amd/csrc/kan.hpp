@@ -47,6 +47,7 @@ struct Model {
     bool fused() const { return (circ & HE_CIRCUIT_FUSED_LINEAR) != 0; }
     bool folded() const { return (circ & HE_CIRCUIT_FOLDED_PERIOD) != 0; }
     bool naive() const { return (circ & HE_CIRCUIT_NAIVE_PERMUTATION) != 0; }
+    bool shared_moddown() const { return (circ & HE_CIRCUIT_SHARED_MODDOWN) != 0; }
     std::vector<LayerC> layers;
     std::vector<long> steps;
     std::unordered_map<std::string, Pt> pt_cache;   // Montgomery NTT plaintexts for lincombs

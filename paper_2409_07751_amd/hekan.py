@@ -60,7 +60,8 @@ STEP_CONJUGATE = -(1 << 31)
 # he_kan_desc.circuit: restructurings of the paper's layer circuit (0 = the paper's order)
 CIRCUIT_PAPER = 0
 CIRCUIT_SHARED_COMPARISON, CIRCUIT_FUSED_LINEAR, CIRCUIT_FOLDED_PERIOD = 1, 2, 4
-CIRCUIT_RESTRUCTURED = 7
+CIRCUIT_SHARED_MODDOWN = 16
+CIRCUIT_RESTRUCTURED = 23
 CIRCUIT_NAIVE_PERMUTATION = 8
 
 

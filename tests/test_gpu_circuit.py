@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 # he_kan_desc.circuit bits: 1 shared comparison, 2 fused linear layers, 4 folded period,
 # 8 no lazy combination (the naive permutation)
-VARIANTS = [0, 1, 2, 4, 7]
+VARIANTS = [0, 1, 2, 4, 16, 23]
 
 
 def note(*a):
@@ -30,7 +30,7 @@ def note(*a):
 
 
 def oracle_circuit(flags):
-    return circuit.Circuit(bool(flags & 1), bool(flags & 2), bool(flags & 4), bool(flags & 8))
+    return circuit.Circuit(bool(flags & 1), bool(flags & 2), bool(flags & 4), bool(flags & 8), bool(flags & 16))
 
 
 def model_layers(wl):
@@ -94,7 +94,7 @@ def test_toy_two_polycomp_branch_bit_exact(hk):
     wl = synth.WORKLOADS["toy"]
     # the first layer cannot share the comparison: 4 copies < g+2k+1 = 5 blocks
     assert (1 << (wl.g + 2 * wl.k - 1).bit_length()) < wl.g + 2 * wl.k + 1
-    run_variants(hk, "toy", [0, 7])
+    run_variants(hk, "toy", [0, 23])
 
 
 def test_toy_without_lazy_combination_bit_exact(hk):

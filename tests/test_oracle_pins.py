@@ -501,7 +501,7 @@ def compiled_layers(name, ncal=512):
 
 CIRCUITS = {"paper": circuit.PAPER, "shared": circuit.Circuit(shared_comparison=True),
             "fused": circuit.Circuit(fused_linear=True), "folded": circuit.Circuit(folded_period=True),
-            "restructured": circuit.RESTRUCTURED}
+            "shared_moddown": circuit.Circuit(shared_moddown=True), "restructured": circuit.RESTRUCTURED}
 
 
 @pytest.mark.parametrize("circ", list(CIRCUITS))
