@@ -39,7 +39,7 @@ NTT_KERNELS = ("ntt_fwd_pass1", "ntt_fwd_pass2", "ntt_inv_pass2", "ntt_inv_pass1
 # the default key-switch configuration (--no-autotune: the column pass's
 # launches are the same in every configuration, the row pass's are not);
 # emptied whenever the kernel changes until the counters are taken again
-TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 308710000, "ntt_fwd_pass2": 483240000}
+TRAFFIC_BYTES_PER_LAUNCH = {"ntt_fwd_pass1": 308730000, "ntt_fwd_pass2": 482820000}
 TRAFFIC_SOURCE = "profiles/%s_image_b16_hbm_traffic.md (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a copy)"
 # Instruction issue of the same launches: wave64 VALU instructions per launch
 # (rocprofv3 SQ_INSTS_VALU summed over the class's dispatches of one timed
@@ -49,7 +49,7 @@ TRAFFIC_SOURCE = "profiles/%s_image_b16_hbm_traffic.md (rocprofv3 FETCH_SIZE + W
 # 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G instructions/s.  Emptied whenever
 # the kernel changes until the counters are taken again.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
-VALU_INSTS_PER_LAUNCH = {"ntt_fwd_pass1": 62606796, "ntt_fwd_pass2": 36468501}
+VALU_INSTS_PER_LAUNCH = {"ntt_fwd_pass1": 62606796, "ntt_fwd_pass2": 36462952}
 VALU_SOURCE = "profiles/%s_image_b16_valu.md (rocprofv3 SQ_INSTS_VALU)"
 
 

@@ -986,10 +986,10 @@ Ct Ctx::rotate_sum(const std::vector<std::pair<const Ct *, long>> &items, const 
         u = have_u ? add(u, *it.first) : *it.first;
         have_u = true;
     }
-    // the rotated terms: sigma_g of each accumulator into A (Q_l u P), sigma_g
-    // of each c_0 into b's component 0
+    // the rotated terms: sigma_g of each accumulator into A (Q_l u P), with
+    // P sigma_g(c_0) added to component 0's Q limbs (ModDown's division by P
+    // makes it sigma_g(c_0), exactly, as in a single rotation's tail)
     Buf A;
-    Ct b;
     for (auto &it : items) {
         const u64 g = galois_elt(it.second);
         if (g == 1) continue;
@@ -998,20 +998,16 @@ Ct Ctx::rotate_sum(const std::vector<std::pair<const Ct *, long>> &items, const 
         const Ct &x = *it.first;
         Buf acc = keyswitch_acc(x.d() + N, ls, es, l, nb, kit->second);
         const bool first = !A;
-        if (first) {
-            A = alloc((size_t)nb * 2 * next * N);
-            b = new_ct(l, nb);
-        }
+        if (first) A = alloc((size_t)nb * 2 * next * N);
         launch_automorph_acc(d_pc, PolySet{A->p, (long)N, (long)next * N, next, 2 * nb},
-                             PolySet{acc->p, (long)N, (long)next * N, next, 2 * nb}, g, logN, lmap(nq), !first, st);
-        launch_automorph_acc(d_pc, c0set(b), c0set(x), g, logN, lmap(nq), !first, st);
-        n_launch += 2;
+                             PolySet{acc->p, (long)N, (long)next * N, next, 2 * nb}, c0set(x), pmod->p,
+                             pmod->p + L + 1, g, logN, lmap(nq), nq, !first, st);
+        n_launch++;
     }
     if (!A) return u;
-    // ModDown of the summed accumulators, b's component 0 as the base and the
-    // unrotated sum as the addend
+    // ModDown of the summed accumulators, the unrotated sum as the addend
     Ct o = new_ct(l, nb);
-    moddown_into(A, l, nb, 1, b.d(), ls, es, 1, o, have_u ? &u : nullptr);
+    moddown_into(A, l, nb, 1, nullptr, 0, 0, 0, o, have_u ? &u : nullptr);
     return o;
 }
 

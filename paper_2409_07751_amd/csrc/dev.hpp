@@ -103,9 +103,12 @@ void launch_lincomb(const PrimeConst *pc, PolySet out, const u64 *const *a_bases
                     int N, hipStream_t s);
 // automorphism in the NTT domain, out[j] = a[perm_g(j)]
 void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s);
-// out[j] = [out[j] +] a[perm_g(j)] modulo each limb's prime (lm)
-void launch_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, u64 g, int logN, LimbMap lm, bool accumulate,
-                          hipStream_t s);
+// out[j] = [out[j] +] a[perm_g(j)] modulo each limb's prime (lm), plus on
+// component 0 (even polynomials) of the Q limbs (< nq) pm[i] c0[perm_g(j)]
+// (pm: P mod q_i by prime index, pmp its Shoup words); c0 holds one
+// polynomial per pair of a's
+void launch_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, PolySet c0, const u64 *pm, const u64 *pmp,
+                          u64 g, int logN, LimbMap lm, int nq, bool accumulate, hipStream_t s);
 // inner product of the extended digits with a switching key (NTT +
 // Montgomery form): acc_c[t] = sum_j e_j[t] * key_j[c][kt(t)], c = 0, 1, where
 // e_j[t] is the input d itself on digit j's own limbs and ext_j[t] elsewhere.

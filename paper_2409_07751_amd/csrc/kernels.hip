@@ -164,26 +164,36 @@ void launch_automorph(PolySet out, PolySet a, u64 g, int logN, hipStream_t s)
     hipLaunchKernelGGL(k_automorph, gr, dim3(256), 0, s, out, a, g, logN);
 }
 
-// out = [out +] sigma_g(a) limb by limb (NTT form: a permutation of the
-// slots), modulo each limb's prime; a and out do not overlap
-__global__ void k_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, u64 g, int logN, LimbMap lm,
-                                int accumulate)
+// One rotation's share of a sum of rotations with a single ModDown: out
+// (the running sum of accumulators, polynomial 2 e + c over Q_l u P) [+]=
+// sigma_g(a) limb by limb (NTT form: a permutation of the slots), and on
+// component 0's Q limbs (limb < nq) also [P]_{q_limb} sigma_g(c0_e), which the
+// division by P in ModDown turns into sigma_g(c0_e) exactly; a, c0 and out
+// do not overlap
+__global__ void k_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, PolySet c0, const u64 *pm,
+                                const u64 *pmp, u64 g, int logN, LimbMap lm, int nq, int accumulate)
 {
     const int y = blockIdx.y;
     const int poly = y % a.npoly, limb = y / a.npoly;
     const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (1u << logN)) return;
-    const u64 v = a.base[limb * a.lstride + poly * a.pstride + auto_src(j, g, logN)];
+    const u32 src = auto_src(j, g, logN);
+    const int pr = lm.prime(limb);
+    const u64 q = pc[pr].q;
+    u64 v = a.base[limb * a.lstride + poly * a.pstride + src];
+    if ((poly & 1) == 0 && limb < nq)
+        v = addm(v, shoup(c0.base[limb * c0.lstride + (poly >> 1) * c0.pstride + src], pm[pr], pmp[pr], q), q);
     u64 *o = out.base + limb * out.lstride + poly * out.pstride + j;
-    *o = accumulate ? addm(*o, v, pc[lm.prime(limb)].q) : v;
+    *o = accumulate ? addm(*o, v, q) : v;
 }
 
-void launch_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, u64 g, int logN, LimbMap lm, bool accumulate,
-                          hipStream_t s)
+void launch_automorph_acc(const PrimeConst *pc, PolySet out, PolySet a, PolySet c0, const u64 *pm, const u64 *pmp,
+                          u64 g, int logN, LimbMap lm, int nq, bool accumulate, hipStream_t s)
 {
     const int N = 1 << logN;
     dim3 gr((N + 255) / 256, a.nl * a.npoly);
-    hipLaunchKernelGGL(k_automorph_acc, gr, dim3(256), 0, s, pc, out, a, g, logN, lm, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_automorph_acc, gr, dim3(256), 0, s, pc, out, a, c0, pm, pmp, g, logN, lm, nq,
+                       accumulate ? 1 : 0);
 }
 
 __global__ void k_copy(PolySet out, PolySet a, int N)
