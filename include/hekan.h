@@ -539,6 +539,17 @@ int he_ct_mod_raise(he_ctx *ctx, const he_ct *a, he_ct **out);
 int he_ct_mul(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, const he_ct *b, he_ct **out);
 /* out = rot(a, step): slots move left by step (right if negative). */
 int he_ct_rotate(he_ctx *ctx, const he_eval_keys *ek, const he_ct *a, int32_t step, he_ct **out);
+/* out = sum_i rot(in[i], steps[i]) for n >= 1 ciphertexts of one level and
+ * batch size (steps[i] = 0: the term is added as it is) with a single
+ * ModDown: each rotation's key-switch accumulators over Q_l u P, permuted by
+ * its automorphism, plus P times its permuted c_0, are added and divided by P
+ * once (the giant steps of a baby-step giant-step product; Bossuat, Mouchet,
+ * Troncoso-Pastoriza and Hubaux 2021).  The residues differ from those of n
+ * separate he_ct_rotate calls added up only by the rounding of the divisions
+ * by P.  HE_ESHAPE if the levels or batch sizes differ, HE_EKEY if a step has
+ * no key. */
+int he_ct_rotate_sum(he_ctx *ctx, const he_eval_keys *ek, const he_ct *const *in, const int32_t *steps, size_t n,
+                     he_ct **out);
 /* out = rescale(a): divide by q_level with rounding, drop one limb. */
 int he_ct_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -706,6 +706,24 @@ int he_ct_rotate(he_ctx *ctx, const he_eval_keys *k, const he_ct *a, int32_t ste
     });
 }
 
+int he_ct_rotate_sum(he_ctx *ctx, const he_eval_keys *k, const he_ct *const *in, const int32_t *steps, size_t n,
+                     he_ct **out)
+{
+    if (!ctx || !k || !out || !in || !steps || n == 0) return HE_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&]() {
+        check_ek(ctx, k);
+        std::vector<std::pair<const Ct *, long>> items;
+        for (size_t i = 0; i < n; i++) {
+            check_ct(ctx, in[i]);
+            if (in[i]->c.level != in[0]->c.level || in[i]->c.nb != in[0]->c.nb)
+                throw HeError(HE_ESHAPE, "rotate_sum: the ciphertexts differ in level or batch size");
+            items.push_back({&in[i]->c, (long)steps[i]});
+        }
+        *out = wrap(ctx, ctx->c->rotate_sum(items, *k->k));
+    });
+}
+
 int he_ct_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out)
 {
     if (!ctx || !out) return HE_EINVAL;

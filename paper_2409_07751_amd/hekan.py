@@ -151,6 +151,8 @@ _SIGS = {
                   ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_rotate": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                      ctypes.POINTER(ctypes.c_void_p)],
+    "he_ct_rotate_sum": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_rescale": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
     "he_ct_rescale_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "he_ct_lincomb": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, _dp, ctypes.c_size_t,
@@ -312,6 +314,14 @@ class Context:
 
     def rotate(self, keys, a, step):
         return self._new(self.lib.he_ct_rotate, _ek(keys), a.h, step)
+
+    def rotate_sum(self, keys, cts, steps):
+        """he_ct_rotate_sum: sum_i rot(cts[i], steps[i]) with one ModDown."""
+        if len(cts) != len(steps):
+            raise ValueError("one step per ciphertext")
+        hs = (ctypes.c_void_p * len(cts))(*[c.h.value for c in cts])
+        st = (ctypes.c_int32 * len(steps))(*[int(s) for s in steps])
+        return self._new(self.lib.he_ct_rotate_sum, _ek(keys), hs, st, len(cts))
 
     def rescale(self, a):
         return self._new(self.lib.he_ct_rescale, a.h)

@@ -68,6 +68,9 @@ def test_rejected_arguments(hk, tiny):
     have = {int(v) % ctx.slots for v in model.rotation_steps()}
     miss = next(v for v in range(1, ctx.slots) if v not in have)
     raises(hk, hk.HE_EKEY, ctx.rotate, keys, a, miss)                # no key for this step
+    raises(hk, hk.HE_EKEY, ctx.rotate_sum, keys, [a, a], [0, miss])  # no key for one of the steps
+    raises(hk, hk.HE_ESHAPE, ctx.rotate_sum, keys, [a, low], [0, 1])  # levels differ
+    raises(hk, hk.HE_EINVAL, ctx.rotate_sum, keys, [], [])           # no terms
     raises(hk, hk.HE_EINVAL, ctx.decrypt, keys, a, ctx.slots + 1)    # more values than slots
     raises(hk, hk.HE_ESHAPE, ctx.encrypt, keys, np.zeros(ctx.slots + 1), 1)
     q, _, _ = ctx.primes()
@@ -112,6 +115,8 @@ def test_handles_of_another_context(hk, tiny):
             raises(hk, hk.HE_ESTATE, ctx.mul, keys, mine, other_ct)
             raises(hk, hk.HE_ESTATE, ctx.rotate, other_keys, mine, 1)
             raises(hk, hk.HE_ESTATE, ctx.rotate, keys, other_ct, 1)
+            raises(hk, hk.HE_ESTATE, ctx.rotate_sum, other_keys, [mine, mine], [0, 1])
+            raises(hk, hk.HE_ESTATE, ctx.rotate_sum, keys, [mine, other_ct], [0, 1])
             raises(hk, hk.HE_ESTATE, ctx.add, mine, other_ct)
             raises(hk, hk.HE_ESTATE, ctx.rescale, other_ct)
             raises(hk, hk.HE_ESTATE, ctx.lincomb, [mine, other_ct], [1.0, 2.0], 3)

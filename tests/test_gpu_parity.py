@@ -510,6 +510,31 @@ def test_integer_words_give_the_same_residues(hk, tiny):
         ctx.close()
 
 
+@pytest.mark.parametrize("which", ["tiny", "formula"])
+def test_rotate_sum_bit_exact(which, request):
+    """he_ct_rotate_sum (rotations sharing one ModDown, an unrotated term
+    added as it is) equals the oracle's rotate_sum at the top level, a middle
+    level and levels 1 and 0; a sum of unrotated terms only is a plain
+    addition."""
+    wl, ctx, octx = request.getfixturevalue(which)
+    steps = [0, 1, -5, 7, 1024]
+    keys = ctx.keygen(synth.SEED_KEYGEN, steps[1:])
+    ev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps[1:]))
+    for lvl in (wl.L, wl.L // 2, 1, 0):
+        note("rotate_sum", which, "level", lvl)
+        arrs = [rand_ct(octx, lvl, 70 + 10 * lvl + i) for i in range(len(steps))]
+        cts = [ctx.import_ct(A, lvl) for A in arrs]
+        octs = [O.Ciphertext(lvl, A[0], A[1]) for A in arrs]
+        got = ctx.rotate_sum(keys, cts, steps)
+        want = ev.rotate_sum(list(zip(octs, steps)))
+        e = got.export()
+        assert got.level == want.level == lvl
+        assert (e[0] == want.c0).all() and (e[1] == want.c1).all()
+        plain = ctx.rotate_sum(keys, cts[:2], [0, 0]).export()
+        ref = ev.add(octs[0], octs[1])
+        assert (plain[0] == ref.c0).all() and (plain[1] == ref.c1).all()
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("alpha,w", [(1, 1), (2, 2)])
 def test_all_fp64_chain_ops_bit_exact(hk, alpha, w):
