@@ -189,15 +189,10 @@ def ops_bit_exact(ctx, octx, keys, okeys, levels):
                  ev.lincomb([(oa, z), (ob, z[::-1].copy())], lvl - 1))
 
 
-@pytest.mark.timeout(900)
-def test_ops_bit_exact_image_top_level(image):
-    """N = 2^16, 25 Q limbs, 4 special primes, 5-limb digits: one relinearised
-    product and one rotation at the top level, bit-exact."""
-    wl, ctx, octx = image
-    note("image keygen (1 rotation)")
-    keys = ctx.keygen(synth.SEED_KEYGEN, [3])
+def oracle_keys_for(octx, steps):
+    """Oracle keys for exactly the relinearisation key and the Galois keys of
+    `steps` (the full key set is slow to generate at N = 2^16)."""
     okeys = O.Keys.__new__(O.Keys)
-    # oracle keys for exactly the two switching keys needed
     okeys.ctx = octx
     p = octx.p
     s = np.zeros(p.N, np.int64)
@@ -209,24 +204,63 @@ def test_ops_bit_exact_image_top_level(image):
     O.lib().oc_poly_mul(O.P(okeys.s_res), O.P(okeys.s_res), O.P(s2), ktot, p.logN, O.P(octx.all_mods))
     dnum = (p.L + 1 + p.w - 1) // p.w
     okeys.keys = {0: okeys._gen(synth.SEED_KEYGEN, 0, s2, dnum)}
-    g = octx.galois_elt(3)
-    sg = np.zeros_like(okeys.s_res)
-    O.lib().oc_automorph(O.P(okeys.s_res), O.P(sg), ktot, p.logN, O.P(octx.all_mods), g)
-    okeys.keys[g] = okeys._gen(synth.SEED_KEYGEN, g, sg, dnum)
+    for t in steps:
+        g = octx.galois_elt(t)
+        sg = np.zeros_like(okeys.s_res)
+        O.lib().oc_automorph(O.P(okeys.s_res), O.P(sg), ktot, p.logN, O.P(octx.all_mods), g)
+        okeys.keys[g] = okeys._gen(synth.SEED_KEYGEN, g, sg, dnum)
+    return okeys
+
+
+def top_level_ops_bit_exact(ctx, octx, lvl, rotate_sum=False):
+    keys = ctx.keygen(synth.SEED_KEYGEN, [3])
+    okeys = oracle_keys_for(octx, [3])
     assert (keys.export(0, 4) == okeys.keys[0][4]).all()
     ev = O.Oracle(octx, okeys)
-    lvl = wl.L
     A, B = rand_ct(octx, lvl, 1), rand_ct(octx, lvl, 2)
     ca, cb = ctx.import_ct(A, lvl), ctx.import_ct(B, lvl)
     oa, ob = O.Ciphertext(lvl, A[0], A[1]), O.Ciphertext(lvl, B[0], B[1])
-    note("image mul")
+    note("mul at level", lvl, "N", octx.p.N)
     m = ctx.mul(keys, ca, cb).export()
     om = ev.mul(oa, ob)
     assert (m[0] == om.c0).all() and (m[1] == om.c1).all()
-    note("image rotate")
+    note("rotate")
     r = ctx.rotate(keys, ca, 3).export()
     orr = ev.rotate(oa, 3)
     assert (r[0] == orr.c0).all() and (r[1] == orr.c1).all()
+    if rotate_sum:
+        note("rotate_sum")
+        r = ctx.rotate_sum(keys, [ca, cb], [3, 0]).export()
+        orr = ev.rotate_sum([(oa, 3), (ob, 0)])
+        assert (r[0] == orr.c0).all() and (r[1] == orr.c1).all()
+
+
+@pytest.mark.timeout(900)
+def test_ops_bit_exact_image_top_level(image):
+    """N = 2^16, 25 Q limbs, 4 special primes, 5-limb digits: one relinearised
+    product, one rotation and a sum of a rotation and a ciphertext with one
+    ModDown at the top level, bit-exact."""
+    wl, ctx, octx = image
+    top_level_ops_bit_exact(ctx, octx, wl.L, rotate_sum=True)
+
+
+@pytest.mark.timeout(900)
+def test_all_fp64_chain_image_top_level(hk):
+    """The image ring with every prime below 2^46 (46-bit q_0, 25 x 45-bit,
+    five 46-bit special primes, 5-limb digits: 26 + 5 limbs, 6 digits at the
+    top, every limb on FP64 and the fused key product from q_0 on): the
+    relinearised product, a rotation and a rotation sum at the top level,
+    bit-exact against the oracle."""
+    p = O.Params(16, 25, 45, 5, 5, 46, 46)
+    octx = O.Context(p)
+    assert max(int(v) for v in list(octx.q) + list(octx.pm)) < 2 ** 46
+    ctx = hk.Context(16, 25, 45, 5, 5, base_bits=46, special_bits=46)
+    try:
+        q, pm, S = ctx.primes()
+        assert (q == octx.q).all() and (pm == octx.pm).all() and (S == octx.S).all()
+        top_level_ops_bit_exact(ctx, octx, 25, rotate_sum=True)
+    finally:
+        ctx.close()
 
 
 # ------------------------------------------------------------ KAN inference
