@@ -358,8 +358,8 @@ int he_ct_import(he_ctx *ctx, const uint64_t *in, int32_t level, he_ct **out);
  * in boot_levels (HE_EDEPTH at evaluation otherwise).
  */
 typedef struct {
-    int32_t cts_levels;        /* 1 .. log_n - 1 */
-    int32_t stc_levels;        /* 1 .. log_n - 1 */
+    int32_t cts_levels;        /* 1 .. log_n - 1 (log2 slots when sparse) */
+    int32_t stc_levels;        /* 1 .. log_n - 1 (log2 slots when sparse) */
     double k_range;            /* K > 0 */
     int32_t double_angles;     /* r >= 0 */
     int32_t cos_degree;        /* >= 1 */
@@ -373,6 +373,14 @@ typedef struct {
      * L_c.  The result holds the real parts of the slots; it uses
      * cts_levels + the series' depth + double_angles + 1 boot levels. */
     int32_t real_slots;
+    /* 0: all N/2 slots.  Else n, a power of two from 2 to N/2: a sparsely
+     * packed refresh (Cheon, Han, Kim, Kim, Song 2018) of a message whose slot
+     * vector repeats with period n (a polynomial in X^(N/(2n))): after ModRaise
+     * SubSum adds the rotations by n 2^k (k < log2(N/(2n))), and CoeffToSlot
+     * and SlotToCoeff run only the first log2 n butterfly stages (which act
+     * on every aligned block of n slots as the n-slot special DFT), so
+     * cts_levels and stc_levels are at most log2 n.  Needs real_slots = 0. */
+    int32_t slots;
 } he_boot_desc;
 
 typedef struct he_boot he_boot;

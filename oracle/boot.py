@@ -36,6 +36,17 @@ bootstrap(ct) at level l (a computation level):
      q_0 / (2 pi S_l) in stc_levels groups (F_0 first), the last group landing
      at the top computation level: the slots hold tau(m) / S_l, the input's
      slot values.
+Sparse packing (slots = n < N/2, a power of two; Cheon, Han, Kim, Kim, Song
+2018): a message whose slot vector repeats with period n is a polynomial in
+Y = X^(N/(2n)) of degree < 2n, with n slots of its own at the powers of
+zeta' = zeta^(N/(2n)).  For s < log2 n the stage F_s pairs indices inside
+aligned blocks of n and its twiddles are those of the n-slot factorisation
+(zeta^((5^j mod 8h) M/(2h)) = zeta'^((5^j mod 8h) n/(2h))), so the first
+log2 n stages act on every block as the n-slot transform.  After ModRaise,
+t = m + q_0 I is a full polynomial again; SubSum, the sum of the rotations by
+n 2^k (k < log2(M/n)), keeps its monomials in Y times M/n and makes the slots
+n-periodic; CoeffToSlot then runs the first log2 n stages only, its constant
+times n/M, and SlotToCoeff likewise (steps 3 to 5 unchanged).
 Every merged diagonal entry is one path through the butterflies, so it is
 sign * 2^-(stages, CoeffToSlot only) * zeta^e exactly; its parts are the
 doubles nearest zeta^e's, scaled by the power of two and the sign (exact),
@@ -60,7 +71,9 @@ class BootParams:
     coeffs: Chebyshev coefficients of cos(2 pi (y - 1/4) / 2^r) on [-K, K];
     real_slots: refresh real slot values with SlotToCoeff first (below);
     hoist_moddown: the giant steps of each baby-step giant-step product
-    share one ModDown (linear_transform)."""
+    share one ModDown (linear_transform); slots: n, the period of the slot
+    vector a sparse refresh keeps (a power of two below N/2; 0: all N/2
+    slots)."""
     cts_levels: int
     stc_levels: int
     K: float
@@ -68,6 +81,7 @@ class BootParams:
     coeffs: tuple
     real_slots: bool = False
     hoist_moddown: bool = True
+    slots: int = 0
 
 
 # SlotToCoeff-first refresh: the coefficients it writes are c1 times the slots
@@ -86,8 +100,28 @@ def cos_coeffs(K, r, degree):
     return tuple(float(v) for v in c)
 
 
-def make_params(cts_levels, stc_levels, K, r, degree, real_slots=False, hoist_moddown=True):
-    return BootParams(cts_levels, stc_levels, float(K), r, cos_coeffs(K, r, degree), real_slots, hoist_moddown)
+def make_params(cts_levels, stc_levels, K, r, degree, real_slots=False, hoist_moddown=True, slots=0):
+    return BootParams(cts_levels, stc_levels, float(K), r, cos_coeffs(K, r, degree), real_slots, hoist_moddown,
+                      slots)
+
+
+def slot_stages(logN, bp):
+    """(n, log2 n): the slots a refresh keeps and the butterfly stages its
+    transforms run"""
+    M = 1 << (logN - 1)
+    n = bp.slots or M
+    if n & (n - 1) or not 2 <= n <= M:
+        raise ValueError("slots must be a power of two between 2 and N/2")
+    if n < M and bp.real_slots:
+        raise ValueError("the sparse refresh keeps complex slots (real_slots must be off)")
+    return n, n.bit_length() - 1
+
+
+def subsum_steps(logN, bp):
+    """the rotation steps of SubSum: n 2^k for k < log2(M/n)"""
+    M = 1 << (logN - 1)
+    n, _ = slot_stages(logN, bp)
+    return [n << k for k in range((M // n).bit_length() - 1)]
 
 
 def evalmod_plain(y, bp):
@@ -242,11 +276,14 @@ def linear_transform(ev, x, diags, u, t, hoist=True):
 
 
 def transform_plan(logN, bp, S_top, q0, S_in):
-    """[(stages, inverse, const)] for CoeffToSlot then SlotToCoeff."""
-    m = logN - 1
+    """[(stages, inverse, const)] for CoeffToSlot then SlotToCoeff (a sparse
+    refresh: the first log2 n stages, CoeffToSlot's constant times n/M for
+    SubSum's factor M/n)."""
+    n, m = slot_stages(logN, bp)
+    sub = n / float(1 << (logN - 1))
     plan = []
     for gi, st in enumerate(stage_groups(m, bp.cts_levels, ascending=False)):
-        plan.append((st, True, S_top / (2.0 * float(q0)) if gi == 0 else 1.0))
+        plan.append((st, True, S_top / (2.0 * float(q0)) * sub if gi == 0 else 1.0))
     for gi, st in enumerate(stage_groups(m, bp.stc_levels, ascending=True)):
         plan.append((st, False, float(q0) / (2.0 * math.pi * S_in) if gi == 0 else 1.0))
     return plan
@@ -254,12 +291,12 @@ def transform_plan(logN, bp, S_top, q0, S_in):
 
 def rotation_steps(logN, bp):
     """every rotation step the bootstrapping uses, with STEP_CONJUGATE"""
-    m = logN - 1
-    steps = {ckks.STEP_CONJUGATE}
+    _, m = slot_stages(logN, bp)
+    steps = {ckks.STEP_CONJUGATE} | set(subsum_steps(logN, bp))
     for st, inv in [(g, True) for g in stage_groups(m, bp.cts_levels, False)] + \
                    [(g, False) for g in stage_groups(m, bp.stc_levels, True)]:
         I, J, _, _ = group_terms(logN, st, inv)
-        M = 1 << m
+        M = 1 << (logN - 1)
         o = (J - I) % M
         o = np.where(o > M // 2, o - M, o)
         offs = sorted(set(int(v) for v in np.unique(o)))
@@ -323,6 +360,7 @@ def bootstrap_real(ev, ct, bp, trace=None):
 def bootstrap(ev, ct, bp, trace=None):
     """The refreshed ciphertext at the top computation level (steps above).
     trace: optional dict receiving the intermediate ciphertexts."""
+    slot_stages(ev.ctx.p.logN, bp)
     if bp.real_slots:
         return bootstrap_real(ev, ct, bp, trace)
     ctx, p = ev.ctx, ev.ctx.p
@@ -332,6 +370,8 @@ def bootstrap(ev, ct, bp, trace=None):
     x = ev.mod_raise(ev.mod_drop(ct, 0))
     if trace is not None:
         trace["raised"] = x
+    for t in subsum_steps(p.logN, bp):
+        x = ev.add(x, ev.rotate(x, t))
     for st, inv, cst in plan[:bp.cts_levels]:
         x = linear_transform(ev, x, group_diagonals(p.logN, st, inv, cst), 1 << min(st), x.level - 1,
                              bp.hoist_moddown)

@@ -40,7 +40,7 @@ static long floordiv_l(long a, long b) { return a >= 0 ? a / b : -((-a + b - 1) 
 // (sizes m / G, the first m % G one larger)
 static std::vector<std::vector<int>> stage_groups(int m, int G, bool ascending)
 {
-    if (G < 1 || G > m) throw HeError(-1, "bootstrapping: stage groups must be between 1 and log2(N/2)");
+    if (G < 1 || G > m) throw HeError(-1, "bootstrapping: stage groups must be between 1 and log2 of the slots");
     std::vector<int> order(m);
     for (int i = 0; i < m; i++) order[i] = ascending ? i : m - 1 - i;
     std::vector<std::vector<int>> out;
@@ -121,16 +121,22 @@ BootGroup boot_group(int logN, const std::vector<int> &stages, bool inverse, con
     return G;
 }
 
-Boot::Boot(Ctx *c, int cts, int stc, double K_, int r_, const std::vector<double> &cf_, bool real_)
-    : ctx(c), cts_levels(cts), stc_levels(stc), r(r_), real(real_), K(K_), cf(cf_)
+Boot::Boot(Ctx *c, int cts, int stc, double K_, int r_, const std::vector<double> &cf_, bool real_, long slots_)
+    : ctx(c), cts_levels(cts), stc_levels(stc), r(r_), real(real_), slots(slots_ ? slots_ : c->N / 2), K(K_), cf(cf_)
 {
-    const int m = c->logN - 1;
+    if (slots < 2 || slots > c->N / 2 || (slots & (slots - 1)))
+        throw HeError(-1, "bootstrapping: slots must be a power of two between 2 and N/2");
+    if (real && slots < c->N / 2) throw HeError(-1, "bootstrapping: a sparse refresh keeps complex slots");
+    int m = 0;
+    while ((1l << m) < slots) m++;
+    for (long t = slots; t < c->N / 2; t <<= 1) subsum.push_back(t);
     if (!(K > 0.0) || r < 0 || cf.size() < 2) throw HeError(-1, "bootstrapping: bad EvalMod parameters");
     std::vector<double> zr(2l * c->N), zi(2l * c->N);
     zeta_table(c->logN, zr.data(), zi.data());
     for (auto &st : stage_groups(m, cts, false)) this->cts.push_back(boot_group(c->logN, st, true, zr, zi));
     for (auto &st : stage_groups(m, stc, true)) this->stc.push_back(boot_group(c->logN, st, false, zr, zi));
     std::vector<long> s{kStepConjugate};
+    s.insert(s.end(), subsum.begin(), subsum.end());
     for (auto *gs : {&this->cts, &this->stc})
         for (const BootGroup &G : *gs)
             for (auto &kv : G.diag) {
@@ -239,9 +245,13 @@ Ct boot_coeff_to_slot(Ctx &c, Boot &b, const Keys &k, const Ct &in)
     if (in.level < 0 || in.level > c.top) throw HeError(-1, "bootstrapping: the input must be at a computation level");
     const double q0 = (double)c.q[0];
     Ct x = c.mod_raise(c.mod_drop(in, 0));
+    // sparse: SubSum makes the slots n-periodic (times N/(2n), undone by the
+    // first group's constant)
+    for (long t : b.subsum) x = c.rotate_add(x, t, x, k);
+    const double sub = (double)b.slots / (double)(c.N / 2);
     for (size_t gi = 0; gi < b.cts.size(); gi++) {
         if (x.level < 1) throw HeError(-3, "bootstrapping does not fit the levels");
-        const double cst = gi == 0 ? c.S[c.L] / (2.0 * q0) : 1.0;
+        const double cst = gi == 0 ? c.S[c.L] / (2.0 * q0) * sub : 1.0;
         x = lintrans(c, b, k, b.cts[gi], "C" + std::to_string(gi), cst, x, x.level - 1);
     }
     return x;

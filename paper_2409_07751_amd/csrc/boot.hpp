@@ -26,12 +26,15 @@ struct Boot {
     Ctx *ctx;
     int cts_levels, stc_levels, r;
     bool real;  // real slot values, SlotToCoeff first (bootstrap_real)
+    long slots;  // n: the transforms' period (N/2 unless sparse)
     double K;
     std::vector<double> cf;  // Chebyshev series of cos(2 pi (y - 1/4) / 2^r) on [-K, K]
     std::vector<BootGroup> cts, stc;
-    std::vector<long> steps;  // rotation steps, with kStepConjugate
+    std::vector<long> subsum;  // SubSum's rotation steps n 2^k (sparse only)
+    std::vector<long> steps;   // rotation steps, with kStepConjugate
     std::map<std::string, Pt> pt_cache;
-    Boot(Ctx *c, int cts_levels, int stc_levels, double K, int r, const std::vector<double> &cf, bool real = false);
+    Boot(Ctx *c, int cts_levels, int stc_levels, double K, int r, const std::vector<double> &cf, bool real = false,
+         long slots = 0);
 };
 
 // refresh of nb ciphertexts (one batch) at a computation level: the result is

@@ -383,7 +383,8 @@ int he_boot_create(he_ctx *ctx, const he_boot_desc *d, he_boot **out)
         need(ctx->c->top < ctx->c->L, "the context has no boot levels");
         std::vector<double> cf(d->cos_coeffs, d->cos_coeffs + d->cos_degree + 1);
         need(d->real_slots == 0 || d->real_slots == 1, "real_slots must be 0 or 1");
-        Boot *b = new Boot(ctx->c, d->cts_levels, d->stc_levels, d->k_range, d->double_angles, cf, d->real_slots != 0);
+        Boot *b = new Boot(ctx->c, d->cts_levels, d->stc_levels, d->k_range, d->double_angles, cf, d->real_slots != 0,
+                           d->slots);
         *out = new he_boot{retain(ctx), b};
     });
 }

@@ -51,7 +51,7 @@ class he_kan_desc(ctypes.Structure):
 class he_boot_desc(ctypes.Structure):
     _fields_ = [("cts_levels", ctypes.c_int32), ("stc_levels", ctypes.c_int32), ("k_range", ctypes.c_double),
                 ("double_angles", ctypes.c_int32), ("cos_degree", ctypes.c_int32), ("cos_coeffs", _dp),
-                ("real_slots", ctypes.c_int32)]
+                ("real_slots", ctypes.c_int32), ("slots", ctypes.c_int32)]
 
 
 # the rotation "step" naming the complex conjugation (HE_STEP_CONJUGATE)
@@ -400,9 +400,10 @@ class Context:
         # requests given as ciphertexts or as lists of input chunks, request-major
         return [c for r in cts for c in (r if isinstance(r, (list, tuple)) else [r])]
 
-    def boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots=False):
-        """he_boot_create: a bootstrapping plan (see he_boot_desc)"""
-        return Boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots)
+    def boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots=False, slots=0):
+        """he_boot_create: a bootstrapping plan (see he_boot_desc; slots: a
+        sparse refresh of n-periodic slot vectors, 0 for all N/2)"""
+        return Boot(self, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots, slots)
 
     def bootstrap(self, boot, keys, ct):
         return self._new(self.lib.he_bootstrap, boot.h, _ek(keys), ct.h)
@@ -648,11 +649,11 @@ class Ciphertext:
 class Boot:
     """A bootstrapping plan (he_boot_create)."""
 
-    def __init__(self, ctx, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots=False):
+    def __init__(self, ctx, cts_levels, stc_levels, k_range, double_angles, cos_coeffs, real_slots=False, slots=0):
         self.ctx = ctx
         cf = _arr(cos_coeffs, np.float64)
         desc = he_boot_desc(cts_levels, stc_levels, float(k_range), double_angles, len(cf) - 1, _ptr(cf),
-                            1 if real_slots else 0)
+                            1 if real_slots else 0, int(slots))
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.he_boot_create(ctx.h, ctypes.byref(desc), ctypes.byref(h)))
         self.h = h

@@ -62,6 +62,32 @@ def test_butterfly_stages_factor_the_special_dft(logN):
         assert np.abs(B - (2.0 / N) * R @ U0.conj().T).max() < 1e-13
 
 
+@pytest.mark.parametrize("logN,n", [(6, 2), (6, 8), (7, 16), (8, 32)])
+def test_first_stages_are_the_sparse_special_dft_on_every_block(logN, n):
+    """The sparse packing's transform: F_{log2 n - 1} ... F_0 of the full
+    factorisation is block diagonal, every aligned block of n being the n-slot
+    special DFT U0'[j][k] = zeta'^(5^j k) (zeta' = exp(i pi / (2 n)), a
+    primitive 4n-th root) times the n-point bit reversal; and its inverse
+    stages (F^H/2) give (1/n) R' U0'^H on every block."""
+    M, m = 1 << (logN - 1), n.bit_length() - 1
+    e = np.array([[pow(5, j, 4 * n) * k % (4 * n) for k in range(n)] for j in range(n)])
+    U = np.exp(1j * np.pi * e / (2 * n))
+    R = bit_reversal(m)
+    A = np.eye(M)
+    for st in boot.stage_groups(m, min(2, m), True):
+        A = dense(logN, st, False) @ A
+    B = np.eye(M)
+    for st in boot.stage_groups(m, min(2, m), False):
+        B = dense(logN, st, True) @ B
+    for b in range(M // n):
+        blk = slice(b * n, (b + 1) * n)
+        assert np.abs(A[blk, blk] @ R - U).max() < 1e-12
+        assert np.abs(B[blk, blk] - R @ U.conj().T / n).max() < 1e-13
+        A[blk, blk] = 0
+        B[blk, blk] = 0
+    assert np.abs(A).max() == 0 and np.abs(B).max() == 0
+
+
 def test_group_diagonals_are_the_group_matrix():
     logN = 7
     M = 1 << (logN - 1)
@@ -416,6 +442,35 @@ def test_deep_composite_brings_the_circuit_within_1e2_of_the_exact_kan():
 def boot11_real(boot11):
     bs, p, ctx, bp, keys, ev = boot11
     return bs, p, ctx, boot.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree, real_slots=True), keys, ev
+
+
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_sparse_refresh_keeps_a_periodic_message(boot11, n):
+    """A sparsely packed refresh (slots n: SubSum, then the transforms' first
+    log2 n stages) of a message whose slots repeat with period n decrypts to
+    it, periodic, with fewer key switches than the full-slot refresh; and the
+    CoeffToSlot output holds the sparse plaintext's coefficients over 2 q_0
+    (near integers plus m / (2 q_0), within [-K/2, K/2])."""
+    bs, p, ctx, bp_full, _, _ = boot11
+    M = p.slots
+    bp = boot.make_params(2 if n > 8 else 1, 2 if n > 8 else 1, bs.K, bs.r, bs.degree, slots=n)
+    keys = ckks.Keys(ctx, synth.SEED_KEYGEN, boot.rotation_steps(bs.logN, bp))
+    ev = ckks.Oracle(ctx, keys)
+    z = np.tile(np.random.default_rng(n).uniform(-1, 1, n), M // n)
+    ct = ev.encrypt(z, 22)
+    want = ev.decrypt(ct, p.slots)
+    tr = {}
+    out = boot.bootstrap(ev, ct, bp, tr)
+    assert out.level == p.top_level
+    got = ev.decrypt_c(out, p.slots)
+    assert np.abs(got.real - want).max() < 1e-6 and np.abs(got.imag).max() < 1e-6
+    assert np.abs(got.real - np.tile(got.real[:n], M // n)).max() < 1e-7
+    assert ev.count["ks"] < 79  # the full-slot refresh of boot11: 79 key switches
+    w = decrypt_wide(ev, tr["cts"])
+    assert np.abs(w.real).max() <= bs.K / 2 and np.abs(w.imag).max() <= bs.K / 2
+    assert np.abs(2 * w.real - np.round(2 * w.real)).max() < 1e-3
+    with pytest.raises(ValueError):
+        boot.bootstrap(ev, ct, boot.make_params(1, 1, bs.K, bs.r, bs.degree, real_slots=True, slots=n))
 
 
 def test_real_slot_refresh_with_slot_to_coeff_first(boot11_real):
