@@ -499,6 +499,10 @@ def serve_run(args):
 TABLE3_SHAPES = ((64, 3, 2), (128, 5, 3), (256, 5, 3), (256, 10, 3), (256, 10, 5))
 
 
+# slot counts of the sparsely packed refreshes the bootstrapping block times
+BOOT_SPARSE_SLOTS = (512, 4096)
+
+
 def boot_bench(args):
     """CKKS bootstrapping at N = 2^16 (the boot16 parameter set): ms per refresh
     of one ciphertext and refreshes/s in batches, its key switches and levels,
@@ -519,9 +523,13 @@ def boot_bench(args):
     model = ctx.compile(layers, refresh=True, circuit=hekan.CIRCUIT_RESTRUCTURED)
     # the real-slot refresh (SlotToCoeff first)
     rplan = ctx.boot(bs.cts, bs.real_stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), real_slots=True)
+    # sparsely packed refreshes of n-periodic slot vectors
+    splans = {n: ctx.boot(bs.cts, bs.stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), slots=n)
+              for n in BOOT_SPARSE_SLOTS}
     t0 = time.time()
     keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(plan.rotation_steps()) | set(rplan.rotation_steps()) |
-                                                set(model.rotation_steps())))
+                                                set(model.rotation_steps()) |
+                                                set(s for sp in splans.values() for s in sp.rotation_steps())))
     ctx.sync()
     log("bootstrapping: keygen %.1fs" % (time.time() - t0))
     B = args.boot_batch
@@ -611,6 +619,34 @@ def boot_bench(args):
     rerr = max(float(np.abs(ctx.decrypt(keys, o, z.shape[1]) - z[i]).max()) for i, o in enumerate(routs))
     del routs, rout
     # one refresh of one ciphertext replayed from a HIP graph
+    # sparse refreshes: one ciphertext and a batch, n-periodic inputs
+    sparse = {}
+    M = 1 << (bs.logN - 1)
+    for n, sp in splans.items():
+        zs = [np.tile(z[i][:n], M // n) for i in range(B)]
+        scts = [ctx.encrypt(keys, zs[i], synth.SEED_ENC + 200 + i) for i in range(B)]
+        so = ctx.bootstrap(sp, keys, scts[0])
+        ctx.sync()
+        k0 = ctx.counters()["keyswitches"]
+        t0 = time.time()
+        for _ in range(args.boot_reps):
+            so = ctx.bootstrap(sp, keys, scts[0])
+        ctx.sync()
+        s1 = (time.time() - t0) / args.boot_reps
+        sks = (ctx.counters()["keyswitches"] - k0) / args.boot_reps
+        souts = ctx.bootstrap_batch(sp, keys, scts)
+        ctx.sync()
+        t0 = time.time()
+        for _ in range(args.boot_reps):
+            souts = ctx.bootstrap_batch(sp, keys, scts)
+        ctx.sync()
+        sb = (time.time() - t0) / args.boot_reps
+        serr = max(float(np.abs(ctx.decrypt(keys, o, M) - zs[i]).max()) for i, o in enumerate(souts))
+        sparse[str(n)] = {"ms_per_bootstrap_b1": round(s1 * 1e3, 3), "bootstraps_per_s_b1": round(1.0 / s1, 2),
+                          "ms_per_batch": round(sb * 1e3, 3), "bootstraps_per_s_batched": round(B / sb, 2),
+                          "keyswitches_per_bootstrap": sks, "max_abs_err": serr}
+        del so, souts, scts
+    log("bootstrapping: sparse refreshes %s" % sparse)
     graph_ms = {}
     for name, pl, c_in in (("full_slot", plan, cts[0]), ("real_slot", rplan, low[0])):
         g, gouts = ctx.graph_capture_bootstrap(pl, keys, [c_in])
@@ -628,7 +664,10 @@ def boot_bench(args):
     want = pc.plain_forward(x, layers)
     kin = [ctx.encrypt(keys, x[i], synth.SEED_ENC + 100 + i) for i in range(B)]
     kan = {}
-    for name, pl in (("full_slot_refresh", plan), ("real_slot_refresh", rplan)):
+    # (the layer outputs repeat with period 16, so the sparse refresh of 512
+    # slots applies)
+    for name, pl in (("full_slot_refresh", plan), ("real_slot_refresh", rplan),
+                     ("sparse_512_slot_refresh", splans[512])):
         kout = ctx.eval_kan_boot(model, pl, keys, kin)
         ctx.sync()
         t0 = time.time()
@@ -657,6 +696,8 @@ def boot_bench(args):
                           "ms_per_bootstrap_b1": round(rsingle * 1e3, 3), "bootstraps_per_s_b1": round(1.0 / rsingle, 2),
                           "ms_per_batch": round(rbatched * 1e3, 3), "bootstraps_per_s_batched": round(B / rbatched, 2),
                           "keyswitches_per_bootstrap": rks, "max_abs_err": rerr},
+           "sparse_slots": dict(plan="slots = n: SubSum, then %d/%d stage groups over the first log2 n stages; "
+                                     "inputs repeat with period n" % (bs.cts, bs.stc), **sparse),
            "graph_replay_ms_b1": graph_ms,
            "kan_formula_with_bootstrapping": dict(
                model="KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B, **kan)}

@@ -193,12 +193,17 @@ def kan_layers(name):
                                  [list(c) for c in wl.comp_degrees], wl.grid, wl.silu_range, prescale=wl.prescale)
 
 
-def test_kan_with_bootstrapping_between_layers_bit_exact(b11):
+@pytest.mark.parametrize("slots", [0, 64])
+def test_kan_with_bootstrapping_between_layers_bit_exact(b11, slots):
     """The [2,5,1] KAN with a bootstrapping in place of the client-aided
     refresh: the whole inference on the server, residues equal to the
-    oracle's, decrypted output within 1e-2 of the FP64 circuit."""
+    oracle's, decrypted output within 1e-2 of the FP64 circuit; also with the
+    sparse refresh of 64 slots (the layer output repeats with period 8)."""
     from oracle import circuit, kan
     hk, bs, bp, ctx, octx, plan, keys, ev = b11
+    if slots:
+        bp = OB.make_params(2, 2, bs.K, bs.r, bs.degree, slots=slots)
+        plan = ctx.boot(2, 2, bs.K, bs.r, bp.coeffs, slots=slots)
     wl, layers = kan_layers("tiny16")
     model = ctx.compile(layers, refresh=True, circuit=hk.CIRCUIT_PAPER)
     steps = sorted(set(model.rotation_steps()) | set(plan.rotation_steps()))
