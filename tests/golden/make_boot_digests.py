@@ -3,7 +3,8 @@ one CKKS bootstrapping on the N = 2^16 bootstrappable parameter set (boot16 of
 paper_2409_07751_amd.synth: 51 + 10x45 + 17x58-bit primes, 4 special primes,
 4-limb digits, sparse secret of weight 192), which the GPU parity tests
 compare against; and the same for the real-slot refresh with SlotToCoeff
-first (`real`).
+first (`real`), and the sparsely packed refresh of 512 slots of a 512-periodic
+input (`sparse512`; `--sparse-only` adds just that entry to the existing file).
 
 Runs only the CPU oracle (oracle/) on seeded synthetic inputs; nothing here
 touches the GPU path.  The input is synth.boot_inputs(boot16, 1)[0]
@@ -43,8 +44,46 @@ def entry(ct):
             "sampled": [int((ct.c0, ct.c1)[p][l][n]) for p, l, n in pos]}
 
 
+SPARSE_SLOTS = 512
+
+
+def sparse_input(bs):
+    """the first 512 values of synth.boot_inputs(boot16, 1)[0], repeated over
+    every slot"""
+    z = synth.boot_inputs(bs, 1)[0]
+    return np.tile(z[:SPARSE_SLOTS], len(z) // SPARSE_SLOTS)
+
+
+def sparse_entry(bs, p, ctx):
+    sbp = boot.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree, slots=SPARSE_SLOTS)
+    steps = boot.rotation_steps(bs.logN, sbp)
+    ev = O.Oracle(ctx, O.Keys(ctx, synth.SEED_KEYGEN, steps))
+    ct = ev.encrypt(sparse_input(bs), synth.SEED_ENC)
+    tr = {}
+    t0 = time.time()
+    out = boot.bootstrap(ev, ct, sbp, tr)
+    print("sparse bootstrap %.0f s, %s" % (time.time() - t0, ev.count), flush=True)
+    err = float(np.abs(ev.decrypt(out, p.slots) - ev.decrypt(ct, p.slots)).max())
+    print("sparse: max |decrypt(out) - decrypt(in)| = %.3g" % err, flush=True)
+    return {"plan": "slots %d: SubSum, CoeffToSlot and SlotToCoeff in %d/%d groups over the first %d stages"
+                    % (SPARSE_SLOTS, bs.cts, bs.stc, SPARSE_SLOTS.bit_length() - 1),
+            "input": "the first %d values of synth.boot_inputs(boot16, 1)[0] repeated, encrypted with seed SEED_ENC"
+                     % SPARSE_SLOTS,
+            "steps": steps, "max_abs_err": err,
+            "stages": {"input": entry(ct), "cts": entry(tr["cts"]), "output": entry(out)}}
+
+
 def main():
     bs = synth.BOOTSETS["boot16"]
+    if "--sparse-only" in sys.argv:
+        p = O.Params(bs.logN, bs.L, bs.scale_bits, bs.alpha, bs.w, bs.base_bits, bs.special_bits, bs.sigma,
+                     bs.boot_levels, bs.boot_bits, bs.h)
+        res = json.load(open(OUT))
+        res["sparse512"] = sparse_entry(bs, p, O.Context(p))
+        with open(OUT, "w") as f:
+            json.dump(res, f, indent=1)
+        print("wrote", OUT, flush=True)
+        return
     p = O.Params(bs.logN, bs.L, bs.scale_bits, bs.alpha, bs.w, bs.base_bits, bs.special_bits, bs.sigma,
                  bs.boot_levels, bs.boot_bits, bs.h)
     ctx = O.Context(p)
@@ -82,6 +121,7 @@ def main():
                    "stages": {"stc_first": entry(tr["stc_first"]), "cts": entry(tr["cts"]),
                               "evalmod": entry(tr["evalmod"]), "output": entry(rout)}}
     print("real-slot: max |decrypt(out) - decrypt(in)| = %.3g" % rerr, flush=True)
+    res["sparse512"] = sparse_entry(bs, p, ctx)
     with open(OUT, "w") as f:
         json.dump(res, f, indent=1)
     print("max |decrypt(out) - decrypt(in)| = %.3g; wrote %s" % (err, OUT), flush=True)

@@ -232,7 +232,8 @@ def test_boot16_full_size_equals_oracle_digests():
     oracle's residues (tests/golden/boot_digests.json, written by
     make_boot_digests.py from the oracle alone): the encrypted input,
     CoeffToSlot and the refreshed output, bit for bit, then batched runs
-    against the single one, and the decrypted error."""
+    against the single one, and the decrypted error; the same for the
+    real-slot refresh and for the sparsely packed refresh of 512 slots."""
     import json
     import os
     import time
@@ -281,6 +282,26 @@ def test_boot16_full_size_equals_oracle_digests():
         assert rout.level == rg["stages"]["output"]["level"] and digest(e) == rg["stages"]["output"]["sha256"]
         y = ctx.decrypt(rkeys, rout, len(z))
         assert np.abs(y - z).max() < max(4 * rg["max_abs_err"], 1e-6)
+        del rout, rct, rkeys, rplan
+        # the sparsely packed refresh of 512 slots of a 512-periodic input
+        sg = gold["sparse512"]
+        sbp = OB.make_params(bs.cts, bs.stc, bs.K, bs.r, bs.degree, slots=512)
+        splan = ctx.boot(bs.cts, bs.stc, bs.K, bs.r, sbp.coeffs, slots=512)
+        assert sorted(splan.rotation_steps()) == sg["steps"]
+        skeys = ctx.keygen(synth.SEED_KEYGEN, sg["steps"])
+        zs = np.tile(z[:512], len(z) // 512)
+        sct = ctx.encrypt(skeys, zs, synth.SEED_ENC)
+        ss = sg["stages"]
+        assert digest(sct.export()) == ss["input"]["sha256"]
+        scts = ctx.boot_coeff_to_slot(splan, skeys, sct)
+        assert scts.level == ss["cts"]["level"] and digest(scts.export()) == ss["cts"]["sha256"]
+        sout = ctx.bootstrap(splan, skeys, sct)
+        e = sout.export()
+        for (p, l, n), v in zip(ss["output"]["positions"], ss["output"]["sampled"]):
+            assert int(e[p][l][n]) == v, (p, l, n)
+        assert sout.level == ss["output"]["level"] and digest(e) == ss["output"]["sha256"]
+        y = ctx.decrypt(skeys, sout, len(zs))
+        assert np.abs(y - zs).max() < max(4 * sg["max_abs_err"], 1e-6)
     finally:
         ctx.close()
 
