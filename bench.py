@@ -526,10 +526,15 @@ def boot_bench(args):
     # sparsely packed refreshes of n-periodic slot vectors
     splans = {n: ctx.boot(bs.cts, bs.stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), slots=n)
               for n in BOOT_SPARSE_SLOTS}
+    # and of real n-periodic slot vectors, SlotToCoeff first
+    n_real = BOOT_SPARSE_SLOTS[0]
+    srplan = ctx.boot(bs.cts, bs.real_stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), real_slots=True,
+                      slots=n_real)
     t0 = time.time()
     keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(plan.rotation_steps()) | set(rplan.rotation_steps()) |
                                                 set(model.rotation_steps()) |
-                                                set(s for sp in splans.values() for s in sp.rotation_steps())))
+                                                set(s for sp in splans.values() for s in sp.rotation_steps()) |
+                                                set(srplan.rotation_steps())))
     ctx.sync()
     log("bootstrapping: keygen %.1fs" % (time.time() - t0))
     B = args.boot_batch
@@ -622,9 +627,11 @@ def boot_bench(args):
     # sparse refreshes: one ciphertext and a batch, n-periodic inputs
     sparse = {}
     M = 1 << (bs.logN - 1)
-    for n, sp in splans.items():
+    for name, n, sp in [(str(n), n, sp) for n, sp in splans.items()] + [("%d_real_slots" % n_real, n_real, srplan)]:
         zs = [np.tile(z[i][:n], M // n) for i in range(B)]
         scts = [ctx.encrypt(keys, zs[i], synth.SEED_ENC + 200 + i) for i in range(B)]
+        if sp is srplan:
+            scts = [ctx.mod_drop(c, bs.real_stc) for c in scts]
         so = ctx.bootstrap(sp, keys, scts[0])
         ctx.sync()
         k0 = ctx.counters()["keyswitches"]
@@ -642,7 +649,7 @@ def boot_bench(args):
         ctx.sync()
         sb = (time.time() - t0) / args.boot_reps
         serr = max(float(np.abs(ctx.decrypt(keys, o, M) - zs[i]).max()) for i, o in enumerate(souts))
-        sparse[str(n)] = {"ms_per_bootstrap_b1": round(s1 * 1e3, 3), "bootstraps_per_s_b1": round(1.0 / s1, 2),
+        sparse[name] = {"ms_per_bootstrap_b1": round(s1 * 1e3, 3), "bootstraps_per_s_b1": round(1.0 / s1, 2),
                           "ms_per_batch": round(sb * 1e3, 3), "bootstraps_per_s_batched": round(B / sb, 2),
                           "keyswitches_per_bootstrap": sks, "max_abs_err": serr}
         del so, souts, scts
@@ -667,7 +674,7 @@ def boot_bench(args):
     # (the layer outputs repeat with period 16, so the sparse refresh of 512
     # slots applies)
     for name, pl in (("full_slot_refresh", plan), ("real_slot_refresh", rplan),
-                     ("sparse_512_slot_refresh", splans[512])):
+                     ("sparse_512_slot_refresh", splans[512]), ("sparse_512_real_slot_refresh", srplan)):
         kout = ctx.eval_kan_boot(model, pl, keys, kin)
         ctx.sync()
         t0 = time.time()
@@ -697,7 +704,8 @@ def boot_bench(args):
                           "ms_per_batch": round(rbatched * 1e3, 3), "bootstraps_per_s_batched": round(B / rbatched, 2),
                           "keyswitches_per_bootstrap": rks, "max_abs_err": rerr},
            "sparse_slots": dict(plan="slots = n: SubSum, then %d/%d stage groups over the first log2 n stages; "
-                                     "inputs repeat with period n" % (bs.cts, bs.stc), **sparse),
+                                     "inputs repeat with period n; '_real_slots': SlotToCoeff first in %d groups, "
+                                     "the input at level %d" % (bs.cts, bs.stc, bs.real_stc, bs.real_stc), **sparse),
            "graph_replay_ms_b1": graph_ms,
            "kan_formula_with_bootstrapping": dict(
                model="KAN [4,10,10,1], 2 bootstraps per inference, batch %d" % B, **kan)}

@@ -379,7 +379,8 @@ typedef struct {
      * SubSum adds the rotations by n 2^k (k < log2(N/(2n))), and CoeffToSlot
      * and SlotToCoeff run only the first log2 n butterfly stages (which act
      * on every aligned block of n slots as the n-slot special DFT), so
-     * cts_levels and stc_levels are at most log2 n.  Needs real_slots = 0. */
+     * cts_levels and stc_levels are at most log2 n.  With real_slots = 1 the
+     * SlotToCoeff that runs first is sparse as well. */
     int32_t slots;
 } he_boot_desc;
 

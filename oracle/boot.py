@@ -112,8 +112,6 @@ def slot_stages(logN, bp):
     n = bp.slots or M
     if n & (n - 1) or not 2 <= n <= M:
         raise ValueError("slots must be a power of two between 2 and N/2")
-    if n < M and bp.real_slots:
-        raise ValueError("the sparse refresh keeps complex slots (real_slots must be off)")
     return n, n.bit_length() - 1
 
 
@@ -330,20 +328,27 @@ def bootstrap_real(ev, ct, bp, trace=None):
          sin(2 pi y) ~ 2 pi S c1 z / q_0 (one EvalMod: the imaginary half,
          which holds no message, is dropped);
       4. one product by q_0 / (2 pi S c1) lands at the top computation level.
-    The input must hold stc_levels levels; the result's slots are Re z."""
+    The input must hold stc_levels levels; the result's slots are Re z.  A
+    sparse refresh (slots n) runs the first log2 n stages in steps 1 and 2,
+    with SubSum after ModRaise and CoeffToSlot's constant times n/M, as in
+    bootstrap."""
     ctx, p = ev.ctx, ev.ctx.p
+    n, m = slot_stages(p.logN, bp)
     if ct.level > p.top_level or ct.level < bp.stc_levels:
         raise ValueError("real-slot bootstrapping input must be at a computation level >= stc_levels")
     x = ct
-    for gi, st in enumerate(stage_groups(p.logN - 1, bp.stc_levels, ascending=True)):
+    for gi, st in enumerate(stage_groups(m, bp.stc_levels, ascending=True)):
         x = linear_transform(ev, x, group_diagonals(p.logN, st, False, REAL_C1 if gi == 0 else 1.0), 1 << min(st),
                              x.level - 1, bp.hoist_moddown)
     if trace is not None:
         trace["stc_first"] = x
     lp = x.level
     x = ev.mod_raise(ev.mod_drop(x, 0))
-    for gi, st in enumerate(stage_groups(p.logN - 1, bp.cts_levels, ascending=False)):
-        cst = float(ctx.S[p.L]) / (2.0 * float(ctx.q[0])) if gi == 0 else 1.0
+    for t in subsum_steps(p.logN, bp):
+        x = ev.add(x, ev.rotate(x, t))
+    sub = n / float(p.slots)
+    for gi, st in enumerate(stage_groups(m, bp.cts_levels, ascending=False)):
+        cst = float(ctx.S[p.L]) / (2.0 * float(ctx.q[0])) * sub if gi == 0 else 1.0
         x = linear_transform(ev, x, group_diagonals(p.logN, st, True, cst), 1 << min(st), x.level - 1,
                              bp.hoist_moddown)
     if trace is not None:

@@ -126,7 +126,6 @@ Boot::Boot(Ctx *c, int cts, int stc, double K_, int r_, const std::vector<double
 {
     if (slots < 2 || slots > c->N / 2 || (slots & (slots - 1)))
         throw HeError(-1, "bootstrapping: slots must be a power of two between 2 and N/2");
-    if (real && slots < c->N / 2) throw HeError(-1, "bootstrapping: a sparse refresh keeps complex slots");
     int m = 0;
     while ((1l << m) < slots) m++;
     for (long t = slots; t < c->N / 2; t <<= 1) subsum.push_back(t);

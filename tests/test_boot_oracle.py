@@ -469,8 +469,15 @@ def test_sparse_refresh_keeps_a_periodic_message(boot11, n):
     w = decrypt_wide(ev, tr["cts"])
     assert np.abs(w.real).max() <= bs.K / 2 and np.abs(w.imag).max() <= bs.K / 2
     assert np.abs(2 * w.real - np.round(2 * w.real)).max() < 1e-3
+    # the real-slot variant (SlotToCoeff first, also sparse) of the same input
+    rbp = boot.make_params(1, 1, bs.K, bs.r, bs.degree, real_slots=True, slots=n)
+    rev = ckks.Oracle(ctx, ckks.Keys(ctx, synth.SEED_KEYGEN, boot.rotation_steps(bs.logN, rbp)))
+    rct = rev.mod_drop(rev.encrypt(z, 23), 1)
+    rout = boot.bootstrap(rev, rct, rbp)
+    assert rout.level == p.top_level
+    assert np.abs(rev.decrypt(rout, p.slots) - rev.decrypt(rct, p.slots)).max() < 1e-6
     with pytest.raises(ValueError):
-        boot.bootstrap(ev, ct, boot.make_params(1, 1, bs.K, bs.r, bs.degree, real_slots=True, slots=n))
+        boot.bootstrap(ev, ct, boot.make_params(1, 1, bs.K, bs.r, bs.degree, slots=n + 1))
 
 
 def test_real_slot_refresh_with_slot_to_coeff_first(boot11_real):

@@ -405,17 +405,17 @@ def test_real_slot_refresh_bit_exact(b11):
     assert e.value.code == hk.HE_EINVAL
 
 
-@pytest.mark.parametrize("n", [8, 64, 256])
-def test_sparse_refresh_bit_exact(b11, n):
+@pytest.mark.parametrize("n,real", [(8, False), (64, False), (256, False), (64, True), (256, True)])
+def test_sparse_refresh_bit_exact(b11, n, real):
     """The sparsely packed refresh (he_boot_desc.slots = n: SubSum, then the
-    transforms' first log2 n stages) of n-periodic messages against the
-    oracle's, bit for bit, single and batched, and within 1e-6 of the input;
-    a sparse plan with real slots, slots that are not a power of two or more
-    stage groups than log2 n is refused."""
+    transforms' first log2 n stages; with real_slots, SlotToCoeff first) of
+    n-periodic messages against the oracle's, bit for bit, single and batched,
+    and within 1e-6 of the input; slots that are not a power of two or above
+    N/2, or more stage groups than log2 n, are refused."""
     hk, bs, bp, ctx, octx, plan, keys, ev = b11
     G = 1 if n == 8 else 2
-    sbp = OB.make_params(G, G, bs.K, bs.r, bs.degree, slots=n)
-    splan = ctx.boot(G, G, bs.K, bs.r, sbp.coeffs, slots=n)
+    sbp = OB.make_params(G, G, bs.K, bs.r, bs.degree, real_slots=real, slots=n)
+    splan = ctx.boot(G, G, bs.K, bs.r, sbp.coeffs, real_slots=real, slots=n)
     steps = splan.rotation_steps()
     assert sorted(steps) == OB.rotation_steps(bs.logN, sbp)
     note("sparse refresh, slots", n, "keys", len(steps))
@@ -423,7 +423,7 @@ def test_sparse_refresh_bit_exact(b11, n):
     sev = O.Oracle(octx, O.Keys(octx, synth.SEED_KEYGEN, steps))
     M = octx.p.slots
     zs = [np.tile(np.random.default_rng(n + i).uniform(-1, 1, n), M // n) for i in range(2)]
-    ocs = [sev.mod_drop(sev.encrypt(z, 140 + i), 1) for i, z in enumerate(zs)]
+    ocs = [sev.mod_drop(sev.encrypt(z, 140 + i), G if real else 1) for i, z in enumerate(zs)]
     want = [OB.bootstrap(sev, oc, sbp) for oc in ocs]
     got = ctx.bootstrap(splan, skeys, imp(ctx, ocs[0]))
     assert got.level == bs.Lc and (got.export() == as_ct(want[0])).all()
@@ -431,8 +431,8 @@ def test_sparse_refresh_bit_exact(b11, n):
     for o, w, z in zip(outs, want, zs):
         assert (o.export() == as_ct(w)).all()
         assert np.abs(ctx.decrypt(keys, o, M) - z).max() < 1e-6
-    for args, kw in (((1, 1), {"real_slots": True, "slots": n}), ((1, 1), {"slots": n + 1}),
-                     ((1, 1), {"slots": 2 * M}), ((G + 8, 1), {"slots": n})):
+    for args, kw in (((1, 1), {"slots": n + 1}), ((1, 1), {"slots": 2 * M}), ((G + 8, 1), {"slots": n}),
+                     ((1, G + 8), {"real_slots": True, "slots": n})):
         with pytest.raises(hk.HeError) as e:
             ctx.boot(*args, bs.K, bs.r, sbp.coeffs, **kw)
         assert e.value.code == hk.HE_EINVAL
