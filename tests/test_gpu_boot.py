@@ -343,11 +343,12 @@ def test_deep_comparison_kan_with_bootstrapping_reaches_the_exact_kan():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("real", [False, True])
-def test_formula_kan_with_bootstrapping_at_n16(real):
+@pytest.mark.parametrize("real,slots", [(False, 0), (True, 0), (True, 512)])
+def test_formula_kan_with_bootstrapping_at_n16(real, slots):
     """The [4,10,10,1] formula KAN (restructured, three 8-level layers) at
-    N = 2^16 with a refresh between layers (boot16, the full-slot refresh or
-    the real-slot one with SlotToCoeff first): four requests in one batch
+    N = 2^16 with a refresh between layers (boot16, the full-slot refresh,
+    the real-slot one with SlotToCoeff first, or that one sparsely packed on
+    512 slots, the layer outputs repeating with period 16): four requests in one batch
     decrypt within 1e-2 of the FP64 circuit, and the batch equals the
     requests run one at a time, bit for bit."""
     from oracle import kan
@@ -357,7 +358,7 @@ def test_formula_kan_with_bootstrapping_at_n16(real):
     wl, layers = kan_layers("formula16")
     ctx = hctx(hk, bs)
     try:
-        plan = ctx.boot(bs.cts, bs.real_stc if real else bs.stc, bs.K, bs.r, bp.coeffs, real_slots=real)
+        plan = ctx.boot(bs.cts, bs.real_stc if real else bs.stc, bs.K, bs.r, bp.coeffs, real_slots=real, slots=slots)
         model = ctx.compile(layers, refresh=True, circuit=hk.CIRCUIT_RESTRUCTURED)
         keys = ctx.keygen(synth.SEED_KEYGEN, sorted(set(model.rotation_steps()) | set(plan.rotation_steps())))
         xs = synth.inputs(wl, 4, stream=6)
