@@ -269,6 +269,12 @@ int he_model_rotation_steps(const he_model *m, int32_t *steps, size_t cap, size_
  * ciphertext in slots [0, chunk size).  Writes the nc + 1 bounds
  * (min(cap, nc + 1) of them) and nc to *n_chunks. */
 int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t *n_chunks);
+/* The period of layer `layer`'s output slots (d S: d the next power of two
+ * >= the layer's n_out, S the vectors per ciphertext): the output repeats
+ * with it over all N/2 slots, so a sparsely packed refresh of any multiple of
+ * it keeps the output (he_boot_desc.slots).  HE_EINVAL for a layer out of
+ * range. */
+int he_model_output_period(const he_model *m, int32_t layer, int64_t *period);
 
 /* -------------------------------------------------------------------- keys */
 
@@ -413,7 +419,9 @@ int he_bootstrap_batch(he_ctx *ctx, he_boot *b, const he_eval_keys *ek, const he
  * chunks, request-major) with a bootstrapping of every layer's output before
  * the next layer, in place of the client-aided refresh: the whole inference
  * runs on the server.  Each layer must fit the computation levels (HE_EDEPTH
- * otherwise); the model is compiled with refresh_between_layers = 1. */
+ * otherwise); the model is compiled with refresh_between_layers = 1.  A
+ * sparsely packed plan's slots must be a multiple of every refreshed layer's
+ * output period (he_model_output_period; HE_ESHAPE otherwise). */
 int he_eval_kan_boot(he_ctx *ctx, const he_model *m, he_boot *b, const he_eval_keys *ek, const he_ct *const *in,
                      size_t n, he_ct **out);
 

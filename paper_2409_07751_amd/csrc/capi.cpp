@@ -374,6 +374,13 @@ int he_model_input_chunks(const he_model *m, int32_t *bounds, size_t cap, size_t
     return HE_OK;
 }
 
+int he_model_output_period(const he_model *m, int32_t layer, int64_t *period)
+{
+    if (!m || !period || layer < 0 || (size_t)layer >= m->m->layers.size()) return HE_EINVAL;
+    *period = (int64_t)(m->m->layers[layer].d * m->m->S);
+    return HE_OK;
+}
+
 int he_boot_create(he_ctx *ctx, const he_boot_desc *d, he_boot **out)
 {
     if (!ctx || !out) return HE_EINVAL;
@@ -439,6 +446,11 @@ int he_eval_kan_boot(he_ctx *ctx, const he_model *m, he_boot *b, const he_eval_k
         if (b->owner != ctx) throw HeError(HE_ESTATE, "bootstrapping plan of another context");
         Ctx &c = *ctx->c;
         Model &md = *m->m;
+        for (size_t li = 0; li + 1 < md.layers.size(); li++)
+            if (b->b->slots % (md.layers[li].d * md.S) != 0)
+                throw HeError(HE_ESHAPE, "the refresh keeps " + std::to_string(b->b->slots) +
+                                             " slots, not a multiple of layer " + std::to_string(li) +
+                                             "'s output period " + std::to_string(md.layers[li].d * md.S));
         Ct x = eval_layer(c, md, *k->k, batch_inputs(ctx, in, n, md.n_inputs()), 0);
         for (size_t li = 1; li < md.layers.size(); li++)
             x = eval_layer(c, md, *k->k, {bootstrap(c, *b->b, *k->k, x)}, li);

@@ -110,6 +110,7 @@ _SIGS = {
                            ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)],
     "he_model_rotation_steps": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "he_model_input_chunks": [ctypes.c_void_p, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "he_model_output_period": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
     "he_keygen": [ctypes.c_void_p, ctypes.c_uint64, _i32p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p),
                   ctypes.POINTER(ctypes.c_void_p)],
     "he_secret_key_free": [ctypes.c_void_p],
@@ -701,6 +702,12 @@ class Model:
         b = np.zeros(n.value + 1, np.int32)
         self.ctx.check(self.ctx.lib.he_model_input_chunks(self.h, _ptr(b), n.value + 1, ctypes.byref(n)))
         return [int(v) for v in b]
+
+    def output_period(self, layer):
+        """he_model_output_period: the period of the layer's output slots"""
+        v = ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.he_model_output_period(self.h, layer, ctypes.byref(v)))
+        return v.value
 
     def rotation_steps(self):
         n = ctypes.c_size_t()

@@ -219,6 +219,13 @@ def test_kan_with_bootstrapping_between_layers_bit_exact(b11, slots):
     assert (got.export() == as_ct(want)).all()
     y = ctx.decrypt(mkeys, got, 1)
     assert abs(y[0] - kan.he_friendly_kan(x[None], layers)[0][0]) < 1e-2
+    if slots:
+        # the refreshed layer's output repeats with period 8: a plan of 4 slots is refused
+        assert model.output_period(0) == 8
+        small = ctx.boot(1, 1, bs.K, bs.r, bp.coeffs, slots=4)
+        with pytest.raises(hk.HeError) as e:
+            ctx.eval_kan_boot(model, small, mkeys, [ct])
+        assert e.value.code == hk.HE_ESHAPE
 
 
 def digest(a):
