@@ -446,15 +446,20 @@ def test_sparse_refresh_bit_exact(b11, n, real):
         assert e.value.code == hk.HE_EINVAL
 
 
-@pytest.mark.parametrize("real,n", [(False, 2), (True, 1)])
-def test_graph_bootstrap_replays_equal_eager(b11, real, n):
+@pytest.mark.parametrize("real,n,slots", [(False, 2, 0), (True, 1, 0), (True, 2, 64)])
+def test_graph_bootstrap_replays_equal_eager(b11, real, n, slots):
     """A refresh captured into a HIP graph (he_graph_capture_bootstrap): every
     replay, with eager work of the same context between replays, reproduces
-    the eager result bit for bit."""
+    the eager result bit for bit (full-slot, real-slot and sparse real-slot
+    plans)."""
     hk, bs, bp, ctx, octx, plan, keys, ev = b11
     stc = bs.real_stc if real else bs.stc
-    pl = ctx.boot(bs.cts, stc, bs.K, bs.r, bp.coeffs, real_slots=real) if real else plan
+    pl = ctx.boot(bs.cts, stc, bs.K, bs.r, bp.coeffs, real_slots=real, slots=slots) if real else plan
+    if slots:
+        keys = ctx.keygen(synth.SEED_KEYGEN, pl.rotation_steps())
     zs = synth.boot_inputs(bs, n, stream=9)
+    if slots:
+        zs = [np.tile(z[:slots], len(z) // slots) for z in zs]
     ocs = [ev.mod_drop(ev.encrypt(z, 140 + i), 3) for i, z in enumerate(zs)]
     cts = [imp(ctx, oc) for oc in ocs[:n]]
     eager = [o.export() for o in ctx.bootstrap_batch(pl, keys, cts)]
