@@ -499,8 +499,11 @@ def serve_run(args):
 TABLE3_SHAPES = ((64, 3, 2), (128, 5, 3), (256, 5, 3), (256, 10, 3), (256, 10, 5))
 
 
-# slot counts of the sparsely packed refreshes the bootstrapping block times
+# slot counts of the sparsely packed refreshes the bootstrapping block times,
+# and of the sparse real-slot one (also the formula KAN's, whose layer outputs
+# repeat with period 16)
 BOOT_SPARSE_SLOTS = (512, 4096)
+BOOT_SPARSE_REAL_SLOTS = 64
 
 
 def boot_bench(args):
@@ -527,7 +530,7 @@ def boot_bench(args):
     splans = {n: ctx.boot(bs.cts, bs.stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), slots=n)
               for n in BOOT_SPARSE_SLOTS}
     # and of real n-periodic slot vectors, SlotToCoeff first
-    n_real = BOOT_SPARSE_SLOTS[0]
+    n_real = BOOT_SPARSE_REAL_SLOTS
     srplan = ctx.boot(bs.cts, bs.real_stc, bs.K, bs.r, pc.boot_cos_coeffs(bs.K, bs.r, bs.degree), real_slots=True,
                       slots=n_real)
     t0 = time.time()
@@ -671,10 +674,11 @@ def boot_bench(args):
     want = pc.plain_forward(x, layers)
     kin = [ctx.encrypt(keys, x[i], synth.SEED_ENC + 100 + i) for i in range(B)]
     kan = {}
-    # (the layer outputs repeat with period 16, so the sparse refresh of 512
-    # slots applies)
+    # (the layer outputs repeat with period 16, so sparse refreshes of 512 and
+    # of 64 slots apply)
     for name, pl in (("full_slot_refresh", plan), ("real_slot_refresh", rplan),
-                     ("sparse_512_slot_refresh", splans[512]), ("sparse_512_real_slot_refresh", srplan)):
+                     ("sparse_512_slot_refresh", splans[512]),
+                     ("sparse_%d_real_slot_refresh" % n_real, srplan)):
         kout = ctx.eval_kan_boot(model, pl, keys, kin)
         ctx.sync()
         t0 = time.time()
