@@ -549,11 +549,18 @@ def boot_bench(args):
     first = time.time() - t0
     if args.boot_profile:
         # refreshes of one ciphertext separated by idle gaps (for a kernel trace)
+        pp, c_in = plan, cts[0]
+        if args.boot_profile_plan == "sparse_real":
+            n = BOOT_SPARSE_REAL_SLOTS
+            pp = srplan
+            c_in = ctx.mod_drop(ctx.encrypt(keys, np.tile(z[0][:n], (1 << (bs.logN - 1)) // n), 300), bs.real_stc)
+            out = ctx.bootstrap(pp, keys, c_in)
+            ctx.sync()
         del rplan
         l0 = ctx.counters()["launches"]
         for _ in range(args.boot_reps):
             time.sleep(0.2)
-            out = ctx.bootstrap(plan, keys, cts[0])
+            out = ctx.bootstrap(pp, keys, c_in)
             ctx.sync()
         log("bootstrapping profile: %d refreshes, %.0f launches each" %
             (args.boot_reps, (ctx.counters()["launches"] - l0) / args.boot_reps))
@@ -811,6 +818,8 @@ def main():
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--no-boot", action="store_true", help="skip the bootstrapping measurement")
     ap.add_argument("--boot-only", action="store_true", help="only the bootstrapping measurement (its own JSON line)")
+    ap.add_argument("--boot-profile-plan", choices=("full", "sparse_real"), default="full",
+                    help="the refresh --boot-profile repeats: full-slot, or the sparse real-slot one")
     ap.add_argument("--boot-profile", action="store_true",
                     help="with --boot-only: refreshes of one ciphertext separated by 0.2 s idle gaps, for a trace")
     ap.add_argument("--boot-batch", type=int, default=8)
